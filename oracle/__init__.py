@@ -1,0 +1,220 @@
+"""FP64 CPU oracle for the factored extrinsic likelihood (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: only the test-suite, the package smoke check and the
+CPU-baseline leg of the benchmark may import this module.  The product path
+(the HIP library and its Python binding) never imports, loads or calls it, and
+the two share no code.
+
+The arithmetic lives in ``oracle.cpp`` (plain loops, IEEE double, OpenMP over
+samples); this module only marshals numpy arrays into it.  ``pregrid`` (the
+Fourier refinement of Eq. (q-time-pregrid)) is written here in numpy.
+
+Every function states the passage of the paper it follows.  Parity status of
+each function (what pins it) is listed in the tests' docstrings.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+THETA_NAMES = ("ra", "dec", "psi", "incl", "phiref", "tref", "dist")
+GRAD_NAMES = ("ra", "dec", "psi", "cos_incl", "phiref", "tref", "ln_dist")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (-O2 -fopenmp)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["g++", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c++17", _SRC, "-o", tmp]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        d = ctypes.c_double
+        p = ctypes.c_void_p
+        lib.oracle_ylm.argtypes = [ctypes.c_int, ctypes.c_int, d, d, p]
+        lib.oracle_antenna.argtypes = [p, d, d, d, d, p, p]
+        lib.oracle_arrival_time.argtypes = [p, d, d, d, d]
+        lib.oracle_arrival_time.restype = d
+        lib.oracle_interp.argtypes = [p, ctypes.c_int, d, d, ctypes.c_int64, p, p]
+        lib.oracle_lnL_factored.argtypes = [ctypes.c_int, ctypes.c_int, p, p, d, p, p, p]
+        lib.oracle_lnL_factored.restype = d
+        lib.oracle_lnL.argtypes = [p, ctypes.c_int64, p, p, ctypes.c_int]
+        lib.oracle_grad.argtypes = [p, ctypes.c_int64, p, p, p, ctypes.c_int]
+        lib.oracle_lnZ.argtypes = [ctypes.c_int64, p, p, p, p]
+        _lib = lib
+    return _lib
+
+
+class _CPoint(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32),
+        ("M", ctypes.c_int32),
+        ("n_t", ctypes.c_int32),
+        ("lm", ctypes.c_void_p),
+        ("t0", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("Q", ctypes.c_void_p),
+        ("U", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
+        ("det_tensor", ctypes.c_void_p),
+        ("det_pos", ctypes.c_void_p),
+        ("gmst", ctypes.c_double),
+        ("d_ref", ctypes.c_double),
+    ]
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class _Packed:
+    cp: _CPoint
+    keep: tuple
+
+
+def _pack(pt) -> _Packed:
+    """pt: mapping with lm [M,2], t0, dt, Q [K,M,n_t] complex, U/V [K,M,M] complex,
+    det_tensor [K,3,3], det_pos [K,3] (light-seconds), gmst, d_ref."""
+    lm = _c(pt["lm"], np.int32)
+    Q = _c(pt["Q"], np.complex128)
+    U = _c(pt["U"], np.complex128)
+    V = _c(pt["V"], np.complex128)
+    D = _c(pt["det_tensor"], np.float64)
+    R = _c(pt["det_pos"], np.float64)
+    K, M, n_t = Q.shape
+    assert U.shape == (K, M, M) and V.shape == (K, M, M) and lm.shape == (M, 2)
+    assert D.shape == (K, 3, 3) and R.shape == (K, 3)
+    cp = _CPoint(K, M, n_t, _ptr(lm).value, float(pt["t0"]), float(pt["dt"]), _ptr(Q).value,
+                 _ptr(U).value, _ptr(V).value, _ptr(D).value, _ptr(R).value,
+                 float(pt["gmst"]), float(pt["d_ref"]))
+    return _Packed(cp, (lm, Q, U, V, D, R))
+
+
+# ---------------------------------------------------------------------------
+# Building blocks
+# ---------------------------------------------------------------------------
+def ylm(l: int, m: int, iota: float, phi: float) -> complex:
+    """-2Y_lm(iota, phi), Eq. (strain_mode) harmonics (Wigner-d sum)."""
+    out = np.zeros(2)
+    _load().oracle_ylm(int(l), int(m), float(iota), float(phi), _ptr(out))
+    return complex(out[0], out[1])
+
+
+def antenna(det_tensor, ra, dec, psi, gmst):
+    """Static complex antenna factor F = F+ + i Fx of one detector
+    (Sec. "Review of the RIFT likelihood", static response).  Returns (F, N)."""
+    D = _c(det_tensor, np.float64)
+    out = np.zeros(2)
+    N = np.zeros(3)
+    _load().oracle_antenna(_ptr(D), float(ra), float(dec), float(psi), float(gmst), _ptr(out), _ptr(N))
+    return complex(out[0], out[1]), N
+
+
+def arrival_time(det_pos, ra, dec, gmst, tref):
+    """t_k = t_ref - r_k . N (same section; r_k in light-seconds)."""
+    r = _c(det_pos, np.float64)
+    return _load().oracle_arrival_time(_ptr(r), float(ra), float(dec), float(gmst), float(tref))
+
+
+def interp(q, t0, dt, t):
+    """Four-point cubic read C_3 of a uniformly sampled complex series
+    (Eq. (q-time-pregrid)); 4-point Lagrange on nodes j-1..j+2, zero outside."""
+    q = _c(q, np.complex128)
+    t = _c(np.atleast_1d(t), np.float64)
+    out = np.zeros(t.shape[0], np.complex128)
+    _load().oracle_interp(_ptr(q), q.shape[0], float(t0), float(dt), t.shape[0], _ptr(t), _ptr(out))
+    return out
+
+
+def lnL_factored(F, Y, x, Qhat, U, V) -> float:
+    """Eq. (def:lnL:Decomposed) from F[K], Y[M], x = D_ref/D and Q already read at t_k."""
+    F = _c(F, np.complex128)
+    Y = _c(Y, np.complex128)
+    Qhat = _c(Qhat, np.complex128)
+    U = _c(U, np.complex128)
+    V = _c(V, np.complex128)
+    K, M = Qhat.shape
+    return _load().oracle_lnL_factored(K, M, _ptr(F), _ptr(Y), float(x), _ptr(Qhat), _ptr(U), _ptr(V))
+
+
+# ---------------------------------------------------------------------------
+# The path
+# ---------------------------------------------------------------------------
+def lnL(pt, theta, nthreads: int = 0) -> np.ndarray:
+    """lnL for every sample; theta is [7, n] (ra, dec, psi, incl, phiref, tref, dist)."""
+    th = _c(theta, np.float64)
+    assert th.ndim == 2 and th.shape[0] == 7
+    n = th.shape[1]
+    out = np.empty(n)
+    pk = _pack(pt)
+    _load().oracle_lnL(ctypes.byref(pk.cp), n, _ptr(th), _ptr(out), int(nthreads))
+    return out
+
+
+def grad(pt, theta, nthreads: int = 0):
+    """(lnL [n], d lnL/d(ra, dec, psi, cos incl, phiref, tref, ln dist) [7, n])."""
+    th = _c(theta, np.float64)
+    n = th.shape[1]
+    out = np.empty(n)
+    g = np.empty((7, n))
+    pk = _pack(pt)
+    _load().oracle_grad(ctypes.byref(pk.cp), n, _ptr(th), _ptr(out), _ptr(g), int(nthreads))
+    return out, g
+
+
+def lnZ(lnL_values, lnw=None):
+    """Eq. (lnL:MonteCarlo) in log form with 1/N, and Eq. (neff). Returns (lnZ, neff)."""
+    l = _c(lnL_values, np.float64)
+    w = None if lnw is None else _c(lnw, np.float64)
+    z = np.zeros(1)
+    ne = np.zeros(1)
+    _load().oracle_lnZ(l.shape[0], _ptr(l), None if w is None else _ptr(w), _ptr(z), _ptr(ne))
+    return float(z[0]), float(ne[0])
+
+
+def pregrid(q, r: int):
+    """Fourier refinement of a sampled complex series, Eq. (q-time-pregrid).
+
+    Append the reversed copy (so the periodic extension is continuous), FFT,
+    zero-pad the spectrum by r (the Nyquist bin split in halves between +/-),
+    inverse FFT times r, and keep the samples spanning the original window:
+    (N-1) r + 1 fine samples at spacing h/r, fine[j r] == q[j].
+    """
+    q = np.asarray(q, np.complex128)
+    n = q.shape[-1]
+    refl = np.concatenate([q, q[..., ::-1]], axis=-1)
+    L = 2 * n
+    spec = np.fft.fft(refl, axis=-1)
+    big = np.zeros(q.shape[:-1] + (L * r,), np.complex128)
+    half = L // 2
+    big[..., :half] = spec[..., :half]
+    big[..., -half + 1:] = spec[..., half + 1:]
+    big[..., half] = 0.5 * spec[..., half]
+    big[..., L * r - half] = 0.5 * spec[..., half]
+    fine = np.fft.ifft(big, axis=-1) * r
+    return fine[..., : (n - 1) * r + 1]

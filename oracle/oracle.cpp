@@ -1,0 +1,378 @@
+// Plain FP64 CPU oracle for the factored extrinsic likelihood and its
+// Monte-Carlo evidence reduction.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing on the product path may include, link,
+// load or call this file.  It exists to be the slow, obviously correct
+// reference that the HIP kernels are compared against, and it shares no code
+// with them.
+//
+// Everything here follows the paper's own order of operations:
+//   * antenna response and arrival time:   Sec. "Review of the RIFT likelihood"
+//     (static response paragraph: constant F+, Fx; t_k = t_c - x_k . n)
+//   * spin-weighted harmonics -2Y_lm:      Eq. (strain_mode)
+//   * four-point cubic read of Q on the fine grid:  Eq. (q-time-pregrid)
+//   * factored log-likelihood:             Eq. (def:lnL:Decomposed)
+//   * Monte-Carlo marginal likelihood:     Eq. (lnL:MonteCarlo)
+//   * effective sample size:               Eq. (neff)
+//   * gradient (the differentiable path):  Sec. "The differentiable likelihood"
+//
+// Readings where the paper is silent or inconsistent (all listed in the
+// design notes of the repository):
+//   * complex antenna factor F = F+ + i Fx (the strain is h = h+ - i hx, and
+//     the response h_k = F+ h+ + Fx hx must equal Re[F h]);
+//   * arrival time t_k = t_ref - r_k . N, with N pointing to the source and r_k
+//     in light-seconds;
+//   * "four-point cubic" = 4-point Lagrange interpolation on nodes j-1..j+2,
+//     with taps outside the stored window reading zero;
+//   * the V term carries Re(...), as in Eq. (def:lnL:Decomposed);
+//   * ln Z normalised by 1/N with caller-supplied ln(p/p_s).
+//
+// Build: g++ -O2 -fopenmp -shared -fPIC oracle.cpp -o liboracle.so
+// Precision: IEEE double throughout, libm transcendentals.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <limits>
+#include <omp.h>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual number with NT tangents, for the oracle gradient.
+// ---------------------------------------------------------------------------
+template <int NT>
+struct Dual {
+  double v;
+  double d[NT];
+  Dual() : v(0) { for (int i = 0; i < NT; ++i) d[i] = 0; }
+  Dual(double x) : v(x) { for (int i = 0; i < NT; ++i) d[i] = 0; }
+};
+template <int NT> Dual<NT> operator+(const Dual<NT>& a, const Dual<NT>& b) {
+  Dual<NT> r; r.v = a.v + b.v; for (int i = 0; i < NT; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+template <int NT> Dual<NT> operator-(const Dual<NT>& a, const Dual<NT>& b) {
+  Dual<NT> r; r.v = a.v - b.v; for (int i = 0; i < NT; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+template <int NT> Dual<NT> operator-(const Dual<NT>& a) {
+  Dual<NT> r; r.v = -a.v; for (int i = 0; i < NT; ++i) r.d[i] = -a.d[i]; return r; }
+template <int NT> Dual<NT> operator*(const Dual<NT>& a, const Dual<NT>& b) {
+  Dual<NT> r; r.v = a.v * b.v; for (int i = 0; i < NT; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
+template <int NT> Dual<NT> operator/(const Dual<NT>& a, const Dual<NT>& b) {
+  Dual<NT> r; r.v = a.v / b.v;
+  for (int i = 0; i < NT; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+  return r; }
+template <int NT> Dual<NT> operator+(const Dual<NT>& a, double b) { return a + Dual<NT>(b); }
+template <int NT> Dual<NT> operator+(double a, const Dual<NT>& b) { return Dual<NT>(a) + b; }
+template <int NT> Dual<NT> operator-(const Dual<NT>& a, double b) { return a - Dual<NT>(b); }
+template <int NT> Dual<NT> operator-(double a, const Dual<NT>& b) { return Dual<NT>(a) - b; }
+template <int NT> Dual<NT> operator*(const Dual<NT>& a, double b) { return a * Dual<NT>(b); }
+template <int NT> Dual<NT> operator*(double a, const Dual<NT>& b) { return Dual<NT>(a) * b; }
+template <int NT> Dual<NT> operator/(const Dual<NT>& a, double b) { return a / Dual<NT>(b); }
+template <int NT> Dual<NT> operator/(double a, const Dual<NT>& b) { return Dual<NT>(a) / b; }
+template <int NT> Dual<NT> sin(const Dual<NT>& a) {
+  Dual<NT> r;
+  r.v = std::sin(a.v);
+  double c = std::cos(a.v);
+  for (int i = 0; i < NT; ++i) r.d[i] = c * a.d[i];
+  return r;
+}
+template <int NT> Dual<NT> cos(const Dual<NT>& a) {
+  Dual<NT> r;
+  r.v = std::cos(a.v);
+  double s = -std::sin(a.v);
+  for (int i = 0; i < NT; ++i) r.d[i] = s * a.d[i];
+  return r;
+}
+template <int NT> Dual<NT> exp(const Dual<NT>& a) {
+  Dual<NT> r;
+  r.v = std::exp(a.v);
+  for (int i = 0; i < NT; ++i) r.d[i] = r.v * a.d[i];
+  return r;
+}
+template <int NT> Dual<NT> acos(const Dual<NT>& a) {
+  Dual<NT> r;
+  r.v = std::acos(a.v);
+  double g = -1.0 / std::sqrt(1.0 - a.v * a.v);
+  for (int i = 0; i < NT; ++i) r.d[i] = g * a.d[i];
+  return r;
+}
+using std::sin;
+using std::cos;
+using std::exp;
+using std::acos;
+template <int NT> double value(const Dual<NT>& a) { return a.v; }
+inline double value(double a) { return a; }
+
+// Minimal complex type usable with both double and Dual.
+template <class T>
+struct Cx {
+  T re, im;
+};
+template <class T> Cx<T> cmul(const Cx<T>& a, const Cx<T>& b) {
+  return Cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+template <class T> Cx<T> cconj(const Cx<T>& a) { return Cx<T>{a.re, T(0.0) - a.im}; }
+
+double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+// ---------------------------------------------------------------------------
+// Point description (paper order of every array).
+// ---------------------------------------------------------------------------
+struct Point {
+  int32_t K, M, n_t;
+  const int32_t* lm;      // [M][2] (l, m)
+  double t0, dt;          // Q grid: t_j = t0 + j dt  (seconds)
+  const double* Q;        // [K][M][n_t] complex interleaved
+  const double* U;        // [K][M][M] complex interleaved, U_{k, i, j}
+  const double* V;        // [K][M][M] complex interleaved
+  const double* det_tensor;  // [K][3][3]
+  const double* det_pos;     // [K][3] light-seconds
+  double gmst;            // Greenwich sidereal angle at the reference epoch (rad)
+  double d_ref;           // reference distance of Eq. (strain_mode)
+};
+
+// -2Y_lm(iota, phi): Wigner-d sum (Goldberg et al. 1967 form), spin weight -2,
+// i.e. (-1)^s sqrt((2l+1)/4pi) d^l_{m,s}(iota) e^{i m phi} with s = 2.
+template <class T>
+Cx<T> ylm_m2(int l, int m, const T& iota, const T& phi) {
+  const int s = 2;
+  T c = cos(iota * 0.5);
+  T sn = sin(iota * 0.5);
+  T d(0.0);
+  int kmin = (m - s > 0) ? (m - s) : 0;
+  int kmax = (l + m < l - s) ? (l + m) : (l - s);
+  double pref = std::sqrt(factorial(l + m) * factorial(l - m) * factorial(l + s) * factorial(l - s));
+  for (int k = kmin; k <= kmax; ++k) {
+    double coef = ((k % 2) ? -1.0 : 1.0) * pref /
+                  (factorial(l + m - k) * factorial(l - s - k) * factorial(k) * factorial(k + s - m));
+    int pc = 2 * l + m - s - 2 * k;
+    int ps = 2 * k + s - m;
+    T term(coef);
+    for (int i = 0; i < pc; ++i) term = term * c;
+    for (int i = 0; i < ps; ++i) term = term * sn;
+    d = d + term;
+  }
+  double norm = ((s % 2) ? -1.0 : 1.0) * std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
+  T amp = d * norm;
+  T ang = phi * double(m);
+  return Cx<T>{amp * cos(ang), amp * sin(ang)};
+}
+
+// Source direction N (towards the source) and polarisation axes X, Y in the
+// Earth-fixed frame (x: Greenwich meridian on the equator, z: north pole).
+template <class T>
+void sky_frame(const T& ra, const T& dec, const T& psi, double gmst, T N[3], T X[3], T Y[3]) {
+  T gha = gmst - ra;
+  T cg = cos(gha), sg = sin(gha), cd = cos(dec), sd = sin(dec), cp = cos(psi), sp = sin(psi);
+  N[0] = cd * cg; N[1] = T(0.0) - cd * sg; N[2] = sd;
+  T ea[3] = {sg, cg, T(0.0)};
+  T ed[3] = {T(0.0) - sd * cg, sd * sg, cd};
+  for (int i = 0; i < 3; ++i) {
+    X[i] = T(0.0) - cp * ea[i] + sp * ed[i];
+    Y[i] = sp * ea[i] + cp * ed[i];
+  }
+}
+
+// F = F+ + i Fx with F+ = D : (X X^T - Y Y^T) and Fx = D : (X Y^T + Y X^T).
+template <class T>
+Cx<T> antenna(const double* D, const T X[3], const T Y[3]) {
+  T fp(0.0), fx(0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double dij = D[3 * i + j];
+      fp = fp + dij * (X[i] * X[j] - Y[i] * Y[j]);
+      fx = fx + dij * (X[i] * Y[j] + Y[i] * X[j]);
+    }
+  return Cx<T>{fp, fx};
+}
+
+// Four-point Lagrange read of a uniformly sampled complex series.  The
+// stencil is nodes j-1, j, j+1, j+2 around u = (t - t0)/dt, j = floor(u);
+// nodes outside [0, n_t) contribute zero.
+template <class T>
+Cx<T> interp_lagrange4(const double* q, int n_t, double t0, double dt, const T& t) {
+  T u = (t - t0) / dt;
+  if (!std::isfinite(value(u))) {  // a non-finite time poisons the read
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    return Cx<T>{T(nan), T(nan)};
+  }
+  double j = std::floor(value(u));
+  T s = u - j;
+  T w[4];
+  w[0] = T(0.0) - s * (s - 1.0) * (s - 2.0) / 6.0;
+  w[1] = (s + 1.0) * (s - 1.0) * (s - 2.0) / 2.0;
+  w[2] = T(0.0) - (s + 1.0) * s * (s - 2.0) / 2.0;
+  w[3] = (s + 1.0) * s * (s - 1.0) / 6.0;
+  Cx<T> out{T(0.0), T(0.0)};
+  for (int i = 0; i < 4; ++i) {
+    double node = j - 1.0 + i;
+    if (!(node >= 0.0 && node < (double)n_t)) continue;  // zero extension (also NaN)
+    int64_t n = (int64_t)node;
+    out.re = out.re + w[i] * q[2 * n];
+    out.im = out.im + w[i] * q[2 * n + 1];
+  }
+  return out;
+}
+
+// Factored log-likelihood, Eq. (def:lnL:Decomposed), given F_k, Y_lm, x = D_ref/D
+// and the Q values already read at t_k.
+template <class T>
+T lnL_factored(int K, int M, const Cx<T>* F, const Cx<T>* Y, const T& x,
+               const Cx<T>* Qhat, const double* U, const double* V) {
+  T data(0.0), quad(0.0);
+  for (int k = 0; k < K; ++k) {
+    for (int i = 0; i < M; ++i) {
+      Cx<T> c = cconj(cmul(F[k], Y[i]));
+      Cx<T> q = Qhat[k * M + i];
+      data = data + (c.re * q.re - c.im * q.im);
+    }
+    Cx<T> a{T(0.0), T(0.0)}, b{T(0.0), T(0.0)};
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j) {
+        const double* u = U + 2 * ((size_t)(k * M + i) * M + j);
+        const double* v = V + 2 * ((size_t)(k * M + i) * M + j);
+        Cx<T> uu{T(u[0]), T(u[1])}, vv{T(v[0]), T(v[1])};
+        Cx<T> ta = cmul(cmul(cconj(Y[i]), uu), Y[j]);
+        Cx<T> tb = cmul(cmul(Y[i], vv), Y[j]);
+        a.re = a.re + ta.re; a.im = a.im + ta.im;
+        b.re = b.re + tb.re; b.im = b.im + tb.im;
+      }
+    T f2abs = F[k].re * F[k].re + F[k].im * F[k].im;
+    Cx<T> f2 = cmul(F[k], F[k]);
+    quad = quad + f2abs * a.re + (f2.re * b.re - f2.im * b.im);
+  }
+  return x * data - x * x * quad * 0.25;
+}
+
+// Full per-sample likelihood from the extrinsic parameters.
+template <class T>
+T lnL_one(const Point& p, const T& ra, const T& dec, const T& psi, const T& iota,
+          const T& phi, const T& tref, const T& dist) {
+  T N[3], X[3], Y3[3];
+  sky_frame(ra, dec, psi, p.gmst, N, X, Y3);
+  std::vector<Cx<T>> F(p.K), Y(p.M), Qhat((size_t)p.K * p.M);
+  for (int k = 0; k < p.K; ++k) {
+    F[k] = antenna(p.det_tensor + 9 * k, X, Y3);
+    const double* r = p.det_pos + 3 * k;
+    T tk = tref - (r[0] * N[0] + r[1] * N[1] + r[2] * N[2]);
+    for (int i = 0; i < p.M; ++i)
+      Qhat[(size_t)k * p.M + i] =
+          interp_lagrange4(p.Q + 2 * ((size_t)(k * p.M + i) * p.n_t), p.n_t, p.t0, p.dt, tk);
+  }
+  for (int i = 0; i < p.M; ++i) Y[i] = ylm_m2(p.lm[2 * i], p.lm[2 * i + 1], iota, phi);
+  T x = p.d_ref / dist;
+  return lnL_factored(p.K, p.M, F.data(), Y.data(), x, Qhat.data(), p.U, p.V);
+}
+
+}  // namespace
+
+extern "C" {
+
+int oracle_version() { return 1; }
+
+// -2Y_lm(iota, phi) -> out[2] = (re, im)
+void oracle_ylm(int l, int m, double iota, double phi, double* out) {
+  Cx<double> y = ylm_m2<double>(l, m, iota, phi);
+  out[0] = y.re; out[1] = y.im;
+}
+
+// Complex antenna factor of one detector; out[2] = (F+, Fx).  N_out[3] (may be
+// NULL) receives the unit vector towards the source.
+void oracle_antenna(const double* det_tensor, double ra, double dec, double psi, double gmst,
+                    double* out, double* N_out) {
+  double N[3], X[3], Y[3];
+  sky_frame<double>(ra, dec, psi, gmst, N, X, Y);
+  Cx<double> f = antenna<double>(det_tensor, X, Y);
+  out[0] = f.re; out[1] = f.im;
+  if (N_out) for (int i = 0; i < 3; ++i) N_out[i] = N[i];
+}
+
+// Arrival time at a detector at position r (light-seconds).
+double oracle_arrival_time(const double* r, double ra, double dec, double gmst, double tref) {
+  double N[3], X[3], Y[3];
+  sky_frame<double>(ra, dec, 0.0, gmst, N, X, Y);
+  return tref - (r[0] * N[0] + r[1] * N[1] + r[2] * N[2]);
+}
+
+// Four-point Lagrange read of one complex series q[n_t][2] at times t[n].
+void oracle_interp(const double* q, int n_t, double t0, double dt, int64_t n, const double* t,
+                   double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    Cx<double> v = interp_lagrange4<double>(q, n_t, t0, dt, t[i]);
+    out[2 * i] = v.re; out[2 * i + 1] = v.im;
+  }
+}
+
+// Eq. (def:lnL:Decomposed) from given F[K][2], Y[M][2], x, Qhat[K][M][2].
+double oracle_lnL_factored(int K, int M, const double* F, const double* Y, double x,
+                           const double* Qhat, const double* U, const double* V) {
+  std::vector<Cx<double>> f(K), y(M), q((size_t)K * M);
+  for (int k = 0; k < K; ++k) f[k] = Cx<double>{F[2 * k], F[2 * k + 1]};
+  for (int i = 0; i < M; ++i) y[i] = Cx<double>{Y[2 * i], Y[2 * i + 1]};
+  for (size_t i = 0; i < (size_t)K * M; ++i) q[i] = Cx<double>{Qhat[2 * i], Qhat[2 * i + 1]};
+  return lnL_factored<double>(K, M, f.data(), y.data(), x, q.data(), U, V);
+}
+
+// lnL for n samples; theta is SoA [7][n]: ra, dec, psi, incl, phiref, tref, dist.
+void oracle_lnL(const Point* p, int64_t n, const double* theta, double* lnL, int nthreads) {
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    lnL[i] = lnL_one<double>(*p, theta[i], theta[n + i], theta[2 * n + i], theta[3 * n + i],
+                             theta[4 * n + i], theta[5 * n + i], theta[6 * n + i]);
+  }
+}
+
+// lnL and its gradient with respect to (ra, dec, psi, cos incl, phiref, tref, ln dist),
+// grad SoA [7][n].  Forward-mode dual numbers over the same code as oracle_lnL.
+void oracle_grad(const Point* p, int64_t n, const double* theta, double* lnL, double* grad,
+                 int nthreads) {
+  typedef Dual<7> D7;
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    D7 v[7];
+    for (int a = 0; a < 7; ++a) v[a] = D7(theta[a * n + i]);
+    // independent coordinates: ra, dec, psi, cos(incl), phiref, tref, ln(dist)
+    D7 ra = v[0], dec = v[1], psi = v[2], phi = v[4], tref = v[5];
+    ra.d[0] = 1; dec.d[1] = 1; psi.d[2] = 1; phi.d[4] = 1; tref.d[5] = 1;
+    D7 cosi(std::cos(theta[3 * n + i])); cosi.d[3] = 1;
+    D7 iota = acos(cosi);
+    iota.v = theta[3 * n + i];  // keep the caller's angle exactly; tangent from acos
+    D7 lnd(std::log(theta[6 * n + i])); lnd.d[6] = 1;
+    D7 dist = exp(lnd);
+    dist.v = theta[6 * n + i];
+    D7 r = lnL_one<D7>(*p, ra, dec, psi, iota, phi, tref, dist);
+    lnL[i] = r.v;
+    for (int a = 0; a < 7; ++a) grad[a * n + i] = r.d[a];
+  }
+}
+
+// Eq. (lnL:MonteCarlo) in log form and Eq. (neff):
+//   lnZ = ln[(1/N) sum_i exp(lnL_i + lnw_i)],  neff = sum_i p_i / max_i p_i.
+// lnw may be NULL (all zero).  Any NaN makes both outputs NaN.
+void oracle_lnZ(int64_t n, const double* lnL, const double* lnw, double* lnZ, double* neff) {
+  const double ninf = -std::numeric_limits<double>::infinity();
+  double m = ninf;
+  bool nan = false;
+  for (int64_t i = 0; i < n; ++i) {
+    double l = lnL[i] + (lnw ? lnw[i] : 0.0);
+    if (std::isnan(l)) nan = true;
+    else if (l > m) m = l;
+  }
+  if (nan || n <= 0) {
+    *lnZ = std::numeric_limits<double>::quiet_NaN();
+    *neff = std::numeric_limits<double>::quiet_NaN();
+    return;
+  }
+  if (m == ninf) { *lnZ = ninf; *neff = 0.0; return; }
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += std::exp(lnL[i] + (lnw ? lnw[i] : 0.0) - m);
+  *lnZ = m + std::log(s) - std::log((double)n);
+  *neff = s;
+}
+
+}  // extern "C"
