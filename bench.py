@@ -1,0 +1,407 @@
+#!/usr/bin/env python3
+"""Benchmark of the factored extrinsic likelihood on one MI355X.
+
+Default workload (the headline configuration): 3 detectors, 21 modes (l <= 4),
+Q pregridded at 32768 Hz over +-0.1 s (6554 samples per mode and detector),
+network SNR 600, 1e6 prior extrinsic samples.  One step = the whole path over
+the batch: every sample's lnL (written out) and the log-sum-exp into ln Z and
+n_eff.  `value` is the FP64 path's lnL evaluations per second (every lnL
+within 1e-9 relative of the FP64 oracle); the mixed path is reported beside it
+with its error statement.
+
+    python bench.py [--steps K] [--warmup W] [--extras] [--no-cpu]
+
+Prints ONE JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "extrinsic lnL evals/sec (+ grad evals/sec) at |ΔlnL|≤1e-3 vs FP64 oracle"
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed); unpacked issue is half of it
+PEAK_HBM_GBS = 8000.0
+
+
+def lclass(lmax):
+    return 2 if lmax <= 2 else (3 if lmax <= 3 else (4 if lmax <= 4 else 8))
+
+
+def basis_count(L):
+    NI = 2 * L
+    return (NI + 1) + L * 2 * (NI + 1) + L * 2 * NI
+
+
+def flops_per_sample(K, M, lmax):
+    """Algorithmic flops of one lnL evaluation in this formulation (FMA = 2),
+    transcendentals (5 sincos) not included.  See the design notes."""
+    L = lclass(lmax)
+    NI = 2 * L
+    B = basis_count(L)
+    sky = 58
+    per_det = 49 + 3 + 11               # antenna, delay + stencil; data combine; norm weights
+    harm = 6 * NI + 12 * L + M * (2 * L + 4)
+    data = 24 * M * K
+    quad = B * (6 * K + 2)
+    return sky + per_det * K + harm + data + quad + 5
+
+
+def bytes_per_sample(weighted=False, write_lnL=True):
+    return 56 + (8 if weighted else 0) + (8 if write_lnL else 0)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def c2_inputs(synth, n):
+    pt = synth.make_point(3, 21, 6554, 32768.0, 600.0, 2)
+    th = synth.prior_samples(n, 2)
+    return pt, th
+
+
+def run_path(ile, torch, pt, tht, precision, steps, warmup, tune):
+    n = tht.shape[1]
+    plan = ile.Plan([pt], [n], precision=precision)
+    if tune:
+        plan.tune(tht)
+    lnl = torch.empty(n, dtype=torch.float64, device="cuda")
+    z = torch.empty(1, dtype=torch.float64, device="cuda")
+    ne = torch.empty(1, dtype=torch.float64, device="cuda")
+    err = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.lnZ(tht, lnZ_out=z, neff_out=ne, lnL_out=lnl, err_out=err)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    secs, wall = time_steps(step, steps, 0, torch)
+    kms, launches = plan.profile_read()
+    plan.profile(False)
+    out = {
+        "secs": secs,
+        "wall": wall,
+        "kernel_ms_avg": kms / max(1, launches),
+        "launches": launches,
+        "lnZ": z.item(),
+        "neff": ne.item(),
+        "lnZ_err_bound": err.item(),
+        "config": plan.config,
+        "refined": plan.refined() if precision == "mixed" else 0,
+        "lnL": lnl,
+    }
+    plan.close()
+    return out
+
+
+def cpu_baseline(pt, th, gpu_lnL, budget_s=12.0):
+    """The FP64 oracle as it stands, on this host, on a bounded prefix of the
+    same samples (about `budget_s` seconds of CPU work)."""
+    import oracle
+
+    oracle.build(force=False)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n = th.shape[1]
+    done = 0
+    chunk = 20000
+    t0 = time.perf_counter()
+    outs = []
+    while done < n and time.perf_counter() - t0 < budget_s:
+        c = min(chunk, n - done)
+        outs.append(oracle.lnL(pt, th[:, done:done + c], nthreads=nthreads))
+        done += c
+    el = time.perf_counter() - t0
+    l_or = np.concatenate(outs)
+    d = np.abs(gpu_lnL[:done] - l_or)
+    return {
+        "value": done / el,
+        "unit": "lnL evals/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": f"first {done} of the {n} samples of the same workload ({el:.1f} s)",
+    }, {
+        "samples": int(done),
+        "max_abs_dlnL": float(d.max()),
+        "max_rel_dlnL": float((d / np.maximum(1.0, np.abs(l_or))).max()),
+    }
+
+
+# ---------------------------------------------------------------------------
+# Extra configurations
+# ---------------------------------------------------------------------------
+def extra_c1(ile, synth, torch, steps):
+    pt = synth.make_point(2, 2, 410, 4096.0, 20.0, 1)
+    res = {}
+    for n in (10_000, 10_000_000):
+        th = torch.as_tensor(synth.prior_samples(n, 1), device="cuda").contiguous()
+        r = run_path(ile, torch, pt, th, "fp64", steps, 3, tune=False)
+        res[f"n{n}"] = {"lnL_evals_per_s": n * steps / r["secs"], "ms_per_step": 1e3 * r["secs"] / steps,
+                        "kernel_ms": r["kernel_ms_avg"]}
+        del th
+    return res
+
+
+def extra_c3(ile, synth, torch, steps, n_points=512, per_point=200_000):
+    """512 points, M ~ U{2,4,9,16,21}, n_t ~ U[400, 6554] at 32768 Hz, K = 3,
+    SNR log-U[20, 1000], 2e5 samples each; one graph-captured launch set."""
+    rng = np.random.default_rng(3)
+    net = synth.network(3, 3)
+    base = {M: synth.make_point(3, M, 6554, 32768.0, 100.0, 300 + M, net=net) for M in (2, 4, 9, 16, 21)}
+    pts, counts = [], []
+    for p in range(n_points):
+        M = int(rng.choice([2, 4, 9, 16, 21]))
+        n_t = int(rng.integers(400, 6555))
+        snr = 20.0 * 50.0 ** rng.uniform()
+        b = base[M]
+        c0 = (6554 - n_t) // 2
+        pt = dict(b)
+        pt["Q"] = b["Q"][:, :, c0:c0 + n_t] * (snr / 100.0)
+        pt["U"] = b["U"] * (snr / 100.0) ** 2
+        pt["V"] = b["V"] * (snr / 100.0) ** 2
+        pt["t0"] = b["t0"] + c0 * b["dt"]
+        pts.append(pt)
+        counts.append(per_point)
+    N = n_points * per_point
+    log(f"c3: {n_points} points, {N} samples")
+    th = torch.empty((7, N), dtype=torch.float64, device="cuda")
+    chunk = 4_000_000
+    for s in range(0, N, chunk):
+        c = min(chunk, N - s)
+        th[:, s:s + c] = torch.as_tensor(synth.prior_samples(c, 1000 + s // chunk), device="cuda")
+    res = {}
+    M_of = [int(p["lm"].shape[0]) for p in pts]
+    flops = sum(flops_per_sample(3, M, int(p["lm"][:, 0].max())) * c for p, M, c in zip(pts, M_of, counts))
+    for prec in ("fp64", "mixed"):
+        plan = ile.Plan(pts, counts, precision=prec)
+        choice = plan.tune(th)
+        z = torch.empty(n_points, dtype=torch.float64, device="cuda")
+        ne = torch.empty(n_points, dtype=torch.float64, device="cuda")
+        plan.lnZ(th, lnZ_out=z, neff_out=ne)
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.lnZ(th, lnZ_out=z, neff_out=ne)
+        secs, _ = time_steps(g.replay, steps, 1, torch)
+        res[prec] = {"lnL_evals_per_s": N * steps / secs, "ms_per_step": 1e3 * secs / steps,
+                     "tuned_config": plan.config, "tuner_choice": choice,
+                     "alu_frac": flops * steps / secs / (1e12 * (PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS))}
+        if prec == "mixed":
+            res[prec]["refined"] = plan.refined()
+        plan.close()
+    return res
+
+
+def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64):
+    """4096 chains x 64 leapfrog-style gradient evaluations (K = 3, 9 modes,
+    SNR 600), the 64 steps captured into one graph."""
+    pt = synth.make_point(3, 9, 6554, 32768.0, 600.0, 4)
+    th0 = synth.prior_samples(1, 4)[:, 0]
+    sig = np.array([1e-3, 1e-3, 5e-3, 5e-3, 5e-3, 3e-6, 5e-3])
+    start = synth.perturbed_samples(th0, sig, chains, 5)
+    plan = ile.Plan([pt], [chains])
+    q = torch.as_tensor(start, device="cuda").contiguous()
+    c = q.clone()
+    c[3] = torch.cos(q[3])
+    c[6] = torch.log(q[6])
+    cq = c.clone()
+    p = torch.zeros_like(c)
+    sigt = torch.as_tensor(sig, device="cuda")[:, None]
+    eps = 0.1
+    th = torch.empty_like(q)
+    g = torch.empty_like(q)
+
+    def to_theta():
+        th.copy_(cq)
+        th[3] = torch.arccos(torch.clamp(cq[3], -1 + 1e-12, 1 - 1e-12))
+        th[6] = torch.exp(cq[6])
+
+    def run():
+        to_theta()
+        plan.grad(0, th, grad_out=g)
+        for _ in range(nsteps - 1):
+            p.add_(0.5 * eps * g)
+            cq.add_(eps * sigt * sigt * p)
+            to_theta()
+            plan.grad(0, th, grad_out=g)
+            p.add_(0.5 * eps * g)
+
+    run()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        run()
+    secs, _ = time_steps(graph.replay, steps, 1, torch)
+    # kernel-only rate from a separate eager pass with events
+    plan.profile(True)
+    run()
+    kms, launches = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    evals = chains * nsteps
+    return {"grad_evals_per_s": evals * steps / secs, "ms_per_graph": 1e3 * secs / steps,
+            "kernel_ms_avg": kms / max(1, launches), "chains": chains, "steps_per_chain": nsteps}
+
+
+def extra_c5(ile, synth, torch, steps):
+    """K = 5 (two 40-km-class), 21 modes, 13108 samples at 32768 Hz, SNR 1000:
+    1e7 samples in 10 chunks of 1e6 (ln Z merged), mixed precision; plus a
+    64-point batch of 2e5 samples each."""
+    pt = synth.make_point(5, 21, 13108, 32768.0, 1000.0, 5)
+    n = 10_000_000
+    th = torch.empty((7, n), dtype=torch.float64, device="cuda")
+    for s in range(0, n, 2_000_000):
+        th[:, s:s + 2_000_000] = torch.as_tensor(synth.prior_samples(2_000_000, 500 + s // 2_000_000), device="cuda")
+    res = {}
+    chunks = [1_000_000] * 10
+    for prec in ("fp64", "mixed"):
+        # ten chunks as ten "points" sharing the tables: one launch, then an LSE merge
+        plan = ile.Plan([pt] * 10, chunks, precision=prec)
+        z = torch.empty(10, dtype=torch.float64, device="cuda")
+        plan.lnZ(th, lnZ_out=z)
+        secs, _ = time_steps(lambda: plan.lnZ(th, lnZ_out=z), steps, 1, torch)
+        zz = z.cpu().numpy()
+        m = zz.max()
+        res[prec] = {"lnL_evals_per_s": n * steps / secs, "ms_per_step": 1e3 * secs / steps,
+                     "lnZ": float(m + math.log(np.mean(np.exp(zz - m))))}
+        plan.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--samples", type=int, default=1_000_000)
+    ap.add_argument("--extras", action="store_true", help="also run the C1/C3/C4/C5 workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "design only)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2609_37393_amd import ile, synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    ile.load()
+    n = args.samples
+    log(f"building inputs (n = {n})")
+    pt, th = c2_inputs(synth, n)
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    K, M = pt["Q"].shape[0], pt["Q"].shape[1]
+    lmax = int(pt["lm"][:, 0].max())
+
+    log("fp64 path")
+    r64 = run_path(ile, torch, pt, tht, "fp64", args.steps, args.warmup, tune=not args.no_tune)
+    log("mixed path")
+    r32 = run_path(ile, torch, pt, tht, "mixed", args.steps, args.warmup, tune=not args.no_tune)
+
+    fps = flops_per_sample(K, M, lmax)
+    value = n * args.steps / r64["secs"]
+    kern_s = r64["kernel_ms_avg"] / 1e3
+    achieved = fps * n / kern_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "lnL evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r64["secs"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3 detectors, 21 modes (l<=4), Q 6554 samples/mode/detector at 32768 Hz, "
+                        "network SNR 600, 1e6 prior extrinsic samples; lnL per sample + ln Z",
+            "n_samples": n,
+            "launch": r64["config"],
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "kernel": "k_tiles<double,3,4,MODE_LSE64>",
+            "kernel_ms_avg": r64["kernel_ms_avg"],
+            "flops_per_sample": fps,
+            "hbm_bytes_per_sample": bytes_per_sample(),
+        },
+        "mixed": {
+            "lnL_evals_per_s": n * args.steps / r32["secs"],
+            "ms_per_step": 1e3 * r32["secs"] / args.steps,
+            "speedup_vs_fp64": r64["secs"] / r32["secs"],
+            "kernel_ms_avg": r32["kernel_ms_avg"],
+            "alu_frac_of_fp32_peak": fps * n / (r32["kernel_ms_avg"] / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+            "refined_samples": r32["refined"],
+            "dlnZ_vs_fp64": abs(r32["lnZ"] - r64["lnZ"]),
+            "lnZ_err_bound": r32["lnZ_err_bound"],
+            "launch": r32["config"],
+        },
+        "lnZ": r64["lnZ"],
+        "neff": r64["neff"],
+    }
+    gpu_lnL = r64["lnL"].cpu().numpy()
+    l32 = r32["lnL"].cpu().numpy()
+    top = gpu_lnL >= gpu_lnL.max() - 20.0
+    out["mixed"]["max_dlnL_posterior_set_vs_fp64"] = float(np.abs(l32[top] - gpu_lnL[top]).max())
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        cb, par = cpu_baseline(pt, th, gpu_lnL)
+        out["cpu_baseline"] = cb
+        out["parity"] = par
+    if args.extras:
+        for name, fn in (("c1", extra_c1), ("c4", extra_c4), ("c5", extra_c5), ("c3", extra_c3)):
+            log(f"extra {name}")
+            try:
+                out[name] = fn(ile, synth, torch, max(3, args.steps // 10))
+            except Exception as e:  # report, keep the headline line
+                out[name] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * rift_ile.h -- C ABI of the MI355X (gfx950) factored extrinsic likelihood.
+ *
+ * The library evaluates, for every extrinsic sample
+ *   theta = (ra, dec, psi, incl, phiref, tref, dist)
+ * of one intrinsic point, the factored log-likelihood of the paper's
+ * Eq. (def:lnL:Decomposed) (matrix form Eq. (lnL:MatrixForm)):
+ *
+ *   lnL = x Re sum_k sum_lm conj(F_k Y_lm) Q_{k,lm}(t_k)
+ *       - x^2/4 sum_k [ |F_k|^2 Y^H U_k Y + Re(F_k^2 Y^T V_k Y) ],   x = D_ref / dist,
+ *
+ * with the static complex antenna factor F_k = F+_k + i Fx_k of detector k, the
+ * arrival time t_k = tref - r_k . N (N the unit vector towards the source), the
+ * spin-weighted harmonics Y_lm = -2Y_lm(incl, phiref) of Eq. (strain_mode), and
+ * Q read between its stored samples by the four-point cubic of
+ * Eq. (q-time-pregrid) (4-point Lagrange on nodes j-1..j+2; nodes outside the
+ * stored window read zero).  It then reduces the weighted samples into the
+ * Monte-Carlo marginal likelihood of Eq. (lnL:MonteCarlo),
+ *
+ *   ln Z = ln[ (1/N) sum_i exp(lnL_i + lnw_i) ],   lnw_i = ln(p/p_s) of sample i,
+ *
+ * and the effective sample size of Eq. (neff), n_eff = sum_i p_i / max_i p_i.
+ * The gradient entry points return d lnL / d(ra, dec, psi, cos incl, phiref,
+ * tref, ln dist) (Sec. "The differentiable likelihood").
+ *
+ * Conventions (where the paper is silent or inconsistent):
+ *   - Earth-fixed frame: x towards the Greenwich meridian on the equator, z
+ *     north.  Greenwich hour angle gha = gmst_rad - ra.  N = (cos dec cos gha,
+ *     -cos dec sin gha, sin dec).  Polarisation axes X = -cos psi e_a + sin psi
+ *     e_d, Y = sin psi e_a + cos psi e_d with e_a = (sin gha, cos gha, 0),
+ *     e_d = (-sin dec cos gha, sin dec sin gha, cos dec).
+ *     F+ = D:(X X^T - Y Y^T), Fx = D:(X Y^T + Y X^T).
+ *   - All times are seconds relative to one geocentric reference epoch: Q is
+ *     sampled at t_j = t0 + j dt, tref is on the same axis.
+ *
+ * Memory: bulk arrays are DEVICE pointers owned by the caller.  Small metadata
+ * (mode list, detector geometry, per-point sample counts) are HOST pointers.
+ * Complex numbers are interleaved (re, im) doubles.  The library keeps no
+ * pointer to caller memory after a call returns, except a plan, which keeps
+ * copies of what it needs.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Evaluation
+ * calls on a plan only enqueue work and return; outputs are valid once the
+ * stream has reached them.  Plan creation and destruction synchronise the
+ * stream (they allocate and free device memory), so the one-shot entry points
+ * (which create and destroy a plan internally) return only after their work
+ * has finished.
+ *
+ * Errors: a negative status means nothing was enqueued and nothing written
+ * (invalid arguments are detected on the host before any launch), except
+ * RIFT_EDEVICE, which reports a failed HIP call (e.g. a launch).  Faults that
+ * happen asynchronously on the device surface at the next synchronisation.
+ * Non-finite sample values are not errors: that sample's lnL is NaN, and so is
+ * the ln Z of its point.  lnw = -inf excludes a sample from ln Z.
+ */
+#ifndef RIFT_ILE_H
+#define RIFT_ILE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RIFT_ILE_VERSION 1
+#define RIFT_ILE_MAX_DET 8   /* detectors per point */
+#define RIFT_ILE_MAX_MODES 25 /* modes per point */
+#define RIFT_ILE_MAX_L 8     /* largest l of a mode; |m| <= l */
+
+typedef enum {
+  RIFT_OK = 0,
+  RIFT_EINVAL = -1,      /* bad argument (null pointer, size or mode out of range) */
+  RIFT_EDEVICE = -2,     /* a HIP runtime call failed */
+  RIFT_ENOMEM = -3,      /* device or host allocation failed */
+  RIFT_EUNSUPPORTED = -4 /* valid request this build does not implement */
+} rift_status;
+
+typedef enum {
+  RIFT_FP64 = 0, /* every step in IEEE double */
+  RIFT_MIXED = 1 /* FP32 pass with an a-priori error bound per sample, FP64
+                    recompute of every sample that can matter for ln Z, FP64
+                    accumulation across detectors and FP64 log-sum-exp */
+} rift_precision;
+
+/* One intrinsic point lambda: the precomputed arrays of Eq. (QUV) and the
+ * detector network. */
+typedef struct {
+  int32_t n_det;            /* K, 1..RIFT_ILE_MAX_DET */
+  int32_t n_modes;          /* M, 1..RIFT_ILE_MAX_MODES */
+  int32_t n_t;              /* samples of Q per mode and detector, >= 4 */
+  const int32_t *lm;        /* HOST [M][2]: (l, m), 2 <= l <= RIFT_ILE_MAX_L, |m| <= l, no repeats */
+  double t0;                /* time of Q sample 0 (s) */
+  double dt;                /* Q sample spacing (s), > 0 */
+  const double *Q;          /* DEVICE [K][M][n_t] complex: Q_{k,lm}(t_j), paper index order */
+  const double *U;          /* DEVICE [K][M][M] complex, U_{k,lm,l'm'}, Hermitian (not checked) */
+  const double *V;          /* DEVICE [K][M][M] complex, V_{k,lm,l'm'}, symmetric (not checked) */
+  const double *det_tensor; /* HOST [K][3][3] response tensor D_k, symmetric */
+  const double *det_pos;    /* HOST [K][3] detector position / c (light-seconds) */
+  double gmst_rad;          /* sidereal angle of the static response (rad) */
+  double d_ref;             /* D_ref of Eq. (strain_mode), same unit as dist */
+} rift_ile_point;
+
+/* theta layout used by every entry point: DEVICE, structure of arrays
+ * [7][n] doubles: ra, dec, psi, incl, phiref, tref (s), dist.
+ * grad layout: DEVICE [7][n] doubles: d/d ra, dec, psi, cos(incl), phiref,
+ * tref, ln(dist). */
+
+/* lnL of n samples of one point, Eq. (def:lnL:Decomposed).
+ * lnL: DEVICE [n] output.  precision: rift_precision (RIFT_MIXED returns the
+ * FP32 pass; every value is within its a-priori bound of the FP64 result).
+ * n == 0 is a no-op. */
+int rift_ile_lnL(const rift_ile_point *pt, int64_t n, const double *theta, double *lnL,
+                 int precision, void *stream);
+
+/* ln Z and n_eff of n_points intrinsic points, Eqs. (lnL:MonteCarlo), (neff).
+ * n_per_point: HOST [n_points], each >= 1; the samples of point p are the
+ * n_per_point[p] consecutive columns of theta after those of points < p.
+ * theta: DEVICE [7][N] with N = sum(n_per_point).  lnw: DEVICE [N] or NULL
+ * (all zero).  lnZ, neff: DEVICE [n_points] outputs (neff may be NULL).
+ * lnL: DEVICE [N] output of every sample's lnL, or NULL.
+ * All points are evaluated by one persistent kernel launch. */
+int rift_ile_lnZ(const rift_ile_point *pts, int32_t n_points, const int64_t *n_per_point,
+                 const double *theta, const double *lnw, double *lnZ, double *neff, double *lnL,
+                 int precision, void *stream);
+
+/* lnL and its gradient for n samples of one point (FP64).  lnL: DEVICE [n]
+ * (may be NULL); grad: DEVICE [7][n]. */
+int rift_ile_grad(const rift_ile_point *pt, int64_t n, const double *theta, double *lnL,
+                  double *grad, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Plans: points prepared once (repacked tables, harmonic-basis coefficients,
+ * launch configuration), then evaluated many times without any allocation,
+ * host synchronisation or host-to-device copy, so that the evaluation calls
+ * can be captured into a HIP graph.                                          */
+typedef struct rift_ile_plan_s *rift_ile_plan;
+
+/* Prepare n_points points for batches whose point p has n_per_point[p]
+ * samples (HOST array, each >= 1).  Enqueues the preparation on `stream`
+ * (device memory for the plan is allocated synchronously).  *out receives the
+ * plan. */
+int rift_ile_plan_create(const rift_ile_point *pts, int32_t n_points, const int64_t *n_per_point,
+                         int precision, void *stream, rift_ile_plan *out);
+
+/* ln Z / n_eff of every point of the plan for one batch laid out as in
+ * rift_ile_lnZ.  lnZ_err: DEVICE [n_points] or NULL, receives an upper bound on
+ * |ln Z - ln Z_FP64| (RIFT_MIXED) or 0 (RIFT_FP64). */
+int rift_ile_plan_lnZ(rift_ile_plan plan, const double *theta, const double *lnw, double *lnZ,
+                      double *neff, double *lnL, double *lnZ_err, void *stream);
+
+/* lnL (may be NULL) and gradient of n samples of point `point` of the plan. */
+int rift_ile_plan_grad(rift_ile_plan plan, int32_t point, int64_t n, const double *theta,
+                       double *lnL, double *grad, void *stream);
+
+/* Autotuner: time the candidate launch shapes on this batch and keep the
+ * fastest (synchronises `stream`; not capturable). Returns the chosen index. */
+int rift_ile_plan_tune(rift_ile_plan plan, const double *theta, const double *lnw, void *stream);
+
+/* Launch shape of the plan: threads per block, samples per tile, persistent
+ * blocks per CU.  Setting validates on the host. */
+typedef struct {
+  int32_t block;        /* 64, 128, 256, 512 */
+  int32_t tile_blocks;  /* samples per tile = block * tile_blocks */
+  int32_t blocks_per_cu; /* persistent grid = blocks_per_cu * CUs */
+} rift_ile_config;
+int rift_ile_plan_get_config(rift_ile_plan plan, rift_ile_config *cfg);
+int rift_ile_plan_set_config(rift_ile_plan plan, const rift_ile_config *cfg);
+
+/* Statistics of the last rift_ile_plan_lnZ call on the plan (synchronises the
+ * stream it ran on): samples recomputed in FP64 by the mixed path, summed over
+ * points. */
+int rift_ile_plan_refined(rift_ile_plan plan, int64_t *n_refined);
+
+/* Timing of the plan's main evaluation kernel (the per-sample likelihood
+ * kernel of rift_ile_plan_lnZ, or the gradient kernel of rift_ile_plan_grad):
+ * enable != 0 clears the record and starts bracketing every such launch with
+ * HIP events on its stream; enable == 0 stops.  _read synchronises on the
+ * recorded events and returns the summed kernel time (ms) and the number of
+ * launches.  Not for use under graph capture. */
+int rift_ile_plan_profile(rift_ile_plan plan, int enable);
+int rift_ile_plan_profile_read(rift_ile_plan plan, double *total_ms, int64_t *launches);
+
+int rift_ile_plan_destroy(rift_ile_plan plan);
+
+const char *rift_ile_strerror(int status);
+int rift_ile_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIFT_ILE_H */

@@ -1,0 +1,436 @@
+// Device side of the factored extrinsic likelihood for gfx950.
+//
+// One lane evaluates one extrinsic sample.  Per sample (Eq. (def:lnL:Decomposed)):
+//   sky frame and arrival times in FP64 (the delay feeds a sub-sample read),
+//   antenna factors F_k = F+ + i Fx from the shared polarisation tensors,
+//   -2Y_lm(incl, phiref) from per-mode Fourier coefficients in incl,
+//   the data term x Re sum conj(F_k Y) Q_k(t_k) with a four-point Lagrange read
+//   of the time-major table Q[k][t][mode] (taps outside the window read 0),
+//   the model-norm term x^2/4 sum_k [|F_k|^2 a_k + Re(F_k^2 b_k)].
+//
+// Model-norm term.  a_k = Y^H U_k Y and b_k = Y^T V_k Y depend on the sample
+// only through (incl, phiref), and both are finite trigonometric polynomials:
+// d^l_{m,2}(incl) has degree l in incl (even/odd in incl for even/odd m), and
+// the phiref dependence of a pair of modes is e^{i(m'-m) phi} (a_k) or
+// e^{i(m+m') phi} (b_k).  So with L = max l,
+//   g_c(incl, phi) in { a_k/4, Re b_k/4, -Im b_k/4 }
+//   = sum_b C[b][c] beta_b(incl, phi),
+//   beta_b in { cos(n incl) [1 | cos(q phi) | sin(q phi)], q even,
+//               sin(n incl) [cos(q phi) | sin(q phi)],     q odd },
+// n <= 2L, q <= 2L, and the per-sample work is one contraction of the basis
+// values with the uniform coefficient table C (scalar loads).  C is exact up
+// to rounding: a setup kernel samples g_c on a grid finer than twice the
+// degree and projects (discrete orthogonality).  The finite angular harmonic
+// content this relies on is the paper's Eq. (ap:angleharm) argument applied to
+// (incl, phiref).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rift {
+
+constexpr int KMAX = 8;    // detectors
+constexpr int MMAX = 25;   // modes
+constexpr int LMAXC = 8;   // largest l
+
+template <class R>
+struct C2 {
+  R x, y;
+};
+
+// Per-point description, resident in device memory (uniform per block).
+struct PointDesc {
+  int32_t K;        // real detectors
+  int32_t M;        // modes
+  int32_t n_t;      // table samples per detector and mode
+  int32_t L;        // mode class: max l rounded to 2, 3, 4 or 8
+  int32_t B;        // basis functions of the class
+  int32_t KT;       // detector class (padded K)
+  int32_t m_min;    // smallest m (modes are stored sorted by m)
+  int32_t pad0;
+  int64_t n;        // samples of this point in a batch
+  int64_t s0;       // first sample column of this point in a batch
+  double t0, inv_dt, gmst, d_ref;
+  double T;         // mixed path: refinement margin (nats)
+  double lnN;       // ln(n)
+  double dten[KMAX][6];   // D00, D11, D22, 2 D01, 2 D02, 2 D12
+  double rpos[KMAX][3];   // light-seconds
+  int32_t m[MMAX];        // m of internal mode i (sorted ascending)
+  int32_t odd[MMAX];      // m odd
+  double ycoef[MMAX][LMAXC + 1];  // d^l_{m,2}(incl) sqrt((2l+1)/4pi) = sum_n ycoef cos|sin(n incl)
+  float ycoef32[MMAX][LMAXC + 1];
+  float dten32[KMAX][6];
+  // mixed path: |lnL_FP32 - lnL_FP64| <= x bnd_d + x^2 sum_k (|F_k|^2 + 1e-6) bnd_q[k]
+  double bnd_d;
+  double bnd_q[KMAX];
+  const double* Q64;      // [KT][n_t][M] complex
+  const float* Q32;       // [KT][n_t][M] complex
+  const double* C64;      // [B][3 KT]
+  const float* C32;       // [B][3 KT]
+};
+
+// Work unit: samples [s, s + cnt) (global columns) of point p.
+struct Tile {
+  int32_t p;
+  int32_t cnt;
+  int64_t s;
+};
+
+template <int L>
+struct Cls {
+  static constexpr int NI = 2 * L;                        // incl degree of g_c
+  static constexpr int NQ = 2 * L;                        // phi degree of g_c
+  static constexpr int MAXM = (L == 2) ? 5 : (L == 3) ? 12 : (L == 4) ? 21 : 25;
+  static constexpr int NY = L + 1;                        // Fourier terms of d_lm
+  static constexpr int B = (NI + 1) + (NQ / 2) * 2 * (NI + 1) + ((NQ + 1) / 2) * 2 * NI;
+};
+
+__device__ __forceinline__ void sincos_(double a, double* s, double* c) { sincos(a, s, c); }
+__device__ __forceinline__ void sincos_(float a, float* s, float* c) { sincosf(a, s, c); }
+
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Address spaces: the point description and the coefficient tables are read
+// with uniform addresses through the constant space (scalar loads into
+// SGPRs); per-lane data (samples, the Q table, outputs) through the global
+// space (vector loads).
+#define RIFT_CONST __attribute__((address_space(4)))
+#define RIFT_GLOBAL __attribute__((address_space(1)))
+
+struct PointDesc;
+typedef const RIFT_CONST PointDesc* PDesc;
+
+template <class T>
+__device__ __forceinline__ const RIFT_CONST T* as_const(const T* p) {
+  return (const RIFT_CONST T*)p;
+}
+template <class T>
+__device__ __forceinline__ const RIFT_GLOBAL T* as_global(const T* p) {
+  return (const RIFT_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ RIFT_GLOBAL T* as_global_w(T* p) {
+  return (RIFT_GLOBAL T*)p;
+}
+
+// Identity the optimiser cannot see through.  Applied to the (uniform) point
+// pointer at the top of every sample iteration so that the ~10^3 uniform
+// coefficient loads of a sample stay scalar loads inside the loop instead of
+// being hoisted out of it.
+template <class T>
+__device__ __forceinline__ const RIFT_CONST T* opaque(const T* p) {
+  uint64_t v = (uint64_t)p;
+  asm volatile("" : "+s"(v));
+  return (const RIFT_CONST T*)v;
+}
+template <class T>
+__device__ __forceinline__ const RIFT_CONST T* opaque(const RIFT_CONST T* p) {
+  uint64_t v = (uint64_t)p;
+  asm volatile("" : "+s"(v));
+  return (const RIFT_CONST T*)v;
+}
+template <class R>
+__device__ __forceinline__ C2<R> ldq(const RIFT_GLOBAL R* q, int64_t idx) {
+  C2<R> v;
+  v.x = q[2 * idx];
+  v.y = q[2 * idx + 1];
+  return v;
+}
+
+template <class R>
+struct Tab;
+template <>
+struct Tab<double> {
+  static __device__ __forceinline__ const RIFT_GLOBAL double* Q(PDesc P) { return as_global(P->Q64); }
+  static __device__ __forceinline__ const RIFT_CONST double* C(PDesc P) { return as_const(P->C64); }
+  static __device__ __forceinline__ double y(PDesc P, int i, int n) { return P->ycoef[i][n]; }
+  static __device__ __forceinline__ double d(PDesc P, int k, int a) { return P->dten[k][a]; }
+};
+template <>
+struct Tab<float> {
+  static __device__ __forceinline__ const RIFT_GLOBAL float* Q(PDesc P) { return as_global(P->Q32); }
+  static __device__ __forceinline__ const RIFT_CONST float* C(PDesc P) { return as_const(P->C32); }
+  static __device__ __forceinline__ float y(PDesc P, int i, int n) { return P->ycoef32[i][n]; }
+  static __device__ __forceinline__ float d(PDesc P, int k, int a) { return P->dten32[k][a]; }
+};
+
+// Result of one sample evaluation.
+struct Eval {
+  double lnL;
+  float bound;  // a-priori |lnL - lnL_FP64| bound (FP32 arithmetic only)
+};
+
+// Everything per sample.  R is the arithmetic type of the bulk (FP64 or FP32);
+// the sky frame, delays and the final combination are always FP64.
+//
+// `trig` is this lane's column of a block-shared scratch array (stride
+// `ts` elements) holding cos(n incl), n = 0..NI, then sin(n incl): the
+// model-norm contraction runs as a loop over basis rows (a handful of
+// scalar coefficient loads per iteration) and reads these by index.
+template <class R, int KT, int L, bool BOUND>
+__device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int ts, double ra,
+                                            double dec, double psi, double incl, double phi,
+                                            double tref, double dist) {
+  typedef Cls<L> CL;
+  constexpr int NI = CL::NI;
+  constexpr int NY = CL::NY;
+  const int M = P->M;
+  const int n_t = P->n_t;
+
+  // --- sky frame (FP64) --------------------------------------------------
+  double sg, cg, sd, cd;
+  sincos_(P->gmst - ra, &sg, &cg);
+  sincos_(dec, &sd, &cd);
+  const double N0 = cd * cg, N1 = -cd * sg, N2 = sd;
+
+  // --- polarisation tensors (R) ------------------------------------------
+  R sp, cp;
+  sincos_((R)psi, &sp, &cp);
+  const R ea0 = (R)sg, ea1 = (R)cg;
+  const R ed0 = (R)(-sd * cg), ed1 = (R)(sd * sg), ed2 = (R)cd;
+  const R X0 = -cp * ea0 + sp * ed0, X1 = -cp * ea1 + sp * ed1, X2 = sp * ed2;
+  const R Y0 = sp * ea0 + cp * ed0, Y1 = sp * ea1 + cp * ed1, Y2 = cp * ed2;
+  const R ep[6] = {X0 * X0 - Y0 * Y0, X1 * X1 - Y1 * Y1, X2 * X2 - Y2 * Y2,
+                   X0 * X1 - Y0 * Y1, X0 * X2 - Y0 * Y2, X1 * X2 - Y1 * Y2};
+  const R ex[6] = {2 * X0 * Y0, 2 * X1 * Y1, 2 * X2 * Y2,
+                   X0 * Y1 + Y0 * X1, X0 * Y2 + Y0 * X2, X1 * Y2 + Y1 * X2};
+
+  // --- harmonics in incl (Chebyshev recurrences) --------------------------
+  R si, ci;
+  sincos_((R)incl, &si, &ci);
+  R cn[NY], sn[NY];
+  {
+    R c0 = 1, c1 = ci, s0 = 0, s1 = si;
+#pragma unroll
+    for (int n = 0; n <= NI; ++n) {
+      const R c = (n == 0) ? c0 : c1;
+      const R s = (n == 0) ? s0 : s1;
+      if (n < NY) {
+        cn[n] = c;
+        sn[n] = s;
+      }
+      trig[n * ts] = c;
+      trig[(NI + 1 + n) * ts] = s;
+      if (n > 0) {
+        const R c2 = 2 * ci * c1 - c0, s2 = 2 * ci * s1 - s0;
+        c0 = c1;
+        c1 = c2;
+        s0 = s1;
+        s1 = s2;
+      }
+    }
+  }
+  R sf, cf;
+  sincos_((R)phi, &sf, &cf);
+
+  // --- antenna factors and stencils per detector --------------------------
+  R Fre[KT], Fim[KT];
+  R w[KT][4];
+  int64_t rowoff[KT][4];
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    R fp = 0, fx = 0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      fp += Tab<R>::d(P, k, a) * ep[a];
+      fx += Tab<R>::d(P, k, a) * ex[a];
+    }
+    Fre[k] = fp;
+    Fim[k] = fx;
+    const RIFT_CONST double* r = P->rpos[k];
+    const double tk = tref - (r[0] * N0 + r[1] * N1 + r[2] * N2);
+    double u = (tk - P->t0) * P->inv_dt;
+    if (!(fabs(u) < 1.0e9)) {  // non-finite (or absurd) time: poison the sample
+      bad = true;
+      u = 0.0;
+    }
+    const double jf = floor(u);
+    const R s = (R)(u - jf);
+    const int j = (int)jf;
+    w[k][0] = -s * (s - 1) * (s - 2) * (R)(1.0 / 6.0);
+    w[k][1] = (s + 1) * (s - 1) * (s - 2) * (R)0.5;
+    w[k][2] = -(s + 1) * s * (s - 2) * (R)0.5;
+    w[k][3] = (s + 1) * s * (s - 1) * (R)(1.0 / 6.0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      int row = j - 1 + t;
+      const bool ok = (row >= 0) && (row < n_t);
+      w[k][t] = ok ? w[k][t] : (R)0;
+      row = row < 0 ? 0 : (row >= n_t ? n_t - 1 : row);
+      rowoff[k][t] = ((int64_t)k * n_t + row) * M;
+    }
+  }
+
+  // --- data term: loop over modes; Y_i = d_i(incl) e^{i m_i phi} ----------
+  // modes are sorted by m, so the phase walks upward from e^{i m_min phi}
+  const RIFT_GLOBAL R* Qt = Tab<R>::Q(P);
+  C2<R> Z[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) Z[k].x = Z[k].y = 0;
+  {
+    C2<R> ph;
+    ph.x = 1;
+    ph.y = 0;
+    const int mmin = P->m_min;
+    for (int t = 0; t < -mmin; ++t) {
+      const R a = ph.x * cf + ph.y * sf, bb = ph.y * cf - ph.x * sf;
+      ph.x = a;
+      ph.y = bb;
+    }
+    int mc = mmin < 0 ? mmin : 0;
+    for (int i = 0; i < M; ++i) {
+      const int mi = P->m[i];
+      while (mc < mi) {
+        const R a = ph.x * cf - ph.y * sf, bb = ph.y * cf + ph.x * sf;
+        ph.x = a;
+        ph.y = bb;
+        ++mc;
+      }
+      R d = 0;
+      if (P->odd[i]) {
+#pragma unroll
+        for (int n = 1; n < NY; ++n) d += Tab<R>::y(P, i, n) * sn[n];
+      } else {
+#pragma unroll
+        for (int n = 0; n < NY; ++n) d += Tab<R>::y(P, i, n) * cn[n];
+      }
+      const R yx = d * ph.x, yy = d * ph.y;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const C2<R> q0 = ldq(Qt, rowoff[k][0] + i), q1 = ldq(Qt, rowoff[k][1] + i);
+        const C2<R> q2 = ldq(Qt, rowoff[k][2] + i), q3 = ldq(Qt, rowoff[k][3] + i);
+        const R qx = w[k][0] * q0.x + w[k][1] * q1.x + w[k][2] * q2.x + w[k][3] * q3.x;
+        const R qy = w[k][0] * q0.y + w[k][1] * q1.y + w[k][2] * q2.y + w[k][3] * q3.y;
+        Z[k].x += yx * qx + yy * qy;
+        Z[k].y += yx * qy - yy * qx;
+      }
+    }
+  }
+  double data = 0.0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) data += (double)(Fre[k] * Z[k].x) + (double)(Fim[k] * Z[k].y);
+
+  // --- model-norm term: basis contraction (loop over basis rows) ----------
+  const RIFT_CONST R* Cc = Tab<R>::C(P);
+  R acc[3 * KT];
+#pragma unroll
+  for (int c = 0; c < 3 * KT; ++c) acc[c] = 0;
+  {
+    // q = 0: cos(n incl)
+#pragma unroll 1
+    for (int n = 0; n <= NI; ++n) {
+      const R beta = trig[n * ts];
+      const RIFT_CONST R* cr = Cc + n * 3 * KT;
+#pragma unroll
+      for (int c = 0; c < 3 * KT; ++c) acc[c] += cr[c] * beta;
+    }
+    int b = NI + 1;
+    C2<R> eq;
+    eq.x = cf;
+    eq.y = sf;
+#pragma unroll 1
+    for (int q = 1; q <= NI; ++q) {
+      // even q pairs with cos(n incl) (n = 0..NI), odd q with sin(n incl) (n = 1..NI)
+      const int odd = q & 1;
+      const int n0 = odd;
+      const int base = odd ? (NI + 1) : 0;
+#pragma unroll 1
+      for (int n = n0; n <= NI; ++n, b += 2) {
+        const R t = trig[(base + n) * ts];
+        const R b1 = t * eq.x, b2 = t * eq.y;
+        const RIFT_CONST R* cr = Cc + b * 3 * KT;
+#pragma unroll
+        for (int c = 0; c < 3 * KT; ++c) acc[c] += cr[c] * b1 + cr[3 * KT + c] * b2;
+      }
+      const R ex_ = eq.x * cf - eq.y * sf, ey_ = eq.x * sf + eq.y * cf;
+      eq.x = ex_;
+      eq.y = ey_;
+    }
+  }
+  double quad = 0.0;
+  double wq = 0.0;  // sum_k (|F_k|^2 + 1e-6) bnd_q[k]  (error bound)
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const R f2 = Fre[k] * Fre[k] + Fim[k] * Fim[k];
+    const R g2r = Fre[k] * Fre[k] - Fim[k] * Fim[k];
+    const R g2i = 2 * Fre[k] * Fim[k];
+    quad += (double)(f2 * acc[3 * k]) + (double)(g2r * acc[3 * k + 1]) +
+            (double)(g2i * acc[3 * k + 2]);
+    if (BOUND) wq += ((double)f2 + 1e-6) * P->bnd_q[k];
+  }
+
+  const double x = P->d_ref / dist;
+  Eval e;
+  e.lnL = x * data - x * x * quad;
+  if (bad) e.lnL = __builtin_nan("");
+  e.bound = 0.0f;
+  if (BOUND) e.bound = (float)(x * P->bnd_d + x * x * wq);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// log-sum-exp pairs (max, sum exp(l - max)); NaN propagates through the sum.
+// ---------------------------------------------------------------------------
+struct MS {
+  double m, s;
+};
+__device__ __forceinline__ MS ms_of(double l) {
+  MS r;
+  if (l != l) {
+    r.m = -__builtin_inf();
+    r.s = __builtin_nan("");
+  } else if (l == -__builtin_inf()) {
+    r.m = l;
+    r.s = 0.0;
+  } else {
+    r.m = l;
+    r.s = 1.0;
+  }
+  return r;
+}
+__device__ __forceinline__ MS ms_combine(MS a, MS b) {
+  MS r;
+  r.m = fmax(a.m, b.m);
+  const double ta = (a.s == 0.0) ? 0.0 : a.s * exp(a.m - r.m);
+  const double tb = (b.s == 0.0) ? 0.0 : b.s * exp(b.m - r.m);
+  r.s = ta + tb;
+  return r;
+}
+__device__ __forceinline__ MS ms_wave(MS v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    MS o;
+    o.m = __shfl_xor(v.m, off);
+    o.s = __shfl_xor(v.s, off);
+    v = ms_combine(v, o);
+  }
+  return v;
+}
+// Block-wide reduction in a fixed order (deterministic).  `sh` holds one MS
+// per wave.
+__device__ __forceinline__ MS ms_block(MS v, MS* sh) {
+  v = ms_wave(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  MS r = sh[0];
+  for (int w = 1; w < nw; ++w) r = ms_combine(r, sh[w]);
+  return r;
+}
+
+__device__ __forceinline__ double dmax_wave(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double dsum_wave(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+}  // namespace rift

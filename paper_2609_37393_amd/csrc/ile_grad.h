@@ -1,0 +1,307 @@
+// Hand-written gradient of the factored log-likelihood (FP64), one lane per
+// sample: lnL and d lnL / d(ra, dec, psi, cos incl, phiref, tref, ln dist)
+// (Sec. "The differentiable likelihood": the same closed form, differentiated).
+//
+// With gha = gmst - ra, the rotating-frame identities used below are
+//   dN/dgha = -cos(dec) e_a,  de_a/dgha = cos(dec) N - sin(dec) e_d,  de_d/dgha = sin(dec) e_a,
+//   dN/ddec = e_d,            de_a/ddec = 0,                          de_d/ddec = -N,
+// so that dX/dgha = -cos(psi) cos(dec) N + sin(dec) Y, dY/dgha = sin(psi) cos(dec) N - sin(dec) X,
+// dX/ddec = -sin(psi) N, dY/ddec = -cos(psi) N, dF/dpsi = -2i F.  With
+// S_NX = 2 N.D.X and S_NY = 2 N.D.Y:
+//   dF+/dgha = -cpsi cdec S_NX - spsi cdec S_NY + 2 sdec Fx
+//   dFx/dgha = -cpsi cdec S_NY + spsi cdec S_NX - 2 sdec F+
+//   dF+/ddec = -spsi S_NX + cpsi S_NY,   dFx/ddec = -spsi S_NY - cpsi S_NX
+//   dt_k/dgha = cdec r_k.e_a,  dt_k/ddec = -r_k.e_d,  dt_k/dtref = 1.
+// The table read contributes dQ/dt from the derivative of the Lagrange weights
+// (the derivative within the cell; the cubic is only C0 at the nodes).
+#pragma once
+
+#include "ile_device.h"
+
+namespace rift {
+
+template <int KT, int L>
+__device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, int ts, double ra,
+                                            double dec, double psi, double incl, double phi,
+                                            double tref, double dist, double g[7]) {
+  typedef Cls<L> CL;
+  constexpr int NI = CL::NI;
+  constexpr int NY = CL::NY;
+  const int M = P->M;
+  const int n_t = P->n_t;
+  const RIFT_GLOBAL double* Qt = as_global(P->Q64);
+
+  double sg, cg, sd, cd, sp, cp;
+  sincos(P->gmst - ra, &sg, &cg);
+  sincos(dec, &sd, &cd);
+  sincos(psi, &sp, &cp);
+  const double N[3] = {cd * cg, -cd * sg, sd};
+  const double ea[3] = {sg, cg, 0.0};
+  const double ed[3] = {-sd * cg, sd * sg, cd};
+  double X[3], Y[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    X[a] = -cp * ea[a] + sp * ed[a];
+    Y[a] = sp * ea[a] + cp * ed[a];
+  }
+
+  // harmonics in incl (registers up to l, scratch column up to 2l)
+  double si, ci;
+  sincos(incl, &si, &ci);
+  double cn[NY], sn[NY];
+  {
+    double c0 = 1.0, c1 = ci, s0 = 0.0, s1 = si;
+#pragma unroll
+    for (int n = 0; n <= NI; ++n) {
+      const double c = (n == 0) ? c0 : c1;
+      const double s = (n == 0) ? s0 : s1;
+      if (n < NY) {
+        cn[n] = c;
+        sn[n] = s;
+      }
+      trig[n * ts] = c;
+      trig[(NI + 1 + n) * ts] = s;
+      if (n > 0) {
+        const double c2 = 2.0 * ci * c1 - c0, s2 = 2.0 * ci * s1 - s0;
+        c0 = c1;
+        c1 = c2;
+        s0 = s1;
+        s1 = s2;
+      }
+    }
+  }
+  double sf, cf;
+  sincos(phi, &sf, &cf);
+
+  // antenna factors, their derivatives and the stencils
+  double Fp[KT], Fx[KT], dFg[KT][2], dFd[KT][2], dtg[KT], dtd[KT];
+  double w[KT][4], wd[KT][4];
+  int64_t rowoff[KT][4];
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const RIFT_CONST double* dt6 = P->dten[k];
+    const double D00 = dt6[0], D11 = dt6[1], D22 = dt6[2];
+    const double D01 = 0.5 * dt6[3], D02 = 0.5 * dt6[4], D12 = 0.5 * dt6[5];
+    double DX[3], DY[3];
+    DX[0] = D00 * X[0] + D01 * X[1] + D02 * X[2];
+    DX[1] = D01 * X[0] + D11 * X[1] + D12 * X[2];
+    DX[2] = D02 * X[0] + D12 * X[1] + D22 * X[2];
+    DY[0] = D00 * Y[0] + D01 * Y[1] + D02 * Y[2];
+    DY[1] = D01 * Y[0] + D11 * Y[1] + D12 * Y[2];
+    DY[2] = D02 * Y[0] + D12 * Y[1] + D22 * Y[2];
+    const double fp = X[0] * DX[0] + X[1] * DX[1] + X[2] * DX[2] - (Y[0] * DY[0] + Y[1] * DY[1] + Y[2] * DY[2]);
+    const double fx = 2.0 * (X[0] * DY[0] + X[1] * DY[1] + X[2] * DY[2]);
+    const double SNX = 2.0 * (N[0] * DX[0] + N[1] * DX[1] + N[2] * DX[2]);
+    const double SNY = 2.0 * (N[0] * DY[0] + N[1] * DY[1] + N[2] * DY[2]);
+    Fp[k] = fp;
+    Fx[k] = fx;
+    dFg[k][0] = -cp * cd * SNX - sp * cd * SNY + 2.0 * sd * fx;
+    dFg[k][1] = -cp * cd * SNY + sp * cd * SNX - 2.0 * sd * fp;
+    dFd[k][0] = -sp * SNX + cp * SNY;
+    dFd[k][1] = -sp * SNY - cp * SNX;
+
+    const RIFT_CONST double* r = P->rpos[k];
+    const double tk = tref - (r[0] * N[0] + r[1] * N[1] + r[2] * N[2]);
+    dtg[k] = cd * (r[0] * ea[0] + r[1] * ea[1]);
+    dtd[k] = -(r[0] * ed[0] + r[1] * ed[1] + r[2] * ed[2]);
+    double u = (tk - P->t0) * P->inv_dt;
+    if (!(fabs(u) < 1.0e9)) {
+      bad = true;
+      u = 0.0;
+    }
+    const double jf = floor(u);
+    const double s = u - jf;
+    const int j = (int)jf;
+    const double s2 = s * s;
+    const double idt = P->inv_dt;
+    w[k][0] = -s * (s - 1.0) * (s - 2.0) / 6.0;
+    w[k][1] = (s + 1.0) * (s - 1.0) * (s - 2.0) * 0.5;
+    w[k][2] = -(s + 1.0) * s * (s - 2.0) * 0.5;
+    w[k][3] = (s + 1.0) * s * (s - 1.0) / 6.0;
+    wd[k][0] = -(3.0 * s2 - 6.0 * s + 2.0) / 6.0 * idt;
+    wd[k][1] = (3.0 * s2 - 4.0 * s - 1.0) * 0.5 * idt;
+    wd[k][2] = -(3.0 * s2 - 2.0 * s - 2.0) * 0.5 * idt;
+    wd[k][3] = (3.0 * s2 - 1.0) / 6.0 * idt;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      int row = j - 1 + t;
+      const bool ok = (row >= 0) && (row < n_t);
+      if (!ok) {
+        w[k][t] = 0.0;
+        wd[k][t] = 0.0;
+      }
+      row = row < 0 ? 0 : (row >= n_t ? n_t - 1 : row);
+      rowoff[k][t] = ((int64_t)k * n_t + row) * M;
+    }
+  }
+
+  // data term and its derivatives: loop over modes
+  C2<double> Z[KT], Zt[KT], Zi[KT], Zf[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) Z[k].x = Z[k].y = Zt[k].x = Zt[k].y = Zi[k].x = Zi[k].y = Zf[k].x = Zf[k].y = 0.0;
+  {
+    C2<double> ph;
+    ph.x = 1.0;
+    ph.y = 0.0;
+    const int mmin = P->m_min;
+    for (int t = 0; t < -mmin; ++t) {
+      const double a = ph.x * cf + ph.y * sf, bb = ph.y * cf - ph.x * sf;
+      ph.x = a;
+      ph.y = bb;
+    }
+    int mc = mmin < 0 ? mmin : 0;
+    for (int i = 0; i < M; ++i) {
+      const int mi = P->m[i];
+      while (mc < mi) {
+        const double a = ph.x * cf - ph.y * sf, bb = ph.y * cf + ph.x * sf;
+        ph.x = a;
+        ph.y = bb;
+        ++mc;
+      }
+      double d = 0.0, dd = 0.0;
+      if (P->odd[i]) {
+#pragma unroll
+        for (int n = 1; n < NY; ++n) {
+          d += P->ycoef[i][n] * sn[n];
+          dd += P->ycoef[i][n] * (double)n * cn[n];
+        }
+      } else {
+#pragma unroll
+        for (int n = 0; n < NY; ++n) {
+          d += P->ycoef[i][n] * cn[n];
+          dd -= P->ycoef[i][n] * (double)n * sn[n];
+        }
+      }
+      const double yx = d * ph.x, yy = d * ph.y, ix = dd * ph.x, iy = dd * ph.y;
+      const double mv = (double)mi;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const C2<double> q0 = ldq(Qt, rowoff[k][0] + i), q1 = ldq(Qt, rowoff[k][1] + i);
+        const C2<double> q2 = ldq(Qt, rowoff[k][2] + i), q3 = ldq(Qt, rowoff[k][3] + i);
+        const double qx = w[k][0] * q0.x + w[k][1] * q1.x + w[k][2] * q2.x + w[k][3] * q3.x;
+        const double qy = w[k][0] * q0.y + w[k][1] * q1.y + w[k][2] * q2.y + w[k][3] * q3.y;
+        const double tx = wd[k][0] * q0.x + wd[k][1] * q1.x + wd[k][2] * q2.x + wd[k][3] * q3.x;
+        const double ty = wd[k][0] * q0.y + wd[k][1] * q1.y + wd[k][2] * q2.y + wd[k][3] * q3.y;
+        const double zx = yx * qx + yy * qy;  // conj(Y) q
+        const double zy = yx * qy - yy * qx;
+        Z[k].x += zx;
+        Z[k].y += zy;
+        Zt[k].x += yx * tx + yy * ty;
+        Zt[k].y += yx * ty - yy * tx;
+        Zi[k].x += ix * qx + iy * qy;
+        Zi[k].y += ix * qy - iy * qx;
+        // d/dphi conj(Y) = -i m conj(Y): (-i m)(zx + i zy) = m zy - i m zx
+        Zf[k].x += mv * zy;
+        Zf[k].y -= mv * zx;
+      }
+    }
+  }
+  double data = 0.0, gg = 0.0, gdec = 0.0, gpsi = 0.0, gi = 0.0, gf = 0.0, gt = 0.0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const double fp = Fp[k], fx = Fx[k];
+    data += fp * Z[k].x + fx * Z[k].y;
+    const double dt_term = fp * Zt[k].x + fx * Zt[k].y;
+    gg += dFg[k][0] * Z[k].x + dFg[k][1] * Z[k].y + dt_term * dtg[k];
+    gdec += dFd[k][0] * Z[k].x + dFd[k][1] * Z[k].y + dt_term * dtd[k];
+    gpsi += 2.0 * fx * Z[k].x - 2.0 * fp * Z[k].y;  // dF/dpsi = (2 Fx, -2 F+)
+    gi += fp * Zi[k].x + fx * Zi[k].y;
+    gf += fp * Zf[k].x + fx * Zf[k].y;
+    gt += dt_term;
+  }
+
+  // model-norm term and its incl/phi derivatives: loop over basis rows.  For
+  // T_n = cos or sin(n incl) and T'_n its incl-derivative, a pair of basis
+  // functions T_n cos(q phi), T_n sin(q phi) has derivatives
+  // (T'_n cos, -q T_n sin) and (T'_n sin, q T_n cos).
+  const RIFT_CONST double* Cc = as_const(P->C64);
+  double R[3 * KT], Ri[3 * KT], Rf[3 * KT];
+#pragma unroll
+  for (int c = 0; c < 3 * KT; ++c) R[c] = Ri[c] = Rf[c] = 0.0;
+#pragma unroll 1
+  for (int n = 0; n <= NI; ++n) {
+    const double v = trig[n * ts], vi = -(double)n * trig[(NI + 1 + n) * ts];
+    const RIFT_CONST double* cr = Cc + n * 3 * KT;
+#pragma unroll
+    for (int c = 0; c < 3 * KT; ++c) {
+      R[c] += cr[c] * v;
+      Ri[c] += cr[c] * vi;
+    }
+  }
+  {
+    int b = NI + 1;
+    C2<double> eq;
+    eq.x = cf;
+    eq.y = sf;
+#pragma unroll 1
+    for (int q = 1; q <= NI; ++q) {
+      const int odd = q & 1;
+      const double qd = (double)q;
+#pragma unroll 1
+      for (int n = odd; n <= NI; ++n, b += 2) {
+        const double nd = (double)n;
+        const double t = odd ? trig[(NI + 1 + n) * ts] : trig[n * ts];
+        const double tp = odd ? nd * trig[n * ts] : -nd * trig[(NI + 1 + n) * ts];
+        const double v1 = t * eq.x, i1 = tp * eq.x, f1 = -qd * t * eq.y;
+        const double v2 = t * eq.y, i2 = tp * eq.y, f2 = qd * t * eq.x;
+        const RIFT_CONST double* cr = Cc + b * 3 * KT;
+#pragma unroll
+        for (int c = 0; c < 3 * KT; ++c) {
+          const double c1 = cr[c], c2 = cr[3 * KT + c];
+          R[c] += c1 * v1 + c2 * v2;
+          Ri[c] += c1 * i1 + c2 * i2;
+          Rf[c] += c1 * f1 + c2 * f2;
+        }
+      }
+      const double ex_ = eq.x * cf - eq.y * sf, ey_ = eq.x * sf + eq.y * cf;
+      eq.x = ex_;
+      eq.y = ey_;
+    }
+  }
+  double quad = 0.0, qg = 0.0, qdec = 0.0, qpsi = 0.0, qi = 0.0, qf = 0.0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const double a = Fp[k], c = Fx[k];
+    const double w0 = a * a + c * c, w1 = a * a - c * c, w2 = 2.0 * a * c;
+    quad += w0 * R[3 * k] + w1 * R[3 * k + 1] + w2 * R[3 * k + 2];
+    qi += w0 * Ri[3 * k] + w1 * Ri[3 * k + 1] + w2 * Ri[3 * k + 2];
+    qf += w0 * Rf[3 * k] + w1 * Rf[3 * k + 1] + w2 * Rf[3 * k + 2];
+    // weights' change for a change (da, dc) of (F+, Fx)
+    {
+      const double da = dFg[k][0], dc = dFg[k][1];
+      qg += 2.0 * (a * da + c * dc) * R[3 * k] + 2.0 * (a * da - c * dc) * R[3 * k + 1] +
+            2.0 * (da * c + a * dc) * R[3 * k + 2];
+    }
+    {
+      const double da = dFd[k][0], dc = dFd[k][1];
+      qdec += 2.0 * (a * da + c * dc) * R[3 * k] + 2.0 * (a * da - c * dc) * R[3 * k + 1] +
+              2.0 * (da * c + a * dc) * R[3 * k + 2];
+    }
+    {
+      const double da = 2.0 * c, dc = -2.0 * a;
+      qpsi += 2.0 * (a * da + c * dc) * R[3 * k] + 2.0 * (a * da - c * dc) * R[3 * k + 1] +
+              2.0 * (da * c + a * dc) * R[3 * k + 2];
+    }
+  }
+
+  const double x = P->d_ref / dist;
+  const double x2 = x * x;
+  const double lnL = x * data - x2 * quad;
+  g[0] = -(x * gg - x2 * qg);          // d/dra = -d/dgha
+  g[1] = x * gdec - x2 * qdec;
+  g[2] = x * gpsi - x2 * qpsi;
+  g[3] = -(x * gi - x2 * qi) / si;     // d/dcos(incl) = -(1/sin incl) d/dincl
+  g[4] = x * gf - x2 * qf;
+  g[5] = x * gt;
+  g[6] = -x * data + 2.0 * x2 * quad;  // x = D_ref e^{-ln dist}
+  if (bad) {
+    const double nan = __builtin_nan("");
+#pragma unroll
+    for (int a = 0; a < 7; ++a) g[a] = nan;
+    return nan;
+  }
+  return lnL;
+}
+
+}  // namespace rift

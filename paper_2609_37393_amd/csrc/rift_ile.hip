@@ -1,0 +1,1016 @@
+// Host side, setup kernels and entry points of the MI355X factored extrinsic
+// likelihood (C ABI declared in include/rift_ile.h).
+//
+// Flow of one batch (Eqs. (def:lnL:Decomposed), (lnL:MonteCarlo), (neff)):
+//   plan creation (once per set of points):
+//     k_repack   Q[K][M][n_t] (paper order) -> time-major Q[KT][n_t][M] (FP64, FP32)
+//     k_qmax     max |Q_k| per detector (error bound of the mixed path)
+//     k_basis    harmonic-basis coefficients of the model-norm term
+//   evaluation (no allocation, no host synchronisation -> graph-capturable):
+//     FP64 : k_tiles<double>  one persistent launch over (point, sample-block)
+//            tiles, per-tile (max, sum exp) partials -> k_merge -> ln Z, n_eff
+//     MIXED: k_tiles<float> (value + a-priori bound) -> k_mlow -> k_select
+//            (samples whose bound reaches within T of the best) -> k_refine
+//            (FP64 recompute of those) -> k_final (LSE + omitted-error sum)
+//            -> k_merge
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rift_ile.h"
+#include "ile_kernels.h"
+
+using namespace rift;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Setup kernels
+// ---------------------------------------------------------------------------
+
+// Q[k][i][t] (caller order, complex) -> Qt[k][t][i_internal]; padded detectors 0.
+__global__ void k_repack(const double* __restrict__ Q, double* __restrict__ Q64,
+                         float* __restrict__ Q32, const int32_t* __restrict__ perm, int K, int KT,
+                         int M, int n_t) {
+  const int64_t total = (int64_t)KT * n_t * M;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % M);
+    const int64_t kt = e / M;
+    const int t = (int)(kt % n_t);
+    const int k = (int)(kt / n_t);
+    double re = 0.0, im = 0.0;
+    if (k < K) {
+      const int64_t src = ((int64_t)k * M + perm[i]) * n_t + t;
+      re = Q[2 * src];
+      im = Q[2 * src + 1];
+    }
+    Q64[2 * e] = re;
+    Q64[2 * e + 1] = im;
+    if (Q32) {
+      Q32[2 * e] = (float)re;
+      Q32[2 * e + 1] = (float)im;
+    }
+  }
+}
+
+// out[k] = max_{t,i} |Q64[k][t][i]|, one block per detector.
+__global__ void k_qmax(const double* __restrict__ Q64, double* __restrict__ out, int n_t, int M) {
+  const int k = blockIdx.x;
+  const int64_t n = (int64_t)n_t * M;
+  const double* q = Q64 + 2 * (int64_t)k * n;
+  double m = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) m = fmax(m, hypot(q[2 * e], q[2 * e + 1]));
+  m = dmax_wave(m);
+  __shared__ double sh[16];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
+    out[k] = r;
+  }
+}
+
+// Basis function b of class L: kind 0 = cos(n i), 1 = cos(n i) cos(q f),
+// 2 = cos(n i) sin(q f), 3 = sin(n i) cos(q f), 4 = sin(n i) sin(q f).
+// The order matches the contraction loop of eval_sample.
+__host__ __device__ inline void basis_index(int L, int b, int* kind, int* n, int* q) {
+  const int NI = 2 * L;
+  int bb = b;
+  for (int qq = 0; qq <= NI; ++qq) {
+    if (qq == 0) {
+      if (bb <= NI) { *kind = 0; *n = bb; *q = 0; return; }
+      bb -= NI + 1;
+    } else if ((qq & 1) == 0) {
+      if (bb < 2 * (NI + 1)) { *kind = 1 + (bb & 1); *n = bb >> 1; *q = qq; return; }
+      bb -= 2 * (NI + 1);
+    } else {
+      if (bb < 2 * NI) { *kind = 3 + (bb & 1); *n = 1 + (bb >> 1); *q = qq; return; }
+      bb -= 2 * NI;
+    }
+  }
+  *kind = -1; *n = 0; *q = 0;
+}
+
+inline int basis_count(int L) {
+  const int NI = 2 * L, NQ = 2 * L;
+  return (NI + 1) + (NQ / 2) * 2 * (NI + 1) + ((NQ + 1) / 2) * 2 * NI;
+}
+
+// Harmonic-basis coefficients of g_c = (a_k/4, Re b_k/4, -Im b_k/4) for one
+// detector per block: sample g_c on an NG x NG grid of (incl, phi) over
+// [0, 2 pi)^2 (NG = 4L + 4, more than twice the degree 2L) and project
+// (discrete orthogonality of the basis on that grid).  U, V in caller order,
+// modes mapped through perm.  Writes column 3k..3k+2 of C64/C32 [B][3 KT].
+__global__ void k_basis(const PointDesc* __restrict__ P, const double* __restrict__ U,
+                        const double* __restrict__ V, const int32_t* __restrict__ perm,
+                        double* __restrict__ C64, float* __restrict__ C32) {
+  extern __shared__ double g[];  // [3][NG][NG]
+  const int k = blockIdx.x;
+  const int M = P->M, L = P->L, KT = P->KT, B = P->B;
+  const int NG = 4 * L + 4;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int gp = threadIdx.x; gp < NG * NG; gp += blockDim.x) {
+    const int pi_ = gp / NG, pf = gp % NG;
+    const double inc = two_pi * pi_ / NG, ph = two_pi * pf / NG;
+    double yr[MMAX], yi[MMAX];
+    for (int i = 0; i < M; ++i) {
+      double d = 0.0;
+      for (int n = 0; n <= L; ++n) {
+        const double c = P->ycoef[i][n];
+        d += P->odd[i] ? c * sin(n * inc) : c * cos(n * inc);
+      }
+      double s, cc;
+      sincos(P->m[i] * ph, &s, &cc);
+      yr[i] = d * cc;
+      yi[i] = d * s;
+    }
+    double ar = 0.0, br = 0.0, bi = 0.0;
+    if (k < P->K) {
+      for (int i = 0; i < M; ++i) {
+        const int ci = perm[i];
+        for (int j = 0; j < M; ++j) {
+          const int cj = perm[j];
+          const int64_t o = 2 * (((int64_t)k * M + ci) * M + cj);
+          const double ur = U[o], ui = U[o + 1], vr = V[o], vi = V[o + 1];
+          // Re[conj(Y_i) U_ij Y_j] and Y_i V_ij Y_j
+          const double wr = yr[i] * yr[j] + yi[i] * yi[j];
+          const double wi = yr[i] * yi[j] - yi[i] * yr[j];
+          ar += ur * wr - ui * wi;
+          const double sr = yr[i] * yr[j] - yi[i] * yi[j];
+          const double si = yr[i] * yi[j] + yi[i] * yr[j];
+          br += vr * sr - vi * si;
+          bi += vr * si + vi * sr;
+        }
+      }
+    }
+    g[0 * NG * NG + gp] = 0.25 * ar;
+    g[1 * NG * NG + gp] = 0.25 * br;
+    g[2 * NG * NG + gp] = -0.25 * bi;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    int kind, n, q;
+    basis_index(L, b, &kind, &n, &q);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int gp = 0; gp < NG * NG; ++gp) {
+      const int pi_ = gp / NG, pf = gp % NG;
+      const double inc = two_pi * pi_ / NG, ph = two_pi * pf / NG;
+      double t;
+      if (kind == 0) t = cos(n * inc);
+      else if (kind == 1) t = cos(n * inc) * cos(q * ph);
+      else if (kind == 2) t = cos(n * inc) * sin(q * ph);
+      else if (kind == 3) t = sin(n * inc) * cos(q * ph);
+      else t = sin(n * inc) * sin(q * ph);
+      for (int c = 0; c < 3; ++c) acc[c] += g[c * NG * NG + gp] * t;
+    }
+    const double nu_i = (n == 0) ? 1.0 : 0.5;
+    const double nu_f = (q == 0) ? 1.0 : 0.5;
+    const double norm = 1.0 / ((double)NG * NG * nu_i * nu_f);
+    for (int c = 0; c < 3; ++c) {
+      const double v = acc[c] * norm;
+      C64[b * 3 * KT + 3 * k + c] = v;
+      if (C32) C32[b * 3 * KT + 3 * k + c] = (float)v;
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Per point: M_low = max over its tiles of max(lnL32 + lnw - bound).
+__global__ void k_mlow(const PointDesc* __restrict__ descs, const int32_t* __restrict__ trange,
+                       const double* __restrict__ tmax, double* __restrict__ mlow) {
+  const int p = blockIdx.x;
+  double m = -__builtin_inf();
+  for (int t = trange[2 * p] + threadIdx.x; t < trange[2 * p + 1]; t += blockDim.x) m = fmax(m, tmax[t]);
+  m = dmax_wave(m);
+  __shared__ double sh[8];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
+    mlow[p] = r;
+  }
+}
+
+// Samples that may lie within T of the best go to the point's refine list;
+// their bound is set to -1 to mark them.
+__global__ void k_select(const PointDesc* __restrict__ descs, const Tile* __restrict__ tiles,
+                         int n_tiles, const double* __restrict__ lnL, const double* __restrict__ lnw,
+                         float* __restrict__ bnd, const double* __restrict__ mlow,
+                         int32_t* __restrict__ cnt, int32_t* __restrict__ list) {
+  const int tidx = blockIdx.x;
+  if (tidx >= n_tiles) return;
+  const Tile t = tiles[tidx];
+  const PointDesc* P = descs + t.p;
+  const double thr = mlow[t.p] - P->T;
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    const double v = lnL[i] + (lnw ? lnw[i] : 0.0) + (double)bnd[i];
+    if (v >= thr) {
+      const int slot = atomicAdd(cnt + t.p, 1);
+      list[P->s0 + slot] = (int32_t)(i - P->s0);
+      bnd[i] = -1.0f;
+    }
+  }
+}
+
+// Mixed path: per-tile LSE over the final values and the bound on what the
+// unrefined samples can still be off by:
+//   err = sum_{unrefined} exp(lnL32 + lnw - M_low) (e^{bound} - 1).
+__global__ void k_final(const Tile* __restrict__ tiles, const double* __restrict__ lnL,
+                        const double* __restrict__ lnw, const float* __restrict__ bnd,
+                        const double* __restrict__ mlow, double* __restrict__ part,
+                        double* __restrict__ terr) {
+  __shared__ MS sh[8];
+  __shared__ double shd[8];
+  const int tidx = blockIdx.x;
+  const Tile t = tiles[tidx];
+  const double ml = mlow[t.p];
+  MS acc;
+  acc.m = -__builtin_inf();
+  acc.s = 0.0;
+  double err = 0.0;
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    const double l = lnL[i] + (lnw ? lnw[i] : 0.0);
+    acc = ms_combine(acc, ms_of(l));
+    const float b = bnd[i];
+    if (b > 0.0f && l == l && l > -__builtin_inf()) err += exp(l + log(expm1((double)b)) - ml);
+  }
+  const MS r = ms_block(acc, sh);
+  err = dsum_wave(err);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) shd[threadIdx.x >> 6] = err;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = shd[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) e += shd[w];
+    part[2 * tidx] = r.m;
+    part[2 * tidx + 1] = r.s;
+    terr[tidx] = e;
+  }
+}
+
+// Per point: combine tile partials in a fixed order -> ln Z, n_eff, error bound.
+__global__ void k_merge(const PointDesc* __restrict__ descs, const int32_t* __restrict__ trange,
+                        const double* __restrict__ part, const double* __restrict__ terr,
+                        const double* __restrict__ mlow, double* __restrict__ lnZ,
+                        double* __restrict__ neff, double* __restrict__ lnZ_err) {
+  __shared__ MS sh[8];
+  __shared__ double shd[8];
+  const int p = blockIdx.x;
+  MS acc;
+  acc.m = -__builtin_inf();
+  acc.s = 0.0;
+  double err = 0.0;
+  for (int t = trange[2 * p] + threadIdx.x; t < trange[2 * p + 1]; t += blockDim.x) {
+    MS v;
+    v.m = part[2 * t];
+    v.s = part[2 * t + 1];
+    acc = ms_combine(acc, v);
+    if (terr) err += terr[t];
+  }
+  const MS r = ms_block(acc, sh);
+  err = dsum_wave(err);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) shd[threadIdx.x >> 6] = err;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double e = shd[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) e += shd[w];
+    const PointDesc* P = descs + p;
+    double z;
+    if (r.s != r.s) z = __builtin_nan("");
+    else if (r.m == -__builtin_inf()) z = -__builtin_inf();
+    else z = r.m + log(r.s) - P->lnN;
+    lnZ[p] = z;
+    if (neff) neff[p] = (r.m == -__builtin_inf() && r.s == r.s) ? 0.0 : r.s;
+    if (lnZ_err) {
+      double bound = 0.0;
+      if (terr && r.s > 0.0) bound = log1p(e * exp(mlow[p] - r.m) / r.s);
+      lnZ_err[p] = bound;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+#define HCHK(x)                                   \
+  do {                                            \
+    hipError_t e_ = (x);                          \
+    if (e_ != hipSuccess) return RIFT_EDEVICE;    \
+  } while (0)
+
+inline int kt_class(int K) { return K <= 2 ? 2 : (K <= 3 ? 3 : (K <= 5 ? 5 : 8)); }
+inline int l_class(int lmax) { return lmax <= 2 ? 2 : (lmax <= 3 ? 3 : (lmax <= 4 ? 4 : 8)); }
+inline int lbit(int L) { return L == 2 ? 1 : (L == 3 ? 2 : (L == 4 ? 4 : 8)); }
+
+double factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+// Wigner d^l_{m,s}(beta), explicit sum over k (s = 2 for spin weight -2).
+double wigner_d(int l, int m, int s, double beta) {
+  const double c = cos(0.5 * beta), sn = sin(0.5 * beta);
+  const int k0 = std::max(0, m - s), k1 = std::min(l + m, l - s);
+  const double pre = sqrt(factorial(l + m) * factorial(l - m) * factorial(l + s) * factorial(l - s));
+  double d = 0.0;
+  for (int k = k0; k <= k1; ++k) {
+    const double den = factorial(l + m - k) * factorial(l - s - k) * factorial(k) * factorial(k + s - m);
+    d += ((k & 1) ? -1.0 : 1.0) * pre / den * pow(c, 2 * l + m - s - 2 * k) * pow(sn, 2 * k + s - m);
+  }
+  return d;
+}
+
+// Fourier coefficients in incl of sqrt((2l+1)/4pi) d^l_{m,2}(incl): a cosine
+// series for even m, a sine series for odd m, degree <= l (exact by a 32-point
+// DFT since l <= 8).
+void ylm_fourier(int l, int m, double* out /* [LMAXC+1] */) {
+  const int N = 32;
+  const double two_pi = 6.283185307179586476925286766559;
+  const double norm = sqrt((2.0 * l + 1.0) / (2.0 * two_pi));
+  for (int n = 0; n <= LMAXC; ++n) out[n] = 0.0;
+  for (int n = 0; n <= l; ++n) {
+    double acc = 0.0;
+    for (int p = 0; p < N; ++p) {
+      const double b = two_pi * p / N;
+      const double d = wigner_d(l, m, 2, b);
+      acc += d * ((m & 1) ? sin(n * b) : cos(n * b));
+    }
+    out[n] = norm * acc * ((n == 0) ? 1.0 : 2.0) / N;
+  }
+  if (m & 1) out[0] = 0.0;
+}
+
+struct DeviceInfo {
+  int dev = -1;
+  int n_cu = 0;
+};
+
+int device_info(DeviceInfo* di) {
+  HCHK(hipGetDevice(&di->dev));
+  HCHK(hipDeviceGetAttribute(&di->n_cu, hipDeviceAttributeMultiprocessorCount, di->dev));
+  return RIFT_OK;
+}
+
+int validate_point(const rift_ile_point* pt) {
+  if (!pt) return RIFT_EINVAL;
+  if (pt->n_det < 1 || pt->n_det > RIFT_ILE_MAX_DET) return RIFT_EINVAL;
+  if (pt->n_modes < 1 || pt->n_modes > RIFT_ILE_MAX_MODES) return RIFT_EINVAL;
+  if (pt->n_t < 4) return RIFT_EINVAL;
+  if ((int64_t)pt->n_t * pt->n_modes * RIFT_ILE_MAX_DET > ((int64_t)1 << 40)) return RIFT_EINVAL;
+  if (!pt->lm || !pt->Q || !pt->U || !pt->V || !pt->det_tensor || !pt->det_pos) return RIFT_EINVAL;
+  if ((((uintptr_t)pt->Q) | ((uintptr_t)pt->U) | ((uintptr_t)pt->V)) & 7u) return RIFT_EINVAL;
+  if (!std::isfinite(pt->t0) || !std::isfinite(pt->dt) || !(pt->dt > 0.0)) return RIFT_EINVAL;
+  if (!std::isfinite(pt->gmst_rad) || !std::isfinite(pt->d_ref) || !(pt->d_ref > 0.0)) return RIFT_EINVAL;
+  for (int i = 0; i < pt->n_modes; ++i) {
+    const int l = pt->lm[2 * i], m = pt->lm[2 * i + 1];
+    if (l < 2 || l > RIFT_ILE_MAX_L || m < -l || m > l) return RIFT_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (pt->lm[2 * j] == l && pt->lm[2 * j + 1] == m) return RIFT_EINVAL;
+  }
+  for (int k = 0; k < pt->n_det; ++k) {
+    for (int a = 0; a < 9; ++a)
+      if (!std::isfinite(pt->det_tensor[9 * k + a])) return RIFT_EINVAL;
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(pt->det_pos[3 * k + a])) return RIFT_EINVAL;
+  }
+  return RIFT_OK;
+}
+
+int check_dev_ptr(const void* p) { return (p && (((uintptr_t)p) & 7u) == 0) ? RIFT_OK : RIFT_EINVAL; }
+
+// Rough relative cost per sample of a point (for tile ordering).
+double point_cost(int KT, int L, int M) {
+  return 200.0 + 12.0 * M * KT + 3.0 * KT * basis_count(L);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct rift_ile_plan_s {
+  int n_points = 0;
+  int prec = RIFT_FP64;
+  DeviceInfo di;
+  int KT = 2;
+  int lset = 0;
+  int64_t N = 0;
+  std::vector<int64_t> n_per;
+  std::vector<PointDesc> h_desc;
+  PointDesc* d_desc = nullptr;
+  std::vector<void*> bufs;  // device allocations owned by the plan
+  // tiles (depend on the config)
+  rift_ile_config cfg{256, 4, 4};
+  std::vector<Tile> h_tiles;
+  Tile* d_tiles = nullptr;
+  int n_tiles = 0;
+  int32_t* d_trange = nullptr;  // [n_points][2]
+  double* d_part = nullptr;     // [n_tiles][2]
+  double* d_tmax = nullptr;     // [n_tiles]
+  double* d_terr = nullptr;     // [n_tiles]
+  int32_t* d_counter = nullptr;
+  // mixed scratch
+  double* d_mlow = nullptr;   // [n_points]
+  int32_t* d_cnt = nullptr;   // [n_points]
+  int32_t* d_list = nullptr;  // [N]
+  float* d_bnd = nullptr;     // [N]
+  double* d_L = nullptr;      // [N]
+  int refine_blocks = 32;
+  hipStream_t last = nullptr;
+  // optional timing of the main evaluation kernel
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+};
+
+namespace {
+
+int palloc(rift_ile_plan p, size_t bytes, void** out) {
+  void* d = nullptr;
+  if (hipMalloc(&d, bytes < 256 ? 256 : bytes) != hipSuccess) return RIFT_ENOMEM;
+  p->bufs.push_back(d);
+  *out = d;
+  return RIFT_OK;
+}
+
+void plan_free_all(rift_ile_plan p) {
+  for (void* b : p->bufs) (void)hipFree(b);
+  p->bufs.clear();
+}
+
+int build_tiles(rift_ile_plan p) {
+  const int S = p->cfg.block * p->cfg.tile_blocks;
+  // points in decreasing cost per sample; each point's tiles are contiguous
+  std::vector<int> order(p->n_points);
+  for (int i = 0; i < p->n_points; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const PointDesc &A = p->h_desc[a], &Bd = p->h_desc[b];
+    return point_cost(A.KT, A.L, A.M) > point_cost(Bd.KT, Bd.L, Bd.M);
+  });
+  std::vector<int32_t> trange(2 * p->n_points);
+  p->h_tiles.clear();
+  for (int oi = 0; oi < p->n_points; ++oi) {
+    const int pi = order[oi];
+    const PointDesc& D = p->h_desc[pi];
+    trange[2 * pi] = (int32_t)p->h_tiles.size();
+    for (int64_t s = 0; s < D.n; s += S) {
+      Tile t;
+      t.p = pi;
+      t.cnt = (int32_t)std::min<int64_t>(S, D.n - s);
+      t.s = D.s0 + s;
+      p->h_tiles.push_back(t);
+    }
+    trange[2 * pi + 1] = (int32_t)p->h_tiles.size();
+  }
+  if (p->h_tiles.size() > (size_t)0x7fffffff) return RIFT_EUNSUPPORTED;
+  p->n_tiles = (int)p->h_tiles.size();
+  // (re)allocate tile-sized buffers
+  void* v;
+  int st;
+  if ((st = palloc(p, sizeof(Tile) * p->n_tiles, &v))) return st;
+  p->d_tiles = (Tile*)v;
+  if ((st = palloc(p, sizeof(int32_t) * 2 * p->n_points, &v))) return st;
+  p->d_trange = (int32_t*)v;
+  if ((st = palloc(p, sizeof(double) * 2 * p->n_tiles, &v))) return st;
+  p->d_part = (double*)v;
+  if ((st = palloc(p, sizeof(double) * p->n_tiles, &v))) return st;
+  p->d_tmax = (double*)v;
+  if ((st = palloc(p, sizeof(double) * p->n_tiles, &v))) return st;
+  p->d_terr = (double*)v;
+  HCHK(hipMemcpy(p->d_tiles, p->h_tiles.data(), sizeof(Tile) * p->n_tiles, hipMemcpyHostToDevice));
+  HCHK(hipMemcpy(p->d_trange, trange.data(), sizeof(int32_t) * 2 * p->n_points, hipMemcpyHostToDevice));
+  return RIFT_OK;
+}
+
+// Kernel tables -------------------------------------------------------------
+tile_fn pick_tiles_kt(bool f64, int KT, int lset) {
+  switch (KT) {
+    case 2: return f64 ? get_tiles64_kt2(lset) : get_tiles32_kt2(lset);
+    case 3: return f64 ? get_tiles64_kt3(lset) : get_tiles32_kt3(lset);
+    case 5: return f64 ? get_tiles64_kt5(lset) : get_tiles32_kt5(lset);
+    default: return f64 ? get_tiles64_kt8(lset) : get_tiles32_kt8(lset);
+  }
+}
+refine_fn pick_refine_kt(int KT, int lset) {
+  switch (KT) {
+    case 2: return get_refine_kt2(lset);
+    case 3: return get_refine_kt3(lset);
+    case 5: return get_refine_kt5(lset);
+    default: return get_refine_kt8(lset);
+  }
+}
+grad_fn pick_grad_kt(int KT, int L) {
+  switch (KT) {
+    case 2: return get_grad_kt2(L);
+    case 3: return get_grad_kt3(L);
+    case 5: return get_grad_kt5(L);
+    default: return get_grad_kt8(L);
+  }
+}
+
+int validate_config(const rift_ile_config* c) {
+  if (!c) return RIFT_EINVAL;
+  if (c->block != 64 && c->block != 128 && c->block != 256 && c->block != 512) return RIFT_EINVAL;
+  if (c->tile_blocks < 1 || c->tile_blocks > 64) return RIFT_EINVAL;
+  if (c->blocks_per_cu < 0 || c->blocks_per_cu > 32) return RIFT_EINVAL;
+  return RIFT_OK;
+}
+
+int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* lnw, double* lnL,
+                 hipStream_t st) {
+  TileArgs a;
+  a.descs = p->d_desc;
+  a.tiles = p->d_tiles;
+  a.n_tiles = p->n_tiles;
+  a.persistent = p->cfg.blocks_per_cu > 0 ? 1 : 0;
+  a.counter = p->d_counter;
+  a.theta = theta;
+  a.lnw = lnw;
+  a.N = p->N;
+  a.lnL = lnL;
+  a.bnd = p->d_bnd;
+  a.part = p->d_part;
+  a.tmax = p->d_tmax;
+  tile_fn f = pick_tiles_kt(mode == MODE_LSE64, p->KT, p->lset);
+  if (!f) return RIFT_EUNSUPPORTED;
+  int grid = p->n_tiles;
+  if (a.persistent) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, p->d_counter, 1, 0);
+    grid = std::min(p->n_tiles, p->cfg.blocks_per_cu * p->di.n_cu);
+  }
+  if (grid <= 0) return RIFT_OK;
+  const size_t shm = (size_t)trig_rows(p->lset) * p->cfg.block * (mode == MODE_LSE64 ? sizeof(double) : sizeof(float));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p->profiling) {
+    HCHK(hipEventCreate(&e0));
+    HCHK(hipEventCreate(&e1));
+    p->ev.push_back(e0);
+    p->ev.push_back(e1);
+    HCHK(hipEventRecord(e0, st));
+  }
+  hipLaunchKernelGGL(f, dim3(grid), dim3(p->cfg.block), shm, st, a);
+  HCHK(hipGetLastError());
+  if (p->profiling) HCHK(hipEventRecord(e1, st));
+  return RIFT_OK;
+}
+
+void clear_events(rift_ile_plan p) {
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int rift_ile_version(void) { return RIFT_ILE_VERSION; }
+
+const char* rift_ile_strerror(int status) {
+  switch (status) {
+    case RIFT_OK: return "ok";
+    case RIFT_EINVAL: return "invalid argument";
+    case RIFT_EDEVICE: return "HIP runtime error";
+    case RIFT_ENOMEM: return "out of memory";
+    case RIFT_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+int rift_ile_plan_profile(rift_ile_plan plan, int enable) {
+  if (!plan) return RIFT_EINVAL;
+  if (enable) {
+    if (plan->last) HCHK(hipStreamSynchronize(plan->last));
+    clear_events(plan);
+  }
+  plan->profiling = enable != 0;
+  return RIFT_OK;
+}
+
+int rift_ile_plan_profile_read(rift_ile_plan plan, double* total_ms, int64_t* launches) {
+  if (!plan || !total_ms || !launches) return RIFT_EINVAL;
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < plan->ev.size(); i += 2) {
+    HCHK(hipEventSynchronize(plan->ev[i + 1]));
+    float ms = 0.0f;
+    HCHK(hipEventElapsedTime(&ms, plan->ev[i], plan->ev[i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)(plan->ev.size() / 2);
+  return RIFT_OK;
+}
+
+int rift_ile_plan_destroy(rift_ile_plan plan) {
+  if (!plan) return RIFT_EINVAL;
+  if (plan->last) (void)hipStreamSynchronize(plan->last);
+  clear_events(plan);
+  plan_free_all(plan);
+  delete plan;
+  return RIFT_OK;
+}
+
+int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int64_t* n_per_point,
+                         int precision, void* stream, rift_ile_plan* out) {
+  if (!out || !pts || !n_per_point || n_points < 1 || n_points > (1 << 20)) return RIFT_EINVAL;
+  if (precision != RIFT_FP64 && precision != RIFT_MIXED) return RIFT_EINVAL;
+  int64_t N = 0;
+  for (int p = 0; p < n_points; ++p) {
+    int st = validate_point(pts + p);
+    if (st) return st;
+    if (n_per_point[p] < 1 || n_per_point[p] > ((int64_t)1 << 31) - 1) return RIFT_EINVAL;
+    N += n_per_point[p];
+  }
+  if (N > ((int64_t)1 << 40)) return RIFT_EINVAL;
+  *out = nullptr;
+  rift_ile_plan p = new (std::nothrow) rift_ile_plan_s;
+  if (!p) return RIFT_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = device_info(&p->di);
+  if (rc) { delete p; return rc; }
+  p->n_points = n_points;
+  p->prec = precision;
+  p->N = N;
+  p->n_per.assign(n_per_point, n_per_point + n_points);
+  p->h_desc.resize(n_points);
+  const bool mixed = precision == RIFT_MIXED;
+  int KT = 2;
+  for (int i = 0; i < n_points; ++i) KT = std::max(KT, kt_class(pts[i].n_det));
+  p->KT = KT;
+
+#define PCHK(x)                 \
+  do {                          \
+    int s_ = (x);               \
+    if (s_) {                   \
+      plan_free_all(p);         \
+      delete p;                 \
+      return s_;                \
+    }                           \
+  } while (0)
+#define PHIP(x)                    \
+  do {                             \
+    if ((x) != hipSuccess) {       \
+      plan_free_all(p);            \
+      delete p;                    \
+      return RIFT_EDEVICE;         \
+    }                              \
+  } while (0)
+
+  void* v = nullptr;
+  PCHK(palloc(p, sizeof(PointDesc) * n_points, &v));
+  p->d_desc = (PointDesc*)v;
+  std::vector<int32_t*> d_perm(n_points);
+  std::vector<double*> d_qmax(n_points);
+  int64_t s0 = 0;
+  for (int pi = 0; pi < n_points; ++pi) {
+    const rift_ile_point& pt = pts[pi];
+    PointDesc& D = p->h_desc[pi];
+    memset(&D, 0, sizeof(D));
+    const int K = pt.n_det, M = pt.n_modes;
+    int lmax = 2;
+    for (int i = 0; i < M; ++i) lmax = std::max(lmax, (int)pt.lm[2 * i]);
+    D.K = K;
+    D.M = M;
+    D.n_t = pt.n_t;
+    D.L = l_class(lmax);
+    D.B = basis_count(D.L);
+    D.KT = KT;
+    D.n = n_per_point[pi];
+    D.s0 = s0;
+    s0 += D.n;
+    D.t0 = pt.t0;
+    D.inv_dt = 1.0 / pt.dt;
+    D.gmst = pt.gmst_rad;
+    D.d_ref = pt.d_ref;
+    D.lnN = log((double)D.n);
+    // refinement margin: an unrefined sample weighs < e^{-T} of the best one
+    D.T = log((double)D.n) + 12.0;
+    p->lset |= lbit(D.L);
+    for (int k = 0; k < K; ++k) {
+      const double* d = pt.det_tensor + 9 * k;
+      const double six[6] = {d[0], d[4], d[8], d[1] + d[3], d[2] + d[6], d[5] + d[7]};
+      for (int a = 0; a < 6; ++a) {
+        D.dten[k][a] = six[a];
+        D.dten32[k][a] = (float)six[a];
+      }
+      for (int a = 0; a < 3; ++a) D.rpos[k][a] = pt.det_pos[3 * k + a];
+    }
+    // modes sorted by m (stable) so the phase e^{i m phi} walks upward
+    std::vector<int> perm(M);
+    for (int i = 0; i < M; ++i) perm[i] = i;
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return pt.lm[2 * a + 1] < pt.lm[2 * b + 1]; });
+    for (int i = 0; i < M; ++i) {
+      const int l = pt.lm[2 * perm[i]], m = pt.lm[2 * perm[i] + 1];
+      D.m[i] = m;
+      D.odd[i] = (m & 1) ? 1 : 0;
+      ylm_fourier(l, m, D.ycoef[i]);
+      for (int n = 0; n <= LMAXC; ++n) D.ycoef32[i][n] = (float)D.ycoef[i][n];
+    }
+    D.m_min = D.m[0];
+    // device tables
+    const int64_t qn = (int64_t)KT * pt.n_t * M;
+    PCHK(palloc(p, sizeof(double) * 2 * qn, &v));
+    D.Q64 = (const double*)v;
+    if (mixed) {
+      PCHK(palloc(p, sizeof(float) * 2 * qn, &v));
+      D.Q32 = (const float*)v;
+    }
+    PCHK(palloc(p, sizeof(double) * D.B * 3 * KT, &v));
+    D.C64 = (const double*)v;
+    if (mixed) {
+      PCHK(palloc(p, sizeof(float) * D.B * 3 * KT, &v));
+      D.C32 = (const float*)v;
+    }
+    PCHK(palloc(p, sizeof(int32_t) * M, &v));
+    d_perm[pi] = (int32_t*)v;
+    PHIP(hipMemcpyAsync(d_perm[pi], perm.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
+    PCHK(palloc(p, sizeof(double) * KT, &v));
+    d_qmax[pi] = (double*)v;
+    PHIP(hipStreamSynchronize(st));  // perm staged before the host vector goes away
+  }
+  // a batch mixing l > 4 with smaller points runs every point in the l <= 8
+  // class (exact for any l <= 8, one kernel instance)
+  if ((p->lset & 8) && p->lset != 8) {
+    p->lset = 8;
+    for (int pi = 0; pi < n_points; ++pi) {
+      PointDesc& D = p->h_desc[pi];
+      if (D.L != 8) {
+        D.L = 8;
+        D.B = basis_count(8);
+        for (auto* b : {(void*)D.C64, (void*)D.C32}) {
+          if (!b) continue;
+          auto it = std::find(p->bufs.begin(), p->bufs.end(), b);
+          if (it != p->bufs.end()) { (void)hipFree(*it); p->bufs.erase(it); }
+        }
+        PCHK(palloc(p, sizeof(double) * D.B * 3 * KT, &v));
+        D.C64 = (const double*)v;
+        D.C32 = nullptr;
+        if (mixed) {
+          PCHK(palloc(p, sizeof(float) * D.B * 3 * KT, &v));
+          D.C32 = (const float*)v;
+        }
+      }
+    }
+  }
+  PHIP(hipMemcpyAsync(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice, st));
+  for (int pi = 0; pi < n_points; ++pi) {
+    const rift_ile_point& pt = pts[pi];
+    PointDesc& D = p->h_desc[pi];
+    const int64_t qn = (int64_t)KT * pt.n_t * pt.n_modes;
+    const int gq = (int)std::min<int64_t>((qn + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_repack, dim3(gq), dim3(256), 0, st, pt.Q, (double*)D.Q64, (float*)D.Q32,
+                       d_perm[pi], pt.n_det, KT, pt.n_modes, pt.n_t);
+    hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(256), 0, st, D.Q64, d_qmax[pi], pt.n_t, pt.n_modes);
+    const int NG = 4 * D.L + 4;
+    hipLaunchKernelGGL(k_basis, dim3(KT), dim3(256), sizeof(double) * 3 * NG * NG, st,
+                       p->d_desc + pi, pt.U, pt.V, d_perm[pi], (double*)D.C64, (float*)D.C32);
+    PHIP(hipGetLastError());
+  }
+  PHIP(hipStreamSynchronize(st));
+  // error-bound constants of the mixed path
+  for (int pi = 0; pi < n_points && mixed; ++pi) {
+    PointDesc& D = p->h_desc[pi];
+    std::vector<double> qmax(KT), C((size_t)D.B * 3 * KT);
+    PHIP(hipMemcpy(qmax.data(), d_qmax[pi], sizeof(double) * KT, hipMemcpyDeviceToHost));
+    PHIP(hipMemcpy(C.data(), D.C64, sizeof(double) * C.size(), hipMemcpyDeviceToHost));
+    const double u = 5.9604644775390625e-08;  // 2^-24
+    double ysum = 0.0;
+    for (int i = 0; i < D.M; ++i)
+      for (int n = 0; n <= LMAXC; ++n) ysum += fabs(D.ycoef[i][n]);
+    double fq = 0.0;
+    for (int k = 0; k < D.K; ++k) {
+      double fm = 0.0;
+      for (int a = 0; a < 6; ++a) fm += fabs(D.dten[k][a]);
+      fq += 1.5 * fm * qmax[k];
+    }
+    // data term: |Q^| <= 1.25 max|Q| (sum of |Lagrange weights|); rounding of
+    // table, weights, harmonics (phase walk <= 16 steps), antenna and the
+    // (M K)-term sum, each a small multiple of u.
+    D.bnd_d = 2.0 * 1.25 * (60.0 + (double)D.M * D.K) * u * fq * ysum;
+    for (int k = 0; k < KT; ++k) {
+      double l1 = 0.0;
+      for (int b = 0; b < D.B; ++b)
+        for (int c = 0; c < 3; ++c) l1 += fabs(C[(size_t)b * 3 * KT + 3 * k + c]);
+      // |beta| <= 1 up to the recurrences' rounding; B-term sums
+      D.bnd_q[k] = 2.0 * (60.0 + (double)D.B) * u * l1;
+    }
+  }
+  PHIP(hipMemcpy(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice));
+  PCHK(palloc(p, sizeof(int32_t) * 64, &v));
+  p->d_counter = (int32_t*)v;
+  if (mixed) {
+    PCHK(palloc(p, sizeof(double) * n_points, &v));
+    p->d_mlow = (double*)v;
+    PCHK(palloc(p, sizeof(int32_t) * n_points, &v));
+    p->d_cnt = (int32_t*)v;
+    PCHK(palloc(p, sizeof(int32_t) * N, &v));
+    p->d_list = (int32_t*)v;
+    PCHK(palloc(p, sizeof(float) * N, &v));
+    p->d_bnd = (float*)v;
+    PCHK(palloc(p, sizeof(double) * N, &v));
+    p->d_L = (double*)v;
+  }
+  PCHK(build_tiles(p));
+#undef PCHK
+#undef PHIP
+  p->last = st;
+  *out = p;
+  return RIFT_OK;
+}
+
+int rift_ile_plan_get_config(rift_ile_plan plan, rift_ile_config* cfg) {
+  if (!plan || !cfg) return RIFT_EINVAL;
+  *cfg = plan->cfg;
+  return RIFT_OK;
+}
+
+int rift_ile_plan_set_config(rift_ile_plan plan, const rift_ile_config* cfg) {
+  if (!plan) return RIFT_EINVAL;
+  int st = validate_config(cfg);
+  if (st) return st;
+  if (plan->last) HCHK(hipStreamSynchronize(plan->last));
+  const bool retile = cfg->block * cfg->tile_blocks != plan->cfg.block * plan->cfg.tile_blocks;
+  plan->cfg = *cfg;
+  if (retile) return build_tiles(plan);  // old tile buffers stay owned until destroy
+  return RIFT_OK;
+}
+
+int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, double* lnZ,
+                      double* neff, double* lnL, double* lnZ_err, void* stream) {
+  if (!p || check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  if ((lnw && check_dev_ptr(lnw)) || (neff && check_dev_ptr(neff)) || (lnL && check_dev_ptr(lnL)) ||
+      (lnZ_err && check_dev_ptr(lnZ_err)))
+    return RIFT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  p->last = st;
+  int rc;
+  if (p->prec == RIFT_FP64) {
+    if ((rc = launch_tiles(p, MODE_LSE64, theta, lnw, lnL, st))) return rc;
+    hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_part,
+                       (const double*)nullptr, (const double*)nullptr, lnZ, neff, lnZ_err);
+    HCHK(hipGetLastError());
+    return RIFT_OK;
+  }
+  double* L = lnL ? lnL : p->d_L;
+  if ((rc = launch_tiles(p, MODE_PASS32, theta, lnw, L, st))) return rc;
+  hipLaunchKernelGGL(k_mlow, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_tmax,
+                     p->d_mlow);
+  hipLaunchKernelGGL(k_fill_i32, dim3((p->n_points + 255) / 256), dim3(256), 0, st, p->d_cnt,
+                     p->n_points, 0);
+  hipLaunchKernelGGL(k_select, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_desc, p->d_tiles,
+                     p->n_tiles, (const double*)L, lnw, p->d_bnd, (const double*)p->d_mlow, p->d_cnt,
+                     p->d_list);
+  refine_fn rf = pick_refine_kt(p->KT, p->lset);
+  if (!rf) return RIFT_EUNSUPPORTED;
+  hipLaunchKernelGGL(rf, dim3(p->refine_blocks, p->n_points), dim3(256),
+                     (size_t)trig_rows(p->lset) * 256 * sizeof(double), st, p->d_desc, theta, p->N,
+                     (const int32_t*)p->d_cnt, (const int32_t*)p->d_list, L);
+  hipLaunchKernelGGL(k_final, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
+                     lnw, (const float*)p->d_bnd, (const double*)p->d_mlow, p->d_part, p->d_terr);
+  hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_part,
+                     (const double*)p->d_terr, (const double*)p->d_mlow, lnZ, neff, lnZ_err);
+  HCHK(hipGetLastError());
+  return RIFT_OK;
+}
+
+int rift_ile_plan_refined(rift_ile_plan p, int64_t* n_refined) {
+  if (!p || !n_refined) return RIFT_EINVAL;
+  *n_refined = 0;
+  if (p->prec != RIFT_MIXED) return RIFT_OK;
+  if (p->last) HCHK(hipStreamSynchronize(p->last));
+  std::vector<int32_t> c(p->n_points);
+  HCHK(hipMemcpy(c.data(), p->d_cnt, sizeof(int32_t) * p->n_points, hipMemcpyDeviceToHost));
+  for (int32_t v : c) *n_refined += v;
+  return RIFT_OK;
+}
+
+int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, double* lnL,
+                       double* grad, void* stream) {
+  if (!p || point < 0 || point >= p->n_points || n < 0) return RIFT_EINVAL;
+  if (n == 0) return RIFT_OK;
+  if (check_dev_ptr(theta) || check_dev_ptr(grad) || (lnL && check_dev_ptr(lnL))) return RIFT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  p->last = st;
+  const PointDesc& D = p->h_desc[point];
+  grad_fn f = pick_grad_kt(p->KT, D.L);
+  if (!f) return RIFT_EUNSUPPORTED;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)p->di.n_cu * 16);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p->profiling) {
+    HCHK(hipEventCreate(&e0));
+    HCHK(hipEventCreate(&e1));
+    p->ev.push_back(e0);
+    p->ev.push_back(e1);
+    HCHK(hipEventRecord(e0, st));
+  }
+  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), (size_t)trig_rows(lbit(D.L)) * 256 * sizeof(double), st,
+                     (const PointDesc*)(p->d_desc + point),
+                     theta, n, lnL, grad);
+  HCHK(hipGetLastError());
+  if (p->profiling) HCHK(hipEventRecord(e1, st));
+  return RIFT_OK;
+}
+
+int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, void* stream) {
+  if (!p || check_dev_ptr(theta) || (lnw && check_dev_ptr(lnw))) return RIFT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const bool prof = p->profiling;
+  p->profiling = false;
+  static const rift_ile_config cands[] = {
+      {256, 1, 0}, {256, 4, 0}, {128, 4, 0}, {512, 2, 0}, {256, 1, 4}, {256, 2, 4},
+      {256, 4, 4}, {256, 8, 2}, {128, 8, 4}, {512, 1, 2}, {512, 2, 2}, {64, 16, 8},
+  };
+  const int nc = (int)(sizeof(cands) / sizeof(cands[0]));
+  double* d_out = nullptr;
+  if (hipMalloc(&d_out, sizeof(double) * 2 * p->n_points) != hipSuccess) return RIFT_ENOMEM;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(d_out);
+    return RIFT_EDEVICE;
+  }
+  int best = -1;
+  float best_ms = 1e30f;
+  int rc = RIFT_OK;
+  for (int c = 0; c < nc && rc == RIFT_OK; ++c) {
+    rc = rift_ile_plan_set_config(p, &cands[c]);
+    if (rc) break;
+    rc = rift_ile_plan_lnZ(p, theta, lnw, d_out, d_out + p->n_points, nullptr, nullptr, st);  // warm-up
+    if (rc) break;
+    float ms_sum = 0.0f;
+    for (int r = 0; r < 3 && rc == RIFT_OK; ++r) {
+      (void)hipEventRecord(e0, st);
+      rc = rift_ile_plan_lnZ(p, theta, lnw, d_out, d_out + p->n_points, nullptr, nullptr, st);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) rc = RIFT_EDEVICE;
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms_sum += ms;
+    }
+    if (rc == RIFT_OK && ms_sum < best_ms) {
+      best_ms = ms_sum;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_out);
+  p->profiling = prof;
+  if (rc) return rc;
+  rc = rift_ile_plan_set_config(p, &cands[best]);
+  return rc ? rc : best;
+}
+
+int rift_ile_lnZ(const rift_ile_point* pts, int32_t n_points, const int64_t* n_per_point,
+                 const double* theta, const double* lnw, double* lnZ, double* neff, double* lnL,
+                 int precision, void* stream) {
+  if (check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  rift_ile_plan p = nullptr;
+  int rc = rift_ile_plan_create(pts, n_points, n_per_point, precision, stream, &p);
+  if (rc) return rc;
+  rc = rift_ile_plan_lnZ(p, theta, lnw, lnZ, neff, lnL, nullptr, stream);
+  int rc2 = rift_ile_plan_destroy(p);
+  return rc ? rc : rc2;
+}
+
+int rift_ile_lnL(const rift_ile_point* pt, int64_t n, const double* theta, double* lnL, int precision,
+                 void* stream) {
+  if (n < 0) return RIFT_EINVAL;
+  if (n == 0) return validate_point(pt);
+  if (check_dev_ptr(theta) || check_dev_ptr(lnL)) return RIFT_EINVAL;
+  rift_ile_plan p = nullptr;
+  int rc = rift_ile_plan_create(pt, 1, &n, precision, stream, &p);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  rc = launch_tiles(p, precision == RIFT_FP64 ? MODE_LSE64 : MODE_PASS32, theta, nullptr, lnL, st);
+  int rc2 = rift_ile_plan_destroy(p);
+  return rc ? rc : rc2;
+}
+
+int rift_ile_grad(const rift_ile_point* pt, int64_t n, const double* theta, double* lnL, double* grad,
+                  void* stream) {
+  if (n < 0) return RIFT_EINVAL;
+  if (n == 0) return validate_point(pt);
+  if (check_dev_ptr(theta) || check_dev_ptr(grad)) return RIFT_EINVAL;
+  rift_ile_plan p = nullptr;
+  int rc = rift_ile_plan_create(pt, 1, &n, RIFT_FP64, stream, &p);
+  if (rc) return rc;
+  rc = rift_ile_plan_grad(p, 0, n, theta, lnL, grad, stream);
+  int rc2 = rift_ile_plan_destroy(p);
+  return rc ? rc : rc2;
+}
+
+}  // extern "C"

@@ -1,0 +1,334 @@
+"""Python binding of librift_ile.so (ctypes; torch for device memory and streams).
+
+Argument marshalling only: every step of the likelihood runs in the HIP
+library.  There is no fallback -- if the library or a GPU is missing, calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librift_ile.so")
+
+RIFT_FP64 = 0
+RIFT_MIXED = 1
+PRECISIONS = {"fp64": RIFT_FP64, "mixed": RIFT_MIXED}
+
+GRAD_NAMES = ("ra", "dec", "psi", "cos_incl", "phiref", "tref", "ln_dist")
+
+EXPORTS = (
+    "rift_ile_lnL",
+    "rift_ile_lnZ",
+    "rift_ile_grad",
+    "rift_ile_plan_create",
+    "rift_ile_plan_lnZ",
+    "rift_ile_plan_grad",
+    "rift_ile_plan_tune",
+    "rift_ile_plan_get_config",
+    "rift_ile_plan_set_config",
+    "rift_ile_plan_refined",
+    "rift_ile_plan_profile",
+    "rift_ile_plan_profile_read",
+    "rift_ile_plan_destroy",
+    "rift_ile_strerror",
+    "rift_ile_version",
+)
+
+
+class CPoint(ctypes.Structure):
+    _fields_ = [
+        ("n_det", ctypes.c_int32),
+        ("n_modes", ctypes.c_int32),
+        ("n_t", ctypes.c_int32),
+        ("lm", ctypes.c_void_p),
+        ("t0", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("Q", ctypes.c_void_p),
+        ("U", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
+        ("det_tensor", ctypes.c_void_p),
+        ("det_pos", ctypes.c_void_p),
+        ("gmst_rad", ctypes.c_double),
+        ("d_ref", ctypes.c_double),
+    ]
+
+
+class CConfig(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("tile_blocks", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load librift_ile.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2609_37393_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER(CPoint)
+    lib.rift_ile_lnL.argtypes = [P, i64, vp, vp, ctypes.c_int, vp]
+    lib.rift_ile_lnZ.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
+    lib.rift_ile_grad.argtypes = [P, i64, vp, vp, vp, vp]
+    lib.rift_ile_plan_create.argtypes = [P, i32, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.rift_ile_plan_lnZ.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.rift_ile_plan_grad.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+    lib.rift_ile_plan_tune.argtypes = [vp, vp, vp, vp]
+    lib.rift_ile_plan_get_config.argtypes = [vp, ctypes.POINTER(CConfig)]
+    lib.rift_ile_plan_set_config.argtypes = [vp, ctypes.POINTER(CConfig)]
+    lib.rift_ile_plan_refined.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.rift_ile_plan_profile.argtypes = [vp, ctypes.c_int]
+    lib.rift_ile_plan_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.rift_ile_plan_destroy.argtypes = [vp]
+    lib.rift_ile_strerror.argtypes = [ctypes.c_int]
+    lib.rift_ile_strerror.restype = ctypes.c_char_p
+    lib.rift_ile_version.restype = ctypes.c_int
+    for name in EXPORTS:
+        getattr(lib, name)
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc < 0:
+        msg = load().rift_ile_strerror(rc).decode()
+        raise RuntimeError(f"{what} failed: {msg} ({rc})")
+    return rc
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_f64(a, device) -> torch.Tensor:
+    t = torch.as_tensor(a)
+    if t.is_complex():
+        t = torch.view_as_real(t.to(torch.complex128).contiguous())
+    return t.to(device=device, dtype=torch.float64).contiguous()
+
+
+@dataclass
+class DevicePoint:
+    """One intrinsic point with its arrays resident on the GPU (Q, U, V) and the
+    small metadata on the host."""
+    lm: np.ndarray
+    t0: float
+    dt: float
+    Q: torch.Tensor       # [K, M, n_t, 2] float64 (complex interleaved)
+    U: torch.Tensor       # [K, M, M, 2]
+    V: torch.Tensor
+    det_tensor: np.ndarray
+    det_pos: np.ndarray
+    gmst: float
+    d_ref: float
+
+    @classmethod
+    def from_dict(cls, pt, device="cuda"):
+        return cls(
+            lm=np.ascontiguousarray(pt["lm"], dtype=np.int32),
+            t0=float(pt["t0"]),
+            dt=float(pt["dt"]),
+            Q=_dev_f64(pt["Q"], device),
+            U=_dev_f64(pt["U"], device),
+            V=_dev_f64(pt["V"], device),
+            det_tensor=np.ascontiguousarray(pt["det_tensor"], dtype=np.float64),
+            det_pos=np.ascontiguousarray(pt["det_pos"], dtype=np.float64),
+            gmst=float(pt["gmst"]),
+            d_ref=float(pt["d_ref"]),
+        )
+
+    @property
+    def device(self):
+        return self.Q.device
+
+    def cstruct(self) -> CPoint:
+        K, M, n_t = self.Q.shape[:3]
+        return CPoint(K, M, n_t, self.lm.ctypes.data, self.t0, self.dt, self.Q.data_ptr(),
+                      self.U.data_ptr(), self.V.data_ptr(), self.det_tensor.ctypes.data,
+                      self.det_pos.ctypes.data, self.gmst, self.d_ref)
+
+
+def _as_point(pt, device) -> DevicePoint:
+    return pt if isinstance(pt, DevicePoint) else DevicePoint.from_dict(pt, device)
+
+
+def _theta(theta, device) -> torch.Tensor:
+    th = torch.as_tensor(theta)
+    if th.ndim != 2 or th.shape[0] != 7:
+        raise ValueError("theta must be [7, n]: ra, dec, psi, incl, phiref, tref, dist")
+    return th.to(device=device, dtype=torch.float64).contiguous()
+
+
+def lnL(point, theta, precision: str = "fp64", device="cuda") -> torch.Tensor:
+    """lnL [n] of the samples theta [7, n] (Eq. (def:lnL:Decomposed))."""
+    lib = load()
+    p = _as_point(point, device)
+    th = _theta(theta, p.device)
+    n = th.shape[1]
+    out = torch.empty(n, dtype=torch.float64, device=p.device)
+    cp = p.cstruct()
+    _check(lib.rift_ile_lnL(ctypes.byref(cp), n, th.data_ptr(), out.data_ptr(), PRECISIONS[precision],
+                            _stream(p.device)), "rift_ile_lnL")
+    return out
+
+
+def grad(point, theta, device="cuda"):
+    """(lnL [n], d lnL / d(ra, dec, psi, cos incl, phiref, tref, ln dist) [7, n])."""
+    lib = load()
+    p = _as_point(point, device)
+    th = _theta(theta, p.device)
+    n = th.shape[1]
+    out = torch.empty(n, dtype=torch.float64, device=p.device)
+    g = torch.empty((7, n), dtype=torch.float64, device=p.device)
+    cp = p.cstruct()
+    _check(lib.rift_ile_grad(ctypes.byref(cp), n, th.data_ptr(), out.data_ptr(), g.data_ptr(),
+                             _stream(p.device)), "rift_ile_grad")
+    return out, g
+
+
+def lnZ(points, theta, n_per_point=None, lnw=None, precision: str = "fp64", want_lnL=False,
+        device="cuda"):
+    """ln Z and n_eff per point (Eqs. (lnL:MonteCarlo), (neff)); one persistent launch.
+
+    points: list of points; theta [7, N] with the samples of point p in the
+    n_per_point[p] consecutive columns after those of the previous points.
+    Returns (lnZ [P], neff [P]) or (lnZ, neff, lnL [N]).
+    """
+    lib = load()
+    if not isinstance(points, (list, tuple)):
+        points = [points]
+    pts = [_as_point(p, device) for p in points]
+    dev = pts[0].device
+    th = _theta(theta, dev)
+    N = th.shape[1]
+    counts = np.asarray([N] if n_per_point is None else n_per_point, dtype=np.int64)
+    if counts.sum() != N or counts.size != len(pts):
+        raise ValueError("n_per_point must sum to theta.shape[1], one count per point")
+    cps = (CPoint * len(pts))(*[p.cstruct() for p in pts])
+    w = None if lnw is None else torch.as_tensor(lnw).to(device=dev, dtype=torch.float64).contiguous()
+    z = torch.empty(len(pts), dtype=torch.float64, device=dev)
+    ne = torch.empty(len(pts), dtype=torch.float64, device=dev)
+    ll = torch.empty(N, dtype=torch.float64, device=dev) if want_lnL else None
+    _check(lib.rift_ile_lnZ(cps, len(pts), counts.ctypes.data, th.data_ptr(),
+                            None if w is None else w.data_ptr(), z.data_ptr(), ne.data_ptr(),
+                            None if ll is None else ll.data_ptr(), PRECISIONS[precision],
+                            _stream(dev)), "rift_ile_lnZ")
+    return (z, ne, ll) if want_lnL else (z, ne)
+
+
+class Plan:
+    """Prepared points for repeated (graph-capturable) evaluation."""
+
+    def __init__(self, points, n_per_point, precision: str = "fp64", device="cuda"):
+        self.lib = load()
+        if not isinstance(points, (list, tuple)):
+            points = [points]
+        self.points = [_as_point(p, device) for p in points]
+        self.device = self.points[0].device
+        self.counts = np.asarray(n_per_point, dtype=np.int64)
+        self.N = int(self.counts.sum())
+        self.precision = precision
+        cps = (CPoint * len(self.points))(*[p.cstruct() for p in self.points])
+        h = ctypes.c_void_p()
+        _check(self.lib.rift_ile_plan_create(cps, len(self.points), self.counts.ctypes.data,
+                                             PRECISIONS[precision], _stream(self.device), ctypes.byref(h)),
+               "rift_ile_plan_create")
+        self.handle = h
+
+    def lnZ(self, theta, lnw=None, lnZ_out=None, neff_out=None, lnL_out=None, err_out=None):
+        th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
+            else _theta(theta, self.device)
+        P = len(self.points)
+        z = lnZ_out if lnZ_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        ne = neff_out if neff_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        _check(self.lib.rift_ile_plan_lnZ(self.handle, th.data_ptr(), None if lnw is None else lnw.data_ptr(),
+                                          z.data_ptr(), ne.data_ptr(),
+                                          None if lnL_out is None else lnL_out.data_ptr(),
+                                          None if err_out is None else err_out.data_ptr(),
+                                          _stream(self.device)), "rift_ile_plan_lnZ")
+        return z, ne
+
+    def grad(self, point, theta, lnL_out=None, grad_out=None):
+        th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
+            else _theta(theta, self.device)
+        n = th.shape[1]
+        g = grad_out if grad_out is not None else torch.empty((7, n), dtype=torch.float64, device=self.device)
+        _check(self.lib.rift_ile_plan_grad(self.handle, int(point), n, th.data_ptr(),
+                                           None if lnL_out is None else lnL_out.data_ptr(), g.data_ptr(),
+                                           _stream(self.device)), "rift_ile_plan_grad")
+        return g
+
+    def tune(self, theta, lnw=None) -> int:
+        return _check(self.lib.rift_ile_plan_tune(self.handle, theta.data_ptr(),
+                                                  None if lnw is None else lnw.data_ptr(),
+                                                  _stream(self.device)), "rift_ile_plan_tune")
+
+    @property
+    def config(self):
+        c = CConfig()
+        _check(self.lib.rift_ile_plan_get_config(self.handle, ctypes.byref(c)), "get_config")
+        return {"block": c.block, "tile_blocks": c.tile_blocks, "blocks_per_cu": c.blocks_per_cu}
+
+    @config.setter
+    def config(self, cfg):
+        c = CConfig(int(cfg["block"]), int(cfg["tile_blocks"]), int(cfg["blocks_per_cu"]))
+        _check(self.lib.rift_ile_plan_set_config(self.handle, ctypes.byref(c)), "set_config")
+
+    def refined(self) -> int:
+        v = ctypes.c_int64()
+        _check(self.lib.rift_ile_plan_refined(self.handle, ctypes.byref(v)), "refined")
+        return int(v.value)
+
+    def profile(self, enable: bool):
+        _check(self.lib.rift_ile_plan_profile(self.handle, 1 if enable else 0), "profile")
+
+    def profile_read(self):
+        """(summed kernel ms, launches) of the main evaluation kernel."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self.lib.rift_ile_plan_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)),
+               "profile_read")
+        return ms.value, int(n.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.rift_ile_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LnL(torch.autograd.Function):
+    """lnL(theta) with the hand-written gradient; theta [7, n] in the sampler's
+    coordinates is NOT used directly: inputs are (ra, dec, psi, incl, phiref,
+    tref, dist) and backward returns d/d(ra, dec, psi, incl, phiref, tref, dist)
+    (chain rule from the library's cos(incl) and ln(dist) derivatives)."""
+
+    @staticmethod
+    def forward(ctx, theta, point):
+        l, g = grad(point, theta.detach(), device=theta.device)
+        th = theta.detach()
+        gi = g.clone()
+        gi[3] = -torch.sin(th[3]) * g[3]   # d/dincl = -sin(incl) d/dcos(incl)
+        gi[6] = g[6] / th[6]               # d/ddist = (1/dist) d/dln(dist)
+        ctx.save_for_backward(gi)
+        return l
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (gi,) = ctx.saved_tensors
+        return grad_out[None, :] * gi, None

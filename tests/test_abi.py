@@ -1,0 +1,132 @@
+"""The C ABI on the CPU: the library loads, exports every entry point that
+include/rift_ile.h declares, and its host-side validation rejects bad
+arguments before any HIP call (no GPU needed for these paths)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rift_ile.h")
+EINVAL = -1
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2609_37393_amd import ile
+
+    if not os.path.exists(ile.LIB_PATH):
+        from paper_2609_37393_amd import build
+
+        build.build()
+    return ile.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    decl = set(re.findall(r"\b(rift_ile_\w+)\s*\(", open(HEADER).read()))
+    assert {"rift_ile_lnL", "rift_ile_lnZ", "rift_ile_grad"} <= decl
+    for name in sorted(decl):
+        assert hasattr(lib, name), name
+
+
+def test_version_and_strerror(lib):
+    assert lib.rift_ile_version() == 1
+    assert lib.rift_ile_strerror(0) == b"ok"
+    assert lib.rift_ile_strerror(EINVAL) == b"invalid argument"
+    assert lib.rift_ile_strerror(-99) == b"unknown status"
+
+
+def _point(ile, **over):
+    lm = np.array([[2, 2], [2, -2]], np.int32)
+    D = np.zeros((2, 3, 3))
+    R = np.zeros((2, 3))
+    keep = (lm, D, R)
+    f = dict(n_det=2, n_modes=2, n_t=410, lm=lm.ctypes.data, t0=-0.05, dt=1 / 4096, Q=0x1000,
+             U=0x2000, V=0x3000, det_tensor=D.ctypes.data, det_pos=R.ctypes.data, gmst_rad=0.1,
+             d_ref=100.0)
+    f.update(over)
+    return ile.CPoint(**f), keep
+
+
+BAD = [
+    dict(n_det=0), dict(n_det=9), dict(n_modes=0), dict(n_modes=26), dict(n_t=3),
+    dict(dt=0.0), dict(dt=-1e-3), dict(dt=float("nan")), dict(t0=float("inf")),
+    dict(d_ref=0.0), dict(gmst_rad=float("nan")), dict(Q=None), dict(U=None), dict(V=None),
+    dict(lm=None), dict(det_tensor=None), dict(det_pos=None), dict(Q=0x1004),
+]
+
+
+@pytest.mark.parametrize("over", BAD)
+def test_invalid_point_rejected_on_host(lib, over):
+    from paper_2609_37393_amd import ile
+
+    cp, keep = _point(ile, **over)
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, 0, None) == EINVAL
+    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0x5000, 0x6000, None) == EINVAL
+    n = np.array([10], np.int64)
+    assert lib.rift_ile_lnZ(ctypes.byref(cp), 1, n.ctypes.data, 0x4000, None, 0x5000, None, None, 0,
+                            None) == EINVAL
+
+
+@pytest.mark.parametrize("lm", [[[1, 0], [2, 2]], [[2, 3], [2, 2]], [[9, 0], [2, 2]], [[2, 2], [2, 2]]])
+def test_invalid_modes_rejected(lib, lm):
+    from paper_2609_37393_amd import ile
+
+    arr = np.array(lm, np.int32)
+    cp, keep = _point(ile, lm=arr.ctypes.data)
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, 0, None) == EINVAL
+
+
+def test_invalid_detector_geometry_rejected(lib):
+    from paper_2609_37393_amd import ile
+
+    D = np.zeros((2, 3, 3))
+    D[1, 0, 0] = np.nan
+    cp, keep = _point(ile, det_tensor=D.ctypes.data)
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, 0, None) == EINVAL
+
+
+def test_invalid_call_arguments_rejected(lib):
+    from paper_2609_37393_amd import ile
+
+    cp, keep = _point(ile)
+    # negative n, null or misaligned sample / output pointers, bad precision
+    assert lib.rift_ile_lnL(ctypes.byref(cp), -1, 0x4000, 0x5000, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, None, 0x5000, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, None, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4001, 0x5000, 0, None) == EINVAL
+    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0x5000, None, None) == EINVAL
+    n = np.array([10], np.int64)
+    assert lib.rift_ile_lnZ(ctypes.byref(cp), 0, n.ctypes.data, 0x4000, None, 0x5000, None, None, 0,
+                            None) == EINVAL
+    assert lib.rift_ile_lnZ(ctypes.byref(cp), 1, None, 0x4000, None, 0x5000, None, None, 0,
+                            None) == EINVAL
+    n0 = np.array([0], np.int64)
+    assert lib.rift_ile_lnZ(ctypes.byref(cp), 1, n0.ctypes.data, 0x4000, None, 0x5000, None, None, 0,
+                            None) == EINVAL
+    h = ctypes.c_void_p()
+    assert lib.rift_ile_plan_create(ctypes.byref(cp), 1, n.ctypes.data, 7, None, ctypes.byref(h)) == EINVAL
+    assert lib.rift_ile_plan_destroy(None) == EINVAL
+    assert lib.rift_ile_plan_lnZ(None, 0x4000, None, 0x5000, None, None, None, None) == EINVAL
+    assert lib.rift_ile_plan_grad(None, 0, 1, 0x4000, None, 0x5000, None) == EINVAL
+
+
+def test_zero_samples_is_a_validated_noop(lib):
+    from paper_2609_37393_amd import ile
+
+    cp, keep = _point(ile)
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 0, None, None, 0, None) == 0
+    bad, keep2 = _point(ile, n_det=0)
+    assert lib.rift_ile_lnL(ctypes.byref(bad), 0, None, None, 0, None) == EINVAL
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_2609_37393_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "liboracle" not in txt, f

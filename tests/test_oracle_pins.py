@@ -12,6 +12,8 @@ import pytest
 
 from paper_2609_37393_amd import synth
 
+from ._helpers import consistent_point, response
+
 RNG = np.random.default_rng(12345)
 
 
@@ -225,18 +227,6 @@ def test_pregrid_plus_cubic_beats_native_cubic(oracle_mod):
 # The factored likelihood, Eq. (def:lnL:Decomposed), against the direct
 # noise-weighted inner products of Eqs. (resp:strain:static), (resp:static:ip)
 # ---------------------------------------------------------------------------
-def _response(oracle_mod, pt, th):
-    ra, dec, psi, inc, phi, tref, dist = th
-    K = pt["Q"].shape[0]
-    F = np.zeros(K, complex)
-    tk = np.zeros(K)
-    for k in range(K):
-        F[k], _ = oracle_mod.antenna(pt["det_tensor"][k], ra, dec, psi, pt["gmst"])
-        tk[k] = oracle_mod.arrival_time(pt["det_pos"][k], ra, dec, pt["gmst"], tref)
-    Y = np.array([oracle_mod.ylm(l, m, inc, phi) for l, m in pt["lm"]])
-    return F, tk, Y, pt["d_ref"] / dist
-
-
 def _direct_lnL(sp, F, tk, Y, x):
     """sum_k <h_k|d>_k - 1/2 <h_k|h_k>_k with h_k = Re[F_k T_{t_k} h_Y] built in
     the frequency domain from the mode spectra (no factorisation used)."""
@@ -262,7 +252,7 @@ def test_factored_equals_direct_inner_product(oracle_mod, K, M):
     sp = pt["spectra"]
     th = synth.prior_samples(20, 5)
     for i in range(th.shape[1]):
-        F, tk, Y, x = _response(oracle_mod, pt, th[:, i])
+        F, tk, Y, x = response(oracle_mod, pt, th[:, i])
         Qhat = np.array([_direct_Q(sp, k, tk[k]) for k in range(K)])
         got = oracle_mod.lnL_factored(F, Y, x, Qhat, pt["U"], pt["V"])
         want = _direct_lnL(sp, F, tk, Y, x)
@@ -278,38 +268,8 @@ def test_full_oracle_matches_direct_within_interpolation_error(oracle_mod):
     th = synth.prior_samples(30, 6)
     got = oracle_mod.lnL(pt, th)
     for i in range(th.shape[1]):
-        want = _direct_lnL(sp, *_response(oracle_mod, pt, th[:, i]))
+        want = _direct_lnL(sp, *response(oracle_mod, pt, th[:, i]))
         assert abs(got[i] - want) < 2e-6 * (abs(want) + 60.0**2), (i, got[i], want)
-
-
-def _consistent_point(oracle_mod, K, M, n_t, fs, snr, seed, theta_true, on_node=True, noise=False):
-    """A noiseless injection made *with the oracle's own response* at theta_true,
-    with detector positions nudged along N so each t_k lands on a grid node."""
-    net = synth.network(K, seed)
-    ra, dec, psi, inc, phi, tref, dist = theta_true
-    _, N = oracle_mod.antenna(net["det_tensor"][0], ra, dec, psi, net["gmst"])
-    dt = 1.0 / fs
-    t0 = -(n_t // 2) * dt
-    if on_node:
-        for k in range(K):
-            tk = tref - net["det_pos"][k] @ N
-            node = t0 + dt * round((tk - t0) / dt)
-            net["det_pos"][k] = net["det_pos"][k] + (tk - node) * N
-    F = np.zeros(K, complex)
-    tk = np.zeros(K)
-    for k in range(K):
-        F[k], _ = oracle_mod.antenna(net["det_tensor"][k], ra, dec, psi, net["gmst"])
-        tk[k] = oracle_mod.arrival_time(net["det_pos"][k], ra, dec, net["gmst"], tref)
-    lm = synth.modes(M)
-    Y = np.array([oracle_mod.ylm(l, m, inc, phi) for l, m in lm])
-    x = 100.0 / dist
-    inj = {"z": x * F[:, None] * Y[None, :], "tk": tk}
-    pt = synth.make_point(K, M, n_t, fs, snr, seed, injection=inj, net=net, noise=noise,
-                          keep_spectra=True)
-    # the generator rescales the amplitude to hit `snr`: move the true distance
-    th = np.array(theta_true, dtype=np.float64).copy()
-    th[6] = dist / pt["inj_scale"]
-    return pt, th
 
 
 @pytest.mark.parametrize("snr", [20.0, 600.0])
@@ -317,12 +277,12 @@ def test_noiseless_injection_gives_half_rho_squared(oracle_mod, snr):
     """At the true parameters of a noiseless injection, lnL = rho^2/2 (the data
     term is <h|h> and the model norm is <h|h>)."""
     th0 = np.array([1.1, 0.3, 0.7, 0.9, 2.0, 0.004, 400.0])
-    pt, th0 = _consistent_point(oracle_mod, 3, 9, 6554, 32768.0, snr, 31, th0)
+    pt, th0 = consistent_point(oracle_mod, 3, 9, 6554, 32768.0, snr, 31, th0)
     got = oracle_mod.lnL(pt, th0[:, None])[0]
     assert abs(got - snr**2 / 2) < 1e-10 * snr**2, got
     # off-node: within the cubic's error budget
     th0 = np.array([1.1, 0.3, 0.7, 0.9, 2.0, 0.004, 400.0])
-    pt2, th2 = _consistent_point(oracle_mod, 3, 9, 6554, 32768.0, snr, 31, th0, on_node=False)
+    pt2, th2 = consistent_point(oracle_mod, 3, 9, 6554, 32768.0, snr, 31, th0, on_node=False)
     got2 = oracle_mod.lnL(pt2, th2[:, None])[0]
     assert abs(got2 - snr**2 / 2) < 5e-6 * snr**2
 
@@ -330,7 +290,7 @@ def test_noiseless_injection_gives_half_rho_squared(oracle_mod, snr):
 def test_cauchy_schwarz_bound(oracle_mod):
     """lnL = 1/2<d|d> - 1/2<d-h|d-h> <= 1/2<d|d> for every sample."""
     th0 = np.array([4.0, -0.6, 2.2, 2.1, 0.4, -0.003, 150.0])
-    pt, th0 = _consistent_point(oracle_mod, 3, 9, 6554, 32768.0, 200.0, 41, th0, noise=True)
+    pt, th0 = consistent_point(oracle_mod, 3, 9, 6554, 32768.0, 200.0, 41, th0, noise=True)
     near = synth.perturbed_samples(th0, [1e-3, 1e-3, 5e-3, 5e-3, 5e-3, 3e-6, 5e-3], 500, 3)
     th = np.concatenate([synth.prior_samples(2000, 4), near], axis=1)
     l = oracle_mod.lnL(pt, th)
@@ -445,7 +405,7 @@ def test_lnZ_dense_quadrature_slice(oracle_mod):
     """A periodic grid in (psi, phiref) fed through lnZ is the trapezoid rule of
     the (psi, phiref) marginal; it must agree with Gauss-Legendre quadrature."""
     th0 = np.array([2.3, 0.5, 1.0, 1.2, 0.7, 0.001, 300.0])
-    pt, th0 = _consistent_point(oracle_mod, 3, 4, 3000, 32768.0, 5.0, 61, th0, noise=True)
+    pt, th0 = consistent_point(oracle_mod, 3, 4, 3000, 32768.0, 5.0, 61, th0, noise=True)
     n = 64
     grid = np.repeat(th0[:, None], n * n, axis=1)
     grid[2] = np.repeat(np.pi * np.arange(n) / n, n)
@@ -484,7 +444,7 @@ def _from_coords(c):
 
 def test_gradient_matches_central_differences(oracle_mod):
     th0 = np.array([2.0, -0.2, 0.4, 1.3, 3.0, 0.002, 250.0])
-    pt, th0 = _consistent_point(oracle_mod, 3, 9, 6554, 32768.0, 100.0, 71, th0, noise=True)
+    pt, th0 = consistent_point(oracle_mod, 3, 9, 6554, 32768.0, 100.0, 71, th0, noise=True)
     th = np.concatenate([synth.perturbed_samples(th0, [3e-3, 3e-3, 1e-2, 1e-2, 1e-2, 2e-5, 1e-2], 20, 2),
                          synth.prior_samples(20, 11)], axis=1)
     th[3] = np.clip(th[3], 0.05, np.pi - 0.05)
