@@ -73,7 +73,7 @@ def freq_grid(f_hi: int = 1700):
     return np.arange(-f_hi, f_hi + 1, dtype=np.float64)
 
 
-def mode_spectra(M: int, seed: int, f_lo: float = 20.0, f_hi: int = 1700,
+def mode_spectra(M, seed: int, f_lo: float = 20.0, f_hi: int = 1700,
                  f_c: float = 150.0, width_s: float = 1e-3):
     """Two-sided spectra G_lm(f) of Gaussian-enveloped chirp peaks.
 
@@ -81,13 +81,15 @@ def mode_spectra(M: int, seed: int, f_lo: float = 20.0, f_hi: int = 1700,
     times a seeded phase exp(i(phi0 + 2 pi f tau + beta f^2)) per mode and
     sign of f.  Quadrupole modes get amplitude 1, the others 0.1-0.5.
     """
+    lm = modes(M) if np.isscalar(M) else np.asarray(M, np.int32)
+    M = lm.shape[0]
     rng = _rng(seed, 22)
     f = freq_grid(f_hi)
     sigma_f = 1.0 / (2.0 * np.pi * width_s)
     env = np.exp(-((np.abs(f) - f_c) ** 2) / (2.0 * sigma_f**2))
     env[np.abs(f) < f_lo] = 0.0
     G = np.zeros((M, f.size), np.complex128)
-    for i, (l, m) in enumerate(MODE_ORDER[:M]):
+    for i, (l, m) in enumerate(lm):
         amp = 1.0 if l == 2 and abs(m) == 2 else rng.uniform(0.1, 0.5)
         phi0 = rng.uniform(0, 2 * np.pi, size=2)
         tau = rng.normal(0.0, 2e-4, size=2)
@@ -142,14 +144,17 @@ def _strain(z, tk, f, G):
 
 def make_point(K: int, M: int, n_t: int, fs: float, snr: float, seed: int,
                injection=None, net=None, noise: bool = True, d_ref: float = 100.0,
-               keep_spectra: bool = False):
+               keep_spectra: bool = False, lm=None):
     """One intrinsic point: Q [K, M, n_t] on t_j = t0 + j/fs with t0 = -(n_t//2)/fs,
     U, V [K, M, M], the network, and the injection scaled to network SNR `snr`.
 
     injection: {"z": [K, M] complex, "tk": [K]} (response-folded coefficients and
-    arrival times); default is `random_injection`.
+    arrival times); default is `random_injection`.  lm: explicit [M, 2] mode
+    list (default: the first M of MODE_ORDER).
     """
-    f, G = mode_spectra(M, seed)
+    lm = modes(M) if lm is None else np.asarray(lm, np.int32)
+    M = lm.shape[0]
+    f, G = mode_spectra(lm, seed)
     w = noise_weights(K, f, seed)
     net = net if net is not None else network(K, seed)
     inj = injection if injection is not None else random_injection(K, M, seed)
@@ -186,7 +191,7 @@ def make_point(K: int, M: int, n_t: int, fs: float, snr: float, seed: int,
     idx = np.mod(np.arange(n_t) - j0, nfft)
     Q = full[:, :, idx]
     pt = {
-        "lm": modes(M),
+        "lm": lm,
         "t0": -j0 / fs,
         "dt": 1.0 / fs,
         "Q": Q,

@@ -43,9 +43,7 @@ def consistent_point(oracle_mod, K, M, n_t, fs, snr, seed, theta_true, on_node=T
     x = 100.0 / dist
     inj = {"z": x * F[:, None] * Y[None, :], "tk": tk}
     pt = synth.make_point(K, M, n_t, fs, snr, seed, injection=inj, net=net, noise=noise,
-                          keep_spectra=True)
-    if lm is not None:
-        pt["lm"] = modes
+                          keep_spectra=True, lm=modes)
     th = np.array(theta_true, dtype=np.float64).copy()
     th[6] = dist / pt["inj_scale"]
     return pt, th

@@ -56,9 +56,7 @@ CASES = [
 
 def _point(case):
     K, M, n_t, fs, snr, n, seed, lmax = case
-    pt = synth.make_point(K, M, n_t, fs, snr, seed)
-    if lmax is not None:
-        pt["lm"] = _mode_set(M, lmax)
+    pt = synth.make_point(K, M, n_t, fs, snr, seed, lm=None if lmax is None else _mode_set(M, lmax))
     th = synth.prior_samples(n, seed)
     return pt, th
 
