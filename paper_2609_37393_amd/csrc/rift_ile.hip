@@ -742,8 +742,10 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     d_qmax[pi] = (double*)v;
     PHIP(hipStreamSynchronize(st));  // perm staged before the host vector goes away
   }
-  // a batch mixing l > 4 with smaller points runs every point in the l <= 8
-  // class (exact for any l <= 8, one kernel instance)
+  // kernel instances exist for one class (1, 2, 4, 8) and for any mix of the
+  // l <= 4 classes (7); a batch mixing l > 4 with smaller points runs every
+  // point in the l <= 8 class (exact for any l <= 8)
+  if (!(p->lset & 8) && p->lset != 1 && p->lset != 2 && p->lset != 4) p->lset = 7;
   if ((p->lset & 8) && p->lset != 8) {
     p->lset = 8;
     for (int pi = 0; pi < n_points; ++pi) {
