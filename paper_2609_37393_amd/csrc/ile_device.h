@@ -33,6 +33,7 @@ namespace rift {
 constexpr int KMAX = 8;    // detectors
 constexpr int MMAX = 25;   // modes
 constexpr int LMAXC = 8;   // largest l
+constexpr int QPAD = 4;    // zero rows on each side of every Q series
 
 template <class R>
 struct C2 {
@@ -64,8 +65,11 @@ struct PointDesc {
   // mixed path: |lnL_FP32 - lnL_FP64| <= x bnd_d + x^2 sum_k (|F_k|^2 + 1e-6) bnd_q[k]
   double bnd_d;
   double bnd_q[KMAX];
-  const double* Q64;      // [KT][n_t][M] complex
-  const float* Q32;       // [KT][n_t][M] complex
+  // Q series of each (detector, mode), time-contiguous with QPAD zero rows at
+  // both ends: [KT][M][n_t + 2 QPAD] complex.  A stencil starting at row
+  // j-1 in [-QPAD, n_t] reads padded rows j-1+QPAD .. j+2+QPAD.
+  const double* Q64;
+  const float* Q32;
   const double* C64;      // [B][3 KT]
   const float* C32;       // [B][3 KT]
 };
@@ -227,8 +231,9 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
   // --- antenna factors and stencils per detector --------------------------
   R Fre[KT], Fim[KT];
   R w[KT][4];
-  int64_t rowoff[KT][4];
+  int soff[KT];  // first padded row of the 4-row stencil
   bool bad = false;
+  const int ntp = n_t + 2 * QPAD;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     R fp = 0, fx = 0;
@@ -248,19 +253,14 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
     }
     const double jf = floor(u);
     const R s = (R)(u - jf);
-    const int j = (int)jf;
+    int j0 = (int)jf - 1;  // stencil rows j0 .. j0+3
+    // wholly outside the stored window: read four zero pad rows
+    j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
+    soff[k] = j0 + QPAD;
     w[k][0] = -s * (s - 1) * (s - 2) * (R)(1.0 / 6.0);
     w[k][1] = (s + 1) * (s - 1) * (s - 2) * (R)0.5;
     w[k][2] = -(s + 1) * s * (s - 2) * (R)0.5;
     w[k][3] = (s + 1) * s * (s - 1) * (R)(1.0 / 6.0);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      int row = j - 1 + t;
-      const bool ok = (row >= 0) && (row < n_t);
-      w[k][t] = ok ? w[k][t] : (R)0;
-      row = row < 0 ? 0 : (row >= n_t ? n_t - 1 : row);
-      rowoff[k][t] = ((int64_t)k * n_t + row) * M;
-    }
   }
 
   // --- data term: loop over modes; Y_i = d_i(incl) e^{i m_i phi} ----------
@@ -299,8 +299,10 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
       const R yx = d * ph.x, yy = d * ph.y;
 #pragma unroll
       for (int k = 0; k < KT; ++k) {
-        const C2<R> q0 = ldq(Qt, rowoff[k][0] + i), q1 = ldq(Qt, rowoff[k][1] + i);
-        const C2<R> q2 = ldq(Qt, rowoff[k][2] + i), q3 = ldq(Qt, rowoff[k][3] + i);
+        // series (k, i) starts at a uniform address; the lane's 4 taps are contiguous
+        const RIFT_GLOBAL R* ser = Qt + (int64_t)(k * M + i) * ntp * 2;
+        const C2<R> q0 = ldq(ser, soff[k]), q1 = ldq(ser, soff[k] + 1);
+        const C2<R> q2 = ldq(ser, soff[k] + 2), q3 = ldq(ser, soff[k] + 3);
         const R qx = w[k][0] * q0.x + w[k][1] * q1.x + w[k][2] * q2.x + w[k][3] * q3.x;
         const R qy = w[k][0] * q0.y + w[k][1] * q1.y + w[k][2] * q2.y + w[k][3] * q3.y;
         Z[k].x += yx * qx + yy * qy;

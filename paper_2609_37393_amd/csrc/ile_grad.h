@@ -76,7 +76,8 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
   // antenna factors, their derivatives and the stencils
   double Fp[KT], Fx[KT], dFg[KT][2], dFd[KT][2], dtg[KT], dtd[KT];
   double w[KT][4], wd[KT][4];
-  int64_t rowoff[KT][4];
+  int soff[KT];
+  const int ntp = n_t + 2 * QPAD;
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
@@ -112,7 +113,9 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
     }
     const double jf = floor(u);
     const double s = u - jf;
-    const int j = (int)jf;
+    int j0 = (int)jf - 1;
+    j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
+    soff[k] = j0 + QPAD;
     const double s2 = s * s;
     const double idt = P->inv_dt;
     w[k][0] = -s * (s - 1.0) * (s - 2.0) / 6.0;
@@ -123,17 +126,6 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
     wd[k][1] = (3.0 * s2 - 4.0 * s - 1.0) * 0.5 * idt;
     wd[k][2] = -(3.0 * s2 - 2.0 * s - 2.0) * 0.5 * idt;
     wd[k][3] = (3.0 * s2 - 1.0) / 6.0 * idt;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      int row = j - 1 + t;
-      const bool ok = (row >= 0) && (row < n_t);
-      if (!ok) {
-        w[k][t] = 0.0;
-        wd[k][t] = 0.0;
-      }
-      row = row < 0 ? 0 : (row >= n_t ? n_t - 1 : row);
-      rowoff[k][t] = ((int64_t)k * n_t + row) * M;
-    }
   }
 
   // data term and its derivatives: loop over modes
@@ -177,8 +169,9 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
       const double mv = (double)mi;
 #pragma unroll
       for (int k = 0; k < KT; ++k) {
-        const C2<double> q0 = ldq(Qt, rowoff[k][0] + i), q1 = ldq(Qt, rowoff[k][1] + i);
-        const C2<double> q2 = ldq(Qt, rowoff[k][2] + i), q3 = ldq(Qt, rowoff[k][3] + i);
+        const RIFT_GLOBAL double* ser = Qt + (int64_t)(k * M + i) * ntp * 2;
+        const C2<double> q0 = ldq(ser, soff[k]), q1 = ldq(ser, soff[k] + 1);
+        const C2<double> q2 = ldq(ser, soff[k] + 2), q3 = ldq(ser, soff[k] + 3);
         const double qx = w[k][0] * q0.x + w[k][1] * q1.x + w[k][2] * q2.x + w[k][3] * q3.x;
         const double qy = w[k][0] * q0.y + w[k][1] * q1.y + w[k][2] * q2.y + w[k][3] * q3.y;
         const double tx = wd[k][0] * q0.x + wd[k][1] * q1.x + wd[k][2] * q2.x + wd[k][3] * q3.x;

@@ -34,19 +34,22 @@ namespace {
 // Setup kernels
 // ---------------------------------------------------------------------------
 
-// Q[k][i][t] (caller order, complex) -> Qt[k][t][i_internal]; padded detectors 0.
+// Q[k][i][t] (caller order, complex) -> Qt[k][i_internal][QPAD + t], every
+// series padded with QPAD zero rows at both ends; padded detectors all zero.
 __global__ void k_repack(const double* __restrict__ Q, double* __restrict__ Q64,
                          float* __restrict__ Q32, const int32_t* __restrict__ perm, int K, int KT,
                          int M, int n_t) {
-  const int64_t total = (int64_t)KT * n_t * M;
+  const int ntp = n_t + 2 * QPAD;
+  const int64_t total = (int64_t)KT * M * ntp;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % M);
-    const int64_t kt = e / M;
-    const int t = (int)(kt % n_t);
-    const int k = (int)(kt / n_t);
+    const int tp = (int)(e % ntp);
+    const int64_t ki = e / ntp;
+    const int i = (int)(ki % M);
+    const int k = (int)(ki / M);
+    const int t = tp - QPAD;
     double re = 0.0, im = 0.0;
-    if (k < K) {
+    if (k < K && t >= 0 && t < n_t) {
       const int64_t src = ((int64_t)k * M + perm[i]) * n_t + t;
       re = Q[2 * src];
       im = Q[2 * src + 1];
@@ -60,10 +63,10 @@ __global__ void k_repack(const double* __restrict__ Q, double* __restrict__ Q64,
   }
 }
 
-// out[k] = max_{t,i} |Q64[k][t][i]|, one block per detector.
+// out[k] = max |Q64| over detector k's series, one block per detector.
 __global__ void k_qmax(const double* __restrict__ Q64, double* __restrict__ out, int n_t, int M) {
   const int k = blockIdx.x;
-  const int64_t n = (int64_t)n_t * M;
+  const int64_t n = (int64_t)(n_t + 2 * QPAD) * M;
   const double* q = Q64 + 2 * (int64_t)k * n;
   double m = 0.0;
   for (int64_t e = threadIdx.x; e < n; e += blockDim.x) m = fmax(m, hypot(q[2 * e], q[2 * e + 1]));
@@ -722,7 +725,7 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     }
     D.m_min = D.m[0];
     // device tables
-    const int64_t qn = (int64_t)KT * pt.n_t * M;
+    const int64_t qn = (int64_t)KT * (pt.n_t + 2 * QPAD) * M;
     PCHK(palloc(p, sizeof(double) * 2 * qn, &v));
     D.Q64 = (const double*)v;
     if (mixed) {
@@ -772,11 +775,11 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
   for (int pi = 0; pi < n_points; ++pi) {
     const rift_ile_point& pt = pts[pi];
     PointDesc& D = p->h_desc[pi];
-    const int64_t qn = (int64_t)KT * pt.n_t * pt.n_modes;
+    const int64_t qn = (int64_t)KT * (pt.n_t + 2 * QPAD) * pt.n_modes;
     const int gq = (int)std::min<int64_t>((qn + 255) / 256, 65535);
     hipLaunchKernelGGL(k_repack, dim3(gq), dim3(256), 0, st, pt.Q, (double*)D.Q64, (float*)D.Q32,
                        d_perm[pi], pt.n_det, KT, pt.n_modes, pt.n_t);
-    hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(256), 0, st, D.Q64, d_qmax[pi], pt.n_t, pt.n_modes);
+    hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(1024), 0, st, D.Q64, d_qmax[pi], pt.n_t, pt.n_modes);
     const int NG = 4 * D.L + 4;
     hipLaunchKernelGGL(k_basis, dim3(KT), dim3(256), sizeof(double) * 3 * NG * NG, st,
                        p->d_desc + pi, pt.U, pt.V, d_perm[pi], (double*)D.C64, (float*)D.C32);
