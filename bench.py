@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--extras", action="store_true", help="also run the C1/C3/C4/C5 workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a plain 256-MiB elementwise copy kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -400,6 +402,13 @@ def main():
             except Exception as e:  # report, keep the headline line
                 out[name] = {"error": repr(e)}
             torch.cuda.empty_cache()
+    if args.calib_copy:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.add(a, 0.0, out=b)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

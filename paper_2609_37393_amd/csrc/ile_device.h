@@ -392,6 +392,21 @@ __device__ __forceinline__ MS ms_of(double l) {
   }
   return r;
 }
+// Add one sample's l to (max, sum): one exp instead of two.
+__device__ __forceinline__ MS ms_push(MS a, double l) {
+  if (l != l) {  // NaN poisons the sum
+    a.s = __builtin_nan("");
+    return a;
+  }
+  if (l == -__builtin_inf()) return a;
+  if (l > a.m) {
+    a.s = (a.s == 0.0) ? 1.0 : a.s * exp(a.m - l) + 1.0;
+    a.m = l;
+  } else {
+    a.s += exp(l - a.m);
+  }
+  return a;
+}
 __device__ __forceinline__ MS ms_combine(MS a, MS b) {
   MS r;
   r.m = fmax(a.m, b.m);

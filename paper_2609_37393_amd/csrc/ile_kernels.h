@@ -50,7 +50,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
     const double w = lnw ? lnw[i] : 0.0;
     if (lnL) lnL[i] = e.lnL;
     if (MODE == MODE_LSE64) {
-      acc = ms_combine(acc, ms_of(e.lnL + w));
+      acc = ms_push(acc, e.lnL + w);
     } else {
       as_global_w(a.bnd)[i] = e.bound;
       const double v = e.lnL + w - (double)e.bound;

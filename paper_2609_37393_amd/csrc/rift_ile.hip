@@ -247,9 +247,11 @@ __global__ void k_final(const Tile* __restrict__ tiles, const double* __restrict
   for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
     const int64_t i = t.s + o;
     const double l = lnL[i] + (lnw ? lnw[i] : 0.0);
-    acc = ms_combine(acc, ms_of(l));
+    acc = ms_push(acc, l);
     const float b = bnd[i];
-    if (b > 0.0f && l == l && l > -__builtin_inf()) err += exp(l + log(expm1((double)b)) - ml);
+    // unrefined samples: exp(l - M_low) (e^b - 1), skipped once it underflows
+    const double lb = l + (double)b - ml;
+    if (b > 0.0f && lb > -745.0) err += exp(l - ml + log(expm1((double)b)));
   }
   const MS r = ms_block(acc, sh);
   err = dsum_wave(err);
