@@ -159,9 +159,11 @@ int rift_ile_plan_tune(rift_ile_plan plan, const double *theta, const double *ln
 /* Launch shape of the plan: threads per block, samples per tile, persistent
  * blocks per CU.  Setting validates on the host. */
 typedef struct {
-  int32_t block;        /* 64, 128, 256, 512 */
-  int32_t tile_blocks;  /* samples per tile = block * tile_blocks */
-  int32_t blocks_per_cu; /* persistent grid = blocks_per_cu * CUs */
+  int32_t block;         /* 64, 128, 256, 512 */
+  int32_t tile_blocks;   /* samples per tile = block * tile_blocks */
+  int32_t blocks_per_cu; /* persistent grid = blocks_per_cu * CUs; 0 = one block per tile */
+  int32_t sort;          /* 1: bin the batch by detector arrival times first so that a
+                            wavefront's Q reads share cache lines; 0: evaluate in input order */
 } rift_ile_config;
 int rift_ile_plan_get_config(rift_ile_plan plan, rift_ile_config *cfg);
 int rift_ile_plan_set_config(rift_ile_plan plan, const rift_ile_config *cfg);

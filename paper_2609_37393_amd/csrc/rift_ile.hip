@@ -310,6 +310,248 @@ __global__ void k_merge(const PointDesc* __restrict__ descs, const int32_t* __re
 }
 
 // ---------------------------------------------------------------------------
+// Arrival-time binning: samples are counting-sorted by a Morton key of their
+// stencil rows at (up to) three detectors, so that the 64 lanes of a
+// wavefront read nearby rows of every Q series.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long ord_enc(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double ord_dec(unsigned long long e) {
+  const unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+  return __longlong_as_double((long long)b);
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int n, unsigned long long v0,
+                           unsigned long long v1) {
+  // even slots v0 (running min), odd slots v1 (running max)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = (i & 1) ? v1 : v0;
+}
+
+// Stencil row coordinate u_k = (t_k - t0)/dt of the first bin_dims detectors,
+// stored per sample, and its range per (point, detector).
+__global__ void k_bin_range(const PointDesc* __restrict__ descs, const Tile* __restrict__ tiles,
+                            const double* __restrict__ theta, int64_t N, float* __restrict__ ucoord,
+                            unsigned long long* __restrict__ range) {
+  const Tile t = tiles[blockIdx.x];
+  const PointDesc* P = descs + t.p;
+  const int D = P->bin_dims;
+  double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
+  double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    double sg, cg, sd, cd;
+    sincos(P->gmst - theta[i], &sg, &cg);
+    sincos(theta[N + i], &sd, &cd);
+    const double N0 = cd * cg, N1 = -cd * sg, N2 = sd;
+    for (int k = 0; k < D; ++k) {
+      const double tk = theta[5 * N + i] - (P->rpos[k][0] * N0 + P->rpos[k][1] * N1 + P->rpos[k][2] * N2);
+      const double u = (tk - P->t0) * P->inv_dt;
+      ucoord[3 * i + k] = (float)u;
+      if (u == u && fabs(u) < 1e9) {
+        lo[k] = fmin(lo[k], u);
+        hi[k] = fmax(hi[k], u);
+      }
+    }
+  }
+  __shared__ double sh[2][3][8];
+  for (int k = 0; k < 3; ++k) {
+    double a = lo[k], b = hi[k];
+    for (int off = 32; off >= 1; off >>= 1) {
+      a = fmin(a, __shfl_xor(a, off));
+      b = fmax(b, __shfl_xor(b, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      sh[0][k][threadIdx.x >> 6] = a;
+      sh[1][k][threadIdx.x >> 6] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)D) {
+    const int k = threadIdx.x;
+    double a = sh[0][k][0], b = sh[1][k][0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      a = fmin(a, sh[0][k][w]);
+      b = fmax(b, sh[1][k][w]);
+    }
+    if (a <= b) {
+      atomicMin(range + 6 * t.p + 2 * k, ord_enc(a));
+      atomicMax(range + 6 * t.p + 2 * k + 1, ord_enc(b));
+    }
+  }
+}
+
+
+// Bucket of every sample (Morton order of its cells) and the histogram.
+__global__ void k_bin_keys(const PointDesc* __restrict__ descs, const Tile* __restrict__ tiles,
+                           const float* __restrict__ ucoord, const unsigned long long* __restrict__ range,
+                           int32_t* __restrict__ bucket, int32_t* __restrict__ hist) {
+  const Tile t = tiles[blockIdx.x];
+  const PointDesc* P = descs + t.p;
+  const int D = P->bin_dims, bits = P->bin_bits;
+  const int ncell = 1 << bits;
+  float lo[3], inv[3];
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = 0.0f;
+    inv[k] = 0.0f;
+    if (k < D) {
+      const double a = ord_dec(range[6 * t.p + 2 * k]), b = ord_dec(range[6 * t.p + 2 * k + 1]);
+      if (a <= b) {
+        lo[k] = (float)a;
+        inv[k] = (float)(ncell / (b - a + 1e-3));
+      }
+    }
+  }
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    uint32_t key = 0;
+    for (int k = 0; k < D; ++k) {
+      const float f = (ucoord[3 * i + k] - lo[k]) * inv[k];
+      const int c = (f >= 0.0f) ? (f < (float)(ncell - 1) ? (int)f : ncell - 1) : 0;  // NaN -> 0
+      // Morton interleave with stride D: key < 2^(D bits)
+      for (int b = 0; b < bits; ++b) key |= (((uint32_t)c >> b) & 1u) << (D * b + k);
+    }
+    const int32_t bkt = (int32_t)(P->bin_base + key);
+    bucket[i] = bkt;
+    atomicAdd(hist + bkt, 1);
+  }
+}
+
+// Exclusive scan of n int32 (three kernels): block sums, scan of the sums,
+// per-block scan plus offset.  Each block covers SCAN_CHUNK elements.
+constexpr int SCAN_T = 256, SCAN_PER = 16, SCAN_CHUNK = SCAN_T * SCAN_PER;
+
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* sh, int32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t acc = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      const int32_t t = sh[w];
+      sh[w] = acc;
+      acc += t;
+    }
+    sh[8] = acc;
+  }
+  __syncthreads();
+  const int32_t r = x - v + sh[wave];
+  *total = sh[8];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_scan_sums(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ sums) {
+  __shared__ int32_t sh[9];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+  int32_t v = 0;
+  for (int j = 0; j < SCAN_PER; ++j)
+    if (base + j < n) v += a[base + j];
+  int32_t tot;
+  block_excl_scan(v, sh, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(int32_t* __restrict__ sums, int nb) {
+  // one block: exclusive scan of nb block sums, in chunks of the block size
+  __shared__ int32_t sh[9];
+  int32_t carry = 0;
+  for (int b0 = 0; b0 < nb; b0 += blockDim.x) {
+    const int j = b0 + threadIdx.x;
+    const int32_t v = (j < nb) ? sums[j] : 0;
+    int32_t tot;
+    const int32_t e = block_excl_scan(v, sh, &tot);
+    if (j < nb) sums[j] = carry + e;
+    carry += tot;
+  }
+}
+
+__global__ void k_scan_apply(const int32_t* __restrict__ a, int64_t n, const int32_t* __restrict__ sums,
+                             int32_t* __restrict__ out, int32_t* __restrict__ out2) {
+  __shared__ int32_t sh[9];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+  int32_t loc[SCAN_PER];
+  int32_t v = 0;
+  for (int j = 0; j < SCAN_PER; ++j) {
+    loc[j] = (base + j < n) ? a[base + j] : 0;
+    v += loc[j];
+  }
+  int32_t tot;
+  int32_t e = block_excl_scan(v, sh, &tot) + sums[blockIdx.x];
+  for (int j = 0; j < SCAN_PER; ++j) {
+    if (base + j < n) {
+      out[base + j] = e;
+      out2[base + j] = e;
+    }
+    e += loc[j];
+  }
+}
+
+// Counting-sort scatter: every sample takes the next slot of its bucket.
+__global__ void k_bin_scatter(const Tile* __restrict__ tiles, const double* __restrict__ theta, int64_t N,
+                              const int32_t* __restrict__ bucket, int32_t* __restrict__ cursor,
+                              double* __restrict__ aos, int32_t* __restrict__ perm) {
+  const Tile t = tiles[blockIdx.x];
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    const int64_t slot = atomicAdd(cursor + bucket[i], 1);
+    double* dst = aos + 8 * slot;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) dst[a] = theta[a * N + i];
+    dst[7] = 0.0;
+    perm[slot] = (int32_t)i;
+  }
+}
+
+// Per-tile (max, sum) over lnL + lnw in input order (deterministic).
+__global__ void k_lse_tiles(const Tile* __restrict__ tiles, const double* __restrict__ lnL,
+                            const double* __restrict__ lnw, double* __restrict__ part) {
+  __shared__ MS sh[8];
+  const Tile t = tiles[blockIdx.x];
+  MS acc;
+  acc.m = -__builtin_inf();
+  acc.s = 0.0;
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    acc = ms_push(acc, lnL[i] + (lnw ? lnw[i] : 0.0));
+  }
+  const MS r = ms_block(acc, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r.m;
+    part[2 * blockIdx.x + 1] = r.s;
+  }
+}
+
+// Per-tile max(lnL32 + lnw - bound) in input order (mixed path).
+__global__ void k_tmax_tiles(const Tile* __restrict__ tiles, const double* __restrict__ lnL,
+                             const double* __restrict__ lnw, const float* __restrict__ bnd,
+                             double* __restrict__ tmax) {
+  __shared__ double shd[8];
+  const Tile t = tiles[blockIdx.x];
+  double m = -__builtin_inf();
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    const double v = lnL[i] + (lnw ? lnw[i] : 0.0) - (double)bnd[i];
+    if (v == v) m = fmax(m, v);
+  }
+  m = dmax_wave(m);
+  if ((threadIdx.x & 63) == 0) shd[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = shd[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, shd[w]);
+    tmax[blockIdx.x] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host helpers
 // ---------------------------------------------------------------------------
 #define HCHK(x)                                   \
@@ -421,7 +663,7 @@ struct rift_ile_plan_s {
   PointDesc* d_desc = nullptr;
   std::vector<void*> bufs;  // device allocations owned by the plan
   // tiles (depend on the config)
-  rift_ile_config cfg{256, 4, 4};
+  rift_ile_config cfg{256, 4, 4, 1};
   std::vector<Tile> h_tiles;
   Tile* d_tiles = nullptr;
   int n_tiles = 0;
@@ -437,6 +679,16 @@ struct rift_ile_plan_s {
   float* d_bnd = nullptr;     // [N]
   double* d_L = nullptr;      // [N]
   int refine_blocks = 32;
+  // binning (sorted evaluation)
+  int64_t n_buckets = 0;
+  float* d_ucoord = nullptr;               // [N][3]
+  int32_t* d_bucket = nullptr;             // [N]
+  int32_t* d_hist = nullptr;               // [n_buckets]
+  int32_t* d_cursor = nullptr;             // [n_buckets]
+  int32_t* d_scan = nullptr;               // block sums
+  unsigned long long* d_range = nullptr;   // [n_points][3][2]
+  double* d_aos = nullptr;                 // [N][8]
+  int32_t* d_perm = nullptr;               // [N]
   hipStream_t last = nullptr;
   // optional timing of the main evaluation kernel
   bool profiling = false;
@@ -533,6 +785,7 @@ int validate_config(const rift_ile_config* c) {
   if (c->block != 64 && c->block != 128 && c->block != 256 && c->block != 512) return RIFT_EINVAL;
   if (c->tile_blocks < 1 || c->tile_blocks > 64) return RIFT_EINVAL;
   if (c->blocks_per_cu < 0 || c->blocks_per_cu > 32) return RIFT_EINVAL;
+  if (c->sort != 0 && c->sort != 1) return RIFT_EINVAL;
   return RIFT_OK;
 }
 
@@ -551,6 +804,8 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.bnd = p->d_bnd;
   a.part = p->d_part;
   a.tmax = p->d_tmax;
+  a.theta_aos = p->cfg.sort ? p->d_aos : nullptr;
+  a.perm = p->cfg.sort ? p->d_perm : nullptr;
   tile_fn f = pick_tiles_kt(mode == MODE_LSE64, p->KT, p->lset);
   if (!f) return RIFT_EUNSUPPORTED;
   int grid = p->n_tiles;
@@ -577,6 +832,34 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
 void clear_events(rift_ile_plan p) {
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   p->ev.clear();
+}
+
+unsigned long long ord_enc_host(double x) {
+  unsigned long long b;
+  memcpy(&b, &x, sizeof b);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Counting sort of the batch into arrival-time buckets (see k_bin_*).
+int run_binning(rift_ile_plan p, const double* theta, hipStream_t st) {
+  const int blk = p->cfg.block;
+  hipLaunchKernelGGL(k_fill_u64, dim3((6 * p->n_points + 255) / 256), dim3(256), 0, st, p->d_range,
+                     6 * p->n_points, ord_enc_host(__builtin_inf()), ord_enc_host(-__builtin_inf()));
+  hipLaunchKernelGGL(k_bin_range, dim3(p->n_tiles), dim3(blk), 0, st, p->d_desc, p->d_tiles, theta, p->N,
+                     p->d_ucoord, p->d_range);
+  const int nbk = (int)p->n_buckets;
+  hipLaunchKernelGGL(k_fill_i32, dim3(std::min((nbk + 255) / 256, 65535)), dim3(256), 0, st, p->d_hist, nbk, 0);
+  hipLaunchKernelGGL(k_bin_keys, dim3(p->n_tiles), dim3(blk), 0, st, p->d_desc, p->d_tiles,
+                     (const float*)p->d_ucoord, (const unsigned long long*)p->d_range, p->d_bucket, p->d_hist);
+  const int nb = (int)((p->n_buckets + SCAN_CHUNK - 1) / SCAN_CHUNK);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_T), 0, st, (const int32_t*)p->d_hist, p->n_buckets, p->d_scan);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, st, p->d_scan, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, st, (const int32_t*)p->d_hist, p->n_buckets,
+                     (const int32_t*)p->d_scan, p->d_hist, p->d_cursor);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(p->n_tiles), dim3(blk), 0, st, p->d_tiles, theta, p->N,
+                     (const int32_t*)p->d_bucket, p->d_cursor, p->d_aos, p->d_perm);
+  HCHK(hipGetLastError());
+  return RIFT_OK;
 }
 
 }  // namespace
@@ -702,6 +985,13 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     D.gmst = pt.gmst_rad;
     D.d_ref = pt.d_ref;
     D.lnN = log((double)D.n);
+    // binning: about 48 samples per occupied-or-not bucket, <= 6 bits per detector
+    D.bin_dims = std::min(K, 3);
+    {
+      int tot = (int)ceil(log2(std::max(1.0, (double)D.n / 48.0)));
+      tot = std::max(0, std::min(18, tot));
+      D.bin_bits = tot / D.bin_dims;
+    }
     // refinement margin: an unrefined sample weighs < e^{-T} of the best one
     D.T = log((double)D.n) + 12.0;
     p->lset |= lbit(D.L);
@@ -816,9 +1106,41 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
       D.bnd_q[k] = 2.0 * (60.0 + (double)D.B) * u * l1;
     }
   }
+  // bucket bases of the binning
+  {
+    int64_t base = 0;
+    for (int pi = 0; pi < n_points; ++pi) {
+      p->h_desc[pi].bin_base = base;
+      base += (int64_t)1 << (p->h_desc[pi].bin_dims * p->h_desc[pi].bin_bits);
+    }
+    if (base > 0x3fffffff) {
+      plan_free_all(p);
+      delete p;
+      return RIFT_EUNSUPPORTED;
+    }
+    p->n_buckets = base;
+  }
   PHIP(hipMemcpy(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice));
   PCHK(palloc(p, sizeof(int32_t) * 64, &v));
   p->d_counter = (int32_t*)v;
+  PCHK(palloc(p, sizeof(float) * 3 * N, &v));
+  p->d_ucoord = (float*)v;
+  PCHK(palloc(p, sizeof(int32_t) * N, &v));
+  p->d_bucket = (int32_t*)v;
+  PCHK(palloc(p, sizeof(int32_t) * p->n_buckets, &v));
+  p->d_hist = (int32_t*)v;
+  PCHK(palloc(p, sizeof(int32_t) * p->n_buckets, &v));
+  p->d_cursor = (int32_t*)v;
+  PCHK(palloc(p, sizeof(int32_t) * ((p->n_buckets + SCAN_CHUNK - 1) / SCAN_CHUNK + 1), &v));
+  p->d_scan = (int32_t*)v;
+  PCHK(palloc(p, sizeof(unsigned long long) * 6 * n_points, &v));
+  p->d_range = (unsigned long long*)v;
+  PCHK(palloc(p, sizeof(double) * 8 * N, &v));
+  p->d_aos = (double*)v;
+  PCHK(palloc(p, sizeof(int32_t) * N, &v));
+  p->d_perm = (int32_t*)v;
+  PCHK(palloc(p, sizeof(double) * N, &v));
+  p->d_L = (double*)v;
   if (mixed) {
     PCHK(palloc(p, sizeof(double) * n_points, &v));
     p->d_mlow = (double*)v;
@@ -828,8 +1150,6 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     p->d_list = (int32_t*)v;
     PCHK(palloc(p, sizeof(float) * N, &v));
     p->d_bnd = (float*)v;
-    PCHK(palloc(p, sizeof(double) * N, &v));
-    p->d_L = (double*)v;
   }
   PCHK(build_tiles(p));
 #undef PCHK
@@ -865,15 +1185,23 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
   hipStream_t st = (hipStream_t)stream;
   p->last = st;
   int rc;
+  const bool sorted = p->cfg.sort != 0;
+  double* L = lnL ? lnL : p->d_L;
+  if (sorted && (rc = run_binning(p, theta, st))) return rc;
   if (p->prec == RIFT_FP64) {
-    if ((rc = launch_tiles(p, MODE_LSE64, theta, lnw, lnL, st))) return rc;
+    if ((rc = launch_tiles(p, MODE_LSE64, theta, lnw, sorted ? L : lnL, st))) return rc;
+    if (sorted)
+      hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
+                         lnw, p->d_part);
     hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_part,
                        (const double*)nullptr, (const double*)nullptr, lnZ, neff, lnZ_err);
     HCHK(hipGetLastError());
     return RIFT_OK;
   }
-  double* L = lnL ? lnL : p->d_L;
   if ((rc = launch_tiles(p, MODE_PASS32, theta, lnw, L, st))) return rc;
+  if (sorted)
+    hipLaunchKernelGGL(k_tmax_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
+                       lnw, (const float*)p->d_bnd, p->d_tmax);
   hipLaunchKernelGGL(k_mlow, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_tmax,
                      p->d_mlow);
   hipLaunchKernelGGL(k_fill_i32, dim3((p->n_points + 255) / 256), dim3(256), 0, st, p->d_cnt,
@@ -938,8 +1266,9 @@ int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, 
   const bool prof = p->profiling;
   p->profiling = false;
   static const rift_ile_config cands[] = {
-      {256, 1, 0}, {256, 4, 0}, {128, 4, 0}, {512, 2, 0}, {256, 1, 4}, {256, 2, 4},
-      {256, 4, 4}, {256, 8, 2}, {128, 8, 4}, {512, 1, 2}, {512, 2, 2}, {64, 16, 8},
+      {256, 1, 0, 1}, {256, 4, 0, 1}, {128, 4, 0, 1}, {512, 2, 0, 1}, {256, 1, 4, 1}, {256, 2, 4, 1},
+      {256, 4, 4, 1}, {256, 8, 2, 1}, {128, 8, 4, 1}, {512, 1, 2, 1}, {64, 16, 8, 1},
+      {256, 4, 0, 0}, {256, 8, 2, 0}, {512, 2, 0, 0},
   };
   const int nc = (int)(sizeof(cands) / sizeof(cands[0]));
   double* d_out = nullptr;
@@ -1002,6 +1331,7 @@ int rift_ile_lnL(const rift_ile_point* pt, int64_t n, const double* theta, doubl
   int rc = rift_ile_plan_create(pt, 1, &n, precision, stream, &p);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
+  p->cfg.sort = 0;  // input-order evaluation: no reduction follows
   rc = launch_tiles(p, precision == RIFT_FP64 ? MODE_LSE64 : MODE_PASS32, theta, nullptr, lnL, st);
   int rc2 = rift_ile_plan_destroy(p);
   return rc ? rc : rc2;

@@ -61,7 +61,7 @@ class CPoint(ctypes.Structure):
 
 class CConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile_blocks", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("sort", ctypes.c_int32)]
 
 
 _lib = None
@@ -277,11 +277,14 @@ class Plan:
     def config(self):
         c = CConfig()
         _check(self.lib.rift_ile_plan_get_config(self.handle, ctypes.byref(c)), "get_config")
-        return {"block": c.block, "tile_blocks": c.tile_blocks, "blocks_per_cu": c.blocks_per_cu}
+        return {"block": c.block, "tile_blocks": c.tile_blocks, "blocks_per_cu": c.blocks_per_cu,
+                "sort": c.sort}
 
     @config.setter
     def config(self, cfg):
-        c = CConfig(int(cfg["block"]), int(cfg["tile_blocks"]), int(cfg["blocks_per_cu"]))
+        cur = self.config
+        cur.update(cfg)
+        c = CConfig(int(cur["block"]), int(cur["tile_blocks"]), int(cur["blocks_per_cu"]), int(cur["sort"]))
         _check(self.lib.rift_ile_plan_set_config(self.handle, ctypes.byref(c)), "set_config")
 
     def refined(self) -> int:

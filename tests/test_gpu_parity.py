@@ -225,8 +225,8 @@ def test_launch_shapes_agree_and_are_deterministic(ile):
     tht = torch.as_tensor(th, device="cuda").contiguous()
     plan = ile.Plan([pt], [th.shape[1]])
     ref = None
-    for cfg in [dict(block=256, tile_blocks=4, blocks_per_cu=4), dict(block=64, tile_blocks=1, blocks_per_cu=0),
-                dict(block=512, tile_blocks=2, blocks_per_cu=2), dict(block=128, tile_blocks=8, blocks_per_cu=8)]:
+    for cfg in [dict(block=256, tile_blocks=4, blocks_per_cu=4, sort=1), dict(block=64, tile_blocks=1, blocks_per_cu=0, sort=0),
+                dict(block=512, tile_blocks=2, blocks_per_cu=2, sort=1), dict(block=128, tile_blocks=8, blocks_per_cu=8, sort=0)]:
         plan.config = cfg
         z1, _ = plan.lnZ(tht)
         z2, _ = plan.lnZ(tht)
@@ -236,6 +236,29 @@ def test_launch_shapes_agree_and_are_deterministic(ile):
         assert abs(z1.item() - ref) <= 1e-12 * max(1, abs(ref))
     best = plan.tune(tht)
     assert best >= 0
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sorted_evaluation_is_bitwise_identical(ile, prec):
+    """Binning the batch by arrival time changes only the evaluation order:
+    per-sample lnL and the input-order reductions are bitwise identical."""
+    import torch
+
+    pts = synth.batched_points(4, 21, K=3, nt_range=(400, 6554))
+    counts = [20000, 5000, 777, 30000]
+    th = np.concatenate([synth.prior_samples(c, 400 + i) for i, c in enumerate(counts)], axis=1)
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    lnw = torch.as_tensor(np.random.default_rng(2).normal(0, 1, th.shape[1]), device="cuda")
+    plan = ile.Plan(pts, counts, precision=prec)
+    res = {}
+    for sort in (0, 1):
+        plan.config = dict(block=256, tile_blocks=4, blocks_per_cu=2, sort=sort)
+        ll = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
+        z, ne = plan.lnZ(tht, lnw=lnw, lnL_out=ll)
+        res[sort] = (ll.clone(), z.clone(), ne.clone())
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
     plan.close()
 
 
