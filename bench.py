@@ -99,6 +99,20 @@ def run_path(ile, torch, pt, tht, precision, steps, warmup, tune):
     def step():
         plan.lnZ(tht, lnZ_out=z, neff_out=ne, lnL_out=lnl, err_out=err)
 
+    # the tuned shape with and without arrival-time binning (context only)
+    variants = {}
+    base = plan.config
+    for srt in (0, 1):
+        cfg = dict(base)
+        cfg["sort"] = srt
+        plan.config = cfg
+        sec_v, _ = time_steps(step, max(3, steps // 5), 2, torch)
+        plan.profile(True)
+        step()
+        kms_v, nl = plan.profile_read()
+        plan.profile(False)
+        variants[f"sort{srt}"] = {"ms_per_step": 1e3 * sec_v / max(3, steps // 5), "kernel_ms": kms_v / max(1, nl)}
+    plan.config = base
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -116,6 +130,7 @@ def run_path(ile, torch, pt, tht, precision, steps, warmup, tune):
         "lnZ_err_bound": err.item(),
         "config": plan.config,
         "refined": plan.refined() if precision == "mixed" else 0,
+        "variants": variants,
         "lnL": lnl,
     }
     plan.close()
@@ -358,6 +373,7 @@ def main():
                         "network SNR 600, 1e6 prior extrinsic samples; lnL per sample + ln Z",
             "n_samples": n,
             "launch": r64["config"],
+            "launch_variants": r64["variants"],
         },
         "roofline": {
             "bound": "alu",

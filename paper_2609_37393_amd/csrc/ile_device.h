@@ -310,8 +310,11 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
         const C2<R> q2 = ldq(ser, soff[k] + 2), q3 = ldq(ser, soff[k] + 3);
         const R qx = w[k][0] * q0.x + w[k][1] * q1.x + w[k][2] * q2.x + w[k][3] * q3.x;
         const R qy = w[k][0] * q0.y + w[k][1] * q1.y + w[k][2] * q2.y + w[k][3] * q3.y;
-        Z[k].x += yx * qx + yy * qy;
-        Z[k].y += yx * qy - yy * qx;
+        // separate FMA chains (a + (b + c) would cost mul + fma + add)
+        Z[k].x = fma(yx, qx, Z[k].x);
+        Z[k].x = fma(yy, qy, Z[k].x);
+        Z[k].y = fma(yx, qy, Z[k].y);
+        Z[k].y = fma(-yy, qx, Z[k].y);
       }
     }
   }
@@ -320,36 +323,66 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
   for (int k = 0; k < KT; ++k) data += (double)(Fre[k] * Z[k].x) + (double)(Fim[k] * Z[k].y);
 
   // --- model-norm term: basis contraction (loop over basis rows) ----------
+  // Each iteration prefetches the next row's coefficients (uniform -> SGPRs)
+  // and the next cos/sin(n incl) before the FMAs on the current ones.
   const RIFT_CONST R* Cc = Tab<R>::C(P);
   R acc[3 * KT];
 #pragma unroll
   for (int c = 0; c < 3 * KT; ++c) acc[c] = 0;
   {
-    // q = 0: cos(n incl)
+    // q = 0: rows n = 0..NI, basis cos(n incl)
+    R cur[3 * KT];
+#pragma unroll
+    for (int c = 0; c < 3 * KT; ++c) cur[c] = Cc[c];
+    R tcur = trig[0];
 #pragma unroll 1
     for (int n = 0; n <= NI; ++n) {
-      const R beta = trig[n * ts];
-      const RIFT_CONST R* cr = Cc + n * 3 * KT;
+      const int nn = (n < NI) ? n + 1 : n;
+      R nxt[3 * KT];
 #pragma unroll
-      for (int c = 0; c < 3 * KT; ++c) acc[c] += cr[c] * beta;
+      for (int c = 0; c < 3 * KT; ++c) nxt[c] = Cc[nn * 3 * KT + c];
+      const R tnxt = trig[nn * ts];
+#pragma unroll
+      for (int c = 0; c < 3 * KT; ++c) acc[c] = fma(cur[c], tcur, acc[c]);
+#pragma unroll
+      for (int c = 0; c < 3 * KT; ++c) cur[c] = nxt[c];
+      tcur = tnxt;
     }
+  }
+  {
+    // q >= 1: pairs of rows (T_n cos(q phi), T_n sin(q phi)); even q pairs
+    // with cos(n incl) for n = 0..NI, odd q with sin(n incl) for n = 1..NI
+    const int B = CL::B;
     int b = NI + 1;
     C2<R> eq;
     eq.x = cf;
     eq.y = sf;
+    R cur[6 * KT];
+#pragma unroll
+    for (int c = 0; c < 6 * KT; ++c) cur[c] = Cc[b * 3 * KT + c];
 #pragma unroll 1
     for (int q = 1; q <= NI; ++q) {
-      // even q pairs with cos(n incl) (n = 0..NI), odd q with sin(n incl) (n = 1..NI)
       const int odd = q & 1;
-      const int n0 = odd;
       const int base = odd ? (NI + 1) : 0;
+      R tcur = trig[(base + odd) * ts];
 #pragma unroll 1
-      for (int n = n0; n <= NI; ++n, b += 2) {
-        const R t = trig[(base + n) * ts];
-        const R b1 = t * eq.x, b2 = t * eq.y;
-        const RIFT_CONST R* cr = Cc + b * 3 * KT;
+      for (int n = odd; n <= NI; ++n, b += 2) {
+        // next pair of rows (the last iteration re-reads its own rows)
+        const int bn = (b + 2 < B) ? b + 2 : b;
+        R nxt[6 * KT];
 #pragma unroll
-        for (int c = 0; c < 3 * KT; ++c) acc[c] += cr[c] * b1 + cr[3 * KT + c] * b2;
+        for (int c = 0; c < 6 * KT; ++c) nxt[c] = Cc[bn * 3 * KT + c];
+        const int tn = (n < NI) ? base + n + 1 : base + n;
+        const R tnxt = trig[tn * ts];
+        const R b1 = tcur * eq.x, b2 = tcur * eq.y;
+#pragma unroll
+        for (int c = 0; c < 3 * KT; ++c) {
+          acc[c] = fma(cur[c], b1, acc[c]);
+          acc[c] = fma(cur[3 * KT + c], b2, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 6 * KT; ++c) cur[c] = nxt[c];
+        tcur = tnxt;
       }
       const R ex_ = eq.x * cf - eq.y * sf, ey_ = eq.x * sf + eq.y * cf;
       eq.x = ex_;
