@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace rift {
 
 constexpr int KMAX = 8;    // detectors
@@ -36,7 +38,7 @@ constexpr int LMAXC = 8;   // largest l
 constexpr int QPAD = 4;    // zero rows on each side of every Q series
 
 template <class R>
-struct C2 {
+struct alignas(2 * sizeof(R)) C2 {
   R x, y;
 };
 
@@ -139,6 +141,23 @@ __device__ __forceinline__ const RIFT_CONST T* opaque(const RIFT_CONST T* p) {
   asm volatile("" : "+s"(v));
   return (const RIFT_CONST T*)v;
 }
+// Empty register use: the value must be computed before this point.
+template <class R>
+__device__ __forceinline__ void pin(R& v) {
+  asm volatile("" : "+v"(v));
+}
+// Empty scalar use: the (uniform) value must be in SGPRs at this point.
+template <class R>
+__device__ __forceinline__ void pin_s(R v) {
+  asm volatile("" ::"s"(v));
+}
+// Pin a (uniform) global pointer to SGPRs, so that per-lane accesses at a
+// 32-bit offset from it use the scalar-base addressing form.
+__device__ __forceinline__ const RIFT_GLOBAL char* uniform_ptr(const RIFT_GLOBAL char* p) {
+  uint64_t v = (uint64_t)p;
+  asm volatile("" : "+s"(v));
+  return (const RIFT_GLOBAL char*)v;
+}
 template <class R>
 __device__ __forceinline__ C2<R> ldq(const RIFT_GLOBAL R* q, int64_t idx) {
   C2<R> v;
@@ -163,6 +182,245 @@ struct Tab<float> {
   static __device__ __forceinline__ float y(PDesc P, int i, int n) { return P->ycoef32[i][n]; }
   static __device__ __forceinline__ float d(PDesc P, int k, int a) { return P->dten32[k][a]; }
 };
+
+// Row b of the harmonic basis of class L (the order of the coefficient
+// table): kind 0 = cos(n incl); 1, 2 = cos(n incl) {cos, sin}(q phi) for even
+// q >= 2; 3, 4 = sin(n incl) {cos, sin}(q phi) for odd q.  Packed as
+// kind | n << 4 | q << 12.
+template <int L>
+__host__ __device__ constexpr int basis_row(int b) {
+  constexpr int NI = 2 * L;
+  int bb = b;
+  for (int q = 0; q <= NI; ++q) {
+    if (q == 0) {
+      if (bb <= NI) return 0 | (bb << 4);
+      bb -= NI + 1;
+    } else if ((q & 1) == 0) {
+      if (bb < 2 * (NI + 1)) return (1 + (bb & 1)) | ((bb >> 1) << 4) | (q << 12);
+      bb -= 2 * (NI + 1);
+    } else {
+      if (bb < 2 * NI) return (3 + (bb & 1)) | ((1 + (bb >> 1)) << 4) | (q << 12);
+      bb -= 2 * NI;
+    }
+  }
+  return -1;
+}
+
+// Model-norm contraction acc[c] = sum_b C[b][c] beta_b(incl, phi), fully
+// unrolled over the B x 3 KT coefficients (classes L <= 4): every index is a
+// template constant, so the tables below stay in registers.  The uniform
+// coefficients stream through SGPRs in chunks of 128 bytes, each chunk
+// prefetched while the previous one is used.  Scalar loads complete out of
+// order, so the wait for a chunk (pin_s) comes before the next chunk is
+// issued (a wait never covers the prefetch), and the accumulators are pinned
+// after each chunk's FMAs so that those FMAs stay ahead of the next wait.
+template <class R, int KT, int L>
+struct Contract {
+  static constexpr int NI = 2 * L;
+  static constexpr int W = 3 * KT;
+  static constexpr int NC = Cls<L>::B * W;
+  static constexpr int CH = 128 / (int)sizeof(R);
+  static constexpr int NCH = (NC + CH - 1) / CH;
+  struct Tabs {
+    R ct[NI + 1], st[NI + 1];  // cos(n incl), sin(n incl)
+    R ex[NI + 1], ey[NI + 1];  // e^{i q phi}
+  };
+
+  template <int J>
+  static __device__ __forceinline__ void coef(R c, R* acc, const Tabs& T) {
+    if constexpr (J < NC) {
+      constexpr int rb = basis_row<L>(J / W);
+      constexpr int kind = rb & 15, n = (rb >> 4) & 255, q = rb >> 12;
+      R beta;
+      if constexpr (kind == 0) beta = T.ct[n];
+      else if constexpr (kind == 1) beta = T.ct[n] * T.ex[q];
+      else if constexpr (kind == 2) beta = T.ct[n] * T.ey[q];
+      else if constexpr (kind == 3) beta = T.st[n] * T.ex[q];
+      else beta = T.st[n] * T.ey[q];
+      acc[J % W] = fma(c, beta, acc[J % W]);
+    }
+  }
+  template <int C, int... I>
+  static __device__ __forceinline__ void fm(const R (&buf)[CH], R* acc, const Tabs& T,
+                                            std::integer_sequence<int, I...>) {
+    (coef<C * CH + I>(buf[I], acc, T), ...);
+  }
+  template <int C>
+  static __device__ __forceinline__ void ld(R (&buf)[CH], const RIFT_CONST R* Cc) {
+    const RIFT_CONST R* p = opaque(Cc) + C * CH;
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (C * CH + i < NC) buf[i] = p[i];
+  }
+  template <int C>
+  static __device__ __forceinline__ void wait(const R (&buf)[CH]) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (C * CH + i < NC) pin_s(buf[i]);
+  }
+  template <int C>
+  static __device__ __forceinline__ void step(const RIFT_CONST R* Cc, R (&cur)[CH], R (&nxt)[CH],
+                                              R* acc, const Tabs& T) {
+    if constexpr (C < NCH) {
+      wait<C>(cur);
+      if constexpr (C + 1 < NCH) ld<C + 1>(nxt, Cc);
+      fm<C>(cur, acc, T, std::make_integer_sequence<int, CH>{});
+#pragma unroll
+      for (int c = 0; c < W; ++c) pin(acc[c]);
+      step<C + 1>(Cc, nxt, cur, acc, T);
+    }
+  }
+  static __device__ __forceinline__ void run(PDesc P, R ci, R si, R cf, R sf, R* acc) {
+    Tabs T;
+    T.ct[0] = 1;
+    T.st[0] = 0;
+    T.ct[1] = ci;
+    T.st[1] = si;
+#pragma unroll
+    for (int n = 2; n <= NI; ++n) {
+      T.ct[n] = 2 * ci * T.ct[n - 1] - T.ct[n - 2];
+      T.st[n] = 2 * ci * T.st[n - 1] - T.st[n - 2];
+    }
+    T.ex[0] = 1;
+    T.ey[0] = 0;
+    T.ex[1] = cf;
+    T.ey[1] = sf;
+#pragma unroll
+    for (int q = 2; q <= NI; ++q) {
+      T.ex[q] = T.ex[q - 1] * cf - T.ey[q - 1] * sf;
+      T.ey[q] = T.ex[q - 1] * sf + T.ey[q - 1] * cf;
+    }
+    const RIFT_CONST R* Cc = Tab<R>::C(P);
+    R bA[CH], bB[CH];
+    ld<0>(bA, Cc);
+    step<0>(Cc, bA, bB, acc, T);
+  }
+};
+
+// Data term of detectors K0 .. K0+G-1 (G <= 3):
+//   sum_k Re[conj(F_k) sum_i conj(Y_i) Qhat_{k,i}]
+//   = sum_k Fre_k Re(Z_k) + Fim_k Im(Z_k),  Z_k = sum_i conj(Y_i) Qhat_{k,i},
+// with Y_i = d_i(incl) e^{i m_i phi} (modes sorted by m, so the phase walks
+// upward from e^{i m_min phi}) and Qhat the four-point Lagrange read at
+// fraction sfr_k of the cell that starts at byte offset boff_k.
+// The taps of mode i+1 (all G detectors) are in flight while mode i is
+// combined, so a sample waits about one memory round trip per mode.  Series
+// (k, i) starts at a uniform address; a lane's four taps are contiguous at a
+// 32-bit offset from it.
+template <class R, int NY, int K0, int G>
+__device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb, uint64_t sstride,
+                                             int M, const uint32_t* boff, const R* sfr,
+                                             const R* Fre, const R* Fim, const R* cn, const R* sn,
+                                             R cf, R sf) {
+  typedef R R2 __attribute__((ext_vector_type(2)));
+  R w[G][4];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const R s = sfr[K0 + g];
+    w[g][0] = -s * (s - 1) * (s - 2) * (R)(1.0 / 6.0);
+    w[g][1] = (s + 1) * (s - 1) * (s - 2) * (R)0.5;
+    w[g][2] = -(s + 1) * s * (s - 2) * (R)0.5;
+    w[g][3] = (s + 1) * s * (s - 1) * (R)(1.0 / 6.0);
+  }
+  C2<R> Z[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) Z[g].x = Z[g].y = 0;
+  C2<R> ph;
+  ph.x = 1;
+  ph.y = 0;
+  const int mmin = P->m_min;
+  for (int t = 0; t < -mmin; ++t) {
+    const R a = ph.x * cf + ph.y * sf, bb = ph.y * cf - ph.x * sf;
+    ph.x = a;
+    ph.y = bb;
+  }
+  int mc = mmin < 0 ? mmin : 0;
+  // issue the 4 G tap loads of mode i into buf
+  auto load = [&](C2<R>(&buf)[G][4], int i) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const RIFT_GLOBAL char* ser =
+          uniform_ptr(Qb + (uint64_t)((K0 + g) * M + i) * sstride) + boff[K0 + g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const R2 v = *(const RIFT_GLOBAL R2*)(ser + j * sizeof(R2));
+        buf[g][j].x = v.x;
+        buf[g][j].y = v.y;
+      }
+    }
+  };
+  // combine mode i (taps in buf) into Z
+  auto step = [&](const C2<R>(&buf)[G][4], int i) {
+    const int mi = P->m[i];
+    while (mc < mi) {
+      const R a = ph.x * cf - ph.y * sf, bb = ph.y * cf + ph.x * sf;
+      ph.x = a;
+      ph.y = bb;
+      ++mc;
+    }
+    R d = 0;
+    if (P->odd[i]) {
+#pragma unroll
+      for (int n = 1; n < NY; ++n) d += Tab<R>::y(P, i, n) * sn[n];
+    } else {
+#pragma unroll
+      for (int n = 0; n < NY; ++n) d += Tab<R>::y(P, i, n) * cn[n];
+    }
+    const R yx = d * ph.x, yy = d * ph.y;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const R qx = w[g][0] * buf[g][0].x + w[g][1] * buf[g][1].x + w[g][2] * buf[g][2].x +
+                   w[g][3] * buf[g][3].x;
+      const R qy = w[g][0] * buf[g][0].y + w[g][1] * buf[g][1].y + w[g][2] * buf[g][2].y +
+                   w[g][3] * buf[g][3].y;
+      // separate FMA chains (a + (b + c) would cost mul + fma + add)
+      Z[g].x = fma(yx, qx, Z[g].x);
+      Z[g].x = fma(yy, qy, Z[g].x);
+      Z[g].y = fma(yx, qy, Z[g].y);
+      Z[g].y = fma(-yy, qx, Z[g].y);
+    }
+    // the accumulators are final for this mode here: keeps the FMAs of this
+    // step ahead of the next load batch (instead of sinking them past it,
+    // which would keep both tap buffers and the new batch live)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      pin(Z[g].x);
+      pin(Z[g].y);
+    }
+  };
+  // Two tap buffers in turn, so that no register copy waits on a load.  Every
+  // load issued is consumed before the group ends (no loads left in flight
+  // into the next group or sample), and the loop body has the same loads on
+  // every path.  The scheduling barriers keep each load batch in its place.
+  C2<R> ta[G][4], tb[G][4];
+  load(ta, 0);
+  int i = 0;
+#pragma unroll 1
+  for (; i + 2 < M; i += 2) {
+    load(tb, i + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(ta, i);
+    __builtin_amdgcn_sched_barrier(0);
+    load(ta, i + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    step(tb, i + 1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // one or two modes left; ta holds mode i
+  if (i + 1 < M) {
+    load(tb, i + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(ta, i);
+    step(tb, i + 1);
+  } else {
+    step(ta, i);
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    acc += (double)(Fre[K0 + g] * Z[g].x) + (double)(Fim[K0 + g] * Z[g].y);
+  return acc;
+}
 
 // Result of one sample evaluation.
 struct Eval {
@@ -219,8 +477,10 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
         cn[n] = c;
         sn[n] = s;
       }
-      trig[n * ts] = c;
-      trig[(NI + 1 + n) * ts] = s;
+      if constexpr (L > 4) {  // the runtime contraction loop reads these
+        trig[n * ts] = c;
+        trig[(NI + 1 + n) * ts] = s;
+      }
       if (n > 0) {
         const R c2 = 2 * ci * c1 - c0, s2 = 2 * ci * s1 - s0;
         c0 = c1;
@@ -235,8 +495,8 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
 
   // --- antenna factors and stencils per detector --------------------------
   R Fre[KT], Fim[KT];
-  R w[KT][4];
-  int soff[KT];  // first padded row of the 4-row stencil
+  R sfr[KT];        // fractional position inside the stencil cell
+  uint32_t boff[KT];  // byte offset of the first stencil row in its series
   bool bad = false;
   const int ntp = n_t + 2 * QPAD;
 #pragma unroll
@@ -261,132 +521,90 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
     int j0 = (int)jf - 1;  // stencil rows j0 .. j0+3
     // wholly outside the stored window: read four zero pad rows
     j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
-    soff[k] = j0 + QPAD;
-    w[k][0] = -s * (s - 1) * (s - 2) * (R)(1.0 / 6.0);
-    w[k][1] = (s + 1) * (s - 1) * (s - 2) * (R)0.5;
-    w[k][2] = -(s + 1) * s * (s - 2) * (R)0.5;
-    w[k][3] = (s + 1) * s * (s - 1) * (R)(1.0 / 6.0);
+    boff[k] = (uint32_t)(j0 + QPAD) * (uint32_t)sizeof(C2<R>);
+    sfr[k] = s;
   }
 
-  // --- data term: loop over modes; Y_i = d_i(incl) e^{i m_i phi} ----------
-  // modes are sorted by m, so the phase walks upward from e^{i m_min phi}
-  const RIFT_GLOBAL R* Qt = Tab<R>::Q(P);
-  C2<R> Z[KT];
-#pragma unroll
-  for (int k = 0; k < KT; ++k) Z[k].x = Z[k].y = 0;
-  {
-    C2<R> ph;
-    ph.x = 1;
-    ph.y = 0;
-    const int mmin = P->m_min;
-    for (int t = 0; t < -mmin; ++t) {
-      const R a = ph.x * cf + ph.y * sf, bb = ph.y * cf - ph.x * sf;
-      ph.x = a;
-      ph.y = bb;
-    }
-    int mc = mmin < 0 ? mmin : 0;
-    for (int i = 0; i < M; ++i) {
-      const int mi = P->m[i];
-      while (mc < mi) {
-        const R a = ph.x * cf - ph.y * sf, bb = ph.y * cf + ph.x * sf;
-        ph.x = a;
-        ph.y = bb;
-        ++mc;
-      }
-      R d = 0;
-      if (P->odd[i]) {
-#pragma unroll
-        for (int n = 1; n < NY; ++n) d += Tab<R>::y(P, i, n) * sn[n];
-      } else {
-#pragma unroll
-        for (int n = 0; n < NY; ++n) d += Tab<R>::y(P, i, n) * cn[n];
-      }
-      const R yx = d * ph.x, yy = d * ph.y;
-#pragma unroll
-      for (int k = 0; k < KT; ++k) {
-        // series (k, i) starts at a uniform address; the lane's 4 taps are contiguous
-        const RIFT_GLOBAL R* ser = Qt + (int64_t)(k * M + i) * ntp * 2;
-        const C2<R> q0 = ldq(ser, soff[k]), q1 = ldq(ser, soff[k] + 1);
-        const C2<R> q2 = ldq(ser, soff[k] + 2), q3 = ldq(ser, soff[k] + 3);
-        const R qx = w[k][0] * q0.x + w[k][1] * q1.x + w[k][2] * q2.x + w[k][3] * q3.x;
-        const R qy = w[k][0] * q0.y + w[k][1] * q1.y + w[k][2] * q2.y + w[k][3] * q3.y;
-        // separate FMA chains (a + (b + c) would cost mul + fma + add)
-        Z[k].x = fma(yx, qx, Z[k].x);
-        Z[k].x = fma(yy, qy, Z[k].x);
-        Z[k].y = fma(yx, qy, Z[k].y);
-        Z[k].y = fma(-yy, qx, Z[k].y);
-      }
-    }
-  }
-  double data = 0.0;
-#pragma unroll
-  for (int k = 0; k < KT; ++k) data += (double)(Fre[k] * Z[k].x) + (double)(Fim[k] * Z[k].y);
+  // --- data term, in groups of at most three detectors -------------------
+  const RIFT_GLOBAL char* Qb = (const RIFT_GLOBAL char*)Tab<R>::Q(P);
+  const uint64_t sstride = (uint64_t)ntp * sizeof(C2<R>);
+  double data = data_group<R, NY, 0, (KT < 3 ? KT : 3)>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn,
+                                                         sn, cf, sf);
+  if constexpr (KT > 3)
+    data += data_group<R, NY, 3, (KT - 3 < 3 ? KT - 3 : 3)>(P, Qb, sstride, M, boff, sfr, Fre, Fim,
+                                                            cn, sn, cf, sf);
+  if constexpr (KT > 6)
+    data += data_group<R, NY, 6, KT - 6>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn, sn, cf, sf);
 
-  // --- model-norm term: basis contraction (loop over basis rows) ----------
-  // Each iteration prefetches the next row's coefficients (uniform -> SGPRs)
-  // and the next cos/sin(n incl) before the FMAs on the current ones.
-  const RIFT_CONST R* Cc = Tab<R>::C(P);
+  // --- model-norm term: basis contraction ----------------------------------
   R acc[3 * KT];
 #pragma unroll
   for (int c = 0; c < 3 * KT; ++c) acc[c] = 0;
-  {
-    // q = 0: rows n = 0..NI, basis cos(n incl)
-    R cur[3 * KT];
+  if constexpr (L <= 4) {
+    Contract<R, KT, L>::run(P, ci, si, cf, sf, acc);
+  } else {
+    // runtime loop over basis rows (reads cos/sin(n incl) from this lane's
+    // column of the block-shared scratch array)
+    const RIFT_CONST R* Cc = Tab<R>::C(P);
+    {
+      // q = 0: rows n = 0..NI, basis cos(n incl)
+      R cur[3 * KT];
 #pragma unroll
-    for (int c = 0; c < 3 * KT; ++c) cur[c] = Cc[c];
-    R tcur = trig[0];
+      for (int c = 0; c < 3 * KT; ++c) cur[c] = Cc[c];
+      R tcur = trig[0];
 #pragma unroll 1
-    for (int n = 0; n <= NI; ++n) {
-      const int nn = (n < NI) ? n + 1 : n;
-      R nxt[3 * KT];
+      for (int n = 0; n <= NI; ++n) {
+        const int nn = (n < NI) ? n + 1 : n;
+        R nxt[3 * KT];
 #pragma unroll
-      for (int c = 0; c < 3 * KT; ++c) nxt[c] = Cc[nn * 3 * KT + c];
-      const R tnxt = trig[nn * ts];
+        for (int c = 0; c < 3 * KT; ++c) nxt[c] = Cc[nn * 3 * KT + c];
+        const R tnxt = trig[nn * ts];
 #pragma unroll
-      for (int c = 0; c < 3 * KT; ++c) acc[c] = fma(cur[c], tcur, acc[c]);
+        for (int c = 0; c < 3 * KT; ++c) acc[c] = fma(cur[c], tcur, acc[c]);
 #pragma unroll
-      for (int c = 0; c < 3 * KT; ++c) cur[c] = nxt[c];
-      tcur = tnxt;
-    }
-  }
-  {
-    // q >= 1: pairs of rows (T_n cos(q phi), T_n sin(q phi)); even q pairs
-    // with cos(n incl) for n = 0..NI, odd q with sin(n incl) for n = 1..NI
-    const int B = CL::B;
-    int b = NI + 1;
-    C2<R> eq;
-    eq.x = cf;
-    eq.y = sf;
-    R cur[6 * KT];
-#pragma unroll
-    for (int c = 0; c < 6 * KT; ++c) cur[c] = Cc[b * 3 * KT + c];
-#pragma unroll 1
-    for (int q = 1; q <= NI; ++q) {
-      const int odd = q & 1;
-      const int base = odd ? (NI + 1) : 0;
-      R tcur = trig[(base + odd) * ts];
-#pragma unroll 1
-      for (int n = odd; n <= NI; ++n, b += 2) {
-        // next pair of rows (the last iteration re-reads its own rows)
-        const int bn = (b + 2 < B) ? b + 2 : b;
-        R nxt[6 * KT];
-#pragma unroll
-        for (int c = 0; c < 6 * KT; ++c) nxt[c] = Cc[bn * 3 * KT + c];
-        const int tn = (n < NI) ? base + n + 1 : base + n;
-        const R tnxt = trig[tn * ts];
-        const R b1 = tcur * eq.x, b2 = tcur * eq.y;
-#pragma unroll
-        for (int c = 0; c < 3 * KT; ++c) {
-          acc[c] = fma(cur[c], b1, acc[c]);
-          acc[c] = fma(cur[3 * KT + c], b2, acc[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < 6 * KT; ++c) cur[c] = nxt[c];
+        for (int c = 0; c < 3 * KT; ++c) cur[c] = nxt[c];
         tcur = tnxt;
       }
-      const R ex_ = eq.x * cf - eq.y * sf, ey_ = eq.x * sf + eq.y * cf;
-      eq.x = ex_;
-      eq.y = ey_;
+    }
+    {
+      // q >= 1: pairs of rows (T_n cos(q phi), T_n sin(q phi)); even q pairs
+      // with cos(n incl) for n = 0..NI, odd q with sin(n incl) for n = 1..NI
+      const int B = CL::B;
+      int b = NI + 1;
+      C2<R> eq;
+      eq.x = cf;
+      eq.y = sf;
+      R cur[6 * KT];
+#pragma unroll
+      for (int c = 0; c < 6 * KT; ++c) cur[c] = Cc[b * 3 * KT + c];
+#pragma unroll 1
+      for (int q = 1; q <= NI; ++q) {
+        const int odd = q & 1;
+        const int base = odd ? (NI + 1) : 0;
+        R tcur = trig[(base + odd) * ts];
+#pragma unroll 1
+        for (int n = odd; n <= NI; ++n, b += 2) {
+          // next pair of rows (the last iteration re-reads its own rows)
+          const int bn = (b + 2 < B) ? b + 2 : b;
+          R nxt[6 * KT];
+#pragma unroll
+          for (int c = 0; c < 6 * KT; ++c) nxt[c] = Cc[bn * 3 * KT + c];
+          const int tn = (n < NI) ? base + n + 1 : base + n;
+          const R tnxt = trig[tn * ts];
+          const R b1 = tcur * eq.x, b2 = tcur * eq.y;
+#pragma unroll
+          for (int c = 0; c < 3 * KT; ++c) {
+            acc[c] = fma(cur[c], b1, acc[c]);
+            acc[c] = fma(cur[3 * KT + c], b2, acc[c]);
+          }
+#pragma unroll
+          for (int c = 0; c < 6 * KT; ++c) cur[c] = nxt[c];
+          tcur = tnxt;
+        }
+        const R ex_ = eq.x * cf - eq.y * sf, ey_ = eq.x * sf + eq.y * cf;
+        eq.x = ex_;
+        eq.y = ey_;
+      }
     }
   }
   double quad = 0.0;
