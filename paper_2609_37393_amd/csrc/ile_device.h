@@ -67,11 +67,19 @@ struct PointDesc {
   // mixed path: |lnL_FP32 - lnL_FP64| <= x bnd_d + x^2 sum_k (|F_k|^2 + 1e-6) bnd_q[k]
   double bnd_d;
   double bnd_q[KMAX];
-  // arrival-time binning (sorted evaluation): first bin_dims detectors,
-  // bin_bits bits per detector, buckets bin_base .. bin_base + 2^(dims bits)
+  // arrival-time binning (sorted evaluation): a Morton key of bin_bits
+  // bits per detector over the first bin_dims detectors; its top bin_cb
+  // bits are the coarse bucket.  The point's sort tiles are bin_st0 ..
+  // bin_st0 + bin_nst - 1; its [coarse bucket][sort tile] count matrix
+  // starts at bin_mbase; its coarse buckets are bin_cbase .. in the global
+  // numbering of the local-sort launch.
   int32_t bin_dims;
   int32_t bin_bits;
-  int64_t bin_base;
+  int32_t bin_cb;
+  int32_t bin_nst;
+  int32_t bin_st0;
+  int32_t bin_cbase;
+  int64_t bin_mbase;
   // Q series of each (detector, mode), time-contiguous with QPAD zero rows at
   // both ends: [KT][M][n_t + 2 QPAD] complex.  A stencil starting at row
   // j-1 in [-QPAD, n_t] reads padded rows j-1+QPAD .. j+2+QPAD.

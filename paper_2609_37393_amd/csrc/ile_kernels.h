@@ -26,11 +26,12 @@ struct TileArgs {
   float* bnd;           // [N] (pass32)
   double* part;         // [n_tiles][2]: (max, sum) (lse64)
   double* tmax;         // [n_tiles]: max(lnL + lnw - bound) (pass32)
-  // sorted mode: samples read from theta_aos[pos][8] (ra, dec, psi, incl,
-  // phiref, tref, dist, -) and results written to index perm[pos]; the
-  // reductions then run in input order in a separate pass
+  // sorted mode: samples read from the records theta_aos[pos][8] (ra, dec,
+  // psi, incl, phiref, tref, dist, int64 bits whose upper 48 hold the sample
+  // index) and results
+  // written to that sample index; the reductions then run in input order in
+  // a separate pass
   const double* theta_aos;
-  const int32_t* perm;
 };
 
 // One tile: every sample's lnL (and bound), then a block reduction.
@@ -48,13 +49,12 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
   const int64_t N = a.N;
   if (a.theta_aos) {
     const RIFT_GLOBAL double* aos = as_global(a.theta_aos);
-    const RIFT_GLOBAL int32_t* perm = as_global(a.perm);
     for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
       const int64_t pos = t.s + o;
       const RIFT_GLOBAL double* th = aos + 8 * pos;
       const Eval e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, th[0], th[1],
                                                                 th[2], th[3], th[4], th[5], th[6]);
-      const int64_t i = perm[pos];
+      const int64_t i = (int64_t)__double_as_longlong(th[7]) >> 16;
       lnL[i] = e.lnL;
       if (MODE == MODE_PASS32) as_global_w(a.bnd)[i] = e.bound;
     }

@@ -309,120 +309,11 @@ __global__ void k_merge(const PointDesc* __restrict__ descs, const int32_t* __re
   }
 }
 
-// ---------------------------------------------------------------------------
-// Arrival-time binning: samples are counting-sorted by a Morton key of their
-// stencil rows at (up to) three detectors, so that the 64 lanes of a
-// wavefront read nearby rows of every Q series.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long ord_enc(double x) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double ord_dec(unsigned long long e) {
-  const unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
-  return __longlong_as_double((long long)b);
-}
-
-__global__ void k_fill_u64(unsigned long long* __restrict__ p, int n, unsigned long long v0,
-                           unsigned long long v1) {
-  // even slots v0 (running min), odd slots v1 (running max)
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = (i & 1) ? v1 : v0;
-}
-
-// Stencil row coordinate u_k = (t_k - t0)/dt of the first bin_dims detectors,
-// stored per sample, and its range per (point, detector).
-__global__ void k_bin_range(const PointDesc* __restrict__ descs, const Tile* __restrict__ tiles,
-                            const double* __restrict__ theta, int64_t N, float* __restrict__ ucoord,
-                            unsigned long long* __restrict__ range) {
-  const Tile t = tiles[blockIdx.x];
-  const PointDesc* P = descs + t.p;
-  const int D = P->bin_dims;
-  double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
-  double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
-  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
-    const int64_t i = t.s + o;
-    double sg, cg, sd, cd;
-    sincos(P->gmst - theta[i], &sg, &cg);
-    sincos(theta[N + i], &sd, &cd);
-    const double N0 = cd * cg, N1 = -cd * sg, N2 = sd;
-    for (int k = 0; k < D; ++k) {
-      const double tk = theta[5 * N + i] - (P->rpos[k][0] * N0 + P->rpos[k][1] * N1 + P->rpos[k][2] * N2);
-      const double u = (tk - P->t0) * P->inv_dt;
-      ucoord[3 * i + k] = (float)u;
-      if (u == u && fabs(u) < 1e9) {
-        lo[k] = fmin(lo[k], u);
-        hi[k] = fmax(hi[k], u);
-      }
-    }
-  }
-  __shared__ double sh[2][3][8];
-  for (int k = 0; k < 3; ++k) {
-    double a = lo[k], b = hi[k];
-    for (int off = 32; off >= 1; off >>= 1) {
-      a = fmin(a, __shfl_xor(a, off));
-      b = fmax(b, __shfl_xor(b, off));
-    }
-    if ((threadIdx.x & 63) == 0) {
-      sh[0][k][threadIdx.x >> 6] = a;
-      sh[1][k][threadIdx.x >> 6] = b;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < (unsigned)D) {
-    const int k = threadIdx.x;
-    double a = sh[0][k][0], b = sh[1][k][0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-      a = fmin(a, sh[0][k][w]);
-      b = fmax(b, sh[1][k][w]);
-    }
-    if (a <= b) {
-      atomicMin(range + 6 * t.p + 2 * k, ord_enc(a));
-      atomicMax(range + 6 * t.p + 2 * k + 1, ord_enc(b));
-    }
-  }
-}
-
-
-// Bucket of every sample (Morton order of its cells) and the histogram.
-__global__ void k_bin_keys(const PointDesc* __restrict__ descs, const Tile* __restrict__ tiles,
-                           const float* __restrict__ ucoord, const unsigned long long* __restrict__ range,
-                           int32_t* __restrict__ bucket, int32_t* __restrict__ hist) {
-  const Tile t = tiles[blockIdx.x];
-  const PointDesc* P = descs + t.p;
-  const int D = P->bin_dims, bits = P->bin_bits;
-  const int ncell = 1 << bits;
-  float lo[3], inv[3];
-  for (int k = 0; k < 3; ++k) {
-    lo[k] = 0.0f;
-    inv[k] = 0.0f;
-    if (k < D) {
-      const double a = ord_dec(range[6 * t.p + 2 * k]), b = ord_dec(range[6 * t.p + 2 * k + 1]);
-      if (a <= b) {
-        lo[k] = (float)a;
-        inv[k] = (float)(ncell / (b - a + 1e-3));
-      }
-    }
-  }
-  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
-    const int64_t i = t.s + o;
-    uint32_t key = 0;
-    for (int k = 0; k < D; ++k) {
-      const float f = (ucoord[3 * i + k] - lo[k]) * inv[k];
-      const int c = (f >= 0.0f) ? (f < (float)(ncell - 1) ? (int)f : ncell - 1) : 0;  // NaN -> 0
-      // Morton interleave with stride D: key < 2^(D bits)
-      for (int b = 0; b < bits; ++b) key |= (((uint32_t)c >> b) & 1u) << (D * b + k);
-    }
-    const int32_t bkt = (int32_t)(P->bin_base + key);
-    bucket[i] = bkt;
-    atomicAdd(hist + bkt, 1);
-  }
-}
-
 // Exclusive scan of n int32 (three kernels): block sums, scan of the sums,
 // per-block scan plus offset.  Each block covers SCAN_CHUNK elements.
 constexpr int SCAN_T = 256, SCAN_PER = 16, SCAN_CHUNK = SCAN_T * SCAN_PER;
 
+// sh: one slot per wavefront plus one (the total)
 __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* sh, int32_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int32_t x = v;
@@ -439,11 +330,11 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t* sh, int32
       sh[w] = acc;
       acc += t;
     }
-    sh[8] = acc;
+    sh[blockDim.x >> 6] = acc;
   }
   __syncthreads();
   const int32_t r = x - v + sh[wave];
-  *total = sh[8];
+  *total = sh[blockDim.x >> 6];
   __syncthreads();
   return r;
 }
@@ -473,8 +364,9 @@ __global__ void k_scan_top(int32_t* __restrict__ sums, int nb) {
   }
 }
 
-__global__ void k_scan_apply(const int32_t* __restrict__ a, int64_t n, const int32_t* __restrict__ sums,
-                             int32_t* __restrict__ out, int32_t* __restrict__ out2) {
+// (may run in place: out == a)
+__global__ void k_scan_apply(const int32_t* a, int64_t n, const int32_t* __restrict__ sums, int32_t* out,
+                             int32_t* __restrict__ out2) {
   __shared__ int32_t sh[9];
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
   int32_t loc[SCAN_PER];
@@ -488,25 +380,257 @@ __global__ void k_scan_apply(const int32_t* __restrict__ a, int64_t n, const int
   for (int j = 0; j < SCAN_PER; ++j) {
     if (base + j < n) {
       out[base + j] = e;
-      out2[base + j] = e;
+      if (out2) out2[base + j] = e;
     }
     e += loc[j];
   }
 }
 
-// Counting-sort scatter: every sample takes the next slot of its bucket.
-__global__ void k_bin_scatter(const Tile* __restrict__ tiles, const double* __restrict__ theta, int64_t N,
-                              const int32_t* __restrict__ bucket, int32_t* __restrict__ cursor,
-                              double* __restrict__ aos, int32_t* __restrict__ perm) {
-  const Tile t = tiles[blockIdx.x];
+// ---------------------------------------------------------------------------
+// Arrival-time binning: the samples of each point are sorted by a Morton key
+// of their stencil rows at (up to) three detectors, so that the 64 lanes of a
+// wavefront read nearby rows of every Q series.  The binned batch is a copy
+// of theta as 64-byte records (ra, dec, psi, incl, phiref, tref, dist, and
+// sample index << 16 in the last slot), which the evaluation kernel reads in
+// order.
+//
+// No device-scope atomics (they serialise across the XCDs) and no random
+// gathers (a scattered 8-byte read costs a whole cache line):
+//   k_bin_range   per sort tile: stencil coordinates (FP32; they only decide
+//                 the order) and their range;
+//   k_bin_hist    per sort tile: the point's range, the key of every sample,
+//                 and the tile's coarse-bucket histogram -> column of the
+//                 point's [coarse bucket][sort tile] count matrix;
+//   k_scan_*      exclusive scan of the count matrix (positions);
+//   k_bin_coarse  per sort tile: every record to the next slot of its coarse
+//                 bucket (LDS cursors; theta read in input order);
+//   k_bin_local   per coarse bucket: counting sort on the low key bits in LDS,
+//                 records moved to their final positions (inside the bucket).
+// The order inside a cell is not fixed; lnL values do not depend on it and
+// every reduction runs in input order.
+// ---------------------------------------------------------------------------
+constexpr int BIN_TILE = 4096;   // samples per sort tile
+constexpr int BIN_T = 1024;      // threads of the sort kernels
+constexpr int BIN_LOW_MAX = 10;  // low key bits sorted in LDS (<= 1024 bins)
+constexpr int BIN_CB_MAX = 10;   // coarse buckets per point <= 1024
+
+// Stencil row coordinate u_k = (t_k - t0)/dt of the first bin_dims detectors
+// per sample (FP32), and its range per sort tile.
+__global__ void __launch_bounds__(BIN_T) k_bin_range(const PointDesc* __restrict__ descs,
+                                                     const Tile* __restrict__ stiles,
+                                                     const double* __restrict__ theta, int64_t N,
+                                                     float* __restrict__ ucoord,
+                                                     float* __restrict__ rpart) {
+  const Tile t = stiles[blockIdx.x];
+  const PointDesc* P = descs + t.p;
+  const int D = P->bin_dims;
+  const float gmst = (float)P->gmst, t0 = (float)P->t0, idt = (float)P->inv_dt;
+  float rp[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int c = 0; c < 3; ++c) rp[k][c] = (k < D) ? (float)P->rpos[k][c] : 0.0f;
+  float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
   for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
     const int64_t i = t.s + o;
-    const int64_t slot = atomicAdd(cursor + bucket[i], 1);
-    double* dst = aos + 8 * slot;
+    float sg, cg, sd, cd;
+    __sincosf(gmst - (float)theta[i], &sg, &cg);
+    __sincosf((float)theta[N + i], &sd, &cd);
+    const float N0 = cd * cg, N1 = -cd * sg, N2 = sd;
+    const float tr = (float)theta[5 * N + i];
 #pragma unroll
-    for (int a = 0; a < 7; ++a) dst[a] = theta[a * N + i];
-    dst[7] = 0.0;
-    perm[slot] = (int32_t)i;
+    for (int k = 0; k < 3; ++k) {
+      if (k >= D) break;
+      const float tk = tr - (rp[k][0] * N0 + rp[k][1] * N1 + rp[k][2] * N2);
+      const float u = (tk - t0) * idt;
+      ucoord[3 * i + k] = u;
+      if (u == u && fabsf(u) < 1e9f) {
+        lo[k] = fminf(lo[k], u);
+        hi[k] = fmaxf(hi[k], u);
+      }
+    }
+  }
+  __shared__ float sh[2][3][BIN_T / 64];
+  for (int k = 0; k < 3; ++k) {
+    float a = lo[k], b = hi[k];
+    for (int off = 32; off >= 1; off >>= 1) {
+      a = fminf(a, __shfl_xor(a, off));
+      b = fmaxf(b, __shfl_xor(b, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      sh[0][k][threadIdx.x >> 6] = a;
+      sh[1][k][threadIdx.x >> 6] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    float a = sh[0][k][0], b = sh[1][k][0];
+    for (int w = 1; w < BIN_T / 64; ++w) {
+      a = fminf(a, sh[0][k][w]);
+      b = fmaxf(b, sh[1][k][w]);
+    }
+    rpart[6 * blockIdx.x + 2 * k] = a;
+    rpart[6 * blockIdx.x + 2 * k + 1] = b;
+  }
+}
+
+// Keys and the coarse histogram of every sort tile, written to column
+// (tile - bin_st0) of the point's [coarse bucket][sort tile] matrix.  Each
+// block first reduces the point's range from the tile partials (fixed order).
+__global__ void __launch_bounds__(BIN_T) k_bin_hist(const PointDesc* __restrict__ descs,
+                                                    const Tile* __restrict__ stiles,
+                                                    const float* __restrict__ ucoord,
+                                                    const float* __restrict__ rpart,
+                                                    uint16_t* __restrict__ key,
+                                                    int32_t* __restrict__ mat) {
+  __shared__ int32_t h[1 << BIN_CB_MAX];
+  __shared__ float rng[6][BIN_T / 64];
+  const Tile t = stiles[blockIdx.x];
+  const PointDesc* P = descs + t.p;
+  const int D = P->bin_dims, bits = P->bin_bits;
+  const int tb = D * bits, cb = P->bin_cb;
+  const int nc = 1 << cb;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) h[c] = 0;
+  {
+    const int t0 = P->bin_st0, nt = P->bin_nst;
+    for (int c = 0; c < 6; ++c) {
+      const bool mx = c & 1;
+      float v = mx ? -__builtin_inff() : __builtin_inff();
+      for (int j = threadIdx.x; j < nt; j += blockDim.x)
+        v = mx ? fmaxf(v, rpart[6 * (t0 + j) + c]) : fminf(v, rpart[6 * (t0 + j) + c]);
+      for (int off = 32; off >= 1; off >>= 1) {
+        const float o = __shfl_xor(v, off);
+        v = mx ? fmaxf(v, o) : fminf(v, o);
+      }
+      if ((threadIdx.x & 63) == 0) rng[c][threadIdx.x >> 6] = v;
+    }
+  }
+  __syncthreads();
+  float lo[3], scl[3];
+  const int ncell = 1 << bits;
+  for (int k = 0; k < 3; ++k) {
+    float a = rng[2 * k][0], b = rng[2 * k + 1][0];
+    for (int w = 1; w < BIN_T / 64; ++w) {
+      a = fminf(a, rng[2 * k][w]);
+      b = fmaxf(b, rng[2 * k + 1][w]);
+    }
+    lo[k] = (a <= b) ? a : 0.0f;
+    scl[k] = (a <= b) ? (float)ncell / (b - a + 1e-3f) : 0.0f;
+  }
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    uint32_t k = 0;
+    for (int d = 0; d < D; ++d) {
+      const float f = (ucoord[3 * i + d] - lo[d]) * scl[d];
+      const int c = (f >= 0.0f) ? (f < (float)(ncell - 1) ? (int)f : ncell - 1) : 0;  // NaN -> 0
+      // Morton interleave: detector d at bit positions d, d + D, d + 2D, ...
+      for (int bb = 0; bb < bits; ++bb) k |= (((uint32_t)c >> bb) & 1u) << (D * bb + d);
+    }
+    key[i] = (uint16_t)k;
+    atomicAdd(&h[k >> (tb - cb)], 1);
+  }
+  __syncthreads();
+  const int64_t col = blockIdx.x - P->bin_st0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) mat[P->bin_mbase + (int64_t)c * P->bin_nst + col] = h[c];
+}
+
+// Coarse scatter: every sample of a sort tile takes the next slot of its
+// coarse bucket in this tile's range (LDS cursors) and its record goes there,
+// with (sample index << 16 | low key bits) in the last slot.  Slots are global
+// sample positions (the scanned matrix starts each point at its first column).
+__global__ void __launch_bounds__(BIN_T) k_bin_coarse(const PointDesc* __restrict__ descs,
+                                                      const Tile* __restrict__ stiles,
+                                                      const uint16_t* __restrict__ key,
+                                                      const int32_t* __restrict__ mat,
+                                                      const double* __restrict__ theta, int64_t N,
+                                                      double* __restrict__ trec) {
+  __shared__ int32_t cur[1 << BIN_CB_MAX];
+  const Tile t = stiles[blockIdx.x];
+  const PointDesc* P = descs + t.p;
+  const int tb = P->bin_dims * P->bin_bits, cb = P->bin_cb;
+  const int nc = 1 << cb;
+  const int64_t col = blockIdx.x - P->bin_st0;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) cur[c] = mat[P->bin_mbase + (int64_t)c * P->bin_nst + col];
+  __syncthreads();
+  const uint32_t lowmask = (1u << (tb - cb)) - 1u;
+  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+    const int64_t i = t.s + o;
+    const uint32_t k = key[i];
+    const int64_t slot = atomicAdd(&cur[k >> (tb - cb)], 1);
+    const long long tag = ((long long)i << 16) | (long long)(k & lowmask);
+    double2* dst = reinterpret_cast<double2*>(trec + 8 * slot);
+    dst[0] = make_double2(theta[i], theta[N + i]);
+    dst[1] = make_double2(theta[2 * N + i], theta[3 * N + i]);
+    dst[2] = make_double2(theta[4 * N + i], theta[5 * N + i]);
+    dst[3] = make_double2(theta[6 * N + i], __longlong_as_double(tag));
+  }
+}
+
+// One block per coarse bucket: counting sort of its records on the low key
+// bits (LDS), in chunks of BIN_LCHUNK records, each record moving from its
+// coarse slot to its final position (both inside the bucket's range).
+constexpr int BIN_LT = 256;
+constexpr int BIN_LPER = 8;
+constexpr int BIN_LCHUNK = BIN_LT * BIN_LPER;
+__global__ void __launch_bounds__(BIN_LT) k_bin_local(const PointDesc* __restrict__ descs,
+                                                      const int32_t* __restrict__ cb_point,
+                                                      const int32_t* __restrict__ mat,
+                                                      const double* __restrict__ trec,
+                                                      double* __restrict__ aos) {
+  __shared__ int32_t h[1 << BIN_LOW_MAX];
+  __shared__ int32_t ws[BIN_LT / 64 + 1];
+  const int p = cb_point[blockIdx.x];
+  const PointDesc* P = descs + p;
+  const int c = blockIdx.x - P->bin_cbase;
+  const int nc = 1 << P->bin_cb;
+  const int nlow = 1 << (P->bin_dims * P->bin_bits - P->bin_cb);
+  const int64_t beg = mat[P->bin_mbase + (int64_t)c * P->bin_nst];
+  const int64_t end = (c + 1 < nc) ? (int64_t)mat[P->bin_mbase + (int64_t)(c + 1) * P->bin_nst] : P->s0 + P->n;
+  for (int64_t c0 = beg; c0 < end; c0 += BIN_LCHUNK) {
+    const int64_t c1 = (c0 + BIN_LCHUNK < end) ? c0 + BIN_LCHUNK : end;
+    for (int b = threadIdx.x; b < nlow; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    double2 rec[BIN_LPER][4];
+    uint32_t kk[BIN_LPER];
+#pragma unroll
+    for (int j = 0; j < BIN_LPER; ++j) {
+      const int64_t e = c0 + j * BIN_LT + threadIdx.x;
+      kk[j] = 0;
+      if (e < c1) {
+        const double2* src = reinterpret_cast<const double2*>(trec + 8 * e);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) rec[j][a] = src[a];
+        kk[j] = (uint32_t)(__double_as_longlong(rec[j][3].y) & 0xffff);
+        atomicAdd(&h[kk[j]], 1);
+      }
+    }
+    __syncthreads();
+    // exclusive scan of the nlow bins (each thread a contiguous run)
+    {
+      const int per = (nlow + BIN_LT - 1) / BIN_LT;
+      const int b0 = threadIdx.x * per;
+      int32_t run = 0;
+      for (int b = b0; b < b0 + per && b < nlow; ++b) run += h[b];
+      int32_t tot;
+      int32_t off = block_excl_scan(run, ws, &tot);
+      for (int b = b0; b < b0 + per && b < nlow; ++b) {
+        const int32_t v = h[b];
+        h[b] = off;
+        off += v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < BIN_LPER; ++j) {
+      const int64_t e = c0 + j * BIN_LT + threadIdx.x;
+      if (e < c1) {
+        const int64_t pos = c0 + atomicAdd(&h[kk[j]], 1);
+        double2* dst = reinterpret_cast<double2*>(aos + 8 * pos);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) dst[a] = rec[j][a];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -679,16 +803,22 @@ struct rift_ile_plan_s {
   float* d_bnd = nullptr;     // [N]
   double* d_L = nullptr;      // [N]
   int refine_blocks = 32;
-  // binning (sorted evaluation)
-  int64_t n_buckets = 0;
-  float* d_ucoord = nullptr;               // [N][3]
-  int32_t* d_bucket = nullptr;             // [N]
-  int32_t* d_hist = nullptr;               // [n_buckets]
-  int32_t* d_cursor = nullptr;             // [n_buckets]
-  int32_t* d_scan = nullptr;               // block sums
-  unsigned long long* d_range = nullptr;   // [n_points][3][2]
-  double* d_aos = nullptr;                 // [N][8]
-  int32_t* d_perm = nullptr;               // [N]
+  // binning (sorted evaluation), see k_bin_*
+  bool bin_ready = false;          // buffers below allocated (on first use of sort)
+  std::vector<Tile> h_stiles;
+  std::vector<int32_t> h_cbp;
+  int n_stiles = 0;
+  Tile* d_stiles = nullptr;        // sort tiles of BIN_TILE samples
+  int64_t n_mat = 0;               // [coarse bucket][sort tile] entries, all points
+  int n_cb = 0;                    // coarse buckets, all points
+  float* d_ucoord = nullptr;       // [N][3]
+  float* d_rpart = nullptr;        // [n_stiles][6]
+  uint16_t* d_key = nullptr;       // [N]
+  int32_t* d_mat = nullptr;        // [n_mat]
+  int32_t* d_scan = nullptr;       // block sums of the matrix scan
+  double* d_trec = nullptr;        // [N][8] records after the coarse scatter
+  int32_t* d_cbp = nullptr;        // [n_cb] point of each coarse bucket
+  double* d_aos = nullptr;         // [N][8] records in binned order
   hipStream_t last = nullptr;
   // optional timing of the main evaluation kernel
   bool profiling = false;
@@ -805,7 +935,6 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.part = p->d_part;
   a.tmax = p->d_tmax;
   a.theta_aos = p->cfg.sort ? p->d_aos : nullptr;
-  a.perm = p->cfg.sort ? p->d_perm : nullptr;
   tile_fn f = pick_tiles_kt(mode == MODE_LSE64, p->KT, p->lset);
   if (!f) return RIFT_EUNSUPPORTED;
   int grid = p->n_tiles;
@@ -834,30 +963,56 @@ void clear_events(rift_ile_plan p) {
   p->ev.clear();
 }
 
-unsigned long long ord_enc_host(double x) {
-  unsigned long long b;
-  memcpy(&b, &x, sizeof b);
-  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+// Device buffers of the binning, allocated the first time a configuration
+// with sort = 1 is used (146 bytes per sample).
+int ensure_bin_buffers(rift_ile_plan p) {
+  if (p->bin_ready) return RIFT_OK;
+  if (p->N > 0x7fffffff) return RIFT_EUNSUPPORTED;
+  const int64_t N = p->N;
+  void* v;
+  int st;
+#define BCHK(x) \
+  if ((st = (x))) return st
+  BCHK(palloc(p, sizeof(Tile) * p->n_stiles, &v));
+  p->d_stiles = (Tile*)v;
+  HCHK(hipMemcpy(p->d_stiles, p->h_stiles.data(), sizeof(Tile) * p->n_stiles, hipMemcpyHostToDevice));
+  BCHK(palloc(p, sizeof(int32_t) * p->n_cb, &v));
+  p->d_cbp = (int32_t*)v;
+  HCHK(hipMemcpy(p->d_cbp, p->h_cbp.data(), sizeof(int32_t) * p->n_cb, hipMemcpyHostToDevice));
+  BCHK(palloc(p, sizeof(float) * 3 * N, &v));
+  p->d_ucoord = (float*)v;
+  BCHK(palloc(p, sizeof(float) * 6 * p->n_stiles, &v));
+  p->d_rpart = (float*)v;
+  BCHK(palloc(p, sizeof(uint16_t) * N, &v));
+  p->d_key = (uint16_t*)v;
+  BCHK(palloc(p, sizeof(int32_t) * p->n_mat, &v));
+  p->d_mat = (int32_t*)v;
+  BCHK(palloc(p, sizeof(int32_t) * ((p->n_mat + SCAN_CHUNK - 1) / SCAN_CHUNK + 1), &v));
+  p->d_scan = (int32_t*)v;
+  BCHK(palloc(p, sizeof(double) * 8 * N, &v));
+  p->d_trec = (double*)v;
+  BCHK(palloc(p, sizeof(double) * 8 * N, &v));
+  p->d_aos = (double*)v;
+#undef BCHK
+  p->bin_ready = true;
+  return RIFT_OK;
 }
 
-// Counting sort of the batch into arrival-time buckets (see k_bin_*).
+// Arrival-time binning of the batch (see k_bin_*): records in d_aos.
 int run_binning(rift_ile_plan p, const double* theta, hipStream_t st) {
-  const int blk = p->cfg.block;
-  hipLaunchKernelGGL(k_fill_u64, dim3((6 * p->n_points + 255) / 256), dim3(256), 0, st, p->d_range,
-                     6 * p->n_points, ord_enc_host(__builtin_inf()), ord_enc_host(-__builtin_inf()));
-  hipLaunchKernelGGL(k_bin_range, dim3(p->n_tiles), dim3(blk), 0, st, p->d_desc, p->d_tiles, theta, p->N,
-                     p->d_ucoord, p->d_range);
-  const int nbk = (int)p->n_buckets;
-  hipLaunchKernelGGL(k_fill_i32, dim3(std::min((nbk + 255) / 256, 65535)), dim3(256), 0, st, p->d_hist, nbk, 0);
-  hipLaunchKernelGGL(k_bin_keys, dim3(p->n_tiles), dim3(blk), 0, st, p->d_desc, p->d_tiles,
-                     (const float*)p->d_ucoord, (const unsigned long long*)p->d_range, p->d_bucket, p->d_hist);
-  const int nb = (int)((p->n_buckets + SCAN_CHUNK - 1) / SCAN_CHUNK);
-  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_T), 0, st, (const int32_t*)p->d_hist, p->n_buckets, p->d_scan);
+  hipLaunchKernelGGL(k_bin_range, dim3(p->n_stiles), dim3(BIN_T), 0, st, p->d_desc, p->d_stiles, theta, p->N,
+                     p->d_ucoord, p->d_rpart);
+  hipLaunchKernelGGL(k_bin_hist, dim3(p->n_stiles), dim3(BIN_T), 0, st, p->d_desc, p->d_stiles,
+                     (const float*)p->d_ucoord, (const float*)p->d_rpart, p->d_key, p->d_mat);
+  const int nb = (int)((p->n_mat + SCAN_CHUNK - 1) / SCAN_CHUNK);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(SCAN_T), 0, st, (const int32_t*)p->d_mat, p->n_mat, p->d_scan);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, st, p->d_scan, nb);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, st, (const int32_t*)p->d_hist, p->n_buckets,
-                     (const int32_t*)p->d_scan, p->d_hist, p->d_cursor);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(p->n_tiles), dim3(blk), 0, st, p->d_tiles, theta, p->N,
-                     (const int32_t*)p->d_bucket, p->d_cursor, p->d_aos, p->d_perm);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(SCAN_T), 0, st, (const int32_t*)p->d_mat, p->n_mat,
+                     (const int32_t*)p->d_scan, p->d_mat, (int32_t*)nullptr);
+  hipLaunchKernelGGL(k_bin_coarse, dim3(p->n_stiles), dim3(BIN_T), 0, st, p->d_desc, p->d_stiles,
+                     (const uint16_t*)p->d_key, (const int32_t*)p->d_mat, theta, p->N, p->d_trec);
+  hipLaunchKernelGGL(k_bin_local, dim3(p->n_cb), dim3(BIN_LT), 0, st, p->d_desc, (const int32_t*)p->d_cbp,
+                     (const int32_t*)p->d_mat, (const double*)p->d_trec, p->d_aos);
   HCHK(hipGetLastError());
   return RIFT_OK;
 }
@@ -985,12 +1140,19 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     D.gmst = pt.gmst_rad;
     D.d_ref = pt.d_ref;
     D.lnN = log((double)D.n);
-    // binning: about 48 samples per occupied-or-not bucket, <= 6 bits per detector
+    // binning: a Morton key of about 32 samples per cell (<= 16 bits), coarse
+    // buckets of about 1024 samples (<= 1024 per point), at most
+    // BIN_LOW_MAX key bits below the coarse bucket
     D.bin_dims = std::min(K, 3);
     {
-      int tot = (int)ceil(log2(std::max(1.0, (double)D.n / 48.0)));
-      tot = std::max(0, std::min(18, tot));
-      D.bin_bits = tot / D.bin_dims;
+      int tb = (int)ceil(log2(std::max(1.0, (double)D.n / 32.0)));
+      tb = std::max(0, std::min(16, tb));
+      D.bin_bits = tb / D.bin_dims;
+      tb = D.bin_bits * D.bin_dims;
+      int cb = (int)ceil(log2(std::max(1.0, (double)D.n / 1024.0)));
+      cb = std::max(0, std::min(BIN_CB_MAX, cb));
+      cb = std::max(cb, tb - BIN_LOW_MAX);
+      D.bin_cb = std::min(cb, tb);
     }
     // refinement margin: an unrefined sample weighs < e^{-T} of the best one
     D.T = log((double)D.n) + 12.0;
@@ -1106,39 +1268,43 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
       D.bnd_q[k] = 2.0 * (60.0 + (double)D.B) * u * l1;
     }
   }
-  // bucket bases of the binning
+  // binning layout: sort tiles, count-matrix blocks and coarse buckets per
+  // point, all in point order (so the matrix scan starts point p at s0)
+  std::vector<Tile>& stiles = p->h_stiles;
+  std::vector<int32_t>& cbp = p->h_cbp;
   {
-    int64_t base = 0;
+    int64_t mbase = 0;
     for (int pi = 0; pi < n_points; ++pi) {
-      p->h_desc[pi].bin_base = base;
-      base += (int64_t)1 << (p->h_desc[pi].bin_dims * p->h_desc[pi].bin_bits);
+      PointDesc& D = p->h_desc[pi];
+      D.bin_st0 = (int32_t)stiles.size();
+      for (int64_t s = 0; s < D.n; s += BIN_TILE) {
+        Tile t;
+        t.p = pi;
+        t.cnt = (int32_t)std::min<int64_t>(BIN_TILE, D.n - s);
+        t.s = D.s0 + s;
+        stiles.push_back(t);
+      }
+      D.bin_nst = (int32_t)stiles.size() - D.bin_st0;
+      D.bin_mbase = mbase;
+      mbase += ((int64_t)1 << D.bin_cb) * D.bin_nst;
+      D.bin_cbase = (int32_t)cbp.size();
+      for (int c = 0; c < (1 << D.bin_cb); ++c) cbp.push_back(pi);
     }
-    if (base > 0x3fffffff) {
+    if (stiles.size() > (size_t)0x7fffffff || cbp.size() > (size_t)0x7fffffff) {
       plan_free_all(p);
       delete p;
       return RIFT_EUNSUPPORTED;
     }
-    p->n_buckets = base;
+    p->n_stiles = (int)stiles.size();
+    p->n_mat = mbase;
+    p->n_cb = (int)cbp.size();
   }
   PHIP(hipMemcpy(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice));
   PCHK(palloc(p, sizeof(int32_t) * 64, &v));
   p->d_counter = (int32_t*)v;
-  PCHK(palloc(p, sizeof(float) * 3 * N, &v));
-  p->d_ucoord = (float*)v;
-  PCHK(palloc(p, sizeof(int32_t) * N, &v));
-  p->d_bucket = (int32_t*)v;
-  PCHK(palloc(p, sizeof(int32_t) * p->n_buckets, &v));
-  p->d_hist = (int32_t*)v;
-  PCHK(palloc(p, sizeof(int32_t) * p->n_buckets, &v));
-  p->d_cursor = (int32_t*)v;
-  PCHK(palloc(p, sizeof(int32_t) * ((p->n_buckets + SCAN_CHUNK - 1) / SCAN_CHUNK + 1), &v));
-  p->d_scan = (int32_t*)v;
-  PCHK(palloc(p, sizeof(unsigned long long) * 6 * n_points, &v));
-  p->d_range = (unsigned long long*)v;
-  PCHK(palloc(p, sizeof(double) * 8 * N, &v));
-  p->d_aos = (double*)v;
-  PCHK(palloc(p, sizeof(int32_t) * N, &v));
-  p->d_perm = (int32_t*)v;
+  // samples are addressed by int32 positions in the binned order
+  if (N > 0x7fffffff) p->cfg.sort = 0;
+  if (p->cfg.sort) PCHK(ensure_bin_buffers(p));
   PCHK(palloc(p, sizeof(double) * N, &v));
   p->d_L = (double*)v;
   if (mixed) {
@@ -1170,6 +1336,7 @@ int rift_ile_plan_set_config(rift_ile_plan plan, const rift_ile_config* cfg) {
   int st = validate_config(cfg);
   if (st) return st;
   if (plan->last) HCHK(hipStreamSynchronize(plan->last));
+  if (cfg->sort && (st = ensure_bin_buffers(plan))) return st;
   const bool retile = cfg->block * cfg->tile_blocks != plan->cfg.block * plan->cfg.tile_blocks;
   plan->cfg = *cfg;
   if (retile) return build_tiles(plan);  // old tile buffers stay owned until destroy
@@ -1187,6 +1354,7 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
   int rc;
   const bool sorted = p->cfg.sort != 0;
   double* L = lnL ? lnL : p->d_L;
+  if (sorted && !p->bin_ready) return RIFT_EUNSUPPORTED;
   if (sorted && (rc = run_binning(p, theta, st))) return rc;
   if (p->prec == RIFT_FP64) {
     if ((rc = launch_tiles(p, MODE_LSE64, theta, lnw, sorted ? L : lnL, st))) return rc;
@@ -1283,6 +1451,10 @@ int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, 
   int rc = RIFT_OK;
   for (int c = 0; c < nc && rc == RIFT_OK; ++c) {
     rc = rift_ile_plan_set_config(p, &cands[c]);
+    if (rc == RIFT_EUNSUPPORTED) {  // e.g. binning of a batch beyond int32 positions
+      rc = RIFT_OK;
+      continue;
+    }
     if (rc) break;
     rc = rift_ile_plan_lnZ(p, theta, lnw, d_out, d_out + p->n_points, nullptr, nullptr, st);  // warm-up
     if (rc) break;
@@ -1306,6 +1478,7 @@ int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, 
   (void)hipFree(d_out);
   p->profiling = prof;
   if (rc) return rc;
+  if (best < 0) return RIFT_EUNSUPPORTED;
   rc = rift_ile_plan_set_config(p, &cands[best]);
   return rc ? rc : best;
 }
