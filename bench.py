@@ -60,6 +60,41 @@ def bytes_per_sample(weighted=False, write_lnL=True):
     return 56 + (8 if weighted else 0) + (8 if write_lnL else 0)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tiles_fp64_3det_21modes_1e6_hbm_traffic.txt")
+KERNEL_SOURCES = ["paper_2609_37393_amd/csrc/ile_device.h", "paper_2609_37393_amd/csrc/ile_kernels.h",
+                  "paper_2609_37393_amd/csrc/ile_grad.h", "paper_2609_37393_amd/csrc/inst.hip",
+                  "paper_2609_37393_amd/csrc/rift_ile.hip",
+                  "paper_2609_37393_amd/build.py"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def bench_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each calibrated on a plain copy of
+    known size), or None when the kernel sources changed since it was taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -86,10 +121,12 @@ def c2_inputs(synth, n):
     return pt, th
 
 
-def run_path(ile, torch, pt, tht, precision, steps, warmup, tune):
+def run_path(ile, torch, pt, tht, precision, steps, warmup, tune, variants=True, config=None):
     n = tht.shape[1]
     plan = ile.Plan([pt], [n], precision=precision)
-    if tune:
+    if config is not None:
+        plan.config = config
+    elif tune:
         plan.tune(tht)
     lnl = torch.empty(n, dtype=torch.float64, device="cuda")
     z = torch.empty(1, dtype=torch.float64, device="cuda")
@@ -100,9 +137,9 @@ def run_path(ile, torch, pt, tht, precision, steps, warmup, tune):
         plan.lnZ(tht, lnZ_out=z, neff_out=ne, lnL_out=lnl, err_out=err)
 
     # the tuned shape with and without arrival-time binning (context only)
-    variants = {}
+    variants_out = {}
     base = plan.config
-    for srt in (0, 1):
+    for srt in ((0, 1) if variants else ()):
         cfg = dict(base)
         cfg["sort"] = srt
         plan.config = cfg
@@ -111,7 +148,7 @@ def run_path(ile, torch, pt, tht, precision, steps, warmup, tune):
         step()
         kms_v, nl = plan.profile_read()
         plan.profile(False)
-        variants[f"sort{srt}"] = {"ms_per_step": 1e3 * sec_v / max(3, steps // 5), "kernel_ms": kms_v / max(1, nl)}
+        variants_out[f"sort{srt}"] = {"ms_per_step": 1e3 * sec_v / max(3, steps // 5), "kernel_ms": kms_v / max(1, nl)}
     plan.config = base
     for _ in range(warmup):
         step()
@@ -130,7 +167,7 @@ def run_path(ile, torch, pt, tht, precision, steps, warmup, tune):
         "lnZ_err_bound": err.item(),
         "config": plan.config,
         "refined": plan.refined() if precision == "mixed" else 0,
-        "variants": variants,
+        "variants": variants_out,
         "lnL": lnl,
     }
     plan.close()
@@ -138,32 +175,39 @@ def run_path(ile, torch, pt, tht, precision, steps, warmup, tune):
 
 
 def cpu_baseline(pt, th, gpu_lnL, budget_s=12.0):
-    """The FP64 oracle as it stands, on this host, on a bounded prefix of the
-    same samples (about `budget_s` seconds of CPU work)."""
+    """The FP64 oracle as it stands, on this host, for about `budget_s` seconds:
+    consecutive chunks of the same samples, wrapping round to the start if the
+    whole workload finishes early.  Parity is taken on the first pass."""
     import oracle
 
     oracle.build(force=False)
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n = th.shape[1]
     done = 0
-    chunk = 20000
+    first = []
+    chunk = 50000
     t0 = time.perf_counter()
-    outs = []
-    while done < n and time.perf_counter() - t0 < budget_s:
-        c = min(chunk, n - done)
-        outs.append(oracle.lnL(pt, th[:, done:done + c], nthreads=nthreads))
+    pos = 0
+    while time.perf_counter() - t0 < budget_s:
+        c = min(chunk, n - pos)
+        out = oracle.lnL(pt, th[:, pos:pos + c], nthreads=nthreads)
+        if done < n:
+            first.append(out)
         done += c
+        pos = (pos + c) % n
     el = time.perf_counter() - t0
-    l_or = np.concatenate(outs)
-    d = np.abs(gpu_lnL[:done] - l_or)
+    l_or = np.concatenate(first)[:n]
+    m = l_or.size
+    d = np.abs(gpu_lnL[:m] - l_or)
+    passes = done / n
     return {
         "value": done / el,
         "unit": "lnL evals/s",
         "cores": nthreads,
         "kind": "oracle",
-        "sample": f"first {done} of the {n} samples of the same workload ({el:.1f} s)",
+        "sample": f"{done} evaluations ({passes:.2f} passes over the {n} samples of the same workload) in {el:.1f} s",
     }, {
-        "samples": int(done),
+        "samples": int(m),
         "max_abs_dlnL": float(d.max()),
         "max_rel_dlnL": float((d / np.maximum(1.0, np.abs(l_or))).max()),
     }
@@ -323,6 +367,10 @@ def main():
     ap.add_argument("--extras", action="store_true", help="also run the C1/C3/C4/C5 workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="time only the chosen launch shape (for profiler runs)")
+    ap.add_argument("--config", default=None,
+                    help="fixed launch shape block,tile_blocks,blocks_per_cu,sort for both paths (no tuning)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a plain 256-MiB elementwise copy kernel (counter calibration)")
     args = ap.parse_args()
@@ -347,9 +395,15 @@ def main():
     lmax = int(pt["lm"][:, 0].max())
 
     log("fp64 path")
-    r64 = run_path(ile, torch, pt, tht, "fp64", args.steps, args.warmup, tune=not args.no_tune)
+    fixed = None
+    if args.config:
+        b, tb, bpc, srt = (int(x) for x in args.config.split(","))
+        fixed = {"block": b, "tile_blocks": tb, "blocks_per_cu": bpc, "sort": srt}
+    r64 = run_path(ile, torch, pt, tht, "fp64", args.steps, args.warmup, tune=not args.no_tune,
+                   variants=not args.no_variants, config=fixed)
     log("mixed path")
-    r32 = run_path(ile, torch, pt, tht, "mixed", args.steps, args.warmup, tune=not args.no_tune)
+    r32 = run_path(ile, torch, pt, tht, "mixed", args.steps, args.warmup, tune=not args.no_tune,
+                   variants=not args.no_variants, config=fixed)
 
     fps = flops_per_sample(K, M, lmax)
     value = n * args.steps / r64["secs"]
@@ -381,7 +435,7 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": bench_traffic(),
             "kernel": "k_tiles<double,3,4,MODE_LSE64>",
             "kernel_ms_avg": r64["kernel_ms_avg"],
             "flops_per_sample": fps,
