@@ -71,14 +71,13 @@ struct PointDesc {
   // bits per detector over the first bin_dims detectors; its top bin_cb
   // bits are the coarse bucket.  The point's sort tiles are bin_st0 ..
   // bin_st0 + bin_nst - 1; its [coarse bucket][sort tile] count matrix
-  // starts at bin_mbase; its coarse buckets are bin_cbase .. in the global
-  // numbering of the local-sort launch.
+  // starts at bin_mbase.
   int32_t bin_dims;
   int32_t bin_bits;
   int32_t bin_cb;
   int32_t bin_nst;
   int32_t bin_st0;
-  int32_t bin_cbase;
+  int32_t bin_pad;
   int64_t bin_mbase;
   // Q series of each (detector, mode), time-contiguous with QPAD zero rows at
   // both ends: [KT][M][n_t + 2 QPAD] complex.  A stencil starting at row

@@ -404,14 +404,13 @@ __global__ void k_scan_apply(const int32_t* a, int64_t n, const int32_t* __restr
 //   k_scan_*      exclusive scan of the count matrix (positions);
 //   k_bin_coarse  per sort tile: every record to the next slot of its coarse
 //                 bucket (LDS cursors; theta read in input order);
-//   k_bin_local   per coarse bucket: counting sort on the low key bits in LDS,
-//                 records moved to their final positions (inside the bucket).
+//   k_bin_chunk   per chunk of 2048 coarse-ordered records: counting sort by
+//                 the key in LDS, records moved to their final positions.
 // The order inside a cell is not fixed; lnL values do not depend on it and
 // every reduction runs in input order.
 // ---------------------------------------------------------------------------
 constexpr int BIN_TILE = 4096;   // samples per sort tile
 constexpr int BIN_T = 1024;      // threads of the sort kernels
-constexpr int BIN_LOW_MAX = 10;  // low key bits sorted in LDS (<= 1024 bins)
 constexpr int BIN_CB_MAX = 10;   // coarse buckets per point <= 1024
 
 // Stencil row coordinate u_k = (t_k - t0)/dt of the first bin_dims detectors
@@ -536,8 +535,8 @@ __global__ void __launch_bounds__(BIN_T) k_bin_hist(const PointDesc* __restrict_
 
 // Coarse scatter: every sample of a sort tile takes the next slot of its
 // coarse bucket in this tile's range (LDS cursors) and its record goes there,
-// with (sample index << 16 | low key bits) in the last slot.  Slots are global
-// sample positions (the scanned matrix starts each point at its first column).
+// with (sample index << 16 | key) in the last slot.  Slots are global sample
+// positions (the scanned matrix starts each point at its first column).
 __global__ void __launch_bounds__(BIN_T) k_bin_coarse(const PointDesc* __restrict__ descs,
                                                       const Tile* __restrict__ stiles,
                                                       const uint16_t* __restrict__ key,
@@ -552,12 +551,11 @@ __global__ void __launch_bounds__(BIN_T) k_bin_coarse(const PointDesc* __restric
   const int64_t col = blockIdx.x - P->bin_st0;
   for (int c = threadIdx.x; c < nc; c += blockDim.x) cur[c] = mat[P->bin_mbase + (int64_t)c * P->bin_nst + col];
   __syncthreads();
-  const uint32_t lowmask = (1u << (tb - cb)) - 1u;
   for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
     const int64_t i = t.s + o;
     const uint32_t k = key[i];
     const int64_t slot = atomicAdd(&cur[k >> (tb - cb)], 1);
-    const long long tag = ((long long)i << 16) | (long long)(k & lowmask);
+    const long long tag = ((long long)i << 16) | (long long)k;
     double2* dst = reinterpret_cast<double2*>(trec + 8 * slot);
     dst[0] = make_double2(theta[i], theta[N + i]);
     dst[1] = make_double2(theta[2 * N + i], theta[3 * N + i]);
@@ -566,71 +564,89 @@ __global__ void __launch_bounds__(BIN_T) k_bin_coarse(const PointDesc* __restric
   }
 }
 
-// One block per coarse bucket: counting sort of its records on the low key
-// bits (LDS), in chunks of BIN_LCHUNK records, each record moving from its
-// coarse slot to its final position (both inside the bucket's range).
-constexpr int BIN_LT = 256;
-constexpr int BIN_LPER = 8;
-constexpr int BIN_LCHUNK = BIN_LT * BIN_LPER;
-__global__ void __launch_bounds__(BIN_LT) k_bin_local(const PointDesc* __restrict__ descs,
-                                                      const int32_t* __restrict__ cb_point,
-                                                      const int32_t* __restrict__ mat,
+// Fine order: the coarse-ordered records of each point are cut into chunks
+// of BIN_CHUNK; each block counting-sorts one chunk by its key offset from
+// the chunk's smallest key (LDS histogram) and moves the records to their
+// places.  Every block does the same work whatever the key distribution.  A
+// chunk whose keys span more than BIN_SPAN values (several sparse coarse
+// cells, each already small) keeps its coarse order.
+constexpr int BIN_CT = 256;
+constexpr int BIN_CPER = 8;
+constexpr int BIN_CHUNK = BIN_CT * BIN_CPER;
+constexpr int BIN_SPAN = 4096;
+__global__ void __launch_bounds__(BIN_CT) k_bin_chunk(const Tile* __restrict__ chunks,
                                                       const double* __restrict__ trec,
                                                       double* __restrict__ aos) {
-  __shared__ int32_t h[1 << BIN_LOW_MAX];
-  __shared__ int32_t ws[BIN_LT / 64 + 1];
-  const int p = cb_point[blockIdx.x];
-  const PointDesc* P = descs + p;
-  const int c = blockIdx.x - P->bin_cbase;
-  const int nc = 1 << P->bin_cb;
-  const int nlow = 1 << (P->bin_dims * P->bin_bits - P->bin_cb);
-  const int64_t beg = mat[P->bin_mbase + (int64_t)c * P->bin_nst];
-  const int64_t end = (c + 1 < nc) ? (int64_t)mat[P->bin_mbase + (int64_t)(c + 1) * P->bin_nst] : P->s0 + P->n;
-  for (int64_t c0 = beg; c0 < end; c0 += BIN_LCHUNK) {
-    const int64_t c1 = (c0 + BIN_LCHUNK < end) ? c0 + BIN_LCHUNK : end;
-    for (int b = threadIdx.x; b < nlow; b += blockDim.x) h[b] = 0;
+  __shared__ int32_t h[BIN_SPAN];
+  __shared__ int32_t ws[BIN_CT / 64 + 1];
+  __shared__ uint32_t mm[2][BIN_CT / 64];
+  const Tile t = chunks[blockIdx.x];
+  uint32_t kk[BIN_CPER];
+  uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+  for (int j = 0; j < BIN_CPER; ++j) {
+    const int q = j * BIN_CT + threadIdx.x;
+    kk[j] = 0;
+    if (q < t.cnt) {
+      kk[j] = (uint32_t)(__double_as_longlong(trec[8 * (t.s + q) + 7]) & 0xffff);
+      lo = min(lo, kk[j]);
+      hi = max(hi, kk[j]);
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    mm[0][threadIdx.x >> 6] = lo;
+    mm[1][threadIdx.x >> 6] = hi;
+  }
+  for (int b = threadIdx.x; b < BIN_SPAN; b += BIN_CT) h[b] = 0;
+  __syncthreads();
+  lo = mm[0][0];
+  hi = mm[1][0];
+  for (int w = 1; w < BIN_CT / 64; ++w) {
+    lo = min(lo, mm[0][w]);
+    hi = max(hi, mm[1][w]);
+  }
+  const bool sort = hi >= lo && hi - lo < (uint32_t)BIN_SPAN;
+  int32_t dst[BIN_CPER];
+  if (sort) {
+#pragma unroll
+    for (int j = 0; j < BIN_CPER; ++j)
+      if (j * BIN_CT + (int)threadIdx.x < t.cnt) atomicAdd(&h[kk[j] - lo], 1);
     __syncthreads();
-    double2 rec[BIN_LPER][4];
-    uint32_t kk[BIN_LPER];
+    // exclusive scan of the BIN_SPAN bins (each thread a contiguous run)
+    constexpr int per = BIN_SPAN / BIN_CT;
+    const int b0 = threadIdx.x * per;
+    int32_t run = 0;
 #pragma unroll
-    for (int j = 0; j < BIN_LPER; ++j) {
-      const int64_t e = c0 + j * BIN_LT + threadIdx.x;
-      kk[j] = 0;
-      if (e < c1) {
-        const double2* src = reinterpret_cast<const double2*>(trec + 8 * e);
+    for (int b = 0; b < per; ++b) run += h[b0 + b];
+    int32_t tot;
+    int32_t off = block_excl_scan(run, ws, &tot);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) rec[j][a] = src[a];
-        kk[j] = (uint32_t)(__double_as_longlong(rec[j][3].y) & 0xffff);
-        atomicAdd(&h[kk[j]], 1);
-      }
+    for (int b = 0; b < per; ++b) {
+      const int32_t v = h[b0 + b];
+      h[b0 + b] = off;
+      off += v;
     }
     __syncthreads();
-    // exclusive scan of the nlow bins (each thread a contiguous run)
-    {
-      const int per = (nlow + BIN_LT - 1) / BIN_LT;
-      const int b0 = threadIdx.x * per;
-      int32_t run = 0;
-      for (int b = b0; b < b0 + per && b < nlow; ++b) run += h[b];
-      int32_t tot;
-      int32_t off = block_excl_scan(run, ws, &tot);
-      for (int b = b0; b < b0 + per && b < nlow; ++b) {
-        const int32_t v = h[b];
-        h[b] = off;
-        off += v;
-      }
-    }
-    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < BIN_LPER; ++j) {
-      const int64_t e = c0 + j * BIN_LT + threadIdx.x;
-      if (e < c1) {
-        const int64_t pos = c0 + atomicAdd(&h[kk[j]], 1);
-        double2* dst = reinterpret_cast<double2*>(aos + 8 * pos);
+    for (int j = 0; j < BIN_CPER; ++j)
+      dst[j] = (j * BIN_CT + (int)threadIdx.x < t.cnt) ? atomicAdd(&h[kk[j] - lo], 1) : 0;
+  } else {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) dst[a] = rec[j][a];
-      }
+    for (int j = 0; j < BIN_CPER; ++j) dst[j] = j * BIN_CT + threadIdx.x;
+  }
+#pragma unroll
+  for (int j = 0; j < BIN_CPER; ++j) {
+    const int q = j * BIN_CT + threadIdx.x;
+    if (q < t.cnt) {
+      const double2* from = reinterpret_cast<const double2*>(trec + 8 * (t.s + q));
+      double2* to = reinterpret_cast<double2*>(aos + 8 * (t.s + dst[j]));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) to[c] = from[c];
     }
-    __syncthreads();
   }
 }
 
@@ -806,18 +822,18 @@ struct rift_ile_plan_s {
   // binning (sorted evaluation), see k_bin_*
   bool bin_ready = false;          // buffers below allocated (on first use of sort)
   std::vector<Tile> h_stiles;
-  std::vector<int32_t> h_cbp;
+  std::vector<Tile> h_chunks;      // BIN_CHUNK-record chunks of every point
   int n_stiles = 0;
   Tile* d_stiles = nullptr;        // sort tiles of BIN_TILE samples
   int64_t n_mat = 0;               // [coarse bucket][sort tile] entries, all points
-  int n_cb = 0;                    // coarse buckets, all points
   float* d_ucoord = nullptr;       // [N][3]
   float* d_rpart = nullptr;        // [n_stiles][6]
   uint16_t* d_key = nullptr;       // [N]
   int32_t* d_mat = nullptr;        // [n_mat]
   int32_t* d_scan = nullptr;       // block sums of the matrix scan
   double* d_trec = nullptr;        // [N][8] records after the coarse scatter
-  int32_t* d_cbp = nullptr;        // [n_cb] point of each coarse bucket
+  Tile* d_chunks = nullptr;        // fine-sort chunks
+  int n_chunks = 0;
   double* d_aos = nullptr;         // [N][8] records in binned order
   hipStream_t last = nullptr;
   // optional timing of the main evaluation kernel
@@ -976,9 +992,9 @@ int ensure_bin_buffers(rift_ile_plan p) {
   BCHK(palloc(p, sizeof(Tile) * p->n_stiles, &v));
   p->d_stiles = (Tile*)v;
   HCHK(hipMemcpy(p->d_stiles, p->h_stiles.data(), sizeof(Tile) * p->n_stiles, hipMemcpyHostToDevice));
-  BCHK(palloc(p, sizeof(int32_t) * p->n_cb, &v));
-  p->d_cbp = (int32_t*)v;
-  HCHK(hipMemcpy(p->d_cbp, p->h_cbp.data(), sizeof(int32_t) * p->n_cb, hipMemcpyHostToDevice));
+  BCHK(palloc(p, sizeof(Tile) * p->n_chunks, &v));
+  p->d_chunks = (Tile*)v;
+  HCHK(hipMemcpy(p->d_chunks, p->h_chunks.data(), sizeof(Tile) * p->n_chunks, hipMemcpyHostToDevice));
   BCHK(palloc(p, sizeof(float) * 3 * N, &v));
   p->d_ucoord = (float*)v;
   BCHK(palloc(p, sizeof(float) * 6 * p->n_stiles, &v));
@@ -1011,8 +1027,8 @@ int run_binning(rift_ile_plan p, const double* theta, hipStream_t st) {
                      (const int32_t*)p->d_scan, p->d_mat, (int32_t*)nullptr);
   hipLaunchKernelGGL(k_bin_coarse, dim3(p->n_stiles), dim3(BIN_T), 0, st, p->d_desc, p->d_stiles,
                      (const uint16_t*)p->d_key, (const int32_t*)p->d_mat, theta, p->N, p->d_trec);
-  hipLaunchKernelGGL(k_bin_local, dim3(p->n_cb), dim3(BIN_LT), 0, st, p->d_desc, (const int32_t*)p->d_cbp,
-                     (const int32_t*)p->d_mat, (const double*)p->d_trec, p->d_aos);
+  hipLaunchKernelGGL(k_bin_chunk, dim3(p->n_chunks), dim3(BIN_CT), 0, st, (const Tile*)p->d_chunks,
+                     (const double*)p->d_trec, p->d_aos);
   HCHK(hipGetLastError());
   return RIFT_OK;
 }
@@ -1141,8 +1157,7 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     D.d_ref = pt.d_ref;
     D.lnN = log((double)D.n);
     // binning: a Morton key of about 32 samples per cell (<= 16 bits), coarse
-    // buckets of about 1024 samples (<= 1024 per point), at most
-    // BIN_LOW_MAX key bits below the coarse bucket
+    // buckets of about 1024 samples (<= 1024 per point)
     D.bin_dims = std::min(K, 3);
     {
       int tb = (int)ceil(log2(std::max(1.0, (double)D.n / 32.0)));
@@ -1151,7 +1166,6 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
       tb = D.bin_bits * D.bin_dims;
       int cb = (int)ceil(log2(std::max(1.0, (double)D.n / 1024.0)));
       cb = std::max(0, std::min(BIN_CB_MAX, cb));
-      cb = std::max(cb, tb - BIN_LOW_MAX);
       D.bin_cb = std::min(cb, tb);
     }
     // refinement margin: an unrefined sample weighs < e^{-T} of the best one
@@ -1271,7 +1285,6 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
   // binning layout: sort tiles, count-matrix blocks and coarse buckets per
   // point, all in point order (so the matrix scan starts point p at s0)
   std::vector<Tile>& stiles = p->h_stiles;
-  std::vector<int32_t>& cbp = p->h_cbp;
   {
     int64_t mbase = 0;
     for (int pi = 0; pi < n_points; ++pi) {
@@ -1287,17 +1300,22 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
       D.bin_nst = (int32_t)stiles.size() - D.bin_st0;
       D.bin_mbase = mbase;
       mbase += ((int64_t)1 << D.bin_cb) * D.bin_nst;
-      D.bin_cbase = (int32_t)cbp.size();
-      for (int c = 0; c < (1 << D.bin_cb); ++c) cbp.push_back(pi);
+      for (int64_t s = 0; s < D.n; s += BIN_CHUNK) {
+        Tile t;
+        t.p = pi;
+        t.cnt = (int32_t)std::min<int64_t>(BIN_CHUNK, D.n - s);
+        t.s = D.s0 + s;
+        p->h_chunks.push_back(t);
+      }
     }
-    if (stiles.size() > (size_t)0x7fffffff || cbp.size() > (size_t)0x7fffffff) {
+    p->n_chunks = (int)p->h_chunks.size();
+    if (stiles.size() > (size_t)0x7fffffff || p->h_chunks.size() > (size_t)0x7fffffff) {
       plan_free_all(p);
       delete p;
       return RIFT_EUNSUPPORTED;
     }
     p->n_stiles = (int)stiles.size();
     p->n_mat = mbase;
-    p->n_cb = (int)cbp.size();
   }
   PHIP(hipMemcpy(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice));
   PCHK(palloc(p, sizeof(int32_t) * 64, &v));
