@@ -30,6 +30,9 @@ FLAGS = [
     "-fPIC",
     # packed FP32 VALU ops are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only inside one source expression: the same
+    # expression gives the same bits in every kernel that inlines it
+    "-ffp-contract=on",
     "-Wall",
     "-Wno-unused-function",
 ]

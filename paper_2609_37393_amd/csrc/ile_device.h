@@ -304,6 +304,56 @@ struct Contract {
   }
 };
 
+// Per-mode arithmetic of the data term, every multiply-add written as an
+// explicit fma (with multiply-adds otherwise fused only within one source
+// expression, an expression gives the same bits in every kernel that inlines
+// it).
+//   phase_up: ph <- ph e^{i phi};  phase_down: ph <- ph e^{-i phi}
+template <class R>
+__device__ __forceinline__ void phase_up(C2<R>& ph, R cf, R sf) {
+  const R a = fma(ph.x, cf, -ph.y * sf), b = fma(ph.y, cf, ph.x * sf);
+  ph.x = a;
+  ph.y = b;
+}
+template <class R>
+__device__ __forceinline__ void phase_down(C2<R>& ph, R cf, R sf) {
+  const R a = fma(ph.x, cf, ph.y * sf), b = fma(ph.y, cf, -ph.x * sf);
+  ph.x = a;
+  ph.y = b;
+}
+// d_i(incl) from its Fourier coefficients (sin series for odd m).
+template <class R, int NY>
+__device__ __forceinline__ R mode_d(PDesc P, int i, const R* cn, const R* sn) {
+  R d = 0;
+  if (P->odd[i]) {
+#pragma unroll
+    for (int n = 1; n < NY; ++n) d = fma(Tab<R>::y(P, i, n), sn[n], d);
+  } else {
+#pragma unroll
+    for (int n = 0; n < NY; ++n) d = fma(Tab<R>::y(P, i, n), cn[n], d);
+  }
+  return d;
+}
+// Z += conj(Y) Qhat with Qhat the Lagrange combination of four taps.
+template <class R>
+__device__ __forceinline__ void mode_acc(C2<R>& Z, const R* w, C2<R> q0, C2<R> q1, C2<R> q2, C2<R> q3,
+                                         R yx, R yy) {
+  const R qx = fma(w[3], q3.x, fma(w[2], q2.x, fma(w[1], q1.x, w[0] * q0.x)));
+  const R qy = fma(w[3], q3.y, fma(w[2], q2.y, fma(w[1], q1.y, w[0] * q0.y)));
+  Z.x = fma(yx, qx, Z.x);
+  Z.x = fma(yy, qy, Z.x);
+  Z.y = fma(yx, qy, Z.y);
+  Z.y = fma(-yy, qx, Z.y);
+}
+// The four Lagrange weights on nodes -1, 0, 1, 2 at fraction s.
+template <class R>
+__device__ __forceinline__ void lagrange4(R s, R* w) {
+  w[0] = -s * (s - 1) * (s - 2) * (R)(1.0 / 6.0);
+  w[1] = (s + 1) * (s - 1) * (s - 2) * (R)0.5;
+  w[2] = -(s + 1) * s * (s - 2) * (R)0.5;
+  w[3] = (s + 1) * s * (s - 1) * (R)(1.0 / 6.0);
+}
+
 // Data term of detectors K0 .. K0+G-1 (G <= 3):
 //   sum_k Re[conj(F_k) sum_i conj(Y_i) Qhat_{k,i}]
 //   = sum_k Fre_k Re(Z_k) + Fim_k Im(Z_k),  Z_k = sum_i conj(Y_i) Qhat_{k,i},
@@ -322,13 +372,7 @@ __device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb
   typedef R R2 __attribute__((ext_vector_type(2)));
   R w[G][4];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const R s = sfr[K0 + g];
-    w[g][0] = -s * (s - 1) * (s - 2) * (R)(1.0 / 6.0);
-    w[g][1] = (s + 1) * (s - 1) * (s - 2) * (R)0.5;
-    w[g][2] = -(s + 1) * s * (s - 2) * (R)0.5;
-    w[g][3] = (s + 1) * s * (s - 1) * (R)(1.0 / 6.0);
-  }
+  for (int g = 0; g < G; ++g) lagrange4(sfr[K0 + g], w[g]);
   C2<R> Z[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) Z[g].x = Z[g].y = 0;
@@ -336,11 +380,7 @@ __device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb
   ph.x = 1;
   ph.y = 0;
   const int mmin = P->m_min;
-  for (int t = 0; t < -mmin; ++t) {
-    const R a = ph.x * cf + ph.y * sf, bb = ph.y * cf - ph.x * sf;
-    ph.x = a;
-    ph.y = bb;
-  }
+  for (int t = 0; t < -mmin; ++t) phase_down(ph, cf, sf);
   int mc = mmin < 0 ? mmin : 0;
   // issue the 4 G tap loads of mode i into buf
   auto load = [&](C2<R>(&buf)[G][4], int i) {
@@ -360,32 +400,13 @@ __device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb
   auto step = [&](const C2<R>(&buf)[G][4], int i) {
     const int mi = P->m[i];
     while (mc < mi) {
-      const R a = ph.x * cf - ph.y * sf, bb = ph.y * cf + ph.x * sf;
-      ph.x = a;
-      ph.y = bb;
+      phase_up(ph, cf, sf);
       ++mc;
     }
-    R d = 0;
-    if (P->odd[i]) {
-#pragma unroll
-      for (int n = 1; n < NY; ++n) d += Tab<R>::y(P, i, n) * sn[n];
-    } else {
-#pragma unroll
-      for (int n = 0; n < NY; ++n) d += Tab<R>::y(P, i, n) * cn[n];
-    }
+    const R d = mode_d<R, NY>(P, i, cn, sn);
     const R yx = d * ph.x, yy = d * ph.y;
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const R qx = w[g][0] * buf[g][0].x + w[g][1] * buf[g][1].x + w[g][2] * buf[g][2].x +
-                   w[g][3] * buf[g][3].x;
-      const R qy = w[g][0] * buf[g][0].y + w[g][1] * buf[g][1].y + w[g][2] * buf[g][2].y +
-                   w[g][3] * buf[g][3].y;
-      // separate FMA chains (a + (b + c) would cost mul + fma + add)
-      Z[g].x = fma(yx, qx, Z[g].x);
-      Z[g].x = fma(yy, qy, Z[g].x);
-      Z[g].y = fma(yx, qy, Z[g].y);
-      Z[g].y = fma(-yy, qx, Z[g].y);
-    }
+    for (int g = 0; g < G; ++g) mode_acc(Z[g], w[g], buf[g][0], buf[g][1], buf[g][2], buf[g][3], yx, yy);
     // the accumulators are final for this mode here: keeps the FMAs of this
     // step ahead of the next load batch (instead of sinking them past it,
     // which would keep both tap buffers and the new batch live)
@@ -435,21 +456,41 @@ struct Eval {
   float bound;  // a-priori |lnL - lnL_FP64| bound (FP32 arithmetic only)
 };
 
+// Data term of one sample with its taps read straight from the table.
+template <class R, int KT, int L>
+__device__ __forceinline__ double data_direct(PDesc P, const int32_t* row, const R* sfr, const R* Fre,
+                                              const R* Fim, const R* cn, const R* sn, R cf, R sf) {
+  constexpr int NY = Cls<L>::NY;
+  const int M = P->M;
+  uint32_t boff[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) boff[k] = (uint32_t)row[k] * (uint32_t)sizeof(C2<R>);
+  const RIFT_GLOBAL char* Qb = (const RIFT_GLOBAL char*)Tab<R>::Q(P);
+  const uint64_t sstride = (uint64_t)(P->n_t + 2 * QPAD) * sizeof(C2<R>);
+  double data = data_group<R, NY, 0, (KT < 3 ? KT : 3)>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn, sn,
+                                                         cf, sf);
+  if constexpr (KT > 3)
+    data += data_group<R, NY, 3, (KT - 3 < 3 ? KT - 3 : 3)>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn,
+                                                            sn, cf, sf);
+  if constexpr (KT > 6)
+    data += data_group<R, NY, 6, KT - 6>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn, sn, cf, sf);
+  return data;
+}
+
 // Everything per sample.  R is the arithmetic type of the bulk (FP64 or FP32);
-// the sky frame, delays and the final combination are always FP64.
+// the sky frame, delays and the final combination are always FP64.  The data
+// term comes from data_fn(row, sfr, Fre, Fim, cn, sn, cf, sf).
 //
-// `trig` is this lane's column of a block-shared scratch array (stride
-// `ts` elements) holding cos(n incl), n = 0..NI, then sin(n incl): the
-// model-norm contraction runs as a loop over basis rows (a handful of
-// scalar coefficient loads per iteration) and reads these by index.
-template <class R, int KT, int L, bool BOUND>
-__device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int ts, double ra,
-                                            double dec, double psi, double incl, double phi,
-                                            double tref, double dist) {
+// `trig` is this lane's column of a block-shared scratch array (stride `ts`
+// elements) that receives cos(n incl), n = 0..NI, then sin(n incl), for the
+// runtime contraction loop of the l <= 8 class.
+template <class R, int KT, int L, bool BOUND, class DataFn>
+__device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, int ts, double ra,
+                                                 double dec, double psi, double incl, double phi,
+                                                 double tref, double dist, DataFn&& data_fn) {
   typedef Cls<L> CL;
   constexpr int NI = CL::NI;
   constexpr int NY = CL::NY;
-  const int M = P->M;
   const int n_t = P->n_t;
 
   // --- sky frame (FP64) --------------------------------------------------
@@ -503,9 +544,8 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
   // --- antenna factors and stencils per detector --------------------------
   R Fre[KT], Fim[KT];
   R sfr[KT];        // fractional position inside the stencil cell
-  uint32_t boff[KT];  // byte offset of the first stencil row in its series
+  int32_t row[KT];  // padded index of the first stencil row, in [0, n_t + QPAD]
   bool bad = false;
-  const int ntp = n_t + 2 * QPAD;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     R fp = 0, fx = 0;
@@ -528,20 +568,11 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
     int j0 = (int)jf - 1;  // stencil rows j0 .. j0+3
     // wholly outside the stored window: read four zero pad rows
     j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
-    boff[k] = (uint32_t)(j0 + QPAD) * (uint32_t)sizeof(C2<R>);
+    row[k] = j0 + QPAD;
     sfr[k] = s;
   }
 
-  // --- data term, in groups of at most three detectors -------------------
-  const RIFT_GLOBAL char* Qb = (const RIFT_GLOBAL char*)Tab<R>::Q(P);
-  const uint64_t sstride = (uint64_t)ntp * sizeof(C2<R>);
-  double data = data_group<R, NY, 0, (KT < 3 ? KT : 3)>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn,
-                                                         sn, cf, sf);
-  if constexpr (KT > 3)
-    data += data_group<R, NY, 3, (KT - 3 < 3 ? KT - 3 : 3)>(P, Qb, sstride, M, boff, sfr, Fre, Fim,
-                                                            cn, sn, cf, sf);
-  if constexpr (KT > 6)
-    data += data_group<R, NY, 6, KT - 6>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn, sn, cf, sf);
+  const double data = data_fn(row, sfr, Fre, Fim, cn, sn, cf, sf);
 
   // --- model-norm term: basis contraction ----------------------------------
   R acc[3 * KT];
@@ -633,6 +664,16 @@ __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int t
   e.bound = 0.0f;
   if (BOUND) e.bound = (float)(x * P->bnd_d + x * x * wq);
   return e;
+}
+
+template <class R, int KT, int L, bool BOUND>
+__device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int ts, double ra,
+                                            double dec, double psi, double incl, double phi,
+                                            double tref, double dist) {
+  return eval_sample_with<R, KT, L, BOUND>(
+      P, trig, ts, ra, dec, psi, incl, phi, tref, dist,
+      [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
+          R sf) { return data_direct<R, KT, L>(P, row, sfr, Fre, Fim, cn, sn, cf, sf); });
 }
 
 // ---------------------------------------------------------------------------

@@ -951,6 +951,8 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.part = p->d_part;
   a.tmax = p->d_tmax;
   a.theta_aos = p->cfg.sort ? p->d_aos : nullptr;
+  const size_t rsz = (mode == MODE_LSE64 ? sizeof(double) : sizeof(float));
+  const size_t trig_bytes = (p->lset & 8) ? (size_t)trig_rows(p->lset) * p->cfg.block * rsz : 0;
   tile_fn f = pick_tiles_kt(mode == MODE_LSE64, p->KT, p->lset);
   if (!f) return RIFT_EUNSUPPORTED;
   int grid = p->n_tiles;
@@ -959,7 +961,7 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
     grid = std::min(p->n_tiles, p->cfg.blocks_per_cu * p->di.n_cu);
   }
   if (grid <= 0) return RIFT_OK;
-  const size_t shm = (size_t)trig_rows(p->lset) * p->cfg.block * (mode == MODE_LSE64 ? sizeof(double) : sizeof(float));
+  const size_t shm = trig_bytes;  // per-lane scratch column, l <= 8 class only
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p->profiling) {
     HCHK(hipEventCreate(&e0));
