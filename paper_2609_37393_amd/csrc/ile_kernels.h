@@ -132,13 +132,155 @@ __global__ void __launch_bounds__(512) k_tiles(TileArgs a) {
   }
 }
 
-// FP64 recompute of the refine list of point blockIdx.y.
+// One sample evaluated by a whole wavefront (FP64): the same definition as
+// eval_sample, split over the lanes for latency.  Lanes below 2 L + 1 fill
+// the wavefront's table of cos/sin(n incl) and cos/sin(q phi), n, q <= 2 L;
+// lanes below K fill detector k's antenna factor, norm weights and stencil.
+// Then lane l takes the (detector, mode) pairs l, l+64, ... of the data term
+// and the coefficients l, l+64, ... of the model-norm contraction; the shares
+// meet in wavefront sums.  tab: this wavefront's LDS scratch of
+// WIDE_TAB(L, KT) doubles.  Every lane returns the sample's lnL.
+#define WIDE_TAB(L, KT) (4 * (2 * (L) + 1) + 8 * (KT))
+template <int KT, int L>
+__device__ __forceinline__ double eval_wide(PDesc P, double ra, double dec, double psi, double incl,
+                                            double phi, double tref, double dist, double* tab) {
+  constexpr int NI = 2 * L;
+  constexpr int NY = L + 1;
+  const int lane = threadIdx.x & 63;
+  const int K = P->K, M = P->M, n_t = P->n_t;
+  double* ctab = tab;
+  double* stab = tab + (NI + 1);
+  double* cq = tab + 2 * (NI + 1);
+  double* sq = tab + 3 * (NI + 1);
+  double* det = tab + 4 * (NI + 1);  // per detector: fp, fx, f2, g2r, g2i, row, s, bad
+  if (lane <= NI) {
+    double s, c;
+    sincos((double)lane * incl, &s, &c);
+    ctab[lane] = c;
+    stab[lane] = s;
+    sincos((double)lane * phi, &s, &c);
+    cq[lane] = c;
+    sq[lane] = s;
+  }
+  if (lane < K) {
+    const int k = lane;
+    double sg, cg, sd, cd, sp, cp;
+    sincos(P->gmst - ra, &sg, &cg);
+    sincos(dec, &sd, &cd);
+    sincos(psi, &sp, &cp);
+    const double N0 = cd * cg, N1 = -cd * sg, N2 = sd;
+    const double ed0 = -sd * cg, ed1 = sd * sg, ed2 = cd;
+    const double X0 = -cp * sg + sp * ed0, X1 = -cp * cg + sp * ed1, X2 = sp * ed2;
+    const double Y0 = sp * sg + cp * ed0, Y1 = sp * cg + cp * ed1, Y2 = cp * ed2;
+    const double ep[6] = {X0 * X0 - Y0 * Y0, X1 * X1 - Y1 * Y1, X2 * X2 - Y2 * Y2,
+                          X0 * X1 - Y0 * Y1, X0 * X2 - Y0 * Y2, X1 * X2 - Y1 * Y2};
+    const double ex[6] = {2 * X0 * Y0, 2 * X1 * Y1, 2 * X2 * Y2,
+                          X0 * Y1 + Y0 * X1, X0 * Y2 + Y0 * X2, X1 * Y2 + Y1 * X2};
+    double fp = 0.0, fx = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      fp += P->dten[k][a] * ep[a];
+      fx += P->dten[k][a] * ex[a];
+    }
+    const double tk = tref - (P->rpos[k][0] * N0 + P->rpos[k][1] * N1 + P->rpos[k][2] * N2);
+    double u = (tk - P->t0) * P->inv_dt;
+    double bad = 0.0;
+    if (!(fabs(u) < 1.0e9)) {
+      bad = 1.0;
+      u = 0.0;
+    }
+    const double jf = floor(u);
+    int j0 = (int)jf - 1;
+    j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
+    double* dk = det + 8 * k;
+    dk[0] = fp;
+    dk[1] = fx;
+    dk[2] = fp * fp + fx * fx;
+    dk[3] = fp * fp - fx * fx;
+    dk[4] = 2 * fp * fx;
+    dk[5] = (double)(j0 + QPAD);
+    dk[6] = u - jf;
+    dk[7] = bad;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // data term: pairs (k, i)
+  const RIFT_GLOBAL double* Q = as_global(P->Q64);
+  const int64_t ntp = n_t + 2 * QPAD;
+  double data = 0.0;
+  for (int pr = lane; pr < K * M; pr += 64) {
+    const int k = pr / M, i = pr % M;
+    const double* dk = det + 8 * k;
+    double w[4];
+    lagrange4(dk[6], w);
+    const RIFT_GLOBAL double* q = Q + 2 * (((int64_t)k * M + i) * ntp + (int64_t)dk[5]);
+    double qx = 0.0, qy = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      qx += w[j] * q[2 * j];
+      qy += w[j] * q[2 * j + 1];
+    }
+    // Y_i = d_i(incl) e^{i m_i phi}
+    const int m = P->m[i];
+    double d = 0.0;
+    if (P->odd[i]) {
+      for (int n = 1; n < NY; ++n) d += P->ycoef[i][n] * stab[n];
+    } else {
+      for (int n = 0; n < NY; ++n) d += P->ycoef[i][n] * ctab[n];
+    }
+    const int am = m < 0 ? -m : m;
+    const double yx = d * cq[am], yy = d * (m < 0 ? -sq[am] : sq[am]);
+    // Re[conj(F) conj(Y) Qhat]
+    data += dk[0] * (yx * qx + yy * qy) + dk[1] * (yx * qy - yy * qx);
+  }
+  // model-norm term: coefficient j = b * 3 KT + 3 k + c, weights |F|^2,
+  // Re F^2, Im F^2 for c = 0, 1, 2
+  double quad = 0.0;
+  const RIFT_GLOBAL double* C = as_global(P->C64);
+  const int W = 3 * KT;
+#pragma unroll 4
+  for (int j = lane; j < Cls<L>::B * W; j += 64) {
+    const int b = j / W, col = j - b * W, k = col / 3, c = col - 3 * k;
+    const int rb = basis_row<L>(b);
+    const int kind = rb & 15, n = (rb >> 4) & 255, qq = rb >> 12;
+    double beta = (kind >= 3) ? stab[n] : ctab[n];
+    if (kind != 0) beta *= ((kind & 1) == 1) ? cq[qq] : sq[qq];
+    const double wt = (k < K) ? det[8 * k + 2 + c] : 0.0;
+    quad += C[j] * beta * wt;
+  }
+  double bad = (lane < K) ? det[8 * lane + 7] : 0.0;
+  data = dsum_wave(data);
+  quad = dsum_wave(quad);
+  bad = dsum_wave(bad);
+  const double x = P->d_ref / dist;
+  double l = x * data - x * x * quad;
+  if (bad != 0.0) l = __builtin_nan("");
+  return l;
+}
+
+// FP64 recompute of the refine list of point blockIdx.y: a whole wavefront
+// per sample while the list is short (latency), one lane per sample when it
+// is long (throughput).
 template <int KT, int L>
 __device__ __forceinline__ void refine_point(const PointDesc* P, const double* theta, int64_t N,
                                              const int32_t* cnt, const int32_t* list, double* lnL,
-                                             int p, double* trig) {
+                                             int p, double* trig, double* wtab) {
   const int c = as_const(cnt)[p];
   const int64_t s0 = as_const(P)->s0;
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  if (c <= waves) {
+    const int wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    double* tab = wtab + (threadIdx.x >> 6) * WIDE_TAB(L, KT);
+    for (int e = wv; e < c; e += waves) {
+      const int64_t i = s0 + as_global(list)[s0 + e];
+      const RIFT_GLOBAL double* th = as_global(theta) + i;
+      const double l = eval_wide<KT, L>(opaque(P), th[0], th[N], th[2 * N], th[3 * N], th[4 * N], th[5 * N],
+                                        th[6 * N], tab);
+      if ((threadIdx.x & 63) == 0) as_global_w(lnL)[i] = l;
+    }
+    return;
+  }
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c; e += gridDim.x * blockDim.x) {
     const int64_t i = s0 + as_global(list)[s0 + e];
     const RIFT_GLOBAL double* th = as_global(theta) + i;
@@ -154,14 +296,15 @@ __global__ void __launch_bounds__(256) k_refine(const PointDesc* __restrict__ de
                                                 const int32_t* __restrict__ cnt,
                                                 const int32_t* __restrict__ list, double* lnL) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double wtab[4 * WIDE_TAB(8, KT)];  // per wavefront, for the largest class
   double* trig = reinterpret_cast<double*>(smem) + threadIdx.x;
   const int p = blockIdx.y;
   const PointDesc* P = descs + p;
   const int L = __builtin_amdgcn_readfirstlane(as_const(P)->L);
-  if ((LSET & 1) && L == 2) refine_point<KT, 2>(P, theta, N, cnt, list, lnL, p, trig);
-  else if ((LSET & 2) && L == 3) refine_point<KT, 3>(P, theta, N, cnt, list, lnL, p, trig);
-  else if ((LSET & 4) && L == 4) refine_point<KT, 4>(P, theta, N, cnt, list, lnL, p, trig);
-  else if ((LSET & 8) && L == 8) refine_point<KT, 8>(P, theta, N, cnt, list, lnL, p, trig);
+  if ((LSET & 1) && L == 2) refine_point<KT, 2>(P, theta, N, cnt, list, lnL, p, trig, wtab);
+  else if ((LSET & 2) && L == 3) refine_point<KT, 3>(P, theta, N, cnt, list, lnL, p, trig, wtab);
+  else if ((LSET & 4) && L == 4) refine_point<KT, 4>(P, theta, N, cnt, list, lnL, p, trig, wtab);
+  else if ((LSET & 8) && L == 8) refine_point<KT, 8>(P, theta, N, cnt, list, lnL, p, trig, wtab);
 }
 
 // Gradient: one lane per sample, grid-stride.

@@ -318,4 +318,9 @@ def test_c2_full_size_sampled(ile, oracle_mod):
             assert abs(z.item() - z_or) <= 1e-9 * max(1, abs(z_or))
         else:
             assert abs(z.item() - z_or) <= 1e-3
+            # the few refined samples (a wavefront each) carry FP64 values
+            assert 1 <= plan.refined() <= 64
+            top = np.argsort(l_or_all)[-plan.refined():]
+            S_top = lnL_scale(oracle_mod, pt, th[:, top])
+            assert np.all(np.abs(ll[top] - l_or_all[top]) <= 1e-9 * S_top + 1e-12)
         plan.close()
