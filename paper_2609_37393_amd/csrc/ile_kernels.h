@@ -18,7 +18,7 @@ struct TileArgs {
   const Tile* tiles;
   int32_t n_tiles;
   int32_t persistent;
-  int32_t* counter;
+  int32_t* counter;  // [0]: next tile, [1]: finished blocks (persistent form; both 0 at launch)
   const double* theta;  // [7][N]
   const double* lnw;    // [N] or null
   int64_t N;
@@ -26,6 +26,7 @@ struct TileArgs {
   float* bnd;           // [N] (pass32)
   double* part;         // [n_tiles][2]: (max, sum) (lse64)
   double* tmax;         // [n_tiles]: max(lnL + lnw - bound) (pass32)
+  int32_t* cnt;         // [n_points]: refine-list lengths, zeroed here (pass32)
   // sorted mode: samples read from the records theta_aos[pos][8] (ra, dec,
   // psi, incl, phiref, tref, dist, int64 bits whose upper 48 hold the sample
   // index) and results
@@ -47,6 +48,8 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
   acc.s = 0.0;
   double tm = -__builtin_inf();
   const int64_t N = a.N;
+  // the point's refine list starts empty for the selection that follows
+  if (MODE == MODE_PASS32 && threadIdx.x == 0 && t.s == as_const(P)->s0) a.cnt[t.p] = 0;
   if (a.theta_aos) {
     const RIFT_GLOBAL double* aos = as_global(a.theta_aos);
     for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
@@ -129,6 +132,15 @@ __global__ void __launch_bounds__(512) k_tiles(TileArgs a) {
     if (t >= a.n_tiles) break;
     dispatch_tile<R, KT, LSET, MODE>(a, t, sh, shd, trig);
     if (!a.persistent) break;
+  }
+  // persistent form: the last block to finish leaves the queue at 0 for the
+  // next launch (every other block has taken its last tile by then)
+  if (a.persistent && threadIdx.x == 0) {
+    const int done = atomicAdd(a.counter + 1, 1);
+    if (done == (int)gridDim.x - 1) {
+      atomicExch(a.counter, 0);
+      atomicExch(a.counter + 1, 0);
+    }
   }
 }
 

@@ -9,8 +9,8 @@
 //   evaluation (no allocation, no host synchronisation -> graph-capturable):
 //     FP64 : k_tiles<double>  one persistent launch over (point, sample-block)
 //            tiles, per-tile (max, sum exp) partials -> k_merge -> ln Z, n_eff
-//     MIXED: k_tiles<float> (value + a-priori bound) -> k_mlow -> k_select
-//            (samples whose bound reaches within T of the best) -> k_refine
+//     MIXED: k_tiles<float> (value + a-priori bound) -> k_select (M_low, and
+//            the samples whose bound reaches within T of the best) -> k_refine
 //            (FP64 recompute of those) -> k_final (LSE + omitted-error sum)
 //            -> k_merge
 #include <hip/hip_runtime.h>
@@ -189,34 +189,30 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
-// Per point: M_low = max over its tiles of max(lnL32 + lnw - bound).
-__global__ void k_mlow(const PointDesc* __restrict__ descs, const int32_t* __restrict__ trange,
-                       const double* __restrict__ tmax, double* __restrict__ mlow) {
-  const int p = blockIdx.x;
-  double m = -__builtin_inf();
-  for (int t = trange[2 * p] + threadIdx.x; t < trange[2 * p + 1]; t += blockDim.x) m = fmax(m, tmax[t]);
-  m = dmax_wave(m);
-  __shared__ double sh[8];
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double r = sh[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
-    mlow[p] = r;
-  }
-}
-
 // Samples that may lie within T of the best go to the point's refine list;
-// their bound is set to -1 to mark them.
+// their bound is set to -1 to mark them.  Each block first reduces its
+// point's M_low = max over the point's tiles of max(lnL32 + lnw - bound)
+// (fixed order); the block of the point's first tile stores it for the
+// kernels that follow.
 __global__ void k_select(const PointDesc* __restrict__ descs, const Tile* __restrict__ tiles,
-                         int n_tiles, const double* __restrict__ lnL, const double* __restrict__ lnw,
-                         float* __restrict__ bnd, const double* __restrict__ mlow,
-                         int32_t* __restrict__ cnt, int32_t* __restrict__ list) {
+                         int n_tiles, const int32_t* __restrict__ trange, const double* __restrict__ tmax,
+                         const double* __restrict__ lnL, const double* __restrict__ lnw,
+                         float* __restrict__ bnd, double* __restrict__ mlow, int32_t* __restrict__ cnt,
+                         int32_t* __restrict__ list) {
+  __shared__ double sh[8];
   const int tidx = blockIdx.x;
   if (tidx >= n_tiles) return;
   const Tile t = tiles[tidx];
   const PointDesc* P = descs + t.p;
-  const double thr = mlow[t.p] - P->T;
+  double m = -__builtin_inf();
+  for (int u = trange[2 * t.p] + threadIdx.x; u < trange[2 * t.p + 1]; u += blockDim.x) m = fmax(m, tmax[u]);
+  m = dmax_wave(m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
+  if (threadIdx.x == 0 && tidx == trange[2 * t.p]) mlow[t.p] = m;
+  const double thr = m - P->T;
   for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
     const int64_t i = t.s + o;
     const double v = lnL[i] + (lnw ? lnw[i] : 0.0) + (double)bnd[i];
@@ -950,16 +946,14 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.bnd = p->d_bnd;
   a.part = p->d_part;
   a.tmax = p->d_tmax;
+  a.cnt = p->d_cnt;
   a.theta_aos = p->cfg.sort ? p->d_aos : nullptr;
   const size_t rsz = (mode == MODE_LSE64 ? sizeof(double) : sizeof(float));
   const size_t trig_bytes = (p->lset & 8) ? (size_t)trig_rows(p->lset) * p->cfg.block * rsz : 0;
   tile_fn f = pick_tiles_kt(mode == MODE_LSE64, p->KT, p->lset);
   if (!f) return RIFT_EUNSUPPORTED;
   int grid = p->n_tiles;
-  if (a.persistent) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, p->d_counter, 1, 0);
-    grid = std::min(p->n_tiles, p->cfg.blocks_per_cu * p->di.n_cu);
-  }
+  if (a.persistent) grid = std::min(p->n_tiles, p->cfg.blocks_per_cu * p->di.n_cu);
   if (grid <= 0) return RIFT_OK;
   const size_t shm = trig_bytes;  // per-lane scratch column, l <= 8 class only
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1322,6 +1316,7 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
   PHIP(hipMemcpy(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice));
   PCHK(palloc(p, sizeof(int32_t) * 64, &v));
   p->d_counter = (int32_t*)v;
+  PHIP(hipMemset(p->d_counter, 0, sizeof(int32_t) * 64));  // the kernel leaves it at 0 after each launch
   // samples are addressed by int32 positions in the binned order
   if (N > 0x7fffffff) p->cfg.sort = 0;
   if (p->cfg.sort) PCHK(ensure_bin_buffers(p));
@@ -1390,17 +1385,13 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
   if (sorted)
     hipLaunchKernelGGL(k_tmax_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                        lnw, (const float*)p->d_bnd, p->d_tmax);
-  hipLaunchKernelGGL(k_mlow, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_tmax,
-                     p->d_mlow);
-  hipLaunchKernelGGL(k_fill_i32, dim3((p->n_points + 255) / 256), dim3(256), 0, st, p->d_cnt,
-                     p->n_points, 0);
   hipLaunchKernelGGL(k_select, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_desc, p->d_tiles,
-                     p->n_tiles, (const double*)L, lnw, p->d_bnd, (const double*)p->d_mlow, p->d_cnt,
-                     p->d_list);
+                     p->n_tiles, (const int32_t*)p->d_trange, (const double*)p->d_tmax, (const double*)L, lnw,
+                     p->d_bnd, p->d_mlow, p->d_cnt, p->d_list);
   refine_fn rf = pick_refine_kt(p->KT, p->lset);
   if (!rf) return RIFT_EUNSUPPORTED;
   hipLaunchKernelGGL(rf, dim3(p->refine_blocks, p->n_points), dim3(256),
-                     (size_t)trig_rows(p->lset) * 256 * sizeof(double), st, p->d_desc, theta, p->N,
+                     (p->lset & 8) ? (size_t)trig_rows(p->lset) * 256 * sizeof(double) : 0, st, p->d_desc, theta, p->N,
                      (const int32_t*)p->d_cnt, (const int32_t*)p->d_list, L);
   hipLaunchKernelGGL(k_final, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                      lnw, (const float*)p->d_bnd, (const double*)p->d_mlow, p->d_part, p->d_terr);
