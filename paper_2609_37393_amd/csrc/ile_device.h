@@ -388,11 +388,25 @@ __device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb
     for (int g = 0; g < G; ++g) {
       const RIFT_GLOBAL char* ser =
           uniform_ptr(Qb + (uint64_t)((K0 + g) * M + i) * sstride) + boff[K0 + g];
+      if constexpr (sizeof(R) == 8) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const R2 v = *(const RIFT_GLOBAL R2*)(ser + j * sizeof(R2));
-        buf[g][j].x = v.x;
-        buf[g][j].y = v.y;
+        for (int j = 0; j < 4; ++j) {
+          const R2 v = *(const RIFT_GLOBAL R2*)(ser + j * sizeof(R2));
+          buf[g][j].x = v.x;
+          buf[g][j].y = v.y;
+        }
+      } else {
+        // FP32: two 16-byte reads of two taps each (8-byte aligned; global
+        // reads need only dword alignment), half the read instructions
+        typedef float F4 __attribute__((ext_vector_type(4), aligned(8)));
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const F4 v = *(const RIFT_GLOBAL F4*)(ser + 2 * j * sizeof(R2));
+          buf[g][2 * j].x = v.x;
+          buf[g][2 * j].y = v.y;
+          buf[g][2 * j + 1].x = v.z;
+          buf[g][2 * j + 1].y = v.w;
+        }
       }
     }
   };
