@@ -157,7 +157,10 @@ int rift_ile_plan_grad(rift_ile_plan plan, int32_t point, int64_t n, const doubl
 int rift_ile_plan_tune(rift_ile_plan plan, const double *theta, const double *lnw, void *stream);
 
 /* Launch shape of the plan: threads per block, samples per tile, persistent
- * blocks per CU.  Setting validates on the host. */
+ * blocks per CU.  Setting validates on the host: RIFT_EINVAL for values out of
+ * range, RIFT_EUNSUPPORTED for a block whose likelihood kernel would need more
+ * LDS than one block may hold (16 KiB per wavefront for the data term's read
+ * staging, plus a per-lane column for the l <= 8 class). */
 typedef struct {
   int32_t block;         /* 64, 128, 256, 512 */
   int32_t tile_blocks;   /* samples per tile = block * tile_blocks */

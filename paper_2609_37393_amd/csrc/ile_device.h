@@ -36,6 +36,17 @@ constexpr int KMAX = 8;    // detectors
 constexpr int MMAX = 25;   // modes
 constexpr int LMAXC = 8;   // largest l
 constexpr int QPAD = 4;    // zero rows on each side of every Q series
+// Q tables hold W consecutive (internal) modes per time row, W = 2 for FP64
+// and 4 for FP32: a row is 32 bytes in both, and a four-row stencil of one
+// mode group is 128 bytes.
+constexpr int QW64 = 2;
+constexpr int QW32 = 4;
+__host__ __device__ constexpr int q_groups(int M, int W) { return (M + W - 1) / W; }
+// LDS staging of the data term: one unit is the 128-byte stencil block of a
+// (mode group, detector) pair for each of the 64 lanes of a wavefront; every
+// wavefront owns two unit buffers.
+constexpr int STAGE_UNIT = 64 * 128;
+constexpr int STAGE_WAVE = 2 * STAGE_UNIT;
 
 template <class R>
 struct alignas(2 * sizeof(R)) C2 {
@@ -79,9 +90,10 @@ struct PointDesc {
   int32_t bin_st0;
   int32_t bin_pad;
   int64_t bin_mbase;
-  // Q series of each (detector, mode), time-contiguous with QPAD zero rows at
-  // both ends: [KT][M][n_t + 2 QPAD] complex.  A stencil starting at row
-  // j-1 in [-QPAD, n_t] reads padded rows j-1+QPAD .. j+2+QPAD.
+  // Q of each detector in groups of W internal modes, QPAD zero rows at both
+  // ends of every series: [KT][ceil(M / W)][n_t + 2 QPAD][W] complex, the
+  // slots past M zero.  A stencil starting at row j-1 in [-QPAD, n_t] reads
+  // padded rows j-1+QPAD .. j+2+QPAD.
   const double* Q64;
   const float* Q32;
   const double* C64;      // [B][3 KT]
@@ -115,6 +127,7 @@ __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfi
 // space (vector loads).
 #define RIFT_CONST __attribute__((address_space(4)))
 #define RIFT_GLOBAL __attribute__((address_space(1)))
+#define RIFT_LDS __attribute__((address_space(3)))
 
 struct PointDesc;
 typedef const RIFT_CONST PointDesc* PDesc;
@@ -177,6 +190,7 @@ template <class R>
 struct Tab;
 template <>
 struct Tab<double> {
+  static constexpr int W = QW64;
   static __device__ __forceinline__ const RIFT_GLOBAL double* Q(PDesc P) { return as_global(P->Q64); }
   static __device__ __forceinline__ const RIFT_CONST double* C(PDesc P) { return as_const(P->C64); }
   static __device__ __forceinline__ double y(PDesc P, int i, int n) { return P->ycoef[i][n]; }
@@ -184,6 +198,7 @@ struct Tab<double> {
 };
 template <>
 struct Tab<float> {
+  static constexpr int W = QW32;
   static __device__ __forceinline__ const RIFT_GLOBAL float* Q(PDesc P) { return as_global(P->Q32); }
   static __device__ __forceinline__ const RIFT_CONST float* C(PDesc P) { return as_const(P->C32); }
   static __device__ __forceinline__ float y(PDesc P, int i, int n) { return P->ycoef32[i][n]; }
@@ -354,22 +369,58 @@ __device__ __forceinline__ void lagrange4(R s, R* w) {
   w[3] = (s + 1) * s * (s - 1) * (R)(1.0 / 6.0);
 }
 
-// Data term of detectors K0 .. K0+G-1 (G <= 3):
+// Detector groups of the data term (KT >= 2): at most three detectors share
+// a pass over the modes; a remainder of one is split as 2 + 2, so every group
+// has two or three detectors.
+__host__ __device__ constexpr int det_group_size(int KT, int j) {
+  int n3 = KT / 3, r = KT % 3;
+  if (r == 1) {
+    n3 -= 1;
+    r = 4;
+  }
+  if (j < n3) return 3;
+  const int jj = j - n3;
+  if (r == 2) return jj == 0 ? 2 : 0;
+  if (r == 4) return jj < 2 ? 2 : 0;
+  return 0;
+}
+__host__ __device__ constexpr int det_group_start(int KT, int j) {
+  int s = 0;
+  for (int t = 0; t < j; ++t) s += det_group_size(KT, t);
+  return s;
+}
+
+// Data term of detectors K0 .. K0+G-1 (2 <= G <= 3):
 //   sum_k Re[conj(F_k) sum_i conj(Y_i) Qhat_{k,i}]
 //   = sum_k Fre_k Re(Z_k) + Fim_k Im(Z_k),  Z_k = sum_i conj(Y_i) Qhat_{k,i},
 // with Y_i = d_i(incl) e^{i m_i phi} (modes sorted by m, so the phase walks
 // upward from e^{i m_min phi}) and Qhat the four-point Lagrange read at
 // fraction sfr_k of the cell that starts at byte offset boff_k.
-// The taps of mode i+1 (all G detectors) are in flight while mode i is
-// combined, so a sample waits about one memory round trip per mode.  Series
-// (k, i) starts at a uniform address; a lane's four taps are contiguous at a
-// 32-bit offset from it.
+//
+// The table holds W modes per time row, so the four stencil rows of a mode
+// group are one contiguous 128-byte block per lane, at a 32-bit offset from
+// the uniform start of series (k, group).  The blocks are read cooperatively:
+// eight lanes fetch the eight 16-byte chunks of one lane's block, so a read
+// instruction touches about 8 blocks' cache lines instead of 64 (the vector
+// memory path costs about one cycle per distinct line per instruction).  The
+// reads go straight to LDS (global_load_lds): lane l = 8 q + c' of read t
+// fetches chunk c = c' ^ q of the block of lane j = 8 t + q, which lands at
+// j * 128 + c' * 16 = j * 128 + (c ^ (j & 7)) * 16, so that lane j's own
+// 16-byte reads of its eight chunks are free of bank conflicts.
+//
+// Units (group p, detector g) are streamed with g fastest through the
+// wavefront's two LDS buffers: unit u+1 is in flight while unit u is
+// combined.  Requires the whole wavefront to be active.
 template <class R, int NY, int K0, int G>
-__device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb, uint64_t sstride,
-                                             int M, const uint32_t* boff, const R* sfr,
-                                             const R* Fre, const R* Fim, const R* cn, const R* sn,
-                                             R cf, R sf) {
+__device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb, uint64_t gstride,
+                                             uint64_t kstride, int M, int NGR, const uint32_t* boff,
+                                             RIFT_LDS unsigned char* stage, const R* sfr, const R* Fre,
+                                             const R* Fim, const R* cn, const R* sn, R cf, R sf) {
+  static_assert(G >= 2 && G <= 3, "detector groups of two or three");
+  constexpr int W = Tab<R>::W;
+  static_assert(4 * W * sizeof(C2<R>) == 128, "128-byte stencil blocks");
   typedef R R2 __attribute__((ext_vector_type(2)));
+  typedef float F4 __attribute__((ext_vector_type(4)));
   R w[G][4];
 #pragma unroll
   for (int g = 0; g < G; ++g) lagrange4(sfr[K0 + g], w[g]);
@@ -382,81 +433,96 @@ __device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb
   const int mmin = P->m_min;
   for (int t = 0; t < -mmin; ++t) phase_down(ph, cf, sf);
   int mc = mmin < 0 ? mmin : 0;
-  // issue the 4 G tap loads of mode i into buf
-  auto load = [&](C2<R>(&buf)[G][4], int i) {
+  // Y of the W modes of group p; the slots past M repeat mode M-1 (their
+  // taps are zero, so they add exact zeros)
+  R yx[W], yy[W];
+  auto ycomp = [&](int p) {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const RIFT_GLOBAL char* ser =
-          uniform_ptr(Qb + (uint64_t)((K0 + g) * M + i) * sstride) + boff[K0 + g];
+    for (int s = 0; s < W; ++s) {
+      const int i = p * W + s;
+      const int ic = i < M ? i : M - 1;
+      const int mi = P->m[ic];
+      while (mc < mi) {
+        phase_up(ph, cf, sf);
+        ++mc;
+      }
+      const R d = mode_d<R, NY>(P, ic, cn, sn);
+      yx[s] = d * ph.x;
+      yy[s] = d * ph.y;
+    }
+  };
+  const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+  const int q = lane >> 3;
+  const uint32_t cx = (uint32_t)((lane & 7) ^ q) << 4;
+  // read t of detector g: this lane's source offset
+  uint32_t offt[G][8];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) offt[g][t] = (uint32_t)__shfl((int)boff[K0 + g], 8 * t + q) + cx;
+  // chunk c of this lane's block: rbase ^ (c << 4)
+  const uint32_t rbase = (uint32_t)lane * 128u + ((uint32_t)(lane & 7) << 4);
+  auto issue = [&](int p, int g, int b) {
+    const RIFT_GLOBAL char* ser = uniform_ptr(Qb + (uint64_t)(K0 + g) * kstride + (uint64_t)p * gstride);
+    RIFT_LDS unsigned char* dst = stage + b * STAGE_UNIT;
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      __builtin_amdgcn_global_load_lds((const RIFT_GLOBAL void*)(ser + offt[g][t]), (RIFT_LDS void*)(dst + t * 1024),
+                                       16, 0, 0);
+  };
+  auto consume = [&](int b, int g) {
+    const RIFT_LDS unsigned char* src = stage + b * STAGE_UNIT;
+    C2<R> u[4][W];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint32_t a = rbase ^ ((uint32_t)c << 4);
       if constexpr (sizeof(R) == 8) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const R2 v = *(const RIFT_GLOBAL R2*)(ser + j * sizeof(R2));
-          buf[g][j].x = v.x;
-          buf[g][j].y = v.y;
-        }
+        const R2 v = *(const RIFT_LDS R2*)(src + a);
+        u[c >> 1][c & 1].x = v.x;
+        u[c >> 1][c & 1].y = v.y;
       } else {
-        // FP32: two 16-byte reads of two taps each (8-byte aligned; global
-        // reads need only dword alignment), half the read instructions
-        typedef float F4 __attribute__((ext_vector_type(4), aligned(8)));
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const F4 v = *(const RIFT_GLOBAL F4*)(ser + 2 * j * sizeof(R2));
-          buf[g][2 * j].x = v.x;
-          buf[g][2 * j].y = v.y;
-          buf[g][2 * j + 1].x = v.z;
-          buf[g][2 * j + 1].y = v.w;
-        }
+        const F4 v = *(const RIFT_LDS F4*)(src + a);
+        u[c >> 1][2 * (c & 1)].x = v.x;
+        u[c >> 1][2 * (c & 1)].y = v.y;
+        u[c >> 1][2 * (c & 1) + 1].x = v.z;
+        u[c >> 1][2 * (c & 1) + 1].y = v.w;
       }
     }
-  };
-  // combine mode i (taps in buf) into Z
-  auto step = [&](const C2<R>(&buf)[G][4], int i) {
-    const int mi = P->m[i];
-    while (mc < mi) {
-      phase_up(ph, cf, sf);
-      ++mc;
-    }
-    const R d = mode_d<R, NY>(P, i, cn, sn);
-    const R yx = d * ph.x, yy = d * ph.y;
 #pragma unroll
-    for (int g = 0; g < G; ++g) mode_acc(Z[g], w[g], buf[g][0], buf[g][1], buf[g][2], buf[g][3], yx, yy);
-    // the accumulators are final for this mode here: keeps the FMAs of this
-    // step ahead of the next load batch (instead of sinking them past it,
-    // which would keep both tap buffers and the new batch live)
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      pin(Z[g].x);
-      pin(Z[g].y);
-    }
+    for (int s = 0; s < W; ++s) mode_acc(Z[g], w[g], u[0][s], u[1][s], u[2][s], u[3][s], yx[s], yy[s]);
+    // the unit is combined here, before the next refill is issued (instead
+    // of its FMAs sinking past later units, keeping their reads live)
+    pin(Z[g].x);
+    pin(Z[g].y);
   };
-  // Two tap buffers in turn, so that no register copy waits on a load.  Every
-  // load issued is consumed before the group ends (no loads left in flight
-  // into the next group or sample), and the loop body has the same loads on
-  // every path.  The scheduling barriers keep each load batch in its place.
-  C2<R> ta[G][4], tb[G][4];
-  load(ta, 0);
-  int i = 0;
+  // Unit u = p G + g uses buffer u & 1; an iteration covers an even number of
+  // units, so every buffer index is a constant.  Each buffer is refilled only
+  // after the LDS reads of its previous unit have completed, and a unit is
+  // read only after its own global reads have (the newer unit's eight reads
+  // may still be in flight).
+  constexpr int UPI = (G % 2 == 0) ? G : 2 * G;
+  const int total = NGR * G;
+  issue(0, 0, 0);
 #pragma unroll 1
-  for (; i + 2 < M; i += 2) {
-    load(tb, i + 1);
-    __builtin_amdgcn_sched_barrier(0);
-    step(ta, i);
-    __builtin_amdgcn_sched_barrier(0);
-    load(ta, i + 2);
-    __builtin_amdgcn_sched_barrier(0);
-    step(tb, i + 1);
-    __builtin_amdgcn_sched_barrier(0);
+  for (int p0 = 0; p0 < NGR; p0 += UPI / G) {
+#pragma unroll
+    for (int v = 0; v < UPI; ++v) {
+      const int p = p0 + v / G;
+      const int g = v % G;
+      if (g == 0 && p >= NGR) break;
+      if (p * G + g + 1 < total) {
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        issue(g + 1 == G ? p + 1 : p, (g + 1) % G, (v + 1) & 1);
+        if (g == 0) ycomp(p);
+        asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+      } else {
+        if (g == 0) ycomp(p);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      }
+      consume(v & 1, g);
+    }
   }
-  // one or two modes left; ta holds mode i
-  if (i + 1 < M) {
-    load(tb, i + 1);
-    __builtin_amdgcn_sched_barrier(0);
-    step(ta, i);
-    step(tb, i + 1);
-  } else {
-    step(ta, i);
-  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   double acc = 0.0;
 #pragma unroll
   for (int g = 0; g < G; ++g)
@@ -472,22 +538,29 @@ struct Eval {
 
 // Data term of one sample with its taps read straight from the table.
 template <class R, int KT, int L>
-__device__ __forceinline__ double data_direct(PDesc P, const int32_t* row, const R* sfr, const R* Fre,
-                                              const R* Fim, const R* cn, const R* sn, R cf, R sf) {
+__device__ __forceinline__ double data_direct(PDesc P, RIFT_LDS unsigned char* stage, const int32_t* row,
+                                              const R* sfr, const R* Fre, const R* Fim, const R* cn,
+                                              const R* sn, R cf, R sf) {
+  static_assert(KT >= 2, "detector counts are padded to at least two");
   constexpr int NY = Cls<L>::NY;
+  constexpr int W = Tab<R>::W;
   const int M = P->M;
+  const int NGR = q_groups(M, W);
   uint32_t boff[KT];
 #pragma unroll
-  for (int k = 0; k < KT; ++k) boff[k] = (uint32_t)row[k] * (uint32_t)sizeof(C2<R>);
+  for (int k = 0; k < KT; ++k) boff[k] = (uint32_t)row[k] * (uint32_t)(W * sizeof(C2<R>));
   const RIFT_GLOBAL char* Qb = (const RIFT_GLOBAL char*)Tab<R>::Q(P);
-  const uint64_t sstride = (uint64_t)(P->n_t + 2 * QPAD) * sizeof(C2<R>);
-  double data = data_group<R, NY, 0, (KT < 3 ? KT : 3)>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn, sn,
-                                                         cf, sf);
-  if constexpr (KT > 3)
-    data += data_group<R, NY, 3, (KT - 3 < 3 ? KT - 3 : 3)>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn,
-                                                            sn, cf, sf);
-  if constexpr (KT > 6)
-    data += data_group<R, NY, 6, KT - 6>(P, Qb, sstride, M, boff, sfr, Fre, Fim, cn, sn, cf, sf);
+  const uint64_t gstride = (uint64_t)(P->n_t + 2 * QPAD) * (W * sizeof(C2<R>));
+  const uint64_t kstride = (uint64_t)NGR * gstride;
+  constexpr int G0 = det_group_size(KT, 0), G1 = det_group_size(KT, 1), G2 = det_group_size(KT, 2);
+  double data =
+      data_group<R, NY, 0, G0>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr, Fre, Fim, cn, sn, cf, sf);
+  if constexpr (G1 > 0)
+    data += data_group<R, NY, det_group_start(KT, 1), G1>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr,
+                                                          Fre, Fim, cn, sn, cf, sf);
+  if constexpr (G2 > 0)
+    data += data_group<R, NY, det_group_start(KT, 2), G2>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr,
+                                                          Fre, Fim, cn, sn, cf, sf);
   return data;
 }
 
@@ -680,14 +753,16 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
   return e;
 }
 
+// `stage` is this wavefront's STAGE_WAVE bytes of LDS; the whole wavefront
+// must call this together.
 template <class R, int KT, int L, bool BOUND>
-__device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int ts, double ra,
-                                            double dec, double psi, double incl, double phi,
-                                            double tref, double dist) {
+__device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int ts,
+                                            RIFT_LDS unsigned char* stage, double ra, double dec, double psi,
+                                            double incl, double phi, double tref, double dist) {
   return eval_sample_with<R, KT, L, BOUND>(
       P, trig, ts, ra, dec, psi, incl, phi, tref, dist,
       [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
-          R sf) { return data_direct<R, KT, L>(P, row, sfr, Fre, Fim, cn, sn, cf, sf); });
+          R sf) { return data_direct<R, KT, L>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf); });
 }
 
 // ---------------------------------------------------------------------------

@@ -78,6 +78,7 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
   double w[KT][4], wd[KT][4];
   int soff[KT];
   const int ntp = n_t + 2 * QPAD;
+  const int NGR = q_groups(M, QW64);
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
@@ -169,9 +170,9 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
       const double mv = (double)mi;
 #pragma unroll
       for (int k = 0; k < KT; ++k) {
-        const RIFT_GLOBAL double* ser = Qt + (int64_t)(k * M + i) * ntp * 2;
-        const C2<double> q0 = ldq(ser, soff[k]), q1 = ldq(ser, soff[k] + 1);
-        const C2<double> q2 = ldq(ser, soff[k] + 2), q3 = ldq(ser, soff[k] + 3);
+        const RIFT_GLOBAL double* ser = Qt + 2 * ((int64_t)(k * NGR + i / QW64) * ntp * QW64 + i % QW64);
+        const C2<double> q0 = ldq(ser, soff[k] * QW64), q1 = ldq(ser, (soff[k] + 1) * QW64);
+        const C2<double> q2 = ldq(ser, (soff[k] + 2) * QW64), q3 = ldq(ser, (soff[k] + 3) * QW64);
         const double qx = w[k][0] * q0.x + w[k][1] * q1.x + w[k][2] * q2.x + w[k][3] * q3.x;
         const double qy = w[k][0] * q0.y + w[k][1] * q1.y + w[k][2] * q2.y + w[k][3] * q3.y;
         const double tx = wd[k][0] * q0.x + wd[k][1] * q1.x + wd[k][2] * q2.x + wd[k][3] * q3.x;

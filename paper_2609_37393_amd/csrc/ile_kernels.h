@@ -36,8 +36,11 @@ struct TileArgs {
 };
 
 // One tile: every sample's lnL (and bound), then a block reduction.
+// The sample loops run whole wavefronts (the data term reads cooperatively):
+// lanes past the end of the tile evaluate its last sample and drop the result.
 template <class R, int KT, int L, int MODE>
-__device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, double* shd, R* trig) {
+__device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, double* shd, R* trig,
+                                         RIFT_LDS unsigned char* stage) {
   const Tile t = a.tiles[tidx];
   const PointDesc* P = a.descs + __builtin_amdgcn_readfirstlane(t.p);
   const RIFT_GLOBAL double* theta = as_global(a.theta);
@@ -50,25 +53,34 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
   const int64_t N = a.N;
   // the point's refine list starts empty for the selection that follows
   if (MODE == MODE_PASS32 && threadIdx.x == 0 && t.s == as_const(P)->s0) a.cnt[t.p] = 0;
+  const int wbase = (int)(threadIdx.x & ~63u);
+  const int lane = (int)threadIdx.x - wbase;
   if (a.theta_aos) {
     const RIFT_GLOBAL double* aos = as_global(a.theta_aos);
-    for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
-      const int64_t pos = t.s + o;
+    for (int ob = wbase; ob < t.cnt; ob += blockDim.x) {
+      const int o = ob + lane;
+      const bool live = o < t.cnt;
+      const int64_t pos = t.s + (live ? o : t.cnt - 1);
       const RIFT_GLOBAL double* th = aos + 8 * pos;
-      const Eval e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, th[0], th[1],
-                                                                th[2], th[3], th[4], th[5], th[6]);
+      const Eval e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0],
+                                                                th[1], th[2], th[3], th[4], th[5], th[6]);
       const int64_t i = (int64_t)__double_as_longlong(th[7]) >> 16;
-      lnL[i] = e.lnL;
-      if (MODE == MODE_PASS32) as_global_w(a.bnd)[i] = e.bound;
+      if (live) {
+        lnL[i] = e.lnL;
+        if (MODE == MODE_PASS32) as_global_w(a.bnd)[i] = e.bound;
+      }
     }
     return;
   }
-  for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
-    const int64_t i = t.s + o;
+  for (int ob = wbase; ob < t.cnt; ob += blockDim.x) {
+    const int o = ob + lane;
+    const bool live = o < t.cnt;
+    const int64_t i = t.s + (live ? o : t.cnt - 1);
     const RIFT_GLOBAL double* th = theta + i;
-    const Eval e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, th[0], th[N],
-                                                              th[2 * N], th[3 * N], th[4 * N], th[5 * N],
-                                                              th[6 * N]);
+    const Eval e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0],
+                                                              th[N], th[2 * N], th[3 * N], th[4 * N],
+                                                              th[5 * N], th[6 * N]);
+    if (!live) continue;
     const double w = lnw ? lnw[i] : 0.0;
     if (lnL) lnL[i] = e.lnL;
     if (MODE == MODE_LSE64) {
@@ -100,12 +112,13 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
 
 // Class sets compiled into one kernel (bit 0: L=2, 1: L=3, 2: L=4, 3: L=8).
 template <class R, int KT, int LSET, int MODE>
-__device__ __forceinline__ void dispatch_tile(const TileArgs& a, int tidx, MS* sh, double* shd, R* trig) {
+__device__ __forceinline__ void dispatch_tile(const TileArgs& a, int tidx, MS* sh, double* shd, R* trig,
+                                              RIFT_LDS unsigned char* stage) {
   const int L = __builtin_amdgcn_readfirstlane(as_const(a.descs)[as_const(a.tiles)[tidx].p].L);
-  if ((LSET & 1) && L == 2) run_tile<R, KT, 2, MODE>(a, tidx, sh, shd, trig);
-  else if ((LSET & 2) && L == 3) run_tile<R, KT, 3, MODE>(a, tidx, sh, shd, trig);
-  else if ((LSET & 4) && L == 4) run_tile<R, KT, 4, MODE>(a, tidx, sh, shd, trig);
-  else if ((LSET & 8) && L == 8) run_tile<R, KT, 8, MODE>(a, tidx, sh, shd, trig);
+  if ((LSET & 1) && L == 2) run_tile<R, KT, 2, MODE>(a, tidx, sh, shd, trig, stage);
+  else if ((LSET & 2) && L == 3) run_tile<R, KT, 3, MODE>(a, tidx, sh, shd, trig, stage);
+  else if ((LSET & 4) && L == 4) run_tile<R, KT, 4, MODE>(a, tidx, sh, shd, trig, stage);
+  else if ((LSET & 8) && L == 8) run_tile<R, KT, 8, MODE>(a, tidx, sh, shd, trig, stage);
 }
 
 // Per-lane scratch column for cos/sin(n incl), n <= 2 L: 2 (2 L + 1) values.
@@ -117,8 +130,11 @@ __global__ void __launch_bounds__(512) k_tiles(TileArgs a) {
   __shared__ MS sh[8];
   __shared__ double shd[8];
   __shared__ int s_t;
+  // dynamic LDS: the wavefronts' staging buffers, then (l <= 8 class) the
+  // per-lane trig columns
   extern __shared__ __align__(16) unsigned char smem[];
-  R* trig = reinterpret_cast<R*>(smem) + threadIdx.x;
+  RIFT_LDS unsigned char* stage = (RIFT_LDS unsigned char*)smem + (threadIdx.x >> 6) * STAGE_WAVE;
+  R* trig = reinterpret_cast<R*>(smem + (blockDim.x >> 6) * STAGE_WAVE) + threadIdx.x;
   // one code path for both launch forms: the non-persistent form runs the
   // body once with its block index as the tile
   int t = blockIdx.x;
@@ -130,7 +146,7 @@ __global__ void __launch_bounds__(512) k_tiles(TileArgs a) {
       t = s_t;
     }
     if (t >= a.n_tiles) break;
-    dispatch_tile<R, KT, LSET, MODE>(a, t, sh, shd, trig);
+    dispatch_tile<R, KT, LSET, MODE>(a, t, sh, shd, trig, stage);
     if (!a.persistent) break;
   }
   // persistent form: the last block to finish leaves the queue at 0 for the
@@ -220,18 +236,20 @@ __device__ __forceinline__ double eval_wide(PDesc P, double ra, double dec, doub
   // data term: pairs (k, i)
   const RIFT_GLOBAL double* Q = as_global(P->Q64);
   const int64_t ntp = n_t + 2 * QPAD;
+  const int NGR = q_groups(M, QW64);
   double data = 0.0;
   for (int pr = lane; pr < K * M; pr += 64) {
     const int k = pr / M, i = pr % M;
     const double* dk = det + 8 * k;
     double w[4];
     lagrange4(dk[6], w);
-    const RIFT_GLOBAL double* q = Q + 2 * (((int64_t)k * M + i) * ntp + (int64_t)dk[5]);
+    const RIFT_GLOBAL double* q =
+        Q + 2 * ((((int64_t)k * NGR + i / QW64) * ntp + (int64_t)dk[5]) * QW64 + i % QW64);
     double qx = 0.0, qy = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      qx += w[j] * q[2 * j];
-      qy += w[j] * q[2 * j + 1];
+      qx += w[j] * q[2 * QW64 * j];
+      qy += w[j] * q[2 * QW64 * j + 1];
     }
     // Y_i = d_i(incl) e^{i m_i phi}
     const int m = P->m[i];
@@ -277,7 +295,7 @@ __device__ __forceinline__ double eval_wide(PDesc P, double ra, double dec, doub
 template <int KT, int L>
 __device__ __forceinline__ void refine_point(const PointDesc* P, const double* theta, int64_t N,
                                              const int32_t* cnt, const int32_t* list, double* lnL,
-                                             int p, double* trig, double* wtab) {
+                                             int p, double* trig, double* wtab, RIFT_LDS unsigned char* stage) {
   const int c = as_const(cnt)[p];
   const int64_t s0 = as_const(P)->s0;
   const int waves = gridDim.x * (blockDim.x >> 6);
@@ -293,12 +311,15 @@ __device__ __forceinline__ void refine_point(const PointDesc* P, const double* t
     }
     return;
   }
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < c; e += gridDim.x * blockDim.x) {
+  // whole wavefronts (cooperative reads): lanes past the end repeat the last entry
+  const int lane = (int)(threadIdx.x & 63u);
+  for (int eb = blockIdx.x * blockDim.x + (int)(threadIdx.x & ~63u); eb < c; eb += gridDim.x * blockDim.x) {
+    const int e = eb + lane < c ? eb + lane : c - 1;
     const int64_t i = s0 + as_global(list)[s0 + e];
     const RIFT_GLOBAL double* th = as_global(theta) + i;
-    const Eval r = eval_sample<double, KT, L, false>(opaque(P), trig, blockDim.x, th[0], th[N], th[2 * N],
-                                                     th[3 * N], th[4 * N], th[5 * N], th[6 * N]);
-    as_global_w(lnL)[i] = r.lnL;
+    const Eval r = eval_sample<double, KT, L, false>(opaque(P), trig, blockDim.x, stage, th[0], th[N],
+                                                     th[2 * N], th[3 * N], th[4 * N], th[5 * N], th[6 * N]);
+    if (eb + lane < c) as_global_w(lnL)[i] = r.lnL;
   }
 }
 
@@ -307,16 +328,18 @@ __global__ void __launch_bounds__(256) k_refine(const PointDesc* __restrict__ de
                                                 const double* __restrict__ theta, int64_t N,
                                                 const int32_t* __restrict__ cnt,
                                                 const int32_t* __restrict__ list, double* lnL) {
+  // dynamic LDS: staging buffers (4 wavefronts), then the trig columns
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double wtab[4 * WIDE_TAB(8, KT)];  // per wavefront, for the largest class
-  double* trig = reinterpret_cast<double*>(smem) + threadIdx.x;
+  RIFT_LDS unsigned char* stage = (RIFT_LDS unsigned char*)smem + (threadIdx.x >> 6) * STAGE_WAVE;
+  double* trig = reinterpret_cast<double*>(smem + 4 * STAGE_WAVE) + threadIdx.x;
   const int p = blockIdx.y;
   const PointDesc* P = descs + p;
   const int L = __builtin_amdgcn_readfirstlane(as_const(P)->L);
-  if ((LSET & 1) && L == 2) refine_point<KT, 2>(P, theta, N, cnt, list, lnL, p, trig, wtab);
-  else if ((LSET & 2) && L == 3) refine_point<KT, 3>(P, theta, N, cnt, list, lnL, p, trig, wtab);
-  else if ((LSET & 4) && L == 4) refine_point<KT, 4>(P, theta, N, cnt, list, lnL, p, trig, wtab);
-  else if ((LSET & 8) && L == 8) refine_point<KT, 8>(P, theta, N, cnt, list, lnL, p, trig, wtab);
+  if ((LSET & 1) && L == 2) refine_point<KT, 2>(P, theta, N, cnt, list, lnL, p, trig, wtab, stage);
+  else if ((LSET & 2) && L == 3) refine_point<KT, 3>(P, theta, N, cnt, list, lnL, p, trig, wtab, stage);
+  else if ((LSET & 4) && L == 4) refine_point<KT, 4>(P, theta, N, cnt, list, lnL, p, trig, wtab, stage);
+  else if ((LSET & 8) && L == 8) refine_point<KT, 8>(P, theta, N, cnt, list, lnL, p, trig, wtab, stage);
 }
 
 // Gradient: one lane per sample, grid-stride.

@@ -34,39 +34,39 @@ namespace {
 // Setup kernels
 // ---------------------------------------------------------------------------
 
-// Q[k][i][t] (caller order, complex) -> Qt[k][i_internal][QPAD + t], every
-// series padded with QPAD zero rows at both ends; padded detectors all zero.
-__global__ void k_repack(const double* __restrict__ Q, double* __restrict__ Q64,
-                         float* __restrict__ Q32, const int32_t* __restrict__ perm, int K, int KT,
-                         int M, int n_t) {
+// Q[k][i][t] (caller order, complex) -> Qt[k][i_internal / W][QPAD + t][i_internal % W]:
+// W internal modes per padded time row, QPAD zero rows at both ends of every
+// series, zero slots past M and zero padded detectors.
+template <class T>
+__global__ void k_repack(const double* __restrict__ Q, T* __restrict__ Qt,
+                         const int32_t* __restrict__ perm, int K, int KT, int M, int n_t, int W) {
   const int ntp = n_t + 2 * QPAD;
-  const int64_t total = (int64_t)KT * M * ntp;
+  const int ngr = q_groups(M, W);
+  const int64_t total = (int64_t)KT * ngr * ntp * W;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int tp = (int)(e % ntp);
-    const int64_t ki = e / ntp;
-    const int i = (int)(ki % M);
-    const int k = (int)(ki / M);
+    const int sl = (int)(e % W);
+    const int64_t rest = e / W;
+    const int tp = (int)(rest % ntp);
+    const int64_t kg = rest / ntp;
+    const int g = (int)(kg % ngr);
+    const int k = (int)(kg / ngr);
+    const int i = g * W + sl;
     const int t = tp - QPAD;
     double re = 0.0, im = 0.0;
-    if (k < K && t >= 0 && t < n_t) {
+    if (k < K && i < M && t >= 0 && t < n_t) {
       const int64_t src = ((int64_t)k * M + perm[i]) * n_t + t;
       re = Q[2 * src];
       im = Q[2 * src + 1];
     }
-    Q64[2 * e] = re;
-    Q64[2 * e + 1] = im;
-    if (Q32) {
-      Q32[2 * e] = (float)re;
-      Q32[2 * e + 1] = (float)im;
-    }
+    Qt[2 * e] = (T)re;
+    Qt[2 * e + 1] = (T)im;
   }
 }
 
-// out[k] = max |Q64| over detector k's series, one block per detector.
-__global__ void k_qmax(const double* __restrict__ Q64, double* __restrict__ out, int n_t, int M) {
+// out[k] = max |Q64| over detector k's n complex entries, one block per detector.
+__global__ void k_qmax(const double* __restrict__ Q64, double* __restrict__ out, int64_t n) {
   const int k = blockIdx.x;
-  const int64_t n = (int64_t)(n_t + 2 * QPAD) * M;
   const double* q = Q64 + 2 * (int64_t)k * n;
   double m = 0.0;
   for (int64_t e = threadIdx.x; e < n; e += blockDim.x) m = fmax(m, hypot(q[2 * e], q[2 * e + 1]));
@@ -742,11 +742,13 @@ void ylm_fourier(int l, int m, double* out /* [LMAXC+1] */) {
 struct DeviceInfo {
   int dev = -1;
   int n_cu = 0;
+  int max_lds = 0;  // LDS bytes per block
 };
 
 int device_info(DeviceInfo* di) {
   HCHK(hipGetDevice(&di->dev));
   HCHK(hipDeviceGetAttribute(&di->n_cu, hipDeviceAttributeMultiprocessorCount, di->dev));
+  HCHK(hipDeviceGetAttribute(&di->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, di->dev));
   return RIFT_OK;
 }
 
@@ -931,6 +933,13 @@ int validate_config(const rift_ile_config* c) {
   return RIFT_OK;
 }
 
+// Dynamic LDS of the likelihood kernels: each wavefront's staging buffers of
+// the data term, then (l <= 8 class) a trig column per lane.
+size_t eval_lds_bytes(int lset, int block, size_t rsz) {
+  const size_t trig = (lset & 8) ? (size_t)trig_rows(lset) * block * rsz : 0;
+  return (size_t)(block / 64) * STAGE_WAVE + trig;
+}
+
 int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* lnw, double* lnL,
                  hipStream_t st) {
   TileArgs a;
@@ -949,13 +958,13 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.cnt = p->d_cnt;
   a.theta_aos = p->cfg.sort ? p->d_aos : nullptr;
   const size_t rsz = (mode == MODE_LSE64 ? sizeof(double) : sizeof(float));
-  const size_t trig_bytes = (p->lset & 8) ? (size_t)trig_rows(p->lset) * p->cfg.block * rsz : 0;
+  const size_t shm = eval_lds_bytes(p->lset, p->cfg.block, rsz);
+  if (shm + 1024 > (size_t)p->di.max_lds) return RIFT_EUNSUPPORTED;
   tile_fn f = pick_tiles_kt(mode == MODE_LSE64, p->KT, p->lset);
   if (!f) return RIFT_EUNSUPPORTED;
   int grid = p->n_tiles;
   if (a.persistent) grid = std::min(p->n_tiles, p->cfg.blocks_per_cu * p->di.n_cu);
   if (grid <= 0) return RIFT_OK;
-  const size_t shm = trig_bytes;  // per-lane scratch column, l <= 8 class only
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p->profiling) {
     HCHK(hipEventCreate(&e0));
@@ -1189,11 +1198,11 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     }
     D.m_min = D.m[0];
     // device tables
-    const int64_t qn = (int64_t)KT * (pt.n_t + 2 * QPAD) * M;
-    PCHK(palloc(p, sizeof(double) * 2 * qn, &v));
+    const int64_t qrows = (int64_t)KT * (pt.n_t + 2 * QPAD);
+    PCHK(palloc(p, sizeof(double) * 2 * qrows * q_groups(M, QW64) * QW64, &v));
     D.Q64 = (const double*)v;
     if (mixed) {
-      PCHK(palloc(p, sizeof(float) * 2 * qn, &v));
+      PCHK(palloc(p, sizeof(float) * 2 * qrows * q_groups(M, QW32) * QW32, &v));
       D.Q32 = (const float*)v;
     }
     PCHK(palloc(p, sizeof(double) * D.B * 3 * KT, &v));
@@ -1239,11 +1248,14 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
   for (int pi = 0; pi < n_points; ++pi) {
     const rift_ile_point& pt = pts[pi];
     PointDesc& D = p->h_desc[pi];
-    const int64_t qn = (int64_t)KT * (pt.n_t + 2 * QPAD) * pt.n_modes;
-    const int gq = (int)std::min<int64_t>((qn + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_repack, dim3(gq), dim3(256), 0, st, pt.Q, (double*)D.Q64, (float*)D.Q32,
-                       d_perm[pi], pt.n_det, KT, pt.n_modes, pt.n_t);
-    hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(1024), 0, st, D.Q64, d_qmax[pi], pt.n_t, pt.n_modes);
+    const int64_t qper = (int64_t)(pt.n_t + 2 * QPAD) * q_groups(pt.n_modes, QW64) * QW64;
+    const int gq = (int)std::min<int64_t>((KT * qper + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_repack<double>, dim3(gq), dim3(256), 0, st, pt.Q, (double*)D.Q64, d_perm[pi],
+                       pt.n_det, KT, pt.n_modes, pt.n_t, QW64);
+    if (D.Q32)
+      hipLaunchKernelGGL(k_repack<float>, dim3(gq), dim3(256), 0, st, pt.Q, (float*)D.Q32, d_perm[pi],
+                         pt.n_det, KT, pt.n_modes, pt.n_t, QW32);
+    hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(1024), 0, st, D.Q64, d_qmax[pi], qper);
     const int NG = 4 * D.L + 4;
     hipLaunchKernelGGL(k_basis, dim3(KT), dim3(256), sizeof(double) * 3 * NG * NG, st,
                        p->d_desc + pi, pt.U, pt.V, d_perm[pi], (double*)D.C64, (float*)D.C32);
@@ -1351,6 +1363,9 @@ int rift_ile_plan_set_config(rift_ile_plan plan, const rift_ile_config* cfg) {
   int st = validate_config(cfg);
   if (st) return st;
   if (plan->last) HCHK(hipStreamSynchronize(plan->last));
+  // the likelihood kernels' LDS must fit one block (the FP64 form needs the most)
+  if (eval_lds_bytes(plan->lset, cfg->block, sizeof(double)) + 1024 > (size_t)plan->di.max_lds)
+    return RIFT_EUNSUPPORTED;
   if (cfg->sort && (st = ensure_bin_buffers(plan))) return st;
   const bool retile = cfg->block * cfg->tile_blocks != plan->cfg.block * plan->cfg.tile_blocks;
   plan->cfg = *cfg;
@@ -1391,7 +1406,7 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
   refine_fn rf = pick_refine_kt(p->KT, p->lset);
   if (!rf) return RIFT_EUNSUPPORTED;
   hipLaunchKernelGGL(rf, dim3(p->refine_blocks, p->n_points), dim3(256),
-                     (p->lset & 8) ? (size_t)trig_rows(p->lset) * 256 * sizeof(double) : 0, st, p->d_desc, theta, p->N,
+                     eval_lds_bytes(p->lset, 256, sizeof(double)), st, p->d_desc, theta, p->N,
                      (const int32_t*)p->d_cnt, (const int32_t*)p->d_list, L);
   hipLaunchKernelGGL(k_final, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                      lnw, (const float*)p->d_bnd, (const double*)p->d_mlow, p->d_part, p->d_terr);
