@@ -115,6 +115,20 @@ def time_steps(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def warm_up(fn, warmup, torch, min_s=0.3):
+    """W untimed steps, then more of the same until at least `min_s` seconds of
+    GPU work have run: the clocks settle only after ~0.1 s of sustained load,
+    so a short warm-up would time the kernels below their steady state."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < min_s:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
 def c2_inputs(synth, n):
     pt = synth.make_point(3, 21, 6554, 32768.0, 600.0, 2)
     th = synth.prior_samples(n, 2)
@@ -150,9 +164,7 @@ def run_path(ile, torch, pt, tht, precision, steps, warmup, tune, variants=True,
         plan.profile(False)
         variants_out[f"sort{srt}"] = {"ms_per_step": 1e3 * sec_v / max(3, steps // 5), "kernel_ms": kms_v / max(1, nl)}
     plan.config = base
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
+    warm_up(step, warmup, torch)
     plan.profile(True)
     secs, wall = time_steps(step, steps, 0, torch)
     kms, launches = plan.profile_read()

@@ -404,9 +404,11 @@ __host__ __device__ constexpr int det_group_start(int KT, int j) {
 // instruction touches about 8 blocks' cache lines instead of 64 (the vector
 // memory path costs about one cycle per distinct line per instruction).  The
 // reads go straight to LDS (global_load_lds): lane l = 8 q + c' of read t
-// fetches chunk c = c' ^ q of the block of lane j = 8 t + q, which lands at
-// j * 128 + c' * 16 = j * 128 + (c ^ (j & 7)) * 16, so that lane j's own
-// 16-byte reads of its eight chunks are free of bank conflicts.
+// fetches chunk c = c' ^ key(j) of the block of lane j = 8 t + q, which lands
+// at j * 128 + c' * 16 = j * 128 + (c ^ key(j)) * 16.  With key(j) =
+// (j >> 1) & 7 the eight lanes of equal j * 128 mod 256 within any sixteen
+// consecutive lanes read eight different 16-byte columns, so lane j's own
+// reads of its chunks are free of bank conflicts.
 //
 // Units (group p, detector g) are streamed with g fastest through the
 // wavefront's two LDS buffers: unit u+1 is in flight while unit u is
@@ -453,15 +455,17 @@ __device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb
   };
   const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
   const int q = lane >> 3;
-  const uint32_t cx = (uint32_t)((lane & 7) ^ q) << 4;
+  // key(8 t + q) = ((t & 1) << 2) | (q >> 1): the chunk offsets of even and odd reads
+  const uint32_t cx0 = (uint32_t)((lane & 7) ^ (q >> 1)) << 4;
+  const uint32_t cx1 = (uint32_t)((lane & 7) ^ (4 | (q >> 1))) << 4;
   // read t of detector g: this lane's source offset
   uint32_t offt[G][8];
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int t = 0; t < 8; ++t) offt[g][t] = (uint32_t)__shfl((int)boff[K0 + g], 8 * t + q) + cx;
+    for (int t = 0; t < 8; ++t) offt[g][t] = (uint32_t)__shfl((int)boff[K0 + g], 8 * t + q) + ((t & 1) ? cx1 : cx0);
   // chunk c of this lane's block: rbase ^ (c << 4)
-  const uint32_t rbase = (uint32_t)lane * 128u + ((uint32_t)(lane & 7) << 4);
+  const uint32_t rbase = (uint32_t)lane * 128u + ((uint32_t)((lane >> 1) & 7) << 4);
   auto issue = [&](int p, int g, int b) {
     const RIFT_GLOBAL char* ser = uniform_ptr(Qb + (uint64_t)(K0 + g) * kstride + (uint64_t)p * gstride);
     RIFT_LDS unsigned char* dst = stage + b * STAGE_UNIT;
