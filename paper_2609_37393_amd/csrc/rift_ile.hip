@@ -1344,6 +1344,16 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     PCHK(palloc(p, sizeof(float) * N, &v));
     p->d_bnd = (float*)v;
   }
+  // initial launch shape: a small batch gets one-block tiles of 64..256
+  // samples, so that it still spreads over the CUs
+  {
+    int64_t S = N / (2 * (int64_t)std::max(1, p->di.n_cu));
+    if (S < 1024) {
+      int b = 64;
+      while (b < 256 && 2 * b <= S) b *= 2;
+      p->cfg = rift_ile_config{b, 1, 0, 0};
+    }
+  }
   PCHK(build_tiles(p));
 #undef PCHK
 #undef PHIP
@@ -1462,7 +1472,7 @@ int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, 
   static const rift_ile_config cands[] = {
       {256, 1, 0, 1}, {256, 4, 0, 1}, {128, 4, 0, 1}, {512, 2, 0, 1}, {256, 1, 4, 1}, {256, 2, 4, 1},
       {256, 4, 4, 1}, {256, 8, 2, 1}, {128, 8, 4, 1}, {512, 1, 2, 1}, {64, 16, 8, 1},
-      {256, 4, 0, 0}, {256, 8, 2, 0}, {512, 2, 0, 0},
+      {256, 4, 0, 0}, {256, 8, 2, 0}, {512, 2, 0, 0}, {64, 1, 0, 0}, {128, 1, 0, 0},
   };
   const int nc = (int)(sizeof(cands) / sizeof(cands[0]));
   double* d_out = nullptr;
