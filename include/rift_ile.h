@@ -124,7 +124,9 @@ int rift_ile_lnZ(const rift_ile_point *pts, int32_t n_points, const int64_t *n_p
                  int precision, void *stream);
 
 /* lnL and its gradient for n samples of one point (FP64).  lnL: DEVICE [n]
- * (may be NULL); grad: DEVICE [7][n]. */
+ * (may be NULL); grad: DEVICE [7][n].  A batch that cannot give every CU 256
+ * samples is evaluated 16 lanes per sample, a larger one a lane per sample
+ * (the two differ only in rounding order). */
 int rift_ile_grad(const rift_ile_point *pt, int64_t n, const double *theta, double *lnL,
                   double *grad, void *stream);
 

@@ -298,4 +298,260 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
   return lnL;
 }
 
+// The same value and gradient with a group of G lanes (a power of two, at
+// most 64) per sample, for batches too small to fill the GPU one lane per
+// sample.  The group shares its sample's tables through `tab` (GRAD_TAB(L, KT)
+// doubles of LDS per group):
+//   cos/sin(n incl) and cos/sin(q phi) for n, q = 0..2L;
+//   per detector: F+, Fx, dF/dgha (2), dF/ddec (2), dt/dgha, dt/ddec, stencil
+//   row and fraction, a bad flag, and the model-norm weights (|F|^2,
+//   Re F^2, Im F^2) with their changes along gha, dec and psi (12 values).
+// The (detector, mode) pairs of the data term and the basis rows of the
+// model-norm contraction are spread over the group's lanes; 14 group sums
+// finish it.  Every lane of the group returns the value and g[].  The whole
+// wavefront calls this together (one sample per group).
+#define GRAD_TAB(L, KT) (4 * (2 * (L) + 1) + 24 * (KT))
+template <int G>
+__device__ __forceinline__ double gsum(double v) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+template <int KT, int L, int G>
+__device__ __forceinline__ double eval_grad_group(PDesc P, double ra, double dec, double psi, double incl,
+                                                  double phi, double tref, double dist, double* tab,
+                                                  double g[7]) {
+  constexpr int NI = 2 * L;
+  constexpr int NY = L + 1;
+  const int lg = (int)(threadIdx.x & (G - 1));
+  const int K = P->K, M = P->M, n_t = P->n_t;
+  double* ctab = tab;
+  double* stab = tab + (NI + 1);
+  double* cq = tab + 2 * (NI + 1);
+  double* sq = tab + 3 * (NI + 1);
+  double* det = tab + 4 * (NI + 1);
+  for (int n = lg; n <= NI; n += G) {
+    double s, c;
+    sincos((double)n * incl, &s, &c);
+    ctab[n] = c;
+    stab[n] = s;
+    sincos((double)n * phi, &s, &c);
+    cq[n] = c;
+    sq[n] = s;
+  }
+  for (int k = lg; k < KT; k += G) {
+    double* dk = det + 24 * k;
+    if (k < K) {
+      double sg, cg, sd, cd, sp, cp;
+      sincos(P->gmst - ra, &sg, &cg);
+      sincos(dec, &sd, &cd);
+      sincos(psi, &sp, &cp);
+      const double N[3] = {cd * cg, -cd * sg, sd};
+      const double ea[3] = {sg, cg, 0.0};
+      const double ed[3] = {-sd * cg, sd * sg, cd};
+      double X[3], Y[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        X[a] = -cp * ea[a] + sp * ed[a];
+        Y[a] = sp * ea[a] + cp * ed[a];
+      }
+      const RIFT_CONST double* dt6 = P->dten[k];
+      const double D00 = dt6[0], D11 = dt6[1], D22 = dt6[2];
+      const double D01 = 0.5 * dt6[3], D02 = 0.5 * dt6[4], D12 = 0.5 * dt6[5];
+      double DX[3], DY[3];
+      DX[0] = D00 * X[0] + D01 * X[1] + D02 * X[2];
+      DX[1] = D01 * X[0] + D11 * X[1] + D12 * X[2];
+      DX[2] = D02 * X[0] + D12 * X[1] + D22 * X[2];
+      DY[0] = D00 * Y[0] + D01 * Y[1] + D02 * Y[2];
+      DY[1] = D01 * Y[0] + D11 * Y[1] + D12 * Y[2];
+      DY[2] = D02 * Y[0] + D12 * Y[1] + D22 * Y[2];
+      const double fp = X[0] * DX[0] + X[1] * DX[1] + X[2] * DX[2] - (Y[0] * DY[0] + Y[1] * DY[1] + Y[2] * DY[2]);
+      const double fx = 2.0 * (X[0] * DY[0] + X[1] * DY[1] + X[2] * DY[2]);
+      const double SNX = 2.0 * (N[0] * DX[0] + N[1] * DX[1] + N[2] * DX[2]);
+      const double SNY = 2.0 * (N[0] * DY[0] + N[1] * DY[1] + N[2] * DY[2]);
+      const double gA = -cp * cd * SNX - sp * cd * SNY + 2.0 * sd * fx;
+      const double gC = -cp * cd * SNY + sp * cd * SNX - 2.0 * sd * fp;
+      const double dA = -sp * SNX + cp * SNY;
+      const double dC = -sp * SNY - cp * SNX;
+      const RIFT_CONST double* r = P->rpos[k];
+      const double tk = tref - (r[0] * N[0] + r[1] * N[1] + r[2] * N[2]);
+      double u = (tk - P->t0) * P->inv_dt;
+      double bad = 0.0;
+      if (!(fabs(u) < 1.0e9)) {
+        bad = 1.0;
+        u = 0.0;
+      }
+      const double jf = floor(u);
+      int j0 = (int)jf - 1;
+      j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
+      dk[0] = fp;
+      dk[1] = fx;
+      dk[2] = gA;
+      dk[3] = gC;
+      dk[4] = dA;
+      dk[5] = dC;
+      dk[6] = cd * (r[0] * ea[0] + r[1] * ea[1]);
+      dk[7] = -(r[0] * ed[0] + r[1] * ed[1] + r[2] * ed[2]);
+      dk[8] = (double)(j0 + QPAD);
+      dk[9] = u - jf;
+      dk[10] = bad;
+      dk[11] = 0.0;
+      // weights (|F|^2, F+^2 - Fx^2, 2 F+ Fx) and their changes along a
+      // change (da, dc) of (F+, Fx): 2 (a da + c dc), 2 (a da - c dc), 2 (da c + a dc)
+      const double a = fp, c = fx;
+      dk[12] = a * a + c * c;
+      dk[13] = a * a - c * c;
+      dk[14] = 2.0 * a * c;
+      const double dirs[3][2] = {{gA, gC}, {dA, dC}, {2.0 * c, -2.0 * a}};
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        const double da = dirs[v][0], dc = dirs[v][1];
+        dk[15 + 3 * v] = 2.0 * (a * da + c * dc);
+        dk[16 + 3 * v] = 2.0 * (a * da - c * dc);
+        dk[17 + 3 * v] = 2.0 * (da * c + a * dc);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 24; ++v) dk[v] = 0.0;
+      dk[8] = (double)QPAD;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // data term and its derivatives: pairs (k, i)
+  const RIFT_GLOBAL double* Q = as_global(P->Q64);
+  const int64_t ntp = n_t + 2 * QPAD;
+  const int NGR = q_groups(M, QW64);
+  const double idt = P->inv_dt;
+  double data = 0.0, gg = 0.0, gdec = 0.0, gpsi = 0.0, gi = 0.0, gf = 0.0, gt = 0.0;
+  for (int pr = lg; pr < K * M; pr += G) {
+    const int k = pr / M, i = pr % M;
+    const double* dk = det + 24 * k;
+    const double s = dk[9], s2 = s * s;
+    double w[4], wd[4];
+    w[0] = -s * (s - 1.0) * (s - 2.0) / 6.0;
+    w[1] = (s + 1.0) * (s - 1.0) * (s - 2.0) * 0.5;
+    w[2] = -(s + 1.0) * s * (s - 2.0) * 0.5;
+    w[3] = (s + 1.0) * s * (s - 1.0) / 6.0;
+    wd[0] = -(3.0 * s2 - 6.0 * s + 2.0) / 6.0 * idt;
+    wd[1] = (3.0 * s2 - 4.0 * s - 1.0) * 0.5 * idt;
+    wd[2] = -(3.0 * s2 - 2.0 * s - 2.0) * 0.5 * idt;
+    wd[3] = (3.0 * s2 - 1.0) / 6.0 * idt;
+    const RIFT_GLOBAL double* q =
+        Q + 2 * ((((int64_t)k * NGR + i / QW64) * ntp + (int64_t)dk[8]) * QW64 + i % QW64);
+    double qx = 0.0, qy = 0.0, tx = 0.0, ty = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double vx = q[2 * QW64 * j], vy = q[2 * QW64 * j + 1];
+      qx += w[j] * vx;
+      qy += w[j] * vy;
+      tx += wd[j] * vx;
+      ty += wd[j] * vy;
+    }
+    const int m = P->m[i];
+    double d = 0.0, dd = 0.0;
+    if (P->odd[i]) {
+      for (int n = 1; n < NY; ++n) {
+        d += P->ycoef[i][n] * stab[n];
+        dd += P->ycoef[i][n] * (double)n * ctab[n];
+      }
+    } else {
+      for (int n = 0; n < NY; ++n) {
+        d += P->ycoef[i][n] * ctab[n];
+        dd -= P->ycoef[i][n] * (double)n * stab[n];
+      }
+    }
+    const int am = m < 0 ? -m : m;
+    const double ex = cq[am], ey = m < 0 ? -sq[am] : sq[am];  // e^{i m phi}
+    const double yx = d * ex, yy = d * ey, ix = dd * ex, iy = dd * ey;
+    const double zx = yx * qx + yy * qy, zy = yx * qy - yy * qx;  // conj(Y) Qhat
+    const double ztx = yx * tx + yy * ty, zty = yx * ty - yy * tx;
+    const double zix = ix * qx + iy * qy, ziy = ix * qy - iy * qx;
+    const double mv = (double)m;
+    const double fp = dk[0], fx = dk[1];
+    data += fp * zx + fx * zy;
+    const double dt_term = fp * ztx + fx * zty;
+    gg += dk[2] * zx + dk[3] * zy + dt_term * dk[6];
+    gdec += dk[4] * zx + dk[5] * zy + dt_term * dk[7];
+    gpsi += 2.0 * fx * zx - 2.0 * fp * zy;
+    gi += fp * zix + fx * ziy;
+    gf += fp * (mv * zy) + fx * (-mv * zx);
+    gt += dt_term;
+  }
+  // model-norm term and its derivatives: basis rows b over the lanes, the
+  // 3 KT columns (3 k + c) of each row in turn
+  double quad = 0.0, qg = 0.0, qdec = 0.0, qpsi = 0.0, qi = 0.0, qf = 0.0;
+  const RIFT_GLOBAL double* C = as_global(P->C64);
+  constexpr int W = 3 * KT;
+  for (int b = lg; b < Cls<L>::B; b += G) {
+    const int rb = basis_row<L>(b);
+    const int kind = rb & 15, n = (rb >> 4) & 255, qq = rb >> 12;
+    // T_n(incl) and its incl-derivative
+    const double T = (kind >= 3) ? stab[n] : ctab[n];
+    const double Tp = (kind >= 3) ? (double)n * ctab[n] : -(double)n * stab[n];
+    double beta = T, bi = Tp, bf = 0.0;
+    if (kind != 0) {
+      const double cqv = cq[qq], sqv = sq[qq], qd = (double)qq;
+      if ((kind & 1) == 1) {  // cos(q phi)
+        beta = T * cqv;
+        bi = Tp * cqv;
+        bf = -qd * T * sqv;
+      } else {  // sin(q phi)
+        beta = T * sqv;
+        bi = Tp * sqv;
+        bf = qd * T * cqv;
+      }
+    }
+    const RIFT_GLOBAL double* cr = C + (int64_t)b * W;
+#pragma unroll
+    for (int col = 0; col < W; ++col) {
+      const int k = col / 3, c = col - 3 * k;
+      const double* dk = det + 24 * k;
+      const double cj = cr[col];
+      const double cb = cj * beta;
+      quad += cb * dk[12 + c];
+      qi += cj * bi * dk[12 + c];
+      qf += cj * bf * dk[12 + c];
+      qg += cb * dk[15 + c];
+      qdec += cb * dk[18 + c];
+      qpsi += cb * dk[21 + c];
+    }
+  }
+  double bad = 0.0;
+  for (int k = lg; k < K; k += G) bad += det[24 * k + 10];
+  data = gsum<G>(data);
+  gg = gsum<G>(gg);
+  gdec = gsum<G>(gdec);
+  gpsi = gsum<G>(gpsi);
+  gi = gsum<G>(gi);
+  gf = gsum<G>(gf);
+  gt = gsum<G>(gt);
+  quad = gsum<G>(quad);
+  qg = gsum<G>(qg);
+  qdec = gsum<G>(qdec);
+  qpsi = gsum<G>(qpsi);
+  qi = gsum<G>(qi);
+  qf = gsum<G>(qf);
+  bad = gsum<G>(bad);
+  const double si = stab[1];
+  const double x = P->d_ref / dist;
+  const double x2 = x * x;
+  const double lnL = x * data - x2 * quad;
+  g[0] = -(x * gg - x2 * qg);
+  g[1] = x * gdec - x2 * qdec;
+  g[2] = x * gpsi - x2 * qpsi;
+  g[3] = -(x * gi - x2 * qi) / si;
+  g[4] = x * gf - x2 * qf;
+  g[5] = x * gt;
+  g[6] = -x * data + 2.0 * x2 * quad;
+  if (bad != 0.0) {
+    const double nan = __builtin_nan("");
+#pragma unroll
+    for (int a = 0; a < 7; ++a) g[a] = nan;
+    return nan;
+  }
+  return lnL;
+}
+
 }  // namespace rift

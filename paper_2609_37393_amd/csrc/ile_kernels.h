@@ -362,6 +362,39 @@ __global__ void __launch_bounds__(256) k_grad(const PointDesc* __restrict__ P,
 }
 
 
+// Gradient, a group of GRAD_G lanes per sample (batches too small to fill the
+// GPU one lane per sample).  A wavefront holds 64 / GRAD_G samples; groups
+// past the end repeat the last sample and drop it.  Lanes 0..6 of a group
+// write the seven components.
+constexpr int GRAD_G = 16;
+template <int KT, int L>
+__global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__ P,
+                                                   const double* __restrict__ theta, int64_t n,
+                                                   double* __restrict__ lnL, double* __restrict__ grad) {
+  constexpr int SPW = 64 / GRAD_G;  // samples per wavefront
+  __shared__ double tabs[4 * SPW * GRAD_TAB(L, KT)];
+  const int lg = (int)(threadIdx.x & (GRAD_G - 1));
+  const int gw = (int)((threadIdx.x & 63u) / GRAD_G);
+  double* tab = tabs + ((threadIdx.x >> 6) * SPW + gw) * GRAD_TAB(L, KT);
+  const int64_t per_launch = (int64_t)gridDim.x * (blockDim.x >> 6) * SPW;
+  for (int64_t ib = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * SPW; ib < n;
+       ib += per_launch) {
+    const bool live = ib + gw < n;
+    const int64_t i = live ? ib + gw : n - 1;
+    const RIFT_GLOBAL double* th = as_global(theta) + i;
+    double g[7];
+    const double l = eval_grad_group<KT, L, GRAD_G>(opaque(P), th[0], th[n], th[2 * n], th[3 * n], th[4 * n],
+                                                    th[5 * n], th[6 * n], tab, g);
+    if (live) {
+      if (lg == 0 && lnL) as_global_w(lnL)[i] = l;
+      double v = g[0];
+#pragma unroll
+      for (int a = 1; a < 7; ++a) v = (lg == a) ? g[a] : v;
+      if (lg < 7) as_global_w(grad)[lg * n + i] = v;
+    }
+  }
+}
+
 typedef void (*tile_fn)(TileArgs);
 typedef void (*refine_fn)(const PointDesc*, const double*, int64_t, const int32_t*, const int32_t*, double*);
 typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, double*);
@@ -371,7 +404,8 @@ typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, doubl
   tile_fn get_tiles64_kt##KT(int lset);              \
   tile_fn get_tiles32_kt##KT(int lset);              \
   refine_fn get_refine_kt##KT(int lset);             \
-  grad_fn get_grad_kt##KT(int L);
+  grad_fn get_grad_kt##KT(int L);                   \
+  grad_fn get_gradw_kt##KT(int L);
 RIFT_DECL_GETTERS(2)
 RIFT_DECL_GETTERS(3)
 RIFT_DECL_GETTERS(5)

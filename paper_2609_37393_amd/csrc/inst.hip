@@ -1,7 +1,7 @@
 // Instances of the evaluation kernels for one detector class RIFT_KT and one
 // kernel kind RIFT_KIND (0: FP64 tiles, 1: FP32 tiles, 2: FP64 refine,
-// 3: gradient).  The build compiles this file once per (class, kind) so the
-// instances build in parallel.
+// 3: gradient, a lane or a group of lanes per sample).  The build compiles
+// this file once per (class, kind) so the instances build in parallel.
 #include "ile_kernels.h"
 
 #if !defined(RIFT_KT) || !defined(RIFT_KIND)
@@ -52,6 +52,15 @@ grad_fn RIFT_CAT(get_grad_kt, RIFT_KT)(int L) {
     case 3: return k_grad<RIFT_KT, 3>;
     case 4: return k_grad<RIFT_KT, 4>;
     case 8: return k_grad<RIFT_KT, 8>;
+    default: return nullptr;
+  }
+}
+grad_fn RIFT_CAT(get_gradw_kt, RIFT_KT)(int L) {
+  switch (L) {
+    case 2: return k_grad_wide<RIFT_KT, 2>;
+    case 3: return k_grad_wide<RIFT_KT, 3>;
+    case 4: return k_grad_wide<RIFT_KT, 4>;
+    case 8: return k_grad_wide<RIFT_KT, 8>;
     default: return nullptr;
   }
 }

@@ -923,6 +923,14 @@ grad_fn pick_grad_kt(int KT, int L) {
     default: return get_grad_kt8(L);
   }
 }
+grad_fn pick_gradw_kt(int KT, int L) {
+  switch (KT) {
+    case 2: return get_gradw_kt2(L);
+    case 3: return get_gradw_kt3(L);
+    case 5: return get_gradw_kt5(L);
+    default: return get_gradw_kt8(L);
+  }
+}
 
 int validate_config(const rift_ile_config* c) {
   if (!c) return RIFT_EINVAL;
@@ -1445,9 +1453,13 @@ int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* 
   hipStream_t st = (hipStream_t)stream;
   p->last = st;
   const PointDesc& D = p->h_desc[point];
-  grad_fn f = pick_grad_kt(p->KT, D.L);
+  // a batch that cannot give every CU 256 samples runs 16 lanes per sample
+  const bool wide = n <= (int64_t)256 * p->di.n_cu;
+  grad_fn f = wide ? pick_gradw_kt(p->KT, D.L) : pick_grad_kt(p->KT, D.L);
   if (!f) return RIFT_EUNSUPPORTED;
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)p->di.n_cu * 16);
+  const int64_t blocks = wide ? std::min<int64_t>((n + 15) / 16, (int64_t)p->di.n_cu * 8)
+                              : std::min<int64_t>((n + 255) / 256, (int64_t)p->di.n_cu * 16);
+  const size_t shm = wide ? 0 : (size_t)trig_rows(lbit(D.L)) * 256 * sizeof(double);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p->profiling) {
     HCHK(hipEventCreate(&e0));
@@ -1456,7 +1468,7 @@ int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* 
     p->ev.push_back(e1);
     HCHK(hipEventRecord(e0, st));
   }
-  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), (size_t)trig_rows(lbit(D.L)) * 256 * sizeof(double), st,
+  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), shm, st,
                      (const PointDesc*)(p->d_desc + point),
                      theta, n, lnL, grad);
   HCHK(hipGetLastError());

@@ -198,6 +198,32 @@ def test_gradient_all_classes(ile, oracle_mod, case):
         assert rel.max() < 1e-7, (a, rel.max())
 
 
+def test_gradient_lane_and_group_forms(ile, oracle_mod):
+    """A batch too small to give every CU 256 samples runs 16 lanes per
+    sample, a larger one a lane per sample: both forms match the oracle on the
+    same samples."""
+    import torch
+
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n_big = 256 * n_cu + 1000
+    pt = synth.make_point(3, 9, 6554, 32768.0, 600.0, 3)
+    th = synth.prior_samples(n_big, 71)
+    th[3] = np.clip(th[3], 0.05, np.pi - 0.05)
+    idx = np.linspace(0, n_big - 1, 400).astype(np.int64)
+    sub = np.ascontiguousarray(th[:, idx])
+    l_big, g_big = ile.grad(pt, th)  # one lane per sample
+    l_sub, g_sub = ile.grad(pt, sub)  # 16 lanes per sample
+    l_or, g_or = oracle_mod.grad(pt, sub)
+    S = lnL_scale(oracle_mod, pt, sub)
+    forms = {"lane": (l_big.cpu().numpy()[idx], g_big.cpu().numpy()[:, idx]),
+             "group": (l_sub.cpu().numpy(), g_sub.cpu().numpy())}
+    for name, (l, g) in forms.items():
+        assert np.all(np.abs(l - l_or) <= 1e-9 * S + 1e-12), name
+        for a in range(7):
+            rel = np.abs(g[a] - g_or[a]) / (np.abs(g_or[a]) + 1e-6 * S + 1e-9)
+            assert rel.max() < 1e-7, (name, a, rel.max())
+
+
 def test_autograd_function(ile, oracle_mod):
     import torch
 
