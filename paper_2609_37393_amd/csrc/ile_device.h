@@ -663,7 +663,12 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
     sfr[k] = s;
   }
 
+  // The data term is bound by its Q reads, the contraction below by the ALU:
+  // a wavefront in the data term gets issue priority over one in the
+  // contraction, so that the two on a SIMD keep both busy.
+  __builtin_amdgcn_s_setprio(1);
   const double data = data_fn(row, sfr, Fre, Fim, cn, sn, cf, sf);
+  __builtin_amdgcn_s_setprio(0);
 
   // --- model-norm term: basis contraction ----------------------------------
   R acc[3 * KT];

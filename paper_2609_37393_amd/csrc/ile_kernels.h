@@ -265,19 +265,26 @@ __device__ __forceinline__ double eval_wide(PDesc P, double ra, double dec, doub
     data += dk[0] * (yx * qx + yy * qy) + dk[1] * (yx * qy - yy * qx);
   }
   // model-norm term: coefficient j = b * 3 KT + 3 k + c, weights |F|^2,
-  // Re F^2, Im F^2 for c = 0, 1, 2
+  // Re F^2, Im F^2 for c = 0, 1, 2; basis rows over the lanes, each row's
+  // 3 KT coefficients read together
   double quad = 0.0;
   const RIFT_GLOBAL double* C = as_global(P->C64);
-  const int W = 3 * KT;
-#pragma unroll 4
-  for (int j = lane; j < Cls<L>::B * W; j += 64) {
-    const int b = j / W, col = j - b * W, k = col / 3, c = col - 3 * k;
+  constexpr int W = 3 * KT;
+  for (int b = lane; b < Cls<L>::B; b += 64) {
     const int rb = basis_row<L>(b);
     const int kind = rb & 15, n = (rb >> 4) & 255, qq = rb >> 12;
     double beta = (kind >= 3) ? stab[n] : ctab[n];
     if (kind != 0) beta *= ((kind & 1) == 1) ? cq[qq] : sq[qq];
-    const double wt = (k < K) ? det[8 * k + 2 + c] : 0.0;
-    quad += C[j] * beta * wt;
+    const RIFT_GLOBAL double* cr = C + (int64_t)b * W;
+    double cv[W];
+#pragma unroll
+    for (int col = 0; col < W; ++col) cv[col] = cr[col];
+#pragma unroll
+    for (int col = 0; col < W; ++col) {
+      const int k = col / 3, c = col - 3 * k;
+      const double wt = (k < K) ? det[8 * k + 2 + c] : 0.0;
+      quad += cv[col] * beta * wt;
+    }
   }
   double bad = (lane < K) ? det[8 * lane + 7] : 0.0;
   data = dsum_wave(data);
