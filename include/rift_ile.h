@@ -65,6 +65,7 @@ extern "C" {
 #define RIFT_ILE_VERSION 1
 #define RIFT_ILE_MAX_DET 8   /* detectors per point */
 #define RIFT_ILE_MAX_MODES 25 /* modes per point */
+#define RIFT_ILE_MAX_NT (1 << 26) /* Q samples per mode and detector */
 #define RIFT_ILE_MAX_L 8     /* largest l of a mode; |m| <= l */
 
 typedef enum {
@@ -87,7 +88,7 @@ typedef enum {
 typedef struct {
   int32_t n_det;            /* K, 1..RIFT_ILE_MAX_DET */
   int32_t n_modes;          /* M, 1..RIFT_ILE_MAX_MODES */
-  int32_t n_t;              /* samples of Q per mode and detector, >= 4 */
+  int32_t n_t;              /* samples of Q per mode and detector, 4 .. RIFT_ILE_MAX_NT */
   const int32_t *lm;        /* HOST [M][2]: (l, m), 2 <= l <= RIFT_ILE_MAX_L, |m| <= l, no repeats */
   double t0;                /* time of Q sample 0 (s) */
   double dt;                /* Q sample spacing (s), > 0 */

@@ -756,7 +756,8 @@ int validate_point(const rift_ile_point* pt) {
   if (!pt) return RIFT_EINVAL;
   if (pt->n_det < 1 || pt->n_det > RIFT_ILE_MAX_DET) return RIFT_EINVAL;
   if (pt->n_modes < 1 || pt->n_modes > RIFT_ILE_MAX_MODES) return RIFT_EINVAL;
-  if (pt->n_t < 4) return RIFT_EINVAL;
+  // stencil offsets inside a series are 32-bit byte offsets of 32-byte rows
+  if (pt->n_t < 4 || pt->n_t > RIFT_ILE_MAX_NT) return RIFT_EINVAL;
   if ((int64_t)pt->n_t * pt->n_modes * RIFT_ILE_MAX_DET > ((int64_t)1 << 40)) return RIFT_EINVAL;
   if (!pt->lm || !pt->Q || !pt->U || !pt->V || !pt->det_tensor || !pt->det_pos) return RIFT_EINVAL;
   if ((((uintptr_t)pt->Q) | ((uintptr_t)pt->U) | ((uintptr_t)pt->V)) & 7u) return RIFT_EINVAL;

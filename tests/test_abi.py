@@ -51,7 +51,7 @@ def _point(ile, **over):
 
 
 BAD = [
-    dict(n_det=0), dict(n_det=9), dict(n_modes=0), dict(n_modes=26), dict(n_t=3),
+    dict(n_det=0), dict(n_det=9), dict(n_modes=0), dict(n_modes=26), dict(n_t=3), dict(n_t=(1 << 26) + 1),
     dict(dt=0.0), dict(dt=-1e-3), dict(dt=float("nan")), dict(t0=float("inf")),
     dict(d_ref=0.0), dict(gmst_rad=float("nan")), dict(Q=None), dict(U=None), dict(V=None),
     dict(lm=None), dict(det_tensor=None), dict(det_pos=None), dict(Q=0x1004),
