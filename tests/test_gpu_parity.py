@@ -186,16 +186,25 @@ def test_gradient_matches_oracle_and_differences(ile, oracle_mod):
 
 @pytest.mark.parametrize("case", [CASES[0], CASES[4], CASES[7]], ids=["K2M2", "K5M21", "l8"])
 def test_gradient_all_classes(ile, oracle_mod, case):
+    """Both gradient forms per detector and mode class: 400 samples alone (16
+    lanes per sample) and as the head of a batch large enough for one lane per
+    sample."""
+    import torch
+
     pt, th = _point(case)
     th = th[:, :400].copy()
     th[3] = np.clip(th[3], 0.05, np.pi - 0.05)
-    l, g = ile.grad(pt, th)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    reps = (256 * n_cu + 1000) // th.shape[1] + 1
+    big = np.ascontiguousarray(np.tile(th, (1, reps)))
     l_or, g_or = oracle_mod.grad(pt, th)
     S = lnL_scale(oracle_mod, pt, th)
-    g = g.cpu().numpy()
-    for a in range(7):
-        rel = np.abs(g[a] - g_or[a]) / (np.abs(g_or[a]) + 1e-6 * S + 1e-9)
-        assert rel.max() < 1e-7, (a, rel.max())
+    for form, batch in (("group", th), ("lane", big)):
+        l, g = ile.grad(pt, batch)
+        g = g.cpu().numpy()[:, :400]
+        for a in range(7):
+            rel = np.abs(g[a] - g_or[a]) / (np.abs(g_or[a]) + 1e-6 * S + 1e-9)
+            assert rel.max() < 1e-7, (form, a, rel.max())
 
 
 def test_gradient_lane_and_group_forms(ile, oracle_mod):
