@@ -72,6 +72,29 @@ def test_lnL_fp64_matches_oracle(ile, oracle_mod, case):
     assert np.all(err <= 1e-9 * S + 1e-12), (err / S).max()
 
 
+@pytest.mark.parametrize("case", CASES, ids=[f"K{c[0]}M{c[1]}nt{c[2]}" for c in CASES])
+def test_mixed_all_classes(ile, oracle_mod, case):
+    """Every detector and mode class of the FP32 pass: each FP32 value within
+    max(1e-3, 1e-4 S_i) of the oracle, and the mixed ln Z within 1e-3 of the
+    oracle's and within its own reported bound."""
+    import torch
+
+    pt, th = _point(case)
+    print(f"case {case}", flush=True)
+    l_or = oracle_mod.lnL(pt, th)
+    S = lnL_scale(oracle_mod, pt, th)
+    l32 = ile.lnL(pt, th, precision="mixed").cpu().numpy()
+    assert np.all(np.abs(l32 - l_or) <= np.maximum(1e-3, 1e-4 * S))
+    z_or, _ = oracle_mod.lnZ(l_or)
+    plan = ile.Plan([pt], [th.shape[1]], precision="mixed")
+    err = torch.empty(1, dtype=torch.float64, device="cuda")
+    z, _ = plan.lnZ(torch.as_tensor(th, device="cuda").contiguous(), err_out=err)
+    dz = abs(z.item() - z_or)
+    assert dz <= 1e-3, dz
+    assert dz <= err.item() + 1e-9 * max(1.0, abs(z_or)), (dz, err.item())
+    plan.close()
+
+
 @pytest.mark.parametrize("case", CASES[:5], ids=[f"K{c[0]}M{c[1]}" for c in CASES[:5]])
 def test_lnZ_fp64_matches_oracle(ile, oracle_mod, case):
     pt, _ = _point(case)
