@@ -297,6 +297,27 @@ def test_launch_shapes_agree_and_are_deterministic(ile):
     plan.close()
 
 
+@pytest.mark.parametrize("case", CASES, ids=[f"K{c[0]}M{c[1]}nt{c[2]}" for c in CASES])
+def test_sorted_all_classes(ile, case):
+    """Arrival-time binning over one, two or three detectors (by the class's
+    detector count) leaves every lnL and ln Z bitwise unchanged."""
+    import torch
+
+    pt, th = _point(case)
+    print(f"case {case}", flush=True)
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    plan = ile.Plan([pt], [th.shape[1]])
+    res = {}
+    for sort in (0, 1):
+        plan.config = dict(block=128, tile_blocks=2, blocks_per_cu=0, sort=sort)
+        ll = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
+        z, ne = plan.lnZ(tht, lnL_out=ll)
+        res[sort] = (ll.clone(), z.clone(), ne.clone())
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_sorted_evaluation_is_bitwise_identical(ile, prec):
     """Binning the batch by arrival time changes only the evaluation order:
