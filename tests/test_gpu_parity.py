@@ -349,9 +349,9 @@ def test_graph_capture_replays(ile):
     counts = [1000, 1500, 700, 2000, 300]
     th = np.concatenate([synth.prior_samples(c, 300 + i) for i, c in enumerate(counts)], axis=1)
     tht = torch.as_tensor(th, device="cuda").contiguous()
-    for prec in ("fp64", "mixed"):
+    for prec, sort in (("fp64", 0), ("mixed", 0), ("fp64", 1), ("mixed", 1)):
         plan = ile.Plan(pts, counts, precision=prec)
-        plan.config = dict(block=256, tile_blocks=2, blocks_per_cu=2)
+        plan.config = dict(block=256, tile_blocks=2, blocks_per_cu=2, sort=sort)
         z = torch.empty(5, dtype=torch.float64, device="cuda")
         ne = torch.empty(5, dtype=torch.float64, device="cuda")
         plan.lnZ(tht, lnZ_out=z, neff_out=ne)
@@ -368,7 +368,38 @@ def test_graph_capture_replays(ile):
             torch.cuda.synchronize()
             g.replay()
             torch.cuda.synchronize()
-            assert torch.equal(z, eager), (prec, r)
+            assert torch.equal(z, eager), (prec, sort, r)
+        plan.close()
+
+
+def test_graph_capture_gradient(ile):
+    """A captured gradient evaluation (both forms) replays the eager result."""
+    import torch
+
+    pt, th = _point(CASES[2])
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for n in (2000, 256 * n_cu + 1000):
+        t = np.ascontiguousarray(np.tile(th, (1, n // th.shape[1] + 1))[:, :n])
+        tht = torch.as_tensor(t, device="cuda").contiguous()
+        plan = ile.Plan([pt], [n])
+        g = torch.empty((7, n), dtype=torch.float64, device="cuda")
+        l = torch.empty(n, dtype=torch.float64, device="cuda")
+        plan.grad(0, tht, lnL_out=l, grad_out=g)
+        torch.cuda.synchronize()
+        eager_g, eager_l = g.clone(), l.clone()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            plan.grad(0, tht, lnL_out=l, grad_out=g)
+        for r in range(3):
+            g.fill_(0.0)
+            l.fill_(0.0)
+            _ = torch.randn(1000, device="cuda").sum()
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(g, eager_g) and torch.equal(l, eager_l), (n, r)
         plan.close()
 
 
