@@ -350,28 +350,72 @@ def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64):
             "kernel_ms_avg": kms / max(1, launches), "chains": chains, "steps_per_chain": nsteps}
 
 
-def extra_c5(ile, synth, torch, steps):
+def extra_c5(ile, synth, torch, steps, n_batch=64, per_point=200_000):
     """K = 5 (two 40-km-class), 21 modes, 13108 samples at 32768 Hz, SNR 1000:
-    1e7 samples in 10 chunks of 1e6 (ln Z merged), mixed precision; plus a
-    64-point batch of 2e5 samples each."""
-    pt = synth.make_point(5, 21, 13108, 32768.0, 1000.0, 5)
+    1e7 samples in 10 chunks of 1e6 (ln Z merged), FP64 and mixed precision;
+    plus a 64-point batch of 2e5 samples each (16 intrinsic points at 4 SNR
+    scalings, 400 to 1000), with its mixed-precision ln Z difference from the
+    FP64 path and the largest reported bound over the points."""
+    net = synth.network(5, 5)
+    pt = synth.make_point(5, 21, 13108, 32768.0, 1000.0, 5, net=net)
     n = 10_000_000
     th = torch.empty((7, n), dtype=torch.float64, device="cuda")
     for s in range(0, n, 2_000_000):
         th[:, s:s + 2_000_000] = torch.as_tensor(synth.prior_samples(2_000_000, 500 + s // 2_000_000), device="cuda")
     res = {}
     chunks = [1_000_000] * 10
+    fps = flops_per_sample(5, 21, 4)
     for prec in ("fp64", "mixed"):
         # ten chunks as ten "points" sharing the tables: one launch, then an LSE merge
         plan = ile.Plan([pt] * 10, chunks, precision=prec)
+        plan.tune(th)
         z = torch.empty(10, dtype=torch.float64, device="cuda")
         plan.lnZ(th, lnZ_out=z)
         secs, _ = time_steps(lambda: plan.lnZ(th, lnZ_out=z), steps, 1, torch)
         zz = z.cpu().numpy()
         m = zz.max()
         res[prec] = {"lnL_evals_per_s": n * steps / secs, "ms_per_step": 1e3 * secs / steps,
-                     "lnZ": float(m + math.log(np.mean(np.exp(zz - m))))}
+                     "lnZ": float(m + math.log(np.mean(np.exp(zz - m)))), "tuned_config": plan.config,
+                     "alu_frac": fps * n * steps / secs / (1e12 * (PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS))}
         plan.close()
+    del th
+    # the 64-point batch
+    base = [synth.make_point(5, 21, 13108, 32768.0, 1000.0, 900 + b, net=net) for b in range(n_batch // 4)]
+    pts = []
+    for b in base:
+        for scale in (1.0, 0.8, 0.6, 0.4):
+            q = dict(b)
+            q["Q"] = b["Q"] * scale
+            q["U"] = b["U"] * scale * scale
+            q["V"] = b["V"] * scale * scale
+            pts.append(q)
+    counts = [per_point] * len(pts)
+    N = per_point * len(pts)
+    thb = torch.empty((7, N), dtype=torch.float64, device="cuda")
+    for i in range(len(pts)):
+        thb[:, i * per_point:(i + 1) * per_point] = torch.as_tensor(synth.prior_samples(per_point, 2000 + i),
+                                                                    device="cuda")
+    zb = {}
+    batch = {}
+    for prec in ("fp64", "mixed"):
+        plan = ile.Plan(pts, counts, precision=prec)
+        plan.tune(thb)
+        z = torch.empty(len(pts), dtype=torch.float64, device="cuda")
+        err = torch.empty(len(pts), dtype=torch.float64, device="cuda")
+        plan.lnZ(thb, lnZ_out=z, err_out=err)
+        secs, _ = time_steps(lambda: plan.lnZ(thb, lnZ_out=z, err_out=err), steps, 1, torch)
+        zb[prec] = z.cpu().numpy()
+        batch[prec] = {"lnL_evals_per_s": N * steps / secs, "ms_per_step": 1e3 * secs / steps,
+                       "tuned_config": plan.config,
+                       "alu_frac": fps * N * steps / secs / (1e12 * (PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS))}
+        if prec == "mixed":
+            batch[prec]["max_lnZ_err_bound"] = float(err.max().item())
+            batch[prec]["refined"] = plan.refined()
+        plan.close()
+    batch["max_abs_dlnZ_mixed_vs_fp64"] = float(np.abs(zb["mixed"] - zb["fp64"]).max())
+    batch["points"] = len(pts)
+    batch["samples_per_point"] = per_point
+    res["batch64"] = batch
     return res
 
 
