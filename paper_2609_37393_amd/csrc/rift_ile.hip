@@ -268,28 +268,42 @@ __global__ void k_merge(const PointDesc* __restrict__ descs, const int32_t* __re
                         const double* __restrict__ part, const double* __restrict__ terr,
                         const double* __restrict__ mlow, double* __restrict__ lnZ,
                         double* __restrict__ neff, double* __restrict__ lnZ_err) {
-  __shared__ MS sh[8];
-  __shared__ double shd[8];
+  __shared__ double shm[8], shs[8], she[8];
   const int p = blockIdx.x;
-  MS acc;
-  acc.m = -__builtin_inf();
-  acc.s = 0.0;
-  double err = 0.0;
-  for (int t = trange[2 * p] + threadIdx.x; t < trange[2 * p + 1]; t += blockDim.x) {
-    MS v;
-    v.m = part[2 * t];
-    v.s = part[2 * t + 1];
-    acc = ms_combine(acc, v);
+  const int t0 = trange[2 * p], t1 = trange[2 * p + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // the largest tile maximum first, then every tile's sum scaled to it (the
+  // exponentials independent of each other)
+  double m = -__builtin_inf();
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) m = fmax(m, part[2 * t]);
+  m = dmax_wave(m);
+  if (lane == 0) shm[wave] = m;
+  __syncthreads();
+  m = shm[0];
+  for (int w = 1; w < nw; ++w) m = fmax(m, shm[w]);
+  double sum = 0.0, err = 0.0;
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
+    const double st = part[2 * t + 1];
+    if (m == -__builtin_inf()) sum += (st != st) ? st : 0.0;
+    else if (st != 0.0) sum += st * exp(part[2 * t] - m);
     if (terr) err += terr[t];
   }
-  const MS r = ms_block(acc, sh);
+  sum = dsum_wave(sum);
   err = dsum_wave(err);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) shd[threadIdx.x >> 6] = err;
+  if (lane == 0) {
+    shs[wave] = sum;
+    she[wave] = err;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double e = shd[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) e += shd[w];
+    MS r;
+    r.m = m;
+    r.s = shs[0];
+    double e = she[0];
+    for (int w = 1; w < nw; ++w) {
+      r.s += shs[w];
+      e += she[w];
+    }
     const PointDesc* P = descs + p;
     double z;
     if (r.s != r.s) z = __builtin_nan("");
