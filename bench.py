@@ -313,23 +313,27 @@ def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64):
     p = torch.zeros_like(c)
     sigt = torch.as_tensor(sig, device="cuda")[:, None]
     eps = 0.1
+    step_q = (eps * sigt * sigt).expand_as(p).contiguous()  # eps sigma^2, per parameter
     th = torch.empty_like(q)
     g = torch.empty_like(q)
+    ci = torch.empty_like(q[3])
 
+    # one fused elementwise launch per update where torch has one
     def to_theta():
         th.copy_(cq)
-        th[3] = torch.arccos(torch.clamp(cq[3], -1 + 1e-12, 1 - 1e-12))
-        th[6] = torch.exp(cq[6])
+        torch.clamp(cq[3], -1 + 1e-12, 1 - 1e-12, out=ci)
+        torch.arccos(ci, out=th[3])
+        torch.exp(cq[6], out=th[6])
 
     def run():
         to_theta()
         plan.grad(0, th, grad_out=g)
         for _ in range(nsteps - 1):
-            p.add_(0.5 * eps * g)
-            cq.add_(eps * sigt * sigt * p)
+            p.add_(g, alpha=0.5 * eps)
+            cq.addcmul_(step_q, p)
             to_theta()
             plan.grad(0, th, grad_out=g)
-            p.add_(0.5 * eps * g)
+            p.add_(g, alpha=0.5 * eps)
 
     run()
     torch.cuda.synchronize()

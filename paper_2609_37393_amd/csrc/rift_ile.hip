@@ -224,56 +224,75 @@ __global__ void k_select(const PointDesc* __restrict__ descs, const Tile* __rest
   }
 }
 
-// Mixed path: per-tile LSE over the final values and the bound on what the
-// unrefined samples can still be off by:
-//   err = sum_{unrefined} exp(lnL32 + lnw - M_low) (e^{bound} - 1).
+// Mixed path: per tile, the maximum m_t of the final values, their sum
+// relative to it, and the bound on what the unrefined samples can still be
+// off by, also relative to m_t:
+//   err_t = sum_{unrefined} exp(lnL32 + lnw - m_t) (e^{bound} - 1).
+// With the maximum taken first, one exp per sample serves both sums.
 __global__ void k_final(const Tile* __restrict__ tiles, const double* __restrict__ lnL,
                         const double* __restrict__ lnw, const float* __restrict__ bnd,
-                        const double* __restrict__ mlow, double* __restrict__ part,
-                        double* __restrict__ terr) {
-  __shared__ MS sh[8];
-  __shared__ double shd[8];
+                        double* __restrict__ part, double* __restrict__ terr) {
+  __shared__ double shm[8], shs[8], she[8];
   const int tidx = blockIdx.x;
   const Tile t = tiles[tidx];
-  const double ml = mlow[t.p];
-  MS acc;
-  acc.m = -__builtin_inf();
-  acc.s = 0.0;
-  double err = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double m = -__builtin_inf();  // fmax passes over NaN
   for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
     const int64_t i = t.s + o;
-    const double l = lnL[i] + (lnw ? lnw[i] : 0.0);
-    acc = ms_push(acc, l);
-    const float b = bnd[i];
-    // unrefined samples: exp(l - M_low) (e^b - 1), skipped once it underflows
-    const double lb = l + (double)b - ml;
-    if (b > 0.0f && lb > -745.0) err += exp(l - ml + log(expm1((double)b)));
+    m = fmax(m, lnL[i] + (lnw ? lnw[i] : 0.0));
   }
-  const MS r = ms_block(acc, sh);
-  err = dsum_wave(err);
+  m = dmax_wave(m);
+  if (lane == 0) shm[wave] = m;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) shd[threadIdx.x >> 6] = err;
+  m = shm[0];
+  for (int w = 1; w < nw; ++w) m = fmax(m, shm[w]);
+  double sum = 0.0, err = 0.0;
+  if (m != __builtin_inf()) {
+    for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
+      const int64_t i = t.s + o;
+      const double l = lnL[i] + (lnw ? lnw[i] : 0.0);
+      if (l != l) {
+        sum += l;  // NaN poisons the sum
+      } else if (l != -__builtin_inf()) {
+        const double x = exp(l - m);
+        sum += x;
+        const float b = bnd[i];
+        if (b > 0.0f) err += x * expm1((double)b);
+      }
+    }
+  } else {
+    sum = __builtin_nan("");  // a value of +inf: ln Z is NaN, as on the FP64 path
+  }
+  sum = dsum_wave(sum);
+  err = dsum_wave(err);
+  if (lane == 0) {
+    shs[wave] = sum;
+    she[wave] = err;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double e = shd[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) e += shd[w];
-    part[2 * tidx] = r.m;
-    part[2 * tidx + 1] = r.s;
+    double sv = shs[0], e = she[0];
+    for (int w = 1; w < nw; ++w) {
+      sv += shs[w];
+      e += she[w];
+    }
+    part[2 * tidx] = m;
+    part[2 * tidx + 1] = sv;
     terr[tidx] = e;
   }
 }
 
-// Per point: combine tile partials in a fixed order -> ln Z, n_eff, error bound.
+// Per point: combine tile partials in a fixed order -> ln Z, n_eff, and (with
+// per-tile error terms relative to each tile's maximum) the error bound.
+// The largest tile maximum M comes first; then every tile's sum and error
+// term are scaled by exp(m_t - M), the exponentials independent of each other.
 __global__ void k_merge(const PointDesc* __restrict__ descs, const int32_t* __restrict__ trange,
                         const double* __restrict__ part, const double* __restrict__ terr,
-                        const double* __restrict__ mlow, double* __restrict__ lnZ,
-                        double* __restrict__ neff, double* __restrict__ lnZ_err) {
+                        double* __restrict__ lnZ, double* __restrict__ neff, double* __restrict__ lnZ_err) {
   __shared__ double shm[8], shs[8], she[8];
   const int p = blockIdx.x;
   const int t0 = trange[2 * p], t1 = trange[2 * p + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  // the largest tile maximum first, then every tile's sum scaled to it (the
-  // exponentials independent of each other)
   double m = -__builtin_inf();
   for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) m = fmax(m, part[2 * t]);
   m = dmax_wave(m);
@@ -284,9 +303,14 @@ __global__ void k_merge(const PointDesc* __restrict__ descs, const int32_t* __re
   double sum = 0.0, err = 0.0;
   for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
     const double st = part[2 * t + 1];
-    if (m == -__builtin_inf()) sum += (st != st) ? st : 0.0;
-    else if (st != 0.0) sum += st * exp(part[2 * t] - m);
-    if (terr) err += terr[t];
+    const double et = terr ? terr[t] : 0.0;
+    if (m == -__builtin_inf()) {
+      sum += (st != st) ? st : 0.0;
+    } else if (st != 0.0 || et != 0.0) {
+      const double f = exp(part[2 * t] - m);
+      sum += st * f;
+      err += et * f;
+    }
   }
   sum = dsum_wave(sum);
   err = dsum_wave(err);
@@ -313,7 +337,7 @@ __global__ void k_merge(const PointDesc* __restrict__ descs, const int32_t* __re
     if (neff) neff[p] = (r.m == -__builtin_inf() && r.s == r.s) ? 0.0 : r.s;
     if (lnZ_err) {
       double bound = 0.0;
-      if (terr && r.s > 0.0) bound = log1p(e * exp(mlow[p] - r.m) / r.s);
+      if (terr && r.s > 0.0) bound = log1p(e / r.s);
       lnZ_err[p] = bound;
     }
   }
@@ -1425,7 +1449,7 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
       hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                          lnw, p->d_part);
     hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_part,
-                       (const double*)nullptr, (const double*)nullptr, lnZ, neff, lnZ_err);
+                       (const double*)nullptr, lnZ, neff, lnZ_err);
     HCHK(hipGetLastError());
     return RIFT_OK;
   }
@@ -1442,9 +1466,9 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
                      eval_lds_bytes(p->lset, 256, sizeof(double)), st, p->d_desc, theta, p->N,
                      (const int32_t*)p->d_cnt, (const int32_t*)p->d_list, L);
   hipLaunchKernelGGL(k_final, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
-                     lnw, (const float*)p->d_bnd, (const double*)p->d_mlow, p->d_part, p->d_terr);
+                     lnw, (const float*)p->d_bnd, p->d_part, p->d_terr);
   hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_part,
-                     (const double*)p->d_terr, (const double*)p->d_mlow, lnZ, neff, lnZ_err);
+                     (const double*)p->d_terr, lnZ, neff, lnZ_err);
   HCHK(hipGetLastError());
   return RIFT_OK;
 }
