@@ -135,6 +135,57 @@ def test_single_sample_and_all_excluded(ile, oracle_mod):
     assert z.item() == -np.inf and ne.item() == 0.0
 
 
+def test_mixed_weights_and_exclusions(ile, oracle_mod):
+    """Mixed precision with importance weights, scattered and whole-tile
+    exclusions (ln w = -inf): ln Z within 1e-3 of the oracle's and within the
+    reported bound, n_eff within that bound's relative slack."""
+    import torch
+
+    pt, _ = _point(CASES[2])
+    n = 6000
+    th, lnw = synth.weighted_samples(n, 91)
+    lnw[::97] = -np.inf
+    lnw[:2500] = -np.inf
+    l_or = oracle_mod.lnL(pt, th)
+    z_or, ne_or = oracle_mod.lnZ(l_or, lnw)
+    plan = ile.Plan([pt], [n], precision="mixed")
+    err = torch.empty(1, dtype=torch.float64, device="cuda")
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    w = torch.as_tensor(lnw, device="cuda").contiguous()
+    z, ne = plan.lnZ(tht, lnw=w, err_out=err)
+    dz = abs(z.item() - z_or)
+    assert dz <= 1e-3, dz
+    assert dz <= err.item() + 1e-9 * max(1.0, abs(z_or)), (dz, err.item())
+    assert abs(ne.item() / ne_or - 1.0) <= math.expm1(err.item()) + 1e-9, (ne.item(), ne_or)
+    plan.close()
+
+
+def test_mixed_nonfinite_single_and_all_excluded(ile, oracle_mod):
+    """Mixed precision: a NaN sample makes ln Z NaN; one sample gives its own
+    (refined) lnL; a point with every sample excluded gives -inf, n_eff 0 and
+    a zero bound."""
+    import torch
+
+    pt, th = _point(CASES[1])
+    th = th[:, :300].copy()
+    l1 = oracle_mod.lnL(pt, th[:, :1])[0]
+    plan = ile.Plan([pt], [1], precision="mixed")
+    err = torch.empty(1, dtype=torch.float64, device="cuda")
+    z, ne = plan.lnZ(torch.as_tensor(th[:, :1], device="cuda").contiguous(), err_out=err)
+    assert abs(z.item() - l1) <= 1e-9 * max(1.0, abs(l1)) and ne.item() == 1.0
+    plan.close()
+    plan = ile.Plan([pt], [300], precision="mixed")
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    w = torch.full((300,), -math.inf, dtype=torch.float64, device="cuda")
+    z, ne = plan.lnZ(tht, lnw=w, err_out=err)
+    assert z.item() == -math.inf and ne.item() == 0.0 and err.item() == 0.0
+    th_nan = th.copy()
+    th_nan[5, 7] = np.nan
+    z, _ = plan.lnZ(torch.as_tensor(th_nan, device="cuda").contiguous())
+    assert math.isnan(z.item())
+    plan.close()
+
+
 def test_batched_uneven_points(ile, oracle_mod):
     """Several points with different M, n_t and sample counts in one launch."""
     pts = synth.batched_points(7, 11, K=3, nt_range=(400, 3000))
