@@ -216,7 +216,8 @@ __global__ void k_select(const PointDesc* __restrict__ descs, const Tile* __rest
   for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
     const int64_t i = t.s + o;
     const double v = lnL[i] + (lnw ? lnw[i] : 0.0) + (double)bnd[i];
-    if (v >= thr) {
+    // (a sample at -inf adds nothing, also when the whole point is at -inf)
+    if (v >= thr && v != -__builtin_inf()) {
       const int slot = atomicAdd(cnt + t.p, 1);
       list[P->s0 + slot] = (int32_t)(i - P->s0);
       bnd[i] = -1.0f;

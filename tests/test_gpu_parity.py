@@ -179,6 +179,7 @@ def test_mixed_nonfinite_single_and_all_excluded(ile, oracle_mod):
     w = torch.full((300,), -math.inf, dtype=torch.float64, device="cuda")
     z, ne = plan.lnZ(tht, lnw=w, err_out=err)
     assert z.item() == -math.inf and ne.item() == 0.0 and err.item() == 0.0
+    assert plan.refined() == 0  # excluded samples are never recomputed
     th_nan = th.copy()
     th_nan[5, 7] = np.nan
     z, _ = plan.lnZ(torch.as_tensor(th_nan, device="cuda").contiguous())
