@@ -3,7 +3,8 @@
 //
 // Flow of one batch (Eqs. (def:lnL:Decomposed), (lnL:MonteCarlo), (neff)):
 //   plan creation (once per set of points):
-//     k_repack   Q[K][M][n_t] (paper order) -> time-major Q[KT][n_t][M] (FP64, FP32)
+//     k_repack   Q[K][M][n_t] (paper order) -> Q[KT][ceil(M/W)][n_t + 2 QPAD][W], W modes
+//                per row (FP64, FP32)
 //     k_qmax     max |Q_k| per detector (error bound of the mixed path)
 //     k_basis    harmonic-basis coefficients of the model-norm term
 //   evaluation (no allocation, no host synchronisation -> graph-capturable):
@@ -192,12 +193,11 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
 // Samples that may lie within T of the best go to the point's refine list;
 // their bound is set to -1 to mark them.  Each block first reduces its
 // point's M_low = max over the point's tiles of max(lnL32 + lnw - bound)
-// (fixed order); the block of the point's first tile stores it for the
-// kernels that follow.
+// (fixed order).
 __global__ void k_select(const PointDesc* __restrict__ descs, const Tile* __restrict__ tiles,
                          int n_tiles, const int32_t* __restrict__ trange, const double* __restrict__ tmax,
                          const double* __restrict__ lnL, const double* __restrict__ lnw,
-                         float* __restrict__ bnd, double* __restrict__ mlow, int32_t* __restrict__ cnt,
+                         float* __restrict__ bnd, int32_t* __restrict__ cnt,
                          int32_t* __restrict__ list) {
   __shared__ double sh[8];
   const int tidx = blockIdx.x;
@@ -211,7 +211,6 @@ __global__ void k_select(const PointDesc* __restrict__ descs, const Tile* __rest
   __syncthreads();
   m = sh[0];
   for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
-  if (threadIdx.x == 0 && tidx == trange[2 * t.p]) mlow[t.p] = m;
   const double thr = m - P->T;
   for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
     const int64_t i = t.s + o;
@@ -851,7 +850,6 @@ struct rift_ile_plan_s {
   double* d_terr = nullptr;     // [n_tiles]
   int32_t* d_counter = nullptr;
   // mixed scratch
-  double* d_mlow = nullptr;   // [n_points]
   int32_t* d_cnt = nullptr;   // [n_points]
   int32_t* d_list = nullptr;  // [N]
   float* d_bnd = nullptr;     // [N]
@@ -1383,8 +1381,6 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
   PCHK(palloc(p, sizeof(double) * N, &v));
   p->d_L = (double*)v;
   if (mixed) {
-    PCHK(palloc(p, sizeof(double) * n_points, &v));
-    p->d_mlow = (double*)v;
     PCHK(palloc(p, sizeof(int32_t) * n_points, &v));
     p->d_cnt = (int32_t*)v;
     PCHK(palloc(p, sizeof(int32_t) * N, &v));
@@ -1460,7 +1456,7 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
                        lnw, (const float*)p->d_bnd, p->d_tmax);
   hipLaunchKernelGGL(k_select, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_desc, p->d_tiles,
                      p->n_tiles, (const int32_t*)p->d_trange, (const double*)p->d_tmax, (const double*)L, lnw,
-                     p->d_bnd, p->d_mlow, p->d_cnt, p->d_list);
+                     p->d_bnd, p->d_cnt, p->d_list);
   refine_fn rf = pick_refine_kt(p->KT, p->lset);
   if (!rf) return RIFT_EUNSUPPORTED;
   hipLaunchKernelGGL(rf, dim3(p->refine_blocks, p->n_points), dim3(256),
