@@ -286,6 +286,7 @@ __global__ void k_final(const Tile* __restrict__ tiles, const double* __restrict
 // per-tile error terms relative to each tile's maximum) the error bound.
 // The largest tile maximum M comes first; then every tile's sum and error
 // term are scaled by exp(m_t - M), the exponentials independent of each other.
+// Launched with 512 threads (at most 8 wavefronts: the per-wave slots below).
 __global__ void k_merge(const PointDesc* __restrict__ descs, const int32_t* __restrict__ trange,
                         const double* __restrict__ part, const double* __restrict__ terr,
                         double* __restrict__ lnZ, double* __restrict__ neff, double* __restrict__ lnZ_err) {
@@ -1445,7 +1446,7 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
     if (sorted)
       hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                          lnw, p->d_part);
-    hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_part,
+    hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
                        (const double*)nullptr, lnZ, neff, lnZ_err);
     HCHK(hipGetLastError());
     return RIFT_OK;
@@ -1464,7 +1465,7 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
                      (const int32_t*)p->d_cnt, (const int32_t*)p->d_list, L);
   hipLaunchKernelGGL(k_final, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                      lnw, (const float*)p->d_bnd, p->d_part, p->d_terr);
-  hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(256), 0, st, p->d_desc, p->d_trange, p->d_part,
+  hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
                      (const double*)p->d_terr, lnZ, neff, lnZ_err);
   HCHK(hipGetLastError());
   return RIFT_OK;
