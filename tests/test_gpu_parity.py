@@ -206,6 +206,32 @@ def test_batched_uneven_points(ile, oracle_mod):
         s += c
 
 
+def test_batched_uneven_points_mixed(ile, oracle_mod):
+    """The same uneven batch in mixed precision: every point's ln Z within
+    1e-3 of the oracle's and within that point's reported bound."""
+    import torch
+
+    pts = synth.batched_points(7, 11, K=3, nt_range=(400, 3000))
+    counts = [333, 1024, 1, 2049, 700, 1500, 64]
+    th = np.concatenate([synth.prior_samples(c, 200 + i) for i, c in enumerate(counts)], axis=1)
+    lnw = np.random.default_rng(5).normal(0, 1, th.shape[1])
+    lnw[::37] = -np.inf
+    plan = ile.Plan(pts, counts, precision="mixed")
+    err = torch.empty(len(pts), dtype=torch.float64, device="cuda")
+    z, _ = plan.lnZ(torch.as_tensor(th, device="cuda").contiguous(),
+                    lnw=torch.as_tensor(lnw, device="cuda").contiguous(), err_out=err)
+    z, err = z.cpu().numpy(), err.cpu().numpy()
+    plan.close()
+    s = 0
+    for p, c in enumerate(counts):
+        l_or = oracle_mod.lnL(pts[p], th[:, s:s + c])
+        z_or, _ = oracle_mod.lnZ(l_or, lnw[s:s + c])
+        dz = abs(z[p] - z_or)
+        assert dz <= 1e-3, (p, dz)
+        assert dz <= err[p] + 1e-9 * max(1.0, abs(z_or)), (p, dz, err[p])
+        s += c
+
+
 def _near_peak(oracle_mod, snr, seed, n_prior, n_near, K=3, M=9, n_t=6554):
     th0 = np.array([1.3, -0.4, 0.9, 1.1, 2.2, 0.003, 300.0])
     pt, th0 = consistent_point(oracle_mod, K, M, n_t, 32768.0, snr, seed, th0, on_node=False, noise=True)
