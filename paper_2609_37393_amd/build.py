@@ -1,4 +1,5 @@
-"""Build librift_ile.so (HIP, gfx950) in the package directory.
+"""Build librift_ile.so (HIP, gfx950) in the package directory, and the LDS
+read-bandwidth microbenchmark `lds_peak` beside it.
 
 The evaluation kernels are instantiated per detector class and kernel kind in
 separate objects (csrc/inst.hip compiled with -DRIFT_KT, -DRIFT_KIND) so they
@@ -16,6 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librift_ile.so")
+LDS_PEAK = os.path.join(HERE, "lds_peak")  # LDS read-bandwidth microbenchmark (a program)
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -76,6 +78,12 @@ def build(verbose: bool = False, extra=None, jobs: int | None = None) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # the LDS microbenchmark behind the LDS ceiling in the measurements
+    cmd = [HIPCC, *[f for f in FLAGS if f != "-fPIC"], os.path.join(CSRC, "lds_peak.hip"), "-o", LDS_PEAK + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd, stderr=subprocess.DEVNULL if not verbose else None)
+    os.replace(LDS_PEAK + ".tmp", LDS_PEAK)
     return LIB
 
 
