@@ -191,6 +191,17 @@ def run_path(ile, torch, pt, tht, precision, steps, warmup, tune, variants=True,
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(pt, th, gpu_lnL, budget_s=12.0):
     """The FP64 oracle as it stands, on this host, for about `budget_s` seconds:
     consecutive chunks of the same samples, wrapping round to the start if the
@@ -213,6 +224,15 @@ def cpu_baseline(pt, th, gpu_lnL, budget_s=12.0):
         done += c
         pos = (pos + c) % n
     el = time.perf_counter() - t0
+    # one thread, on a shorter prefix of the same samples
+    t1 = time.perf_counter()
+    done1, pos1 = 0, 0
+    while time.perf_counter() - t1 < budget_s / 4:
+        c = min(5000, n - pos1)
+        oracle.lnL(pt, th[:, pos1:pos1 + c], nthreads=1)
+        done1 += c
+        pos1 = (pos1 + c) % n
+    el1 = time.perf_counter() - t1
     l_or = np.concatenate(first)[:n]
     m = l_or.size
     d = np.abs(gpu_lnL[:m] - l_or)
@@ -223,6 +243,8 @@ def cpu_baseline(pt, th, gpu_lnL, budget_s=12.0):
         "cores": nthreads,
         "kind": "oracle",
         "sample": f"{done} evaluations ({passes:.2f} passes over the {n} samples of the same workload) in {el:.1f} s",
+        "single_thread": {"value": done1 / el1, "sample": f"{done1} evaluations in {el1:.1f} s, 1 thread"},
+        "cpu_model": _cpu_model(),
     }, {
         "samples": int(m),
         "max_abs_dlnL": float(d.max()),
