@@ -261,8 +261,13 @@ def extra_c1(ile, synth, torch, steps):
     for n in (10_000, 10_000_000):
         th = torch.as_tensor(synth.prior_samples(n, 1), device="cuda").contiguous()
         r = run_path(ile, torch, pt, th, "fp64", steps, 3, tune=False)
+        ks = r["kernel_ms_avg"] / 1e3
+        # against its own roofline: 64 algorithmic HBM bytes per sample (theta
+        # in, lnL out) and the FP64 vector peak; HBM-bound at N = 1e7
         res[f"n{n}"] = {"lnL_evals_per_s": n * steps / r["secs"], "ms_per_step": 1e3 * r["secs"] / steps,
-                        "kernel_ms": r["kernel_ms_avg"]}
+                        "kernel_ms": r["kernel_ms_avg"],
+                        "hbm_frac": 64.0 * n / ks / (PEAK_HBM_GBS * 1e9),
+                        "alu_frac": flops_per_sample(2, 2, 2) * n / ks / (PEAK_FP64_TFLOPS * 1e12)}
         del th
     return res
 
