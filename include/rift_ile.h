@@ -141,7 +141,7 @@ typedef struct rift_ile_plan_s *rift_ile_plan;
 /* Prepare n_points points for batches whose point p has n_per_point[p]
  * samples (HOST array, each >= 1).  Enqueues the preparation on `stream`
  * (device memory for the plan is allocated synchronously).  *out receives the
- * plan.  The initial launch shape is {256, 4, 4, 0}, or for a batch too small
+ * plan.  The initial launch shape is {256, 4, 0, 0}, or for a batch too small
  * to give every CU two 1024-sample tiles, one-block tiles of 64 to 256 samples
  * (rift_ile_plan_get_config reports it). */
 int rift_ile_plan_create(const rift_ile_point *pts, int32_t n_points, const int64_t *n_per_point,

@@ -841,7 +841,7 @@ struct rift_ile_plan_s {
   PointDesc* d_desc = nullptr;
   std::vector<void*> bufs;  // device allocations owned by the plan
   // tiles (depend on the config)
-  rift_ile_config cfg{256, 4, 4, 0};
+  rift_ile_config cfg{256, 4, 0, 0};
   std::vector<Tile> h_tiles;
   Tile* d_tiles = nullptr;
   int n_tiles = 0;
