@@ -456,7 +456,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--extras", action="store_true", help="also run the C1/C3/C4/C5 workloads")
+    ap.add_argument("--extras", nargs="?", const="c1,c4,c5,c3", default="",
+                    help="also run the C1/C3/C4/C5 workloads (all, or a comma list such as c4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--warm-s", type=float, default=0.3,
@@ -561,7 +562,10 @@ def main():
         out["cpu_baseline"] = cb
         out["parity"] = par
     if args.extras:
+        wanted = {x.strip() for x in args.extras.split(",") if x.strip()}
         for name, fn in (("c1", extra_c1), ("c4", extra_c4), ("c5", extra_c5), ("c3", extra_c3)):
+            if name not in wanted:
+                continue
             log(f"extra {name}")
             try:
                 out[name] = fn(ile, synth, torch, max(3, args.steps // 10))
