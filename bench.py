@@ -341,25 +341,17 @@ def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64):
     sigt = torch.as_tensor(sig, device="cuda")[:, None]
     eps = 0.1
     step_q = (eps * sigt * sigt).expand_as(p).contiguous()  # eps sigma^2, per parameter
-    th = torch.empty_like(q)
     g = torch.empty_like(q)
-    ci = torch.empty_like(q[3])
 
-    # one fused elementwise launch per update where torch has one
-    def to_theta():
-        th.copy_(cq)
-        torch.clamp(cq[3], -1 + 1e-12, 1 - 1e-12, out=ci)
-        torch.arccos(ci, out=th[3])
-        torch.exp(cq[6], out=th[6])
-
+    # the chain moves in (.., cos incl, .., .., ln dist), the coordinates of
+    # the gradient, and hands them to the library as they are; one fused
+    # elementwise launch per leapfrog update
     def run():
-        to_theta()
-        plan.grad(0, th, grad_out=g)
+        plan.grad(0, cq, grad_out=g, sampler_coords=True)
         for _ in range(nsteps - 1):
             p.add_(g, alpha=0.5 * eps)
             cq.addcmul_(step_q, p)
-            to_theta()
-            plan.grad(0, th, grad_out=g)
+            plan.grad(0, cq, grad_out=g, sampler_coords=True)
             p.add_(g, alpha=0.5 * eps)
 
     run()

@@ -157,6 +157,14 @@ int rift_ile_plan_lnZ(rift_ile_plan plan, const double *theta, const double *lnw
 int rift_ile_plan_grad(rift_ile_plan plan, int32_t point, int64_t n, const double *theta,
                        double *lnL, double *grad, void *stream);
 
+/* As rift_ile_plan_grad, with theta given in the coordinates the gradient is
+ * taken in (for gradient-based samplers that move in them): rows 3 and 6 hold
+ * cos(incl) and ln(dist) instead of incl and dist.  cos(incl) is clamped to
+ * |cos(incl)| <= 1 - 1e-12, where the derivative in it stays finite.  Same
+ * layout, ownership and errors as rift_ile_plan_grad. */
+int rift_ile_plan_grad_sampler(rift_ile_plan plan, int32_t point, int64_t n, const double *theta,
+                               double *lnL, double *grad, void *stream);
+
 /* Autotuner: time the candidate launch shapes on this batch and keep the
  * fastest (synchronises `stream`; not capturable). Returns the chosen index. */
 int rift_ile_plan_tune(rift_ile_plan plan, const double *theta, const double *lnw, void *stream);

@@ -349,19 +349,32 @@ __global__ void __launch_bounds__(256) k_refine(const PointDesc* __restrict__ de
   else if ((LSET & 8) && L == 8) refine_point<KT, 8>(P, theta, N, cnt, list, lnL, p, trig, wtab, stage);
 }
 
+// Rows 3 and 6 of theta: (incl, dist), or with `coords` set the coordinates
+// the gradient is taken in, (cos incl, ln dist).  cos incl is clamped to
+// |cos incl| <= 1 - 1e-12, where the m = +-1 terms of d/d cos incl are finite.
+__device__ __forceinline__ void theta_coords(int coords, double& incl, double& dist) {
+  if (coords) {
+    incl = acos(fmin(fmax(incl, -1.0 + 1e-12), 1.0 - 1e-12));
+    dist = exp(dist);
+  }
+}
+
 // Gradient: one lane per sample, grid-stride.
 template <int KT, int L>
 __global__ void __launch_bounds__(256) k_grad(const PointDesc* __restrict__ P,
                                               const double* __restrict__ theta, int64_t n,
-                                              double* __restrict__ lnL, double* __restrict__ grad) {
+                                              double* __restrict__ lnL, double* __restrict__ grad,
+                                              int coords) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* trig = reinterpret_cast<double*>(smem) + threadIdx.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const RIFT_GLOBAL double* th = as_global(theta) + i;
+    double incl = th[3 * n], dist = th[6 * n];
+    theta_coords(coords, incl, dist);
     double g[7];
-    const double l = eval_grad<KT, L>(opaque(P), trig, blockDim.x, th[0], th[n], th[2 * n], th[3 * n],
-                                      th[4 * n], th[5 * n], th[6 * n], g);
+    const double l = eval_grad<KT, L>(opaque(P), trig, blockDim.x, th[0], th[n], th[2 * n], incl,
+                                      th[4 * n], th[5 * n], dist, g);
     if (lnL) as_global_w(lnL)[i] = l;
 #pragma unroll
     for (int a = 0; a < 7; ++a) as_global_w(grad)[a * n + i] = g[a];
@@ -377,7 +390,8 @@ constexpr int GRAD_G = 16;
 template <int KT, int L>
 __global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__ P,
                                                    const double* __restrict__ theta, int64_t n,
-                                                   double* __restrict__ lnL, double* __restrict__ grad) {
+                                                   double* __restrict__ lnL, double* __restrict__ grad,
+                                                   int coords) {
   constexpr int SPW = 64 / GRAD_G;  // samples per wavefront
   __shared__ double tabs[4 * SPW * GRAD_TAB(L, KT)];
   const int lg = (int)(threadIdx.x & (GRAD_G - 1));
@@ -389,9 +403,11 @@ __global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__
     const bool live = ib + gw < n;
     const int64_t i = live ? ib + gw : n - 1;
     const RIFT_GLOBAL double* th = as_global(theta) + i;
+    double incl = th[3 * n], dist = th[6 * n];
+    theta_coords(coords, incl, dist);
     double g[7];
-    const double l = eval_grad_group<KT, L, GRAD_G>(opaque(P), th[0], th[n], th[2 * n], th[3 * n], th[4 * n],
-                                                    th[5 * n], th[6 * n], tab, g);
+    const double l = eval_grad_group<KT, L, GRAD_G>(opaque(P), th[0], th[n], th[2 * n], incl, th[4 * n],
+                                                    th[5 * n], dist, tab, g);
     if (live) {
       if (lg == 0 && lnL) as_global_w(lnL)[i] = l;
       double v = g[0];
@@ -404,7 +420,7 @@ __global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__
 
 typedef void (*tile_fn)(TileArgs);
 typedef void (*refine_fn)(const PointDesc*, const double*, int64_t, const int32_t*, const int32_t*, double*);
-typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, double*);
+typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, double*, int);
 
 // Getters (one translation unit per detector class and kernel kind).
 #define RIFT_DECL_GETTERS(KT)                        \

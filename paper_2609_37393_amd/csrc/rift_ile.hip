@@ -1482,8 +1482,8 @@ int rift_ile_plan_refined(rift_ile_plan p, int64_t* n_refined) {
   return RIFT_OK;
 }
 
-int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, double* lnL,
-                       double* grad, void* stream) {
+static int plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, int coords, double* lnL,
+              double* grad, void* stream) {
   if (!p || point < 0 || point >= p->n_points || n < 0) return RIFT_EINVAL;
   if (n == 0) return RIFT_OK;
   if (check_dev_ptr(theta) || check_dev_ptr(grad) || (lnL && check_dev_ptr(lnL))) return RIFT_EINVAL;
@@ -1507,10 +1507,20 @@ int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* 
   }
   hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), shm, st,
                      (const PointDesc*)(p->d_desc + point),
-                     theta, n, lnL, grad);
+                     theta, n, lnL, grad, coords);
   HCHK(hipGetLastError());
   if (p->profiling) HCHK(hipEventRecord(e1, st));
   return RIFT_OK;
+}
+
+int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, double* lnL,
+                       double* grad, void* stream) {
+  return plan_grad(p, point, n, theta, 0, lnL, grad, stream);
+}
+
+int rift_ile_plan_grad_sampler(rift_ile_plan p, int32_t point, int64_t n, const double* theta,
+                               double* lnL, double* grad, void* stream) {
+  return plan_grad(p, point, n, theta, 1, lnL, grad, stream);
 }
 
 int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, void* stream) {

@@ -29,6 +29,7 @@ EXPORTS = (
     "rift_ile_plan_create",
     "rift_ile_plan_lnZ",
     "rift_ile_plan_grad",
+    "rift_ile_plan_grad_sampler",
     "rift_ile_plan_tune",
     "rift_ile_plan_get_config",
     "rift_ile_plan_set_config",
@@ -83,6 +84,7 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_plan_create.argtypes = [P, i32, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.rift_ile_plan_lnZ.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rift_ile_plan_grad.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+    lib.rift_ile_plan_grad_sampler.argtypes = [vp, i32, i64, vp, vp, vp, vp]
     lib.rift_ile_plan_tune.argtypes = [vp, vp, vp, vp]
     lib.rift_ile_plan_get_config.argtypes = [vp, ctypes.POINTER(CConfig)]
     lib.rift_ile_plan_set_config.argtypes = [vp, ctypes.POINTER(CConfig)]
@@ -258,14 +260,18 @@ class Plan:
                                           _stream(self.device)), "rift_ile_plan_lnZ")
         return z, ne
 
-    def grad(self, point, theta, lnL_out=None, grad_out=None):
+    def grad(self, point, theta, lnL_out=None, grad_out=None, sampler_coords=False):
+        """Gradient of lnL in (ra, dec, psi, cos incl, phiref, tref, ln dist).
+        With sampler_coords, rows 3 and 6 of theta hold cos incl and ln dist
+        (rift_ile_plan_grad_sampler) instead of incl and dist."""
         th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
             else _theta(theta, self.device)
         n = th.shape[1]
         g = grad_out if grad_out is not None else torch.empty((7, n), dtype=torch.float64, device=self.device)
-        _check(self.lib.rift_ile_plan_grad(self.handle, int(point), n, th.data_ptr(),
-                                           None if lnL_out is None else lnL_out.data_ptr(), g.data_ptr(),
-                                           _stream(self.device)), "rift_ile_plan_grad")
+        fn = self.lib.rift_ile_plan_grad_sampler if sampler_coords else self.lib.rift_ile_plan_grad
+        _check(fn(self.handle, int(point), n, th.data_ptr(),
+                  None if lnL_out is None else lnL_out.data_ptr(), g.data_ptr(),
+                  _stream(self.device)), "rift_ile_plan_grad")
         return g
 
     def tune(self, theta, lnw=None) -> int:

@@ -334,6 +334,44 @@ def test_gradient_lane_and_group_forms(ile, oracle_mod):
             assert rel.max() < 1e-7, (name, a, rel.max())
 
 
+def test_gradient_in_sampler_coordinates(ile, oracle_mod):
+    """theta given as (.., cos incl, .., .., ln dist) through
+    rift_ile_plan_grad_sampler, in both kernel forms: lnL and the gradient
+    match the oracle at the same point given as (incl, dist)."""
+    import torch
+
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    n_big = 256 * n_cu + 1000
+    pt = synth.make_point(3, 9, 6554, 32768.0, 600.0, 3)
+    th = synth.prior_samples(n_big, 73)
+    th[3] = np.clip(th[3], 0.05, np.pi - 0.05)
+    ts = th.copy()
+    ts[3] = np.cos(th[3])
+    ts[6] = np.log(th[6])
+    # the point the oracle sees: the same conversion back, as the kernel makes it
+    tb = th.copy()
+    tb[3] = np.arccos(ts[3])
+    tb[6] = np.exp(ts[6])
+    idx = np.linspace(0, n_big - 1, 400).astype(np.int64)
+    sub = np.ascontiguousarray(tb[:, idx])
+    l_or, g_or = oracle_mod.grad(pt, sub)
+    S = lnL_scale(oracle_mod, pt, sub)
+    for name, x in (("lane", ts), ("group", np.ascontiguousarray(ts[:, idx]))):
+        n = x.shape[1]
+        plan = ile.Plan([pt], [n])
+        xt = torch.as_tensor(x, device="cuda").contiguous()
+        ll = torch.empty(n, dtype=torch.float64, device="cuda")
+        g = plan.grad(0, xt, lnL_out=ll, sampler_coords=True).cpu().numpy()
+        ll = ll.cpu().numpy()
+        plan.close()
+        if name == "lane":
+            g, ll = g[:, idx], ll[idx]
+        assert np.all(np.abs(ll - l_or) <= 1e-9 * S + 1e-12), name
+        for a in range(7):
+            rel = np.abs(g[a] - g_or[a]) / (np.abs(g_or[a]) + 1e-6 * S + 1e-9)
+            assert rel.max() < 1e-7, (name, a, rel.max())
+
+
 def test_autograd_function(ile, oracle_mod):
     import torch
 
