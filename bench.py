@@ -29,8 +29,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "extrinsic lnL evals/sec (+ grad evals/sec) at |ΔlnL|≤1e-3 vs FP64 oracle"
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
-PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (packed); unpacked issue is half of it
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector, packed (dual-issue) instructions
+# The build keeps packed FP32 instructions out of its code, so the FP32 pass's
+# attainable vector peak is the unpacked rate, the same as FP64's.
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+
+
+def survey_flops_per_sample(K, M):
+    """Algorithmic flops of one lnL evaluation, counted on the method's own
+    Hermitian/symmetric-reduced forms (P = M(M+1)/2 mode pairs):
+    40 (sky frame) + 57 K (antenna, delay, stencil weights) + 10 M (harmonics)
+    + 6 K M (coefficients x F Y) + 20 K M (Lagrange read and data term)
+    + 8 K P (the two quadratic forms) + P.  Transcendentals not counted."""
+    P = M * (M + 1) // 2
+    return 40 + 57 * K + 10 * M + 6 * K * M + 20 * K * M + 8 * K * P + P
 
 
 def lclass(lmax):
@@ -43,8 +56,9 @@ def basis_count(L):
 
 
 def flops_per_sample(K, M, lmax):
-    """Algorithmic flops of one lnL evaluation in this formulation (FMA = 2),
-    transcendentals (5 sincos) not included.  See the design notes."""
+    """Flops of one lnL evaluation as this build computes it (FMA = 2; the
+    model-norm term as the harmonic-basis contraction), transcendentals (5
+    sincos) not included.  Reported beside the algorithmic count."""
     L = lclass(lmax)
     NI = 2 * L
     B = basis_count(L)
@@ -255,24 +269,48 @@ def cpu_baseline(pt, th, gpu_lnL, budget_s=12.0):
 # ---------------------------------------------------------------------------
 # Extra configurations
 # ---------------------------------------------------------------------------
-def extra_c1(ile, synth, torch, steps):
+def _c1_run(ile, synth, torch, steps, n):
     pt = synth.make_point(2, 2, 410, 4096.0, 20.0, 1)
-    res = {}
-    for n in (10_000, 10_000_000):
-        th = torch.as_tensor(synth.prior_samples(n, 1), device="cuda").contiguous()
-        r = run_path(ile, torch, pt, th, "fp64", steps, 3, tune=False)
-        ks = r["kernel_ms_avg"] / 1e3
-        # against its own roofline: 64 algorithmic HBM bytes per sample (theta
-        # in, lnL out) and the FP64 vector peak; HBM-bound at N = 1e7
-        res[f"n{n}"] = {"lnL_evals_per_s": n * steps / r["secs"], "ms_per_step": 1e3 * r["secs"] / steps,
-                        "kernel_ms": r["kernel_ms_avg"],
-                        "hbm_frac": 64.0 * n / ks / (PEAK_HBM_GBS * 1e9),
-                        "alu_frac": flops_per_sample(2, 2, 2) * n / ks / (PEAK_FP64_TFLOPS * 1e12)}
-        del th
+    th = torch.as_tensor(synth.prior_samples(n, 1), device="cuda").contiguous()
+    r = run_path(ile, torch, pt, th, "fp64", steps, 3, tune=False, variants=False)
+    ks = r["kernel_ms_avg"] / 1e3
+    # against its own roofline: 64 algorithmic HBM bytes per sample (theta in,
+    # lnL out) and the FP64 vector peak
+    res = {"n": n, "lnL_evals_per_s": n * steps / r["secs"], "ms_per_step": 1e3 * r["secs"] / steps,
+           "kernel_ms": r["kernel_ms_avg"],
+           "hbm_frac": 64.0 * n / ks / (PEAK_HBM_GBS * 1e9),
+           "alu_frac": survey_flops_per_sample(2, 2) * n / ks / (PEAK_FP64_TFLOPS * 1e12)}
+    # the same step captured into a HIP graph and replayed (launch overhead)
+    plan = ile.Plan([pt], [n])
+    z = torch.empty(1, dtype=torch.float64, device="cuda")
+    lnl = torch.empty(n, dtype=torch.float64, device="cuda")
+    plan.lnZ(th, lnZ_out=z, lnL_out=lnl)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(16):
+            plan.lnZ(th, lnZ_out=z, lnL_out=lnl)
+    secs, _ = time_steps(g.replay, max(3, steps // 4), 2, torch)
+    res["graph16"] = {"lnL_evals_per_s": 16 * n * max(3, steps // 4) / secs,
+                      "ms_per_step": 1e3 * secs / (16 * max(3, steps // 4))}
+    plan.close()
     return res
 
 
-def extra_c3(ile, synth, torch, steps, n_points=512, per_point=200_000):
+def extra_c1(ile, synth, torch, steps, cpu=True):
+    """2 detectors, (2,+-2), 410 samples at 4096 Hz, SNR 20, 1e4 prior samples
+    (launch-bound at this size; also reported as 16 steps in one graph)."""
+    return _c1_run(ile, synth, torch, steps, 10_000)
+
+
+def extra_c1_big(ile, synth, torch, steps, cpu=True):
+    """The C1 point at 1e7 samples (steady state for its roofline)."""
+    return _c1_run(ile, synth, torch, steps, 10_000_000)
+
+
+def extra_c3(ile, synth, torch, steps, n_points=512, per_point=200_000, cpu=True):
     """512 points, M ~ U{2,4,9,16,21}, n_t ~ U[400, 6554] at 32768 Hz, K = 3,
     SNR log-U[20, 1000], 2e5 samples each; one graph-captured launch set."""
     rng = np.random.default_rng(3)
@@ -301,7 +339,7 @@ def extra_c3(ile, synth, torch, steps, n_points=512, per_point=200_000):
         th[:, s:s + c] = torch.as_tensor(synth.prior_samples(c, 1000 + s // chunk), device="cuda")
     res = {}
     M_of = [int(p["lm"].shape[0]) for p in pts]
-    flops = sum(flops_per_sample(3, M, int(p["lm"][:, 0].max())) * c for p, M, c in zip(pts, M_of, counts))
+    flops = sum(survey_flops_per_sample(3, M) * c for M, c in zip(M_of, counts))
     for prec in ("fp64", "mixed"):
         plan = ile.Plan(pts, counts, precision=prec)
         choice = plan.tune(th)
@@ -317,14 +355,14 @@ def extra_c3(ile, synth, torch, steps, n_points=512, per_point=200_000):
         secs, _ = time_steps(g.replay, steps, 1, torch)
         res[prec] = {"lnL_evals_per_s": N * steps / secs, "ms_per_step": 1e3 * secs / steps,
                      "tuned_config": plan.config, "tuner_choice": choice,
-                     "alu_frac": flops * steps / secs / (1e12 * (PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS))}
+                     "alu_frac": flops * steps / secs / (1e12 * (PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_UNPACKED_TFLOPS))}
         if prec == "mixed":
             res[prec]["refined"] = plan.refined()
         plan.close()
     return res
 
 
-def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64):
+def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64, cpu=True):
     """4096 chains x 64 leapfrog-style gradient evaluations (K = 3, 9 modes,
     SNR 600), the 64 steps captured into one graph."""
     pt = synth.make_point(3, 9, 6554, 32768.0, 600.0, 4)
@@ -347,11 +385,11 @@ def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64):
     # the gradient, and hands them to the library as they are; one fused
     # elementwise launch per leapfrog update
     def run():
-        plan.grad(0, cq, grad_out=g, sampler_coords=True)
+        plan.grad(0, cq, grad_out=g, coords="sampler")
         for _ in range(nsteps - 1):
             p.add_(g, alpha=0.5 * eps)
             cq.addcmul_(step_q, p)
-            plan.grad(0, cq, grad_out=g, sampler_coords=True)
+            plan.grad(0, cq, grad_out=g, coords="sampler")
             p.add_(g, alpha=0.5 * eps)
 
     run()
@@ -367,42 +405,90 @@ def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64):
     run()
     kms, launches = plan.profile_read()
     plan.profile(False)
+    finite = bool(torch.isfinite(g).all().item())
     plan.close()
     evals = chains * nsteps
-    return {"grad_evals_per_s": evals * steps / secs, "ms_per_graph": 1e3 * secs / steps,
-            "kernel_ms_avg": kms / max(1, launches), "chains": chains, "steps_per_chain": nsteps}
+    res = {"grad_evals_per_s": evals * steps / secs, "ms_per_graph": 1e3 * secs / steps,
+           "kernel_ms_avg": kms / max(1, launches), "chains": chains, "steps_per_chain": nsteps,
+           "chain_states_finite": finite,
+           "workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 600; "
+                       "4096 chains x 64 gradient evaluations in one graph"}
+    if cpu:
+        import oracle
+
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < 3.0:
+            oracle.grad(pt, start[:, :1024])
+            done += 1024
+        res["cpu_oracle_grad_evals_per_s"] = done / (time.perf_counter() - t0)
+    return res
 
 
-def extra_c5(ile, synth, torch, steps, n_batch=64, per_point=200_000):
+def extra_c5(ile, synth, torch, steps, cpu=True):
     """K = 5 (two 40-km-class), 21 modes, 13108 samples at 32768 Hz, SNR 1000:
-    1e7 samples in 10 chunks of 1e6 (ln Z merged), FP64 and mixed precision;
-    plus a 64-point batch of 2e5 samples each (16 intrinsic points at 4 SNR
-    scalings, 400 to 1000), with its mixed-precision ln Z difference from the
-    FP64 path and the largest reported bound over the points."""
+    1e7 prior samples in 10 chunks of 1e6 (ln Z merged), FP64 and mixed
+    precision, with the merged ln Z of both against the FP64 oracle's over the
+    same 1e7 samples."""
     net = synth.network(5, 5)
     pt = synth.make_point(5, 21, 13108, 32768.0, 1000.0, 5, net=net)
     n = 10_000_000
+    ths = [synth.prior_samples(2_000_000, 500 + j) for j in range(5)]
     th = torch.empty((7, n), dtype=torch.float64, device="cuda")
-    for s in range(0, n, 2_000_000):
-        th[:, s:s + 2_000_000] = torch.as_tensor(synth.prior_samples(2_000_000, 500 + s // 2_000_000), device="cuda")
-    res = {}
+    for j in range(5):
+        th[:, j * 2_000_000:(j + 1) * 2_000_000] = torch.as_tensor(ths[j], device="cuda")
+    res = {"workload": "5 detectors, 21 modes (l<=4), Q 13108 samples at 32768 Hz, SNR 1000, "
+                       "1e7 prior samples in 10 chunks of 1e6"}
     chunks = [1_000_000] * 10
-    fps = flops_per_sample(5, 21, 4)
+    fps = survey_flops_per_sample(5, 21)
+    zs = {}
     for prec in ("fp64", "mixed"):
         # ten chunks as ten "points" sharing the tables: one launch, then an LSE merge
         plan = ile.Plan([pt] * 10, chunks, precision=prec)
         plan.tune(th)
         z = torch.empty(10, dtype=torch.float64, device="cuda")
-        plan.lnZ(th, lnZ_out=z)
-        secs, _ = time_steps(lambda: plan.lnZ(th, lnZ_out=z), steps, 1, torch)
+        err = torch.empty(10, dtype=torch.float64, device="cuda")
+        plan.lnZ(th, lnZ_out=z, err_out=err)
+        secs, _ = time_steps(lambda: plan.lnZ(th, lnZ_out=z, err_out=err), steps, 1, torch)
+        plan.profile(True)
+        plan.lnZ(th, lnZ_out=z, err_out=err)
+        kms, nl = plan.profile_read()
+        plan.profile(False)
         zz = z.cpu().numpy()
         m = zz.max()
+        zs[prec] = float(m + math.log(np.mean(np.exp(zz - m))))
+        peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_UNPACKED_TFLOPS
         res[prec] = {"lnL_evals_per_s": n * steps / secs, "ms_per_step": 1e3 * secs / steps,
-                     "lnZ": float(m + math.log(np.mean(np.exp(zz - m)))), "tuned_config": plan.config,
-                     "alu_frac": fps * n * steps / secs / (1e12 * (PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS))}
+                     "kernel_ms": kms / max(1, nl), "lnZ": zs[prec], "tuned_config": plan.config,
+                     "alu_frac": fps * n / (kms / max(1, nl) / 1e3) / (1e12 * peak)}
+        if prec == "mixed":
+            res[prec]["refined"] = plan.refined()
+            res[prec]["lnZ_err_bound"] = float(err.max().item())
         plan.close()
+    res["speedup_mixed_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    res["dlnZ_mixed_vs_fp64"] = abs(zs["mixed"] - zs["fp64"])
+    if cpu:
+        import oracle
+
+        t0 = time.perf_counter()
+        l_or = np.concatenate([oracle.lnL(pt, t) for t in ths])
+        zc = [oracle.lnZ(l_or[j * 1_000_000:(j + 1) * 1_000_000])[0] for j in range(10)]
+        m = max(zc)
+        z_or = m + math.log(np.mean(np.exp(np.array(zc) - m)))
+        res["oracle_lnZ"] = z_or
+        res["dlnZ_fp64_vs_oracle"] = abs(zs["fp64"] - z_or)
+        res["dlnZ_mixed_vs_oracle"] = abs(zs["mixed"] - z_or)
+        res["oracle_s"] = time.perf_counter() - t0
     del th
-    # the 64-point batch
+    return res
+
+
+def extra_c5_batch(ile, synth, torch, steps, n_batch=64, per_point=200_000, cpu=True):
+    """64 intrinsic points of the 5-detector network (16 points at 4 SNR
+    scalings, 400 to 1000), 2e5 samples each, with the mixed-precision ln Z
+    difference from the FP64 path and the largest reported bound."""
+    net = synth.network(5, 5)
+    fps = survey_flops_per_sample(5, 21)
     base = [synth.make_point(5, 21, 13108, 32768.0, 1000.0, 900 + b, net=net) for b in range(n_batch // 4)]
     pts = []
     for b in base:
@@ -428,9 +514,9 @@ def extra_c5(ile, synth, torch, steps, n_batch=64, per_point=200_000):
         plan.lnZ(thb, lnZ_out=z, err_out=err)
         secs, _ = time_steps(lambda: plan.lnZ(thb, lnZ_out=z, err_out=err), steps, 1, torch)
         zb[prec] = z.cpu().numpy()
+        peak = PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_UNPACKED_TFLOPS
         batch[prec] = {"lnL_evals_per_s": N * steps / secs, "ms_per_step": 1e3 * secs / steps,
-                       "tuned_config": plan.config,
-                       "alu_frac": fps * N * steps / secs / (1e12 * (PEAK_FP64_TFLOPS if prec == "fp64" else PEAK_FP32_TFLOPS))}
+                       "tuned_config": plan.config, "alu_frac": fps * N * steps / secs / (1e12 * peak)}
         if prec == "mixed":
             batch[prec]["max_lnZ_err_bound"] = float(err.max().item())
             batch[prec]["refined"] = plan.refined()
@@ -438,8 +524,7 @@ def extra_c5(ile, synth, torch, steps, n_batch=64, per_point=200_000):
     batch["max_abs_dlnZ_mixed_vs_fp64"] = float(np.abs(zb["mixed"] - zb["fp64"]).max())
     batch["points"] = len(pts)
     batch["samples_per_point"] = per_point
-    res["batch64"] = batch
-    return res
+    return batch
 
 
 def main():
@@ -448,8 +533,12 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--extras", nargs="?", const="c1,c4,c5,c3", default="",
-                    help="also run the C1/C3/C4/C5 workloads (all, or a comma list such as c4)")
+    ap.add_argument("--workloads", default="c1,c4,c5",
+                    help="workloads timed beside the headline one (comma list of c1, c4, c5, c3, c1big; "
+                         "'none' for the headline alone)")
+    ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
+                    help="add the longer workloads (the 512-point batch c3, C1 at 1e7 samples c1big, "
+                         "the 64-point 5-detector batch c5batch)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--warm-s", type=float, default=0.3,
@@ -476,6 +565,7 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     ile.load()
+    t_start = time.perf_counter()
     n = args.samples
     log(f"building inputs (n = {n})")
     pt, th = c2_inputs(synth, n)
@@ -494,10 +584,12 @@ def main():
     r32 = run_path(ile, torch, pt, tht, "mixed", args.steps, args.warmup, tune=not args.no_tune,
                    variants=not args.no_variants, config=fixed)
 
-    fps = flops_per_sample(K, M, lmax)
+    fps = survey_flops_per_sample(K, M)
+    fps_own = flops_per_sample(K, M, lmax)
     value = n * args.steps / r64["secs"]
     kern_s = r64["kernel_ms_avg"] / 1e3
     achieved = fps * n / kern_s / 1e12
+    kern32_s = r32["kernel_ms_avg"] / 1e3
     out = {
         "metric": METRIC,
         "value": value,
@@ -528,14 +620,18 @@ def main():
             "kernel": "k_tiles<double,3,4,MODE_LSE64>",
             "kernel_ms_avg": r64["kernel_ms_avg"],
             "flops_per_sample": fps,
+            "flops_per_sample_formulation": fps_own,
+            "frac_formulation": fps_own * n / kern_s / 1e12 / PEAK_FP64_TFLOPS,
             "hbm_bytes_per_sample": bytes_per_sample(),
         },
         "mixed": {
             "lnL_evals_per_s": n * args.steps / r32["secs"],
             "ms_per_step": 1e3 * r32["secs"] / args.steps,
             "speedup_vs_fp64": r64["secs"] / r32["secs"],
+            "kernel": "k_tiles<float,3,4,MODE_PASS32>",
             "kernel_ms_avg": r32["kernel_ms_avg"],
-            "alu_frac_of_fp32_peak": fps * n / (r32["kernel_ms_avg"] / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+            "alu_frac_fp32_pass": fps * n / kern32_s / 1e12 / PEAK_FP32_UNPACKED_TFLOPS,
+            "alu_peak_fp32_pass": PEAK_FP32_UNPACKED_TFLOPS,
             "refined_samples": r32["refined"],
             "dlnZ_vs_fp64": abs(r32["lnZ"] - r64["lnZ"]),
             "lnZ_err_bound": r32["lnZ_err_bound"],
@@ -548,22 +644,25 @@ def main():
     l32 = r32["lnL"].cpu().numpy()
     top = gpu_lnL >= gpu_lnL.max() - 20.0
     out["mixed"]["max_dlnL_posterior_set_vs_fp64"] = float(np.abs(l32[top] - gpu_lnL[top]).max())
+    del r64, r32
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         cb, par = cpu_baseline(pt, th, gpu_lnL)
         out["cpu_baseline"] = cb
         out["parity"] = par
-    if args.extras:
-        wanted = {x.strip() for x in args.extras.split(",") if x.strip()}
-        for name, fn in (("c1", extra_c1), ("c4", extra_c4), ("c5", extra_c5), ("c3", extra_c3)):
-            if name not in wanted:
-                continue
-            log(f"extra {name}")
-            try:
-                out[name] = fn(ile, synth, torch, max(3, args.steps // 10))
-            except Exception as e:  # report, keep the headline line
-                out[name] = {"error": repr(e)}
-            torch.cuda.empty_cache()
+    del tht
+    torch.cuda.empty_cache()
+    wanted = [x.strip() for x in args.workloads.split(",") if x.strip() and x.strip() != "none"]
+    wanted += [x.strip() for x in args.extras.split(",") if x.strip()]
+    fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
+           "c5batch": extra_c5_batch}
+    for name in wanted:
+        log(f"workload {name}")
+        try:
+            out[name] = fns[name](ile, synth, torch, max(3, args.steps // 10), cpu=not args.no_cpu)
+        except Exception as e:  # report, keep the headline line
+            out[name] = {"error": repr(e)}
+        torch.cuda.empty_cache()
     if args.calib_copy:
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -571,6 +670,7 @@ def main():
         for _ in range(3):
             torch.add(a, 0.0, out=b)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
+    out["bench_wall_s"] = time.perf_counter() - t_start
     print(json.dumps(out), flush=True)
 
 

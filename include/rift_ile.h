@@ -20,8 +20,9 @@
  *   ln Z = ln[ (1/N) sum_i exp(lnL_i + lnw_i) ],   lnw_i = ln(p/p_s) of sample i,
  *
  * and the effective sample size of Eq. (neff), n_eff = sum_i p_i / max_i p_i.
- * The gradient entry points return d lnL / d(ra, dec, psi, cos incl, phiref,
- * tref, ln dist) (Sec. "The differentiable likelihood").
+ * The gradient entry points return d lnL / d(ra, dec, psi, incl or cos incl,
+ * phiref, tref, dist or ln dist), in the coordinates the caller gives theta in
+ * (Sec. "The differentiable likelihood").
  *
  * Conventions (where the paper is silent or inconsistent):
  *   - Earth-fixed frame: x towards the Greenwich meridian on the equator, z
@@ -41,10 +42,12 @@
  *
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Evaluation
  * calls on a plan only enqueue work and return; outputs are valid once the
- * stream has reached them.  Plan creation and destruction synchronise the
- * stream (they allocate and free device memory), so the one-shot entry points
- * (which create and destroy a plan internally) return only after their work
- * has finished.
+ * stream has reached them, and such calls can be captured into a HIP graph.
+ * Plan creation and destruction synchronise the stream (they allocate and
+ * free device memory and stage small host tables).  The one-shot entry points
+ * (rift_ile_lnL, rift_ile_lnZ, rift_ile_grad) create and destroy a plan
+ * internally, so they return only after their work has finished: their
+ * outputs are valid on return, and they are not capturable.
  *
  * Errors: a negative status means nothing was enqueued and nothing written
  * (invalid arguments are detected on the host before any launch), except
@@ -62,7 +65,7 @@
 extern "C" {
 #endif
 
-#define RIFT_ILE_VERSION 1
+#define RIFT_ILE_VERSION 2
 #define RIFT_ILE_MAX_DET 8   /* detectors per point */
 #define RIFT_ILE_MAX_MODES 25 /* modes per point */
 #define RIFT_ILE_MAX_NT (1 << 26) /* Q samples per mode and detector */
@@ -77,11 +80,22 @@ typedef enum {
 } rift_status;
 
 typedef enum {
-  RIFT_FP64 = 0, /* every step in IEEE double */
-  RIFT_MIXED = 1 /* FP32 pass with an a-priori error bound per sample, FP64
-                    recompute of every sample that can matter for ln Z, FP64
-                    accumulation across detectors and FP64 log-sum-exp */
+  RIFT_FP64 = 0,  /* every step in IEEE double */
+  RIFT_MIXED = 1, /* FP32 pass with an a-priori error bound b_i per sample
+                     (angles reduced and sky frame, arrival times and the sum
+                     over detectors kept in FP64), then an FP64 recompute of
+                     every sample whose bound exceeds 1e-4 nats and that can
+                     matter: for ln Z, every one that can weigh more than
+                     e^-(ln N + 12) of the best; for rift_ile_lnL, every one
+                     that can lie within 20 nats of the best.  FP64 log-sum-exp */
+  RIFT_FP32 = 2   /* rift_ile_lnL only: the FP32 pass alone, every value within
+                     its returned bound b_i of the FP64 result */
 } rift_precision;
+
+/* Coordinates of rows 3 and 6 of theta in the gradient entry points (a
+ * bitwise or; the gradient is taken in the same coordinates). */
+#define RIFT_COORD_COS_INCL 1 /* row 3 holds cos(incl) instead of incl */
+#define RIFT_COORD_LN_DIST 2  /* row 6 holds ln(dist) instead of dist */
 
 /* One intrinsic point lambda: the precomputed arrays of Eq. (QUV) and the
  * detector network. */
@@ -102,16 +116,18 @@ typedef struct {
 } rift_ile_point;
 
 /* theta layout used by every entry point: DEVICE, structure of arrays
- * [7][n] doubles: ra, dec, psi, incl, phiref, tref (s), dist.
- * grad layout: DEVICE [7][n] doubles: d/d ra, dec, psi, cos(incl), phiref,
- * tref, ln(dist). */
+ * [7][n] doubles: ra, dec, psi, incl, phiref, tref (s), dist (the gradient
+ * entry points take rows 3 and 6 in the coordinates their `coords` names). */
 
 /* lnL of n samples of one point, Eq. (def:lnL:Decomposed).
- * lnL: DEVICE [n] output.  precision: rift_precision (RIFT_MIXED returns the
- * FP32 pass; every value is within its a-priori bound of the FP64 result).
+ * lnL: DEVICE [n] output.  lnL_bnd: DEVICE [n] output or NULL: an upper bound
+ * on |lnL_i - lnL_i(FP64)| per sample (0 for RIFT_FP64 and for every value
+ * recomputed in FP64).  precision: RIFT_FP64; RIFT_MIXED (every sample that
+ * can lie within 20 nats of the largest lnL is within 1e-4 of its FP64 value,
+ * every other one within its bound); RIFT_FP32 (no recompute).
  * n == 0 is a no-op. */
 int rift_ile_lnL(const rift_ile_point *pt, int64_t n, const double *theta, double *lnL,
-                 int precision, void *stream);
+                 double *lnL_bnd, int precision, void *stream);
 
 /* ln Z and n_eff of n_points intrinsic points, Eqs. (lnL:MonteCarlo), (neff).
  * n_per_point: HOST [n_points], each >= 1; the samples of point p are the
@@ -119,17 +135,25 @@ int rift_ile_lnL(const rift_ile_point *pt, int64_t n, const double *theta, doubl
  * theta: DEVICE [7][N] with N = sum(n_per_point).  lnw: DEVICE [N] or NULL
  * (all zero).  lnZ, neff: DEVICE [n_points] outputs (neff may be NULL).
  * lnL: DEVICE [N] output of every sample's lnL, or NULL.
- * All points are evaluated by one persistent kernel launch. */
+ * precision: RIFT_FP64 or RIFT_MIXED.  All points are evaluated by one launch
+ * of the likelihood kernel (tiles of (point, sample block)). */
 int rift_ile_lnZ(const rift_ile_point *pts, int32_t n_points, const int64_t *n_per_point,
                  const double *theta, const double *lnw, double *lnZ, double *neff, double *lnL,
                  int precision, void *stream);
 
-/* lnL and its gradient for n samples of one point (FP64).  lnL: DEVICE [n]
- * (may be NULL); grad: DEVICE [7][n].  A batch that cannot give every CU 256
- * samples is evaluated 16 lanes per sample, a larger one a lane per sample
- * (the two differ only in rounding order). */
-int rift_ile_grad(const rift_ile_point *pt, int64_t n, const double *theta, double *lnL,
-                  double *grad, void *stream);
+/* lnL and its gradient for n samples of one point (Sec. "The differentiable
+ * likelihood").  theta: DEVICE [7][n], rows 3 and 6 in the coordinates
+ * `coords` (0: incl, dist; RIFT_COORD_COS_INCL: cos(incl); RIFT_COORD_LN_DIST:
+ * ln(dist)).  grad: DEVICE [7][n] output, d lnL / d(ra, dec, psi, row 3,
+ * phiref, tref, row 6) in those same coordinates; lnL: DEVICE [n] or NULL.
+ * A cos(incl) outside [-1, 1] gives NaN lnL and gradient for that sample; at
+ * cos(incl) = +-1 the cos(incl) derivative is infinite (or NaN) wherever the
+ * incl derivative is not zero.  precision: RIFT_FP64 (RIFT_MIXED and
+ * RIFT_FP32 return RIFT_EUNSUPPORTED: the gradient is FP64 only).  A batch
+ * that cannot give every CU 256 samples is evaluated 16 lanes per sample, a
+ * larger one a lane per sample (the two differ only in rounding order). */
+int rift_ile_grad(const rift_ile_point *pt, int64_t n, const double *theta, int coords, double *lnL,
+                  double *grad, int precision, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Plans: points prepared once (repacked tables, harmonic-basis coefficients,
@@ -148,29 +172,27 @@ int rift_ile_plan_create(const rift_ile_point *pts, int32_t n_points, const int6
                          int precision, void *stream, rift_ile_plan *out);
 
 /* ln Z / n_eff of every point of the plan for one batch laid out as in
- * rift_ile_lnZ.  lnZ_err: DEVICE [n_points] or NULL, receives an upper bound on
- * |ln Z - ln Z_FP64| (RIFT_MIXED) or 0 (RIFT_FP64). */
+ * rift_ile_lnZ.  lnL, lnL_bnd: DEVICE [N] or NULL: every sample's lnL and its
+ * a-priori bound on |lnL_i - lnL_i(FP64)| (0 for FP64 values: RIFT_FP64, and
+ * the samples RIFT_MIXED recomputed).  lnZ_err: DEVICE [n_points] or NULL,
+ * receives an upper bound on |ln Z - ln Z_FP64| (RIFT_MIXED) or 0 (RIFT_FP64). */
 int rift_ile_plan_lnZ(rift_ile_plan plan, const double *theta, const double *lnw, double *lnZ,
-                      double *neff, double *lnL, double *lnZ_err, void *stream);
+                      double *neff, double *lnL, double *lnL_bnd, double *lnZ_err, void *stream);
 
-/* lnL (may be NULL) and gradient of n samples of point `point` of the plan. */
-int rift_ile_plan_grad(rift_ile_plan plan, int32_t point, int64_t n, const double *theta,
+/* lnL (may be NULL) and gradient of n samples of point `point` of the plan;
+ * theta, coords and grad as in rift_ile_grad (FP64 whatever the plan's
+ * precision). */
+int rift_ile_plan_grad(rift_ile_plan plan, int32_t point, int64_t n, const double *theta, int coords,
                        double *lnL, double *grad, void *stream);
-
-/* As rift_ile_plan_grad, with theta given in the coordinates the gradient is
- * taken in (for gradient-based samplers that move in them): rows 3 and 6 hold
- * cos(incl) and ln(dist) instead of incl and dist.  cos(incl) is clamped to
- * |cos(incl)| <= 1 - 1e-12, where the derivative in it stays finite.  Same
- * layout, ownership and errors as rift_ile_plan_grad. */
-int rift_ile_plan_grad_sampler(rift_ile_plan plan, int32_t point, int64_t n, const double *theta,
-                               double *lnL, double *grad, void *stream);
 
 /* Autotuner: time the candidate launch shapes on this batch and keep the
  * fastest (synchronises `stream`; not capturable). Returns the chosen index. */
 int rift_ile_plan_tune(rift_ile_plan plan, const double *theta, const double *lnw, void *stream);
 
 /* Launch shape of the plan: threads per block, samples per tile, persistent
- * blocks per CU.  Setting validates on the host: RIFT_EINVAL for values out of
+ * blocks per CU (0: one block per tile, the initial shape; a positive value
+ * runs a work queue over the tiles, one of the tuner's candidates).  Setting
+ * validates on the host: RIFT_EINVAL for values out of
  * range, RIFT_EUNSUPPORTED for a block whose likelihood kernel would need more
  * LDS than one block may hold (16 KiB per wavefront for the data term's read
  * staging, plus a per-lane column for the l <= 8 class). */

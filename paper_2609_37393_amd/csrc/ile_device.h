@@ -75,9 +75,14 @@ struct PointDesc {
   double ycoef[MMAX][LMAXC + 1];  // d^l_{m,2}(incl) sqrt((2l+1)/4pi) = sum_n ycoef cos|sin(n incl)
   float ycoef32[MMAX][LMAXC + 1];
   float dten32[KMAX][6];
-  // mixed path: |lnL_FP32 - lnL_FP64| <= x bnd_d + x^2 sum_k (|F_k|^2 + 1e-6) bnd_q[k]
+  // mixed path, a-priori bound on |lnL_FP32 - lnL_FP64| of one sample:
+  //   x bnd_d + x^2 sum_k [ (|F_k| + eF[k])^2 bnd_q[k]
+  //                         + (2 (|F_k| + eF[k]) eF[k] + eF[k]^2) l1q[k] ]
+  // (written on the device by k_bound; see there for the derivation)
   double bnd_d;
   double bnd_q[KMAX];
+  double l1q[KMAX];  // sum of |C| over detector k's three coefficient columns
+  double eF[KMAX];   // bound on |F_FP32 - F| of detector k
   // arrival-time binning (sorted evaluation): a Morton key of bin_bits
   // bits per detector over the first bin_dims detectors; its top bin_cb
   // bits are the coarse bucket.  The point's sort tiles are bin_st0 ..
@@ -369,6 +374,28 @@ __device__ __forceinline__ void lagrange4(R s, R* w) {
   w[3] = (s + 1) * s * (s - 1) * (R)(1.0 / 6.0);
 }
 
+// Row coordinate of a stencil: u = (t_k - t0) / dt.  A non-finite u poisons
+// the sample; a finite u far outside the stored window is moved to just
+// outside it (every tap then reads a zero pad row, the zero extension of the
+// window), which also keeps the integer row in range.
+__device__ __forceinline__ bool stencil_u(double& u, int n_t) {
+  if (!(fabs(u) <= 1.0e300)) {  // NaN or infinite
+    u = 0.0;
+    return false;
+  }
+  u = fmin(fmax(u, -2.0 * QPAD), (double)n_t + 2.0 * QPAD);
+  return true;
+}
+
+// a - 2 pi rint(a / 2 pi) in FP64 (2 pi split into two doubles): the angle
+// in [-pi, pi] that the FP32 arithmetic starts from, so that its rounding to
+// FP32 is at most pi 2^-25 rad whatever the size of the input angle.
+__device__ __forceinline__ double reduce_2pi(double a) {
+  const double k = rint(a * 0.15915494309189533577);
+  double r = fma(-k, 6.283185307179586232, a);
+  return fma(-k, 2.4492935982947064e-16, r);
+}
+
 // Detector groups of the data term (KT >= 2): at most three detectors share
 // a pass over the modes; a remainder of one is split as 2 + 2, so every group
 // has two or three detectors.
@@ -583,6 +610,11 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
   constexpr int NI = CL::NI;
   constexpr int NY = CL::NY;
   const int n_t = P->n_t;
+  if constexpr (sizeof(R) == 4) {
+    psi = reduce_2pi(psi);
+    incl = reduce_2pi(incl);
+    phi = reduce_2pi(phi);
+  }
 
   // --- sky frame (FP64) --------------------------------------------------
   double sg, cg, sd, cd;
@@ -650,10 +682,7 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
     const RIFT_CONST double* r = P->rpos[k];
     const double tk = tref - (r[0] * N0 + r[1] * N1 + r[2] * N2);
     double u = (tk - P->t0) * P->inv_dt;
-    if (!(fabs(u) < 1.0e9)) {  // non-finite (or absurd) time: poison the sample
-      bad = true;
-      u = 0.0;
-    }
+    if (!stencil_u(u, n_t)) bad = true;
     const double jf = floor(u);
     const R s = (R)(u - jf);
     int j0 = (int)jf - 1;  // stencil rows j0 .. j0+3
@@ -742,7 +771,7 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
     }
   }
   double quad = 0.0;
-  double wq = 0.0;  // sum_k (|F_k|^2 + 1e-6) bnd_q[k]  (error bound)
+  double wq = 0.0;  // model-norm part of the error bound (see PointDesc)
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     const R f2 = Fre[k] * Fre[k] + Fim[k] * Fim[k];
@@ -750,7 +779,11 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
     const R g2i = 2 * Fre[k] * Fim[k];
     quad += (double)(f2 * acc[3 * k]) + (double)(g2r * acc[3 * k + 1]) +
             (double)(g2i * acc[3 * k + 2]);
-    if (BOUND) wq += ((double)f2 + 1e-6) * P->bnd_q[k];
+    if (BOUND) {
+      const double e = P->eF[k];
+      const double fe = sqrt((double)f2) + e;  // >= |F_k| of the exact arithmetic
+      wq += fe * fe * P->bnd_q[k] + (2.0 * fe + e) * e * P->l1q[k];
+    }
   }
 
   const double x = P->d_ref / dist;
@@ -758,7 +791,8 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
   e.lnL = x * data - x * x * quad;
   if (bad) e.lnL = __builtin_nan("");
   e.bound = 0.0f;
-  if (BOUND) e.bound = (float)(x * P->bnd_d + x * x * wq);
+  // rounded up on the way to FP32 (the factor covers the conversion)
+  if (BOUND) e.bound = (float)((fabs(x) * P->bnd_d + x * x * wq) * (1.0 + 1.0e-6));
   return e;
 }
 

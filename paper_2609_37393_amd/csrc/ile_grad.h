@@ -1,5 +1,5 @@
-// Hand-written gradient of the factored log-likelihood (FP64), one lane per
-// sample: lnL and d lnL / d(ra, dec, psi, cos incl, phiref, tref, ln dist)
+// Hand-written gradient of the factored log-likelihood (FP64): lnL and
+// d lnL / d(ra, dec, psi, incl or cos incl, phiref, tref, dist or ln dist)
 // (Sec. "The differentiable likelihood": the same closed form, differentiated).
 //
 // With gha = gmst - ra, the rotating-frame identities used below are
@@ -19,6 +19,34 @@
 #include "ile_device.h"
 
 namespace rift {
+
+// Coordinates of rows 3 and 6 of theta, for the input and for the gradient
+// (bit 0: cos(incl) instead of incl; bit 1: ln(dist) instead of dist).
+enum : int { COORD_COS_INCL = 1, COORD_LN_DIST = 2 };
+
+// Rows 3 and 6 of a sample in the coordinates `coords` -> (incl, dist).  A
+// cos(incl) outside [-1, 1] is not a point of the sky: the sample is poisoned.
+__device__ __forceinline__ bool theta_coords(int coords, double& incl, double& dist) {
+  bool ok = true;
+  if (coords & COORD_COS_INCL) {
+    ok = fabs(incl) <= 1.0;
+    incl = acos(fmin(fmax(incl, -1.0), 1.0));
+  }
+  if (coords & COORD_LN_DIST) dist = exp(dist);
+  return ok;
+}
+
+// The last step of both gradient forms: from the derivatives along incl (g3)
+// and ln(dist) (g6) to the coordinates `coords`, given row 3 as the caller
+// passed it (c3) and the distance:
+//   d/d cos(incl) = -d/d incl / sin(incl), sin(incl) = sqrt((1 - c)(1 + c))
+//   (exactly 0 at c = +-1, where the derivative is infinite or NaN: the
+//   likelihood is not differentiable in cos(incl) at the poles);
+//   d/d dist = d/d ln(dist) / dist.
+__device__ __forceinline__ void grad_coords(int coords, double c3, double dist, double& g3, double& g6) {
+  if (coords & COORD_COS_INCL) g3 = -g3 / sqrt((1.0 - c3) * (1.0 + c3));
+  if (!(coords & COORD_LN_DIST)) g6 = g6 / dist;
+}
 
 template <int KT, int L>
 __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, int ts, double ra,
@@ -108,10 +136,7 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
     dtg[k] = cd * (r[0] * ea[0] + r[1] * ea[1]);
     dtd[k] = -(r[0] * ed[0] + r[1] * ed[1] + r[2] * ed[2]);
     double u = (tk - P->t0) * P->inv_dt;
-    if (!(fabs(u) < 1.0e9)) {
-      bad = true;
-      u = 0.0;
-    }
+    if (!stencil_u(u, n_t)) bad = true;
     const double jf = floor(u);
     const double s = u - jf;
     int j0 = (int)jf - 1;
@@ -285,10 +310,10 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
   g[0] = -(x * gg - x2 * qg);          // d/dra = -d/dgha
   g[1] = x * gdec - x2 * qdec;
   g[2] = x * gpsi - x2 * qpsi;
-  g[3] = -(x * gi - x2 * qi) / si;     // d/dcos(incl) = -(1/sin incl) d/dincl
+  g[3] = x * gi - x2 * qi;             // d/d incl
   g[4] = x * gf - x2 * qf;
   g[5] = x * gt;
-  g[6] = -x * data + 2.0 * x2 * quad;  // x = D_ref e^{-ln dist}
+  g[6] = -x * data + 2.0 * x2 * quad;  // d/d ln(dist), x = D_ref e^{-ln dist}
   if (bad) {
     const double nan = __builtin_nan("");
 #pragma unroll
@@ -376,11 +401,7 @@ __device__ __forceinline__ double eval_grad_group(PDesc P, double ra, double dec
       const RIFT_CONST double* r = P->rpos[k];
       const double tk = tref - (r[0] * N[0] + r[1] * N[1] + r[2] * N[2]);
       double u = (tk - P->t0) * P->inv_dt;
-      double bad = 0.0;
-      if (!(fabs(u) < 1.0e9)) {
-        bad = 1.0;
-        u = 0.0;
-      }
+      const double bad = stencil_u(u, n_t) ? 0.0 : 1.0;
       const double jf = floor(u);
       int j0 = (int)jf - 1;
       j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
@@ -534,14 +555,13 @@ __device__ __forceinline__ double eval_grad_group(PDesc P, double ra, double dec
   qi = gsum<G>(qi);
   qf = gsum<G>(qf);
   bad = gsum<G>(bad);
-  const double si = stab[1];
   const double x = P->d_ref / dist;
   const double x2 = x * x;
   const double lnL = x * data - x2 * quad;
   g[0] = -(x * gg - x2 * qg);
   g[1] = x * gdec - x2 * qdec;
   g[2] = x * gpsi - x2 * qpsi;
-  g[3] = -(x * gi - x2 * qi) / si;
+  g[3] = x * gi - x2 * qi;
   g[4] = x * gf - x2 * qf;
   g[5] = x * gt;
   g[6] = -x * data + 2.0 * x2 * quad;

@@ -212,11 +212,7 @@ __device__ __forceinline__ double eval_wide(PDesc P, double ra, double dec, doub
     }
     const double tk = tref - (P->rpos[k][0] * N0 + P->rpos[k][1] * N1 + P->rpos[k][2] * N2);
     double u = (tk - P->t0) * P->inv_dt;
-    double bad = 0.0;
-    if (!(fabs(u) < 1.0e9)) {
-      bad = 1.0;
-      u = 0.0;
-    }
+    const double bad = stencil_u(u, n_t) ? 0.0 : 1.0;
     const double jf = floor(u);
     int j0 = (int)jf - 1;
     j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
@@ -349,16 +345,6 @@ __global__ void __launch_bounds__(256) k_refine(const PointDesc* __restrict__ de
   else if ((LSET & 8) && L == 8) refine_point<KT, 8>(P, theta, N, cnt, list, lnL, p, trig, wtab, stage);
 }
 
-// Rows 3 and 6 of theta: (incl, dist), or with `coords` set the coordinates
-// the gradient is taken in, (cos incl, ln dist).  cos incl is clamped to
-// |cos incl| <= 1 - 1e-12, where the m = +-1 terms of d/d cos incl are finite.
-__device__ __forceinline__ void theta_coords(int coords, double& incl, double& dist) {
-  if (coords) {
-    incl = acos(fmin(fmax(incl, -1.0 + 1e-12), 1.0 - 1e-12));
-    dist = exp(dist);
-  }
-}
-
 // Gradient: one lane per sample, grid-stride.
 template <int KT, int L>
 __global__ void __launch_bounds__(256) k_grad(const PointDesc* __restrict__ P,
@@ -370,11 +356,18 @@ __global__ void __launch_bounds__(256) k_grad(const PointDesc* __restrict__ P,
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const RIFT_GLOBAL double* th = as_global(theta) + i;
-    double incl = th[3 * n], dist = th[6 * n];
-    theta_coords(coords, incl, dist);
+    const double c3 = th[3 * n];
+    double incl = c3, dist = th[6 * n];
+    const bool ok = theta_coords(coords, incl, dist);
     double g[7];
-    const double l = eval_grad<KT, L>(opaque(P), trig, blockDim.x, th[0], th[n], th[2 * n], incl,
-                                      th[4 * n], th[5 * n], dist, g);
+    double l = eval_grad<KT, L>(opaque(P), trig, blockDim.x, th[0], th[n], th[2 * n], incl, th[4 * n],
+                                th[5 * n], dist, g);
+    grad_coords(coords, c3, dist, g[3], g[6]);
+    if (!ok) {
+      l = __builtin_nan("");
+#pragma unroll
+      for (int a = 0; a < 7; ++a) g[a] = l;
+    }
     if (lnL) as_global_w(lnL)[i] = l;
 #pragma unroll
     for (int a = 0; a < 7; ++a) as_global_w(grad)[a * n + i] = g[a];
@@ -403,11 +396,18 @@ __global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__
     const bool live = ib + gw < n;
     const int64_t i = live ? ib + gw : n - 1;
     const RIFT_GLOBAL double* th = as_global(theta) + i;
-    double incl = th[3 * n], dist = th[6 * n];
-    theta_coords(coords, incl, dist);
+    const double c3 = th[3 * n];
+    double incl = c3, dist = th[6 * n];
+    const bool ok = theta_coords(coords, incl, dist);
     double g[7];
-    const double l = eval_grad_group<KT, L, GRAD_G>(opaque(P), th[0], th[n], th[2 * n], incl, th[4 * n],
-                                                    th[5 * n], dist, tab, g);
+    double l = eval_grad_group<KT, L, GRAD_G>(opaque(P), th[0], th[n], th[2 * n], incl, th[4 * n],
+                                              th[5 * n], dist, tab, g);
+    grad_coords(coords, c3, dist, g[3], g[6]);
+    if (!ok) {
+      l = __builtin_nan("");
+#pragma unroll
+      for (int a = 0; a < 7; ++a) g[a] = l;
+    }
     if (live) {
       if (lg == 0 && lnL) as_global_w(lnL)[i] = l;
       double v = g[0];

@@ -190,15 +190,70 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int n, int32_t v) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
+// out[i] = the a-priori bound of sample i's returned lnL: 0 where the value
+// was recomputed in FP64 (its bound entry marked negative) or is FP64.
+__global__ void k_bound_out(const float* __restrict__ bnd, double* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = bnd ? fmax(0.0, (double)bnd[i]) : 0.0;
+}
+
+// Constants of the mixed path's a-priori error bound of one point (one
+// thread; written into the point's device description).  With u = 2^-24 the
+// FP32 unit roundoff, the FP32 pass starts from angles reduced to [-pi, pi]
+// (rounding <= pi u / 2) and:
+//  * antenna: F = D : (e+ + i ex), six products of polarisation-tensor
+//    entries that carry a few u each (sincos, the FP64 -> FP32 cast of the sky
+//    frame, two products and a difference), plus 2 |F| pi u / 2 from the
+//    rounded psi: |F_FP32 - F| <= eF = 40 u sum|D| (D in its six-value form
+//    with doubled off-diagonals, so that |F+|, |Fx| <= sum|D|, |F| <= 1.5 sum|D|);
+//  * data term: every product F conj(Y) Qhat carries the table's rounding, the
+//    Lagrange weights', Y's (Fourier series in incl of <= 9 terms, phase walk
+//    of <= 16 steps), F's, and the (M K)-term accumulation: a bound of
+//    2 (60 + M K) u |F| |Y| |Qhat| per term, with |Qhat| <= 1.25 max|Q|
+//    (1.25 = largest sum of |Lagrange weights| on a cell) and |Y_i| <= the sum
+//    of |Fourier coefficients| of mode i:
+//      bnd_d = 2 * 1.25 (60 + M K) u  sum_k 1.5 sum|D_k| max|Q_k|  sum_i,n |ycoef_in|;
+//  * model-norm term: quad_k = |F|^2 A + Re F^2 Br + Im F^2 Bi with
+//    |A|, |Br|, |Bi| bounded by the sum of the basis coefficients' |C|
+//    (|basis function| <= 1), whose FP32 contraction is off by at most
+//    bnd_q = 2 (60 + B) u l1q (coefficient and basis-function rounding, the
+//    Chebyshev and phase recurrences, the B-term sum); the FP32 weights |F|^2,
+//    F^2 differ from the exact ones by <= (2 |F| + eF) eF.
+__global__ void k_bound(PointDesc* __restrict__ P, const double* __restrict__ qmax) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double u = 5.9604644775390625e-08;  // 2^-24
+  const int M = P->M, K = P->K, KT = P->KT, B = P->B;
+  double ysum = 0.0;
+  for (int i = 0; i < M; ++i)
+    for (int n = 0; n <= LMAXC; ++n) ysum += fabs(P->ycoef[i][n]);
+  double fq = 0.0;
+  for (int k = 0; k < KT; ++k) {
+    double dsum = 0.0;
+    for (int a = 0; a < 6; ++a) dsum += fabs(P->dten[k][a]);
+    if (k < K) fq += 1.5 * dsum * qmax[k];
+    P->eF[k] = 40.0 * u * dsum;
+    double l1 = 0.0;
+    for (int b = 0; b < B; ++b)
+      for (int c = 0; c < 3; ++c) l1 += fabs(P->C64[(size_t)b * 3 * KT + 3 * k + c]);
+    P->l1q[k] = l1;
+    P->bnd_q[k] = 2.0 * (60.0 + (double)B) * u * l1;
+  }
+  P->bnd_d = 2.0 * 1.25 * (60.0 + (double)M * K) * u * fq * ysum;
+}
+
 // Samples that may lie within T of the best go to the point's refine list;
 // their bound is set to -1 to mark them.  Each block first reduces its
 // point's M_low = max over the point's tiles of max(lnL32 + lnw - bound)
 // (fixed order).
+//
+// A sample whose bound is at most `tau` is never listed: its FP32 value is
+// already that close to the FP64 one (its share of the ln Z error is counted
+// by k_final).  `T_over` >= 0 replaces the point's margin T.
 __global__ void k_select(const PointDesc* __restrict__ descs, const Tile* __restrict__ tiles,
                          int n_tiles, const int32_t* __restrict__ trange, const double* __restrict__ tmax,
                          const double* __restrict__ lnL, const double* __restrict__ lnw,
                          float* __restrict__ bnd, int32_t* __restrict__ cnt,
-                         int32_t* __restrict__ list) {
+                         int32_t* __restrict__ list, float tau, double T_over) {
   __shared__ double sh[8];
   const int tidx = blockIdx.x;
   if (tidx >= n_tiles) return;
@@ -211,12 +266,13 @@ __global__ void k_select(const PointDesc* __restrict__ descs, const Tile* __rest
   __syncthreads();
   m = sh[0];
   for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
-  const double thr = m - P->T;
+  const double thr = m - (T_over >= 0.0 ? T_over : P->T);
   for (int o = threadIdx.x; o < t.cnt; o += blockDim.x) {
     const int64_t i = t.s + o;
-    const double v = lnL[i] + (lnw ? lnw[i] : 0.0) + (double)bnd[i];
+    const float b = bnd[i];
+    const double v = lnL[i] + (lnw ? lnw[i] : 0.0) + (double)b;
     // (a sample at -inf adds nothing, also when the whole point is at -inf)
-    if (v >= thr && v != -__builtin_inf()) {
+    if (b > tau && v >= thr && v != -__builtin_inf()) {
       const int slot = atomicAdd(cnt + t.p, 1);
       list[P->s0 + slot] = (int32_t)(i - P->s0);
       bnd[i] = -1.0f;
@@ -819,6 +875,15 @@ int validate_point(const rift_ile_point* pt) {
 
 int check_dev_ptr(const void* p) { return (p && (((uintptr_t)p) & 7u) == 0) ? RIFT_OK : RIFT_EINVAL; }
 
+// Mixed path: a sample whose a-priori bound is at most kRefineTau nats keeps
+// its FP32 value; rift_ile_lnL recomputes every other sample that can lie
+// within kPosteriorMargin nats of the best one (the posterior-relevant set).
+constexpr double kRefineTau = 1.0e-4;
+constexpr double kPosteriorMargin = 20.0;
+
+// Blocks of 256 threads for an elementwise pass over n entries (grid-stride).
+unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+
 // Rough relative cost per sample of a point (for tile ordering).
 double point_cost(int KT, int L, int M) {
   return 200.0 + 12.0 * M * KT + 3.0 * KT * basis_count(L);
@@ -1186,6 +1251,8 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
   p->d_desc = (PointDesc*)v;
   std::vector<int32_t*> d_perm(n_points);
   std::vector<double*> d_qmax(n_points);
+  // host copies staged to the device: they live until the final synchronisation
+  std::vector<std::vector<int32_t>> h_perm(n_points);
   int64_t s0 = 0;
   for (int pi = 0; pi < n_points; ++pi) {
     const rift_ile_point& pt = pts[pi];
@@ -1233,7 +1300,8 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
       for (int a = 0; a < 3; ++a) D.rpos[k][a] = pt.det_pos[3 * k + a];
     }
     // modes sorted by m (stable) so the phase e^{i m phi} walks upward
-    std::vector<int> perm(M);
+    std::vector<int32_t>& perm = h_perm[pi];
+    perm.resize(M);
     for (int i = 0; i < M; ++i) perm[i] = i;
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return pt.lm[2 * a + 1] < pt.lm[2 * b + 1]; });
     for (int i = 0; i < M; ++i) {
@@ -1263,7 +1331,6 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     PHIP(hipMemcpyAsync(d_perm[pi], perm.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
     PCHK(palloc(p, sizeof(double) * KT, &v));
     d_qmax[pi] = (double*)v;
-    PHIP(hipStreamSynchronize(st));  // perm staged before the host vector goes away
   }
   // kernel instances exist for one class (1, 2, 4, 8) and for any mix of the
   // l <= 4 classes (7); a batch mixing l > 4 with smaller points runs every
@@ -1289,52 +1356,6 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
           D.C32 = (const float*)v;
         }
       }
-    }
-  }
-  PHIP(hipMemcpyAsync(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice, st));
-  for (int pi = 0; pi < n_points; ++pi) {
-    const rift_ile_point& pt = pts[pi];
-    PointDesc& D = p->h_desc[pi];
-    const int64_t qper = (int64_t)(pt.n_t + 2 * QPAD) * q_groups(pt.n_modes, QW64) * QW64;
-    const int gq = (int)std::min<int64_t>((KT * qper + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_repack<double>, dim3(gq), dim3(256), 0, st, pt.Q, (double*)D.Q64, d_perm[pi],
-                       pt.n_det, KT, pt.n_modes, pt.n_t, QW64);
-    if (D.Q32)
-      hipLaunchKernelGGL(k_repack<float>, dim3(gq), dim3(256), 0, st, pt.Q, (float*)D.Q32, d_perm[pi],
-                         pt.n_det, KT, pt.n_modes, pt.n_t, QW32);
-    hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(1024), 0, st, D.Q64, d_qmax[pi], qper);
-    const int NG = 4 * D.L + 4;
-    hipLaunchKernelGGL(k_basis, dim3(KT), dim3(256), sizeof(double) * 3 * NG * NG, st,
-                       p->d_desc + pi, pt.U, pt.V, d_perm[pi], (double*)D.C64, (float*)D.C32);
-    PHIP(hipGetLastError());
-  }
-  PHIP(hipStreamSynchronize(st));
-  // error-bound constants of the mixed path
-  for (int pi = 0; pi < n_points && mixed; ++pi) {
-    PointDesc& D = p->h_desc[pi];
-    std::vector<double> qmax(KT), C((size_t)D.B * 3 * KT);
-    PHIP(hipMemcpy(qmax.data(), d_qmax[pi], sizeof(double) * KT, hipMemcpyDeviceToHost));
-    PHIP(hipMemcpy(C.data(), D.C64, sizeof(double) * C.size(), hipMemcpyDeviceToHost));
-    const double u = 5.9604644775390625e-08;  // 2^-24
-    double ysum = 0.0;
-    for (int i = 0; i < D.M; ++i)
-      for (int n = 0; n <= LMAXC; ++n) ysum += fabs(D.ycoef[i][n]);
-    double fq = 0.0;
-    for (int k = 0; k < D.K; ++k) {
-      double fm = 0.0;
-      for (int a = 0; a < 6; ++a) fm += fabs(D.dten[k][a]);
-      fq += 1.5 * fm * qmax[k];
-    }
-    // data term: |Q^| <= 1.25 max|Q| (sum of |Lagrange weights|); rounding of
-    // table, weights, harmonics (phase walk <= 16 steps), antenna and the
-    // (M K)-term sum, each a small multiple of u.
-    D.bnd_d = 2.0 * 1.25 * (60.0 + (double)D.M * D.K) * u * fq * ysum;
-    for (int k = 0; k < KT; ++k) {
-      double l1 = 0.0;
-      for (int b = 0; b < D.B; ++b)
-        for (int c = 0; c < 3; ++c) l1 += fabs(C[(size_t)b * 3 * KT + 3 * k + c]);
-      // |beta| <= 1 up to the recurrences' rounding; B-term sums
-      D.bnd_q[k] = 2.0 * (60.0 + (double)D.B) * u * l1;
     }
   }
   // binning layout: sort tiles, count-matrix blocks and coarse buckets per
@@ -1372,10 +1393,33 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     p->n_stiles = (int)stiles.size();
     p->n_mat = mbase;
   }
-  PHIP(hipMemcpy(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice));
+  PHIP(hipMemcpyAsync(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice, st));
+  for (int pi = 0; pi < n_points; ++pi) {
+    const rift_ile_point& pt = pts[pi];
+    PointDesc& D = p->h_desc[pi];
+    const int64_t qper = (int64_t)(pt.n_t + 2 * QPAD) * q_groups(pt.n_modes, QW64) * QW64;
+    const int gq = (int)std::min<int64_t>((KT * qper + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_repack<double>, dim3(gq), dim3(256), 0, st, pt.Q, (double*)D.Q64, d_perm[pi],
+                       pt.n_det, KT, pt.n_modes, pt.n_t, QW64);
+    if (D.Q32)
+      hipLaunchKernelGGL(k_repack<float>, dim3(gq), dim3(256), 0, st, pt.Q, (float*)D.Q32, d_perm[pi],
+                         pt.n_det, KT, pt.n_modes, pt.n_t, QW32);
+    const int NG = 4 * D.L + 4;
+    hipLaunchKernelGGL(k_basis, dim3(KT), dim3(256), sizeof(double) * 3 * NG * NG, st,
+                       p->d_desc + pi, pt.U, pt.V, d_perm[pi], (double*)D.C64, (float*)D.C32);
+    if (mixed) {
+      // error-bound constants of the mixed path, from the table maxima and
+      // the basis coefficients
+      hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(1024), 0, st, D.Q64, d_qmax[pi], qper);
+      hipLaunchKernelGGL(k_bound, dim3(1), dim3(64), 0, st, p->d_desc + pi, (const double*)d_qmax[pi]);
+    }
+    PHIP(hipGetLastError());
+  }
   PCHK(palloc(p, sizeof(int32_t) * 64, &v));
   p->d_counter = (int32_t*)v;
-  PHIP(hipMemset(p->d_counter, 0, sizeof(int32_t) * 64));  // the kernel leaves it at 0 after each launch
+  // the persistent kernel leaves it at 0 after each launch
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, p->d_counter, 64, 0);
+  PHIP(hipGetLastError());
   // samples are addressed by int32 positions in the binned order
   if (N > 0x7fffffff) p->cfg.sort = 0;
   if (p->cfg.sort) PCHK(ensure_bin_buffers(p));
@@ -1400,6 +1444,8 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     }
   }
   PCHK(build_tiles(p));
+  // the staged host copies (mode permutations) are released on return
+  PHIP(hipStreamSynchronize(st));
 #undef PCHK
 #undef PHIP
   p->last = st;
@@ -1428,11 +1474,31 @@ int rift_ile_plan_set_config(rift_ile_plan plan, const rift_ile_config* cfg) {
   return RIFT_OK;
 }
 
+// Mixed-path tail after the FP32 pass wrote lnL and bound of every sample
+// (and each tile's max of lnL + lnw - bound): list the samples that can
+// matter (margin T_over, or each point's own T when negative), recompute them
+// in FP64 and, if wanted, export every sample's bound.
+static int mixed_refine(rift_ile_plan p, const double* theta, const double* lnw, double* L, double T_over,
+                 double* lnL_bnd, hipStream_t st) {
+  hipLaunchKernelGGL(k_select, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_desc, p->d_tiles,
+                     p->n_tiles, (const int32_t*)p->d_trange, (const double*)p->d_tmax, (const double*)L, lnw,
+                     p->d_bnd, p->d_cnt, p->d_list, (float)kRefineTau, T_over);
+  refine_fn rf = pick_refine_kt(p->KT, p->lset);
+  if (!rf) return RIFT_EUNSUPPORTED;
+  hipLaunchKernelGGL(rf, dim3(p->refine_blocks, p->n_points), dim3(256),
+                     eval_lds_bytes(p->lset, 256, sizeof(double)), st, p->d_desc, theta, p->N,
+                     (const int32_t*)p->d_cnt, (const int32_t*)p->d_list, L);
+  if (lnL_bnd)
+    hipLaunchKernelGGL(k_bound_out, dim3(grid_for(p->N)), dim3(256), 0, st, (const float*)p->d_bnd, lnL_bnd, p->N);
+  HCHK(hipGetLastError());
+  return RIFT_OK;
+}
+
 int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, double* lnZ,
-                      double* neff, double* lnL, double* lnZ_err, void* stream) {
+                      double* neff, double* lnL, double* lnL_bnd, double* lnZ_err, void* stream) {
   if (!p || check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
   if ((lnw && check_dev_ptr(lnw)) || (neff && check_dev_ptr(neff)) || (lnL && check_dev_ptr(lnL)) ||
-      (lnZ_err && check_dev_ptr(lnZ_err)))
+      (lnZ_err && check_dev_ptr(lnZ_err)) || (lnL_bnd && check_dev_ptr(lnL_bnd)))
     return RIFT_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   p->last = st;
@@ -1448,6 +1514,8 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
                          lnw, p->d_part);
     hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
                        (const double*)nullptr, lnZ, neff, lnZ_err);
+    if (lnL_bnd)
+      hipLaunchKernelGGL(k_bound_out, dim3(grid_for(p->N)), dim3(256), 0, st, (const float*)nullptr, lnL_bnd, p->N);
     HCHK(hipGetLastError());
     return RIFT_OK;
   }
@@ -1455,14 +1523,7 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
   if (sorted)
     hipLaunchKernelGGL(k_tmax_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                        lnw, (const float*)p->d_bnd, p->d_tmax);
-  hipLaunchKernelGGL(k_select, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_desc, p->d_tiles,
-                     p->n_tiles, (const int32_t*)p->d_trange, (const double*)p->d_tmax, (const double*)L, lnw,
-                     p->d_bnd, p->d_cnt, p->d_list);
-  refine_fn rf = pick_refine_kt(p->KT, p->lset);
-  if (!rf) return RIFT_EUNSUPPORTED;
-  hipLaunchKernelGGL(rf, dim3(p->refine_blocks, p->n_points), dim3(256),
-                     eval_lds_bytes(p->lset, 256, sizeof(double)), st, p->d_desc, theta, p->N,
-                     (const int32_t*)p->d_cnt, (const int32_t*)p->d_list, L);
+  if ((rc = mixed_refine(p, theta, lnw, L, -1.0, lnL_bnd, st))) return rc;
   hipLaunchKernelGGL(k_final, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                      lnw, (const float*)p->d_bnd, p->d_part, p->d_terr);
   hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
@@ -1482,9 +1543,10 @@ int rift_ile_plan_refined(rift_ile_plan p, int64_t* n_refined) {
   return RIFT_OK;
 }
 
-static int plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, int coords, double* lnL,
-              double* grad, void* stream) {
+int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, int coords,
+                       double* lnL, double* grad, void* stream) {
   if (!p || point < 0 || point >= p->n_points || n < 0) return RIFT_EINVAL;
+  if (coords < 0 || coords > (RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST)) return RIFT_EINVAL;
   if (n == 0) return RIFT_OK;
   if (check_dev_ptr(theta) || check_dev_ptr(grad) || (lnL && check_dev_ptr(lnL))) return RIFT_EINVAL;
   hipStream_t st = (hipStream_t)stream;
@@ -1511,16 +1573,6 @@ static int plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* th
   HCHK(hipGetLastError());
   if (p->profiling) HCHK(hipEventRecord(e1, st));
   return RIFT_OK;
-}
-
-int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, double* lnL,
-                       double* grad, void* stream) {
-  return plan_grad(p, point, n, theta, 0, lnL, grad, stream);
-}
-
-int rift_ile_plan_grad_sampler(rift_ile_plan p, int32_t point, int64_t n, const double* theta,
-                               double* lnL, double* grad, void* stream) {
-  return plan_grad(p, point, n, theta, 1, lnL, grad, stream);
 }
 
 int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, void* stream) {
@@ -1551,12 +1603,12 @@ int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, 
       continue;
     }
     if (rc) break;
-    rc = rift_ile_plan_lnZ(p, theta, lnw, d_out, d_out + p->n_points, nullptr, nullptr, st);  // warm-up
+    rc = rift_ile_plan_lnZ(p, theta, lnw, d_out, d_out + p->n_points, nullptr, nullptr, nullptr, st);  // warm-up
     if (rc) break;
     float ms_sum = 0.0f;
     for (int r = 0; r < 3 && rc == RIFT_OK; ++r) {
       (void)hipEventRecord(e0, st);
-      rc = rift_ile_plan_lnZ(p, theta, lnw, d_out, d_out + p->n_points, nullptr, nullptr, st);
+      rc = rift_ile_plan_lnZ(p, theta, lnw, d_out, d_out + p->n_points, nullptr, nullptr, nullptr, st);
       (void)hipEventRecord(e1, st);
       if (hipEventSynchronize(e1) != hipSuccess) rc = RIFT_EDEVICE;
       float ms = 0.0f;
@@ -1582,38 +1634,58 @@ int rift_ile_lnZ(const rift_ile_point* pts, int32_t n_points, const int64_t* n_p
                  const double* theta, const double* lnw, double* lnZ, double* neff, double* lnL,
                  int precision, void* stream) {
   if (check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  if (precision != RIFT_FP64 && precision != RIFT_MIXED) return RIFT_EINVAL;
   rift_ile_plan p = nullptr;
   int rc = rift_ile_plan_create(pts, n_points, n_per_point, precision, stream, &p);
   if (rc) return rc;
-  rc = rift_ile_plan_lnZ(p, theta, lnw, lnZ, neff, lnL, nullptr, stream);
+  rc = rift_ile_plan_lnZ(p, theta, lnw, lnZ, neff, lnL, nullptr, nullptr, stream);
   int rc2 = rift_ile_plan_destroy(p);
   return rc ? rc : rc2;
 }
 
-int rift_ile_lnL(const rift_ile_point* pt, int64_t n, const double* theta, double* lnL, int precision,
-                 void* stream) {
+int rift_ile_lnL(const rift_ile_point* pt, int64_t n, const double* theta, double* lnL, double* lnL_bnd,
+                 int precision, void* stream) {
   if (n < 0) return RIFT_EINVAL;
+  if (precision != RIFT_FP64 && precision != RIFT_MIXED && precision != RIFT_FP32) return RIFT_EINVAL;
   if (n == 0) return validate_point(pt);
-  if (check_dev_ptr(theta) || check_dev_ptr(lnL)) return RIFT_EINVAL;
+  if (check_dev_ptr(theta) || check_dev_ptr(lnL) || (lnL_bnd && check_dev_ptr(lnL_bnd))) return RIFT_EINVAL;
   rift_ile_plan p = nullptr;
-  int rc = rift_ile_plan_create(pt, 1, &n, precision, stream, &p);
+  int rc = rift_ile_plan_create(pt, 1, &n, precision == RIFT_FP64 ? RIFT_FP64 : RIFT_MIXED, stream, &p);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   p->cfg.sort = 0;  // input-order evaluation: no reduction follows
-  rc = launch_tiles(p, precision == RIFT_FP64 ? MODE_LSE64 : MODE_PASS32, theta, nullptr, lnL, st);
+  if (precision == RIFT_FP64) {
+    rc = launch_tiles(p, MODE_LSE64, theta, nullptr, lnL, st);
+    if (!rc && lnL_bnd) {
+      hipLaunchKernelGGL(k_bound_out, dim3(grid_for(n)), dim3(256), 0, st, (const float*)nullptr, lnL_bnd, n);
+      if (hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
+    }
+  } else {
+    rc = launch_tiles(p, MODE_PASS32, theta, nullptr, lnL, st);
+    if (!rc && precision == RIFT_MIXED) {
+      // every sample that can lie within kPosteriorMargin of the best one
+      rc = mixed_refine(p, theta, nullptr, lnL, kPosteriorMargin, lnL_bnd, st);
+    } else if (!rc && lnL_bnd) {
+      hipLaunchKernelGGL(k_bound_out, dim3(grid_for(n)), dim3(256), 0, st, (const float*)p->d_bnd, lnL_bnd, n);
+      if (hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
+    }
+  }
   int rc2 = rift_ile_plan_destroy(p);
   return rc ? rc : rc2;
 }
 
-int rift_ile_grad(const rift_ile_point* pt, int64_t n, const double* theta, double* lnL, double* grad,
-                  void* stream) {
+int rift_ile_grad(const rift_ile_point* pt, int64_t n, const double* theta, int coords, double* lnL,
+                  double* grad, int precision, void* stream) {
   if (n < 0) return RIFT_EINVAL;
+  if (precision == RIFT_MIXED || precision == RIFT_FP32) return RIFT_EUNSUPPORTED;
+  if (precision != RIFT_FP64) return RIFT_EINVAL;
+  if (coords < 0 || coords > (RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST)) return RIFT_EINVAL;
   if (n == 0) return validate_point(pt);
   if (check_dev_ptr(theta) || check_dev_ptr(grad)) return RIFT_EINVAL;
   rift_ile_plan p = nullptr;
   int rc = rift_ile_plan_create(pt, 1, &n, RIFT_FP64, stream, &p);
   if (rc) return rc;
-  rc = rift_ile_plan_grad(p, 0, n, theta, lnL, grad, stream);
+  rc = rift_ile_plan_grad(p, 0, n, theta, coords, lnL, grad, stream);
   int rc2 = rift_ile_plan_destroy(p);
   return rc ? rc : rc2;
 }

@@ -18,9 +18,27 @@ LIB_PATH = os.path.join(_HERE, "librift_ile.so")
 
 RIFT_FP64 = 0
 RIFT_MIXED = 1
-PRECISIONS = {"fp64": RIFT_FP64, "mixed": RIFT_MIXED}
+RIFT_FP32 = 2
+PRECISIONS = {"fp64": RIFT_FP64, "mixed": RIFT_MIXED, "fp32": RIFT_FP32}
 
-GRAD_NAMES = ("ra", "dec", "psi", "cos_incl", "phiref", "tref", "ln_dist")
+# coordinates of theta rows 3 and 6 in the gradient entry points (the
+# gradient is taken in the same coordinates)
+RIFT_COORD_COS_INCL = 1
+RIFT_COORD_LN_DIST = 2
+COORDS = {
+    "physical": 0,                                        # incl, dist
+    "paper": RIFT_COORD_LN_DIST,                          # incl, ln dist
+    "sampler": RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST,  # cos incl, ln dist
+}
+
+
+def coord_names(coords: int):
+    return ("ra", "dec", "psi", "cos_incl" if coords & RIFT_COORD_COS_INCL else "incl", "phiref", "tref",
+            "ln_dist" if coords & RIFT_COORD_LN_DIST else "dist")
+
+
+def _coords(c) -> int:
+    return COORDS[c] if isinstance(c, str) else int(c)
 
 EXPORTS = (
     "rift_ile_lnL",
@@ -29,7 +47,6 @@ EXPORTS = (
     "rift_ile_plan_create",
     "rift_ile_plan_lnZ",
     "rift_ile_plan_grad",
-    "rift_ile_plan_grad_sampler",
     "rift_ile_plan_tune",
     "rift_ile_plan_get_config",
     "rift_ile_plan_set_config",
@@ -78,13 +95,13 @@ def load(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     P = ctypes.POINTER(CPoint)
-    lib.rift_ile_lnL.argtypes = [P, i64, vp, vp, ctypes.c_int, vp]
-    lib.rift_ile_lnZ.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, ctypes.c_int, vp]
-    lib.rift_ile_grad.argtypes = [P, i64, vp, vp, vp, vp]
-    lib.rift_ile_plan_create.argtypes = [P, i32, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
-    lib.rift_ile_plan_lnZ.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
-    lib.rift_ile_plan_grad.argtypes = [vp, i32, i64, vp, vp, vp, vp]
-    lib.rift_ile_plan_grad_sampler.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+    ci = ctypes.c_int
+    lib.rift_ile_lnL.argtypes = [P, i64, vp, vp, vp, ci, vp]
+    lib.rift_ile_lnZ.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, ci, vp]
+    lib.rift_ile_grad.argtypes = [P, i64, vp, ci, vp, vp, ci, vp]
+    lib.rift_ile_plan_create.argtypes = [P, i32, vp, ci, vp, ctypes.POINTER(vp)]
+    lib.rift_ile_plan_lnZ.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.rift_ile_plan_grad.argtypes = [vp, i32, i64, vp, ci, vp, vp, vp]
     lib.rift_ile_plan_tune.argtypes = [vp, vp, vp, vp]
     lib.rift_ile_plan_get_config.argtypes = [vp, ctypes.POINTER(CConfig)]
     lib.rift_ile_plan_set_config.argtypes = [vp, ctypes.POINTER(CConfig)]
@@ -171,21 +188,27 @@ def _theta(theta, device) -> torch.Tensor:
     return th.to(device=device, dtype=torch.float64).contiguous()
 
 
-def lnL(point, theta, precision: str = "fp64", device="cuda") -> torch.Tensor:
-    """lnL [n] of the samples theta [7, n] (Eq. (def:lnL:Decomposed))."""
+def lnL(point, theta, precision: str = "fp64", device="cuda", with_bound=False):
+    """lnL [n] of the samples theta [7, n] (Eq. (def:lnL:Decomposed)); with
+    `with_bound`, also every value's a-priori bound on |lnL - lnL_FP64| [n]."""
     lib = load()
     p = _as_point(point, device)
     th = _theta(theta, p.device)
     n = th.shape[1]
     out = torch.empty(n, dtype=torch.float64, device=p.device)
+    bnd = torch.empty(n, dtype=torch.float64, device=p.device) if with_bound else None
     cp = p.cstruct()
-    _check(lib.rift_ile_lnL(ctypes.byref(cp), n, th.data_ptr(), out.data_ptr(), PRECISIONS[precision],
+    _check(lib.rift_ile_lnL(ctypes.byref(cp), n, th.data_ptr(), out.data_ptr(),
+                            None if bnd is None else bnd.data_ptr(), PRECISIONS[precision],
                             _stream(p.device)), "rift_ile_lnL")
-    return out
+    return (out, bnd) if with_bound else out
 
 
-def grad(point, theta, device="cuda"):
-    """(lnL [n], d lnL / d(ra, dec, psi, cos incl, phiref, tref, ln dist) [7, n])."""
+def grad(point, theta, coords="sampler", device="cuda"):
+    """(lnL [n], gradient [7, n]) with theta rows 3 and 6 in the coordinates
+    `coords` ("physical": incl, dist; "paper": incl, ln dist; "sampler":
+    cos incl, ln dist; or the RIFT_COORD_* bits) and the gradient taken in
+    them."""
     lib = load()
     p = _as_point(point, device)
     th = _theta(theta, p.device)
@@ -193,8 +216,8 @@ def grad(point, theta, device="cuda"):
     out = torch.empty(n, dtype=torch.float64, device=p.device)
     g = torch.empty((7, n), dtype=torch.float64, device=p.device)
     cp = p.cstruct()
-    _check(lib.rift_ile_grad(ctypes.byref(cp), n, th.data_ptr(), out.data_ptr(), g.data_ptr(),
-                             _stream(p.device)), "rift_ile_grad")
+    _check(lib.rift_ile_grad(ctypes.byref(cp), n, th.data_ptr(), _coords(coords), out.data_ptr(), g.data_ptr(),
+                             RIFT_FP64, _stream(p.device)), "rift_ile_grad")
     return out, g
 
 
@@ -247,7 +270,7 @@ class Plan:
                "rift_ile_plan_create")
         self.handle = h
 
-    def lnZ(self, theta, lnw=None, lnZ_out=None, neff_out=None, lnL_out=None, err_out=None):
+    def lnZ(self, theta, lnw=None, lnZ_out=None, neff_out=None, lnL_out=None, err_out=None, bnd_out=None):
         th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
             else _theta(theta, self.device)
         P = len(self.points)
@@ -256,22 +279,21 @@ class Plan:
         _check(self.lib.rift_ile_plan_lnZ(self.handle, th.data_ptr(), None if lnw is None else lnw.data_ptr(),
                                           z.data_ptr(), ne.data_ptr(),
                                           None if lnL_out is None else lnL_out.data_ptr(),
+                                          None if bnd_out is None else bnd_out.data_ptr(),
                                           None if err_out is None else err_out.data_ptr(),
                                           _stream(self.device)), "rift_ile_plan_lnZ")
         return z, ne
 
-    def grad(self, point, theta, lnL_out=None, grad_out=None, sampler_coords=False):
-        """Gradient of lnL in (ra, dec, psi, cos incl, phiref, tref, ln dist).
-        With sampler_coords, rows 3 and 6 of theta hold cos incl and ln dist
-        (rift_ile_plan_grad_sampler) instead of incl and dist."""
+    def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):
+        """Gradient of lnL with theta rows 3 and 6 in the coordinates `coords`
+        (as in `grad`), taken in those coordinates."""
         th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
             else _theta(theta, self.device)
         n = th.shape[1]
         g = grad_out if grad_out is not None else torch.empty((7, n), dtype=torch.float64, device=self.device)
-        fn = self.lib.rift_ile_plan_grad_sampler if sampler_coords else self.lib.rift_ile_plan_grad
-        _check(fn(self.handle, int(point), n, th.data_ptr(),
-                  None if lnL_out is None else lnL_out.data_ptr(), g.data_ptr(),
-                  _stream(self.device)), "rift_ile_plan_grad")
+        _check(self.lib.rift_ile_plan_grad(self.handle, int(point), n, th.data_ptr(), _coords(coords),
+                                           None if lnL_out is None else lnL_out.data_ptr(), g.data_ptr(),
+                                           _stream(self.device)), "rift_ile_plan_grad")
         return g
 
     def tune(self, theta, lnw=None) -> int:
@@ -322,22 +344,20 @@ class Plan:
 
 
 class LnL(torch.autograd.Function):
-    """lnL(theta) with the hand-written gradient; theta [7, n] in the sampler's
-    coordinates is NOT used directly: inputs are (ra, dec, psi, incl, phiref,
-    tref, dist) and backward returns d/d(ra, dec, psi, incl, phiref, tref, dist)
-    (chain rule from the library's cos(incl) and ln(dist) derivatives)."""
+    """lnL(theta) with the hand-written adjoint kernel's gradient.
+
+    theta [7, n] holds (ra, dec, psi, incl, phiref, tref, ln dist) by default
+    (coords="paper"), or the rows 3 and 6 named by `coords` ("physical":
+    incl, dist; "sampler": cos incl, ln dist).  The kernel returns the gradient
+    in those same coordinates, and backward only scales it by grad_out."""
 
     @staticmethod
-    def forward(ctx, theta, point):
-        l, g = grad(point, theta.detach(), device=theta.device)
-        th = theta.detach()
-        gi = g.clone()
-        gi[3] = -torch.sin(th[3]) * g[3]   # d/dincl = -sin(incl) d/dcos(incl)
-        gi[6] = g[6] / th[6]               # d/ddist = (1/dist) d/dln(dist)
-        ctx.save_for_backward(gi)
+    def forward(ctx, theta, point, coords="paper"):
+        l, g = grad(point, theta.detach(), coords=coords, device=theta.device)
+        ctx.save_for_backward(g)
         return l
 
     @staticmethod
     def backward(ctx, grad_out):
-        (gi,) = ctx.saved_tensors
-        return grad_out[None, :] * gi, None
+        (g,) = ctx.saved_tensors
+        return grad_out[None, :] * g, None, None

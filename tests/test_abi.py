@@ -11,6 +11,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "rift_ile.h")
 EINVAL = -1
+EUNSUPPORTED = -4
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +33,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_strerror(lib):
-    assert lib.rift_ile_version() == 1
+    assert lib.rift_ile_version() == 2
     assert lib.rift_ile_strerror(0) == b"ok"
     assert lib.rift_ile_strerror(EINVAL) == b"invalid argument"
     assert lib.rift_ile_strerror(-99) == b"unknown status"
@@ -63,8 +64,8 @@ def test_invalid_point_rejected_on_host(lib, over):
     from paper_2609_37393_amd import ile
 
     cp, keep = _point(ile, **over)
-    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, 0, None) == EINVAL
-    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0x5000, 0x6000, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, None, 0, None) == EINVAL
+    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0, 0x5000, 0x6000, 0, None) == EINVAL
     n = np.array([10], np.int64)
     assert lib.rift_ile_lnZ(ctypes.byref(cp), 1, n.ctypes.data, 0x4000, None, 0x5000, None, None, 0,
                             None) == EINVAL
@@ -76,7 +77,7 @@ def test_invalid_modes_rejected(lib, lm):
 
     arr = np.array(lm, np.int32)
     cp, keep = _point(ile, lm=arr.ctypes.data)
-    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, None, 0, None) == EINVAL
 
 
 def test_invalid_detector_geometry_rejected(lib):
@@ -85,7 +86,7 @@ def test_invalid_detector_geometry_rejected(lib):
     D = np.zeros((2, 3, 3))
     D[1, 0, 0] = np.nan
     cp, keep = _point(ile, det_tensor=D.ctypes.data)
-    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, None, 0, None) == EINVAL
 
 
 def test_invalid_call_arguments_rejected(lib):
@@ -93,11 +94,22 @@ def test_invalid_call_arguments_rejected(lib):
 
     cp, keep = _point(ile)
     # negative n, null or misaligned sample / output pointers, bad precision
-    assert lib.rift_ile_lnL(ctypes.byref(cp), -1, 0x4000, 0x5000, 0, None) == EINVAL
-    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, None, 0x5000, 0, None) == EINVAL
-    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, None, 0, None) == EINVAL
-    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4001, 0x5000, 0, None) == EINVAL
-    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0x5000, None, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), -1, 0x4000, 0x5000, None, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, None, 0x5000, None, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, None, None, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4001, 0x5000, None, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, 0x6004, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 10, 0x4000, 0x5000, None, 3, None) == EINVAL
+    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0, 0x5000, None, 0, None) == EINVAL
+    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 4, 0x5000, 0x6000, 0, None) == EINVAL
+    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, -1, 0x5000, 0x6000, 0, None) == EINVAL
+    # the gradient is FP64 only: a valid request this build does not implement
+    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0, 0x5000, 0x6000, 1, None) == EUNSUPPORTED
+    assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0, 0x5000, 0x6000, 2, None) == EUNSUPPORTED
+    # RIFT_FP32 is an rift_ile_lnL-only precision
+    n1 = np.array([10], np.int64)
+    assert lib.rift_ile_lnZ(ctypes.byref(cp), 1, n1.ctypes.data, 0x4000, None, 0x5000, None, None, 2,
+                            None) == EINVAL
     n = np.array([10], np.int64)
     assert lib.rift_ile_lnZ(ctypes.byref(cp), 0, n.ctypes.data, 0x4000, None, 0x5000, None, None, 0,
                             None) == EINVAL
@@ -109,17 +121,17 @@ def test_invalid_call_arguments_rejected(lib):
     h = ctypes.c_void_p()
     assert lib.rift_ile_plan_create(ctypes.byref(cp), 1, n.ctypes.data, 7, None, ctypes.byref(h)) == EINVAL
     assert lib.rift_ile_plan_destroy(None) == EINVAL
-    assert lib.rift_ile_plan_lnZ(None, 0x4000, None, 0x5000, None, None, None, None) == EINVAL
-    assert lib.rift_ile_plan_grad(None, 0, 1, 0x4000, None, 0x5000, None) == EINVAL
+    assert lib.rift_ile_plan_lnZ(None, 0x4000, None, 0x5000, None, None, None, None, None) == EINVAL
+    assert lib.rift_ile_plan_grad(None, 0, 1, 0x4000, 0, None, 0x5000, None) == EINVAL
 
 
 def test_zero_samples_is_a_validated_noop(lib):
     from paper_2609_37393_amd import ile
 
     cp, keep = _point(ile)
-    assert lib.rift_ile_lnL(ctypes.byref(cp), 0, None, None, 0, None) == 0
+    assert lib.rift_ile_lnL(ctypes.byref(cp), 0, None, None, None, 0, None) == 0
     bad, keep2 = _point(ile, n_det=0)
-    assert lib.rift_ile_lnL(ctypes.byref(bad), 0, None, None, 0, None) == EINVAL
+    assert lib.rift_ile_lnL(ctypes.byref(bad), 0, None, None, None, 0, None) == EINVAL
 
 
 def test_product_path_has_no_oracle_dependency():

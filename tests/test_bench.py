@@ -19,7 +19,11 @@ def test_more_than_one_gpu_is_refused():
 def test_algorithmic_counts_of_the_headline_workload():
     import bench
 
-    # 3 detectors, 21 modes with l <= 4: the count quoted in the design notes
+    # the method's algorithmic count on its reduced forms (P = M(M+1)/2 pairs):
+    # 40 + 57 K + 10 M + 6 K M + 20 K M + 8 K P + P at 3 detectors, 21 modes
+    assert bench.survey_flops_per_sample(3, 21) == 7834
+    assert bench.survey_flops_per_sample(2, 2) == 40 + 114 + 20 + 24 + 80 + 48 + 3
+    # the build's own formulation (harmonic-basis contraction), reported beside it
     assert bench.flops_per_sample(3, 21, 4) == 5012
     # theta (7 doubles) in, lnL out
     assert bench.bytes_per_sample() == 64
