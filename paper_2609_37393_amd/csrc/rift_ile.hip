@@ -984,6 +984,14 @@ int build_tiles(rift_ile_plan p) {
   }
   if (p->h_tiles.size() > (size_t)0x7fffffff) return RIFT_EUNSUPPORTED;
   p->n_tiles = (int)p->h_tiles.size();
+  // release the previous tiling's buffers (the caller has synchronised)
+  for (void* b : {(void*)p->d_tiles, (void*)p->d_trange, (void*)p->d_part, (void*)p->d_tmax, (void*)p->d_terr}) {
+    auto it = std::find(p->bufs.begin(), p->bufs.end(), b);
+    if (b && it != p->bufs.end()) {
+      (void)hipFree(b);
+      p->bufs.erase(it);
+    }
+  }
   // (re)allocate tile-sized buffers
   void* v;
   int st;
@@ -1126,6 +1134,10 @@ int ensure_bin_buffers(rift_ile_plan p) {
   p->d_trec = (double*)v;
   BCHK(palloc(p, sizeof(double) * 8 * N, &v));
   p->d_aos = (double*)v;
+  if (!p->d_L) {  // lnL of the binned evaluation when the caller asks for none
+    BCHK(palloc(p, sizeof(double) * N, &v));
+    p->d_L = (double*)v;
+  }
 #undef BCHK
   p->bin_ready = true;
   return RIFT_OK;
@@ -1328,7 +1340,6 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     }
     PCHK(palloc(p, sizeof(int32_t) * M, &v));
     d_perm[pi] = (int32_t*)v;
-    PHIP(hipMemcpyAsync(d_perm[pi], perm.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
     PCHK(palloc(p, sizeof(double) * KT, &v));
     d_qmax[pi] = (double*)v;
   }
@@ -1393,39 +1404,13 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     p->n_stiles = (int)stiles.size();
     p->n_mat = mbase;
   }
-  PHIP(hipMemcpyAsync(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice, st));
-  for (int pi = 0; pi < n_points; ++pi) {
-    const rift_ile_point& pt = pts[pi];
-    PointDesc& D = p->h_desc[pi];
-    const int64_t qper = (int64_t)(pt.n_t + 2 * QPAD) * q_groups(pt.n_modes, QW64) * QW64;
-    const int gq = (int)std::min<int64_t>((KT * qper + 255) / 256, 65535);
-    hipLaunchKernelGGL(k_repack<double>, dim3(gq), dim3(256), 0, st, pt.Q, (double*)D.Q64, d_perm[pi],
-                       pt.n_det, KT, pt.n_modes, pt.n_t, QW64);
-    if (D.Q32)
-      hipLaunchKernelGGL(k_repack<float>, dim3(gq), dim3(256), 0, st, pt.Q, (float*)D.Q32, d_perm[pi],
-                         pt.n_det, KT, pt.n_modes, pt.n_t, QW32);
-    const int NG = 4 * D.L + 4;
-    hipLaunchKernelGGL(k_basis, dim3(KT), dim3(256), sizeof(double) * 3 * NG * NG, st,
-                       p->d_desc + pi, pt.U, pt.V, d_perm[pi], (double*)D.C64, (float*)D.C32);
-    if (mixed) {
-      // error-bound constants of the mixed path, from the table maxima and
-      // the basis coefficients
-      hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(1024), 0, st, D.Q64, d_qmax[pi], qper);
-      hipLaunchKernelGGL(k_bound, dim3(1), dim3(64), 0, st, p->d_desc + pi, (const double*)d_qmax[pi]);
-    }
-    PHIP(hipGetLastError());
-  }
+  // the rest of the plan's device memory, before anything is enqueued (an
+  // allocation that fails leaves nothing enqueued)
   PCHK(palloc(p, sizeof(int32_t) * 64, &v));
   p->d_counter = (int32_t*)v;
-  // the persistent kernel leaves it at 0 after each launch
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, p->d_counter, 64, 0);
-  PHIP(hipGetLastError());
-  // samples are addressed by int32 positions in the binned order
-  if (N > 0x7fffffff) p->cfg.sort = 0;
-  if (p->cfg.sort) PCHK(ensure_bin_buffers(p));
-  PCHK(palloc(p, sizeof(double) * N, &v));
-  p->d_L = (double*)v;
   if (mixed) {
+    PCHK(palloc(p, sizeof(double) * N, &v));
+    p->d_L = (double*)v;
     PCHK(palloc(p, sizeof(int32_t) * n_points, &v));
     p->d_cnt = (int32_t*)v;
     PCHK(palloc(p, sizeof(int32_t) * N, &v));
@@ -1444,6 +1429,33 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
     }
   }
   PCHK(build_tiles(p));
+  // set-up on the stream
+  PHIP(hipMemcpyAsync(p->d_desc, p->h_desc.data(), sizeof(PointDesc) * n_points, hipMemcpyHostToDevice, st));
+  for (int pi = 0; pi < n_points; ++pi) {
+    const rift_ile_point& pt = pts[pi];
+    PointDesc& D = p->h_desc[pi];
+    PHIP(hipMemcpyAsync(d_perm[pi], h_perm[pi].data(), sizeof(int32_t) * pt.n_modes, hipMemcpyHostToDevice, st));
+    const int64_t qper = (int64_t)(pt.n_t + 2 * QPAD) * q_groups(pt.n_modes, QW64) * QW64;
+    const int gq = (int)std::min<int64_t>((KT * qper + 255) / 256, 65535);
+    hipLaunchKernelGGL(k_repack<double>, dim3(gq), dim3(256), 0, st, pt.Q, (double*)D.Q64, d_perm[pi],
+                       pt.n_det, KT, pt.n_modes, pt.n_t, QW64);
+    if (D.Q32)
+      hipLaunchKernelGGL(k_repack<float>, dim3(gq), dim3(256), 0, st, pt.Q, (float*)D.Q32, d_perm[pi],
+                         pt.n_det, KT, pt.n_modes, pt.n_t, QW32);
+    const int NG = 4 * D.L + 4;
+    hipLaunchKernelGGL(k_basis, dim3(KT), dim3(256), sizeof(double) * 3 * NG * NG, st,
+                       p->d_desc + pi, pt.U, pt.V, d_perm[pi], (double*)D.C64, (float*)D.C32);
+    if (mixed) {
+      // error-bound constants of the mixed path, from the table maxima and
+      // the basis coefficients
+      hipLaunchKernelGGL(k_qmax, dim3(KT), dim3(1024), 0, st, D.Q64, d_qmax[pi], qper);
+      hipLaunchKernelGGL(k_bound, dim3(1), dim3(64), 0, st, p->d_desc + pi, (const double*)d_qmax[pi]);
+    }
+    PHIP(hipGetLastError());
+  }
+  // the persistent kernel leaves it at 0 after each launch
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, p->d_counter, 64, 0);
+  PHIP(hipGetLastError());
   // the staged host copies (mode permutations) are released on return
   PHIP(hipStreamSynchronize(st));
 #undef PCHK
@@ -1470,7 +1482,7 @@ int rift_ile_plan_set_config(rift_ile_plan plan, const rift_ile_config* cfg) {
   if (cfg->sort && (st = ensure_bin_buffers(plan))) return st;
   const bool retile = cfg->block * cfg->tile_blocks != plan->cfg.block * plan->cfg.tile_blocks;
   plan->cfg = *cfg;
-  if (retile) return build_tiles(plan);  // old tile buffers stay owned until destroy
+  if (retile) return build_tiles(plan);
   return RIFT_OK;
 }
 
