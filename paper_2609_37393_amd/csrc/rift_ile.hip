@@ -312,8 +312,10 @@ __global__ void k_final(const Tile* __restrict__ tiles, const double* __restrict
       } else if (l != -__builtin_inf()) {
         const double x = exp(l - m);
         sum += x;
-        const float b = bnd[i];
-        if (b > 0.0f) err += x * expm1((double)b);
+        // e^{l - m} (e^b - 1), bounded by e^{l - m + b} where e^b alone
+        // would overflow (a far-off sample with a wide bound: its term is tiny)
+        const double b = (double)bnd[i];
+        if (b > 0.0) err += (b < 30.0) ? x * expm1(b) : exp(l - m + b);
       }
     }
   } else {
