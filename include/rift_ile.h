@@ -76,7 +76,9 @@ typedef enum {
   RIFT_EINVAL = -1,      /* bad argument (null pointer, size or mode out of range) */
   RIFT_EDEVICE = -2,     /* a HIP runtime call failed */
   RIFT_ENOMEM = -3,      /* device or host allocation failed */
-  RIFT_EUNSUPPORTED = -4 /* valid request this build does not implement */
+  RIFT_EUNSUPPORTED = -4, /* valid request this build does not implement */
+  RIFT_ESCRATCH = -5      /* rift_ile_lnZ_noalloc: the request needs more device memory than
+                             its fixed scratch (RIFT_ILE_NOALLOC_SCRATCH_BYTES) */
 } rift_status;
 
 typedef enum {
@@ -221,6 +223,26 @@ int rift_ile_plan_profile(rift_ile_plan plan, int enable);
 int rift_ile_plan_profile_read(rift_ile_plan plan, double *total_ms, int64_t *launches);
 
 int rift_ile_plan_destroy(rift_ile_plan plan);
+
+/* ------------------------------------------------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): rift_ile_lnZ with
+ * the same arguments, semantics and results (the same kernels and launch
+ * shape), whose working memory -- repacked tables, basis coefficients, tiles,
+ * partial sums and, in mixed precision, the per-sample scratch of the
+ * recompute -- lives in a fixed device array of RIFT_ILE_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends.  It
+ * calls no hipMalloc or hipFree (the host bookkeeping uses the host heap).
+ * A request whose working memory does not fit returns RIFT_ESCRATCH before
+ * anything is enqueued; about 7 MB serve a 3-detector, 21-mode point of 6554
+ * samples per series in FP64 (16 more bytes per sample in mixed precision).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (other threads, other streams) race and must be serialised by the
+ * caller.  Synchronises `stream` before returning, like rift_ile_lnZ. */
+#define RIFT_ILE_NOALLOC_SCRATCH_BYTES (64u << 20)
+int rift_ile_lnZ_noalloc(const rift_ile_point *pts, int32_t n_points, const int64_t *n_per_point,
+                         const double *theta, const double *lnw, double *lnZ, double *neff, double *lnL,
+                         int precision, void *stream);
 
 const char *rift_ile_strerror(int status);
 int rift_ile_version(void);

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -907,6 +908,10 @@ struct rift_ile_plan_s {
   std::vector<PointDesc> h_desc;
   PointDesc* d_desc = nullptr;
   std::vector<void*> bufs;  // device allocations owned by the plan
+  // allocation-free plans: every buffer is carved from a fixed device region
+  char* arena = nullptr;
+  size_t arena_cap = 0;
+  size_t arena_off = 0;
   // tiles (depend on the config)
   rift_ile_config cfg{256, 4, 0, 0};
   std::vector<Tile> h_tiles;
@@ -948,6 +953,14 @@ struct rift_ile_plan_s {
 namespace {
 
 int palloc(rift_ile_plan p, size_t bytes, void** out) {
+  if (p->arena) {
+    const size_t off = (p->arena_off + 255) & ~(size_t)255;
+    const size_t len = bytes < 256 ? 256 : bytes;
+    if (off > p->arena_cap || len > p->arena_cap - off) return RIFT_ESCRATCH;
+    *out = p->arena + off;
+    p->arena_off = off + len;
+    return RIFT_OK;
+  }
   void* d = nullptr;
   if (hipMalloc(&d, bytes < 256 ? 256 : bytes) != hipSuccess) return RIFT_ENOMEM;
   p->bufs.push_back(d);
@@ -1177,6 +1190,7 @@ const char* rift_ile_strerror(int status) {
     case RIFT_EDEVICE: return "HIP runtime error";
     case RIFT_ENOMEM: return "out of memory";
     case RIFT_EUNSUPPORTED: return "unsupported request";
+    case RIFT_ESCRATCH: return "request exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -1214,8 +1228,12 @@ int rift_ile_plan_destroy(rift_ile_plan plan) {
   return RIFT_OK;
 }
 
-int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int64_t* n_per_point,
-                         int precision, void* stream, rift_ile_plan* out) {
+namespace {
+// Plan creation; with `arena` set, every device buffer of the plan is carved
+// from [arena, arena + arena_cap) instead of allocated (RIFT_ESCRATCH if it
+// does not fit, before anything is enqueued).
+int plan_create_impl(const rift_ile_point* pts, int32_t n_points, const int64_t* n_per_point, int precision,
+                     void* stream, char* arena, size_t arena_cap, rift_ile_plan* out) {
   if (!out || !pts || !n_per_point || n_points < 1 || n_points > (1 << 20)) return RIFT_EINVAL;
   if (precision != RIFT_FP64 && precision != RIFT_MIXED) return RIFT_EINVAL;
   int64_t N = 0;
@@ -1229,6 +1247,8 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
   *out = nullptr;
   rift_ile_plan p = new (std::nothrow) rift_ile_plan_s;
   if (!p) return RIFT_ENOMEM;
+  p->arena = arena;
+  p->arena_cap = arena ? arena_cap : 0;
   hipStream_t st = (hipStream_t)stream;
   int rc = device_info(&p->di);
   if (rc) { delete p; return rc; }
@@ -1465,6 +1485,12 @@ int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int6
   p->last = st;
   *out = p;
   return RIFT_OK;
+}
+}  // namespace
+
+int rift_ile_plan_create(const rift_ile_point* pts, int32_t n_points, const int64_t* n_per_point,
+                         int precision, void* stream, rift_ile_plan* out) {
+  return plan_create_impl(pts, n_points, n_per_point, precision, stream, nullptr, 0, out);
 }
 
 int rift_ile_plan_get_config(rift_ile_plan plan, rift_ile_config* cfg) {
@@ -1705,3 +1731,48 @@ int rift_ile_grad(const rift_ile_point* pt, int64_t n, const double* theta, int 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry point: its plan lives in a fixed device array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: it passes the device address that
+// hipGetSymbolAddress returns for the current device (kept per device).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[RIFT_ILE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// The current device's scratch address, looked up once per device.
+int scratch_of_current_device(char** out) {
+  int dev = -1;
+  HCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return RIFT_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RIFT_EDEVICE;
+    g_scratch[dev] = (char*)ptr;
+  }
+  *out = g_scratch[dev];
+  return RIFT_OK;
+}
+}  // namespace
+
+extern "C" int rift_ile_lnZ_noalloc(const rift_ile_point* pts, int32_t n_points, const int64_t* n_per_point,
+                                    const double* theta, const double* lnw, double* lnZ, double* neff,
+                                    double* lnL, int precision, void* stream) {
+  if (check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  if (precision != RIFT_FP64 && precision != RIFT_MIXED) return RIFT_EINVAL;
+  char* base = nullptr;
+  int rc = scratch_of_current_device(&base);
+  if (rc) return rc;
+  rift_ile_plan p = nullptr;
+  rc = plan_create_impl(pts, n_points, n_per_point, precision, stream, base, RIFT_ILE_NOALLOC_SCRATCH_BYTES, &p);
+  if (rc) return rc;
+  rc = rift_ile_plan_lnZ(p, theta, lnw, lnZ, neff, lnL, nullptr, nullptr, stream);
+  int rc2 = rift_ile_plan_destroy(p);
+  return rc ? rc : rc2;
+}
