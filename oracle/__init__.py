@@ -61,6 +61,9 @@ def _load():
         lib.oracle_lnL.argtypes = [p, ctypes.c_int64, p, p, ctypes.c_int]
         lib.oracle_grad.argtypes = [p, ctypes.c_int64, p, p, p, ctypes.c_int]
         lib.oracle_lnZ.argtypes = [ctypes.c_int64, p, p, p, p]
+        lib.oracle_rotation_harmonics.argtypes = [p, d, d, p]
+        lib.oracle_wide_coef.argtypes = [p, p, p, p]
+        lib.oracle_lnL_wide.argtypes = [p, ctypes.c_int64, p, p, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -113,6 +116,50 @@ def _pack(pt) -> _Packed:
                  _ptr(U).value, _ptr(V).value, _ptr(D).value, _ptr(R).value,
                  float(pt["gmst"]), float(pt["d_ref"]))
     return _Packed(cp, (lm, Q, U, V, D, R))
+
+
+class _CPointWide(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32),
+        ("M", ctypes.c_int32),
+        ("n_t", ctypes.c_int32),
+        ("lm", ctypes.c_void_p),
+        ("t0", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("response", ctypes.c_int32),
+        ("n_a", ctypes.c_int32),
+        ("Q", ctypes.c_void_p),
+        ("U", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
+        ("det_tensor", ctypes.c_void_p),
+        ("det_pos", ctypes.c_void_p),
+        ("det_arms", ctypes.c_void_p),
+        ("gmst", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("d_ref", ctypes.c_double),
+    ]
+
+
+RESPONSES = {"rotation": 1, "arms": 2}
+
+
+def _pack_wide(pt) -> _Packed:
+    """pt: mapping as for `_pack` plus response ("rotation" | "arms"), Q [K, n_a, M, n_t],
+    U, V [K, n_a M, n_a M] (composite index a M + i), det_arms [K, 2, 3], omega."""
+    lm = _c(pt["lm"], np.int32)
+    Q = _c(pt["Q"], np.complex128)
+    U = _c(pt["U"], np.complex128)
+    V = _c(pt["V"], np.complex128)
+    D = _c(pt["det_tensor"], np.float64)
+    R = _c(pt["det_pos"], np.float64)
+    AR = _c(pt["det_arms"], np.float64)
+    K, n_a, M, n_t = Q.shape
+    A = n_a * M
+    assert U.shape == (K, A, A) and V.shape == (K, A, A) and lm.shape == (M, 2) and AR.shape == (K, 2, 3)
+    cp = _CPointWide(K, M, n_t, _ptr(lm).value, float(pt["t0"]), float(pt["dt"]), RESPONSES[pt["response"]],
+                     n_a, _ptr(Q).value, _ptr(U).value, _ptr(V).value, _ptr(D).value, _ptr(R).value,
+                     _ptr(AR).value, float(pt["gmst"]), float(pt.get("omega", 0.0)), float(pt["d_ref"]))
+    return _Packed(cp, (lm, Q, U, V, D, R, AR))
 
 
 # ---------------------------------------------------------------------------
@@ -195,6 +242,35 @@ def lnZ(lnL_values, lnw=None):
     ne = np.zeros(1)
     _load().oracle_lnZ(l.shape[0], _ptr(l), None if w is None else _ptr(w), _ptr(z), _ptr(ne))
     return float(z[0]), float(ne[0])
+
+
+def rotation_harmonics(det_tensor, dec, psi):
+    """A_n, n = -2..2, of F(g) = sum_n A_n e^{i n g} over the Greenwich hour
+    angle g at fixed dec, psi (Eq. (slowrot:Fharm))."""
+    out = np.zeros(10)
+    _load().oracle_rotation_harmonics(_ptr(_c(det_tensor, np.float64)), float(dec), float(psi), _ptr(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def wide_coef(pt, theta1):
+    """Composite coefficients C~ [K, n_a] and arrival times t_k [K] of one sample
+    (Eqs. (slowrot:postphase), (fsize:bp))."""
+    pk = _pack_wide(pt)
+    K, n_a = pk.cp.K, pk.cp.n_a
+    C = np.zeros(2 * K * n_a)
+    tk = np.zeros(K)
+    _load().oracle_wide_coef(ctypes.byref(pk.cp), _ptr(_c(theta1, np.float64)), _ptr(C), _ptr(tk))
+    return (C[0::2] + 1j * C[1::2]).reshape(K, n_a), tk
+
+
+def lnL_wide(pt, theta, nthreads: int = 0) -> np.ndarray:
+    """Composite-index lnL, Eq. (slowrot:lnL:Decomposed), for theta [7, n]."""
+    th = _c(theta, np.float64)
+    n = th.shape[1]
+    out = np.empty(n)
+    pk = _pack_wide(pt)
+    _load().oracle_lnL_wide(ctypes.byref(pk.cp), n, _ptr(th), _ptr(out), int(nthreads))
+    return out
 
 
 def pregrid(q, r: int):

@@ -15,6 +15,9 @@
 //   * Monte-Carlo marginal likelihood:     Eq. (lnL:MonteCarlo)
 //   * effective sample size:               Eq. (neff)
 //   * gradient (the differentiable path):  Sec. "The differentiable likelihood"
+//   * composite-index likelihood (Earth rotation, Path A; finite arms, Path D):
+//     Sec. "A generalized detector response", Eqs. (slowrot:Fharm),
+//     (slowrot:postphase), (slowrot:lnL:Decomposed), (fsize:bp)
 //
 // Readings where the paper is silent or inconsistent (all listed in the
 // design notes of the repository):
@@ -267,11 +270,182 @@ T lnL_one(const Point& p, const T& ra, const T& dec, const T& psi, const T& iota
   return lnL_factored(p.K, p.M, F.data(), Y.data(), x, Qhat.data(), p.U, p.V);
 }
 
+// ---------------------------------------------------------------------------
+// Generalised (composite-index) response, Sec. "A generalized detector
+// response": the mode index widens to A = (a, lm) and the antenna factor F_k
+// to a coefficient C~^k_a per composite term a.  Two responses:
+//   rotation (Path A, "Earth rotation: a slowly time-varying response"):
+//     a <-> sidereal harmonic n = a - 2 in -2..2.  F_k as a function of the
+//     Greenwich hour angle g is a trigonometric polynomial of degree 2,
+//     F_k(g) = sum_n A_n e^{i n g} (Eq. (slowrot:Fharm)), with A_n depending on
+//     dec and psi only.  C^k_n = A_n e^{i n g(t_ref)} and the arrival-time
+//     post-phase of Eq. (slowrot:postphase) gives C~^k_n = C^k_n e^{i n W (t_k - t_ref)}.
+//     g(t) = gmst + W t - ra, t on the axis of t_ref (W the sidereal rate);
+//     the delay is held at t_k = t_ref - r_k . N(g(t_ref)) (Path A).
+//   arms (Path D, "Long arms: a frequency-dependent response"):
+//     a <-> order p = a of the arm-projection expansion, Eq. (fsize:bp):
+//     b^k_p = 1/2 [ (x.N)^p e:xx - (y.N)^p e:yy ] with x, y the arm unit
+//     vectors, N towards the source and e = e+ + i ex the complex polarisation
+//     tensor of the reading F = F+ + i Fx (so b_0 = D : e = F_k for
+//     D = (x x^T - y y^T)/2).  Static sky frame.
+// The likelihood is Eq. (slowrot:lnL:Decomposed) with Q, U, V over the
+// composite index (layout [k][a][lm][n_t] and [k][a M + i][a' M + j]).
+// ---------------------------------------------------------------------------
+struct PointWide {
+  int32_t K, M, n_t;
+  const int32_t* lm;
+  double t0, dt;
+  int32_t response;        // 1: rotation, 2: arms
+  int32_t n_a;             // composite terms per detector
+  const double* Q;         // [K][n_a][M][n_t] complex
+  const double* U;         // [K][n_a M][n_a M] complex
+  const double* V;         // [K][n_a M][n_a M] complex
+  const double* det_tensor;  // [K][3][3]
+  const double* det_pos;     // [K][3] light-seconds
+  const double* det_arms;    // [K][2][3] arm unit vectors (arms response)
+  double gmst;             // Greenwich sidereal angle at t = 0 (rad)
+  double omega;            // sidereal rate (rad/s), rotation response
+  double d_ref;
+};
+
+// The five sidereal Fourier coefficients A_n (n = -2..2) of F_k(g) at fixed
+// dec and psi: the exact 5-point discrete Fourier transform of the degree-2
+// trigonometric polynomial F_k over g.
+void rotation_harmonics(const double* det_tensor, double dec, double psi, Cx<double> A[5]) {
+  const double two_pi = 2.0 * M_PI;
+  Cx<double> Fg[5];
+  for (int j = 0; j < 5; ++j) {
+    const double g = two_pi * j / 5.0;
+    double N[3], X[3], Y[3];
+    // hour angle g = gmst - ra with gmst = g, ra = 0
+    sky_frame<double>(0.0, dec, psi, g, N, X, Y);
+    Fg[j] = antenna<double>(det_tensor, X, Y);
+  }
+  for (int n = -2; n <= 2; ++n) {
+    Cx<double> acc{0.0, 0.0};
+    for (int j = 0; j < 5; ++j) {
+      const double g = two_pi * j / 5.0;
+      const Cx<double> e{std::cos(n * g), -std::sin(n * g)};
+      const Cx<double> t = cmul(Fg[j], e);
+      acc.re += t.re;
+      acc.im += t.im;
+    }
+    A[n + 2] = Cx<double>{acc.re / 5.0, acc.im / 5.0};
+  }
+}
+
+// Composite coefficients C~[k][a] and arrival times t_k of one sample.
+void wide_coefficients(const PointWide& p, double ra, double dec, double psi, double tref,
+                       std::vector<Cx<double>>& C, std::vector<double>& tk) {
+  C.assign((size_t)p.K * p.n_a, Cx<double>{0.0, 0.0});
+  tk.assign(p.K, 0.0);
+  const double gm = (p.response == 1) ? p.gmst + p.omega * tref : p.gmst;
+  double N[3], X[3], Y[3];
+  sky_frame<double>(ra, dec, psi, gm, N, X, Y);
+  for (int k = 0; k < p.K; ++k) {
+    const double* r = p.det_pos + 3 * k;
+    tk[k] = tref - (r[0] * N[0] + r[1] * N[1] + r[2] * N[2]);
+    if (p.response == 1) {
+      Cx<double> A[5];
+      rotation_harmonics(p.det_tensor + 9 * k, dec, psi, A);
+      const double gref = gm - ra;  // g(t_ref)
+      for (int a = 0; a < p.n_a; ++a) {
+        const int n = a - 2;
+        const double ph = n * gref + n * p.omega * (tk[k] - tref);
+        C[(size_t)k * p.n_a + a] = cmul(A[a], Cx<double>{std::cos(ph), std::sin(ph)});
+      }
+    } else {
+      const double* ax = p.det_arms + 6 * k;
+      const double* ay = ax + 3;
+      // e : a a = (X.a + i Y.a)^2 for a unit arm vector a
+      const double xX = X[0] * ax[0] + X[1] * ax[1] + X[2] * ax[2];
+      const double xY = Y[0] * ax[0] + Y[1] * ax[1] + Y[2] * ax[2];
+      const double yX = X[0] * ay[0] + X[1] * ay[1] + X[2] * ay[2];
+      const double yY = Y[0] * ay[0] + Y[1] * ay[1] + Y[2] * ay[2];
+      const Cx<double> ex = cmul(Cx<double>{xX, xY}, Cx<double>{xX, xY});
+      const Cx<double> ey = cmul(Cx<double>{yX, yY}, Cx<double>{yX, yY});
+      const double ux = N[0] * ax[0] + N[1] * ax[1] + N[2] * ax[2];
+      const double uy = N[0] * ay[0] + N[1] * ay[1] + N[2] * ay[2];
+      double px = 1.0, py = 1.0;
+      for (int a = 0; a < p.n_a; ++a) {
+        C[(size_t)k * p.n_a + a] = Cx<double>{0.5 * (px * ex.re - py * ey.re), 0.5 * (px * ex.im - py * ey.im)};
+        px *= ux;
+        py *= uy;
+      }
+    }
+  }
+}
+
+// Eq. (slowrot:lnL:Decomposed) for one sample: plain loops over detectors,
+// composite terms and modes.
+double lnL_wide_one(const PointWide& p, double ra, double dec, double psi, double iota, double phi,
+                    double tref, double dist) {
+  std::vector<Cx<double>> C, Y(p.M);
+  std::vector<double> tk;
+  wide_coefficients(p, ra, dec, psi, tref, C, tk);
+  for (int i = 0; i < p.M; ++i) Y[i] = ylm_m2<double>(p.lm[2 * i], p.lm[2 * i + 1], iota, phi);
+  const int A = p.n_a * p.M;
+  std::vector<Cx<double>> c(A);
+  double data = 0.0, quad = 0.0;
+  for (int k = 0; k < p.K; ++k) {
+    for (int a = 0; a < p.n_a; ++a)
+      for (int i = 0; i < p.M; ++i) c[a * p.M + i] = cmul(C[(size_t)k * p.n_a + a], Y[i]);
+    // data term: Re sum_A conj(c_A) Q_{k,A}(t_k)
+    for (int a = 0; a < p.n_a; ++a)
+      for (int i = 0; i < p.M; ++i) {
+        const double* q = p.Q + 2 * ((((size_t)k * p.n_a + a) * p.M + i) * p.n_t);
+        const Cx<double> qh = interp_lagrange4<double>(q, p.n_t, p.t0, p.dt, tk[k]);
+        const Cx<double> t = cmul(cconj(c[a * p.M + i]), qh);
+        data += t.re;
+      }
+    // quadratic term: c^H U c + Re(c^T V c)
+    Cx<double> cu{0.0, 0.0}, cv{0.0, 0.0};
+    for (int I = 0; I < A; ++I)
+      for (int J = 0; J < A; ++J) {
+        const double* u = p.U + 2 * (((size_t)k * A + I) * A + J);
+        const double* v = p.V + 2 * (((size_t)k * A + I) * A + J);
+        const Cx<double> tu = cmul(cmul(cconj(c[I]), Cx<double>{u[0], u[1]}), c[J]);
+        const Cx<double> tv = cmul(cmul(c[I], Cx<double>{v[0], v[1]}), c[J]);
+        cu.re += tu.re; cu.im += tu.im;
+        cv.re += tv.re; cv.im += tv.im;
+      }
+    quad += cu.re + cv.re;
+  }
+  const double x = p.d_ref / dist;
+  return x * data - x * x * quad * 0.25;
+}
+
 }  // namespace
 
 extern "C" {
 
 int oracle_version() { return 1; }
+
+// Sidereal harmonics A_n (n = -2..2) of one detector's F(g): out[5][2].
+void oracle_rotation_harmonics(const double* det_tensor, double dec, double psi, double* out) {
+  Cx<double> A[5];
+  rotation_harmonics(det_tensor, dec, psi, A);
+  for (int n = 0; n < 5; ++n) { out[2 * n] = A[n].re; out[2 * n + 1] = A[n].im; }
+}
+
+// Composite coefficients C~[K][n_a][2] and arrival times tk[K] of one sample
+// theta[7] (ra, dec, psi, incl, phiref, tref, dist).
+void oracle_wide_coef(const PointWide* p, const double* theta, double* C, double* tk) {
+  std::vector<Cx<double>> c;
+  std::vector<double> t;
+  wide_coefficients(*p, theta[0], theta[1], theta[2], theta[5], c, t);
+  for (size_t i = 0; i < c.size(); ++i) { C[2 * i] = c[i].re; C[2 * i + 1] = c[i].im; }
+  for (int k = 0; k < p->K; ++k) tk[k] = t[k];
+}
+
+// lnL of the composite-index likelihood for n samples (SoA [7][n]).
+void oracle_lnL_wide(const PointWide* p, int64_t n, const double* theta, double* lnL, int nthreads) {
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    lnL[i] = lnL_wide_one(*p, theta[i], theta[n + i], theta[2 * n + i], theta[3 * n + i], theta[4 * n + i],
+                          theta[5 * n + i], theta[6 * n + i]);
+}
 
 // -2Y_lm(iota, phi) -> out[2] = (re, im)
 void oracle_ylm(int l, int m, double iota, double phi, double* out) {

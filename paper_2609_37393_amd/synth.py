@@ -54,6 +54,7 @@ def network(K: int, seed: int, radius_m: float = R_EARTH_M):
     rng = _rng(seed, 11)
     D = np.zeros((K, 3, 3))
     R = np.zeros((K, 3))
+    arms = np.zeros((K, 2, 3))
     for k in range(K):
         n = rng.normal(size=3)
         n /= np.linalg.norm(n)
@@ -64,8 +65,10 @@ def network(K: int, seed: int, radius_m: float = R_EARTH_M):
         y -= x * np.dot(x, y)
         y /= np.linalg.norm(y)
         D[k] = 0.5 * (np.outer(x, x) - np.outer(y, y))
+        arms[k, 0] = x
+        arms[k, 1] = y
     gmst = float(rng.uniform(0.0, 2.0 * np.pi))
-    return {"det_tensor": D, "det_pos": R, "gmst": gmst}
+    return {"det_tensor": D, "det_pos": R, "gmst": gmst, "det_arms": arms}
 
 
 def freq_grid(f_hi: int = 1700):
@@ -199,6 +202,7 @@ def make_point(K: int, M: int, n_t: int, fs: float, snr: float, seed: int,
         "V": V,
         "det_tensor": net["det_tensor"],
         "det_pos": net["det_pos"],
+        "det_arms": net.get("det_arms"),
         "gmst": net["gmst"],
         "d_ref": float(d_ref),
         "snr": float(snr),
@@ -298,3 +302,104 @@ def batched_points(n_points: int, seed: int, K: int = 3, fs: float = 32768.0,
         inj = injection_fn(K, M, sub) if injection_fn is not None else random_injection(K, M, sub)
         pts.append(make_point(K, M, n_t, fs, snr, sub, injection=inj, net=net))
     return pts
+
+
+# ---------------------------------------------------------------------------
+# Composite-index banks (generalised response)
+# ---------------------------------------------------------------------------
+SIDEREAL_RATE = 7.292115e-5  # rad/s
+
+
+def make_point_wide(K: int, M: int, n_a: int, n_t: int, fs: float, snr: float, seed: int,
+                    response: str = "rotation", omega: float = SIDEREAL_RATE, net=None,
+                    noise: bool = True, d_ref: float = 100.0, lm=None, keep_spectra: bool = False):
+    """One intrinsic point of the composite-index likelihood: a bank of n_a x M
+    templates chi_(a,lm) (index a M + i), its Q [K, n_a, M, n_t], U, V
+    [K, n_a M, n_a M] by their inner-product definitions (Eq. (slowrot:QUV)),
+    and an injection made of the bank's templates, scaled to network SNR `snr`.
+
+    The bank's templates are generic stand-ins with the shapes of the paper's
+    (the elementary modulated templates, or the frequency-weighted modes of the
+    finite-arm expansion, are built upstream of the likelihood): chi_(a,lm)(f) =
+    h_lm(f) w_a(f), with w_a(f) = 1 for the leading term (a = 2, n = 0, for the
+    rotation response; a = 0 for the arms) and otherwise a smooth seeded
+    complex weight of amplitude 0.2-0.6.  The injection's coefficients are a
+    generic rank-one z_(k,(a,lm)) = alpha_(k,a) y_lm with arrival times t_k.
+    """
+    lm = modes(M) if lm is None else np.asarray(lm, np.int32)
+    M = lm.shape[0]
+    f, G = mode_spectra(lm, seed)
+    rng = _rng(seed, 123)
+    lead = 2 if response == "rotation" else 0
+    Wt = np.ones((n_a, f.size), np.complex128)
+    for a in range(n_a):
+        if a == lead:
+            continue
+        amp = rng.uniform(0.2, 0.6)
+        tau = rng.normal(0.0, 3e-4)
+        ph0 = rng.uniform(0.0, 2 * np.pi)
+        slope = rng.normal(0.0, 1e-3)
+        Wt[a] = amp * (1.0 + slope * (np.abs(f) - 150.0) / 150.0) * np.exp(1j * (ph0 + 2 * np.pi * f * tau))
+    Gw = (Wt[:, None, :] * G[None, :, :]).reshape(n_a * M, f.size)
+    w = noise_weights(K, f, seed)
+    net = net if net is not None else network(K, seed)
+    yv = rng.normal(size=M) + 1j * rng.normal(size=M)
+    yv[:2] *= 4.0
+    yv /= np.linalg.norm(yv)
+    alpha = rng.uniform(0.2, 1.0, size=(K, n_a)) * np.exp(1j * rng.uniform(0, 2 * np.pi, size=(K, n_a)))
+    alpha[:, lead] *= 3.0
+    z = (alpha[:, :, None] * yv[None, None, :]).reshape(K, n_a * M)
+    tk = rng.uniform(-0.02, 0.02, size=K)
+    h = _strain(z, tk, f, Gw)
+    rho2 = float(np.sum(w * np.abs(h) ** 2))
+    scale = snr / np.sqrt(rho2) if rho2 > 0 else 0.0
+    h *= scale
+    d = h.copy()
+    if noise:
+        nrng = _rng(seed, 55)
+        pos = f > 0
+        nz = np.zeros((K, f.size), np.complex128)
+        sig = np.sqrt(1.0 / np.where(w > 0, w, np.inf))
+        nz[:, pos] = sig[:, pos] * (nrng.normal(size=(K, pos.sum())) +
+                                    1j * nrng.normal(size=(K, pos.sum()))) / np.sqrt(2.0)
+        nz[:, f < 0] = np.conj(nz[:, pos][:, ::-1])
+        d = d + nz
+    U = np.einsum("kf,if,jf->kij", w, np.conj(Gw), Gw)
+    V = np.einsum("kf,if,jf->kij", w, Gw[:, ::-1], Gw)
+    nfft = int(round(fs))
+    if abs(nfft - fs) > 1e-9 or f[-1] >= fs / 2:
+        raise ValueError("fs must be an integer rate above twice the band edge")
+    A = n_a * M
+    X = np.zeros((K, A, nfft), np.complex128)
+    bins = np.mod(f.astype(np.int64), nfft)
+    X[:, :, bins] = w[:, None, :] * np.conj(Gw)[None, :, :] * d[:, None, :]
+    full = np.fft.ifft(X, axis=-1) * nfft
+    j0 = n_t // 2
+    idx = np.mod(np.arange(n_t) - j0, nfft)
+    Q = full[:, :, idx].reshape(K, n_a, M, n_t)
+    out = {
+        "lm": lm, "t0": -j0 / fs, "dt": 1.0 / fs, "Q": Q, "U": U, "V": V,
+        "det_tensor": net["det_tensor"], "det_pos": net["det_pos"], "det_arms": net["det_arms"],
+        "gmst": net["gmst"], "d_ref": float(d_ref), "response": response, "n_a": int(n_a),
+        "omega": float(omega if response == "rotation" else 0.0), "snr": float(snr),
+        "half_dd": 0.5 * float(np.sum(w * np.abs(d) ** 2)),
+    }
+    if keep_spectra:
+        out["spectra"] = {"f": f, "G": Gw, "w": w, "d": d}
+    return out
+
+
+def widen_static(pt, n_a: int, response: str = "rotation"):
+    """The static point `pt` as a composite-index point whose every template
+    equals its mode (chi_(a,lm) = h_lm for all a): the bank the generalised
+    likelihood reduces to when the expansion is trivial (zero rotation rate,
+    or the arms' zeroth order alone)."""
+    K, M, n_t = pt["Q"].shape
+    Q = np.repeat(pt["Q"][:, None, :, :], n_a, axis=1)
+    U = np.tile(pt["U"], (1, n_a, n_a))
+    V = np.tile(pt["V"], (1, n_a, n_a))
+    out = dict(pt)
+    out.update({"Q": Q, "U": U, "V": V, "response": response, "n_a": int(n_a), "omega": 0.0})
+    if "det_arms" not in out:
+        raise ValueError("the point needs det_arms (synth.network provides them)")
+    return out
