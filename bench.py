@@ -362,12 +362,25 @@ def extra_c3(ile, synth, torch, steps, n_points=512, per_point=200_000, cpu=True
     return res
 
 
+def seed_near_peak(ile, torch, synth, pt, sig, n=200_000, rounds=(100.0, 30.0, 10.0, 3.0, 1.0)):
+    """Seeding of the chains (not timed): the best of n prior draws, then the
+    best of n draws around the current best at shrinking widths (rounds x
+    sig), every lnL from the library itself."""
+    th = synth.prior_samples(n, 4)
+    best = th[:, int(torch.argmax(ile.lnL(pt, th)).item())]
+    for r, w in enumerate(rounds):
+        th = synth.perturbed_samples(best, np.asarray(sig) * w, n, 40 + r)
+        th = np.concatenate([best[:, None], th], axis=1)
+        best = th[:, int(torch.argmax(ile.lnL(pt, th)).item())]
+    return best
+
+
 def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64, cpu=True):
     """4096 chains x 64 leapfrog-style gradient evaluations (K = 3, 9 modes,
     SNR 600), the 64 steps captured into one graph."""
     pt = synth.make_point(3, 9, 6554, 32768.0, 600.0, 4)
-    th0 = synth.prior_samples(1, 4)[:, 0]
     sig = np.array([1e-3, 1e-3, 5e-3, 5e-3, 5e-3, 3e-6, 5e-3])
+    th0 = seed_near_peak(ile, torch, synth, pt, sig)
     start = synth.perturbed_samples(th0, sig, chains, 5)
     plan = ile.Plan([pt], [chains])
     q = torch.as_tensor(start, device="cuda").contiguous()
@@ -376,19 +389,19 @@ def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64, cpu=True):
     c[6] = torch.log(q[6])
     cq = c.clone()
     p = torch.zeros_like(c)
-    sigt = torch.as_tensor(sig, device="cuda")[:, None]
     eps = 0.1
-    step_q = (eps * sigt * sigt).expand_as(p).contiguous()  # eps sigma^2, per parameter
+    step_q = eps * sig * sig  # eps sigma^2 per parameter (mass diag(sigma^-2))
     g = torch.empty_like(q)
 
     # the chain moves in (.., cos incl, .., .., ln dist), the coordinates of
-    # the gradient, and hands them to the library as they are; one fused
-    # elementwise launch per leapfrog update
+    # the gradient, and hands them to the library as they are; per leapfrog
+    # step one launch per momentum half-step and one drift launch (with the
+    # reflecting boundary of cos incl)
     def run():
         plan.grad(0, cq, grad_out=g, coords="sampler")
         for _ in range(nsteps - 1):
             p.add_(g, alpha=0.5 * eps)
-            cq.addcmul_(step_q, p)
+            ile.leapfrog_drift(cq, p, step_q)
             plan.grad(0, cq, grad_out=g, coords="sampler")
             p.add_(g, alpha=0.5 * eps)
 
@@ -405,12 +418,12 @@ def extra_c4(ile, synth, torch, steps, chains=4096, nsteps=64, cpu=True):
     run()
     kms, launches = plan.profile_read()
     plan.profile(False)
-    finite = bool(torch.isfinite(g).all().item())
+    finite = float(torch.isfinite(g).all(dim=0).double().mean().item())
     plan.close()
     evals = chains * nsteps
     res = {"grad_evals_per_s": evals * steps / secs, "ms_per_graph": 1e3 * secs / steps,
            "kernel_ms_avg": kms / max(1, launches), "chains": chains, "steps_per_chain": nsteps,
-           "chain_states_finite": finite,
+           "finite_fraction_after_64_steps": finite,
            "workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 600; "
                        "4096 chains x 64 gradient evaluations in one graph"}
     if cpu:
@@ -527,14 +540,63 @@ def extra_c5_batch(ile, synth, torch, steps, n_batch=64, per_point=200_000, cpu=
     return batch
 
 
+def wide_flops_per_sample(K, M, n_a, response):
+    """Algorithmic flops of one composite-index lnL evaluation: the static
+    count with the mode index widened to A = n_a M (P_A = A(A+1)/2 pairs),
+    plus the composite coefficients (rotation: F at five hour angles, ~40
+    flops each, the 5x5 complex transform and the phases; arms: the arm
+    projections and n_a powers)."""
+    A = n_a * M
+    P = A * (A + 1) // 2
+    coef = (5 * 40 + 200 + 40) if response == "rotation" else (40 + 12 * n_a)
+    return 40 + 57 * K + 10 * M + K * coef + 6 * K * A + 20 * K * A + 8 * K * P + P
+
+
+def extra_wide(ile, synth, torch, steps, cpu=True):
+    """The generalised response (composite index A = (a, lm)): Earth rotation
+    (5 sidereal terms) at widths 20 and 105, finite arms (p_max = 3) at width
+    16; 3 detectors, Q 6554 samples at 32768 Hz, SNR 600.  Each call is
+    timed whole (the description's upload and the synchronisation
+    included)."""
+    res = {}
+    for name, resp, M, n_a, n in (("rotation_w20", "rotation", 4, 5, 1_000_000),
+                                  ("rotation_w105", "rotation", 21, 5, 200_000),
+                                  ("arms_w16", "arms", 4, 4, 1_000_000)):
+        pt = synth.make_point_wide(3, M, n_a, 6554, 32768.0, 600.0, 60 + M, response=resp)
+        dp = ile.DeviceWidePoint.from_dict(pt)
+        th = torch.as_tensor(synth.prior_samples(n, 61), device="cuda").contiguous()
+        ile.wide_lnZ(dp, th)
+        torch.cuda.synchronize()
+        reps = max(3, steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            z, _ = ile.wide_lnZ(dp, th)
+        torch.cuda.synchronize()
+        secs = (time.perf_counter() - t0) / reps
+        fl = wide_flops_per_sample(3, M, n_a, resp)
+        r = {"response": resp, "modes": M, "terms": n_a, "width": M * n_a, "n_samples": n,
+             "lnL_evals_per_s": n / secs, "ms_per_call": 1e3 * secs, "flops_per_sample": fl,
+             "alu_frac_of_call": fl * n / secs / (PEAK_FP64_TFLOPS * 1e12), "lnZ": z.item()}
+        if cpu:
+            import oracle
+
+            k = min(n, 20_000)
+            t0 = time.perf_counter()
+            oracle.lnL_wide(pt, th[:, :k].cpu().numpy())
+            r["cpu_oracle_lnL_evals_per_s"] = k / (time.perf_counter() - t0)
+        res[name] = r
+        del th, dp
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5",
-                    help="workloads timed beside the headline one (comma list of c1, c4, c5, c3, c1big; "
+    ap.add_argument("--workloads", default="c1,c4,c5,wide",
+                    help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
                     help="add the longer workloads (the 512-point batch c3, C1 at 1e7 samples c1big, "
@@ -655,7 +717,7 @@ def main():
     wanted = [x.strip() for x in args.workloads.split(",") if x.strip() and x.strip() != "none"]
     wanted += [x.strip() for x in args.extras.split(",") if x.strip()]
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
-           "c5batch": extra_c5_batch}
+           "c5batch": extra_c5_batch, "wide": extra_wide}
     for name in wanted:
         log(f"workload {name}")
         try:

@@ -225,6 +225,68 @@ int rift_ile_plan_profile_read(rift_ile_plan plan, double *total_ms, int64_t *la
 int rift_ile_plan_destroy(rift_ile_plan plan);
 
 /* ------------------------------------------------------------------------ */
+/* Generalised detector response (Sec. "A generalized detector response"): the
+ * mode index widens to the composite index A = (a, lm) and the static antenna
+ * factor F_k to a coefficient C~^k_a per composite term, Eq.
+ * (slowrot:lnL:Decomposed) / (slowrot:lnL:MatrixForm):
+ *   lnL = x Re sum_k sum_a sum_lm conj(C~^k_a Y_lm) Q_{k,a lm}(t_k)
+ *       - x^2/4 sum_k [ c_k^H U_k c_k + Re(c_k^T V_k c_k) ],  c_{k,(a,lm)} = C~^k_a Y_lm.
+ * RIFT_RESP_ROTATION (Earth rotation, Path A): n_terms = 5, a <-> sidereal
+ *   harmonic n = a - 2; C~_n = A_n(dec, psi) e^{i n g(tref)} e^{i n omega (t_k - tref)}
+ *   with F_k(g) = sum_n A_n e^{i n g} over the Greenwich hour angle
+ *   g(t) = gmst_rad + omega t - ra (Eqs. (slowrot:Fharm), (slowrot:postphase));
+ *   the bank's modulation e^{i n omega t} is referenced to the template's own
+ *   time, and the delay is held at the arrival time of the sky frame at tref.
+ *   omega = 0 with every term's template equal to its mode is the static
+ *   likelihood.
+ * RIFT_RESP_ARMS (finite arms, Path D): n_terms = p_max + 1 <= 8, a <-> order p;
+ *   C~_p = b_p = 1/2 [(x.N)^p e:xx - (y.N)^p e:yy] with the arm unit vectors
+ *   x, y of each detector and e = e+ + i ex (Eq. (fsize:bp)); static sky frame;
+ *   p_max = 0 is the static likelihood (with det_tensor = (x x^T - y y^T)/2). */
+#define RIFT_RESP_ROTATION 1
+#define RIFT_RESP_ARMS 2
+typedef struct {
+  int32_t n_det;            /* K, 1..RIFT_ILE_MAX_DET */
+  int32_t n_modes;          /* M, 1..RIFT_ILE_MAX_MODES */
+  int32_t n_t;              /* samples per series, 4 .. RIFT_ILE_MAX_NT */
+  const int32_t *lm;        /* HOST [M][2] (l, m) as in rift_ile_point */
+  double t0, dt;            /* Q grid t_j = t0 + j dt (s) */
+  int32_t response;         /* RIFT_RESP_ROTATION or RIFT_RESP_ARMS */
+  int32_t n_terms;          /* composite terms per detector (5, or p_max + 1 <= 8) */
+  const double *Q;          /* DEVICE [K][n_terms][M][n_t] complex: Q_{k,(a,lm)}(t_j) */
+  const double *U;          /* DEVICE [K][n_terms M][n_terms M] complex, index a M + i; Hermitian */
+  const double *V;          /* DEVICE, same layout; symmetric */
+  const double *det_tensor; /* HOST [K][3][3] */
+  const double *det_pos;    /* HOST [K][3] light-seconds */
+  const double *det_arms;   /* HOST [K][2][3] arm unit vectors x, y (RIFT_RESP_ARMS), else unused */
+  double gmst_rad;          /* sidereal angle at t = 0 (rad) */
+  double omega;             /* sidereal rate (rad/s), RIFT_RESP_ROTATION */
+  double d_ref;
+} rift_ile_point_wide;
+
+/* lnL of n samples (theta DEVICE [7][n] as for rift_ile_lnL) in FP64; lnL:
+ * DEVICE [n].  Same errors and non-finite semantics as rift_ile_lnL; returns
+ * after the work is done. */
+int rift_ile_wide_lnL(const rift_ile_point_wide *pt, int64_t n, const double *theta, double *lnL,
+                      void *stream);
+/* ln Z and n_eff (DEVICE [1] each, neff may be NULL) of n >= 1 samples with
+ * weights lnw (DEVICE [n] or NULL), Eqs. (lnL:MonteCarlo), (neff); lnL:
+ * DEVICE [n] or NULL. */
+int rift_ile_wide_lnZ(const rift_ile_point_wide *pt, int64_t n, const double *theta, const double *lnw,
+                      double *lnZ, double *neff, double *lnL, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Leapfrog drift for gradient-based samplers in the coordinates of
+ * RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST (Sec. "Sampling the
+ * differentiable extrinsic likelihood"): theta[a][i] += step[a] p[a][i] for
+ * the seven rows, then cos incl (row 3) folded back into [-1, 1] by
+ * reflection, p[3][i] changing sign after an odd number of folds (the
+ * reversible, volume-preserving treatment of the bounded coordinate).
+ * theta, p: DEVICE [7][n] (updated in place); step: HOST [7].  Enqueues and
+ * returns; capturable.  Non-finite values pass through unchanged. */
+int rift_ile_leapfrog_drift(int64_t n, double *theta, double *p, const double *step, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): rift_ile_lnZ with
  * the same arguments, semantics and results (the same kernels and launch

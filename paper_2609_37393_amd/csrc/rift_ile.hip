@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/rift_ile.h"
+#include "ile_host.h"
 #include "ile_kernels.h"
 
 using namespace rift;
@@ -797,45 +798,6 @@ __global__ void k_tmax_tiles(const Tile* __restrict__ tiles, const double* __res
 inline int kt_class(int K) { return K <= 2 ? 2 : (K <= 3 ? 3 : (K <= 5 ? 5 : 8)); }
 inline int l_class(int lmax) { return lmax <= 2 ? 2 : (lmax <= 3 ? 3 : (lmax <= 4 ? 4 : 8)); }
 inline int lbit(int L) { return L == 2 ? 1 : (L == 3 ? 2 : (L == 4 ? 4 : 8)); }
-
-double factorial(int n) {
-  double f = 1.0;
-  for (int i = 2; i <= n; ++i) f *= i;
-  return f;
-}
-
-// Wigner d^l_{m,s}(beta), explicit sum over k (s = 2 for spin weight -2).
-double wigner_d(int l, int m, int s, double beta) {
-  const double c = cos(0.5 * beta), sn = sin(0.5 * beta);
-  const int k0 = std::max(0, m - s), k1 = std::min(l + m, l - s);
-  const double pre = sqrt(factorial(l + m) * factorial(l - m) * factorial(l + s) * factorial(l - s));
-  double d = 0.0;
-  for (int k = k0; k <= k1; ++k) {
-    const double den = factorial(l + m - k) * factorial(l - s - k) * factorial(k) * factorial(k + s - m);
-    d += ((k & 1) ? -1.0 : 1.0) * pre / den * pow(c, 2 * l + m - s - 2 * k) * pow(sn, 2 * k + s - m);
-  }
-  return d;
-}
-
-// Fourier coefficients in incl of sqrt((2l+1)/4pi) d^l_{m,2}(incl): a cosine
-// series for even m, a sine series for odd m, degree <= l (exact by a 32-point
-// DFT since l <= 8).
-void ylm_fourier(int l, int m, double* out /* [LMAXC+1] */) {
-  const int N = 32;
-  const double two_pi = 6.283185307179586476925286766559;
-  const double norm = sqrt((2.0 * l + 1.0) / (2.0 * two_pi));
-  for (int n = 0; n <= LMAXC; ++n) out[n] = 0.0;
-  for (int n = 0; n <= l; ++n) {
-    double acc = 0.0;
-    for (int p = 0; p < N; ++p) {
-      const double b = two_pi * p / N;
-      const double d = wigner_d(l, m, 2, b);
-      acc += d * ((m & 1) ? sin(n * b) : cos(n * b));
-    }
-    out[n] = norm * acc * ((n == 0) ? 1.0 : 2.0) / N;
-  }
-  if (m & 1) out[0] = 0.0;
-}
 
 struct DeviceInfo {
   int dev = -1;

@@ -56,7 +56,13 @@ EXPORTS = (
     "rift_ile_plan_destroy",
     "rift_ile_strerror",
     "rift_ile_version",
+    "rift_ile_wide_lnL",
+    "rift_ile_wide_lnZ",
+    "rift_ile_lnZ_noalloc",
+    "rift_ile_leapfrog_drift",
 )
+
+RESPONSES = {"rotation": 1, "arms": 2}
 
 
 class CPoint(ctypes.Structure):
@@ -73,6 +79,28 @@ class CPoint(ctypes.Structure):
         ("det_tensor", ctypes.c_void_p),
         ("det_pos", ctypes.c_void_p),
         ("gmst_rad", ctypes.c_double),
+        ("d_ref", ctypes.c_double),
+    ]
+
+
+class CPointWide(ctypes.Structure):
+    _fields_ = [
+        ("n_det", ctypes.c_int32),
+        ("n_modes", ctypes.c_int32),
+        ("n_t", ctypes.c_int32),
+        ("lm", ctypes.c_void_p),
+        ("t0", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("response", ctypes.c_int32),
+        ("n_terms", ctypes.c_int32),
+        ("Q", ctypes.c_void_p),
+        ("U", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
+        ("det_tensor", ctypes.c_void_p),
+        ("det_pos", ctypes.c_void_p),
+        ("det_arms", ctypes.c_void_p),
+        ("gmst_rad", ctypes.c_double),
+        ("omega", ctypes.c_double),
         ("d_ref", ctypes.c_double),
     ]
 
@@ -109,6 +137,11 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_plan_profile.argtypes = [vp, ctypes.c_int]
     lib.rift_ile_plan_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.rift_ile_plan_destroy.argtypes = [vp]
+    PW = ctypes.POINTER(CPointWide)
+    lib.rift_ile_wide_lnL.argtypes = [PW, i64, vp, vp, vp]
+    lib.rift_ile_wide_lnZ.argtypes = [PW, i64, vp, vp, vp, vp, vp, vp]
+    lib.rift_ile_lnZ_noalloc.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, ci, vp]
+    lib.rift_ile_leapfrog_drift.argtypes = [i64, vp, vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
     lib.rift_ile_strerror.restype = ctypes.c_char_p
     lib.rift_ile_version.restype = ctypes.c_int
@@ -175,6 +208,90 @@ class DevicePoint:
         return CPoint(K, M, n_t, self.lm.ctypes.data, self.t0, self.dt, self.Q.data_ptr(),
                       self.U.data_ptr(), self.V.data_ptr(), self.det_tensor.ctypes.data,
                       self.det_pos.ctypes.data, self.gmst, self.d_ref)
+
+
+@dataclass
+class DeviceWidePoint:
+    """A composite-index point (generalised response) with Q, U, V on the GPU."""
+    lm: np.ndarray
+    t0: float
+    dt: float
+    response: str
+    Q: torch.Tensor       # [K, n_terms, M, n_t, 2] float64
+    U: torch.Tensor       # [K, n_terms M, n_terms M, 2]
+    V: torch.Tensor
+    det_tensor: np.ndarray
+    det_pos: np.ndarray
+    det_arms: np.ndarray
+    gmst: float
+    omega: float
+    d_ref: float
+
+    @classmethod
+    def from_dict(cls, pt, device="cuda"):
+        return cls(
+            lm=np.ascontiguousarray(pt["lm"], dtype=np.int32), t0=float(pt["t0"]), dt=float(pt["dt"]),
+            response=pt["response"], Q=_dev_f64(pt["Q"], device), U=_dev_f64(pt["U"], device),
+            V=_dev_f64(pt["V"], device),
+            det_tensor=np.ascontiguousarray(pt["det_tensor"], dtype=np.float64),
+            det_pos=np.ascontiguousarray(pt["det_pos"], dtype=np.float64),
+            det_arms=np.ascontiguousarray(pt["det_arms"], dtype=np.float64),
+            gmst=float(pt["gmst"]), omega=float(pt.get("omega", 0.0)), d_ref=float(pt["d_ref"]))
+
+    @property
+    def device(self):
+        return self.Q.device
+
+    def cstruct(self) -> CPointWide:
+        K, n_a, M, n_t = self.Q.shape[:4]
+        return CPointWide(K, M, n_t, self.lm.ctypes.data, self.t0, self.dt, RESPONSES[self.response], n_a,
+                          self.Q.data_ptr(), self.U.data_ptr(), self.V.data_ptr(), self.det_tensor.ctypes.data,
+                          self.det_pos.ctypes.data, self.det_arms.ctypes.data, self.gmst, self.omega, self.d_ref)
+
+
+def _as_wide(pt, device) -> DeviceWidePoint:
+    return pt if isinstance(pt, DeviceWidePoint) else DeviceWidePoint.from_dict(pt, device)
+
+
+def wide_lnL(point, theta, device="cuda") -> torch.Tensor:
+    """lnL [n] of the composite-index likelihood (Eq. (slowrot:lnL:Decomposed))."""
+    lib = load()
+    p = _as_wide(point, device)
+    th = _theta(theta, p.device)
+    n = th.shape[1]
+    out = torch.empty(n, dtype=torch.float64, device=p.device)
+    cp = p.cstruct()
+    _check(lib.rift_ile_wide_lnL(ctypes.byref(cp), n, th.data_ptr(), out.data_ptr(), _stream(p.device)),
+           "rift_ile_wide_lnL")
+    return out
+
+
+def wide_lnZ(point, theta, lnw=None, want_lnL=False, device="cuda"):
+    """(ln Z, n_eff[, lnL]) of the composite-index likelihood over the samples."""
+    lib = load()
+    p = _as_wide(point, device)
+    th = _theta(theta, p.device)
+    n = th.shape[1]
+    w = None if lnw is None else torch.as_tensor(lnw).to(device=p.device, dtype=torch.float64).contiguous()
+    z = torch.empty(1, dtype=torch.float64, device=p.device)
+    ne = torch.empty(1, dtype=torch.float64, device=p.device)
+    ll = torch.empty(n, dtype=torch.float64, device=p.device) if want_lnL else None
+    cp = p.cstruct()
+    _check(lib.rift_ile_wide_lnZ(ctypes.byref(cp), n, th.data_ptr(), None if w is None else w.data_ptr(),
+                                 z.data_ptr(), ne.data_ptr(), None if ll is None else ll.data_ptr(),
+                                 _stream(p.device)), "rift_ile_wide_lnZ")
+    return (z, ne, ll) if want_lnL else (z, ne)
+
+
+def leapfrog_drift(theta: torch.Tensor, p: torch.Tensor, step):
+    """theta += step * p in place (rows as in the sampler's coordinates), with
+    cos incl reflected into [-1, 1] and its momentum flipped (rift_ile_leapfrog_drift)."""
+    lib = load()
+    st = np.ascontiguousarray(step, dtype=np.float64)
+    if st.shape != (7,) or theta.shape != p.shape or theta.shape[0] != 7:
+        raise ValueError("theta, p: [7, n]; step: [7]")
+    _check(lib.rift_ile_leapfrog_drift(theta.shape[1], theta.data_ptr(), p.data_ptr(), st.ctypes.data,
+                                       _stream(theta.device)), "rift_ile_leapfrog_drift")
 
 
 def _as_point(pt, device) -> DevicePoint:

@@ -142,3 +142,60 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "liboracle" not in txt, f
+
+
+def _point_wide(ile, **over):
+    lm = np.array([[2, 2], [2, -2]], np.int32)
+    D = np.zeros((2, 3, 3))
+    R = np.zeros((2, 3))
+    A = np.zeros((2, 2, 3))
+    keep = (lm, D, R, A)
+    f = dict(n_det=2, n_modes=2, n_t=410, lm=lm.ctypes.data, t0=-0.05, dt=1 / 4096, response=1, n_terms=5,
+             Q=0x1000, U=0x2000, V=0x3000, det_tensor=D.ctypes.data, det_pos=R.ctypes.data,
+             det_arms=A.ctypes.data, gmst_rad=0.1, omega=7.292115e-5, d_ref=100.0)
+    f.update(over)
+    return ile.CPointWide(**f), keep
+
+
+BAD_WIDE = BAD + [
+    dict(response=0), dict(response=3), dict(n_terms=4), dict(omega=float("nan")),
+    dict(response=2, n_terms=0), dict(response=2, n_terms=33), dict(response=2, det_arms=None),
+]
+
+
+@pytest.mark.parametrize("over", BAD_WIDE)
+def test_invalid_wide_point_rejected_on_host(lib, over):
+    from paper_2609_37393_amd import ile
+
+    cp, keep = _point_wide(ile, **over)
+    assert lib.rift_ile_wide_lnL(ctypes.byref(cp), 0, None, None, None) == EINVAL
+    assert lib.rift_ile_wide_lnZ(ctypes.byref(cp), 10, 0x4000, None, 0x5000, None, None, None) == EINVAL
+
+
+def test_wide_call_arguments(lib):
+    from paper_2609_37393_amd import ile
+
+    cp, keep = _point_wide(ile)
+    assert lib.rift_ile_wide_lnL(ctypes.byref(cp), 0, None, None, None) == 0
+    cp2, keep2 = _point_wide(ile, response=2, n_terms=4)
+    assert lib.rift_ile_wide_lnL(ctypes.byref(cp2), 0, None, None, None) == 0
+    assert lib.rift_ile_wide_lnL(ctypes.byref(cp), -1, 0x4000, 0x5000, None) == EINVAL
+    assert lib.rift_ile_wide_lnL(ctypes.byref(cp), 10, None, 0x5000, None) == EINVAL
+    assert lib.rift_ile_wide_lnL(ctypes.byref(cp), 10, 0x4000, None, None) == EINVAL
+    assert lib.rift_ile_wide_lnL(ctypes.byref(cp), 10, 0x4004, 0x5000, None) == EINVAL
+    # ln Z of no samples is undefined; a null ln Z output is refused
+    assert lib.rift_ile_wide_lnZ(ctypes.byref(cp), 0, 0x4000, None, 0x5000, None, None, None) == EINVAL
+    assert lib.rift_ile_wide_lnZ(ctypes.byref(cp), 10, 0x4000, None, None, None, None, None) == EINVAL
+
+
+def test_leapfrog_drift_arguments(lib):
+    step = np.full(7, 1e-3)
+    s = step.ctypes.data
+    assert lib.rift_ile_leapfrog_drift(0, None, None, s, None) == 0
+    assert lib.rift_ile_leapfrog_drift(-1, 0x4000, 0x5000, s, None) == EINVAL
+    assert lib.rift_ile_leapfrog_drift(10, 0x4000, 0x5000, None, None) == EINVAL
+    assert lib.rift_ile_leapfrog_drift(10, None, 0x5000, s, None) == EINVAL
+    assert lib.rift_ile_leapfrog_drift(10, 0x4000, 0x5004, s, None) == EINVAL
+    bad = step.copy()
+    bad[3] = np.inf
+    assert lib.rift_ile_leapfrog_drift(10, 0x4000, 0x5000, bad.ctypes.data, None) == EINVAL
