@@ -698,6 +698,7 @@ def main():
             "dlnZ_vs_fp64": abs(r32["lnZ"] - r64["lnZ"]),
             "lnZ_err_bound": r32["lnZ_err_bound"],
             "launch": r32["config"],
+            "launch_variants": r32["variants"],
         },
         "lnZ": r64["lnZ"],
         "neff": r64["neff"],

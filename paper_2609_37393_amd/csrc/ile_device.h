@@ -595,34 +595,22 @@ __device__ __forceinline__ double data_direct(PDesc P, RIFT_LDS unsigned char* s
   return data;
 }
 
-// Everything per sample.  R is the arithmetic type of the bulk (FP64 or FP32);
-// the sky frame, delays and the final combination are always FP64.  The data
-// term comes from data_fn(row, sfr, Fre, Fim, cn, sn, cf, sf).
-//
-// `trig` is this lane's column of a block-shared scratch array (stride `ts`
-// elements) that receives cos(n incl), n = 0..NI, then sin(n incl), for the
-// runtime contraction loop of the l <= 8 class.
-template <class R, int KT, int L, bool BOUND, class DataFn>
-__device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, int ts, double ra,
-                                                 double dec, double psi, double incl, double phi,
-                                                 double tref, double dist, DataFn&& data_fn) {
-  typedef Cls<L> CL;
-  constexpr int NI = CL::NI;
-  constexpr int NY = CL::NY;
-  const int n_t = P->n_t;
-  if constexpr (sizeof(R) == 4) {
-    psi = reduce_2pi(psi);
-    incl = reduce_2pi(incl);
-    phi = reduce_2pi(phi);
-  }
-
-  // --- sky frame (FP64) --------------------------------------------------
+// Antenna factors of one sample and, for the data term, its stencils: the sky
+// frame (FP64), the polarisation tensors and F_k = F+ + i Fx (R), and per
+// detector the arrival time t_k and stencil row / fraction (FP64 phase).
+template <class R, int KT>
+struct Sky {
+  R Fre[KT], Fim[KT];
+  R sfr[KT];        // fractional position inside the stencil cell
+  int32_t row[KT];  // padded index of the first stencil row, in [0, n_t + QPAD]
+  bool bad;         // a non-finite arrival time
+};
+template <class R, int KT, bool STENCIL>
+__device__ __forceinline__ void sky_eval(PDesc P, double ra, double dec, double psi, double tref, Sky<R, KT>& S) {
   double sg, cg, sd, cd;
   sincos_(P->gmst - ra, &sg, &cg);
   sincos_(dec, &sd, &cd);
   const double N0 = cd * cg, N1 = -cd * sg, N2 = sd;
-
-  // --- polarisation tensors (R) ------------------------------------------
   R sp, cp;
   sincos_((R)psi, &sp, &cp);
   const R ea0 = (R)sg, ea1 = (R)cg;
@@ -633,42 +621,8 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
                    X0 * X1 - Y0 * Y1, X0 * X2 - Y0 * Y2, X1 * X2 - Y1 * Y2};
   const R ex[6] = {2 * X0 * Y0, 2 * X1 * Y1, 2 * X2 * Y2,
                    X0 * Y1 + Y0 * X1, X0 * Y2 + Y0 * X2, X1 * Y2 + Y1 * X2};
-
-  // --- harmonics in incl (Chebyshev recurrences) --------------------------
-  R si, ci;
-  sincos_((R)incl, &si, &ci);
-  R cn[NY], sn[NY];
-  {
-    R c0 = 1, c1 = ci, s0 = 0, s1 = si;
-#pragma unroll
-    for (int n = 0; n <= NI; ++n) {
-      const R c = (n == 0) ? c0 : c1;
-      const R s = (n == 0) ? s0 : s1;
-      if (n < NY) {
-        cn[n] = c;
-        sn[n] = s;
-      }
-      if constexpr (L > 4) {  // the runtime contraction loop reads these
-        trig[n * ts] = c;
-        trig[(NI + 1 + n) * ts] = s;
-      }
-      if (n > 0) {
-        const R c2 = 2 * ci * c1 - c0, s2 = 2 * ci * s1 - s0;
-        c0 = c1;
-        c1 = c2;
-        s0 = s1;
-        s1 = s2;
-      }
-    }
-  }
-  R sf, cf;
-  sincos_((R)phi, &sf, &cf);
-
-  // --- antenna factors and stencils per detector --------------------------
-  R Fre[KT], Fim[KT];
-  R sfr[KT];        // fractional position inside the stencil cell
-  int32_t row[KT];  // padded index of the first stencil row, in [0, n_t + QPAD]
-  bool bad = false;
+  S.bad = false;
+  const int n_t = P->n_t;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     R fp = 0, fx = 0;
@@ -677,35 +631,66 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
       fp += Tab<R>::d(P, k, a) * ep[a];
       fx += Tab<R>::d(P, k, a) * ex[a];
     }
-    Fre[k] = fp;
-    Fim[k] = fx;
-    const RIFT_CONST double* r = P->rpos[k];
-    const double tk = tref - (r[0] * N0 + r[1] * N1 + r[2] * N2);
-    double u = (tk - P->t0) * P->inv_dt;
-    if (!stencil_u(u, n_t)) bad = true;
-    const double jf = floor(u);
-    const R s = (R)(u - jf);
-    int j0 = (int)jf - 1;  // stencil rows j0 .. j0+3
-    // wholly outside the stored window: read four zero pad rows
-    j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
-    row[k] = j0 + QPAD;
-    sfr[k] = s;
+    S.Fre[k] = fp;
+    S.Fim[k] = fx;
+    if constexpr (STENCIL) {
+      const RIFT_CONST double* r = P->rpos[k];
+      const double tk = tref - (r[0] * N0 + r[1] * N1 + r[2] * N2);
+      double u = (tk - P->t0) * P->inv_dt;
+      if (!stencil_u(u, n_t)) S.bad = true;
+      const double jf = floor(u);
+      const R s = (R)(u - jf);
+      int j0 = (int)jf - 1;  // stencil rows j0 .. j0+3
+      // wholly outside the stored window: read four zero pad rows
+      j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
+      S.row[k] = j0 + QPAD;
+      S.sfr[k] = s;
+    }
   }
+}
 
-  // The data term is bound by its Q reads, the contraction below by the ALU:
-  // a wavefront in the data term gets issue priority over one in the
-  // contraction, so that the two on a SIMD keep both busy.
-  __builtin_amdgcn_s_setprio(1);
-  const double data = data_fn(row, sfr, Fre, Fim, cn, sn, cf, sf);
-  __builtin_amdgcn_s_setprio(0);
+// The angles that the FP32 arithmetic takes, reduced in FP64 first.
+template <class R>
+__device__ __forceinline__ void reduce_angles(double& psi, double& incl, double& phi) {
+  if constexpr (sizeof(R) == 4) {
+    psi = reduce_2pi(psi);
+    incl = reduce_2pi(incl);
+    phi = reduce_2pi(phi);
+  }
+}
 
-  // --- model-norm term: basis contraction ----------------------------------
+// Model-norm term sum_k |F_k|^2 a_k/4 + Re(F_k^2 b_k)/4 from the basis
+// contraction at (incl, phiref); with BOUND, also the model-norm part of the
+// FP32 error bound (see PointDesc).  `trig` is this lane's column of a
+// block-shared scratch array (stride `ts` elements) that receives
+// cos(n incl), n = 0..NI, then sin(n incl), for the runtime contraction loop
+// of the l <= 8 class.
+template <class R, int KT, int L, bool BOUND>
+__device__ __forceinline__ double quad_term(PDesc P, R* __restrict__ trig, int ts, R ci, R si, R cf, R sf,
+                                            const R* Fre, const R* Fim, double* wq_out) {
+  typedef Cls<L> CL;
+  constexpr int NI = CL::NI;
   R acc[3 * KT];
 #pragma unroll
   for (int c = 0; c < 3 * KT; ++c) acc[c] = 0;
   if constexpr (L <= 4) {
     Contract<R, KT, L>::run(P, ci, si, cf, sf, acc);
   } else {
+    {
+      R c0 = 1, c1 = ci, s0 = 0, s1 = si;
+#pragma unroll
+      for (int n = 0; n <= NI; ++n) {
+        trig[n * ts] = (n == 0) ? c0 : c1;
+        trig[(NI + 1 + n) * ts] = (n == 0) ? s0 : s1;
+        if (n > 0) {
+          const R c2 = 2 * ci * c1 - c0, s2 = 2 * ci * s1 - s0;
+          c0 = c1;
+          c1 = c2;
+          s0 = s1;
+          s1 = s2;
+        }
+      }
+    }
     // runtime loop over basis rows (reads cos/sin(n incl) from this lane's
     // column of the block-shared scratch array)
     const RIFT_CONST R* Cc = Tab<R>::C(P);
@@ -785,15 +770,65 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
       wq += fe * fe * P->bnd_q[k] + (2.0 * fe + e) * e * P->l1q[k];
     }
   }
+  if (BOUND) *wq_out = wq;
+  return quad;
+}
 
+// cos(n incl), sin(n incl) for n < NY by the Chebyshev recurrences.
+template <class R, int NY>
+__device__ __forceinline__ void incl_harmonics(R ci, R si, R* cn, R* sn) {
+  R c0 = 1, c1 = ci, s0 = 0, s1 = si;
+#pragma unroll
+  for (int n = 0; n < NY; ++n) {
+    cn[n] = (n == 0) ? c0 : c1;
+    sn[n] = (n == 0) ? s0 : s1;
+    if (n > 0) {
+      const R c2 = 2 * ci * c1 - c0, s2 = 2 * ci * s1 - s0;
+      c0 = c1;
+      c1 = c2;
+      s0 = s1;
+      s1 = s2;
+    }
+  }
+}
+
+// lnL = x data - x^2 quad with x = D_ref / D (FP64), NaN for a poisoned
+// sample, and the a-priori FP32 bound |x| bnd_d + x^2 wq, rounded up on the
+// way to FP32 (the factor covers the conversion).
+template <bool BOUND>
+__device__ __forceinline__ Eval combine(PDesc P, double dist, double data, double quad, double wq, bool bad) {
   const double x = P->d_ref / dist;
   Eval e;
   e.lnL = x * data - x * x * quad;
   if (bad) e.lnL = __builtin_nan("");
   e.bound = 0.0f;
-  // rounded up on the way to FP32 (the factor covers the conversion)
   if (BOUND) e.bound = (float)((fabs(x) * P->bnd_d + x * x * wq) * (1.0 + 1.0e-6));
   return e;
+}
+
+// Everything per sample.  R is the arithmetic type of the bulk (FP64 or FP32);
+// the sky frame, delays and the final combination are always FP64.  The data
+// term comes from data_fn(row, sfr, Fre, Fim, cn, sn, cf, sf).
+template <class R, int KT, int L, bool BOUND, class DataFn>
+__device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, int ts, double ra,
+                                                 double dec, double psi, double incl, double phi,
+                                                 double tref, double dist, DataFn&& data_fn) {
+  constexpr int NY = Cls<L>::NY;
+  reduce_angles<R>(psi, incl, phi);
+  Sky<R, KT> S;
+  sky_eval<R, KT, true>(P, ra, dec, psi, tref, S);
+  R si, ci;
+  sincos_((R)incl, &si, &ci);
+  R cn[NY], sn[NY];
+  incl_harmonics<R, NY>(ci, si, cn, sn);
+  R sf, cf;
+  sincos_((R)phi, &sf, &cf);
+  __builtin_amdgcn_s_setprio(1);
+  const double data = data_fn(S.row, S.sfr, S.Fre, S.Fim, cn, sn, cf, sf);
+  __builtin_amdgcn_s_setprio(0);
+  double wq = 0.0;
+  const double quad = quad_term<R, KT, L, BOUND>(P, trig, ts, ci, si, cf, sf, S.Fre, S.Fim, &wq);
+  return combine<BOUND>(P, dist, data, quad, wq, S.bad);
 }
 
 // `stage` is this wavefront's STAGE_WAVE bytes of LDS; the whole wavefront
