@@ -260,13 +260,21 @@ typedef struct {
   const double *det_pos;    /* HOST [K][3] light-seconds */
   const double *det_arms;   /* HOST [K][2][3] arm unit vectors x, y (RIFT_RESP_ARMS), else unused */
   double gmst_rad;          /* sidereal angle at t = 0 (rad) */
-  double omega;             /* sidereal rate (rad/s), RIFT_RESP_ROTATION */
+  double omega;             /* sidereal rate (rad/s), RIFT_RESP_ROTATION; |omega| |det_pos[k]| <= 1
+                               for every detector (the turn over the light-travel time, at most
+                               one radian: 1e4 times the Earth's), else RIFT_EINVAL */
   double d_ref;
 } rift_ile_point_wide;
 
 /* lnL of n samples (theta DEVICE [7][n] as for rift_ile_lnL) in FP64; lnL:
- * DEVICE [n].  Same errors and non-finite semantics as rift_ile_lnL; returns
- * after the work is done. */
+ * DEVICE [n].  Same errors and non-finite semantics as rift_ile_lnL.  Both
+ * calls enqueue on `stream` and return: the host arrays of *pt are read
+ * before return; Q, U, V, theta and lnw must stay valid until the stream has
+ * run the work.  Per call the library takes stream-ordered scratch
+ * (hipMallocAsync / hipFreeAsync on `stream`) for U and V packed in the
+ * order of the contraction, 32 K n_terms (n_terms + 1) / 2 C^2 bytes with
+ * C = 5, 12 or 25 the mode capacity at or above M, and 16 bytes per 256
+ * samples for ln Z; RIFT_ENOMEM when that fails. */
 int rift_ile_wide_lnL(const rift_ile_point_wide *pt, int64_t n, const double *theta, double *lnL,
                       void *stream);
 /* ln Z and n_eff (DEVICE [1] each, neff may be NULL) of n >= 1 samples with

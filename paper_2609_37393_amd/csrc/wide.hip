@@ -22,10 +22,14 @@
 //
 // One lane evaluates one sample, in FP64.  Per detector the lane's C~ goes to
 // LDS; the mode harmonics Y stay in registers (modes sorted by m, the phase
-// walked upward).  The quadratic term runs over pairs a <= a' of composite
-// terms, G_aa' = Y^H U_aa' Y and H_aa' = Y^T V_aa' Y with U, V read through
-// the scalar path (uniform across the lanes), and uses the symmetries
-// G_a'a = conj(G_aa') (U Hermitian) and H_a'a = H_aa' (V symmetric).
+// walked upward; the kernel is compiled for mode capacities 5, 12 and 25 so
+// that short mode sets keep few registers).  The quadratic term runs over
+// pairs a <= a' of composite terms, G_aa' = Y^H U_aa' Y and H_aa' = Y^T V_aa' Y,
+// and uses the symmetries G_a'a = conj(G_aa') (U Hermitian) and H_a'a = H_aa'
+// (V symmetric).  A set-up kernel packs U and V per call into the order the
+// contraction walks, [k][pair][i][j] (Re U, Im U, Re V, Im V) with internal
+// mode indices and row stride equal to the capacity, so that the uniform
+// entries reach the lanes through the scalar path at constant offsets.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,12 +46,11 @@ namespace rift {
 namespace {
 
 constexpr int WIDE_MAX_TERMS = 8;  // composite terms per detector
-constexpr int WIDE_MAX_MODES = 25;
 constexpr int WIDE_BLOCK = 256;
 
 struct WideDesc {
-  int32_t K, M, n_t, n_a, response, pad;
-  double t0, inv_dt, gmst, omega, d_ref, lnN;
+  int32_t K, M, n_t, n_a, response, npairs;
+  double t0, inv_dt, gmst, omega, d_ref;
   double dten[KMAX][6];      // D00, D11, D22, 2 D01, 2 D02, 2 D12
   double rpos[KMAX][3];      // light-seconds
   double arms[KMAX][2][3];   // arm unit vectors
@@ -56,13 +59,12 @@ struct WideDesc {
   int32_t odd[MMAX];
   double ycoef[MMAX][LMAXC + 1];
   const double* Q;           // caller's [K][n_a][M][n_t] complex
-  const double* U;           // caller's [K][n_a M][n_a M] complex
-  const double* V;
+  const double* UV;          // packed [K][pair][MC][MC][4] (see the kernel)
 };
-typedef const RIFT_CONST WideDesc* WDesc;
+static_assert(sizeof(WideDesc) <= 3584, "the description travels as a kernel argument");
 
 // Complex response D : (e+ + i ex) of the six-value tensor d at axes X, Y.
-__device__ __forceinline__ C2<double> response6(const RIFT_CONST double* d, const double* X, const double* Y) {
+__device__ __forceinline__ C2<double> response6(const double* d, const double* X, const double* Y) {
   const double ep[6] = {X[0] * X[0] - Y[0] * Y[0], X[1] * X[1] - Y[1] * Y[1], X[2] * X[2] - Y[2] * Y[2],
                         X[0] * X[1] - Y[0] * Y[1], X[0] * X[2] - Y[0] * Y[2], X[1] * X[2] - Y[1] * Y[2]};
   const double ex[6] = {2 * X[0] * Y[0], 2 * X[1] * Y[1], 2 * X[2] * Y[2],
@@ -92,23 +94,56 @@ __device__ __forceinline__ void axes(double sg, double cg, double sd, double cd,
   N[2] = sd;
 }
 
-// G_ab = Y^H U_ab Y and H_ab = Y^T V_ab Y, accumulated into g[4] = (Re G,
-// Im G, Re H, Im H): the rows II of both blocks in turn (a template recursion,
-// so that every mode index is a compile-time constant and Y stays in
-// registers), each row's columns in an unrolled loop.
-template <int II>
+// Packs U and V of every detector into [k][pair][i][j][4] = (Re U, Im U,
+// Re V, Im V) of block (a, b), pair = the index of a <= b in row order, with
+// internal mode indices i, j < MC (entries past M are zero).
+template <int MC>
+__global__ void k_wide_pack(WideDesc D, const double* __restrict__ U, const double* __restrict__ V,
+                            double* __restrict__ out) {
+  const int64_t per_det = (int64_t)D.npairs * MC * MC;
+  const int64_t total = (int64_t)D.K * per_det;
+  const int A = D.n_a * D.M;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / per_det);
+    int r = (int)(e - (int64_t)k * per_det);
+    const int pr = r / (MC * MC);
+    r -= pr * MC * MC;
+    const int i = r / MC, j = r - (r / MC) * MC;
+    int a = 0, rem = pr;
+    while (rem >= D.n_a - a) {
+      rem -= D.n_a - a;
+      ++a;
+    }
+    const int b = a + rem;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < D.M && j < D.M) {
+      const int64_t o = 2 * (((int64_t)k * A + a * D.M + D.perm[i]) * A + b * D.M + D.perm[j]);
+      v[0] = U[o];
+      v[1] = U[o + 1];
+      v[2] = V[o];
+      v[3] = V[o + 1];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[4 * e + c] = v[c];
+  }
+}
+
+// G_ab = Y^H U_ab Y and H_ab = Y^T V_ab Y of one packed block, accumulated
+// into g[4] = (Re G, Im G, Re H, Im H): the rows II in turn (a template
+// recursion, so that every mode index and table offset is a compile-time
+// constant and Y stays in registers), each row's columns in an unrolled loop.
+template <int II, int MC>
 struct PairForms {
-  static __device__ __forceinline__ void run(WDesc P, const RIFT_CONST double* Uk, const RIFT_CONST double* Vk, int A,
-                                             int a, int b, int M, const double* yr, const double* yi, double* g) {
-    if constexpr (II < WIDE_MAX_MODES) {
+  static __device__ __forceinline__ void run(const RIFT_CONST double* blk, int M, const double* yr,
+                                             const double* yi, double* g) {
+    if constexpr (II < MC) {
       if (II < M) {
-        const int64_t row = (int64_t)(a * M + P->perm[II]) * A + b * M;
         double tr = 0.0, ti = 0.0, vr = 0.0, vi = 0.0;  // (U Y)_II, (V Y)_II
 #pragma unroll
-        for (int jj = 0; jj < WIDE_MAX_MODES; ++jj) {
+        for (int jj = 0; jj < MC; ++jj) {
           if (jj < M) {
-            const int64_t o = 2 * (row + P->perm[jj]);
-            const double ur = Uk[o], ui = Uk[o + 1], wr = Vk[o], wi = Vk[o + 1];
+            const RIFT_CONST double* e = blk + 4 * (II * MC + jj);
+            const double ur = e[0], ui = e[1], wr = e[2], wi = e[3];
             tr += ur * yr[jj] - ui * yi[jj];
             ti += ur * yi[jj] + ui * yr[jj];
             vr += wr * yr[jj] - wi * yi[jj];
@@ -120,19 +155,55 @@ struct PairForms {
         g[1] += yr[II] * ti - yi[II] * tr;
         g[2] += yr[II] * vr - yi[II] * vi;
         g[3] += yr[II] * vi + yi[II] * vr;
-        PairForms<II + 1>::run(P, Uk, Vk, A, a, b, M, yr, yi, g);
+        PairForms<II + 1, MC>::run(blk, M, yr, yi, g);
       }
     }
   }
 };
 
-__global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict__ desc,
-                                                     const double* __restrict__ theta, int64_t n,
+// cos(2 pi j / 5), sin(2 pi j / 5), j = 0..4: the five hour angles of the
+// rotation harmonics and the factors of their transform (e^{-2 pi i n j / 5}
+// is entry (n j) mod 5, conjugated).
+__constant__ double kC5[5] = {1.0, 0.30901699437494745, -0.80901699437494745, -0.80901699437494745,
+                              0.30901699437494745};
+__constant__ double kS5[5] = {0.0, 0.95105651629515353, 0.58778525229247314, -0.58778525229247314,
+                              -0.95105651629515353};
+
+// sin and cos of |x| <= 1 by their Taylor series through x^19 / 19! and
+// x^18 / 18! (truncation below 1e-17): the rotation over the light-travel
+// time, Omega (t_k - t_ref), which the validation keeps within one radian.
+__device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
+  const double x2 = x * x;
+  double ps = -1.0 / 121645100408832000.0;  // -1/19!
+  ps = fma(ps, x2, 1.0 / 355687428096000.0);
+  ps = fma(ps, x2, -1.0 / 1307674368000.0);
+  ps = fma(ps, x2, 1.0 / 6227020800.0);
+  ps = fma(ps, x2, -1.0 / 39916800.0);
+  ps = fma(ps, x2, 1.0 / 362880.0);
+  ps = fma(ps, x2, -1.0 / 5040.0);
+  ps = fma(ps, x2, 1.0 / 120.0);
+  ps = fma(ps, x2, -1.0 / 6.0);
+  *s = fma(ps * x2, x, x);
+  double pc = 1.0 / 6402373705728000.0;  // 1/18!
+  pc = fma(pc, x2, -1.0 / 20922789888000.0);
+  pc = fma(pc, x2, 1.0 / 87178291200.0);
+  pc = fma(pc, x2, -1.0 / 479001600.0);
+  pc = fma(pc, x2, 1.0 / 3628800.0);
+  pc = fma(pc, x2, -1.0 / 40320.0);
+  pc = fma(pc, x2, 1.0 / 720.0);
+  pc = fma(pc, x2, -1.0 / 24.0);
+  pc = fma(pc, x2, 0.5);
+  *c = fma(-pc, x2, 1.0);
+}
+
+// Occupancy: three wavefronts per SIMD (<= 168 VGPRs) for up to 5 modes, two
+// otherwise (the 25-mode capacity's Y alone holds 100 VGPRs).
+template <int MC>
+__global__ void __launch_bounds__(WIDE_BLOCK, MC <= 5 ? 3 : 2) k_wide(WideDesc D, const double* __restrict__ theta, int64_t n,
                                                      const double* __restrict__ lnw, double* __restrict__ lnL,
                                                      double* __restrict__ part) {
   __shared__ double cre[WIDE_MAX_TERMS][WIDE_BLOCK], cim[WIDE_MAX_TERMS][WIDE_BLOCK];
   __shared__ MS sh[WIDE_BLOCK / 64];
-  WDesc P = opaque(desc);
   const int t = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * WIDE_BLOCK + t;
   const bool live = i0 < n;
@@ -140,11 +211,11 @@ __global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict_
   const RIFT_GLOBAL double* th = as_global(theta) + i;
   const double ra = th[0], dec = th[n], psi = th[2 * n], incl = th[3 * n], phi = th[4 * n];
   const double tref = th[5 * n], dist = th[6 * n];
-  const int K = P->K, M = P->M, n_t = P->n_t, n_a = P->n_a;
-  const bool rot = P->response == RIFT_RESP_ROTATION;
+  const int K = D.K, M = D.M, n_t = D.n_t, n_a = D.n_a;
+  const bool rot = D.response == RIFT_RESP_ROTATION;
 
   // sky frame at t_ref (the rotation response advances the sidereal angle)
-  const double gm = rot ? P->gmst + P->omega * tref : P->gmst;
+  const double gm = rot ? D.gmst + D.omega * tref : D.gmst;
   const double gref = gm - ra;
   double sg, cg, sd, cd, sp, cp;
   sincos(gref, &sg, &cg);
@@ -173,30 +244,30 @@ __global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict_
       }
     }
   }
-  double yr[WIDE_MAX_MODES], yi[WIDE_MAX_MODES];
+  double yr[MC], yi[MC];
   {
     C2<double> ph;
     ph.x = 1.0;
     ph.y = 0.0;
-    const int mmin = P->m[0];
+    const int mmin = D.m[0];
     for (int q = 0; q < -mmin; ++q) phase_down(ph, cf, sf);
     int mc = mmin < 0 ? mmin : 0;
 #pragma unroll
-    for (int j = 0; j < WIDE_MAX_MODES; ++j) {
+    for (int j = 0; j < MC; ++j) {
       yr[j] = yi[j] = 0.0;
       if (j < M) {
-        const int mj = P->m[j];
+        const int mj = D.m[j];
         while (mc < mj) {
           phase_up(ph, cf, sf);
           ++mc;
         }
         double d = 0.0;
-        if (P->odd[j]) {
+        if (D.odd[j]) {
 #pragma unroll
-          for (int q = 1; q <= LMAXC; ++q) d += P->ycoef[j][q] * sn[q];
+          for (int q = 1; q <= LMAXC; ++q) d += D.ycoef[j][q] * sn[q];
         } else {
 #pragma unroll
-          for (int q = 0; q <= LMAXC; ++q) d += P->ycoef[j][q] * cn[q];
+          for (int q = 0; q <= LMAXC; ++q) d += D.ycoef[j][q] * cn[q];
         }
         yr[j] = d * ph.x;
         yi[j] = d * ph.y;
@@ -206,46 +277,51 @@ __global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict_
 
   double data = 0.0, quad = 0.0;
   bool bad = false;
-  const int A = n_a * M;
   for (int k = 0; k < K; ++k) {
-    const RIFT_CONST double* r = P->rpos[k];
-    const double tk = tref - (r[0] * N[0] + r[1] * N[1] + r[2] * N[2]);
+    const double tk = tref - (D.rpos[k][0] * N[0] + D.rpos[k][1] * N[1] + D.rpos[k][2] * N[2]);
     // composite coefficients of this detector -> this lane's LDS column
     if (rot) {
       // F_k at the five hour angles g_j = 2 pi j / 5, then A_n by the exact
       // five-point transform, then the phases e^{i n theta_k}
+      // (the frames at the five hour angles do not depend on k; they are
+      // rebuilt per detector rather than kept live across the loop, which
+      // would hold 120 registers)
+      double sdk = sd, cdk = cd, spk = sp, cpk = cp;
+      asm volatile("" : "+v"(sdk), "+v"(cdk), "+v"(spk), "+v"(cpk));
       C2<double> Fg[5];
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
-        double sgj, cgj;
-        sincospi(0.4 * j, &sgj, &cgj);
         double Xj[3], Yj[3], Nj[3];
-        axes(sgj, cgj, sd, cd, sp, cp, Xj, Yj, Nj);
-        Fg[j] = response6(P->dten[k], Xj, Yj);
+        axes(kS5[j], kC5[j], sdk, cdk, spk, cpk, Xj, Yj, Nj);
+        Fg[j] = response6(D.dten[k], Xj, Yj);
       }
-      const double thk = gref + P->omega * (tk - tref);
+      // e^{i theta_k} = e^{i g(t_ref)} e^{i Omega (t_k - t_ref)}
+      double sdl, cdl;
+      sincos_small(D.omega * (tk - tref), &sdl, &cdl);
+      const double e1c = cg * cdl - sg * sdl, e1s = sg * cdl + cg * sdl;
+      const double e2c = e1c * e1c - e1s * e1s, e2s = 2.0 * e1c * e1s;
 #pragma unroll
       for (int a = 0; a < 5; ++a) {
         const int nn = a - 2;
         double ar = 0.0, ai = 0.0;
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-          double s, c;
-          sincospi(-0.4 * nn * j, &s, &c);  // e^{-i n g_j}
+          const int r = ((nn * j) % 5 + 5) % 5;
+          const double c = kC5[r], s = -kS5[r];  // e^{-i n g_j}
           ar += Fg[j].x * c - Fg[j].y * s;
           ai += Fg[j].x * s + Fg[j].y * c;
         }
         ar *= 0.2;
         ai *= 0.2;
         // e^{i n theta_k}
-        double er, ei;
-        sincos((double)nn * thk, &ei, &er);
+        const double er = (nn == 0) ? 1.0 : (nn == 1 || nn == -1) ? e1c : e2c;
+        const double ei = (nn == 0) ? 0.0 : (nn == 1) ? e1s : (nn == -1) ? -e1s : (nn == 2) ? e2s : -e2s;
         cre[a][t] = ar * er - ai * ei;
         cim[a][t] = ar * ei + ai * er;
       }
     } else {
-      const RIFT_CONST double* ax = P->arms[k][0];
-      const RIFT_CONST double* ay = P->arms[k][1];
+      const double* ax = D.arms[k][0];
+      const double* ay = D.arms[k][1];
       const double xX = X[0] * ax[0] + X[1] * ax[1] + X[2] * ax[2];
       const double xY = Y3[0] * ax[0] + Y3[1] * ax[1] + Y3[2] * ax[2];
       const double yX = X[0] * ay[0] + X[1] * ay[1] + X[2] * ay[2];
@@ -263,7 +339,7 @@ __global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict_
       }
     }
     // four-point Lagrange stencil at t_k (taps outside the window read zero)
-    double u = (tk - P->t0) * P->inv_dt;
+    double u = (tk - D.t0) * D.inv_dt;
     if (!(fabs(u) <= 1.0e300)) {
       bad = true;
       u = 0.0;
@@ -274,22 +350,34 @@ __global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict_
     const int j0 = (int)jf - 1;
     double w[4];
     lagrange4(s, w);
+#pragma unroll
+    for (int tap = 0; tap < 4; ++tap)
+      if (j0 + tap < 0 || j0 + tap >= n_t) w[tap] = 0.0;
+    // the four rows read are jc .. jc+3, inside the window; row jc + r carries
+    // tap r + jc - j0 (weight 0 when that is not a tap or lies outside)
+    const int jc = j0 < 0 ? 0 : (j0 > n_t - 4 ? n_t - 4 : j0);
+    double wr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int tp = r + jc - j0;
+      double v = 0.0;
+#pragma unroll
+      for (int tap = 0; tap < 4; ++tap) v = (tp == tap) ? w[tap] : v;
+      wr[r] = v;
+    }
     // data term: Re sum_a conj(C~_a) sum_i conj(Y_i) Qhat_{a,i}
     for (int a = 0; a < n_a; ++a) {
       double zr = 0.0, zi = 0.0;
 #pragma unroll
-      for (int j = 0; j < WIDE_MAX_MODES; ++j) {
+      for (int j = 0; j < MC; ++j) {
         if (j < M) {
           const RIFT_GLOBAL double* q =
-              as_global(P->Q) + 2 * ((((int64_t)k * n_a + a) * M + P->perm[j]) * (int64_t)n_t);
+              as_global(D.Q) + 2 * ((((int64_t)k * n_a + a) * M + D.perm[j]) * (int64_t)n_t + jc);
           double qr = 0.0, qi = 0.0;
 #pragma unroll
-          for (int tap = 0; tap < 4; ++tap) {
-            const int node = j0 + tap;
-            if (node >= 0 && node < n_t) {
-              qr += w[tap] * q[2 * node];
-              qi += w[tap] * q[2 * node + 1];
-            }
+          for (int r = 0; r < 4; ++r) {
+            qr += wr[r] * q[2 * r];
+            qi += wr[r] * q[2 * r + 1];
           }
           // conj(Y) Qhat
           zr += yr[j] * qr + yi[j] * qi;
@@ -300,12 +388,11 @@ __global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict_
       data += cre[a][t] * zr + cim[a][t] * zi;
     }
     // model-norm term over pairs a <= a'
-    const RIFT_CONST double* Uk = as_const(P->U) + 2 * (int64_t)k * A * A;
-    const RIFT_CONST double* Vk = as_const(P->V) + 2 * (int64_t)k * A * A;
+    const RIFT_CONST double* blk = as_const(D.UV) + (int64_t)k * D.npairs * (MC * MC * 4);
     for (int a = 0; a < n_a; ++a) {
-      for (int b = a; b < n_a; ++b) {
+      for (int b = a; b < n_a; ++b, blk += MC * MC * 4) {
         double g[4] = {0.0, 0.0, 0.0, 0.0};  // Re G, Im G, Re H, Im H
-        PairForms<0>::run(P, Uk, Vk, A, a, b, M, yr, yi, g);
+        PairForms<0, MC>::run(opaque(blk), M, yr, yi, g);
         const double gr = g[0], gi = g[1], hr = g[2], hi = g[3];
         const double car = cre[a][t], cai = cim[a][t], cbr = cre[b][t], cbi = cim[b][t];
         // conj(C_a) C_b G_ab and C_a C_b H_ab, counted twice off the diagonal
@@ -316,7 +403,7 @@ __global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict_
       }
     }
   }
-  const double x = P->d_ref / dist;
+  const double x = D.d_ref / dist;
   double l = x * data - 0.25 * x * x * quad;
   if (bad) l = __builtin_nan("");
   if (live && lnL) as_global_w(lnL)[i] = l;
@@ -334,8 +421,8 @@ __global__ void __launch_bounds__(WIDE_BLOCK) k_wide(const WideDesc* __restrict_
 }
 
 // ln Z and n_eff from the blocks' (max, sum) pairs, one block, fixed order.
-__global__ void k_wide_merge(const WideDesc* __restrict__ P, const double* __restrict__ part, int nb,
-                             double* __restrict__ lnZ, double* __restrict__ neff) {
+__global__ void k_wide_merge(double lnN, const double* __restrict__ part, int nb, double* __restrict__ lnZ,
+                             double* __restrict__ neff) {
   __shared__ MS sh[WIDE_BLOCK / 64];
   MS acc;
   acc.m = -__builtin_inf();
@@ -352,7 +439,7 @@ __global__ void k_wide_merge(const WideDesc* __restrict__ P, const double* __res
     double z;
     if (r.s != r.s) z = __builtin_nan("");
     else if (r.m == -__builtin_inf()) z = -__builtin_inf();
-    else z = r.m + log(r.s) - P->lnN;
+    else z = r.m + log(r.s) - lnN;
     lnZ[0] = z;
     if (neff) neff[0] = (r.m == -__builtin_inf() && r.s == r.s) ? 0.0 : r.s;
   }
@@ -387,6 +474,13 @@ int validate_wide(const rift_ile_point_wide* pt) {
     if (!std::isfinite(pt->det_tensor[a])) return RIFT_EINVAL;
   for (int a = 0; a < 3 * pt->n_det; ++a)
     if (!std::isfinite(pt->det_pos[a])) return RIFT_EINVAL;
+  // rotation: the turn over the light-travel time, Omega |r_k|, stays within
+  // one radian (the post-phase is evaluated by a series on that range)
+  if (pt->response == RIFT_RESP_ROTATION)
+    for (int k = 0; k < pt->n_det; ++k) {
+      const double* r = pt->det_pos + 3 * k;
+      if (!(fabs(pt->omega) * sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) <= 1.0)) return RIFT_EINVAL;
+    }
   return RIFT_OK;
 }
 
@@ -410,13 +504,13 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
   D.M = pt->n_modes;
   D.n_t = pt->n_t;
   D.n_a = pt->n_terms;
+  D.npairs = pt->n_terms * (pt->n_terms + 1) / 2;
   D.response = pt->response;
   D.t0 = pt->t0;
   D.inv_dt = 1.0 / pt->dt;
   D.gmst = pt->gmst_rad;
   D.omega = pt->response == RIFT_RESP_ROTATION ? pt->omega : 0.0;
   D.d_ref = pt->d_ref;
-  D.lnN = log((double)n);
   for (int k = 0; k < pt->n_det; ++k) {
     const double* d = pt->det_tensor + 9 * k;
     const double six[6] = {d[0], d[4], d[8], d[1] + d[3], d[2] + d[6], d[5] + d[7]};
@@ -437,30 +531,36 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
     ylm_fourier(l, m, D.ycoef[i]);
   }
   D.Q = pt->Q;
-  D.U = pt->U;
-  D.V = pt->V;
+  const int MC = pt->n_modes <= 5 ? 5 : (pt->n_modes <= 12 ? 12 : 25);
+  // stream-ordered scratch: the packed U/V blocks, then the blocks' (max, sum) pairs
+  const size_t uv_bytes = sizeof(double) * 4 * (size_t)D.K * D.npairs * MC * MC;
+  const size_t part_bytes = lnZ ? sizeof(double) * 2 * (size_t)nb : 0;
   hipStream_t st = (hipStream_t)stream;
-  WideDesc* d_desc = nullptr;
-  double* d_part = nullptr;
-  if (hipMalloc(&d_desc, sizeof(WideDesc)) != hipSuccess) return RIFT_ENOMEM;
-  if (lnZ && hipMalloc(&d_part, sizeof(double) * 2 * nb) != hipSuccess) {
-    (void)hipFree(d_desc);
-    return RIFT_ENOMEM;
+  void* scratch = nullptr;
+  if (hipMallocAsync(&scratch, uv_bytes + part_bytes, st) != hipSuccess) return RIFT_ENOMEM;
+  D.UV = (const double*)scratch;
+  double* d_part = lnZ ? (double*)((char*)scratch + uv_bytes) : nullptr;
+  const int64_t pe = (int64_t)D.K * D.npairs * MC * MC;
+  const unsigned pgrid = (unsigned)std::min<int64_t>((pe + 255) / 256, 1024);
+  switch (MC) {
+    case 5:
+      hipLaunchKernelGGL(k_wide_pack<5>, dim3(pgrid), dim3(256), 0, st, D, pt->U, pt->V, (double*)scratch);
+      hipLaunchKernelGGL(k_wide<5>, dim3((unsigned)nb), dim3(WIDE_BLOCK), 0, st, D, theta, n, lnw, lnL, d_part);
+      break;
+    case 12:
+      hipLaunchKernelGGL(k_wide_pack<12>, dim3(pgrid), dim3(256), 0, st, D, pt->U, pt->V, (double*)scratch);
+      hipLaunchKernelGGL(k_wide<12>, dim3((unsigned)nb), dim3(WIDE_BLOCK), 0, st, D, theta, n, lnw, lnL, d_part);
+      break;
+    default:
+      hipLaunchKernelGGL(k_wide_pack<25>, dim3(pgrid), dim3(256), 0, st, D, pt->U, pt->V, (double*)scratch);
+      hipLaunchKernelGGL(k_wide<25>, dim3((unsigned)nb), dim3(WIDE_BLOCK), 0, st, D, theta, n, lnw, lnL, d_part);
   }
-  rc = RIFT_OK;
-  if (hipMemcpyAsync(d_desc, &D, sizeof(WideDesc), hipMemcpyHostToDevice, st) != hipSuccess) rc = RIFT_EDEVICE;
-  if (!rc) {
-    hipLaunchKernelGGL(k_wide, dim3((unsigned)nb), dim3(WIDE_BLOCK), 0, st, (const WideDesc*)d_desc, theta, n, lnw,
-                       lnL, d_part);
-    if (lnZ)
-      hipLaunchKernelGGL(k_wide_merge, dim3(1), dim3(WIDE_BLOCK), 0, st, (const WideDesc*)d_desc,
-                         (const double*)d_part, (int)nb, lnZ, neff);
-    if (hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
-  }
-  // the host copy of the description and the device buffers live until the work is done
-  if (hipStreamSynchronize(st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
-  (void)hipFree(d_desc);
-  if (d_part) (void)hipFree(d_part);
+  if (lnZ)
+    hipLaunchKernelGGL(k_wide_merge, dim3(1), dim3(WIDE_BLOCK), 0, st, log((double)n), (const double*)d_part, (int)nb,
+                       lnZ, neff);
+  rc = hipGetLastError() == hipSuccess ? RIFT_OK : RIFT_EDEVICE;
+  // released in stream order, after the kernels above
+  if (hipFreeAsync(scratch, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
   return rc;
 }
 

@@ -199,3 +199,18 @@ def test_leapfrog_drift_arguments(lib):
     bad = step.copy()
     bad[3] = np.inf
     assert lib.rift_ile_leapfrog_drift(10, 0x4000, 0x5000, bad.ctypes.data, None) == EINVAL
+
+
+def test_wide_rotation_rate_limit(lib):
+    """Under rotation the turn over the light-travel time, |omega| |r_k|, must
+    stay within one radian."""
+    from paper_2609_37393_amd import ile
+
+    R = np.array([[0.02, 0.0, 0.0], [0.0, -0.01, 0.0]])
+    ok, keep = _point_wide(ile, det_pos=R.ctypes.data, omega=40.0)
+    assert lib.rift_ile_wide_lnL(ctypes.byref(ok), 0, None, None, None) == 0
+    bad, keep2 = _point_wide(ile, det_pos=R.ctypes.data, omega=60.0)
+    assert lib.rift_ile_wide_lnL(ctypes.byref(bad), 0, None, None, None) == EINVAL
+    # the arms response has no rotation
+    arms, keep3 = _point_wide(ile, det_pos=R.ctypes.data, omega=60.0, response=2, n_terms=3)
+    assert lib.rift_ile_wide_lnL(ctypes.byref(arms), 0, None, None, None) == 0
