@@ -7,7 +7,9 @@ the two share no code.
 
 The arithmetic lives in ``oracle.cpp`` (plain loops, IEEE double, OpenMP over
 samples); this module only marshals numpy arrays into it.  ``pregrid`` (the
-Fourier refinement of Eq. (q-time-pregrid)) is written here in numpy.
+Fourier refinement of Eq. (q-time-pregrid)) and ``lnL_dmarg`` (the adaptive
+Gauss-Hermite marginal over distance, Eq. (ap:dgh)) are written here in
+numpy.
 
 Every function states the passage of the paper it follows.  Parity status of
 each function (what pins it) is listed in the tests' docstrings.
@@ -64,6 +66,7 @@ def _load():
         lib.oracle_rotation_harmonics.argtypes = [p, d, d, p]
         lib.oracle_wide_coef.argtypes = [p, p, p, p]
         lib.oracle_lnL_wide.argtypes = [p, ctypes.c_int64, p, p, ctypes.c_int]
+        lib.oracle_lnL_terms.argtypes = [p, ctypes.c_int64, p, p, p, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -242,6 +245,67 @@ def lnZ(lnL_values, lnw=None):
     ne = np.zeros(1)
     _load().oracle_lnZ(l.shape[0], _ptr(l), None if w is None else _ptr(w), _ptr(z), _ptr(ne))
     return float(z[0]), float(ne[0])
+
+
+def lnL_terms(pt, theta, nthreads: int = 0):
+    """(K [n], R [n]) with lnL_i(x) = K_i x - R_i x^2 / 2 exactly, x = D_ref / D
+    (Eq. (ap:dexp)): K is the data term and R the model norm at the reference
+    distance.  The distance row of theta is not read."""
+    th = _c(theta, np.float64)
+    n = th.shape[1]
+    Kv = np.empty(n)
+    Rv = np.empty(n)
+    pk = _pack(pt)
+    _load().oracle_lnL_terms(ctypes.byref(pk.cp), n, _ptr(th), _ptr(Kv), _ptr(Rv), int(nthreads))
+    return Kv, Rv
+
+
+def dist_prior_x(x, d_ref, d_min, d_max, power=2.0):
+    """Density in x = d_ref / D of the prior p(D) proportional to D^power on
+    [d_min, d_max] (power 2: uniform in Euclidean volume, p_x proportional to
+    x^-4), normalised to one, zero outside."""
+    x = np.asarray(x, np.float64)
+    # int_{d_min}^{d_max} D^power dD
+    if power == -1.0:
+        norm = np.log(d_max / d_min)
+    else:
+        norm = (d_max ** (power + 1) - d_min ** (power + 1)) / (power + 1)
+    D = d_ref / np.where(x > 0, x, 1.0)
+    inside = (x >= d_ref / d_max) & (x <= d_ref / d_min)
+    # p_x(x) = p(D(x)) |dD/dx| = p(D) d_ref / x^2
+    return np.where(inside, D ** power / norm * d_ref / np.where(x > 0, x, 1.0) ** 2, 0.0)
+
+
+def lnL_dmarg(pt, theta, d_min, d_max, n_nodes, power=2.0, nthreads: int = 0):
+    """ln of the likelihood marginalised over distance, per sample, by the
+    adaptive Gauss-Hermite rule of Eq. (ap:dgh): with lnL(x) = K x - R x^2 / 2,
+    the peak x* = K / R and width sigma_x = R^-1/2 of Eq. (ap:dpeak) centre and
+    scale the n_nodes nodes xi_i (weight exp(-xi^2/2)), and
+        int dx p_x(x) e^{lnL(x)} ~ sum_i w~_i p_x(x* + xi_i sigma_x) e^{lnL(x* + xi_i sigma_x)}
+    with w~_i = sigma_x W_i e^{xi_i^2 / 2} (the Gaussian factor of the rule
+    divided out, since e^{lnL(x* + xi sigma)} = e^{K^2 / 2R} e^{-xi^2 / 2}).
+    The prior is p(D) proportional to D^power on [d_min, d_max].  A sample
+    with R <= 0 (no model power) has no peak to centre on: NaN."""
+    Kv, Rv = lnL_terms(pt, theta, nthreads)
+    xi, W = np.polynomial.hermite_e.hermegauss(int(n_nodes))
+    out = np.empty(Kv.shape[0])
+    d_ref = float(pt["d_ref"])
+    for i in range(Kv.shape[0]):
+        Ki, Ri = Kv[i], Rv[i]
+        if not (Ri > 0.0) or not np.isfinite(Ki):
+            out[i] = np.nan
+            continue
+        xs = Ki / Ri
+        sig = 1.0 / np.sqrt(Ri)
+        x = xs + xi * sig
+        lnl = Ki * x - 0.5 * Ri * x * x
+        wt = sig * W * np.exp(xi * xi / 2.0)
+        terms = wt * dist_prior_x(x, d_ref, d_min, d_max, power)
+        # sum_i terms_i e^{lnl_i}, in log form about the peak value K^2 / 2R
+        peak = 0.5 * Ki * Ki / Ri
+        s = np.sum(terms * np.exp(lnl - peak))
+        out[i] = peak + np.log(s) if s > 0 else -np.inf
+    return out
 
 
 def rotation_harmonics(det_tensor, dec, psi):

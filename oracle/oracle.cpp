@@ -18,6 +18,9 @@
 //   * composite-index likelihood (Earth rotation, Path A; finite arms, Path D):
 //     Sec. "A generalized detector response", Eqs. (slowrot:Fharm),
 //     (slowrot:postphase), (slowrot:lnL:Decomposed), (fsize:bp)
+//   * the distance-free terms K, R of lnL(x) = K x - R x^2 / 2:  Eq. (ap:dexp)
+//     (the adaptive Gauss-Hermite marginal over distance built on them,
+//     Eqs. (ap:dpeak), (ap:dgh), is in the Python layer of the oracle)
 //
 // Readings where the paper is silent or inconsistent (all listed in the
 // design notes of the repository):
@@ -222,9 +225,13 @@ Cx<T> interp_lagrange4(const double* q, int n_t, double t0, double dt, const T& 
 
 // Factored log-likelihood, Eq. (def:lnL:Decomposed), given F_k, Y_lm, x = D_ref/D
 // and the Q values already read at t_k.
+// The two terms of Eq. (def:lnL:Decomposed) at the reference distance:
+// data = Re sum_k sum_lm conj(F_k Y_lm) Qhat_{k,lm} and
+// quad = sum_k [|F_k|^2 Y^H U_k Y + Re(F_k^2 Y^T V_k Y)], so that
+// lnL(x) = x data - x^2 quad / 4 with x = D_ref / D.
 template <class T>
-T lnL_factored(int K, int M, const Cx<T>* F, const Cx<T>* Y, const T& x,
-               const Cx<T>* Qhat, const double* U, const double* V) {
+void terms_factored(int K, int M, const Cx<T>* F, const Cx<T>* Y, const Cx<T>* Qhat, const double* U,
+                    const double* V, T* data_out, T* quad_out) {
   T data(0.0), quad(0.0);
   for (int k = 0; k < K; ++k) {
     for (int i = 0; i < M; ++i) {
@@ -247,7 +254,35 @@ T lnL_factored(int K, int M, const Cx<T>* F, const Cx<T>* Y, const T& x,
     Cx<T> f2 = cmul(F[k], F[k]);
     quad = quad + f2abs * a.re + (f2.re * b.re - f2.im * b.im);
   }
+  *data_out = data;
+  *quad_out = quad;
+}
+
+template <class T>
+T lnL_factored(int K, int M, const Cx<T>* F, const Cx<T>* Y, const T& x,
+               const Cx<T>* Qhat, const double* U, const double* V) {
+  T data, quad;
+  terms_factored(K, M, F, Y, Qhat, U, V, &data, &quad);
   return x * data - x * x * quad * 0.25;
+}
+
+// The per-sample terms (data, quad) of the likelihood, at the reference
+// distance, from the extrinsic parameters other than the distance.
+void terms_one(const Point& p, double ra, double dec, double psi, double iota, double phi, double tref,
+               double* data, double* quad) {
+  double N[3], X[3], Y3[3];
+  sky_frame(ra, dec, psi, p.gmst, N, X, Y3);
+  std::vector<Cx<double>> F(p.K), Y(p.M), Qhat((size_t)p.K * p.M);
+  for (int k = 0; k < p.K; ++k) {
+    F[k] = antenna(p.det_tensor + 9 * k, X, Y3);
+    const double* r = p.det_pos + 3 * k;
+    double tk = tref - (r[0] * N[0] + r[1] * N[1] + r[2] * N[2]);
+    for (int i = 0; i < p.M; ++i)
+      Qhat[(size_t)k * p.M + i] =
+          interp_lagrange4(p.Q + 2 * ((size_t)(k * p.M + i) * p.n_t), p.n_t, p.t0, p.dt, tk);
+  }
+  for (int i = 0; i < p.M; ++i) Y[i] = ylm_m2(p.lm[2 * i], p.lm[2 * i + 1], iota, phi);
+  terms_factored(p.K, p.M, F.data(), Y.data(), Qhat.data(), p.U, p.V, data, quad);
 }
 
 // Full per-sample likelihood from the extrinsic parameters.
@@ -497,6 +532,21 @@ void oracle_lnL(const Point* p, int64_t n, const double* theta, double* lnL, int
   for (int64_t i = 0; i < n; ++i) {
     lnL[i] = lnL_one<double>(*p, theta[i], theta[n + i], theta[2 * n + i], theta[3 * n + i],
                              theta[4 * n + i], theta[5 * n + i], theta[6 * n + i]);
+  }
+}
+
+// The distance-free terms of n samples: K_i = data_i and R_i = quad_i / 2, so
+// that lnL_i(x) = K_i x - R_i x^2 / 2 exactly (Eq. (ap:dexp)); the distance
+// row of theta is not read.
+void oracle_lnL_terms(const Point* p, int64_t n, const double* theta, double* Kout, double* Rout, int nthreads) {
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double data, quad;
+    terms_one(*p, theta[i], theta[n + i], theta[2 * n + i], theta[3 * n + i], theta[4 * n + i], theta[5 * n + i],
+              &data, &quad);
+    Kout[i] = data;
+    Rout[i] = 0.5 * quad;
   }
 }
 
