@@ -589,14 +589,56 @@ def extra_wide(ile, synth, torch, steps, cpu=True):
     return res
 
 
+def extra_dmarg(ile, synth, torch, steps, cpu=True):
+    """The headline point (3 detectors, 21 modes, SNR 600, 1e6 prior
+    samples) with the likelihood marginalised over distance in the kernel:
+    prior p(D) ~ D^2 on [10, 1000] Mpc, a 20-node adaptive Gauss-Hermite rule
+    per sample (Eq. (ap:dgh)), then ln Z_d; against the FP64 oracle's ln Z_d
+    over the same samples."""
+    pt, th = c2_inputs(synth, 1_000_000)
+    n = th.shape[1]
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    plan = ile.Plan([pt], [n])
+    plan.tune(tht)
+    z = torch.empty(1, dtype=torch.float64, device="cuda")
+    ne = torch.empty(1, dtype=torch.float64, device="cuda")
+    ll = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.lnZ_dmarg(tht, 10.0, 1000.0, 20, lnZ_out=z, neff_out=ne, lnL_out=ll)
+
+    warm_up(step, 3, torch, WARM_S)
+    secs, _ = time_steps(step, steps, 0, torch)
+    plan.profile(True)
+    step()
+    kms, nl = plan.profile_read()
+    plan.profile(False)
+    fps = survey_flops_per_sample(3, 21) + 20 * 8
+    res = {"workload": "3 detectors, 21 modes (l<=4), Q 6554 samples at 32768 Hz, SNR 600, 1e6 prior samples; "
+                       "lnL marginalised over distance (p(D) ~ D^2 on [10, 1000] Mpc, 20 Gauss-Hermite nodes)",
+           "lnLd_evals_per_s": n * steps / secs, "ms_per_step": 1e3 * secs / steps, "kernel_ms": kms / max(1, nl),
+           "flops_per_sample": fps, "alu_frac": fps * n / (kms / max(1, nl) / 1e3) / (PEAK_FP64_TFLOPS * 1e12),
+           "lnZd": z.item(), "neff": ne.item(), "launch": plan.config}
+    plan.close()
+    if cpu:
+        import oracle
+
+        t0 = time.perf_counter()
+        want = oracle.lnL_dmarg(pt, th, 10.0, 1000.0, 20)
+        res["cpu_oracle_lnLd_evals_per_s"] = n / (time.perf_counter() - t0)
+        z_or, _ = oracle.lnZ(want)
+        res["dlnZd_vs_oracle"] = abs(res["lnZd"] - z_or)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5,wide",
-                    help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, c3, c1big; "
+    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg",
+                    help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
                     help="add the longer workloads (the 512-point batch c3, C1 at 1e7 samples c1big, "
@@ -718,7 +760,7 @@ def main():
     wanted = [x.strip() for x in args.workloads.split(",") if x.strip() and x.strip() != "none"]
     wanted += [x.strip() for x in args.extras.split(",") if x.strip()]
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
-           "c5batch": extra_c5_batch, "wide": extra_wide}
+           "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg}
     for name in wanted:
         log(f"workload {name}")
         try:

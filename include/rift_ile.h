@@ -284,6 +284,41 @@ int rift_ile_wide_lnZ(const rift_ile_point_wide *pt, int64_t n, const double *th
                       double *lnZ, double *neff, double *lnL, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Direct marginalisation over distance (Sec. "Distance: locating a moving
+ * peak"): lnL is exactly K x - R x^2 / 2 in x = d_ref / D (Eq. (ap:dexp)), so
+ * the likelihood marginalised over the distance prior,
+ *   L_d = int dD p(D) e^{lnL(D)},
+ * is taken per sample by an adaptive Gauss-Hermite rule centred on the peak
+ * x* = K / R and scaled by sigma_x = R^{-1/2} (Eqs. (ap:dpeak), (ap:dgh)):
+ *   ln L_d = K^2 / 2R + ln sigma_x + ln sum_i W_i p_x(x* + xi_i sigma_x),
+ * with (xi_i, W_i) the n_nodes-point rule of the weight e^{-xi^2/2} and
+ * p_x the prior p(D) = 3 D^2 / (d_max^3 - d_min^3) on [d_min, d_max] (uniform
+ * in Euclidean volume) written in x.  No node inside the prior gives -inf
+ * (the rule's answer for a peak far outside it); R <= 0, which only rounding
+ * produces where the model has no power (and K = 0 with it), gives 0 (lnL = 0
+ * at every distance); non-finite samples give NaN.  The rule resolves the
+ * integral where sigma_x is small against the prior's extent in x; a sample
+ * with almost no model power (sigma_x far wider than the prior) may get -inf. */
+typedef struct {
+  double d_min, d_max; /* prior support (Mpc, the unit of d_ref): 0 < d_min < d_max <= 1e60 */
+  int32_t n_nodes;     /* Gauss-Hermite nodes, 1 .. 64 */
+} rift_ile_dist_prior;
+
+/* ln L_d per sample (lnLd: DEVICE [N] or NULL) and, per point, ln Z_d =
+ * ln[(1/n) sum_i e^{ln L_d,i + lnw_i}] with n_eff (Eqs. (lnL:MonteCarlo),
+ * (neff)) over the plan's batch.  theta as for rift_ile_plan_lnZ; its distance
+ * row is not read.  FP64 whatever the plan's precision; the plan's launch
+ * shape and binning apply.  Enqueues and returns (capturable); the rule is
+ * computed on the host when n_nodes changes.  RIFT_EINVAL for a bad prior. */
+int rift_ile_plan_lnZ_dmarg(rift_ile_plan plan, const double *theta, const double *lnw,
+                            const rift_ile_dist_prior *prior, double *lnZ, double *neff, double *lnLd,
+                            void *stream);
+
+/* The n-point Gauss-Hermite rule of the weight e^{-x^2/2} (1 <= n <= 64) that
+ * the distance marginal uses: HOST nodes[n] ascending and weights[n]. */
+int rift_ile_gauss_hermite(int n, double *nodes, double *weights);
+
+/* ------------------------------------------------------------------------ */
 /* Leapfrog drift for gradient-based samplers in the coordinates of
  * RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST (Sec. "Sampling the
  * differentiable extrinsic likelihood"): theta[a][i] += step[a] p[a][i] for

@@ -284,27 +284,32 @@ def lnL_dmarg(pt, theta, d_min, d_max, n_nodes, power=2.0, nthreads: int = 0):
         int dx p_x(x) e^{lnL(x)} ~ sum_i w~_i p_x(x* + xi_i sigma_x) e^{lnL(x* + xi_i sigma_x)}
     with w~_i = sigma_x W_i e^{xi_i^2 / 2} (the Gaussian factor of the rule
     divided out, since e^{lnL(x* + xi sigma)} = e^{K^2 / 2R} e^{-xi^2 / 2}).
-    The prior is p(D) proportional to D^power on [d_min, d_max].  A sample
-    with R <= 0 (no model power) has no peak to centre on: NaN."""
+    The prior is p(D) proportional to D^power on [d_min, d_max].  R >= 0
+    holds exactly (U positive semi-definite, |Y^T V Y| <= Y^H U Y); R <= 0
+    arises only from rounding where the model has no power (F_k Y = 0), and
+    there K = 0 as well, lnL = 0 at every distance and the marginal is the
+    prior's mass: ln L_d = 0.  A non-finite sample gives NaN."""
     Kv, Rv = lnL_terms(pt, theta, nthreads)
     xi, W = np.polynomial.hermite_e.hermegauss(int(n_nodes))
-    out = np.empty(Kv.shape[0])
     d_ref = float(pt["d_ref"])
-    for i in range(Kv.shape[0]):
-        Ki, Ri = Kv[i], Rv[i]
-        if not (Ri > 0.0) or not np.isfinite(Ki):
-            out[i] = np.nan
-            continue
-        xs = Ki / Ri
-        sig = 1.0 / np.sqrt(Ri)
-        x = xs + xi * sig
-        lnl = Ki * x - 0.5 * Ri * x * x
-        wt = sig * W * np.exp(xi * xi / 2.0)
-        terms = wt * dist_prior_x(x, d_ref, d_min, d_max, power)
-        # sum_i terms_i e^{lnl_i}, in log form about the peak value K^2 / 2R
-        peak = 0.5 * Ki * Ki / Ri
-        s = np.sum(terms * np.exp(lnl - peak))
-        out[i] = peak + np.log(s) if s > 0 else -np.inf
+    nopow = np.isfinite(Kv) & np.isfinite(Rv) & (Rv <= 0.0)
+    ok = (Rv > 0.0) & np.isfinite(Kv) & np.isfinite(Rv)
+    Ki = np.where(ok, Kv, 0.0)[:, None]
+    Ri = np.where(ok, Rv, 1.0)[:, None]
+    xs = Ki / Ri
+    sig = 1.0 / np.sqrt(Ri)
+    x = xs + xi[None, :] * sig                      # [n, nodes]
+    lnl = Ki * x - 0.5 * Ri * x * x
+    wt = sig * W[None, :] * np.exp(xi * xi / 2.0)[None, :]
+    terms = wt * dist_prior_x(x, d_ref, d_min, d_max, power)
+    # sum_i terms_i e^{lnl_i}, in log form about the peak value K^2 / 2R
+    peak = 0.5 * Ki * Ki / Ri
+    s = np.sum(terms * np.exp(lnl - peak), axis=1)
+    with np.errstate(divide="ignore"):
+        out = peak[:, 0] + np.log(s)
+    out[s <= 0] = -np.inf
+    out[~ok] = np.nan
+    out[nopow] = 0.0
     return out
 
 

@@ -806,13 +806,64 @@ __device__ __forceinline__ Eval combine(PDesc P, double dist, double data, doubl
   return e;
 }
 
-// Everything per sample.  R is the arithmetic type of the bulk (FP64 or FP32);
-// the sky frame, delays and the final combination are always FP64.  The data
-// term comes from data_fn(row, sfr, Fre, Fim, cn, sn, cf, sf).
+// The distance-free terms of one sample: lnL(x) = x data - x^2 quad with
+// x = D_ref / D; wq is the model-norm part of the FP32 bound (BOUND only).
+struct Terms {
+  double data, quad, wq;
+  bool bad;
+};
+
+// Gauss-Hermite rule of the distance marginal (weight e^{-xi^2/2}; up to
+// DM_MAX nodes) and the prior p(D) proportional to D^2 on [d_min, d_max].
+constexpr int DM_MAX = 64;
+struct DistRule {
+  int32_t n;
+  int32_t pad;
+  double d_min, d_max;
+  double ln_norm;  // ln(3 / (d_max^3 - d_min^3))
+  double xi[DM_MAX], w[DM_MAX];
+};
+
+// ln of the likelihood marginalised over distance, Eq. (ap:dgh), from the
+// terms: with lnL(x) = K x - R x^2 / 2 (K = data, R = 2 quad), the peak
+// x* = K / R and width sigma = R^-1/2 of Eq. (ap:dpeak) centre and scale the
+// nodes, and the rule's weights times e^{lnL(x* + xi sigma)} are
+// sigma W_i e^{K^2 / 2R}, so
+//   ln L_d = K^2 / 2R + ln sigma + ln sum_i W_i p_x(x* + xi_i sigma),
+//   p_x(x) = d_ref^3 x^-4 3 / (d_max^3 - d_min^3) on [d_ref/d_max, d_ref/d_min].
+// No node inside the prior gives -inf; a poisoned sample gives NaN.  R >= 0
+// holds exactly, so R <= 0 comes only from rounding where the model has no
+// power (F_k Y = 0, hence K = 0 too): lnL = 0 at every distance and the
+// marginal is the prior's mass, ln L_d = 0.
+__device__ __forceinline__ double dist_marginal(const DistRule& G, double d_ref, const Terms& t) {
+  const double Kd = t.data, Rd = 2.0 * t.quad;
+  if (t.bad || !(fabs(Kd) <= 1.0e300) || !(fabs(Rd) <= 1.0e300)) return __builtin_nan("");
+  if (!(Rd > 0.0)) return 0.0;
+  const double xs = Kd / Rd;
+  const double sig = 1.0 / sqrt(Rd);
+  const double xlo = d_ref / G.d_max, xhi = d_ref / G.d_min;
+  double s = 0.0;
+  for (int i = 0; i < G.n; ++i) {
+    const double x = fma(G.xi[i], sig, xs);
+    if (x >= xlo && x <= xhi) {
+      const double r = d_ref / x;  // D at the node: p_x = D^4 / d_ref (normalised below)
+      const double r2 = r * r;
+      s = fma(G.w[i], r2 * r2, s);
+    }
+  }
+  if (!(s > 0.0)) return -__builtin_inf();
+  // p_x(x) = d_ref^3 x^-4 exp(ln_norm) = (d_ref / x)^4 exp(ln_norm) / d_ref
+  return 0.5 * Kd * xs + log(sig) + G.ln_norm - log(d_ref) + log(s);
+}
+
+// Everything per sample up to the distance: the terms.  R is the arithmetic
+// type of the bulk (FP64 or FP32); the sky frame, delays and the final
+// combination are always FP64.  The data term comes from
+// data_fn(row, sfr, Fre, Fim, cn, sn, cf, sf).
 template <class R, int KT, int L, bool BOUND, class DataFn>
-__device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, int ts, double ra,
-                                                 double dec, double psi, double incl, double phi,
-                                                 double tref, double dist, DataFn&& data_fn) {
+__device__ __forceinline__ Terms eval_terms_with(PDesc P, R* __restrict__ trig, int ts, double ra, double dec,
+                                                 double psi, double incl, double phi, double tref,
+                                                 DataFn&& data_fn) {
   constexpr int NY = Cls<L>::NY;
   reduce_angles<R>(psi, incl, phi);
   Sky<R, KT> S;
@@ -826,13 +877,33 @@ __device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, 
   __builtin_amdgcn_s_setprio(1);
   const double data = data_fn(S.row, S.sfr, S.Fre, S.Fim, cn, sn, cf, sf);
   __builtin_amdgcn_s_setprio(0);
-  double wq = 0.0;
-  const double quad = quad_term<R, KT, L, BOUND>(P, trig, ts, ci, si, cf, sf, S.Fre, S.Fim, &wq);
-  return combine<BOUND>(P, dist, data, quad, wq, S.bad);
+  Terms t;
+  t.wq = 0.0;
+  t.data = data;
+  t.quad = quad_term<R, KT, L, BOUND>(P, trig, ts, ci, si, cf, sf, S.Fre, S.Fim, &t.wq);
+  t.bad = S.bad;
+  return t;
+}
+
+template <class R, int KT, int L, bool BOUND, class DataFn>
+__device__ __forceinline__ Eval eval_sample_with(PDesc P, R* __restrict__ trig, int ts, double ra,
+                                                 double dec, double psi, double incl, double phi,
+                                                 double tref, double dist, DataFn&& data_fn) {
+  const Terms t = eval_terms_with<R, KT, L, BOUND>(P, trig, ts, ra, dec, psi, incl, phi, tref, data_fn);
+  return combine<BOUND>(P, dist, t.data, t.quad, t.wq, t.bad);
 }
 
 // `stage` is this wavefront's STAGE_WAVE bytes of LDS; the whole wavefront
-// must call this together.
+// must call these together.
+template <class R, int KT, int L>
+__device__ __forceinline__ Terms eval_terms(PDesc P, R* __restrict__ trig, int ts, RIFT_LDS unsigned char* stage,
+                                           double ra, double dec, double psi, double incl, double phi,
+                                           double tref) {
+  return eval_terms_with<R, KT, L, false>(
+      P, trig, ts, ra, dec, psi, incl, phi, tref,
+      [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
+          R sf) { return data_direct<R, KT, L>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf); });
+}
 template <class R, int KT, int L, bool BOUND>
 __device__ __forceinline__ Eval eval_sample(PDesc P, R* __restrict__ trig, int ts,
                                             RIFT_LDS unsigned char* stage, double ra, double dec, double psi,

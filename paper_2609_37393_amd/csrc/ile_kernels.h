@@ -11,7 +11,10 @@ namespace rift {
 // ---------------------------------------------------------------------------
 // Evaluation kernels
 // ---------------------------------------------------------------------------
-enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1 };
+// MODE_LSE64: FP64 lnL and the tile's (max, sum); MODE_PASS32: the FP32 pass
+// of the mixed path; MODE_DMARG64: FP64, the likelihood marginalised over
+// distance (Eq. (ap:dgh)) in place of lnL, and its tile (max, sum).
+enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1, MODE_DMARG64 = 2 };
 
 struct TileArgs {
   const PointDesc* descs;
@@ -33,6 +36,7 @@ struct TileArgs {
   // written to that sample index; the reductions then run in input order in
   // a separate pass
   const double* theta_aos;
+  DistRule dm;  // MODE_DMARG64: the distance rule and prior
 };
 
 // One tile: every sample's lnL (and bound), then a block reduction.
@@ -62,8 +66,15 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
       const bool live = o < t.cnt;
       const int64_t pos = t.s + (live ? o : t.cnt - 1);
       const RIFT_GLOBAL double* th = aos + 8 * pos;
-      const Eval e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0],
-                                                                th[1], th[2], th[3], th[4], th[5], th[6]);
+      Eval e;
+      if constexpr (MODE == MODE_DMARG64) {
+        const Terms tm = eval_terms<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3],
+                                              th[4], th[5]);
+        e.lnL = dist_marginal(a.dm, as_const(P)->d_ref, tm);
+      } else {
+        e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2],
+                                                       th[3], th[4], th[5], th[6]);
+      }
       const int64_t i = (int64_t)__double_as_longlong(th[7]) >> 16;
       if (live) {
         lnL[i] = e.lnL;
@@ -77,13 +88,19 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
     const bool live = o < t.cnt;
     const int64_t i = t.s + (live ? o : t.cnt - 1);
     const RIFT_GLOBAL double* th = theta + i;
-    const Eval e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0],
-                                                              th[N], th[2 * N], th[3 * N], th[4 * N],
-                                                              th[5 * N], th[6 * N]);
+    Eval e;
+    if constexpr (MODE == MODE_DMARG64) {
+      const Terms tm = eval_terms<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N],
+                                            th[3 * N], th[4 * N], th[5 * N]);
+      e.lnL = dist_marginal(a.dm, as_const(P)->d_ref, tm);
+    } else {
+      e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0], th[N],
+                                                     th[2 * N], th[3 * N], th[4 * N], th[5 * N], th[6 * N]);
+    }
     if (!live) continue;
     const double w = lnw ? lnw[i] : 0.0;
     if (lnL) lnL[i] = e.lnL;
-    if (MODE == MODE_LSE64) {
+    if (MODE != MODE_PASS32) {
       acc = ms_push(acc, e.lnL + w);
     } else {
       as_global_w(a.bnd)[i] = e.bound;
@@ -91,7 +108,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
       if (v == v) tm = fmax(tm, v);
     }
   }
-  if (MODE == MODE_LSE64) {
+  if (MODE != MODE_PASS32) {
     const MS r = ms_block(acc, sh);
     if (threadIdx.x == 0) {
       a.part[2 * tidx] = r.m;
@@ -426,6 +443,7 @@ typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, doubl
 #define RIFT_DECL_GETTERS(KT)                        \
   tile_fn get_tiles64_kt##KT(int lset);              \
   tile_fn get_tiles32_kt##KT(int lset);              \
+  tile_fn get_tilesdm_kt##KT(int lset);              \
   refine_fn get_refine_kt##KT(int lset);             \
   grad_fn get_grad_kt##KT(int L);                   \
   grad_fn get_gradw_kt##KT(int L);

@@ -1,6 +1,7 @@
 // Instances of the evaluation kernels for one detector class RIFT_KT and one
 // kernel kind RIFT_KIND (0: FP64 tiles, 1: FP32 tiles, 2: FP64 refine,
-// 3: gradient, a lane or a group of lanes per sample).  The build compiles
+// 3: gradient, a lane or a group of lanes per sample, 4: FP64 tiles of the
+// distance marginal).  The build compiles
 // this file once per (class, kind) so the instances build in parallel.
 #include "ile_kernels.h"
 
@@ -14,11 +15,15 @@
 namespace rift {
 
 // Mode-class sets: 1 (l<=2), 2 (l=3), 4 (l=4), 8 (l<=8), 7 (l<=4 mixed).
-#if RIFT_KIND == 0 || RIFT_KIND == 1
+#if RIFT_KIND == 0 || RIFT_KIND == 1 || RIFT_KIND == 4
 #if RIFT_KIND == 0
 #define RIFT_R double
 #define RIFT_MODE MODE_LSE64
 #define RIFT_NAME RIFT_CAT(get_tiles64_kt, RIFT_KT)
+#elif RIFT_KIND == 4
+#define RIFT_R double
+#define RIFT_MODE MODE_DMARG64
+#define RIFT_NAME RIFT_CAT(get_tilesdm_kt, RIFT_KT)
 #else
 #define RIFT_R float
 #define RIFT_MODE MODE_PASS32

@@ -910,6 +910,8 @@ struct rift_ile_plan_s {
   // optional timing of the main evaluation kernel
   bool profiling = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  // distance marginal: the rule of the last rift_ile_plan_lnZ_dmarg call
+  DistRule dm{};
 };
 
 namespace {
@@ -988,12 +990,16 @@ int build_tiles(rift_ile_plan p) {
 }
 
 // Kernel tables -------------------------------------------------------------
-tile_fn pick_tiles_kt(bool f64, int KT, int lset) {
+tile_fn pick_tiles_kt(int mode, int KT, int lset) {
   switch (KT) {
-    case 2: return f64 ? get_tiles64_kt2(lset) : get_tiles32_kt2(lset);
-    case 3: return f64 ? get_tiles64_kt3(lset) : get_tiles32_kt3(lset);
-    case 5: return f64 ? get_tiles64_kt5(lset) : get_tiles32_kt5(lset);
-    default: return f64 ? get_tiles64_kt8(lset) : get_tiles32_kt8(lset);
+    case 2:
+      return mode == MODE_LSE64 ? get_tiles64_kt2(lset) : mode == MODE_PASS32 ? get_tiles32_kt2(lset) : get_tilesdm_kt2(lset);
+    case 3:
+      return mode == MODE_LSE64 ? get_tiles64_kt3(lset) : mode == MODE_PASS32 ? get_tiles32_kt3(lset) : get_tilesdm_kt3(lset);
+    case 5:
+      return mode == MODE_LSE64 ? get_tiles64_kt5(lset) : mode == MODE_PASS32 ? get_tiles32_kt5(lset) : get_tilesdm_kt5(lset);
+    default:
+      return mode == MODE_LSE64 ? get_tiles64_kt8(lset) : mode == MODE_PASS32 ? get_tiles32_kt8(lset) : get_tilesdm_kt8(lset);
   }
 }
 refine_fn pick_refine_kt(int KT, int lset) {
@@ -1054,10 +1060,11 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.tmax = p->d_tmax;
   a.cnt = p->d_cnt;
   a.theta_aos = p->cfg.sort ? p->d_aos : nullptr;
-  const size_t rsz = (mode == MODE_LSE64 ? sizeof(double) : sizeof(float));
+  a.dm = p->dm;
+  const size_t rsz = (mode == MODE_PASS32 ? sizeof(float) : sizeof(double));
   const size_t shm = eval_lds_bytes(p->lset, p->cfg.block, rsz);
   if (shm + 1024 > (size_t)p->di.max_lds) return RIFT_EUNSUPPORTED;
-  tile_fn f = pick_tiles_kt(mode == MODE_LSE64, p->KT, p->lset);
+  tile_fn f = pick_tiles_kt(mode, p->KT, p->lset);
   if (!f) return RIFT_EUNSUPPORTED;
   int grid = p->n_tiles;
   if (a.persistent) grid = std::min(p->n_tiles, p->cfg.blocks_per_cu * p->di.n_cu);
@@ -1530,6 +1537,102 @@ int rift_ile_plan_lnZ(rift_ile_plan p, const double* theta, const double* lnw, d
                      lnw, (const float*)p->d_bnd, p->d_part, p->d_terr);
   hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
                      (const double*)p->d_terr, lnZ, neff, lnZ_err);
+  HCHK(hipGetLastError());
+  return RIFT_OK;
+}
+
+namespace {
+
+// Orthonormal polynomials of the weight e^{-x^2/2} on the real line (the
+// probabilists' Hermite He_k normalised): q_0 = (2 pi)^{-1/4},
+// x q_k = sqrt(k + 1) q_{k+1} + sqrt(k) q_{k-1}.  Returns q_n(x); with sum2,
+// also sum_{k < n} q_k(x)^2.
+double hermite_q(int n, double x, double* sum2) {
+  double qm = 0.0, q = 0.63161877774606470129;  // (2 pi)^{-1/4}
+  double s = 0.0;
+  for (int k = 0; k < n; ++k) {
+    s += q * q;
+    const double qn = (x * q - sqrt((double)k) * qm) / sqrt((double)(k + 1));
+    qm = q;
+    q = qn;
+  }
+  if (sum2) *sum2 = s;
+  return q;
+}
+
+}  // namespace
+
+// Gauss-Hermite rule of n nodes for the weight e^{-x^2/2}: the nodes are the n
+// simple roots of q_n, bracketed by the sign changes of q_n on a grid finer
+// than their spacing (the grid never meets x = 0, a root for odd n) and
+// bisected to the last bit; the weights are the Christoffel numbers
+// 1 / sum_{k<n} q_k(x_i)^2.  Ascending nodes.
+extern "C" int rift_ile_gauss_hermite(int n, double* nodes, double* weights) {
+  if (n < 1 || n > DM_MAX || !nodes || !weights) return RIFT_EINVAL;
+  const double L = 2.0 * sqrt((double)n) + 3.0;  // beyond the largest root
+  const int steps = 200000;
+  const double h = 2.0 * L / steps;
+  int found = 0;
+  double xa = -L + 0.5 * h, fa = hermite_q(n, xa, nullptr);
+  for (int j = 1; j < steps && found < n; ++j) {
+    const double xb = -L + (j + 0.5) * h, fb = hermite_q(n, xb, nullptr);
+    if ((fa < 0.0) != (fb < 0.0)) {
+      double lo = xa, hi = xb, flo = fa;
+      for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        const double fm = hermite_q(n, mid, nullptr);
+        if ((fm < 0.0) == (flo < 0.0)) {
+          lo = mid;
+          flo = fm;
+        } else {
+          hi = mid;
+        }
+      }
+      const double r = 0.5 * (lo + hi);
+      double s2;
+      (void)hermite_q(n, r, &s2);
+      nodes[found] = r;
+      weights[found] = 1.0 / s2;
+      ++found;
+    }
+    xa = xb;
+    fa = fb;
+  }
+  return found == n ? RIFT_OK : RIFT_EDEVICE;
+}
+
+int rift_ile_plan_lnZ_dmarg(rift_ile_plan p, const double* theta, const double* lnw, const rift_ile_dist_prior* prior,
+                            double* lnZ, double* neff, double* lnLd, void* stream) {
+  if (!p || !prior || check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  if ((lnw && check_dev_ptr(lnw)) || (neff && check_dev_ptr(neff)) || (lnLd && check_dev_ptr(lnLd)))
+    return RIFT_EINVAL;
+  const double d0 = prior->d_min, d1 = prior->d_max;
+  if (!(d0 > 0.0) || !(d1 > d0) || !(d1 <= 1.0e60)) return RIFT_EINVAL;
+  if (prior->n_nodes < 1 || prior->n_nodes > DM_MAX) return RIFT_EINVAL;
+  if (p->dm.n != prior->n_nodes) {
+    DistRule g{};
+    g.n = prior->n_nodes;
+    if (rift_ile_gauss_hermite(g.n, g.xi, g.w)) return RIFT_EDEVICE;
+    p->dm = g;
+  }
+  p->dm.d_min = d0;
+  p->dm.d_max = d1;
+  // 3 / (d_max^3 - d_min^3), in logs (d_max^3 may overflow only past 1e102)
+  p->dm.ln_norm = log(3.0) - 3.0 * log(d1) - log1p(-(d0 / d1) * (d0 / d1) * (d0 / d1));
+  hipStream_t st = (hipStream_t)stream;
+  p->last = st;
+  int rc;
+  const bool sorted = p->cfg.sort != 0;
+  double* L = lnLd ? lnLd : p->d_L;
+  if (sorted && (!p->bin_ready || !L)) return RIFT_EUNSUPPORTED;
+  if (sorted && (rc = run_binning(p, theta, st))) return rc;
+  if ((rc = launch_tiles(p, MODE_DMARG64, theta, lnw, sorted ? L : lnLd, st))) return rc;
+  if (sorted)
+    hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L, lnw,
+                       p->d_part);
+  hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
+                     (const double*)nullptr, lnZ, neff, (double*)nullptr);
   HCHK(hipGetLastError());
   return RIFT_OK;
 }

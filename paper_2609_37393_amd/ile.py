@@ -60,6 +60,8 @@ EXPORTS = (
     "rift_ile_wide_lnZ",
     "rift_ile_lnZ_noalloc",
     "rift_ile_leapfrog_drift",
+    "rift_ile_plan_lnZ_dmarg",
+    "rift_ile_gauss_hermite",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -105,6 +107,10 @@ class CPointWide(ctypes.Structure):
     ]
 
 
+class CDistPrior(ctypes.Structure):
+    _fields_ = [("d_min", ctypes.c_double), ("d_max", ctypes.c_double), ("n_nodes", ctypes.c_int32)]
+
+
 class CConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile_blocks", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("sort", ctypes.c_int32)]
@@ -142,6 +148,8 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_wide_lnZ.argtypes = [PW, i64, vp, vp, vp, vp, vp, vp]
     lib.rift_ile_lnZ_noalloc.argtypes = [P, i32, vp, vp, vp, vp, vp, vp, ci, vp]
     lib.rift_ile_leapfrog_drift.argtypes = [i64, vp, vp, vp, vp]
+    lib.rift_ile_plan_lnZ_dmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CDistPrior), vp, vp, vp, vp]
+    lib.rift_ile_gauss_hermite.argtypes = [ctypes.c_int, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
     lib.rift_ile_strerror.restype = ctypes.c_char_p
     lib.rift_ile_version.restype = ctypes.c_int
@@ -283,6 +291,29 @@ def wide_lnZ(point, theta, lnw=None, want_lnL=False, device="cuda"):
     return (z, ne, ll) if want_lnL else (z, ne)
 
 
+def lnL_dmarg(point, theta, d_min, d_max, n_nodes=20, device="cuda") -> torch.Tensor:
+    """ln L_d [n]: the likelihood marginalised over distance per sample
+    (rift_ile_plan_lnZ_dmarg through a one-point plan)."""
+    th = _theta(theta, device)
+    n = th.shape[1]
+    plan = Plan([point], [n], device=device)
+    try:
+        out = torch.empty(n, dtype=torch.float64, device=device)
+        plan.lnZ_dmarg(th, d_min, d_max, n_nodes, lnL_out=out)
+        torch.cuda.synchronize(device)
+    finally:
+        plan.close()
+    return out
+
+
+def gauss_hermite(n: int):
+    """The library's n-point rule of the weight exp(-x^2/2) (nodes, weights)."""
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _check(load().rift_ile_gauss_hermite(int(n), x.ctypes.data, w.ctypes.data), "rift_ile_gauss_hermite")
+    return x, w
+
+
 def leapfrog_drift(theta: torch.Tensor, p: torch.Tensor, step):
     """theta += step * p in place (rows as in the sampler's coordinates), with
     cos incl reflected into [-1, 1] and its momentum flipped (rift_ile_leapfrog_drift)."""
@@ -399,6 +430,23 @@ class Plan:
                                           None if bnd_out is None else bnd_out.data_ptr(),
                                           None if err_out is None else err_out.data_ptr(),
                                           _stream(self.device)), "rift_ile_plan_lnZ")
+        return z, ne
+
+    def lnZ_dmarg(self, theta, d_min, d_max, n_nodes=20, lnw=None, lnZ_out=None, neff_out=None, lnL_out=None):
+        """(ln Z_d, n_eff) per point of the likelihood marginalised over
+        distance (prior p(D) ~ D^2 on [d_min, d_max], n_nodes-point adaptive
+        Gauss-Hermite rule; rift_ile_plan_lnZ_dmarg); lnL_out receives ln L_d
+        per sample.  The distance row of theta is not read."""
+        th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
+            else _theta(theta, self.device)
+        P = len(self.points)
+        z = lnZ_out if lnZ_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        ne = neff_out if neff_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        pr = CDistPrior(float(d_min), float(d_max), int(n_nodes))
+        _check(self.lib.rift_ile_plan_lnZ_dmarg(self.handle, th.data_ptr(), None if lnw is None else lnw.data_ptr(),
+                                                ctypes.byref(pr), z.data_ptr(), ne.data_ptr(),
+                                                None if lnL_out is None else lnL_out.data_ptr(),
+                                                _stream(self.device)), "rift_ile_plan_lnZ_dmarg")
         return z, ne
 
     def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):
