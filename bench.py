@@ -631,14 +631,45 @@ def extra_dmarg(ile, synth, torch, steps, cpu=True):
     return res
 
 
+def extra_pregrid(ile, synth, torch, steps, cpu=True):
+    """The Fourier refinement x8 of the native 4096 Hz correlation tables
+    (Eq. (q-time-pregrid)) of the headline point (3 detectors x 21 modes, 820
+    native samples) and the five-detector point (5 x 21, 1639 samples): time per
+    table set, and the oracle's FFT implementation on the host beside it."""
+    res = {}
+    for name, K, n in (("c2_table", 3, 820), ("c5_table", 5, 1639)):
+        pt = synth.make_point(K, 21, n, 4096.0, 600.0, 7 + K)
+        q = torch.as_tensor(pt["Q"], device="cuda").contiguous()
+        nf = (n - 1) * 8 + 1
+        out = torch.empty((K, 21, nf), dtype=torch.complex128, device="cuda")
+        step = lambda: ile.pregrid(q, 8, out=out)
+        step()
+        secs, _ = time_steps(step, steps, 2, torch)
+        S = K * 21
+        flops = 4.0 * S * nf * n  # a real kernel value times a complex sample: 2 FMAs per (series, fine, native)
+        r = {"series": S, "native": n, "refined": nf, "ms_per_call": 1e3 * secs / steps,
+             "flops_per_call": flops, "alu_frac": flops / (secs / steps) / (PEAK_FP64_TFLOPS * 1e12)}
+        if cpu:
+            import oracle
+
+            t0 = time.perf_counter()
+            want = oracle.pregrid(pt["Q"], 8)
+            r["cpu_oracle_ms"] = 1e3 * (time.perf_counter() - t0)
+            r["max_abs_diff_vs_oracle"] = float(np.abs(out.cpu().numpy() - want).max())
+            r["max_abs_q"] = float(np.abs(pt["Q"]).max())
+        res[name] = r
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg",
-                    help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, c3, c1big; "
+    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid",
+                    help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, pregrid, "
+                         "c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
                     help="add the longer workloads (the 512-point batch c3, C1 at 1e7 samples c1big, "
@@ -760,7 +791,7 @@ def main():
     wanted = [x.strip() for x in args.workloads.split(",") if x.strip() and x.strip() != "none"]
     wanted += [x.strip() for x in args.extras.split(",") if x.strip()]
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
-           "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg}
+           "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg, "pregrid": extra_pregrid}
     for name in wanted:
         log(f"workload {name}")
         try:

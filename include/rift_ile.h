@@ -319,6 +319,20 @@ int rift_ile_plan_lnZ_dmarg(rift_ile_plan plan, const double *theta, const doubl
 int rift_ile_gauss_hermite(int n, double *nodes, double *weights);
 
 /* ------------------------------------------------------------------------ */
+/* Fourier refinement of sampled series, Eq. (q-time-pregrid): each series of
+ * n native samples (spacing h) is extended by its reversed copy to a
+ * continuous period of 2n samples, its spectrum zero-padded by r (the Nyquist
+ * bin split in halves) and transformed back, keeping the (n - 1) r + 1 samples
+ * at spacing h / r that span the original window; the nodes are reproduced.
+ * Computed as the equivalent real interpolation operator (a periodic sinc of
+ * period 2n in closed form) applied to every series.
+ * q: DEVICE [n_series][n] complex; fine: DEVICE [n_series][(n - 1) r + 1]
+ * complex (not overlapping q).  2 <= n, 1 <= r <= 64, (n - 1) r + 1 <= 2^28.
+ * Enqueues and returns; stream-ordered scratch of 8 r (3n - 1) bytes
+ * (hipMallocAsync / hipFreeAsync on `stream`). */
+int rift_ile_pregrid(const double *q, int64_t n_series, int32_t n, int32_t r, double *fine, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Leapfrog drift for gradient-based samplers in the coordinates of
  * RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST (Sec. "Sampling the
  * differentiable extrinsic likelihood"): theta[a][i] += step[a] p[a][i] for

@@ -62,6 +62,7 @@ EXPORTS = (
     "rift_ile_leapfrog_drift",
     "rift_ile_plan_lnZ_dmarg",
     "rift_ile_gauss_hermite",
+    "rift_ile_pregrid",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -150,6 +151,7 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_leapfrog_drift.argtypes = [i64, vp, vp, vp, vp]
     lib.rift_ile_plan_lnZ_dmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CDistPrior), vp, vp, vp, vp]
     lib.rift_ile_gauss_hermite.argtypes = [ctypes.c_int, vp, vp]
+    lib.rift_ile_pregrid.argtypes = [vp, i64, i32, i32, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
     lib.rift_ile_strerror.restype = ctypes.c_char_p
     lib.rift_ile_version.restype = ctypes.c_int
@@ -304,6 +306,20 @@ def lnL_dmarg(point, theta, d_min, d_max, n_nodes=20, device="cuda") -> torch.Te
     finally:
         plan.close()
     return out
+
+
+def pregrid(q, r: int, out=None, device="cuda") -> torch.Tensor:
+    """Fourier refinement by r of complex series q [..., n] (rift_ile_pregrid):
+    [..., (n - 1) r + 1] complex128 on the device."""
+    lib = load()
+    qt = torch.as_tensor(q).to(device=device, dtype=torch.complex128).contiguous()
+    n = qt.shape[-1]
+    S = int(np.prod(qt.shape[:-1])) if qt.dim() > 1 else 1
+    nf = (n - 1) * int(r) + 1
+    o = out if out is not None else torch.empty(qt.shape[:-1] + (nf,), dtype=torch.complex128, device=device)
+    _check(lib.rift_ile_pregrid(qt.data_ptr(), S, n, int(r), o.data_ptr(), _stream(torch.device(device))),
+           "rift_ile_pregrid")
+    return o
 
 
 def gauss_hermite(n: int):
