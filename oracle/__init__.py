@@ -7,9 +7,10 @@ the two share no code.
 
 The arithmetic lives in ``oracle.cpp`` (plain loops, IEEE double, OpenMP over
 samples); this module only marshals numpy arrays into it.  ``pregrid`` (the
-Fourier refinement of Eq. (q-time-pregrid)) and ``lnL_dmarg`` (the adaptive
-Gauss-Hermite marginal over distance, Eq. (ap:dgh)) are written here in
-numpy.
+Fourier refinement of Eq. (q-time-pregrid)), ``lnL_dmarg`` (the adaptive
+Gauss-Hermite marginal over distance, Eq. (ap:dgh)) and ``lnL_tmarg`` (the
+fixed-spacing rule over time, Eq. (ap:tfixed)) are written here in numpy
+on top of the C likelihood.
 
 Every function states the passage of the paper it follows.  Parity status of
 each function (what pins it) is listed in the tests' docstrings.
@@ -310,6 +311,38 @@ def lnL_dmarg(pt, theta, d_min, d_max, n_nodes, power=2.0, nthreads: int = 0):
     out[s <= 0] = -np.inf
     out[~ok] = np.nan
     out[nopow] = 0.0
+    return out
+
+
+def simpson_weights(n_t: int) -> np.ndarray:
+    """Composite Simpson weights on n_t (odd) equally spaced nodes, in units
+    of the spacing: (1, 4, 2, 4, ..., 2, 4, 1) / 3."""
+    assert n_t >= 3 and n_t % 2 == 1
+    w = np.full(n_t, 2.0)
+    w[1::2] = 4.0
+    w[0] = w[-1] = 1.0
+    return w / 3.0
+
+
+def lnL_tmarg(pt, theta, t_start, h, n_t, nthreads: int = 0):
+    """ln of the likelihood marginalised over geocentric time per sample,
+    under a prior uniform on [t_start, t_start + (n_t - 1) h], by the
+    fixed-spacing rule of Eq. (ap:tfixed) with composite Simpson weights:
+        L_t = (1 / T) int dt e^{lnL(t)} ~ (h / T) sum_k w_k e^{lnL(t_start + k h)},
+    T = (n_t - 1) h.  Each lnL(t_k) is the oracle's own lnL with t_ref = t_k;
+    the time row of theta is not read."""
+    th = _c(theta, np.float64)
+    n = th.shape[1]
+    w = simpson_weights(int(n_t))
+    tk = t_start + h * np.arange(n_t)
+    big = np.repeat(th, n_t, axis=1)           # sample-major: [7, n * n_t]
+    big[5] = np.tile(tk, n)
+    l = lnL(pt, big, nthreads).reshape(n, n_t) + np.log(w)[None, :]
+    m = np.max(l, axis=1)
+    out = np.full(n, np.nan)
+    ok = np.isfinite(m)
+    out[ok] = m[ok] + np.log(np.sum(np.exp(l[ok] - m[ok, None]), axis=1)) - np.log(n_t - 1.0)
+    out[np.isnan(l).any(axis=1)] = np.nan
     return out
 
 
