@@ -661,14 +661,58 @@ def extra_pregrid(ile, synth, torch, steps, cpu=True):
     return res
 
 
+def extra_tmarg(ile, synth, torch, steps, cpu=True):
+    """The headline point (3 detectors, 21 modes, SNR 600) marginalised over
+    geocentric time by the fixed-spacing Simpson rule at the table's rate
+    (Eq. (ap:tfixed)): 657 times over the prior's 20 ms, 1e5 samples of the
+    other six parameters; against the FP64 oracle on a sample of them."""
+    pt = synth.make_point(3, 21, 6554, 32768.0, 600.0, 2)
+    n, n_t = 100_000, 657
+    h = 0.02 / (n_t - 1)
+    th = synth.prior_samples(n, 2)
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    plan = ile.Plan([pt], [n])
+    z = torch.empty(1, dtype=torch.float64, device="cuda")
+    ll = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.lnZ_tmarg(tht, -0.01, h, n_t, lnZ_out=z, lnL_out=ll)
+
+    step()
+    secs, _ = time_steps(step, max(2, steps // 3), 1, torch)
+    per = secs / max(2, steps // 3)
+    plan.profile(True)
+    step()
+    kms, nl = plan.profile_read()
+    plan.profile(False)
+    plan.close()
+    # the model-norm term once, the data term (antenna, stencils, gather, interpolation, coefficients) per time
+    fps = survey_flops_per_sample(3, 21) + (n_t - 1) * 3 * (57 + 26 * 21)
+    res = {"workload": "3 detectors, 21 modes (l<=4), Q 6554 samples at 32768 Hz, SNR 600; 1e5 samples of the other "
+                       "parameters, Simpson rule on 657 times (32768 Hz) over 20 ms",
+           "lnLt_evals_per_s": n / per, "data_terms_per_s": n * n_t / per, "ms_per_call": 1e3 * per,
+           "kernel_ms": kms / max(1, nl), "flops_per_sample": fps,
+           "alu_frac": fps * n / (kms / max(1, nl) / 1e3) / (PEAK_FP64_TFLOPS * 1e12), "lnZt": z.item()}
+    if cpu:
+        import oracle
+
+        idx = np.random.default_rng(1).choice(n, 300, replace=False)
+        t0 = time.perf_counter()
+        want = oracle.lnL_tmarg(pt, th[:, idx], -0.01, h, n_t)
+        res["cpu_oracle_lnLt_evals_per_s"] = idx.size / (time.perf_counter() - t0)
+        res["max_abs_dlnLt_vs_oracle_sampled"] = float(np.nanmax(np.abs(ll.cpu().numpy()[idx] - want)))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid",
+    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg",
                     help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, pregrid, "
+                         "tmarg, "
                          "c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
@@ -791,7 +835,8 @@ def main():
     wanted = [x.strip() for x in args.workloads.split(",") if x.strip() and x.strip() != "none"]
     wanted += [x.strip() for x in args.extras.split(",") if x.strip()]
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
-           "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg, "pregrid": extra_pregrid}
+           "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg, "pregrid": extra_pregrid,
+           "tmarg": extra_tmarg}
     for name in wanted:
         log(f"workload {name}")
         try:

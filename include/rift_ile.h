@@ -314,6 +314,28 @@ int rift_ile_plan_lnZ_dmarg(rift_ile_plan plan, const double *theta, const doubl
                             const rift_ile_dist_prior *prior, double *lnZ, double *neff, double *lnLd,
                             void *stream);
 
+/* Direct marginalisation over geocentric time by the fixed-spacing rule
+ * (Sec. "Time: representing the correlations and placing the integration
+ * nodes", Eq. (ap:tfixed)) under a prior uniform on the window
+ * [t_start, t_start + (n_t - 1) h]:
+ *   ln L_t = ln[(h / T) sum_k w_k e^{lnL(t_start + k h)}],  T = (n_t - 1) h,
+ * with composite Simpson weights w = (1, 4, 2, 4, ..., 2, 4, 1) / 3 (n_t odd).
+ * The model-norm term is evaluated once per sample, the data term at each
+ * time.  The rule resolves the peak only where h is below its width,
+ * 1 / (2 pi rho sigma_f) (Eq. (ap:sigmat)); choosing h is the caller's. */
+typedef struct {
+  double t_start, h; /* first time (s, the axis of t_ref) and spacing (s), h > 0 */
+  int32_t n_t;       /* odd, 3 .. 1000001 */
+} rift_ile_time_rule;
+
+/* ln L_t per sample (lnLt: DEVICE [N] or NULL) and, per point, ln Z_t and
+ * n_eff over the plan's batch, as rift_ile_plan_lnZ_dmarg; theta's t_ref row
+ * is not read.  FP64; enqueues and returns (capturable); RIFT_EINVAL for a
+ * bad rule.  Cost per sample: one model-norm term and n_t data terms. */
+int rift_ile_plan_lnZ_tmarg(rift_ile_plan plan, const double *theta, const double *lnw,
+                            const rift_ile_time_rule *rule, double *lnZ, double *neff, double *lnLt,
+                            void *stream);
+
 /* The n-point Gauss-Hermite rule of the weight e^{-x^2/2} (1 <= n <= 64) that
  * the distance marginal uses: HOST nodes[n] ascending and weights[n]. */
 int rift_ile_gauss_hermite(int n, double *nodes, double *weights);

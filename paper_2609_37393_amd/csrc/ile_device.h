@@ -604,13 +604,36 @@ struct Sky {
   R sfr[KT];        // fractional position inside the stencil cell
   int32_t row[KT];  // padded index of the first stencil row, in [0, n_t + QPAD]
   bool bad;         // a non-finite arrival time
+  double N[3];      // direction to the source
 };
+// The stencils of every detector for geocentric time t (the sky frame in S).
+template <class R, int KT>
+__device__ __forceinline__ void sky_stencils(PDesc P, double t, Sky<R, KT>& S) {
+  const int n_t = P->n_t;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const RIFT_CONST double* r = P->rpos[k];
+    const double tk = t - (r[0] * S.N[0] + r[1] * S.N[1] + r[2] * S.N[2]);
+    double u = (tk - P->t0) * P->inv_dt;
+    if (!stencil_u(u, n_t)) S.bad = true;
+    const double jf = floor(u);
+    const R s = (R)(u - jf);
+    int j0 = (int)jf - 1;  // stencil rows j0 .. j0+3
+    // wholly outside the stored window: read four zero pad rows
+    j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
+    S.row[k] = j0 + QPAD;
+    S.sfr[k] = s;
+  }
+}
 template <class R, int KT, bool STENCIL>
 __device__ __forceinline__ void sky_eval(PDesc P, double ra, double dec, double psi, double tref, Sky<R, KT>& S) {
   double sg, cg, sd, cd;
   sincos_(P->gmst - ra, &sg, &cg);
   sincos_(dec, &sd, &cd);
   const double N0 = cd * cg, N1 = -cd * sg, N2 = sd;
+  S.N[0] = N0;
+  S.N[1] = N1;
+  S.N[2] = N2;
   R sp, cp;
   sincos_((R)psi, &sp, &cp);
   const R ea0 = (R)sg, ea1 = (R)cg;
@@ -622,7 +645,6 @@ __device__ __forceinline__ void sky_eval(PDesc P, double ra, double dec, double 
   const R ex[6] = {2 * X0 * Y0, 2 * X1 * Y1, 2 * X2 * Y2,
                    X0 * Y1 + Y0 * X1, X0 * Y2 + Y0 * X2, X1 * Y2 + Y1 * X2};
   S.bad = false;
-  const int n_t = P->n_t;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     R fp = 0, fx = 0;
@@ -633,20 +655,8 @@ __device__ __forceinline__ void sky_eval(PDesc P, double ra, double dec, double 
     }
     S.Fre[k] = fp;
     S.Fim[k] = fx;
-    if constexpr (STENCIL) {
-      const RIFT_CONST double* r = P->rpos[k];
-      const double tk = tref - (r[0] * N0 + r[1] * N1 + r[2] * N2);
-      double u = (tk - P->t0) * P->inv_dt;
-      if (!stencil_u(u, n_t)) S.bad = true;
-      const double jf = floor(u);
-      const R s = (R)(u - jf);
-      int j0 = (int)jf - 1;  // stencil rows j0 .. j0+3
-      // wholly outside the stored window: read four zero pad rows
-      j0 = j0 < -QPAD ? -QPAD : (j0 > n_t ? n_t : j0);
-      S.row[k] = j0 + QPAD;
-      S.sfr[k] = s;
-    }
   }
+  if constexpr (STENCIL) sky_stencils<R, KT>(P, tref, S);
 }
 
 // The angles that the FP32 arithmetic takes, reduced in FP64 first.
@@ -856,6 +866,62 @@ __device__ __forceinline__ double dist_marginal(const DistRule& G, double d_ref,
   return 0.5 * Kd * xs + log(sig) + G.ln_norm - log(d_ref) + log(s);
 }
 
+// The fixed-spacing rule over geocentric time (Eq. (ap:tfixed)): n (odd)
+// times t0 + k h, composite Simpson weights, prior uniform over the window.
+struct TimeRule {
+  int32_t n;
+  int32_t pad;
+  double t0, h;
+  double ln_scale;                // ln(h / T) = -ln(n - 1), T = (n - 1) h
+  double lw_end, lw_odd, lw_even;  // ln(1/3), ln(4/3), ln(2/3)
+};
+
+// ln of the likelihood marginalised over geocentric time, per sample:
+//   ln L_t = ln[(h / T) sum_k w_k e^{lnL(t0 + k h)}].
+// The model-norm term does not depend on time, so it is evaluated once; the
+// data term once per time (new stencils, the same F and Y).  The log-sum
+// runs online with one exp per time.  A poisoned sample gives NaN.  The
+// whole wavefront calls this together (the data term reads cooperatively).
+template <class R, int KT, int L, class DataFn>
+__device__ __forceinline__ double eval_tmarg_with(PDesc P, R* __restrict__ trig, int ts, double ra, double dec,
+                                                  double psi, double incl, double phi, double dist,
+                                                  const TimeRule& T, DataFn&& data_fn) {
+  constexpr int NY = Cls<L>::NY;
+  reduce_angles<R>(psi, incl, phi);
+  Sky<R, KT> S;
+  sky_eval<R, KT, false>(P, ra, dec, psi, 0.0, S);
+  R si, ci;
+  sincos_((R)incl, &si, &ci);
+  R cn[NY], sn[NY];
+  incl_harmonics<R, NY>(ci, si, cn, sn);
+  R sf, cf;
+  sincos_((R)phi, &sf, &cf);
+  double wq = 0.0;
+  const double quad = quad_term<R, KT, L, false>(P, trig, ts, ci, si, cf, sf, S.Fre, S.Fim, &wq);
+  const double x = P->d_ref / dist;
+  const double base = -x * x * quad;
+  double m = -__builtin_inf(), sum = 0.0;
+  bool bad = !(fabs(x) <= 1.0e300) || !(fabs(base) <= 1.0e300);
+  for (int k = 0; k < T.n; ++k) {
+    S.bad = false;
+    sky_stencils<R, KT>(P, fma((double)k, T.h, T.t0), S);
+    bad = bad || S.bad;
+    __builtin_amdgcn_s_setprio(1);
+    const double data = data_fn(S.row, S.sfr, S.Fre, S.Fim, cn, sn, cf, sf);
+    __builtin_amdgcn_s_setprio(0);
+    const double lw = (k == 0 || k == T.n - 1) ? T.lw_end : ((k & 1) ? T.lw_odd : T.lw_even);
+    const double l = fma(x, data, base) + lw;
+    if (l > m) {
+      sum = (sum == 0.0) ? 1.0 : fma(sum, exp(m - l), 1.0);
+      m = l;
+    } else {
+      sum += exp(l - m);
+    }
+  }
+  if (bad || !(m == m)) return __builtin_nan("");
+  return m + log(sum) + T.ln_scale;
+}
+
 // Everything per sample up to the distance: the terms.  R is the arithmetic
 // type of the bulk (FP64 or FP32); the sky frame, delays and the final
 // combination are always FP64.  The data term comes from
@@ -901,6 +967,15 @@ __device__ __forceinline__ Terms eval_terms(PDesc P, R* __restrict__ trig, int t
                                            double tref) {
   return eval_terms_with<R, KT, L, false>(
       P, trig, ts, ra, dec, psi, incl, phi, tref,
+      [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
+          R sf) { return data_direct<R, KT, L>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf); });
+}
+template <class R, int KT, int L>
+__device__ __forceinline__ double eval_tmarg(PDesc P, R* __restrict__ trig, int ts, RIFT_LDS unsigned char* stage,
+                                            double ra, double dec, double psi, double incl, double phi, double dist,
+                                            const TimeRule& T) {
+  return eval_tmarg_with<R, KT, L>(
+      P, trig, ts, ra, dec, psi, incl, phi, dist, T,
       [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
           R sf) { return data_direct<R, KT, L>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf); });
 }

@@ -13,8 +13,10 @@ namespace rift {
 // ---------------------------------------------------------------------------
 // MODE_LSE64: FP64 lnL and the tile's (max, sum); MODE_PASS32: the FP32 pass
 // of the mixed path; MODE_DMARG64: FP64, the likelihood marginalised over
-// distance (Eq. (ap:dgh)) in place of lnL, and its tile (max, sum).
-enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1, MODE_DMARG64 = 2 };
+// distance (Eq. (ap:dgh)) in place of lnL, and its tile (max, sum);
+// MODE_TMARG64: FP64, the likelihood marginalised over geocentric time by the
+// fixed-spacing rule (Eq. (ap:tfixed)) in place of lnL, and its tile pair.
+enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1, MODE_DMARG64 = 2, MODE_TMARG64 = 3 };
 
 struct TileArgs {
   const PointDesc* descs;
@@ -37,6 +39,7 @@ struct TileArgs {
   // a separate pass
   const double* theta_aos;
   DistRule dm;  // MODE_DMARG64: the distance rule and prior
+  TimeRule tm;  // MODE_TMARG64: the time rule
 };
 
 // One tile: every sample's lnL (and bound), then a block reduction.
@@ -71,6 +74,9 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
         const Terms tm = eval_terms<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3],
                                               th[4], th[5]);
         e.lnL = dist_marginal(a.dm, as_const(P)->d_ref, tm);
+      } else if constexpr (MODE == MODE_TMARG64) {
+        e.lnL = eval_tmarg<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3], th[4], th[6],
+                                     a.tm);
       } else {
         e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2],
                                                        th[3], th[4], th[5], th[6]);
@@ -93,6 +99,9 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
       const Terms tm = eval_terms<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N],
                                             th[3 * N], th[4 * N], th[5 * N]);
       e.lnL = dist_marginal(a.dm, as_const(P)->d_ref, tm);
+    } else if constexpr (MODE == MODE_TMARG64) {
+      e.lnL = eval_tmarg<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N], th[3 * N],
+                                   th[4 * N], th[6 * N], a.tm);
     } else {
       e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0], th[N],
                                                      th[2 * N], th[3 * N], th[4 * N], th[5 * N], th[6 * N]);
@@ -444,6 +453,7 @@ typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, doubl
   tile_fn get_tiles64_kt##KT(int lset);              \
   tile_fn get_tiles32_kt##KT(int lset);              \
   tile_fn get_tilesdm_kt##KT(int lset);              \
+  tile_fn get_tilestm_kt##KT(int lset);              \
   refine_fn get_refine_kt##KT(int lset);             \
   grad_fn get_grad_kt##KT(int L);                   \
   grad_fn get_gradw_kt##KT(int L);

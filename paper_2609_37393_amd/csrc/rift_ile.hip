@@ -912,6 +912,8 @@ struct rift_ile_plan_s {
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   // distance marginal: the rule of the last rift_ile_plan_lnZ_dmarg call
   DistRule dm{};
+  // time marginal: the rule of the last rift_ile_plan_lnZ_tmarg call
+  TimeRule tm{};
 };
 
 namespace {
@@ -991,16 +993,20 @@ int build_tiles(rift_ile_plan p) {
 
 // Kernel tables -------------------------------------------------------------
 tile_fn pick_tiles_kt(int mode, int KT, int lset) {
-  switch (KT) {
-    case 2:
-      return mode == MODE_LSE64 ? get_tiles64_kt2(lset) : mode == MODE_PASS32 ? get_tiles32_kt2(lset) : get_tilesdm_kt2(lset);
-    case 3:
-      return mode == MODE_LSE64 ? get_tiles64_kt3(lset) : mode == MODE_PASS32 ? get_tiles32_kt3(lset) : get_tilesdm_kt3(lset);
-    case 5:
-      return mode == MODE_LSE64 ? get_tiles64_kt5(lset) : mode == MODE_PASS32 ? get_tiles32_kt5(lset) : get_tilesdm_kt5(lset);
-    default:
-      return mode == MODE_LSE64 ? get_tiles64_kt8(lset) : mode == MODE_PASS32 ? get_tiles32_kt8(lset) : get_tilesdm_kt8(lset);
+#define RIFT_PICK(K)                                 \
+  switch (mode) {                                    \
+    case MODE_LSE64: return get_tiles64_kt##K(lset); \
+    case MODE_PASS32: return get_tiles32_kt##K(lset); \
+    case MODE_DMARG64: return get_tilesdm_kt##K(lset); \
+    default: return get_tilestm_kt##K(lset);         \
   }
+  switch (KT) {
+    case 2: RIFT_PICK(2)
+    case 3: RIFT_PICK(3)
+    case 5: RIFT_PICK(5)
+    default: RIFT_PICK(8)
+  }
+#undef RIFT_PICK
 }
 refine_fn pick_refine_kt(int KT, int lset) {
   switch (KT) {
@@ -1061,6 +1067,7 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.cnt = p->d_cnt;
   a.theta_aos = p->cfg.sort ? p->d_aos : nullptr;
   a.dm = p->dm;
+  a.tm = p->tm;
   const size_t rsz = (mode == MODE_PASS32 ? sizeof(float) : sizeof(double));
   const size_t shm = eval_lds_bytes(p->lset, p->cfg.block, rsz);
   if (shm + 1024 > (size_t)p->di.max_lds) return RIFT_EUNSUPPORTED;
@@ -1628,6 +1635,40 @@ int rift_ile_plan_lnZ_dmarg(rift_ile_plan p, const double* theta, const double* 
   if (sorted && (!p->bin_ready || !L)) return RIFT_EUNSUPPORTED;
   if (sorted && (rc = run_binning(p, theta, st))) return rc;
   if ((rc = launch_tiles(p, MODE_DMARG64, theta, lnw, sorted ? L : lnLd, st))) return rc;
+  if (sorted)
+    hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L, lnw,
+                       p->d_part);
+  hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
+                     (const double*)nullptr, lnZ, neff, (double*)nullptr);
+  HCHK(hipGetLastError());
+  return RIFT_OK;
+}
+
+int rift_ile_plan_lnZ_tmarg(rift_ile_plan p, const double* theta, const double* lnw, const rift_ile_time_rule* rule,
+                            double* lnZ, double* neff, double* lnLt, void* stream) {
+  if (!p || !rule || check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  if ((lnw && check_dev_ptr(lnw)) || (neff && check_dev_ptr(neff)) || (lnLt && check_dev_ptr(lnLt)))
+    return RIFT_EINVAL;
+  if (rule->n_t < 3 || rule->n_t > 1000001 || (rule->n_t % 2) == 0) return RIFT_EINVAL;
+  if (!std::isfinite(rule->t_start) || !(rule->h > 0.0) || !std::isfinite(rule->h)) return RIFT_EINVAL;
+  if (!std::isfinite(rule->t_start + (rule->n_t - 1) * rule->h)) return RIFT_EINVAL;
+  TimeRule t{};
+  t.n = rule->n_t;
+  t.t0 = rule->t_start;
+  t.h = rule->h;
+  t.ln_scale = -log((double)(rule->n_t - 1));
+  t.lw_end = log(1.0 / 3.0);
+  t.lw_odd = log(4.0 / 3.0);
+  t.lw_even = log(2.0 / 3.0);
+  p->tm = t;
+  hipStream_t st = (hipStream_t)stream;
+  p->last = st;
+  int rc;
+  const bool sorted = p->cfg.sort != 0;
+  double* L = lnLt ? lnLt : p->d_L;
+  if (sorted && (!p->bin_ready || !L)) return RIFT_EUNSUPPORTED;
+  if (sorted && (rc = run_binning(p, theta, st))) return rc;
+  if ((rc = launch_tiles(p, MODE_TMARG64, theta, lnw, sorted ? L : lnLt, st))) return rc;
   if (sorted)
     hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L, lnw,
                        p->d_part);

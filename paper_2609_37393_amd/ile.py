@@ -63,6 +63,7 @@ EXPORTS = (
     "rift_ile_plan_lnZ_dmarg",
     "rift_ile_gauss_hermite",
     "rift_ile_pregrid",
+    "rift_ile_plan_lnZ_tmarg",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -112,6 +113,10 @@ class CDistPrior(ctypes.Structure):
     _fields_ = [("d_min", ctypes.c_double), ("d_max", ctypes.c_double), ("n_nodes", ctypes.c_int32)]
 
 
+class CTimeRule(ctypes.Structure):
+    _fields_ = [("t_start", ctypes.c_double), ("h", ctypes.c_double), ("n_t", ctypes.c_int32)]
+
+
 class CConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile_blocks", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("sort", ctypes.c_int32)]
@@ -152,6 +157,7 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_plan_lnZ_dmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CDistPrior), vp, vp, vp, vp]
     lib.rift_ile_gauss_hermite.argtypes = [ctypes.c_int, vp, vp]
     lib.rift_ile_pregrid.argtypes = [vp, i64, i32, i32, vp, vp]
+    lib.rift_ile_plan_lnZ_tmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CTimeRule), vp, vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
     lib.rift_ile_strerror.restype = ctypes.c_char_p
     lib.rift_ile_version.restype = ctypes.c_int
@@ -463,6 +469,23 @@ class Plan:
                                                 ctypes.byref(pr), z.data_ptr(), ne.data_ptr(),
                                                 None if lnL_out is None else lnL_out.data_ptr(),
                                                 _stream(self.device)), "rift_ile_plan_lnZ_dmarg")
+        return z, ne
+
+    def lnZ_tmarg(self, theta, t_start, h, n_t, lnw=None, lnZ_out=None, neff_out=None, lnL_out=None):
+        """(ln Z_t, n_eff) per point of the likelihood marginalised over
+        geocentric time by the fixed-spacing Simpson rule on n_t times
+        t_start + k h (rift_ile_plan_lnZ_tmarg); lnL_out receives ln L_t per
+        sample.  The t_ref row of theta is not read."""
+        th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
+            else _theta(theta, self.device)
+        P = len(self.points)
+        z = lnZ_out if lnZ_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        ne = neff_out if neff_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        rule = CTimeRule(float(t_start), float(h), int(n_t))
+        _check(self.lib.rift_ile_plan_lnZ_tmarg(self.handle, th.data_ptr(), None if lnw is None else lnw.data_ptr(),
+                                                ctypes.byref(rule), z.data_ptr(), ne.data_ptr(),
+                                                None if lnL_out is None else lnL_out.data_ptr(),
+                                                _stream(self.device)), "rift_ile_plan_lnZ_tmarg")
         return z, ne
 
     def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):

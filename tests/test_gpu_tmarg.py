@@ -1,0 +1,140 @@
+"""The likelihood marginalised over geocentric time on the GPU
+(rift_ile_plan_lnZ_tmarg, Eq. (ap:tfixed), composite Simpson weights under a
+prior uniform on the window) against the FP64 oracle.
+
+Bar (written here): |d ln L_t| <= 1e-9 max_k S(t_k) + 1e-12 per sample, with
+S(t_k) = |x data(t_k)| + |x^2 quad| the FP64 bar's scale at each time of the
+rule (a log-sum of values each within its bar stays within the largest);
+NaN must agree; ln Z_t within 1e-9 max(1, |ln Z_t|), n_eff to 1e-9 relative."""
+import numpy as np
+import pytest
+
+from paper_2609_37393_amd import synth
+
+from ._helpers import lnL_scale
+from .test_gpu_parity import CASES, _point
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ile():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2609_37393_amd import ile as m
+
+    m.load()
+    return m
+
+
+def _bar(oracle_mod, pt, th, t_start, h, n_t):
+    n = th.shape[1]
+    big = np.repeat(th, n_t, axis=1)
+    big[5] = np.tile(t_start + h * np.arange(n_t), n)
+    S = lnL_scale(oracle_mod, pt, big).reshape(n, n_t)
+    S = np.where(np.isfinite(S), S, 0.0)
+    return 1e-9 * S.max(axis=1) + 1e-12
+
+
+def _compare(got, want, bar, what):
+    assert np.array_equal(np.isnan(got), np.isnan(want)), what
+    fin = np.isfinite(want)
+    d = np.abs(got[fin] - want[fin])
+    assert np.all(d <= bar[fin]), (what, (d / bar[fin]).max())
+
+
+@pytest.mark.parametrize("case", CASES[:7], ids=[f"K{c[0]}M{c[1]}nt{c[2]}" for c in CASES[:7]])
+def test_tmarg_matches_oracle(ile, oracle_mod, case):
+    import torch
+
+    pt, th = _point(case)
+    print(f"case {case}", flush=True)
+    th = th[:, :600]
+    near, lnw_near = synth.weighted_samples(200, case[6] + 90)
+    th = np.concatenate([th, near], axis=1)
+    lnw = np.concatenate([np.zeros(th.shape[1] - 200), lnw_near])
+    n = th.shape[1]
+    for t_start, h, n_t in ((-0.01, 0.02 / 40, 41), (-0.0031, 1.0 / 32768 / 3, 201)):
+        want = oracle_mod.lnL_tmarg(pt, th, t_start, h, n_t)
+        z_or, ne_or = oracle_mod.lnZ(want, lnw)
+        plan = ile.Plan([pt], [n])
+        tht = torch.as_tensor(th, device="cuda").contiguous()
+        w = torch.as_tensor(lnw, device="cuda").contiguous()
+        ll = torch.empty(n, dtype=torch.float64, device="cuda")
+        z, ne = plan.lnZ_tmarg(tht, t_start, h, n_t, lnw=w, lnL_out=ll)
+        _compare(ll.cpu().numpy(), want, _bar(oracle_mod, pt, th, t_start, h, n_t), (case, n_t))
+        assert abs(z.item() - z_or) <= 1e-9 * max(1.0, abs(z_or)), (z.item(), z_or)
+        assert abs(ne.item() - ne_or) <= 1e-9 * ne_or
+        plan.close()
+
+
+def test_tmarg_launch_forms_binning_and_time_row(ile, oracle_mod):
+    import torch
+
+    pts = synth.batched_points(3, 31, K=3, nt_range=(400, 6554))
+    counts = [1500, 1, 700]
+    th = np.concatenate([synth.prior_samples(c, 900 + i) for i, c in enumerate(counts)], axis=1)
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    plan = ile.Plan(pts, counts)
+    res = []
+    for cfg in (dict(block=256, tile_blocks=4, blocks_per_cu=0, sort=0), dict(block=128, tile_blocks=2, blocks_per_cu=4, sort=1),
+                dict(block=64, tile_blocks=1, blocks_per_cu=0, sort=0)):
+        plan.config = cfg
+        ll = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
+        z, ne = plan.lnZ_tmarg(tht, -0.005, 0.0005, 21, lnL_out=ll)
+        res.append((ll.clone(), z.clone(), ne.clone()))
+    for r in res[1:]:
+        assert torch.equal(r[0], res[0][0]) and torch.equal(r[1], res[0][1]) and torch.equal(r[2], res[0][2])
+    th2 = th.copy()
+    th2[5] = np.random.default_rng(2).uniform(-1, 1, th.shape[1])
+    ll2 = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
+    plan.lnZ_tmarg(torch.as_tensor(th2, device="cuda").contiguous(), -0.005, 0.0005, 21, lnL_out=ll2)
+    assert torch.equal(ll2, res[2][0])
+    s = 0
+    for p, c in enumerate(counts):
+        want = oracle_mod.lnL_tmarg(pts[p], th[:, s:s + c], -0.005, 0.0005, 21)
+        _compare(res[0][0][s:s + c].cpu().numpy(), want, _bar(oracle_mod, pts[p], th[:, s:s + c], -0.005, 0.0005, 21), p)
+        s += c
+    plan.close()
+
+
+def test_tmarg_edges_and_rules(ile, oracle_mod):
+    import torch
+
+    pt, th = _point(CASES[2])
+    th = th[:, :300].copy()
+    th[0, 3] = np.nan
+    th[6, 4] = np.inf  # x = 0: no signal term, finite
+    th[2, 5] = np.inf
+    plan = ile.Plan([pt], [th.shape[1]])
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    ll = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
+    plan.lnZ_tmarg(tht, -0.004, 0.0002, 41, lnL_out=ll)
+    got = ll.cpu().numpy()
+    want = oracle_mod.lnL_tmarg(pt, th, -0.004, 0.0002, 41)
+    assert np.isnan(got[3]) and np.isnan(got[5])
+    _compare(got, want, _bar(oracle_mod, pt, th, -0.004, 0.0002, 41), "edges")
+    for t_start, h, n_t in ((0.0, 1e-4, 2), (0.0, 1e-4, 4), (0.0, 0.0, 5), (0.0, -1e-4, 5), (float("nan"), 1e-4, 5),
+                            (0.0, 1e-4, 1000003)):
+        with pytest.raises(RuntimeError):
+            plan.lnZ_tmarg(tht, t_start, h, n_t)
+    plan.close()
+
+
+def test_tmarg_full_size_sampled(ile, oracle_mod):
+    """The headline batch (3 detectors, 21 modes, SNR 600, 1e6 samples) on a
+    41-time rule over the prior's 20 ms: sampled values one by one."""
+    import torch
+
+    pt = synth.make_point(3, 21, 6554, 32768.0, 600.0, 2)
+    th = synth.prior_samples(1_000_000, 2)
+    plan = ile.Plan([pt], [th.shape[1]])
+    ll = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
+    z, _ = plan.lnZ_tmarg(torch.as_tensor(th, device="cuda").contiguous(), -0.01, 0.0005, 41, lnL_out=ll)
+    ll = ll.cpu().numpy()
+    plan.close()
+    idx = np.random.default_rng(8).choice(th.shape[1], 1500, replace=False)
+    want = oracle_mod.lnL_tmarg(pt, th[:, idx], -0.01, 0.0005, 41)
+    _compare(ll[idx], want, _bar(oracle_mod, pt, th[:, idx], -0.01, 0.0005, 41), "c2 sampled")
+    assert np.isfinite(z.item())
