@@ -8,9 +8,10 @@ the two share no code.
 The arithmetic lives in ``oracle.cpp`` (plain loops, IEEE double, OpenMP over
 samples); this module only marshals numpy arrays into it.  ``pregrid`` (the
 Fourier refinement of Eq. (q-time-pregrid)), ``lnL_dmarg`` (the adaptive
-Gauss-Hermite marginal over distance, Eq. (ap:dgh)) and ``lnL_tmarg`` (the
-fixed-spacing rule over time, Eq. (ap:tfixed)) are written here in numpy
-on top of the C likelihood.
+Gauss-Hermite marginal over distance, Eq. (ap:dgh)), ``lnL_tmarg`` (the
+fixed-spacing rule over time, Eq. (ap:tfixed)) and ``lnL_pmarg`` (the
+polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)) are written here in
+numpy on top of the C likelihood.
 
 Every function states the passage of the paper it follows.  Parity status of
 each function (what pins it) is listed in the tests' docstrings.
@@ -343,6 +344,72 @@ def lnL_tmarg(pt, theta, t_start, h, n_t, nthreads: int = 0):
     ok = np.isfinite(m)
     out[ok] = m[ok] + np.log(np.sum(np.exp(l[ok] - m[ok, None]), axis=1)) - np.log(n_t - 1.0)
     out[np.isnan(l).any(axis=1)] = np.nan
+    return out
+
+
+def lnL_psi_grid(pt, theta, u, nthreads: int = 0):
+    """lnL [n, len(u)] at polarisation psi + u / 2 for every sample (the
+    oracle's own lnL at each angle)."""
+    th = _c(theta, np.float64)
+    n = th.shape[1]
+    u = np.asarray(u, np.float64)
+    big = np.repeat(th, u.size, axis=1)
+    big[2] = big[2] + np.tile(u / 2.0, n)
+    return lnL(pt, big, nthreads).reshape(n, u.size)
+
+
+def psi_coefficients(pt, theta, nthreads: int = 0):
+    """(a, c1, c2) per sample of lnL as a function of u = 2 (psi' - psi),
+    q(u) = a + Re(c1 e^{iu}) + Re(c2 e^{2iu}) (Eq. (ap:psiexp)): the exact
+    five-point transform of lnL at u_j = 2 pi j / 5 (the polarisation series
+    ends at 4 psi, so five points determine it)."""
+    uj = 2.0 * np.pi * np.arange(5) / 5.0
+    q = lnL_psi_grid(pt, theta, uj, nthreads)
+    ch = q @ np.exp(-1j * np.outer(uj, np.arange(3))) / 5.0  # c^_0, c^_1, c^_2
+    return ch[:, 0].real, 2.0 * ch[:, 1], 2.0 * ch[:, 2]
+
+
+def lnL_pmarg(pt, theta, method="trapezoid", n_points=64, nthreads: int = 0):
+    """ln of the likelihood marginalised over polarisation per sample, psi
+    uniform on [0, pi) (u = 2 psi uniform on the circle):
+      trapezoid: ln[(1/n) sum_j e^{lnL(psi + pi j / n)}], the oracle's lnL at
+        each of the n angles (the periodic trapezoid rule);
+      laplace: Eq. (ap:psilaplace) at the dominant maximum of q(u) from
+        psi_coefficients: ln L = q(u*) - ln(2 pi A) / 2 with A = -q''(u*),
+        u* the best of 32 equally spaced points refined by Newton's method on
+        q' = 0; a flat q gives a."""
+    if method == "trapezoid":
+        n = int(n_points)
+        l = lnL_psi_grid(pt, theta, 2.0 * np.pi * np.arange(n) / n, nthreads)
+        m = np.max(l, axis=1)
+        out = np.full(l.shape[0], np.nan)
+        ok = np.isfinite(m)
+        out[ok] = m[ok] + np.log(np.sum(np.exp(l[ok] - m[ok, None]), axis=1)) - np.log(n)
+        out[np.isnan(l).any(axis=1)] = np.nan
+        return out
+    a, c1, c2 = psi_coefficients(pt, theta, nthreads)
+    out = np.empty(a.shape[0])
+    for i in range(a.shape[0]):
+        if not (np.isfinite(a[i]) and np.isfinite(c1[i]) and np.isfinite(c2[i])):
+            out[i] = np.nan
+            continue
+
+        def q(u):
+            e1 = np.exp(1j * u)
+            return (a[i] + (c1[i] * e1).real + (c2[i] * e1 * e1).real,
+                    -(c1[i] * e1).imag - 2.0 * (c2[i] * e1 * e1).imag,
+                    -(c1[i] * e1).real - 4.0 * (c2[i] * e1 * e1).real)
+
+        grid = np.pi * np.arange(32) / 16.0
+        u = grid[int(np.argmax([q(g)[0] for g in grid]))]
+        for _ in range(8):
+            v, d1, d2 = q(u)
+            if not d2 < 0.0:
+                break
+            u -= d1 / d2
+        v, d1, d2 = q(u)
+        A = -d2
+        out[i] = v - 0.5 * np.log(2.0 * np.pi * A) if A > 0.0 else a[i]
     return out
 
 
