@@ -377,7 +377,9 @@ def lnL_pmarg(pt, theta, method="trapezoid", n_points=64, nthreads: int = 0):
       laplace: Eq. (ap:psilaplace) at the dominant maximum of q(u) from
         psi_coefficients: ln L = q(u*) - ln(2 pi A) / 2 with A = -q''(u*),
         u* the best of 32 equally spaced points refined by Newton's method on
-        q' = 0; a flat q gives a."""
+        q' = 0, where A >= 100 (the method's relative error O(1/A) is then
+        below ~1e-3); otherwise (weak signal, or two maxima merging) the
+        periodic trapezoid rule on 256 points of the same q."""
     if method == "trapezoid":
         n = int(n_points)
         l = lnL_psi_grid(pt, theta, 2.0 * np.pi * np.arange(n) / n, nthreads)
@@ -409,7 +411,12 @@ def lnL_pmarg(pt, theta, method="trapezoid", n_points=64, nthreads: int = 0):
             u -= d1 / d2
         v, d1, d2 = q(u)
         A = -d2
-        out[i] = v - 0.5 * np.log(2.0 * np.pi * A) if A > 0.0 else a[i]
+        if A >= 100.0:
+            out[i] = v - 0.5 * np.log(2.0 * np.pi * A)
+        else:
+            vals = np.array([q(g)[0] for g in 2.0 * np.pi * np.arange(256) / 256.0])
+            mv = vals.max()
+            out[i] = mv + np.log(np.mean(np.exp(vals - mv)))
     return out
 
 
