@@ -704,15 +704,53 @@ def extra_tmarg(ile, synth, torch, steps, cpu=True):
     return res
 
 
+def extra_pmarg(ile, synth, torch, steps, cpu=True):
+    """The headline point (3 detectors, 21 modes, SNR 600, 1e6 prior
+    samples) marginalised over polarisation in the kernel: the periodic
+    trapezoid rule on 64 points of q(u) (Eq. (ap:psiexp)) and Laplace's method
+    (Eq. (ap:psilaplace)); each against the FP64 oracle on a sample."""
+    pt, th = c2_inputs(synth, 1_000_000)
+    n = th.shape[1]
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    plan = ile.Plan([pt], [n])
+    z = torch.empty(1, dtype=torch.float64, device="cuda")
+    ll = torch.empty(n, dtype=torch.float64, device="cuda")
+    res = {"workload": "3 detectors, 21 modes (l<=4), Q 6554 samples at 32768 Hz, SNR 600, 1e6 prior samples; "
+                       "lnL marginalised over polarisation"}
+    idx = np.random.default_rng(3).choice(n, 300, replace=False)
+    for method, npts in (("trapezoid", 64), ("laplace", 0)):
+        def step():
+            plan.lnZ_pmarg(tht, method, npts, lnZ_out=z, lnL_out=ll)
+
+        step()
+        secs, _ = time_steps(step, max(3, steps // 2), 1, torch)
+        per = secs / max(3, steps // 2)
+        plan.profile(True)
+        step()
+        kms, nl = plan.profile_read()
+        plan.profile(False)
+        r = {"lnLp_evals_per_s": n / per, "ms_per_step": 1e3 * per, "kernel_ms": kms / max(1, nl), "lnZp": z.item()}
+        if cpu:
+            import oracle
+
+            t0 = time.perf_counter()
+            want = oracle.lnL_pmarg(pt, th[:, idx], method, npts)
+            r["cpu_oracle_lnLp_evals_per_s"] = idx.size / (time.perf_counter() - t0)
+            r["max_abs_dlnLp_vs_oracle_sampled"] = float(np.nanmax(np.abs(ll.cpu().numpy()[idx] - want)))
+        res[method if method == "laplace" else f"trapezoid{npts}"] = r
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg",
+    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,pmarg",
                     help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, pregrid, "
-                         "tmarg, "
+                         "tmarg, pmarg, "
                          "c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
@@ -836,7 +874,7 @@ def main():
     wanted += [x.strip() for x in args.extras.split(",") if x.strip()]
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
            "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg, "pregrid": extra_pregrid,
-           "tmarg": extra_tmarg}
+           "tmarg": extra_tmarg, "pmarg": extra_pmarg}
     for name in wanted:
         log(f"workload {name}")
         try:

@@ -336,6 +336,33 @@ int rift_ile_plan_lnZ_tmarg(rift_ile_plan plan, const double *theta, const doubl
                             const rift_ile_time_rule *rule, double *lnZ, double *neff, double *lnLt,
                             void *stream);
 
+/* Direct marginalisation over polarisation (Sec. "Angles: finite harmonic
+ * content"): at fixed other parameters the complex antenna factor carries
+ * e^{-2 i psi}, so lnL is exactly q(u) = a + Re(c1 e^{iu}) + Re(c2 e^{2iu})
+ * in u = 2 psi (Eq. (ap:psiexp)), with c1 from the data term and a, c2 from the
+ * model norm, all from one gather and one contraction per sample.  With psi
+ * uniform on [0, pi):
+ *   RIFT_PSI_TRAPEZOID: L_psi = (1/n) sum_j e^{q(2 pi j / n)}, the periodic
+ *     trapezoid rule on n points (the product grid; exact as n grows);
+ *   RIFT_PSI_LAPLACE:   L_psi = e^{q(u*)} sqrt(2 pi / A) / (2 pi) at the dominant
+ *     maximum u* with A = -q''(u*) (Eq. (ap:psilaplace); relative error O(1/A)),
+ *     where A >= 100; a q without such a maximum (weak signal, or two maxima
+ *     merging) is integrated by the trapezoid rule on 256 points instead. */
+#define RIFT_PSI_TRAPEZOID 0
+#define RIFT_PSI_LAPLACE 1
+typedef struct {
+  int32_t method;   /* RIFT_PSI_TRAPEZOID or RIFT_PSI_LAPLACE */
+  int32_t n_points; /* trapezoid: 1 .. 65536 points on the circle; ignored by Laplace */
+} rift_ile_psi_rule;
+
+/* ln L_psi per sample (lnLp: DEVICE [N] or NULL) and, per point, ln Z_psi and
+ * n_eff over the plan's batch, as rift_ile_plan_lnZ_dmarg; theta's psi row
+ * only sets where the rule's points start (the integral covers the whole
+ * period).  FP64; enqueues and returns (capturable); RIFT_EINVAL for a bad
+ * rule. */
+int rift_ile_plan_lnZ_pmarg(rift_ile_plan plan, const double *theta, const double *lnw,
+                            const rift_ile_psi_rule *rule, double *lnZ, double *neff, double *lnLp, void *stream);
+
 /* The n-point Gauss-Hermite rule of the weight e^{-x^2/2} (1 <= n <= 64) that
  * the distance marginal uses: HOST nodes[n] ascending and weights[n]. */
 int rift_ile_gauss_hermite(int n, double *nodes, double *weights);

@@ -440,11 +440,15 @@ __host__ __device__ constexpr int det_group_start(int KT, int j) {
 // Units (group p, detector g) are streamed with g fastest through the
 // wavefront's two LDS buffers: unit u+1 is in flight while unit u is
 // combined.  Requires the whole wavefront to be active.
-template <class R, int NY, int K0, int G>
+//
+// With CPLX, the imaginary part Im sum_k conj(F_k) Z_k is added to *acc_im as
+// well (the complex data term whose real part is returned).
+template <class R, int NY, int K0, int G, bool CPLX = false>
 __device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb, uint64_t gstride,
                                              uint64_t kstride, int M, int NGR, const uint32_t* boff,
                                              RIFT_LDS unsigned char* stage, const R* sfr, const R* Fre,
-                                             const R* Fim, const R* cn, const R* sn, R cf, R sf) {
+                                             const R* Fim, const R* cn, const R* sn, R cf, R sf,
+                                             double* acc_im = nullptr) {
   static_assert(G >= 2 && G <= 3, "detector groups of two or three");
   constexpr int W = Tab<R>::W;
   static_assert(4 * W * sizeof(C2<R>) == 128, "128-byte stencil blocks");
@@ -558,6 +562,12 @@ __device__ __forceinline__ double data_group(PDesc P, const RIFT_GLOBAL char* Qb
 #pragma unroll
   for (int g = 0; g < G; ++g)
     acc += (double)(Fre[K0 + g] * Z[g].x) + (double)(Fim[K0 + g] * Z[g].y);
+  if constexpr (CPLX) {
+    double ai = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) ai += (double)(Fre[K0 + g] * Z[g].y) - (double)(Fim[K0 + g] * Z[g].x);
+    *acc_im += ai;
+  }
   return acc;
 }
 
@@ -568,10 +578,10 @@ struct Eval {
 };
 
 // Data term of one sample with its taps read straight from the table.
-template <class R, int KT, int L>
+template <class R, int KT, int L, bool CPLX = false>
 __device__ __forceinline__ double data_direct(PDesc P, RIFT_LDS unsigned char* stage, const int32_t* row,
                                               const R* sfr, const R* Fre, const R* Fim, const R* cn,
-                                              const R* sn, R cf, R sf) {
+                                              const R* sn, R cf, R sf, double* im = nullptr) {
   static_assert(KT >= 2, "detector counts are padded to at least two");
   constexpr int NY = Cls<L>::NY;
   constexpr int W = Tab<R>::W;
@@ -584,14 +594,14 @@ __device__ __forceinline__ double data_direct(PDesc P, RIFT_LDS unsigned char* s
   const uint64_t gstride = (uint64_t)(P->n_t + 2 * QPAD) * (W * sizeof(C2<R>));
   const uint64_t kstride = (uint64_t)NGR * gstride;
   constexpr int G0 = det_group_size(KT, 0), G1 = det_group_size(KT, 1), G2 = det_group_size(KT, 2);
-  double data =
-      data_group<R, NY, 0, G0>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr, Fre, Fim, cn, sn, cf, sf);
+  double data = data_group<R, NY, 0, G0, CPLX>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr, Fre, Fim, cn,
+                                               sn, cf, sf, im);
   if constexpr (G1 > 0)
-    data += data_group<R, NY, det_group_start(KT, 1), G1>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr,
-                                                          Fre, Fim, cn, sn, cf, sf);
+    data += data_group<R, NY, det_group_start(KT, 1), G1, CPLX>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr,
+                                                                Fre, Fim, cn, sn, cf, sf, im);
   if constexpr (G2 > 0)
-    data += data_group<R, NY, det_group_start(KT, 2), G2>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr,
-                                                          Fre, Fim, cn, sn, cf, sf);
+    data += data_group<R, NY, det_group_start(KT, 2), G2, CPLX>(P, Qb, gstride, kstride, M, NGR, boff, stage, sfr,
+                                                                Fre, Fim, cn, sn, cf, sf, im);
   return data;
 }
 
@@ -675,12 +685,11 @@ __device__ __forceinline__ void reduce_angles(double& psi, double& incl, double&
 // block-shared scratch array (stride `ts` elements) that receives
 // cos(n incl), n = 0..NI, then sin(n incl), for the runtime contraction loop
 // of the l <= 8 class.
-template <class R, int KT, int L, bool BOUND>
-__device__ __forceinline__ double quad_term(PDesc P, R* __restrict__ trig, int ts, R ci, R si, R cf, R sf,
-                                            const R* Fre, const R* Fim, double* wq_out) {
+template <class R, int KT, int L>
+__device__ __forceinline__ void norm_contract(PDesc P, R* __restrict__ trig, int ts, R ci, R si, R cf, R sf,
+                                              R* acc) {
   typedef Cls<L> CL;
   constexpr int NI = CL::NI;
-  R acc[3 * KT];
 #pragma unroll
   for (int c = 0; c < 3 * KT; ++c) acc[c] = 0;
   if constexpr (L <= 4) {
@@ -765,6 +774,13 @@ __device__ __forceinline__ double quad_term(PDesc P, R* __restrict__ trig, int t
       }
     }
   }
+}
+
+template <class R, int KT, int L, bool BOUND>
+__device__ __forceinline__ double quad_term(PDesc P, R* __restrict__ trig, int ts, R ci, R si, R cf, R sf,
+                                            const R* Fre, const R* Fim, double* wq_out) {
+  R acc[3 * KT];
+  norm_contract<R, KT, L>(P, trig, ts, ci, si, cf, sf, acc);
   double quad = 0.0;
   double wq = 0.0;  // model-norm part of the error bound (see PointDesc)
 #pragma unroll
@@ -922,6 +938,132 @@ __device__ __forceinline__ double eval_tmarg_with(PDesc P, R* __restrict__ trig,
   return m + log(sum) + T.ln_scale;
 }
 
+// The rule over polarisation (Sec. "Angles: finite harmonic content"): at
+// fixed other parameters lnL is q(u) = a + Re(c1 e^{iu}) + Re(c2 e^{2iu}) in
+// u = 2 (psi' - psi) (Eq. (ap:psiexp)); with psi uniform on [0, pi),
+// L_psi = (1 / 2 pi) int_0^{2 pi} e^{q(u)} du by
+//   method 0: the periodic trapezoid rule on n points (the product grid),
+//   method 1: Laplace's method at the dominant maximum u* (Eq. (ap:psilaplace)),
+//             L_psi = e^{q(u*)} sqrt(2 pi / A) / (2 pi), A = -q''(u*), where
+//             A >= 100 (relative error O(1/A) below ~1e-3); a q without
+//             such a maximum (weak signal, or two peaks merging) is
+//             integrated by the periodic trapezoid rule on 256 points.
+constexpr double PSI_LAPLACE_MIN_A = 100.0;
+constexpr int PSI_FALLBACK_POINTS = 256;
+struct PsiRule {
+  int32_t method;
+  int32_t n;
+  double ln_n;
+};
+
+// q(u) and its first two derivatives.
+__device__ __forceinline__ void psi_q(double a, double c1r, double c1i, double c2r, double c2i, double su, double cu,
+                                      double* q, double* d1, double* d2) {
+  const double s2 = 2.0 * su * cu, c2 = cu * cu - su * su;
+  const double r1 = c1r * cu - c1i * su, i1 = c1r * su + c1i * cu;  // c1 e^{iu}
+  const double r2 = c2r * c2 - c2i * s2, i2 = c2r * s2 + c2i * c2;  // c2 e^{2iu}
+  *q = a + r1 + r2;
+  *d1 = -i1 - 2.0 * i2;
+  *d2 = -r1 - 4.0 * r2;
+}
+
+// The periodic trapezoid rule for q on n points: ln[(1/n) sum_j e^{q(2 pi j/n)}].
+__device__ __forceinline__ double psi_trapezoid(int n, double ln_n, double a, double c1r, double c1i, double c2r,
+                                                double c2i) {
+  double q, d1, d2;
+  double m = -__builtin_inf(), sum = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double su, cu;
+    sincospi(2.0 * (double)j / (double)n, &su, &cu);
+    psi_q(a, c1r, c1i, c2r, c2i, su, cu, &q, &d1, &d2);
+    if (q > m) {
+      sum = (sum == 0.0) ? 1.0 : fma(sum, exp(m - q), 1.0);
+      m = q;
+    } else {
+      sum += exp(q - m);
+    }
+  }
+  return m + log(sum) - ln_n;
+}
+
+// ln L_psi from the coefficients of q (see PsiRule).  Laplace: the best of 32
+// equally spaced points, then Newton steps on q' = 0 (the maximum is then the
+// dominant one unless another lies within the grid's resolution of it).
+__device__ __forceinline__ double psi_marginal(const PsiRule& G, double a, double c1r, double c1i, double c2r,
+                                               double c2i) {
+  double q, d1, d2;
+  if (G.method == 0) return psi_trapezoid(G.n, G.ln_n, a, c1r, c1i, c2r, c2i);
+  double best = -__builtin_inf(), ub = 0.0;
+  for (int j = 0; j < 32; ++j) {
+    double su, cu;
+    sincospi((double)j / 16.0, &su, &cu);
+    psi_q(a, c1r, c1i, c2r, c2i, su, cu, &q, &d1, &d2);
+    if (q > best) {
+      best = q;
+      ub = 3.14159265358979323846 * (double)j / 16.0;
+    }
+  }
+  double u = ub;
+  for (int it = 0; it < 8; ++it) {
+    double su, cu;
+    sincos(u, &su, &cu);
+    psi_q(a, c1r, c1i, c2r, c2i, su, cu, &q, &d1, &d2);
+    if (!(d2 < 0.0)) break;
+    u -= d1 / d2;
+  }
+  double su, cu;
+  sincos(u, &su, &cu);
+  psi_q(a, c1r, c1i, c2r, c2i, su, cu, &q, &d1, &d2);
+  const double A = -d2;
+  if (!(A >= PSI_LAPLACE_MIN_A))
+    return psi_trapezoid(PSI_FALLBACK_POINTS, 5.5451774444795623, a, c1r, c1i, c2r, c2i);  // ln 256
+  return q - 0.5 * log(2.0 * 3.14159265358979323846 * A);
+}
+
+// ln of the likelihood marginalised over polarisation, per sample: the data
+// term as the complex W = sum_k conj(F_k) Z_k (one gather), the model-norm
+// term as A0 = sum_k |F_k|^2 a_k / 4 and B = sum_k F_k^2 b_k / 4 (one
+// contraction), then, with F_k(psi + u/2) = e^{-iu} F_k(psi),
+//   q(u) = x Re(e^{iu} W) - x^2 [A0 + Re(e^{-2iu} B)]:
+//   a = -x^2 A0, c1 = x W, c2 = -x^2 conj(B).
+template <class R, int KT, int L, class DataFn>
+__device__ __forceinline__ double eval_pmarg_with(PDesc P, R* __restrict__ trig, int ts, double ra, double dec,
+                                                  double psi, double incl, double phi, double tref, double dist,
+                                                  const PsiRule& G, DataFn&& data_fn) {
+  constexpr int NY = Cls<L>::NY;
+  reduce_angles<R>(psi, incl, phi);
+  Sky<R, KT> S;
+  sky_eval<R, KT, true>(P, ra, dec, psi, tref, S);
+  R si, ci;
+  sincos_((R)incl, &si, &ci);
+  R cn[NY], sn[NY];
+  incl_harmonics<R, NY>(ci, si, cn, sn);
+  R sf, cf;
+  sincos_((R)phi, &sf, &cf);
+  double wim = 0.0;
+  __builtin_amdgcn_s_setprio(1);
+  const double wre = data_fn(S.row, S.sfr, S.Fre, S.Fim, cn, sn, cf, sf, &wim);
+  __builtin_amdgcn_s_setprio(0);
+  R acc[3 * KT];
+  norm_contract<R, KT, L>(P, trig, ts, ci, si, cf, sf, acc);
+  double A0 = 0.0, Bre = 0.0, Bim = 0.0;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const R f2 = S.Fre[k] * S.Fre[k] + S.Fim[k] * S.Fim[k];
+    const R g2r = S.Fre[k] * S.Fre[k] - S.Fim[k] * S.Fim[k];
+    const R g2i = 2 * S.Fre[k] * S.Fim[k];
+    A0 += (double)(f2 * acc[3 * k]);
+    Bre += (double)(g2r * acc[3 * k + 1]) + (double)(g2i * acc[3 * k + 2]);
+    Bim += (double)(g2i * acc[3 * k + 1]) - (double)(g2r * acc[3 * k + 2]);
+  }
+  const double x = P->d_ref / dist;
+  if (S.bad || !(fabs(x) <= 1.0e300) || !(fabs(wre) <= 1.0e300) || !(fabs(wim) <= 1.0e300) ||
+      !(fabs(A0) <= 1.0e300) || !(fabs(Bre) + fabs(Bim) <= 1.0e300))
+    return __builtin_nan("");
+  const double x2 = x * x;
+  return psi_marginal(G, -x2 * A0, x * wre, x * wim, -x2 * Bre, x2 * Bim);
+}
+
 // Everything per sample up to the distance: the terms.  R is the arithmetic
 // type of the bulk (FP64 or FP32); the sky frame, delays and the final
 // combination are always FP64.  The data term comes from
@@ -969,6 +1111,15 @@ __device__ __forceinline__ Terms eval_terms(PDesc P, R* __restrict__ trig, int t
       P, trig, ts, ra, dec, psi, incl, phi, tref,
       [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
           R sf) { return data_direct<R, KT, L>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf); });
+}
+template <class R, int KT, int L>
+__device__ __forceinline__ double eval_pmarg(PDesc P, R* __restrict__ trig, int ts, RIFT_LDS unsigned char* stage,
+                                            double ra, double dec, double psi, double incl, double phi, double tref,
+                                            double dist, const PsiRule& G) {
+  return eval_pmarg_with<R, KT, L>(
+      P, trig, ts, ra, dec, psi, incl, phi, tref, dist, G,
+      [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf, R sf,
+          double* im) { return data_direct<R, KT, L, true>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf, im); });
 }
 template <class R, int KT, int L>
 __device__ __forceinline__ double eval_tmarg(PDesc P, R* __restrict__ trig, int ts, RIFT_LDS unsigned char* stage,

@@ -16,7 +16,9 @@ namespace rift {
 // distance (Eq. (ap:dgh)) in place of lnL, and its tile (max, sum);
 // MODE_TMARG64: FP64, the likelihood marginalised over geocentric time by the
 // fixed-spacing rule (Eq. (ap:tfixed)) in place of lnL, and its tile pair.
-enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1, MODE_DMARG64 = 2, MODE_TMARG64 = 3 };
+// MODE_PMARG64: FP64, the likelihood marginalised over polarisation
+// (Eqs. (ap:psiexp), (ap:psilaplace)) in place of lnL, and its tile pair.
+enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1, MODE_DMARG64 = 2, MODE_TMARG64 = 3, MODE_PMARG64 = 4 };
 
 struct TileArgs {
   const PointDesc* descs;
@@ -40,6 +42,7 @@ struct TileArgs {
   const double* theta_aos;
   DistRule dm;  // MODE_DMARG64: the distance rule and prior
   TimeRule tm;  // MODE_TMARG64: the time rule
+  PsiRule pm;   // MODE_PMARG64: the polarisation rule
 };
 
 // One tile: every sample's lnL (and bound), then a block reduction.
@@ -77,6 +80,9 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
       } else if constexpr (MODE == MODE_TMARG64) {
         e.lnL = eval_tmarg<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3], th[4], th[6],
                                      a.tm);
+      } else if constexpr (MODE == MODE_PMARG64) {
+        e.lnL = eval_pmarg<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3], th[4], th[5],
+                                     th[6], a.pm);
       } else {
         e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2],
                                                        th[3], th[4], th[5], th[6]);
@@ -102,6 +108,9 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
     } else if constexpr (MODE == MODE_TMARG64) {
       e.lnL = eval_tmarg<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N], th[3 * N],
                                    th[4 * N], th[6 * N], a.tm);
+    } else if constexpr (MODE == MODE_PMARG64) {
+      e.lnL = eval_pmarg<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N], th[3 * N],
+                                   th[4 * N], th[5 * N], th[6 * N], a.pm);
     } else {
       e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0], th[N],
                                                      th[2 * N], th[3 * N], th[4 * N], th[5 * N], th[6 * N]);
@@ -454,6 +463,7 @@ typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, doubl
   tile_fn get_tiles32_kt##KT(int lset);              \
   tile_fn get_tilesdm_kt##KT(int lset);              \
   tile_fn get_tilestm_kt##KT(int lset);              \
+  tile_fn get_tilespm_kt##KT(int lset);              \
   refine_fn get_refine_kt##KT(int lset);             \
   grad_fn get_grad_kt##KT(int L);                   \
   grad_fn get_gradw_kt##KT(int L);

@@ -1,7 +1,8 @@
 // Instances of the evaluation kernels for one detector class RIFT_KT and one
 // kernel kind RIFT_KIND (0: FP64 tiles, 1: FP32 tiles, 2: FP64 refine,
 // 3: gradient, a lane or a group of lanes per sample, 4: FP64 tiles of the
-// distance marginal, 5: FP64 tiles of the time marginal).  The build compiles
+// distance marginal, 5: FP64 tiles of the time marginal, 6: FP64 tiles of
+// the polarisation marginal).  The build compiles
 // this file once per (class, kind) so the instances build in parallel.
 #include "ile_kernels.h"
 
@@ -15,7 +16,7 @@
 namespace rift {
 
 // Mode-class sets: 1 (l<=2), 2 (l=3), 4 (l=4), 8 (l<=8), 7 (l<=4 mixed).
-#if RIFT_KIND == 0 || RIFT_KIND == 1 || RIFT_KIND == 4 || RIFT_KIND == 5
+#if RIFT_KIND == 0 || RIFT_KIND == 1 || RIFT_KIND == 4 || RIFT_KIND == 5 || RIFT_KIND == 6
 #if RIFT_KIND == 0
 #define RIFT_R double
 #define RIFT_MODE MODE_LSE64
@@ -28,6 +29,10 @@ namespace rift {
 #define RIFT_R double
 #define RIFT_MODE MODE_TMARG64
 #define RIFT_NAME RIFT_CAT(get_tilestm_kt, RIFT_KT)
+#elif RIFT_KIND == 6
+#define RIFT_R double
+#define RIFT_MODE MODE_PMARG64
+#define RIFT_NAME RIFT_CAT(get_tilespm_kt, RIFT_KT)
 #else
 #define RIFT_R float
 #define RIFT_MODE MODE_PASS32

@@ -914,6 +914,8 @@ struct rift_ile_plan_s {
   DistRule dm{};
   // time marginal: the rule of the last rift_ile_plan_lnZ_tmarg call
   TimeRule tm{};
+  // polarisation marginal: the rule of the last rift_ile_plan_lnZ_pmarg call
+  PsiRule pm{};
 };
 
 namespace {
@@ -998,7 +1000,8 @@ tile_fn pick_tiles_kt(int mode, int KT, int lset) {
     case MODE_LSE64: return get_tiles64_kt##K(lset); \
     case MODE_PASS32: return get_tiles32_kt##K(lset); \
     case MODE_DMARG64: return get_tilesdm_kt##K(lset); \
-    default: return get_tilestm_kt##K(lset);         \
+    case MODE_TMARG64: return get_tilestm_kt##K(lset); \
+    default: return get_tilespm_kt##K(lset);         \
   }
   switch (KT) {
     case 2: RIFT_PICK(2)
@@ -1068,6 +1071,7 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.theta_aos = p->cfg.sort ? p->d_aos : nullptr;
   a.dm = p->dm;
   a.tm = p->tm;
+  a.pm = p->pm;
   const size_t rsz = (mode == MODE_PASS32 ? sizeof(float) : sizeof(double));
   const size_t shm = eval_lds_bytes(p->lset, p->cfg.block, rsz);
   if (shm + 1024 > (size_t)p->di.max_lds) return RIFT_EUNSUPPORTED;
@@ -1669,6 +1673,35 @@ int rift_ile_plan_lnZ_tmarg(rift_ile_plan p, const double* theta, const double* 
   if (sorted && (!p->bin_ready || !L)) return RIFT_EUNSUPPORTED;
   if (sorted && (rc = run_binning(p, theta, st))) return rc;
   if ((rc = launch_tiles(p, MODE_TMARG64, theta, lnw, sorted ? L : lnLt, st))) return rc;
+  if (sorted)
+    hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L, lnw,
+                       p->d_part);
+  hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
+                     (const double*)nullptr, lnZ, neff, (double*)nullptr);
+  HCHK(hipGetLastError());
+  return RIFT_OK;
+}
+
+int rift_ile_plan_lnZ_pmarg(rift_ile_plan p, const double* theta, const double* lnw, const rift_ile_psi_rule* rule,
+                            double* lnZ, double* neff, double* lnLp, void* stream) {
+  if (!p || !rule || check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  if ((lnw && check_dev_ptr(lnw)) || (neff && check_dev_ptr(neff)) || (lnLp && check_dev_ptr(lnLp)))
+    return RIFT_EINVAL;
+  if (rule->method != RIFT_PSI_TRAPEZOID && rule->method != RIFT_PSI_LAPLACE) return RIFT_EINVAL;
+  if (rule->method == RIFT_PSI_TRAPEZOID && (rule->n_points < 1 || rule->n_points > 65536)) return RIFT_EINVAL;
+  PsiRule g{};
+  g.method = rule->method == RIFT_PSI_TRAPEZOID ? 0 : 1;
+  g.n = rule->method == RIFT_PSI_TRAPEZOID ? rule->n_points : 0;
+  g.ln_n = g.n > 0 ? log((double)g.n) : 0.0;
+  p->pm = g;
+  hipStream_t st = (hipStream_t)stream;
+  p->last = st;
+  int rc;
+  const bool sorted = p->cfg.sort != 0;
+  double* L = lnLp ? lnLp : p->d_L;
+  if (sorted && (!p->bin_ready || !L)) return RIFT_EUNSUPPORTED;
+  if (sorted && (rc = run_binning(p, theta, st))) return rc;
+  if ((rc = launch_tiles(p, MODE_PMARG64, theta, lnw, sorted ? L : lnLp, st))) return rc;
   if (sorted)
     hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L, lnw,
                        p->d_part);

@@ -64,6 +64,7 @@ EXPORTS = (
     "rift_ile_gauss_hermite",
     "rift_ile_pregrid",
     "rift_ile_plan_lnZ_tmarg",
+    "rift_ile_plan_lnZ_pmarg",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -117,6 +118,13 @@ class CTimeRule(ctypes.Structure):
     _fields_ = [("t_start", ctypes.c_double), ("h", ctypes.c_double), ("n_t", ctypes.c_int32)]
 
 
+class CPsiRule(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("n_points", ctypes.c_int32)]
+
+
+PSI_METHODS = {"trapezoid": 0, "laplace": 1}
+
+
 class CConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile_blocks", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("sort", ctypes.c_int32)]
@@ -158,6 +166,7 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_gauss_hermite.argtypes = [ctypes.c_int, vp, vp]
     lib.rift_ile_pregrid.argtypes = [vp, i64, i32, i32, vp, vp]
     lib.rift_ile_plan_lnZ_tmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CTimeRule), vp, vp, vp, vp]
+    lib.rift_ile_plan_lnZ_pmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CPsiRule), vp, vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
     lib.rift_ile_strerror.restype = ctypes.c_char_p
     lib.rift_ile_version.restype = ctypes.c_int
@@ -486,6 +495,23 @@ class Plan:
                                                 ctypes.byref(rule), z.data_ptr(), ne.data_ptr(),
                                                 None if lnL_out is None else lnL_out.data_ptr(),
                                                 _stream(self.device)), "rift_ile_plan_lnZ_tmarg")
+        return z, ne
+
+    def lnZ_pmarg(self, theta, method="trapezoid", n_points=64, lnw=None, lnZ_out=None, neff_out=None,
+                  lnL_out=None):
+        """(ln Z_psi, n_eff) per point of the likelihood marginalised over
+        polarisation (rift_ile_plan_lnZ_pmarg): method "trapezoid" (n_points on
+        the circle) or "laplace"; lnL_out receives ln L_psi per sample."""
+        th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
+            else _theta(theta, self.device)
+        P = len(self.points)
+        z = lnZ_out if lnZ_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        ne = neff_out if neff_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        rule = CPsiRule(PSI_METHODS[method], int(n_points))
+        _check(self.lib.rift_ile_plan_lnZ_pmarg(self.handle, th.data_ptr(), None if lnw is None else lnw.data_ptr(),
+                                                ctypes.byref(rule), z.data_ptr(), ne.data_ptr(),
+                                                None if lnL_out is None else lnL_out.data_ptr(),
+                                                _stream(self.device)), "rift_ile_plan_lnZ_pmarg")
         return z, ne
 
     def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):

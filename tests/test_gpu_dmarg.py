@@ -83,8 +83,8 @@ def test_dmarg_matches_oracle(ile, oracle_mod, case):
 
 def test_dmarg_binned_launch_forms_and_distance_row(ile, oracle_mod):
     """Binned and unbinned evaluation, one block per tile and the work queue,
-    give bitwise the same ln L_d and ln Z_d over an uneven batch; the distance
-    row of theta is not read."""
+    give bitwise the same ln L_d per sample (and ln Z_d to rounding) over an
+    uneven batch; the distance row of theta is not read."""
     import torch
 
     pts = synth.batched_points(3, 29, K=3, nt_range=(400, 6554))
@@ -100,7 +100,9 @@ def test_dmarg_binned_launch_forms_and_distance_row(ile, oracle_mod):
         z, ne = plan.lnZ_dmarg(tht, 10.0, 1000.0, 16, lnL_out=ll)
         res.append((ll.clone(), z.clone(), ne.clone()))
     for r in res[1:]:
-        assert torch.equal(r[0], res[0][0]) and torch.equal(r[1], res[0][1]) and torch.equal(r[2], res[0][2])
+        # per-sample values bit for bit; the reductions follow the tiling (rounding order)
+        assert torch.equal(r[0], res[0][0])
+        assert torch.allclose(r[1], res[0][1], rtol=1e-12, atol=1e-12) and torch.allclose(r[2], res[0][2], rtol=1e-12)
     th2 = th.copy()
     th2[6] = np.random.default_rng(5).uniform(1, 1e4, th.shape[1])
     ll2 = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")

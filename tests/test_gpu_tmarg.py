@@ -85,7 +85,9 @@ def test_tmarg_launch_forms_binning_and_time_row(ile, oracle_mod):
         z, ne = plan.lnZ_tmarg(tht, -0.005, 0.0005, 21, lnL_out=ll)
         res.append((ll.clone(), z.clone(), ne.clone()))
     for r in res[1:]:
-        assert torch.equal(r[0], res[0][0]) and torch.equal(r[1], res[0][1]) and torch.equal(r[2], res[0][2])
+        # per-sample values bit for bit; the reductions follow the tiling (rounding order)
+        assert torch.equal(r[0], res[0][0])
+        assert torch.allclose(r[1], res[0][1], rtol=1e-12, atol=1e-12) and torch.allclose(r[2], res[0][2], rtol=1e-12)
     th2 = th.copy()
     th2[5] = np.random.default_rng(2).uniform(-1, 1, th.shape[1])
     ll2 = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
