@@ -10,8 +10,9 @@ samples); this module only marshals numpy arrays into it.  ``pregrid`` (the
 Fourier refinement of Eq. (q-time-pregrid)), ``lnL_dmarg`` (the adaptive
 Gauss-Hermite marginal over distance, Eq. (ap:dgh)), ``lnL_tmarg`` (the
 fixed-spacing rule over time, Eq. (ap:tfixed)) and ``lnL_pmarg`` (the
-polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)) are written here in
-numpy on top of the C likelihood.
+polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)) and ``hmc_step``
+(a Metropolis-adjusted Hamiltonian transition on the gradient) are written
+here in numpy on top of the C likelihood.
 
 Every function states the passage of the paper it follows.  Parity status of
 each function (what pins it) is listed in the tests' docstrings.
@@ -418,6 +419,84 @@ def lnL_pmarg(pt, theta, method="trapezoid", n_points=64, nthreads: int = 0):
             mv = vals.max()
             out[i] = mv + np.log(np.mean(np.exp(vals - mv)))
     return out
+
+
+def _to_physical(c):
+    """Sampler coordinates (ra, dec, psi, cos incl, phiref, tref, ln dist) to
+    the likelihood's (.., incl, .., .., dist); NaN incl outside [-1, 1]."""
+    t = np.array(c, np.float64, copy=True)
+    with np.errstate(invalid="ignore"):
+        t[3] = np.where(np.abs(c[3]) <= 1.0, np.arccos(np.clip(c[3], -1.0, 1.0)), np.nan)
+    t[6] = np.exp(c[6])
+    return t
+
+
+def hmc_log_prior(c, t_min, t_max, d_min, d_max):
+    """ln of the prior density in the sampler coordinates (up to a constant):
+    the isotropic, uniform-in-volume prior of the samples (ra, psi, phiref
+    periodic; sin dec, cos incl, tref uniform; p(D) ~ D^2 on [d_min, d_max])
+    is, in (dec, ln D), ln cos dec + 3 ln D on the box, -inf outside."""
+    c = np.asarray(c, np.float64)
+    inside = (np.abs(c[1]) < np.pi / 2) & (np.abs(c[3]) <= 1.0) & (c[5] >= t_min) & (c[5] <= t_max) & \
+        (c[6] >= np.log(d_min)) & (c[6] <= np.log(d_max))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        v = np.log(np.cos(c[1])) + 3.0 * c[6]
+    return np.where(inside, v, -np.inf)
+
+
+def hmc_potential(pt, c, t_min, t_max, d_min, d_max):
+    """(lnL, U = -lnL - ln prior, dU/dc) in the sampler coordinates."""
+    l, g = grad(pt, _to_physical(c))
+    lp = hmc_log_prior(c, t_min, t_max, d_min, d_max)
+    gp = np.zeros_like(g)
+    gp[1] = -np.tan(c[1])
+    gp[6] = 3.0
+    return l, -(l + lp), -(g + gp)
+
+
+def hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max):
+    """n_leapfrog leapfrog steps from (c0, p0): half kick, drift c += eps
+    sigma^2 p with cos incl folded back into [-1, 1] (period 4) and its
+    momentum negated on odd folds, half kick.  Returns (c, p, lnL, U)."""
+    sig = np.asarray(sigma, np.float64)[:, None]
+    c = np.array(c0, np.float64, copy=True)
+    p = np.array(p0, np.float64, copy=True)
+    l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max)
+    for _ in range(int(n_leapfrog)):
+        p = p - 0.5 * eps * gU
+        c = c + eps * sig * sig * p
+        out = np.isfinite(c[3]) & (np.abs(c[3]) > 1.0)
+        r = np.mod(c[3][out] + 1.0, 4.0)
+        c[3][out] = 1.0 - np.abs(r - 2.0)
+        flip = np.zeros(c.shape[1], bool)
+        flip[np.where(out)[0][r > 2.0]] = True
+        p[3][flip] = -p[3][flip]
+        l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max)
+        p = p - 0.5 * eps * gU
+    return c, p, l, U
+
+
+def hmc_step(pt, c0, z, u, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max):
+    """One Metropolis-adjusted Hamiltonian Monte Carlo transition per chain
+    (the gradient sampler of Sec. "Sampling the differentiable extrinsic
+    likelihood"), with the random inputs given: momenta p = z / sigma (mass
+    diag(sigma^-2)), n_leapfrog leapfrog steps of size eps on
+    U = -lnL - ln prior (the half kicks with the oracle's gradient in the
+    sampler coordinates plus the prior's, the drift c += eps sigma^2 p with
+    cos incl reflected at +-1 and its momentum flipped), then acceptance when
+    ln u < H0 - H1 with H = U + sum sigma^2 p^2 / 2.  Returns (c, lnL at c,
+    accepted)."""
+    sig = np.asarray(sigma, np.float64)[:, None]
+    l0, U0, _ = hmc_potential(pt, c0, t_min, t_max, d_min, d_max)
+    p0 = np.asarray(z, np.float64) / sig
+    H0 = U0 + 0.5 * np.sum(sig * sig * p0 * p0, axis=0)
+    c, p, l1, U1 = hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max)
+    H1 = U1 + 0.5 * np.sum(sig * sig * p * p, axis=0)
+    with np.errstate(invalid="ignore"):
+        acc = np.log(np.asarray(u, np.float64)) < (H0 - H1)
+    acc &= np.isfinite(H1)
+    cout = np.where(acc[None, :], c, c0)
+    return cout, np.where(acc, l1, l0), acc
 
 
 def rotation_harmonics(det_tensor, dec, psi):
