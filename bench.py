@@ -742,15 +742,77 @@ def extra_pmarg(ile, synth, torch, steps, cpu=True):
     return res
 
 
+def extra_hmc(ile, synth, torch, steps, chains=16384, n_leapfrog=8, cpu=True):
+    """Metropolis-adjusted HMC transitions of 16384 chains, 8 leapfrog steps
+    each, on the gradient (3 detectors, 9 modes, SNR 100), every transition
+    one library call with its random numbers drawn beforehand (not timed)."""
+    pt = synth.make_point(3, 9, 6554, 32768.0, 100.0, 44)
+    sig = np.array([1e-3, 1e-3, 5e-3, 5e-3, 5e-3, 3e-6, 5e-3])
+    box = (-0.01, 0.01, 10.0, 1000.0)
+    eps = 0.3
+    th0 = seed_near_peak(ile, torch, synth, pt, sig)
+    start = synth.perturbed_samples(th0, sig, chains, 6)
+    start[3] = np.cos(start[3])
+    start[6] = np.log(start[6])
+    plan = ile.Plan([pt], [chains])
+    c = torch.as_tensor(start, device="cuda").contiguous()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    burn, k = 6, max(10, steps)
+    Z = torch.randn((burn + k, 7, chains), dtype=torch.float64, device="cuda", generator=gen)
+    U = torch.rand((burn + k, chains), dtype=torch.float64, device="cuda", generator=gen)
+    ll = torch.empty(chains, dtype=torch.float64, device="cuda")
+    acc = torch.empty(chains, dtype=torch.int32, device="cuda")
+    acc_sum = torch.zeros(chains, dtype=torch.int32, device="cuda")
+    it = iter(range(burn + k))
+
+    def step():
+        i = next(it)
+        plan.hmc(0, c, Z[i], U[i], sig, eps, n_leapfrog, box, lnL_out=ll, accepted_out=acc)
+        acc_sum.add_(acc)
+
+    for _ in range(burn):  # also warms every launch of the timed step
+        step()
+    acc_sum.zero_()
+    secs, _ = time_steps(step, k, 0, torch)
+    plan.profile(True)
+    plan.hmc(0, c, Z[0], U[0], sig, eps, n_leapfrog, box, lnL_out=ll, accepted_out=acc)
+    kms, nl = plan.profile_read()
+    plan.profile(False)
+    per = secs / k
+    res = {"transitions_per_s": chains / per, "grad_evals_per_s": chains * (n_leapfrog + 1) / per,
+           "ms_per_transition": 1e3 * per, "grad_kernel_ms_avg": kms / max(1, nl),
+           "acceptance": float(acc_sum.double().mean().item() / k), "chains": chains, "n_leapfrog": n_leapfrog,
+           "eps": eps, "mean_lnL": float(ll.mean().item()),
+           "workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 100; 16384 chains, "
+                       "one Metropolis-adjusted HMC transition (8 leapfrog steps) per call",
+           "note": "rate excludes drawing the random numbers; per transition 9 gradient launches and 9 "
+                   "elementwise launches (each the kicks and drift between two gradients)"}
+    if cpu:
+        import oracle
+
+        cs = c[:, :256].cpu().numpy()
+        z = Z[0, :, :256].cpu().numpy()
+        u = U[0, :256].cpu().numpy()
+        t0 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t0 < 3.0:
+            oracle.hmc_step(pt, cs, z, u, sig, eps, n_leapfrog, *box)
+            done += 256
+        res["cpu_oracle_transitions_per_s"] = done / (time.perf_counter() - t0)
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,pmarg",
+    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,pmarg,hmc",
                     help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, pregrid, "
-                         "tmarg, pmarg, "
+                         "tmarg, pmarg, hmc, "
                          "c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
@@ -874,7 +936,7 @@ def main():
     wanted += [x.strip() for x in args.extras.split(",") if x.strip()]
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
            "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg, "pregrid": extra_pregrid,
-           "tmarg": extra_tmarg, "pmarg": extra_pmarg}
+           "tmarg": extra_tmarg, "pmarg": extra_pmarg, "hmc": extra_hmc}
     for name in wanted:
         log(f"workload {name}")
         try:

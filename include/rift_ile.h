@@ -392,6 +392,35 @@ int rift_ile_pregrid(const double *q, int64_t n_series, int32_t n, int32_t r, do
  * returns; capturable.  Non-finite values pass through unchanged. */
 int rift_ile_leapfrog_drift(int64_t n, double *theta, double *p, const double *step, void *stream);
 
+/* One Metropolis-adjusted Hamiltonian Monte Carlo transition per chain on the
+ * likelihood's gradient (Sec. "Sampling the differentiable extrinsic
+ * likelihood"), in the sampler coordinates (ra, dec, psi, cos incl, phiref,
+ * tref, ln dist), with the random numbers supplied by the caller:
+ *   p = z / sigma (mass diag(sigma^-2)); n_leapfrog leapfrog steps of size
+ *   eps on U = -lnL - ln prior (half kick, rift_ile_leapfrog_drift with
+ *   step eps sigma^2, gradient by rift_ile_plan_grad, half kick); accepted
+ *   when ln u < H0 - H1, H = U + sum_a sigma_a^2 p_a^2 / 2.
+ * The prior is the isotropic, uniform-in-volume one of the samples: in these
+ * coordinates ln cos dec + 3 ln D on the box |dec| < pi/2, |cos incl| <= 1,
+ * t_min <= tref <= t_max, d_min <= D <= d_max (ra, psi, phiref periodic), so
+ * a proposal outside the box is rejected.
+ * theta: DEVICE [7][n], the chains' states (updated: the proposal where
+ * accepted, else unchanged); z: DEVICE [7][n] standard normals; u: DEVICE [n]
+ * uniforms in (0, 1); sigma: HOST [7] > 0; lnL: DEVICE [n] or NULL (lnL at the
+ * returned states); accepted: DEVICE [n] or NULL (1 / 0).  `point` is a point
+ * of the plan (its tables give the likelihood).  Host arguments are checked
+ * before any device work (RIFT_EINVAL: n < 0, eps not finite and > 0,
+ * n_leapfrog outside [1, 10000], sigma not finite and > 0, an empty box,
+ * d_min <= 0, null or misaligned pointers); n = 0 is a no-op.  Enqueues and
+ * returns; stream-ordered scratch of 192 n bytes. */
+typedef struct {
+  double t_min, t_max; /* the tref box (s) */
+  double d_min, d_max; /* the distance box (Mpc), 0 < d_min < d_max */
+} rift_ile_hmc_prior;
+int rift_ile_plan_hmc(rift_ile_plan plan, int32_t point, int64_t n, double *theta, const double *z, const double *u,
+                      const double *sigma, double eps, int32_t n_leapfrog, const rift_ile_hmc_prior *prior,
+                      double *lnL, int32_t *accepted, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): rift_ile_lnZ with

@@ -65,6 +65,7 @@ EXPORTS = (
     "rift_ile_pregrid",
     "rift_ile_plan_lnZ_tmarg",
     "rift_ile_plan_lnZ_pmarg",
+    "rift_ile_plan_hmc",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -125,6 +126,11 @@ class CPsiRule(ctypes.Structure):
 PSI_METHODS = {"trapezoid": 0, "laplace": 1}
 
 
+class CHmcPrior(ctypes.Structure):
+    _fields_ = [("t_min", ctypes.c_double), ("t_max", ctypes.c_double), ("d_min", ctypes.c_double),
+                ("d_max", ctypes.c_double)]
+
+
 class CConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile_blocks", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("sort", ctypes.c_int32)]
@@ -167,6 +173,8 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_pregrid.argtypes = [vp, i64, i32, i32, vp, vp]
     lib.rift_ile_plan_lnZ_tmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CTimeRule), vp, vp, vp, vp]
     lib.rift_ile_plan_lnZ_pmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CPsiRule), vp, vp, vp, vp]
+    lib.rift_ile_plan_hmc.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, i32,
+                                      ctypes.POINTER(CHmcPrior), vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
     lib.rift_ile_strerror.restype = ctypes.c_char_p
     lib.rift_ile_version.restype = ctypes.c_int
@@ -513,6 +521,21 @@ class Plan:
                                                 None if lnL_out is None else lnL_out.data_ptr(),
                                                 _stream(self.device)), "rift_ile_plan_lnZ_pmarg")
         return z, ne
+
+    def hmc(self, point, theta, z, u, sigma, eps, n_leapfrog, box, lnL_out=None, accepted_out=None):
+        """One Metropolis-adjusted HMC transition of every chain in place
+        (rift_ile_plan_hmc): theta [7, n] in the sampler coordinates, z [7, n]
+        standard normals, u [n] uniforms, sigma [7], box = (t_min, t_max,
+        d_min, d_max).  Returns (lnL [n], accepted [n] int32)."""
+        n = theta.shape[1]
+        l = lnL_out if lnL_out is not None else torch.empty(n, dtype=torch.float64, device=self.device)
+        acc = accepted_out if accepted_out is not None else torch.empty(n, dtype=torch.int32, device=self.device)
+        sg = np.ascontiguousarray(sigma, dtype=np.float64)
+        pr = CHmcPrior(*[float(b) for b in box])
+        _check(self.lib.rift_ile_plan_hmc(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(), u.data_ptr(),
+                                          sg.ctypes.data, float(eps), int(n_leapfrog), ctypes.byref(pr),
+                                          l.data_ptr(), acc.data_ptr(), _stream(self.device)), "rift_ile_plan_hmc")
+        return l, acc
 
     def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):
         """Gradient of lnL with theta rows 3 and 6 in the coordinates `coords`

@@ -201,6 +201,33 @@ def test_leapfrog_drift_arguments(lib):
     assert lib.rift_ile_leapfrog_drift(10, 0x4000, 0x5000, bad.ctypes.data, None) == EINVAL
 
 
+def test_hmc_arguments(lib):
+    """The HMC transition validates its host arguments before any device
+    work; n = 0 is a validated no-op (the plan is not touched then)."""
+    from paper_2609_37393_amd import ile
+
+    sig = np.array([1e-3, 1e-3, 5e-3, 5e-3, 5e-3, 3e-6, 5e-3])
+    box = ile.CHmcPrior(-0.01, 0.01, 10.0, 1000.0)
+    fake = 0x1000  # never dereferenced on these paths
+
+    def call(plan=fake, n=0, sigma=sig, eps=0.1, L=4, prior=box):
+        return lib.rift_ile_plan_hmc(plan, 0, n, None, None, None, None if sigma is None else sigma.ctypes.data,
+                                     eps, L, None if prior is None else ctypes.byref(prior), None, None, None)
+
+    assert call() == 0
+    assert call(plan=None) == EINVAL
+    assert call(n=-1) == EINVAL
+    assert call(sigma=None) == EINVAL
+    assert call(prior=None) == EINVAL
+    assert call(eps=0.0) == EINVAL and call(eps=float("nan")) == EINVAL
+    assert call(L=0) == EINVAL and call(L=10001) == EINVAL
+    assert call(sigma=np.r_[sig[:5], -1.0, sig[6]]) == EINVAL
+    assert call(prior=ile.CHmcPrior(0.01, -0.01, 10.0, 1000.0)) == EINVAL
+    assert call(prior=ile.CHmcPrior(-0.01, 0.01, 0.0, 1000.0)) == EINVAL
+    assert call(prior=ile.CHmcPrior(-0.01, 0.01, 10.0, float("inf"))) == EINVAL
+    assert call(n=10) == EINVAL  # null state and random-number pointers
+
+
 def test_wide_rotation_rate_limit(lib):
     """Under rotation the turn over the light-travel time, |omega| |r_k|, must
     stay within one radian."""
