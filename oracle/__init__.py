@@ -9,7 +9,8 @@ The arithmetic lives in ``oracle.cpp`` (plain loops, IEEE double, OpenMP over
 samples); this module only marshals numpy arrays into it.  ``pregrid`` (the
 Fourier refinement of Eq. (q-time-pregrid)), ``lnL_dmarg`` (the adaptive
 Gauss-Hermite marginal over distance, Eq. (ap:dgh)), ``lnL_tmarg`` (the
-fixed-spacing rule over time, Eq. (ap:tfixed)) and ``lnL_pmarg`` (the
+fixed-spacing rule over time, Eq. (ap:tfixed)), ``lnL_tband`` (the
+band-limited full-window rule over time, Eq. (ap:tband)) and ``lnL_pmarg`` (the
 polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)) and ``hmc_step``
 (a Metropolis-adjusted Hamiltonian transition on the gradient) are written
 here in numpy on top of the C likelihood.
@@ -346,6 +347,65 @@ def lnL_tmarg(pt, theta, t_start, h, n_t, nthreads: int = 0):
     out[ok] = m[ok] + np.log(np.sum(np.exp(l[ok] - m[ok, None]), axis=1)) - np.log(n_t - 1.0)
     out[np.isnan(l).any(axis=1)] = np.nan
     return out
+
+
+def band_values(y, M: int) -> np.ndarray:
+    """The band-limited reconstruction of Eq. (ap:tband): from values y [n, ...]
+    at the nodes t_j = t_start + j h, the Whittaker-Shannon series
+    sum_j y_j sinc((t - t_j) / h) at the fine points t = t_start + (k / M) h,
+    k = 0 .. (n - 1) M (M fine intervals in each node interval).  Returns
+    [(n - 1) M + 1, ...]."""
+    y = np.asarray(y, np.float64)
+    n = y.shape[0]
+    M = int(M)
+    tk = np.arange((n - 1) * M + 1) / M           # fine times in units of h
+    S = np.sinc(tk[:, None] - np.arange(n)[None, :])
+    return np.tensordot(S, y, axes=(1, 0))
+
+
+def band_rule(y, base, M: int) -> np.ndarray:
+    """ln of the window-averaged exponential of the reconstructed exponent,
+    Eq. (ap:tband) under a prior uniform on the node window: with the
+    reconstruction v_k = band_values(y, M)_k (the part of the exponent linear
+    in the band-limited combination) and the time-independent remainder
+    `base`, the trapezoid rule on the fine points,
+        ln[(1 / ((n - 1) M)) sum_k w_k e^{v_k + base}],  w = 1, ends 1/2.
+    y [n, N], base [N] -> [N]; NaN anywhere in a column gives NaN."""
+    v = band_values(y, M) + np.asarray(base, np.float64)[None, :]
+    K = v.shape[0]
+    lw = np.zeros(K)
+    lw[0] = lw[-1] = np.log(0.5)
+    l = v + lw[:, None]
+    with np.errstate(invalid="ignore"):
+        m = np.max(l, axis=0)
+    out = np.full(l.shape[1], np.nan)
+    ok = np.isfinite(m)
+    out[ok] = m[ok] + np.log(np.sum(np.exp(l[:, ok] - m[None, ok]), axis=0)) - np.log(K - 1.0)
+    out[np.isnan(l).any(axis=0)] = np.nan
+    return out
+
+
+def lnL_tband(pt, theta, t_start, h, n_t, M, nthreads: int = 0):
+    """ln of the likelihood marginalised over geocentric time by the
+    band-limited full-window rule, Eq. (ap:tband), per sample: at fixed other
+    parameters the data term at the reference distance, kappa(t) = K(t), is
+    band limited; it is taken at the n_t nodes t_start + j h (the oracle's own
+    K from lnL_terms, Eq. (ap:dexp)), reconstructed at M fine points per node
+    interval by the sinc series, and lnL = x kappa - R x^2 / 2
+    (x = D_ref / D, R the time-independent model norm) is exponentiated and
+    summed there (band_rule).  The time row of theta is not read."""
+    th = _c(theta, np.float64)
+    n = th.shape[1]
+    n_t = int(n_t)
+    tk = t_start + h * np.arange(n_t)
+    big = np.repeat(th, n_t, axis=1)           # sample-major: [7, n * n_t]
+    big[5] = np.tile(tk, n)
+    Kt, Rt = lnL_terms(pt, big, nthreads)
+    Kt = Kt.reshape(n, n_t)
+    R = Rt.reshape(n, n_t)[:, 0]
+    x = pt["d_ref"] / th[6]
+    y = (x[:, None] * Kt).T                     # [n_t, n]
+    return band_rule(y, -0.5 * R * x * x, M)
 
 
 def lnL_psi_grid(pt, theta, u, nthreads: int = 0):
