@@ -336,6 +336,35 @@ int rift_ile_plan_lnZ_tmarg(rift_ile_plan plan, const double *theta, const doubl
                             const rift_ile_time_rule *rule, double *lnZ, double *neff, double *lnLt,
                             void *stream);
 
+/* Marginalisation over geocentric time by the band-limited full-window rule
+ * (Eq. (ap:tband)) under a prior uniform on the node window
+ * [t_start, t_start + (n_t - 1) h].  At fixed other parameters the exponent is
+ * x kappa(t) - x^2 quad with kappa the data term, which is band limited: it
+ * is taken at the n_t nodes t_start + j h (the data term's only evaluations),
+ * reconstructed at n_fine points per node interval by the sinc series
+ *   kappa(t) ~ sum_j kappa_j sinc((t - t_j) / h),
+ * and the exponentials at the (n_t - 1) n_fine + 1 fine points are summed by
+ * the trapezoid rule (ends 1/2):
+ *   ln L_t = ln[(1 / ((n_t - 1) n_fine)) sum_k w_k e^{l_k}].
+ * The series is truncated to the window, so h must sample kappa's band
+ * (h below 1 / (2 f_max)) and the window should hold the correlation's
+ * support; n_fine resolves the exponential's peak (n_fine >~ h / sigma_t). */
+typedef struct {
+  double t_start, h; /* first node (s, the axis of t_ref) and node spacing (s), h > 0 */
+  int32_t n_t;       /* nodes, 2 .. 64 */
+  int32_t n_fine;    /* fine intervals per node interval, 1 .. 64 */
+} rift_ile_band_rule;
+
+/* ln L_t per sample (lnLt: DEVICE [N] or NULL) and, per point, ln Z_t and
+ * n_eff over the plan's batch, as rift_ile_plan_lnZ_tmarg; theta's t_ref row is
+ * not read.  FP64; enqueues and returns, with stream-ordered scratch of
+ * 8 (n_t N + 127 n_fine + N) bytes; RIFT_EINVAL for a bad rule.  Cost per
+ * sample: one model-norm term, n_t data terms, then ((n_t - 1) n_fine + 1)
+ * sums of at most 64 products and one exp each. */
+int rift_ile_plan_lnZ_tband(rift_ile_plan plan, const double *theta, const double *lnw,
+                            const rift_ile_band_rule *rule, double *lnZ, double *neff, double *lnLt,
+                            void *stream);
+
 /* Direct marginalisation over polarisation (Sec. "Angles: finite harmonic
  * content"): at fixed other parameters the complex antenna factor carries
  * e^{-2 i psi}, so lnL is exactly q(u) = a + Re(c1 e^{iu}) + Re(c2 e^{2iu})

@@ -938,6 +938,46 @@ __device__ __forceinline__ double eval_tmarg_with(PDesc P, R* __restrict__ trig,
   return m + log(sum) + T.ln_scale;
 }
 
+// The data pass of the band-limited full-window rule (Eq. (ap:tband)): at
+// fixed other parameters the exponent is x kappa(t) - x^2 quad with kappa the
+// band-limited data term; this pass takes x kappa at the T.n nodes
+// t0 + k h (new stencils, the same F and Y) into kap[k N + i] (when `live`)
+// and returns the time-independent -x^2 quad (NaN for a poisoned sample).
+// The reconstruction between the nodes and the exponential sum run in a
+// separate kernel over these values.  The whole wavefront calls this
+// together (the data term reads cooperatively).
+template <class R, int KT, int L, class DataFn>
+__device__ __forceinline__ double eval_tkappa_with(PDesc P, R* __restrict__ trig, int ts, double ra, double dec,
+                                                   double psi, double incl, double phi, double dist,
+                                                   const TimeRule& T, RIFT_GLOBAL double* kap, int64_t N, int64_t i,
+                                                   bool live, DataFn&& data_fn) {
+  constexpr int NY = Cls<L>::NY;
+  reduce_angles<R>(psi, incl, phi);
+  Sky<R, KT> S;
+  sky_eval<R, KT, false>(P, ra, dec, psi, 0.0, S);
+  R si, ci;
+  sincos_((R)incl, &si, &ci);
+  R cn[NY], sn[NY];
+  incl_harmonics<R, NY>(ci, si, cn, sn);
+  R sf, cf;
+  sincos_((R)phi, &sf, &cf);
+  double wq = 0.0;
+  const double quad = quad_term<R, KT, L, false>(P, trig, ts, ci, si, cf, sf, S.Fre, S.Fim, &wq);
+  const double x = P->d_ref / dist;
+  const double base = -x * x * quad;
+  bool bad = !(fabs(x) <= 1.0e300) || !(fabs(base) <= 1.0e300);
+  for (int k = 0; k < T.n; ++k) {
+    S.bad = false;
+    sky_stencils<R, KT>(P, fma((double)k, T.h, T.t0), S);
+    bad = bad || S.bad;
+    __builtin_amdgcn_s_setprio(1);
+    const double data = data_fn(S.row, S.sfr, S.Fre, S.Fim, cn, sn, cf, sf);
+    __builtin_amdgcn_s_setprio(0);
+    if (live) kap[(int64_t)k * N + i] = x * data;
+  }
+  return bad ? __builtin_nan("") : base;
+}
+
 // The rule over polarisation (Sec. "Angles: finite harmonic content"): at
 // fixed other parameters lnL is q(u) = a + Re(c1 e^{iu}) + Re(c2 e^{2iu}) in
 // u = 2 (psi' - psi) (Eq. (ap:psiexp)); with psi uniform on [0, pi),
@@ -1127,6 +1167,16 @@ __device__ __forceinline__ double eval_tmarg(PDesc P, R* __restrict__ trig, int 
                                             const TimeRule& T) {
   return eval_tmarg_with<R, KT, L>(
       P, trig, ts, ra, dec, psi, incl, phi, dist, T,
+      [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
+          R sf) { return data_direct<R, KT, L>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf); });
+}
+template <class R, int KT, int L>
+__device__ __forceinline__ double eval_tkappa(PDesc P, R* __restrict__ trig, int ts, RIFT_LDS unsigned char* stage,
+                                             double ra, double dec, double psi, double incl, double phi, double dist,
+                                             const TimeRule& T, RIFT_GLOBAL double* kap, int64_t N, int64_t i,
+                                             bool live) {
+  return eval_tkappa_with<R, KT, L>(
+      P, trig, ts, ra, dec, psi, incl, phi, dist, T, kap, N, i, live,
       [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
           R sf) { return data_direct<R, KT, L>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf); });
 }

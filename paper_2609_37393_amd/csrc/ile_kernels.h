@@ -18,7 +18,12 @@ namespace rift {
 // fixed-spacing rule (Eq. (ap:tfixed)) in place of lnL, and its tile pair.
 // MODE_PMARG64: FP64, the likelihood marginalised over polarisation
 // (Eqs. (ap:psiexp), (ap:psilaplace)) in place of lnL, and its tile pair.
-enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1, MODE_DMARG64 = 2, MODE_TMARG64 = 3, MODE_PMARG64 = 4 };
+// MODE_TBAND64: FP64, the data pass of the band-limited time rule
+// (Eq. (ap:tband)): x kappa at every node into `kap`, the time-independent
+// remainder in place of lnL, and no reduction (a later pass finishes the
+// rule per sample and reduces).
+enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1, MODE_DMARG64 = 2, MODE_TMARG64 = 3, MODE_PMARG64 = 4,
+             MODE_TBAND64 = 5 };
 
 struct TileArgs {
   const PointDesc* descs;
@@ -41,8 +46,9 @@ struct TileArgs {
   // a separate pass
   const double* theta_aos;
   DistRule dm;  // MODE_DMARG64: the distance rule and prior
-  TimeRule tm;  // MODE_TMARG64: the time rule
+  TimeRule tm;  // MODE_TMARG64, MODE_TBAND64: the time nodes
   PsiRule pm;   // MODE_PMARG64: the polarisation rule
+  double* kap;  // MODE_TBAND64: [tm.n][N], x kappa at the nodes
 };
 
 // One tile: every sample's lnL (and bound), then a block reduction.
@@ -72,8 +78,12 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
       const bool live = o < t.cnt;
       const int64_t pos = t.s + (live ? o : t.cnt - 1);
       const RIFT_GLOBAL double* th = aos + 8 * pos;
+      const int64_t i = (int64_t)__double_as_longlong(th[7]) >> 16;
       Eval e;
-      if constexpr (MODE == MODE_DMARG64) {
+      if constexpr (MODE == MODE_TBAND64) {
+        e.lnL = eval_tkappa<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3], th[4], th[6],
+                                      a.tm, as_global_w(a.kap), N, i, live);
+      } else if constexpr (MODE == MODE_DMARG64) {
         const Terms tm = eval_terms<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3],
                                               th[4], th[5]);
         e.lnL = dist_marginal(a.dm, as_const(P)->d_ref, tm);
@@ -87,7 +97,6 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
         e = eval_sample<R, KT, L, MODE == MODE_PASS32>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2],
                                                        th[3], th[4], th[5], th[6]);
       }
-      const int64_t i = (int64_t)__double_as_longlong(th[7]) >> 16;
       if (live) {
         lnL[i] = e.lnL;
         if (MODE == MODE_PASS32) as_global_w(a.bnd)[i] = e.bound;
@@ -101,7 +110,10 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
     const int64_t i = t.s + (live ? o : t.cnt - 1);
     const RIFT_GLOBAL double* th = theta + i;
     Eval e;
-    if constexpr (MODE == MODE_DMARG64) {
+    if constexpr (MODE == MODE_TBAND64) {
+      e.lnL = eval_tkappa<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N], th[3 * N],
+                                    th[4 * N], th[6 * N], a.tm, as_global_w(a.kap), N, i, live);
+    } else if constexpr (MODE == MODE_DMARG64) {
       const Terms tm = eval_terms<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N],
                                             th[3 * N], th[4 * N], th[5 * N]);
       e.lnL = dist_marginal(a.dm, as_const(P)->d_ref, tm);
@@ -118,6 +130,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
     if (!live) continue;
     const double w = lnw ? lnw[i] : 0.0;
     if (lnL) lnL[i] = e.lnL;
+    if (MODE == MODE_TBAND64) continue;
     if (MODE != MODE_PASS32) {
       acc = ms_push(acc, e.lnL + w);
     } else {
@@ -126,6 +139,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
       if (v == v) tm = fmax(tm, v);
     }
   }
+  if (MODE == MODE_TBAND64) return;
   if (MODE != MODE_PASS32) {
     const MS r = ms_block(acc, sh);
     if (threadIdx.x == 0) {
@@ -464,6 +478,7 @@ typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, doubl
   tile_fn get_tilesdm_kt##KT(int lset);              \
   tile_fn get_tilestm_kt##KT(int lset);              \
   tile_fn get_tilespm_kt##KT(int lset);              \
+  tile_fn get_tilestb_kt##KT(int lset);              \
   refine_fn get_refine_kt##KT(int lset);             \
   grad_fn get_grad_kt##KT(int L);                   \
   grad_fn get_gradw_kt##KT(int L);

@@ -764,6 +764,67 @@ __global__ void k_lse_tiles(const Tile* __restrict__ tiles, const double* __rest
   }
 }
 
+// The band-limited full-window rule over geocentric time (Eq. (ap:tband)),
+// after the data pass: x kappa at the n nodes t0 + j h of every sample is
+// reconstructed at the fine points t0 + (k / M) h, k = 0 .. (n - 1) M, by the
+// sinc series sum_j x kappa_j sinc(k / M - j), the time-independent remainder
+// is added and the exponentials are summed by the trapezoid rule under a
+// prior uniform on the window:
+//   ln L_t = ln[(1 / ((n - 1) M)) sum_k w_k e^{l_k}], w = 1, ends 1/2.
+// The sinc weights depend on (k mod M, k div M - j) only: a table
+// tab[s][d + NB - 1] = sinc(d + s / M), |d| < NB, read with uniform indices.
+constexpr int TBAND_MAX_NODES = 64;
+constexpr int TBAND_MAX_FINE = 64;
+
+// sin(pi (d + f)) = (-1)^d sin(pi f): exact zeros at the nodes (s = 0).
+__global__ void k_sinc_table(int NB, int M, double* __restrict__ tab) {
+  const int W = 2 * NB - 1;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < M * W; e += gridDim.x * blockDim.x) {
+    const int s = e / W, d = e - s * W - (NB - 1);
+    double v;
+    if (s == 0) {
+      v = d == 0 ? 1.0 : 0.0;
+    } else {
+      const double f = (double)s / (double)M;
+      v = ((d & 1) ? -1.0 : 1.0) * sinpi(f) / (3.14159265358979323846 * ((double)d + f));
+    }
+    tab[e] = v;
+  }
+}
+
+// One sample per lane; NB >= n nodes held in registers (zero past n, so the
+// unrolled sums need no bounds), the fine loop uniform across the grid.  L
+// holds the remainder on entry and ln L_t on return.
+template <int NB>
+__global__ void __launch_bounds__(256) k_tband(int64_t N, int n, int M, const double* __restrict__ kap,
+                                               const double* __restrict__ tab, double ln_scale,
+                                               double* __restrict__ L) {
+  const int W = 2 * NB - 1;
+  const int K = (n - 1) * M;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    double y[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) y[j] = j < n ? kap[(int64_t)j * N + i] : 0.0;
+    const double base = L[i];
+    double m = -__builtin_inf(), sum = 0.0;
+    for (int k = 0; k <= K; ++k) {
+      const int ii = k / M, s = k - ii * M;
+      const double* __restrict__ T = tab + s * W + (NB - 1) + ii;  // T[-j] = sinc(ii - j + s / M)
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) v = fma(y[j], T[-j], v);
+      const double l = v + base + ((k == 0 || k == K) ? -0.69314718055994530942 : 0.0);
+      if (l > m) {
+        sum = (sum == 0.0) ? 1.0 : fma(sum, exp(m - l), 1.0);
+        m = l;
+      } else {
+        sum += exp(l - m);
+      }
+    }
+    L[i] = (m == m && sum == sum) ? m + log(sum) + ln_scale : __builtin_nan("");
+  }
+}
+
 // Per-tile max(lnL32 + lnw - bound) in input order (mixed path).
 __global__ void k_tmax_tiles(const Tile* __restrict__ tiles, const double* __restrict__ lnL,
                              const double* __restrict__ lnw, const float* __restrict__ bnd,
@@ -916,6 +977,7 @@ struct rift_ile_plan_s {
   TimeRule tm{};
   // polarisation marginal: the rule of the last rift_ile_plan_lnZ_pmarg call
   PsiRule pm{};
+  double* kap = nullptr;  // band-limited time rule: x kappa at the nodes (stream-ordered, per call)
 };
 
 namespace {
@@ -1001,6 +1063,7 @@ tile_fn pick_tiles_kt(int mode, int KT, int lset) {
     case MODE_PASS32: return get_tiles32_kt##K(lset); \
     case MODE_DMARG64: return get_tilesdm_kt##K(lset); \
     case MODE_TMARG64: return get_tilestm_kt##K(lset); \
+    case MODE_TBAND64: return get_tilestb_kt##K(lset); \
     default: return get_tilespm_kt##K(lset);         \
   }
   switch (KT) {
@@ -1072,6 +1135,7 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.dm = p->dm;
   a.tm = p->tm;
   a.pm = p->pm;
+  a.kap = p->kap;
   const size_t rsz = (mode == MODE_PASS32 ? sizeof(float) : sizeof(double));
   const size_t shm = eval_lds_bytes(p->lset, p->cfg.block, rsz);
   if (shm + 1024 > (size_t)p->di.max_lds) return RIFT_EUNSUPPORTED;
@@ -1680,6 +1744,62 @@ int rift_ile_plan_lnZ_tmarg(rift_ile_plan p, const double* theta, const double* 
                      (const double*)nullptr, lnZ, neff, (double*)nullptr);
   HCHK(hipGetLastError());
   return RIFT_OK;
+}
+
+int rift_ile_plan_lnZ_tband(rift_ile_plan p, const double* theta, const double* lnw, const rift_ile_band_rule* rule,
+                            double* lnZ, double* neff, double* lnLt, void* stream) {
+  if (!p || !rule || check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  if ((lnw && check_dev_ptr(lnw)) || (neff && check_dev_ptr(neff)) || (lnLt && check_dev_ptr(lnLt)))
+    return RIFT_EINVAL;
+  if (rule->n_t < 2 || rule->n_t > TBAND_MAX_NODES || rule->n_fine < 1 || rule->n_fine > TBAND_MAX_FINE)
+    return RIFT_EINVAL;
+  if (!std::isfinite(rule->t_start) || !(rule->h > 0.0) || !std::isfinite(rule->h)) return RIFT_EINVAL;
+  if (!std::isfinite(rule->t_start + (rule->n_t - 1) * rule->h)) return RIFT_EINVAL;
+  const int n = rule->n_t, M = rule->n_fine;
+  const int NB = n <= 16 ? 16 : (n <= 32 ? 32 : 64);
+  TimeRule t{};
+  t.n = n;
+  t.t0 = rule->t_start;
+  t.h = rule->h;
+  p->tm = t;
+  hipStream_t st = (hipStream_t)stream;
+  p->last = st;
+  int rc;
+  const bool sorted = p->cfg.sort != 0;
+  if (sorted && !p->bin_ready) return RIFT_EUNSUPPORTED;
+  // stream-ordered scratch: kap [n][N], the sinc table [M][2 NB - 1], and
+  // the per-sample values when the caller takes none
+  const int64_t N = p->N;
+  const size_t tab_n = (size_t)M * (2 * NB - 1);
+  const size_t bytes = sizeof(double) * ((size_t)n * N + tab_n + (lnLt ? 0 : (size_t)N));
+  double* w = nullptr;
+  if (hipMallocAsync((void**)&w, bytes, st) != hipSuccess) return RIFT_ENOMEM;
+  double* tab = w + (size_t)n * N;
+  double* L = lnLt ? lnLt : tab + tab_n;
+  p->kap = w;
+  rc = sorted ? run_binning(p, theta, st) : RIFT_OK;
+  if (!rc) rc = launch_tiles(p, MODE_TBAND64, theta, lnw, L, st);
+  p->kap = nullptr;
+  if (!rc) {
+    hipLaunchKernelGGL(k_sinc_table, dim3((unsigned)((tab_n + 255) / 256)), dim3(256), 0, st, NB, M, tab);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, (int64_t)p->di.n_cu * 8));
+    const double ln_scale = -log((double)(n - 1) * (double)M);
+    const double* kc = w;
+    if (NB == 16)
+      hipLaunchKernelGGL(k_tband<16>, dim3(grid), dim3(256), 0, st, N, n, M, kc, (const double*)tab, ln_scale, L);
+    else if (NB == 32)
+      hipLaunchKernelGGL(k_tband<32>, dim3(grid), dim3(256), 0, st, N, n, M, kc, (const double*)tab, ln_scale, L);
+    else
+      hipLaunchKernelGGL(k_tband<64>, dim3(grid), dim3(256), 0, st, N, n, M, kc, (const double*)tab, ln_scale, L);
+    if (p->n_tiles > 0)
+      hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
+                         lnw, p->d_part);
+    hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
+                       (const double*)nullptr, lnZ, neff, (double*)nullptr);
+    if (hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
+  }
+  if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
+  return rc;
 }
 
 int rift_ile_plan_lnZ_pmarg(rift_ile_plan p, const double* theta, const double* lnw, const rift_ile_psi_rule* rule,

@@ -66,6 +66,7 @@ EXPORTS = (
     "rift_ile_plan_lnZ_tmarg",
     "rift_ile_plan_lnZ_pmarg",
     "rift_ile_plan_hmc",
+    "rift_ile_plan_lnZ_tband",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -126,6 +127,11 @@ class CPsiRule(ctypes.Structure):
 PSI_METHODS = {"trapezoid": 0, "laplace": 1}
 
 
+class CBandRule(ctypes.Structure):
+    _fields_ = [("t_start", ctypes.c_double), ("h", ctypes.c_double), ("n_t", ctypes.c_int32),
+                ("n_fine", ctypes.c_int32)]
+
+
 class CHmcPrior(ctypes.Structure):
     _fields_ = [("t_min", ctypes.c_double), ("t_max", ctypes.c_double), ("d_min", ctypes.c_double),
                 ("d_max", ctypes.c_double)]
@@ -173,6 +179,7 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_pregrid.argtypes = [vp, i64, i32, i32, vp, vp]
     lib.rift_ile_plan_lnZ_tmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CTimeRule), vp, vp, vp, vp]
     lib.rift_ile_plan_lnZ_pmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CPsiRule), vp, vp, vp, vp]
+    lib.rift_ile_plan_lnZ_tband.argtypes = [vp, vp, vp, ctypes.POINTER(CBandRule), vp, vp, vp, vp]
     lib.rift_ile_plan_hmc.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, i32,
                                       ctypes.POINTER(CHmcPrior), vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
@@ -503,6 +510,24 @@ class Plan:
                                                 ctypes.byref(rule), z.data_ptr(), ne.data_ptr(),
                                                 None if lnL_out is None else lnL_out.data_ptr(),
                                                 _stream(self.device)), "rift_ile_plan_lnZ_tmarg")
+        return z, ne
+
+    def lnZ_tband(self, theta, t_start, h, n_t, n_fine, lnw=None, lnZ_out=None, neff_out=None, lnL_out=None):
+        """(ln Z_t, n_eff) per point of the likelihood marginalised over
+        geocentric time by the band-limited full-window rule
+        (rift_ile_plan_lnZ_tband): n_t nodes t_start + j h, n_fine fine
+        intervals per node interval; lnL_out receives ln L_t per sample.  The
+        t_ref row of theta is not read."""
+        th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
+            else _theta(theta, self.device)
+        P = len(self.points)
+        z = lnZ_out if lnZ_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        ne = neff_out if neff_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        rule = CBandRule(float(t_start), float(h), int(n_t), int(n_fine))
+        _check(self.lib.rift_ile_plan_lnZ_tband(self.handle, th.data_ptr(), None if lnw is None else lnw.data_ptr(),
+                                                ctypes.byref(rule), z.data_ptr(), ne.data_ptr(),
+                                                None if lnL_out is None else lnL_out.data_ptr(),
+                                                _stream(self.device)), "rift_ile_plan_lnZ_tband")
         return z, ne
 
     def lnZ_pmarg(self, theta, method="trapezoid", n_points=64, lnw=None, lnZ_out=None, neff_out=None,
