@@ -708,44 +708,48 @@ def extra_tband(ile, synth, torch, steps, cpu=True):
     """The headline point (3 detectors, 21 modes, SNR 600) marginalised over
     geocentric time by the band-limited full-window rule (Eq. (ap:tband)):
     64 nodes at 4096 Hz (above the 3400 Hz Nyquist rate of the 1700 Hz band)
-    over 15.4 ms, 16 fine intervals each (1009 fine times, 65536 Hz), 1e5
-    samples of the other six parameters; against the FP64 oracle on a sample."""
+    over 15.4 ms, 16 or 64 fine intervals each (1009 or 4033 fine times, 65536
+    or 262144 Hz), 1e5 samples of the other six parameters; against the FP64
+    oracle on a sample."""
     pt = synth.make_point(3, 21, 6554, 32768.0, 600.0, 2)
     n = 100_000
-    rule = (-0.0077, 1.0 / 4096, 64, 16)
     th = synth.prior_samples(n, 2)
     tht = torch.as_tensor(th, device="cuda").contiguous()
     plan = ile.Plan([pt], [n])
     z = torch.empty(1, dtype=torch.float64, device="cuda")
     ll = torch.empty(n, dtype=torch.float64, device="cuda")
-
-    def step():
-        plan.lnZ_tband(tht, *rule, lnZ_out=z, lnL_out=ll)
-
-    step()
-    k = max(2, steps // 3)
-    secs, _ = time_steps(step, k, 1, torch)
-    per = secs / k
-    plan.profile(True)
-    step()
-    kms, nl = plan.profile_read()
-    plan.profile(False)
-    plan.close()
-    n_t, M = rule[2], rule[3]
-    fine = (n_t - 1) * M + 1
     res = {"workload": "3 detectors, 21 modes (l<=4), Q 6554 samples at 32768 Hz, SNR 600; 1e5 samples of the other "
-                       "parameters, band-limited rule: 64 nodes at 4096 Hz, 16 fine intervals each (1009 times)",
-           "lnLt_evals_per_s": n / per, "data_terms_per_s": n * n_t / per, "ms_per_call": 1e3 * per,
-           "data_pass_kernel_ms": kms / max(1, nl), "rest_ms": 1e3 * per - kms / max(1, nl),
-           "fine_times": fine, "reconstruction_flops_per_sample": 2 * fine * 64, "lnZt": z.item()}
-    if cpu:
-        import oracle
+                       "parameters, band-limited rule on 64 nodes at 4096 Hz"}
+    for M in (16, 64):
+        rule = (-0.0077, 1.0 / 4096, 64, M)
 
-        idx = np.random.default_rng(1).choice(n, 300, replace=False)
-        t0 = time.perf_counter()
-        want = oracle.lnL_tband(pt, th[:, idx], *rule)
-        res["cpu_oracle_lnLt_evals_per_s"] = idx.size / (time.perf_counter() - t0)
-        res["max_abs_dlnLt_vs_oracle_sampled"] = float(np.nanmax(np.abs(ll.cpu().numpy()[idx] - want)))
+        def step():
+            plan.lnZ_tband(tht, *rule, lnZ_out=z, lnL_out=ll)
+
+        step()
+        k = max(2, steps // 3)
+        secs, _ = time_steps(step, k, 1, torch)
+        per = secs / k
+        plan.profile(True)
+        step()
+        kms, nl = plan.profile_read()
+        plan.profile(False)
+        fine = 63 * M + 1
+        rest = 1e3 * per - kms / max(1, nl)
+        r = {"lnLt_evals_per_s": n / per, "data_terms_per_s": n * 64 / per, "ms_per_call": 1e3 * per,
+             "data_pass_kernel_ms": kms / max(1, nl), "reconstruction_and_reduction_ms": rest, "fine_times": fine,
+             "reconstruction_flops_per_sample": 2 * fine * 64,
+             "reconstruction_tflops": 2 * fine * 64 * n / (rest / 1e3) / 1e12, "lnZt": z.item()}
+        if cpu:
+            import oracle
+
+            idx = np.random.default_rng(1).choice(n, 200, replace=False)
+            t0 = time.perf_counter()
+            want = oracle.lnL_tband(pt, th[:, idx], *rule)
+            r["cpu_oracle_lnLt_evals_per_s"] = idx.size / (time.perf_counter() - t0)
+            r["max_abs_dlnLt_vs_oracle_sampled"] = float(np.nanmax(np.abs(ll.cpu().numpy()[idx] - want)))
+        res[f"fine{M}"] = r
+    plan.close()
     return res
 
 

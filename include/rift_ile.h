@@ -357,8 +357,8 @@ typedef struct {
 
 /* ln L_t per sample (lnLt: DEVICE [N] or NULL) and, per point, ln Z_t and
  * n_eff over the plan's batch, as rift_ile_plan_lnZ_tmarg; theta's t_ref row is
- * not read.  FP64; enqueues and returns, with stream-ordered scratch of
- * 8 (n_t N + 127 n_fine + N) bytes; RIFT_EINVAL for a bad rule.  Cost per
+ * not read.  FP64; enqueues and returns, with stream-ordered scratch of at
+ * most 8 (n_t N + 127 n_fine + N) bytes; RIFT_EINVAL for a bad rule.  Cost per
  * sample: one model-norm term, n_t data terms, then ((n_t - 1) n_fine + 1)
  * sums of at most 64 products and one exp each. */
 int rift_ile_plan_lnZ_tband(rift_ile_plan plan, const double *theta, const double *lnw,

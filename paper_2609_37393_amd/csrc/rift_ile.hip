@@ -793,35 +793,60 @@ __global__ void k_sinc_table(int NB, int M, double* __restrict__ tab) {
 }
 
 // One sample per lane; NB >= n nodes held in registers (zero past n, so the
-// unrolled sums need no bounds), the fine loop uniform across the grid.  L
-// holds the remainder on entry and ln L_t on return.
+// unrolled sums need no bounds).  The fine points run by sub-offset s, whose
+// table row is staged in LDS, then in blocks of eight consecutive node
+// intervals, whose sums share the row's reads T_s[ii + q - j] (the same
+// address in every lane: broadcast reads).  The sample loop is uniform per
+// block (the staging synchronises).  L holds the remainder on entry and
+// ln L_t on return.
+constexpr int TBAND_BLK = 8;
 template <int NB>
 __global__ void __launch_bounds__(256) k_tband(int64_t N, int n, int M, const double* __restrict__ kap,
                                                const double* __restrict__ tab, double ln_scale,
                                                double* __restrict__ L) {
-  const int W = 2 * NB - 1;
-  const int K = (n - 1) * M;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+  constexpr int W = 2 * NB - 1;
+  __shared__ double row[W + TBAND_BLK];
+  for (int64_t ib = blockIdx.x * (int64_t)blockDim.x; ib < N; ib += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = ib + threadIdx.x;
+    const bool live = i < N;
     double y[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) y[j] = j < n ? kap[(int64_t)j * N + i] : 0.0;
-    const double base = L[i];
+    for (int j = 0; j < NB; ++j) y[j] = (live && j < n) ? kap[(int64_t)j * N + i] : 0.0;
+    const double base = live ? L[i] : 0.0;
     double m = -__builtin_inf(), sum = 0.0;
-    for (int k = 0; k <= K; ++k) {
-      const int ii = k / M, s = k - ii * M;
-      const double* __restrict__ T = tab + s * W + (NB - 1) + ii;  // T[-j] = sinc(ii - j + s / M)
-      double v = 0.0;
+    for (int s = 0; s < M; ++s) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < W + TBAND_BLK; e += blockDim.x) row[e] = e < W ? tab[s * W + e] : 0.0;
+      __syncthreads();
+      // fine points ii M + s <= (n - 1) M
+      const int last = s == 0 ? n - 1 : n - 2;
+      for (int ii = 0; ii <= last; ii += TBAND_BLK) {
+        const double* T = row + (NB - 1) + ii;  // T[q - j] = sinc(ii + q - j + s / M)
+        double v[TBAND_BLK];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) v = fma(y[j], T[-j], v);
-      const double l = v + base + ((k == 0 || k == K) ? -0.69314718055994530942 : 0.0);
-      if (l > m) {
-        sum = (sum == 0.0) ? 1.0 : fma(sum, exp(m - l), 1.0);
-        m = l;
-      } else {
-        sum += exp(l - m);
+        for (int q = 0; q < TBAND_BLK; ++q) v[q] = 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+#pragma unroll
+          for (int q = 0; q < TBAND_BLK; ++q) v[q] = fma(y[j], T[q - j], v[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < TBAND_BLK; ++q) {
+          if (ii + q > last) break;
+          const bool end = s == 0 && (ii + q == 0 || ii + q == n - 1);
+          const double l = v[q] + base + (end ? -0.69314718055994530942 : 0.0);
+          // one exp and no divergent branch: e = exp(-|l - m|) rescales the
+          // sum when l is the new maximum and is the new term otherwise (the
+          // first point: m = -inf, e = 0, sum = 1); a NaN l poisons the sum
+          const double d = l - m;
+          const double e = exp(-fabs(d));
+          const bool up = d > 0.0;
+          sum = up ? fma(sum, e, 1.0) : sum + e;
+          m = up ? l : m;
+        }
       }
     }
-    L[i] = (m == m && sum == sum) ? m + log(sum) + ln_scale : __builtin_nan("");
+    if (live) L[i] = (m == m && sum == sum) ? m + log(sum) + ln_scale : __builtin_nan("");
   }
 }
 
