@@ -10,7 +10,9 @@ samples); this module only marshals numpy arrays into it.  ``pregrid`` (the
 Fourier refinement of Eq. (q-time-pregrid)), ``lnL_dmarg`` (the adaptive
 Gauss-Hermite marginal over distance, Eq. (ap:dgh)), ``lnL_tmarg`` (the
 fixed-spacing rule over time, Eq. (ap:tfixed)), ``lnL_tband`` (the
-band-limited full-window rule over time, Eq. (ap:tband)) and ``lnL_pmarg`` (the
+band-limited full-window rule over time, Eq. (ap:tband)), ``lnL_erai`` (the
+joint marginal over phiref and psi by exact reconstruction, Eqs.
+(ap:angleharm), (ap:nyquist)) and ``lnL_pmarg`` (the
 polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)) and ``hmc_step``
 (a Metropolis-adjusted Hamiltonian transition on the gradient) are written
 here in numpy on top of the C likelihood.
@@ -428,6 +430,60 @@ def psi_coefficients(pt, theta, nthreads: int = 0):
     q = lnL_psi_grid(pt, theta, uj, nthreads)
     ch = q @ np.exp(-1j * np.outer(uj, np.arange(3))) / 5.0  # c^_0, c^_1, c^_2
     return ch[:, 0].real, 2.0 * ch[:, 1], 2.0 * ch[:, 2]
+
+
+def erai_grid(pt):
+    """(N_phi, N_psi) of the exact angular reconstruction (Eqs. (ap:angleharm),
+    (ap:nyquist)) for a point's modes: at fixed other parameters lnL is a
+    trigonometric polynomial of degree 2 in u = 2 psi and of degree 2 m_max in
+    phiref (the data term carries e^{i m phi}, the model norm e^{i (m - m') phi}
+    and e^{i (m + m') phi}), so N_psi = 5 and N_phi = 4 m_max + 1 equally
+    spaced angles determine it."""
+    m_max = int(np.max(np.abs(np.asarray(pt["lm"])[:, 1])))
+    return 4 * m_max + 1, 5
+
+
+def angle_coefficients(pt, theta, nthreads: int = 0):
+    """The finite harmonic model of lnL in the angle offsets (alpha, u) from the
+    sample's (phiref, 2 psi), Eq. (ap:angleharm):
+        lnL(phi + alpha, psi + u / 2) = sum_{q, p} c[q, p] e^{i (q alpha + p u)},
+    |q| <= (N_phi - 1) / 2, |p| <= 2, by the exact two-dimensional discrete
+    Fourier transform of the oracle's own lnL on the N_phi x 5 product grid
+    alpha_j = 2 pi j / N_phi, u_c = 2 pi c / 5.  Returns (c [n, N_phi, 5]
+    indexed by (q mod N_phi, p mod 5), the grid's lnL [n, N_phi, 5])."""
+    th = _c(theta, np.float64)
+    n = th.shape[1]
+    Nf, Np = erai_grid(pt)
+    al = 2.0 * np.pi * np.arange(Nf) / Nf
+    uc = 2.0 * np.pi * np.arange(Np) / Np
+    big = np.repeat(th, Nf * Np, axis=1)       # sample-major, then phi, then psi
+    big[4] = big[4] + np.tile(np.repeat(al, Np), n)
+    big[2] = big[2] + np.tile(np.tile(uc / 2.0, Nf), n)
+    L = lnL(pt, big, nthreads).reshape(n, Nf, Np)
+    return np.fft.fft2(L, axes=(1, 2)) / (Nf * Np), L
+
+
+def lnL_erai(pt, theta, n_phi: int, n_psi: int, nthreads: int = 0):
+    """ln of the likelihood marginalised over phiref (uniform on [0, 2 pi)) and
+    psi (uniform on [0, pi)) by exact-reconstruction adaptive integration
+    (ERAI): the finite harmonic model from angle_coefficients, then its
+    exponential averaged over the periodic product grid of n_phi x n_psi
+    offsets alpha_a = 2 pi a / n_phi, psi offset pi b / n_psi (the periodic
+    trapezoid rule on the torus, sized by the caller)."""
+    C, _ = angle_coefficients(pt, theta, nthreads)
+    n, Nf, Np = C.shape
+    qf = np.fft.fftfreq(Nf, 1.0 / Nf)            # 0, 1, .., -1
+    pf = np.fft.fftfreq(Np, 1.0 / Np)
+    Ea = np.exp(1j * np.outer(2.0 * np.pi * np.arange(int(n_phi)) / int(n_phi), qf))  # [n_phi, Nf]
+    Eu = np.exp(1j * np.outer(2.0 * np.pi * np.arange(int(n_psi)) / int(n_psi), pf))  # [n_psi, Np]
+    V = np.einsum("aq,nqp,bp->nab", Ea, C, Eu).real.reshape(n, -1)
+    out = np.full(n, np.nan)
+    with np.errstate(invalid="ignore"):
+        m = np.max(V, axis=1)
+    ok = np.isfinite(m)
+    out[ok] = m[ok] + np.log(np.mean(np.exp(V[ok] - m[ok, None]), axis=1))
+    out[np.isnan(V).any(axis=1)] = np.nan
+    return out
 
 
 def lnL_pmarg(pt, theta, method="trapezoid", n_points=64, nthreads: int = 0):
