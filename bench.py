@@ -753,6 +753,48 @@ def extra_tband(ile, synth, torch, steps, cpu=True):
     return res
 
 
+def extra_erai(ile, synth, torch, steps, cpu=True):
+    """The headline point (3 detectors, 21 modes, SNR 600, 1e6 prior samples)
+    marginalised jointly over phiref and psi by exact reconstruction
+    (Eqs. (ap:angleharm), (ap:nyquist)): 9 data-term and 17 model-norm phases
+    per sample, then the exponential on a 32 x 16 and a 64 x 32 grid; against
+    the FP64 oracle on a sample."""
+    pt, th = c2_inputs(synth, 1_000_000)
+    n = th.shape[1]
+    tht = torch.as_tensor(th, device="cuda").contiguous()
+    plan = ile.Plan([pt], [n])
+    z = torch.empty(1, dtype=torch.float64, device="cuda")
+    ll = torch.empty(n, dtype=torch.float64, device="cuda")
+    res = {"workload": "3 detectors, 21 modes (l<=4), Q 6554 samples at 32768 Hz, SNR 600, 1e6 prior samples; "
+                       "lnL marginalised over phiref and psi (9 + 17 sampling phases)"}
+    for n_phi, n_psi in ((32, 16), (64, 32)):
+        def step():
+            plan.lnZ_erai(tht, n_phi, n_psi, lnZ_out=z, lnL_out=ll)
+
+        step()
+        k = max(2, steps // 3)
+        secs, _ = time_steps(step, k, 1, torch)
+        per = secs / k
+        plan.profile(True)
+        step()
+        kms, nl = plan.profile_read()
+        plan.profile(False)
+        r = {"lnL_evals_per_s": n / per, "ms_per_call": 1e3 * per, "data_pass_kernel_ms": kms / max(1, nl),
+             "grid_and_reduction_ms": 1e3 * per - kms / max(1, nl), "exp_per_sample": n_phi * n_psi,
+             "lnZ": z.item()}
+        if cpu:
+            import oracle
+
+            idx = np.random.default_rng(3).choice(n, 200, replace=False)
+            t0 = time.perf_counter()
+            want = oracle.lnL_erai(pt, th[:, idx], n_phi, n_psi)
+            r["cpu_oracle_evals_per_s"] = idx.size / (time.perf_counter() - t0)
+            r["max_abs_dlnL_vs_oracle_sampled"] = float(np.nanmax(np.abs(ll.cpu().numpy()[idx] - want)))
+        res[f"grid{n_phi}x{n_psi}"] = r
+    plan.close()
+    return res
+
+
 def extra_pmarg(ile, synth, torch, steps, cpu=True):
     """The headline point (3 detectors, 21 modes, SNR 600, 1e6 prior
     samples) marginalised over polarisation in the kernel: the periodic
@@ -859,9 +901,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,tband,pmarg,hmc",
+    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,tband,pmarg,erai,hmc",
                     help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, pregrid, "
-                         "tmarg, tband, pmarg, hmc, "
+                         "tmarg, tband, pmarg, erai, hmc, "
                          "c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
@@ -985,7 +1027,8 @@ def main():
     wanted += [x.strip() for x in args.extras.split(",") if x.strip()]
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
            "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg, "pregrid": extra_pregrid,
-           "tmarg": extra_tmarg, "tband": extra_tband, "pmarg": extra_pmarg, "hmc": extra_hmc}
+           "tmarg": extra_tmarg, "tband": extra_tband, "pmarg": extra_pmarg, "erai": extra_erai,
+           "hmc": extra_hmc}
     for name in wanted:
         log(f"workload {name}")
         try:

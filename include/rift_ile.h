@@ -392,6 +392,35 @@ typedef struct {
 int rift_ile_plan_lnZ_pmarg(rift_ile_plan plan, const double *theta, const double *lnw,
                             const rift_ile_psi_rule *rule, double *lnZ, double *neff, double *lnLp, void *stream);
 
+/* Joint marginalisation over the reference phase and polarisation by
+ * exact-reconstruction adaptive integration (ERAI; Sec. "Angles: finite
+ * harmonic content", Eqs. (ap:angleharm), (ap:nyquist)), with phiref uniform
+ * on [0, 2 pi) and psi on [0, pi).  At fixed sky, inclination, time and
+ * distance, lnL is a finite trigonometric polynomial in (phiref, 2 psi): of
+ * degree 2 in 2 psi and 2 m_max in phiref (m_max the largest |m| of the
+ * plan's modes).  Its coefficients are fixed exactly by the data term at
+ * 2 m_max + 1 and the model norm at 4 m_max + 1 phases (one gather of the
+ * correlation tables per data-term phase, the psi dependence analytic); the
+ * exponential of the reconstructed model is then averaged over the periodic
+ * grid of n_phi x n_psi offsets from the sample's (phiref, psi):
+ *   ln L = ln[(1 / (n_phi n_psi)) sum_{a, b} e^{lnL(phi + 2 pi a / n_phi,
+ *                                                 psi + pi b / n_psi)}].
+ * The grid is the caller's to size from the signal's amplitude (its peak
+ * narrows as 1 / rho). */
+typedef struct {
+  int32_t n_phi, n_psi; /* fine grid, 1 .. 4096 each */
+} rift_ile_angle_rule;
+
+/* ln L per sample (lnLa: DEVICE [N] or NULL) and, per point, ln Z and n_eff
+ * over the plan's batch; theta's phiref and psi rows set where the grid
+ * starts.  FP64; enqueues and returns, with stream-ordered scratch of
+ * 8 ((4 m_max + 2 + 3 (4 m_max + 1)) N + 26 n_phi + 4 n_psi + N) bytes at
+ * most; RIFT_EINVAL for a bad rule, RIFT_EUNSUPPORTED for modes with
+ * |m| > 4.  Cost per sample: 2 m_max + 1 data terms, 4 m_max + 1 model-norm
+ * contractions, then n_phi n_psi exponentials. */
+int rift_ile_plan_lnZ_erai(rift_ile_plan plan, const double *theta, const double *lnw,
+                           const rift_ile_angle_rule *rule, double *lnZ, double *neff, double *lnLa, void *stream);
+
 /* The n-point Gauss-Hermite rule of the weight e^{-x^2/2} (1 <= n <= 64) that
  * the distance marginal uses: HOST nodes[n] ascending and weights[n]. */
 int rift_ile_gauss_hermite(int n, double *nodes, double *weights);

@@ -23,8 +23,8 @@ OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RIFT_ILE_ARCH", "gfx950")
 KT_CLASSES = (2, 3, 5, 8)
-KINDS = (0, 1, 2, 3, 4, 5, 6, 7)  # FP64 tiles, FP32 tiles, FP64 refine, gradient, distance / time / psi marginals,
-#                                   band-limited time rule (data pass)
+KINDS = (0, 1, 2, 3, 4, 5, 6, 7, 8)  # FP64 tiles, FP32 tiles, FP64 refine, gradient, distance / time / psi
+#                                      marginals, data passes of the band-limited time rule and of ERAI
 
 FLAGS = [
     "-O3",

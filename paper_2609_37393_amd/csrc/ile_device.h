@@ -1104,6 +1104,78 @@ __device__ __forceinline__ double eval_pmarg_with(PDesc P, R* __restrict__ trig,
   return psi_marginal(G, -x2 * A0, x * wre, x * wim, -x2 * Bre, x2 * Bim);
 }
 
+// The data pass of the joint phiref / psi marginal by exact reconstruction
+// (ERAI, Eqs. (ap:angleharm), (ap:nyquist)).  At fixed sky, inclination,
+// time and distance, lnL in the offsets (alpha, u = 2 (psi' - psi)) is
+//   q(alpha, u) = a(alpha) + Re(c1(alpha) e^{iu}) + Re(c2(alpha) e^{2iu}),
+// c1 = x W (the complex data term, degree m_max in alpha), a = -x^2 A0 and
+// c2 = -x^2 conj(B) (the model norm, degree 2 m_max), as in the polarisation
+// marginal.  This pass samples c1 at the G.nd = 2 m_max + 1 angles
+// phi + 2 pi j / nd (one gather each, the same stencils) and (a, c2) at the
+// G.nq = 4 m_max + 1 angles phi + 2 pi j / nq (one contraction each), which
+// determine them exactly, into out rows [2 j], [2 j + 1] (c1) and
+// [2 nd + 3 j + 0 .. 2] (a, c2) of stride N (when `live`).  Returns whether
+// the sample is poisoned.  The whole wavefront calls this together.
+struct AngleRule {
+  int32_t nd, nq;
+  double dd, dq;  // 2 pi / nd, 2 pi / nq
+};
+
+template <class R, int KT, int L, class DataFn>
+__device__ __forceinline__ bool eval_erai_with(PDesc P, R* __restrict__ trig, int ts, double ra, double dec,
+                                               double psi, double incl, double phi, double tref, double dist,
+                                               const AngleRule& G, RIFT_GLOBAL double* out, int64_t N, int64_t i,
+                                               bool live, DataFn&& data_fn) {
+  constexpr int NY = Cls<L>::NY;
+  reduce_angles<R>(psi, incl, phi);
+  Sky<R, KT> S;
+  sky_eval<R, KT, true>(P, ra, dec, psi, tref, S);
+  R si, ci;
+  sincos_((R)incl, &si, &ci);
+  R cn[NY], sn[NY];
+  incl_harmonics<R, NY>(ci, si, cn, sn);
+  const double x = P->d_ref / dist;
+  const double x2 = x * x;
+  bool bad = S.bad || !(fabs(x) <= 1.0e300);
+  for (int j = 0; j < G.nd; ++j) {
+    R sf, cf;
+    sincos_((R)fma((double)j, G.dd, phi), &sf, &cf);
+    double wim = 0.0;
+    __builtin_amdgcn_s_setprio(1);
+    const double wre = data_fn(S.row, S.sfr, S.Fre, S.Fim, cn, sn, cf, sf, &wim);
+    __builtin_amdgcn_s_setprio(0);
+    bad = bad || !(fabs(wre) <= 1.0e300) || !(fabs(wim) <= 1.0e300);
+    if (live) {
+      out[(int64_t)(2 * j) * N + i] = x * wre;
+      out[(int64_t)(2 * j + 1) * N + i] = x * wim;
+    }
+  }
+  const int r0 = 2 * G.nd;
+  for (int j = 0; j < G.nq; ++j) {
+    R sf, cf;
+    sincos_((R)fma((double)j, G.dq, phi), &sf, &cf);
+    R acc[3 * KT];
+    norm_contract<R, KT, L>(P, trig, ts, ci, si, cf, sf, acc);
+    double A0 = 0.0, Bre = 0.0, Bim = 0.0;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const R f2 = S.Fre[k] * S.Fre[k] + S.Fim[k] * S.Fim[k];
+      const R g2r = S.Fre[k] * S.Fre[k] - S.Fim[k] * S.Fim[k];
+      const R g2i = 2 * S.Fre[k] * S.Fim[k];
+      A0 += (double)(f2 * acc[3 * k]);
+      Bre += (double)(g2r * acc[3 * k + 1]) + (double)(g2i * acc[3 * k + 2]);
+      Bim += (double)(g2i * acc[3 * k + 1]) - (double)(g2r * acc[3 * k + 2]);
+    }
+    bad = bad || !(fabs(A0) <= 1.0e300) || !(fabs(Bre) + fabs(Bim) <= 1.0e300);
+    if (live) {
+      out[(int64_t)(r0 + 3 * j) * N + i] = -x2 * A0;
+      out[(int64_t)(r0 + 3 * j + 1) * N + i] = -x2 * Bre;
+      out[(int64_t)(r0 + 3 * j + 2) * N + i] = x2 * Bim;
+    }
+  }
+  return bad;
+}
+
 // Everything per sample up to the distance: the terms.  R is the arithmetic
 // type of the bulk (FP64 or FP32); the sky frame, delays and the final
 // combination are always FP64.  The data term comes from
@@ -1169,6 +1241,16 @@ __device__ __forceinline__ double eval_tmarg(PDesc P, R* __restrict__ trig, int 
       P, trig, ts, ra, dec, psi, incl, phi, dist, T,
       [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf,
           R sf) { return data_direct<R, KT, L>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf); });
+}
+template <class R, int KT, int L>
+__device__ __forceinline__ bool eval_erai(PDesc P, R* __restrict__ trig, int ts, RIFT_LDS unsigned char* stage,
+                                         double ra, double dec, double psi, double incl, double phi, double tref,
+                                         double dist, const AngleRule& G, RIFT_GLOBAL double* out, int64_t N,
+                                         int64_t i, bool live) {
+  return eval_erai_with<R, KT, L>(
+      P, trig, ts, ra, dec, psi, incl, phi, tref, dist, G, out, N, i, live,
+      [&](const int32_t* row, const R* sfr, const R* Fre, const R* Fim, const R* cn, const R* sn, R cf, R sf,
+          double* im) { return data_direct<R, KT, L, true>(P, stage, row, sfr, Fre, Fim, cn, sn, cf, sf, im); });
 }
 template <class R, int KT, int L>
 __device__ __forceinline__ double eval_tkappa(PDesc P, R* __restrict__ trig, int ts, RIFT_LDS unsigned char* stage,

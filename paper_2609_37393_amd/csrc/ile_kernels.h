@@ -22,8 +22,12 @@ namespace rift {
 // (Eq. (ap:tband)): x kappa at every node into `kap`, the time-independent
 // remainder in place of lnL, and no reduction (a later pass finishes the
 // rule per sample and reduces).
+// MODE_ERAI64: FP64, the data pass of the joint phiref / psi marginal by
+// exact reconstruction: the angular coefficients at their sampling angles
+// into `ang`, NaN or 0 (poisoned or not) in place of lnL, no reduction.
 enum : int { MODE_LSE64 = 0, MODE_PASS32 = 1, MODE_DMARG64 = 2, MODE_TMARG64 = 3, MODE_PMARG64 = 4,
-             MODE_TBAND64 = 5 };
+             MODE_TBAND64 = 5, MODE_ERAI64 = 6 };
+constexpr bool mode_reduces(int mode) { return mode != MODE_TBAND64 && mode != MODE_ERAI64; }
 
 struct TileArgs {
   const PointDesc* descs;
@@ -49,6 +53,8 @@ struct TileArgs {
   TimeRule tm;  // MODE_TMARG64, MODE_TBAND64: the time nodes
   PsiRule pm;   // MODE_PMARG64: the polarisation rule
   double* kap;  // MODE_TBAND64: [tm.n][N], x kappa at the nodes
+  AngleRule am; // MODE_ERAI64: the sampling angles
+  double* ang;  // MODE_ERAI64: [2 nd + 3 nq][N], the angular coefficients
 };
 
 // One tile: every sample's lnL (and bound), then a block reduction.
@@ -83,6 +89,11 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
       if constexpr (MODE == MODE_TBAND64) {
         e.lnL = eval_tkappa<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3], th[4], th[6],
                                       a.tm, as_global_w(a.kap), N, i, live);
+      } else if constexpr (MODE == MODE_ERAI64) {
+        e.lnL = eval_erai<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3], th[4], th[5],
+                                    th[6], a.am, as_global_w(a.ang), N, i, live)
+                    ? __builtin_nan("")
+                    : 0.0;
       } else if constexpr (MODE == MODE_DMARG64) {
         const Terms tm = eval_terms<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[1], th[2], th[3],
                                               th[4], th[5]);
@@ -113,6 +124,11 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
     if constexpr (MODE == MODE_TBAND64) {
       e.lnL = eval_tkappa<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N], th[3 * N],
                                     th[4 * N], th[6 * N], a.tm, as_global_w(a.kap), N, i, live);
+    } else if constexpr (MODE == MODE_ERAI64) {
+      e.lnL = eval_erai<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N], th[3 * N],
+                                  th[4 * N], th[5 * N], th[6 * N], a.am, as_global_w(a.ang), N, i, live)
+                  ? __builtin_nan("")
+                  : 0.0;
     } else if constexpr (MODE == MODE_DMARG64) {
       const Terms tm = eval_terms<R, KT, L>(opaque(P), trig, blockDim.x, stage, th[0], th[N], th[2 * N],
                                             th[3 * N], th[4 * N], th[5 * N]);
@@ -130,7 +146,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
     if (!live) continue;
     const double w = lnw ? lnw[i] : 0.0;
     if (lnL) lnL[i] = e.lnL;
-    if (MODE == MODE_TBAND64) continue;
+    if (!mode_reduces(MODE)) continue;
     if (MODE != MODE_PASS32) {
       acc = ms_push(acc, e.lnL + w);
     } else {
@@ -139,7 +155,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int tidx, MS* sh, do
       if (v == v) tm = fmax(tm, v);
     }
   }
-  if (MODE == MODE_TBAND64) return;
+  if (!mode_reduces(MODE)) return;
   if (MODE != MODE_PASS32) {
     const MS r = ms_block(acc, sh);
     if (threadIdx.x == 0) {
@@ -479,6 +495,7 @@ typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, doubl
   tile_fn get_tilestm_kt##KT(int lset);              \
   tile_fn get_tilespm_kt##KT(int lset);              \
   tile_fn get_tilestb_kt##KT(int lset);              \
+  tile_fn get_tilesea_kt##KT(int lset);              \
   refine_fn get_refine_kt##KT(int lset);             \
   grad_fn get_grad_kt##KT(int L);                   \
   grad_fn get_gradw_kt##KT(int L);

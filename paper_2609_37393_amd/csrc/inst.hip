@@ -3,7 +3,7 @@
 // 3: gradient, a lane or a group of lanes per sample, 4: FP64 tiles of the
 // distance marginal, 5: FP64 tiles of the time marginal, 6: FP64 tiles of
 // the polarisation marginal, 7: FP64 data pass of the band-limited time
-// rule).  The build compiles
+// rule, 8: FP64 data pass of the joint phiref / psi marginal).  The build compiles
 // this file once per (class, kind) so the instances build in parallel.
 #include "ile_kernels.h"
 
@@ -17,7 +17,8 @@
 namespace rift {
 
 // Mode-class sets: 1 (l<=2), 2 (l=3), 4 (l=4), 8 (l<=8), 7 (l<=4 mixed).
-#if RIFT_KIND == 0 || RIFT_KIND == 1 || RIFT_KIND == 4 || RIFT_KIND == 5 || RIFT_KIND == 6 || RIFT_KIND == 7
+#if RIFT_KIND == 0 || RIFT_KIND == 1 || RIFT_KIND == 4 || RIFT_KIND == 5 || RIFT_KIND == 6 || RIFT_KIND == 7 || \
+    RIFT_KIND == 8
 #if RIFT_KIND == 0
 #define RIFT_R double
 #define RIFT_MODE MODE_LSE64
@@ -38,6 +39,10 @@ namespace rift {
 #define RIFT_R double
 #define RIFT_MODE MODE_TBAND64
 #define RIFT_NAME RIFT_CAT(get_tilestb_kt, RIFT_KT)
+#elif RIFT_KIND == 8
+#define RIFT_R double
+#define RIFT_MODE MODE_ERAI64
+#define RIFT_NAME RIFT_CAT(get_tilesea_kt, RIFT_KT)
 #else
 #define RIFT_R float
 #define RIFT_MODE MODE_PASS32

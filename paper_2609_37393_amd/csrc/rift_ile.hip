@@ -850,6 +850,102 @@ __global__ void __launch_bounds__(256) k_tband(int64_t N, int n, int M, const do
   }
 }
 
+// The joint phiref / psi marginal by exact reconstruction (ERAI), after the
+// data pass: per sample the angular coefficients at their sampling angles
+// (c1 at nd = 2 m_max + 1, a and c2 at nq = 4 m_max + 1 angles) determine
+//   q(alpha, u) = a(alpha) + Re(c1(alpha) e^{iu}) + Re(c2(alpha) e^{2iu})
+// exactly; e^q is averaged over the periodic grid alpha_a = 2 pi a / n_phi,
+// u_b = 2 pi b / n_psi (psi offset pi b / n_psi), the trapezoid rule on the
+// torus with phiref uniform on [0, 2 pi) and psi on [0, pi).
+constexpr int ERAI_MAX_M = 4;
+
+// (a N - j n) / (n N) turns between fine angle a of n and sampling angle j
+// of N; the Dirichlet kernel of odd N, sin(pi N d) / (N sin(pi d)), is 1 at
+// the coincident angles (tested exactly on integers).
+__device__ __forceinline__ double dirichlet_weight(int a, int n, int j, int N) {
+  const int64_t num = (int64_t)a * N - (int64_t)j * n;
+  if (num % ((int64_t)n * N) == 0) return 1.0;
+  return sinpi((double)num / (double)n) / ((double)N * sinpi((double)num / ((double)n * (double)N)));
+}
+
+// Uniform tables: interpolation weights wd [n_phi][NDM] and wq [n_phi][NQM]
+// (zero past nd, nq), and tu [n_psi][4] = cos u, sin u, cos 2u, sin 2u.
+__global__ void k_erai_tables(int n_phi, int n_psi, int nd, int nq, int NDM, int NQM, double* __restrict__ wd,
+                              double* __restrict__ wq, double* __restrict__ tu) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_phi * NDM; e += stride) {
+    const int a = e / NDM, j = e - a * NDM;
+    wd[e] = j < nd ? dirichlet_weight(a, n_phi, j, nd) : 0.0;
+  }
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_phi * NQM; e += stride) {
+    const int a = e / NQM, j = e - a * NQM;
+    wq[e] = j < nq ? dirichlet_weight(a, n_phi, j, nq) : 0.0;
+  }
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n_psi; b += stride) {
+    double s1, c1, s2, c2;
+    sincospi(2.0 * (double)b / (double)n_psi, &s1, &c1);
+    sincospi(4.0 * (double)b / (double)n_psi, &s2, &c2);
+    tu[4 * b] = c1;
+    tu[4 * b + 1] = s1;
+    tu[4 * b + 2] = c2;
+    tu[4 * b + 3] = s2;
+  }
+}
+
+// One sample per lane, its coefficients in registers (zero past nd, nq);
+// the grid loops are uniform, the tables read with uniform addresses.  L
+// holds NaN (poisoned) or 0 on entry and ln L_{phi psi} on return.
+template <int NDM, int NQM>
+__global__ void __launch_bounds__(256) k_erai(int64_t N, int nd, int nq, int n_phi, int n_psi,
+                                              const double* __restrict__ ang, const double* __restrict__ wd,
+                                              const double* __restrict__ wq, const double* __restrict__ tu,
+                                              double ln_scale, double* __restrict__ L) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    double c1r[NDM], c1i[NDM], ca[NQM], c2r[NQM], c2i[NQM];
+#pragma unroll
+    for (int j = 0; j < NDM; ++j) {
+      c1r[j] = j < nd ? ang[(int64_t)(2 * j) * N + i] : 0.0;
+      c1i[j] = j < nd ? ang[(int64_t)(2 * j + 1) * N + i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NQM; ++j) {
+      const int64_t r = 2 * nd + 3 * j;
+      ca[j] = j < nq ? ang[r * N + i] : 0.0;
+      c2r[j] = j < nq ? ang[(r + 1) * N + i] : 0.0;
+      c2i[j] = j < nq ? ang[(r + 2) * N + i] : 0.0;
+    }
+    const double flag = L[i];
+    double m = -__builtin_inf(), sum = 0.0;
+    for (int p = 0; p < n_phi; ++p) {
+      const double* __restrict__ Wd = wd + p * NDM;
+      const double* __restrict__ Wq = wq + p * NQM;
+      double C1r = 0.0, C1i = 0.0, A = 0.0, C2r = 0.0, C2i = 0.0;
+#pragma unroll
+      for (int j = 0; j < NDM; ++j) {
+        C1r = fma(Wd[j], c1r[j], C1r);
+        C1i = fma(Wd[j], c1i[j], C1i);
+      }
+#pragma unroll
+      for (int j = 0; j < NQM; ++j) {
+        A = fma(Wq[j], ca[j], A);
+        C2r = fma(Wq[j], c2r[j], C2r);
+        C2i = fma(Wq[j], c2i[j], C2i);
+      }
+      for (int b = 0; b < n_psi; ++b) {
+        const double* __restrict__ U = tu + 4 * b;
+        const double l = A + C1r * U[0] - C1i * U[1] + C2r * U[2] - C2i * U[3];
+        // one exp, no divergent branch (as in k_tband)
+        const double d = l - m;
+        const double e = exp(-fabs(d));
+        const bool up = d > 0.0;
+        sum = up ? fma(sum, e, 1.0) : sum + e;
+        m = up ? l : m;
+      }
+    }
+    L[i] = (flag == flag && m == m && sum == sum) ? m + log(sum) + ln_scale : __builtin_nan("");
+  }
+}
+
 // Per-tile max(lnL32 + lnw - bound) in input order (mixed path).
 __global__ void k_tmax_tiles(const Tile* __restrict__ tiles, const double* __restrict__ lnL,
                              const double* __restrict__ lnw, const float* __restrict__ bnd,
@@ -1003,6 +1099,8 @@ struct rift_ile_plan_s {
   // polarisation marginal: the rule of the last rift_ile_plan_lnZ_pmarg call
   PsiRule pm{};
   double* kap = nullptr;  // band-limited time rule: x kappa at the nodes (stream-ordered, per call)
+  AngleRule am{};
+  double* ang = nullptr;  // ERAI: the angular coefficients (stream-ordered, per call)
 };
 
 namespace {
@@ -1089,6 +1187,7 @@ tile_fn pick_tiles_kt(int mode, int KT, int lset) {
     case MODE_DMARG64: return get_tilesdm_kt##K(lset); \
     case MODE_TMARG64: return get_tilestm_kt##K(lset); \
     case MODE_TBAND64: return get_tilestb_kt##K(lset); \
+    case MODE_ERAI64: return get_tilesea_kt##K(lset); \
     default: return get_tilespm_kt##K(lset);         \
   }
   switch (KT) {
@@ -1161,6 +1260,8 @@ int launch_tiles(rift_ile_plan p, int mode, const double* theta, const double* l
   a.tm = p->tm;
   a.pm = p->pm;
   a.kap = p->kap;
+  a.am = p->am;
+  a.ang = p->ang;
   const size_t rsz = (mode == MODE_PASS32 ? sizeof(float) : sizeof(double));
   const size_t shm = eval_lds_bytes(p->lset, p->cfg.block, rsz);
   if (shm + 1024 > (size_t)p->di.max_lds) return RIFT_EUNSUPPORTED;
@@ -1816,6 +1917,66 @@ int rift_ile_plan_lnZ_tband(rift_ile_plan p, const double* theta, const double* 
       hipLaunchKernelGGL(k_tband<32>, dim3(grid), dim3(256), 0, st, N, n, M, kc, (const double*)tab, ln_scale, L);
     else
       hipLaunchKernelGGL(k_tband<64>, dim3(grid), dim3(256), 0, st, N, n, M, kc, (const double*)tab, ln_scale, L);
+    if (p->n_tiles > 0)
+      hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
+                         lnw, p->d_part);
+    hipLaunchKernelGGL(k_merge, dim3(p->n_points), dim3(512), 0, st, p->d_desc, p->d_trange, p->d_part,
+                       (const double*)nullptr, lnZ, neff, (double*)nullptr);
+    if (hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
+  }
+  if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
+  return rc;
+}
+
+int rift_ile_plan_lnZ_erai(rift_ile_plan p, const double* theta, const double* lnw, const rift_ile_angle_rule* rule,
+                           double* lnZ, double* neff, double* lnLa, void* stream) {
+  if (!p || !rule || check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
+  if ((lnw && check_dev_ptr(lnw)) || (neff && check_dev_ptr(neff)) || (lnLa && check_dev_ptr(lnLa)))
+    return RIFT_EINVAL;
+  if (rule->n_phi < 1 || rule->n_phi > 4096 || rule->n_psi < 1 || rule->n_psi > 4096) return RIFT_EINVAL;
+  int m_max = 0;
+  for (const PointDesc& D : p->h_desc) m_max = std::max(m_max, std::max(std::abs(D.m[0]), std::abs(D.m[D.M - 1])));
+  if (m_max > ERAI_MAX_M) return RIFT_EUNSUPPORTED;
+  const int nd = 2 * m_max + 1, nq = 4 * m_max + 1;
+  const int NDM = m_max <= 2 ? 5 : 9, NQM = m_max <= 2 ? 9 : 17;
+  AngleRule g{};
+  g.nd = nd;
+  g.nq = nq;
+  g.dd = 2.0 * 3.14159265358979323846 / nd;
+  g.dq = 2.0 * 3.14159265358979323846 / nq;
+  p->am = g;
+  hipStream_t st = (hipStream_t)stream;
+  p->last = st;
+  const bool sorted = p->cfg.sort != 0;
+  if (sorted && !p->bin_ready) return RIFT_EUNSUPPORTED;
+  // stream-ordered scratch: the coefficients [2 nd + 3 nq][N], the tables,
+  // and the per-sample values when the caller takes none
+  const int64_t N = p->N;
+  const size_t rows = (size_t)(2 * nd + 3 * nq);
+  const size_t nwd = (size_t)rule->n_phi * NDM, nwq = (size_t)rule->n_phi * NQM, ntu = 4 * (size_t)rule->n_psi;
+  const size_t bytes = sizeof(double) * (rows * N + nwd + nwq + ntu + (lnLa ? 0 : (size_t)N));
+  double* w = nullptr;
+  if (hipMallocAsync((void**)&w, bytes, st) != hipSuccess) return RIFT_ENOMEM;
+  double* wd = w + rows * N;
+  double* wq = wd + nwd;
+  double* tu = wq + nwq;
+  double* L = lnLa ? lnLa : tu + ntu;
+  p->ang = w;
+  int rc = sorted ? run_binning(p, theta, st) : RIFT_OK;
+  if (!rc) rc = launch_tiles(p, MODE_ERAI64, theta, lnw, L, st);
+  p->ang = nullptr;
+  if (!rc) {
+    const size_t big = std::max(std::max(nwd, nwq), (size_t)rule->n_psi);
+    hipLaunchKernelGGL(k_erai_tables, dim3((unsigned)std::min<size_t>((big + 255) / 256, 1024)), dim3(256), 0, st,
+                       rule->n_phi, rule->n_psi, nd, nq, NDM, NQM, wd, wq, tu);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, (int64_t)p->di.n_cu * 8));
+    const double ln_scale = -log((double)rule->n_phi * (double)rule->n_psi);
+    if (NDM == 5)
+      hipLaunchKernelGGL((k_erai<5, 9>), dim3(grid), dim3(256), 0, st, N, nd, nq, rule->n_phi, rule->n_psi,
+                         (const double*)w, (const double*)wd, (const double*)wq, (const double*)tu, ln_scale, L);
+    else
+      hipLaunchKernelGGL((k_erai<9, 17>), dim3(grid), dim3(256), 0, st, N, nd, nq, rule->n_phi, rule->n_psi,
+                         (const double*)w, (const double*)wd, (const double*)wq, (const double*)tu, ln_scale, L);
     if (p->n_tiles > 0)
       hipLaunchKernelGGL(k_lse_tiles, dim3(p->n_tiles), dim3(p->cfg.block), 0, st, p->d_tiles, (const double*)L,
                          lnw, p->d_part);

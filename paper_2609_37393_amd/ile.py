@@ -67,6 +67,7 @@ EXPORTS = (
     "rift_ile_plan_lnZ_pmarg",
     "rift_ile_plan_hmc",
     "rift_ile_plan_lnZ_tband",
+    "rift_ile_plan_lnZ_erai",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -132,6 +133,10 @@ class CBandRule(ctypes.Structure):
                 ("n_fine", ctypes.c_int32)]
 
 
+class CAngleRule(ctypes.Structure):
+    _fields_ = [("n_phi", ctypes.c_int32), ("n_psi", ctypes.c_int32)]
+
+
 class CHmcPrior(ctypes.Structure):
     _fields_ = [("t_min", ctypes.c_double), ("t_max", ctypes.c_double), ("d_min", ctypes.c_double),
                 ("d_max", ctypes.c_double)]
@@ -179,6 +184,7 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_pregrid.argtypes = [vp, i64, i32, i32, vp, vp]
     lib.rift_ile_plan_lnZ_tmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CTimeRule), vp, vp, vp, vp]
     lib.rift_ile_plan_lnZ_pmarg.argtypes = [vp, vp, vp, ctypes.POINTER(CPsiRule), vp, vp, vp, vp]
+    lib.rift_ile_plan_lnZ_erai.argtypes = [vp, vp, vp, ctypes.POINTER(CAngleRule), vp, vp, vp, vp]
     lib.rift_ile_plan_lnZ_tband.argtypes = [vp, vp, vp, ctypes.POINTER(CBandRule), vp, vp, vp, vp]
     lib.rift_ile_plan_hmc.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, i32,
                                       ctypes.POINTER(CHmcPrior), vp, vp, vp]
@@ -528,6 +534,22 @@ class Plan:
                                                 ctypes.byref(rule), z.data_ptr(), ne.data_ptr(),
                                                 None if lnL_out is None else lnL_out.data_ptr(),
                                                 _stream(self.device)), "rift_ile_plan_lnZ_tband")
+        return z, ne
+
+    def lnZ_erai(self, theta, n_phi, n_psi, lnw=None, lnZ_out=None, neff_out=None, lnL_out=None):
+        """(ln Z, n_eff) per point of the likelihood marginalised over phiref
+        and psi by exact reconstruction (rift_ile_plan_lnZ_erai) on an
+        n_phi x n_psi grid; lnL_out receives the per-sample marginal."""
+        th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
+            else _theta(theta, self.device)
+        P = len(self.points)
+        z = lnZ_out if lnZ_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        ne = neff_out if neff_out is not None else torch.empty(P, dtype=torch.float64, device=self.device)
+        rule = CAngleRule(int(n_phi), int(n_psi))
+        _check(self.lib.rift_ile_plan_lnZ_erai(self.handle, th.data_ptr(), None if lnw is None else lnw.data_ptr(),
+                                               ctypes.byref(rule), z.data_ptr(), ne.data_ptr(),
+                                               None if lnL_out is None else lnL_out.data_ptr(),
+                                               _stream(self.device)), "rift_ile_plan_lnZ_erai")
         return z, ne
 
     def lnZ_pmarg(self, theta, method="trapezoid", n_points=64, lnw=None, lnZ_out=None, neff_out=None,

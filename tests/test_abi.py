@@ -236,6 +236,14 @@ def test_tband_null_plan(lib):
     assert lib.rift_ile_plan_lnZ_tband(0x1000, 0x4000, None, None, 0x5000, None, None, None) == EINVAL
 
 
+def test_erai_null_plan(lib):
+    from paper_2609_37393_amd import ile
+
+    rule = ile.CAngleRule(32, 16)
+    assert lib.rift_ile_plan_lnZ_erai(None, 0x4000, None, ctypes.byref(rule), 0x5000, None, None, None) == EINVAL
+    assert lib.rift_ile_plan_lnZ_erai(0x1000, 0x4000, None, None, 0x5000, None, None, None) == EINVAL
+
+
 def test_wide_rotation_rate_limit(lib):
     """Under rotation the turn over the light-travel time, |omega| |r_k|, must
     stay within one radian."""
