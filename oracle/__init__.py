@@ -13,9 +13,11 @@ fixed-spacing rule over time, Eq. (ap:tfixed)), ``lnL_tband`` (the
 band-limited full-window rule over time, Eq. (ap:tband)), ``lnL_erai`` (the
 joint marginal over phiref and psi by exact reconstruction, Eqs.
 (ap:angleharm), (ap:nyquist)) and ``lnL_pmarg`` (the
-polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)) and ``hmc_step``
-(a Metropolis-adjusted Hamiltonian transition on the gradient) are written
-here in numpy on top of the C likelihood.
+polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)), ``hmc_step``
+(a Metropolis-adjusted Hamiltonian transition on the gradient, optionally
+on the tempered target) and the SMC ladder's ``smc_cess``, ``smc_next_beta``,
+``smc_update`` and ``systematic_resample`` (Eq. (sampler-menu:smc-update))
+are written here in numpy on top of the C likelihood.
 
 Every function states the passage of the paper it follows.  Parity status of
 each function (what pins it) is listed in the tests' docstrings.
@@ -560,24 +562,26 @@ def hmc_log_prior(c, t_min, t_max, d_min, d_max):
     return np.where(inside, v, -np.inf)
 
 
-def hmc_potential(pt, c, t_min, t_max, d_min, d_max):
-    """(lnL, U = -lnL - ln prior, dU/dc) in the sampler coordinates."""
+def hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta=1.0):
+    """(lnL, U = -beta lnL - ln prior, dU/dc) in the sampler coordinates: the
+    tempered target L^beta p of Eq. (sampler-menu:tempered-target) (beta = 1:
+    the posterior)."""
     l, g = grad(pt, _to_physical(c))
     lp = hmc_log_prior(c, t_min, t_max, d_min, d_max)
     gp = np.zeros_like(g)
     gp[1] = -np.tan(c[1])
     gp[6] = 3.0
-    return l, -(l + lp), -(g + gp)
+    return l, -(beta * l + lp), -(beta * g + gp)
 
 
-def hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max):
+def hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta=1.0):
     """n_leapfrog leapfrog steps from (c0, p0): half kick, drift c += eps
     sigma^2 p with cos incl folded back into [-1, 1] (period 4) and its
     momentum negated on odd folds, half kick.  Returns (c, p, lnL, U)."""
     sig = np.asarray(sigma, np.float64)[:, None]
     c = np.array(c0, np.float64, copy=True)
     p = np.array(p0, np.float64, copy=True)
-    l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max)
+    l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta)
     for _ in range(int(n_leapfrog)):
         p = p - 0.5 * eps * gU
         c = c + eps * sig * sig * p
@@ -587,12 +591,12 @@ def hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_ma
         flip = np.zeros(c.shape[1], bool)
         flip[np.where(out)[0][r > 2.0]] = True
         p[3][flip] = -p[3][flip]
-        l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max)
+        l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta)
         p = p - 0.5 * eps * gU
     return c, p, l, U
 
 
-def hmc_step(pt, c0, z, u, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max):
+def hmc_step(pt, c0, z, u, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta=1.0):
     """One Metropolis-adjusted Hamiltonian Monte Carlo transition per chain
     (the gradient sampler of Sec. "Sampling the differentiable extrinsic
     likelihood"), with the random inputs given: momenta p = z / sigma (mass
@@ -601,18 +605,91 @@ def hmc_step(pt, c0, z, u, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max):
     sampler coordinates plus the prior's, the drift c += eps sigma^2 p with
     cos incl reflected at +-1 and its momentum flipped), then acceptance when
     ln u < H0 - H1 with H = U + sum sigma^2 p^2 / 2.  Returns (c, lnL at c,
-    accepted)."""
+    accepted).  With beta < 1 the target is the tempered L^beta p of Eq.
+    (sampler-menu:tempered-target) (the moves of an SMC ladder)."""
     sig = np.asarray(sigma, np.float64)[:, None]
-    l0, U0, _ = hmc_potential(pt, c0, t_min, t_max, d_min, d_max)
+    l0, U0, _ = hmc_potential(pt, c0, t_min, t_max, d_min, d_max, beta)
     p0 = np.asarray(z, np.float64) / sig
     H0 = U0 + 0.5 * np.sum(sig * sig * p0 * p0, axis=0)
-    c, p, l1, U1 = hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max)
+    c, p, l1, U1 = hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta)
     H1 = U1 + 0.5 * np.sum(sig * sig * p * p, axis=0)
     with np.errstate(invalid="ignore"):
         acc = np.log(np.asarray(u, np.float64)) < (H0 - H1)
     acc &= np.isfinite(H1)
     cout = np.where(acc[None, :], c, c0)
     return cout, np.where(acc, l1, l0), acc
+
+
+def _lse(v):
+    v = np.asarray(v, np.float64)
+    m = np.max(v)
+    if not np.isfinite(m):
+        return m if not np.isnan(v).any() else np.nan
+    return m + np.log(np.sum(np.exp(v - m)))
+
+
+def _tempered(lnL, dbeta):
+    """dbeta ln L with L^0 = 1 also where L = 0 (ln L = -inf)."""
+    lnL = np.asarray(lnL, np.float64)
+    return np.zeros_like(lnL) if dbeta == 0.0 else dbeta * lnL
+
+
+def smc_cess(lnW, lnL, dbeta):
+    """Conditional effective sample size fraction of the incremental weights
+    r_i = L_i^dbeta of Eq. (sampler-menu:smc-update) under the current
+    normalised weights W: (sum W r)^2 / sum W r^2, in (0, 1] (1 at dbeta = 0).
+    Computed in log space."""
+    lnW = np.asarray(lnW, np.float64)
+    lnL = np.asarray(lnL, np.float64)
+    lw = lnW - _lse(lnW)
+    return float(np.exp(2.0 * _lse(lw + _tempered(lnL, dbeta)) - _lse(lw + _tempered(lnL, 2.0 * dbeta))))
+
+
+def smc_next_beta(lnW, lnL, beta, target):
+    """The next rung of the tempering ladder chosen from the effective sample
+    size of the incremental weights: the largest beta' in (beta, 1] with
+    smc_cess(beta' - beta) >= target (the fraction is non-increasing in the
+    step: it is 2 K(d) - K(2 d) for the convex cumulant function K), 1 if the
+    whole remaining step qualifies; by bisection to the rounding of the
+    step."""
+    rest = 1.0 - beta
+    if smc_cess(lnW, lnL, rest) >= target:
+        return 1.0
+    lo, hi = 0.0, rest
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if smc_cess(lnW, lnL, mid) >= target:
+            lo = mid
+        else:
+            hi = mid
+    return beta + lo
+
+
+def smc_update(lnW, lnL, beta, beta_new):
+    """The normalisation update of Eq. (sampler-menu:smc-update): with W the
+    normalised weights at beta and r_i = L_i^(beta_new - beta),
+    ln(Z_new / Z_old) = ln sum_i W_i r_i, and the new normalised log weights
+    ln W_i + ln r_i - that.  Returns (dlnZ, lnW_new)."""
+    lnW = np.asarray(lnW, np.float64)
+    lw = lnW - _lse(lnW)
+    v = lw + _tempered(lnL, beta_new - beta)
+    d = _lse(v)
+    return d, v - d
+
+
+def systematic_resample(lnW, u):
+    """Systematic resampling of n draws from the normalised weights with one
+    uniform u in [0, 1): a_i = the first k whose cumulative weight exceeds
+    (i + u) / n."""
+    lnW = np.asarray(lnW, np.float64)
+    n = lnW.size
+    w = np.exp(lnW - _lse(lnW))
+    C = np.cumsum(w)
+    U = (np.arange(n) + u) / n
+    a = np.searchsorted(C, U, side="right")
+    return np.minimum(a, n - 1)
 
 
 def rotation_harmonics(det_tensor, dec, psi):

@@ -1,0 +1,118 @@
+"""Pins of the oracle's SMC ladder (Eq. (sampler-menu:smc-update) on the
+tempered targets of Eq. (sampler-menu:tempered-target)) and of its tempered
+moves, against what the mathematics fixes:
+
+* the normalisation ratios telescope: without resampling, the sum of the
+  updates from beta = 0 to 1 is the prior-Monte-Carlo estimate
+  ln[(1/N) sum_i L_i] (Eq. (sampler-menu:is) with q = p), and the final
+  weights are proportional to L;
+* the effective-size fraction lies in [1/N, 1] (Cauchy-Schwarz), is 1 at a
+  zero step and for a constant likelihood, tends to 1/N when one sample
+  dominates, and does not increase with the step;
+* the chosen rung meets the target fraction (or is the last rung);
+* systematic resampling draws every index floor(N W) or ceil(N W) times, in
+  order, and is the identity for equal weights;
+* the tempered potential's gradient is the derivative of the tempered
+  potential, and at beta = 0 only the prior remains.
+"""
+import numpy as np
+
+from paper_2609_37393_amd import synth
+
+
+def _lnL(n, seed, spread=40.0):
+    rng = np.random.default_rng(seed)
+    return -0.5 * spread * rng.chisquare(3, n)
+
+
+def test_updates_telescope_to_prior_monte_carlo(oracle_mod):
+    lnL = _lnL(5000, 1)
+    lnW = np.zeros(5000)
+    total = 0.0
+    betas = [0.0, 0.02, 0.1, 0.35, 0.7, 1.0]
+    for b0, b1 in zip(betas[:-1], betas[1:]):
+        d, lnW = oracle_mod.smc_update(lnW, lnL, b0, b1)
+        total += d
+    m = lnL.max()
+    want = m + np.log(np.mean(np.exp(lnL - m)))
+    assert abs(total - want) <= 1e-12 * max(1.0, abs(want))
+    ref = lnL - (m + np.log(np.sum(np.exp(lnL - m))))
+    assert np.max(np.abs(lnW - ref)) <= 1e-10
+
+
+def test_cess_bounds_and_monotone(oracle_mod):
+    n = 400
+    lnL = _lnL(n, 2)
+    lnW = np.random.default_rng(3).normal(size=n)
+    assert abs(oracle_mod.smc_cess(lnW, lnL, 0.0) - 1.0) <= 1e-14
+    assert abs(oracle_mod.smc_cess(lnW, np.full(n, -3.7), 0.8) - 1.0) <= 1e-14
+    prev = 1.0
+    for d in np.linspace(0.0, 1.0, 41)[1:]:
+        c = oracle_mod.smc_cess(lnW, lnL, d)
+        assert 1.0 / n - 1e-15 <= c <= prev + 1e-15
+        prev = c
+    spike = np.zeros(n)
+    spike[7] = 1e4
+    assert abs(oracle_mod.smc_cess(np.zeros(n), spike, 1.0) - 1.0 / n) <= 1e-12
+    # -inf likelihoods drop out of every step but the zero step
+    lnL2 = lnL.copy()
+    lnL2[::5] = -np.inf
+    assert abs(oracle_mod.smc_cess(lnW, lnL2, 0.0) - 1.0) <= 1e-14
+    assert 0 < oracle_mod.smc_cess(lnW, lnL2, 0.3) < 1
+
+
+def test_next_rung_meets_the_target(oracle_mod):
+    n = 2000
+    lnL = _lnL(n, 4)
+    lnW = np.zeros(n)
+    beta = 0.0
+    for target in (0.5, 0.8, 0.3):
+        b = oracle_mod.smc_next_beta(lnW, lnL, beta, target)
+        assert beta < b <= 1.0
+        if b < 1.0:
+            assert abs(oracle_mod.smc_cess(lnW, lnL, b - beta) - target) <= 1e-9
+        _, lnW = oracle_mod.smc_update(lnW, lnL, beta, b)
+        beta = b
+    assert oracle_mod.smc_next_beta(lnW, lnL, beta, 1e-6) == 1.0
+    # a larger target takes a smaller step
+    assert oracle_mod.smc_next_beta(np.zeros(n), lnL, 0.0, 0.9) < oracle_mod.smc_next_beta(np.zeros(n), lnL, 0.0, 0.5)
+
+
+def test_systematic_resampling_counts(oracle_mod):
+    rng = np.random.default_rng(5)
+    for n in (1, 7, 1000):
+        lnW = rng.normal(size=n) * 3
+        W = np.exp(lnW - lnW.max())
+        W /= W.sum()
+        for u in (0.0, 0.37, 0.999):
+            a = oracle_mod.systematic_resample(lnW, u)
+            assert a.shape == (n,) and np.all(np.diff(a) >= 0) and a.min() >= 0 and a.max() < n
+            cnt = np.bincount(a, minlength=n)
+            assert np.all(cnt >= np.floor(n * W - 1e-9)) and np.all(cnt <= np.ceil(n * W + 1e-9))
+    assert np.array_equal(oracle_mod.systematic_resample(np.zeros(50), 0.5), np.arange(50))
+
+
+def test_tempered_potential(oracle_mod):
+    sig = np.array([1e-3, 1e-3, 5e-3, 5e-3, 5e-3, 3e-6, 5e-3])
+    box = (-0.01, 0.01, 10.0, 1000.0)
+    pt = synth.make_point(3, 9, 6554, 32768.0, 100.0, 41)
+    th, _ = synth.weighted_samples(2000, 42)
+    best = th[:, np.argmax(oracle_mod.lnL(pt, th))]
+    c = synth.perturbed_samples(best, sig, 5, 43)
+    c[3] = np.cos(c[3])
+    c[6] = np.log(c[6])
+    beta = 0.3
+    l, U, gU = oracle_mod.hmc_potential(pt, c, *box, beta=beta)
+    lp = oracle_mod.hmc_log_prior(c, *box)
+    assert np.allclose(U, -(beta * l + lp), rtol=0, atol=1e-9 * np.abs(l).max())
+    h = np.array([1e-6, 1e-6, 1e-6, 1e-6, 1e-6, 1e-10, 1e-6])
+    for a in range(7):
+        cp, cm = c.copy(), c.copy()
+        cp[a] += h[a]
+        cm[a] -= h[a]
+        fd = (oracle_mod.hmc_potential(pt, cp, *box, beta=beta)[1] -
+              oracle_mod.hmc_potential(pt, cm, *box, beta=beta)[1]) / (2 * h[a])
+        assert np.all(np.abs(fd - gU[a]) <= 1e-4 * (np.abs(gU[a]) + np.abs(fd)) + 1e-3 * np.abs(U) * 1e-9 / h[a]), a
+    _, U0, g0 = oracle_mod.hmc_potential(pt, c, *box, beta=0.0)
+    assert np.array_equal(U0, -lp)
+    assert np.all(g0[[0, 2, 3, 4, 5]] == 0) and np.allclose(g0[1], np.tan(c[1])) and np.all(g0[6] == -3.0)
