@@ -895,15 +895,81 @@ def extra_hmc(ile, synth, torch, steps, chains=16384, n_leapfrog=8, cpu=True):
     return res
 
 
+def extra_smc(ile, synth, torch, steps, particles=65536, cpu=True):
+    """An adaptive SMC ladder (Eqs. (sampler-menu:tempered-target),
+    (sampler-menu:smc-update)) from the prior to the posterior of a 3-detector,
+    9-mode point at SNR 10: 65536 particles; per rung the library's reweight
+    (rung chosen at a conditional effective-size fraction of 0.5),
+    systematic resampling, and two tempered HMC moves (4 leapfrog steps of
+    0.25, proposal widths 0.2 x the cloud's spread).  The caller's logic
+    (widths, random numbers, the loop) is host code; every per-particle step
+    is a library kernel."""
+    pt = synth.make_point(3, 9, 6554, 32768.0, 10.0, 44)
+    n = particles
+    box = (-0.01, 0.01, 10.0, 1000.0)
+    th = synth.prior_samples(n, 5)
+    th[3] = np.cos(th[3])
+    th[6] = np.log(th[6])
+    plan = ile.Plan([pt], [n])
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+
+    def ladder():
+        c = torch.as_tensor(th, device="cuda").contiguous()
+        c2 = torch.empty_like(c)
+        lnL = torch.empty(n, dtype=torch.float64, device="cuda")
+        g = torch.empty((7, n), dtype=torch.float64, device="cuda")
+        plan.grad(0, c, lnL_out=lnL, grad_out=g, coords="sampler")
+        lnW = torch.zeros(n, dtype=torch.float64, device="cuda")
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        beta, lnZ, rungs, acc_sum = 0.0, 0.0, 0, 0.0
+        while beta < 1.0 and rungs < 200:
+            ile.smc_reweight(lnL, lnW, beta, 0.5, out=out)
+            o = out.cpu().numpy()
+            beta, lnZ, rungs = float(o[0]), lnZ + float(o[1]), rungs + 1
+            u = float(torch.rand(1, generator=gen, device="cuda").item())
+            anc = torch.empty(n, dtype=torch.int64, device="cuda")
+            ile.smc_resample(lnW, u, c, c2, anc)
+            c, c2 = c2, c
+            lnW.zero_()  # the moves below return lnL at the moved particles
+            sig = np.maximum(0.2 * c.std(dim=1).cpu().numpy(), 1e-12)
+            for _ in range(2):
+                z = torch.randn((7, n), dtype=torch.float64, device="cuda", generator=gen)
+                uu = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+                _, acc = plan.hmc(0, c, z, uu, sig, 0.25, 4, box, lnL_out=lnL, beta=beta)
+                acc_sum += float(acc.double().mean().item())
+        return beta, lnZ, rungs, acc_sum / max(1, 2 * rungs)
+
+    ladder()  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    beta, lnZ, rungs, acc = ladder()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # the same normalisation by prior Monte Carlo on 1e6 fresh prior draws
+    thp = synth.prior_samples(4_000_000, 6)
+    zp, nep = ile.lnZ([pt], thp)
+    # the reweight alone at this size
+    lnLt = torch.as_tensor(-0.5 * 40.0 * np.random.default_rng(1).chisquare(3, n), device="cuda")
+    lnWt = torch.zeros(n, dtype=torch.float64, device="cuda")
+    secs, _ = time_steps(lambda: ile.smc_reweight(lnLt, lnWt.zero_(), 0.0, 0.5), 10, 2, torch)
+    plan.close()
+    return {"workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 10; 65536 particles from the "
+                        "prior; adaptive SMC ladder (target fraction 0.5), 2 tempered HMC moves per rung",
+            "rungs": rungs, "ladder_ms": 1e3 * wall, "ms_per_rung": 1e3 * wall / max(1, rungs),
+            "final_beta": beta, "lnZ_smc": lnZ, "lnZ_prior_mc_4e6": float(zp[0]), "neff_prior_mc": float(nep[0]),
+            "move_acceptance": acc, "reweight_ms": 1e3 * secs / 10}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,tband,pmarg,erai,hmc",
+    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,tband,pmarg,erai,hmc,smc",
                     help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, pregrid, "
-                         "tmarg, tband, pmarg, erai, hmc, "
+                         "tmarg, tband, pmarg, erai, hmc, smc, "
                          "c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
@@ -1028,7 +1094,7 @@ def main():
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
            "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg, "pregrid": extra_pregrid,
            "tmarg": extra_tmarg, "tband": extra_tband, "pmarg": extra_pmarg, "erai": extra_erai,
-           "hmc": extra_hmc}
+           "hmc": extra_hmc, "smc": extra_smc}
     for name in wanted:
         log(f"workload {name}")
         try:

@@ -479,6 +479,43 @@ int rift_ile_plan_hmc(rift_ile_plan plan, int32_t point, int64_t n, double *thet
                       const double *sigma, double eps, int32_t n_leapfrog, const rift_ile_hmc_prior *prior,
                       double *lnL, int32_t *accepted, void *stream);
 
+/* The same transition on the tempered target L^beta p of Eq.
+ * (sampler-menu:tempered-target), 0 <= beta <= 1 (the moves of an SMC
+ * ladder): U = -beta lnL - ln prior; lnL (the output) stays the untempered
+ * likelihood.  beta = 1 is rift_ile_plan_hmc bit for bit.  RIFT_EINVAL for
+ * beta outside [0, 1], otherwise as rift_ile_plan_hmc. */
+int rift_ile_plan_hmc_tempered(rift_ile_plan plan, int32_t point, int64_t n, double *theta, const double *z,
+                               const double *u, const double *sigma, double eps, int32_t n_leapfrog,
+                               const rift_ile_hmc_prior *prior, double beta, double *lnL, int32_t *accepted,
+                               void *stream);
+
+/* One update of an SMC tempering ladder (Sec. "Sampler menu",
+ * Eq. (sampler-menu:smc-update)) over n weighted particles: with W the
+ * normalised weights from lnW (DEVICE [n], any normalisation; -inf excludes a
+ * particle) and lnL (DEVICE [n]) their log-likelihoods, the next rung is the
+ * largest beta' in (beta, 1] whose incremental weights r = L^(beta' - beta)
+ * keep the conditional effective-size fraction (sum W r)^2 / sum W r^2 at or
+ * above `target` (0 < target <= 1), or 1 if the whole remaining step does;
+ * then ln(Z_beta' / Z_beta) = ln sum W r and lnW is replaced by the normalised
+ * ln(W r) (in place).  out: DEVICE [2] = (beta', dlnZ).  The search is a
+ * safeguarded Newton iteration on the log fraction (non-increasing in the
+ * step), a fixed 40 passes at most, all on the device: enqueues and returns,
+ * with stream-ordered scratch of about 50 KB.  A NaN input gives NaN
+ * outputs.  RIFT_EINVAL: n < 1, beta outside [0, 1], target outside (0, 1],
+ * null or misaligned pointers. */
+int rift_ile_smc_reweight(int64_t n, const double *lnL, double *lnW, double beta, double target, double *out,
+                          void *stream);
+
+/* Systematic resampling of n particles with one uniform u in [0, 1): draw i
+ * takes the first particle whose normalised cumulative weight exceeds
+ * (i + u) / n.  lnW: DEVICE [n]; theta_in, theta_out: DEVICE [7][n], distinct,
+ * both NULL or both given (theta_out[:, i] = theta_in[:, a_i]); ancestors:
+ * DEVICE int64 [n] (a_i) or NULL, not both outputs NULL.  The caller resets
+ * the weights to equal afterwards.  Enqueues and returns, with
+ * stream-ordered scratch of about 8 n bytes. */
+int rift_ile_smc_resample(int64_t n, const double *lnW, double u, const double *theta_in, double *theta_out,
+                          int64_t *ancestors, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): rift_ile_lnZ with

@@ -70,8 +70,8 @@ __device__ __forceinline__ double dlnpi(int a, double g, double dec) {
 // energy H0 = -lnL - ln prior + sum sigma^2 p^2 / 2, then the first half kick
 // p += h dlnpi/dc and the first drift.
 __global__ void k_hmc_first(int64_t n, double* __restrict__ c, const double* __restrict__ z,
-                            const double* __restrict__ g, const double* __restrict__ lnL, double h, Step7 sig,
-                            Step7 step, HmcPrior P, double* __restrict__ p, double* __restrict__ c0,
+                            const double* __restrict__ g, const double* __restrict__ lnL, double h, double beta,
+                            Step7 sig, Step7 step, HmcPrior P, double* __restrict__ p, double* __restrict__ c0,
                             double* __restrict__ H0, double* __restrict__ lnL0) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double ca[7], pa[7];
@@ -85,12 +85,12 @@ __global__ void k_hmc_first(int64_t n, double* __restrict__ c, const double* __r
       c0[a * n + i] = ca[a];
     }
     const double l = lnL[i];
-    H0[i] = -(l + hmc_log_prior(P, ca[1], ca[3], ca[5], ca[6])) + 0.5 * kin;
+    H0[i] = -(beta * l + hmc_log_prior(P, ca[1], ca[3], ca[5], ca[6])) + 0.5 * kin;
     lnL0[i] = l;
     const double dec = ca[1];
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      pa[a] = fma(h, dlnpi(a, g[a * n + i], dec), pa[a]);
+      pa[a] = fma(h, dlnpi(a, beta * g[a * n + i], dec), pa[a]);
       c[a * n + i] = drift_one(a, ca[a], pa[a], step.s[a]);
       p[a * n + i] = pa[a];
     }
@@ -100,12 +100,12 @@ __global__ void k_hmc_first(int64_t n, double* __restrict__ c, const double* __r
 // Between two drifts: the half kick that ends one leapfrog step and the one
 // that starts the next (both at the current state), then the drift.
 __global__ void k_hmc_mid(int64_t n, double* __restrict__ c, double* __restrict__ p, const double* __restrict__ g,
-                          double h, Step7 step) {
+                          double h, double beta, Step7 step) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double dec = c[n + i];
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      const double ga = dlnpi(a, g[a * n + i], dec);
+      const double ga = dlnpi(a, beta * g[a * n + i], dec);
       double pa = fma(h, ga, p[a * n + i]);
       pa = fma(h, ga, pa);
       c[a * n + i] = drift_one(a, c[a * n + i], pa, step.s[a]);
@@ -117,7 +117,7 @@ __global__ void k_hmc_mid(int64_t n, double* __restrict__ c, double* __restrict_
 // The last half kick, the final energy, acceptance against ln u and the
 // returned state: the proposal if accepted, else the start state and its lnL.
 __global__ void k_hmc_end(int64_t n, double* __restrict__ c, const double* __restrict__ p,
-                          const double* __restrict__ g, const double* __restrict__ lnL1, double h,
+                          const double* __restrict__ g, const double* __restrict__ lnL1, double h, double beta,
                           const double* __restrict__ c0, const double* __restrict__ lnL0,
                           const double* __restrict__ H0, const double* __restrict__ u, Step7 sig, HmcPrior P,
                           double* __restrict__ lnL_out, int32_t* __restrict__ accepted) {
@@ -126,11 +126,12 @@ __global__ void k_hmc_end(int64_t n, double* __restrict__ c, const double* __res
     double kin = 0.0;
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      const double pa = fma(h, dlnpi(a, g[a * n + i], dec), p[a * n + i]);
+      const double pa = fma(h, dlnpi(a, beta * g[a * n + i], dec), p[a * n + i]);
       const double v = sig.s[a] * pa;
       kin = fma(v, v, kin);
     }
-    const double H1 = -(lnL1[i] + hmc_log_prior(P, dec, c[3 * n + i], c[5 * n + i], c[6 * n + i])) + 0.5 * kin;
+    const double H1 =
+        -(beta * lnL1[i] + hmc_log_prior(P, dec, c[3 * n + i], c[5 * n + i], c[6 * n + i])) + 0.5 * kin;
     const double d = H0[i] - H1;
     const bool acc = (fabs(H1) <= 1.0e300) && (log(u[i]) < d);
     if (!acc) {
@@ -142,7 +143,318 @@ __global__ void k_hmc_end(int64_t n, double* __restrict__ c, const double* __res
   }
 }
 
+// ---------------------------------------------------------------------------
+// The SMC ladder's update (Eq. (sampler-menu:smc-update)) on the tempered
+// targets L^beta p (Eq. (sampler-menu:tempered-target)).  Log-sums run
+// online as (max, sum e^{v - max}, sum e^{v - max} l) triples with one exp
+// per term and no divergent branch; L^0 = 1 also where ln L = -inf.
+// ---------------------------------------------------------------------------
+constexpr int SMC_BLOCK = 256;
+constexpr int SMC_GRID_MAX = 1024;
+constexpr int SMC_ITERS = 40;
+
+struct Acc3 {
+  double m, s, t;
+};
+
+__device__ __forceinline__ void acc_push(Acc3& a, double v, double l) {
+  if (v == -__builtin_inf()) return;
+  const double d = v - a.m;
+  const double e = exp(-fabs(d));
+  const bool up = d > 0.0;
+  a.s = up ? fma(a.s, e, 1.0) : a.s + e;
+  a.t = up ? fma(a.t, e, l) : fma(e, l, a.t);
+  a.m = up ? v : a.m;
+}
+
+__device__ __forceinline__ Acc3 acc_merge(Acc3 a, Acc3 b) {
+  if (b.m == -__builtin_inf() && b.s == 0.0) return a;
+  if (a.m == -__builtin_inf() && a.s == 0.0) return b;
+  const double m = fmax(a.m, b.m);
+  const double ea = exp(a.m - m), eb = exp(b.m - m);
+  Acc3 r;
+  r.m = (a.m == a.m && b.m == b.m) ? m : __builtin_nan("");
+  r.s = a.s * ea + b.s * eb;
+  r.t = a.t * ea + b.t * eb;
+  return r;
+}
+
+// Block reduction of one triple (SMC_BLOCK threads); the result in thread 0.
+__device__ Acc3 acc_block(Acc3 a, Acc3* sh) {
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = SMC_BLOCK / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = acc_merge(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__device__ __forceinline__ double tempered(double d, double l) { return d == 0.0 ? 0.0 : d * l; }
+
+struct SmcState {
+  double lnS;        // ln sum_i W_i of the input weights
+  double rest;       // 1 - beta
+  double lo, hi, d;  // bracket of the step and the current step
+  int32_t done, iter;
+};
+
+// Pass over the samples: with which = 0 the triple of lnW alone; with
+// which = 1 the triples of lnW + d l and lnW + 2 d l at the state's step
+// (skipped once the search is done unless `force`).
+__global__ void __launch_bounds__(SMC_BLOCK) k_smc_pass(int64_t n, const double* __restrict__ lnW,
+                                                       const double* __restrict__ lnL,
+                                                       const SmcState* __restrict__ st, int which, int force,
+                                                       Acc3* __restrict__ part) {
+  __shared__ Acc3 sh[SMC_BLOCK];
+  if (which == 1 && st->done && !force) return;
+  const double d = which == 1 ? st->d : 0.0;
+  Acc3 a1{-__builtin_inf(), 0.0, 0.0}, a2{-__builtin_inf(), 0.0, 0.0};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double w = lnW[i];
+    if (which == 0) {
+      acc_push(a1, w, 0.0);
+    } else {
+      const double l = lnL[i];
+      acc_push(a1, w + tempered(d, l), l);
+      acc_push(a2, w + tempered(2.0 * d, l), l);
+    }
+  }
+  const Acc3 r1 = acc_block(a1, sh);
+  __syncthreads();
+  const Acc3 r2 = acc_block(a2, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r1;
+    part[2 * blockIdx.x + 1] = r2;
+  }
+}
+
+__device__ Acc3 combine_parts(int nb, const Acc3* __restrict__ part, int which, Acc3* sh) {
+  Acc3 a{-__builtin_inf(), 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) a = acc_merge(a, part[2 * b + which]);
+  return acc_block(a, sh);
+}
+
+// The input weights' normaliser; the search starts at the whole remaining step.
+__global__ void __launch_bounds__(SMC_BLOCK) k_smc_init(int nb, const Acc3* __restrict__ part, double rest,
+                                                       SmcState* __restrict__ st) {
+  __shared__ Acc3 sh[SMC_BLOCK];
+  const Acc3 r = combine_parts(nb, part, 0, sh);
+  if (threadIdx.x == 0) {
+    st->lnS = r.m + log(r.s);
+    st->rest = rest;
+    st->lo = 0.0;
+    st->hi = rest;
+    st->d = rest;
+    st->done = rest == 0.0 ? 1 : 0;
+    st->iter = 0;
+  }
+}
+
+// One step of the safeguarded Newton search for the largest step d in
+// (0, rest] with ln cess(d) = 2 K(d) - K(2 d) >= ln target, K(d) =
+// ln sum_i W_i L_i^d: the function is non-increasing in d with derivative
+// 2 (mean_d l - mean_2d l), the means under the tilted weights.  A step that
+// leaves the bracket bisects it instead.
+__global__ void __launch_bounds__(SMC_BLOCK) k_smc_step(int nb, const Acc3* __restrict__ part, double ln_target,
+                                                       SmcState* __restrict__ st) {
+  __shared__ Acc3 sh[SMC_BLOCK];
+  if (st->done) return;
+  const Acc3 r1 = combine_parts(nb, part, 0, sh);
+  __syncthreads();
+  const Acc3 r2 = combine_parts(nb, part, 1, sh);
+  if (threadIdx.x != 0) return;
+  const double K1 = r1.m + log(r1.s) - st->lnS, K2 = r2.m + log(r2.s) - st->lnS;
+  const double f = 2.0 * K1 - K2 - ln_target;
+  const double fp = 2.0 * (r1.t / r1.s - r2.t / r2.s);
+  double d = st->d, lo = st->lo, hi = st->hi;
+  if (!(f == f)) {
+    st->d = __builtin_nan("");
+    st->done = 1;
+    return;
+  }
+  if (st->iter == 0 && f >= 0.0) {
+    st->done = 1;  // the whole remaining step qualifies
+    return;
+  }
+  if (f >= 0.0) lo = d;
+  else hi = d;
+  double dn = d - f / fp;
+  if (!(dn > lo && dn < hi)) dn = 0.5 * (lo + hi);
+  const bool conv = fabs(dn - d) <= 4e-16 * d || hi - lo <= 4e-16 * hi;
+  st->lo = lo;
+  st->hi = hi;
+  st->d = dn;
+  st->iter += 1;
+  st->done = conv ? 1 : 0;
+}
+
+// Outputs: beta + d and dlnZ = K(d) (from a pass at the final step).
+__global__ void __launch_bounds__(SMC_BLOCK) k_smc_finish(int nb, const Acc3* __restrict__ part, double beta,
+                                                         SmcState* __restrict__ st, double* __restrict__ out) {
+  __shared__ Acc3 sh[SMC_BLOCK];
+  const Acc3 r1 = combine_parts(nb, part, 0, sh);
+  if (threadIdx.x == 0) {
+    const double K1 = r1.m + log(r1.s) - st->lnS;
+    out[0] = beta + st->d;
+    out[1] = K1;
+    st->lnS += K1;  // the new weights' normaliser, relative to the inputs
+  }
+}
+
+// ln W_i <- ln W_i + d l_i - (lnS + dlnZ): normalised new weights.
+__global__ void k_smc_apply(int64_t n, double* __restrict__ lnW, const double* __restrict__ lnL,
+                            const SmcState* __restrict__ st) {
+  const double d = st->d, c = st->lnS;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    lnW[i] = lnW[i] + tempered(d, lnL[i]) - c;
+}
+
+// Systematic resampling: the normalised cumulative weights by a two-level
+// scan (SMC_CHUNK samples per block), then each draw's first index whose
+// cumulative weight exceeds (i + u) / n, and the states gathered from it.
+constexpr int SMC_CHUNK = 4 * SMC_BLOCK;
+
+__global__ void __launch_bounds__(SMC_BLOCK) k_cdf_local(int64_t n, const double* __restrict__ lnW,
+                                                        const SmcState* __restrict__ st, double* __restrict__ C,
+                                                        double* __restrict__ bsum) {
+  __shared__ double sh[SMC_BLOCK];
+  const double lnS = st->lnS;
+  const int64_t base = (int64_t)blockIdx.x * SMC_CHUNK + 4 * threadIdx.x;
+  double v[4], run = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = base + q < n ? exp(lnW[base + q] - lnS) : 0.0;
+    run += v[q];
+  }
+  sh[threadIdx.x] = run;
+  __syncthreads();
+  // inclusive scan of the thread sums
+  for (int o = 1; o < SMC_BLOCK; o <<= 1) {
+    const double x = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0.0;
+    __syncthreads();
+    sh[threadIdx.x] += x;
+    __syncthreads();
+  }
+  double acc = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    acc += v[q];
+    if (base + q < n) C[base + q] = acc;
+  }
+  if (threadIdx.x == SMC_BLOCK - 1) bsum[blockIdx.x] = sh[SMC_BLOCK - 1];
+}
+
+// Exclusive scan of the block sums (one block, sequential per thread chunk).
+__global__ void __launch_bounds__(SMC_BLOCK) k_cdf_blocks(int nb, double* __restrict__ bsum) {
+  __shared__ double sh[SMC_BLOCK];
+  const int per = (nb + SMC_BLOCK - 1) / SMC_BLOCK;
+  const int b0 = threadIdx.x * per;
+  double run = 0.0;
+  for (int b = b0; b < b0 + per && b < nb; ++b) run += bsum[b];
+  sh[threadIdx.x] = run;
+  __syncthreads();
+  for (int o = 1; o < SMC_BLOCK; o <<= 1) {
+    const double x = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0.0;
+    __syncthreads();
+    sh[threadIdx.x] += x;
+    __syncthreads();
+  }
+  double acc = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+  for (int b = b0; b < b0 + per && b < nb; ++b) {
+    const double x = bsum[b];
+    bsum[b] = acc;
+    acc += x;
+  }
+}
+
+__global__ void k_cdf_offset(int64_t n, double* __restrict__ C, const double* __restrict__ boff) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    C[i] += boff[i / SMC_CHUNK];
+}
+
+__global__ void k_resample_pick(int64_t n, const double* __restrict__ C, double u,
+                                const double* __restrict__ th_in, double* __restrict__ th_out,
+                                int64_t* __restrict__ anc) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double U = ((double)i + u) / (double)n;
+    int64_t lo = 0, hi = n;  // first k with C[k] > U, in [0, n]
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (C[mid] > U) hi = mid;
+      else lo = mid + 1;
+    }
+    const int64_t a = lo < n ? lo : n - 1;
+    if (anc) anc[i] = a;
+    if (th_out) {
+#pragma unroll
+      for (int r = 0; r < 7; ++r) th_out[r * n + i] = th_in[r * n + a];
+    }
+  }
+}
+
 }  // namespace
+
+extern "C" int rift_ile_smc_reweight(int64_t n, const double* lnL, double* lnW, double beta, double target,
+                                     double* out, void* stream) {
+  if (n < 1 || !(beta >= 0.0 && beta <= 1.0) || !(target > 0.0 && target <= 1.0)) return RIFT_EINVAL;
+  auto bad = [](const void* q) { return !q || (((uintptr_t)q) & 7u); };
+  if (bad(lnL) || bad(lnW) || bad(out)) return RIFT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = (int)std::min<int64_t>((n + SMC_BLOCK - 1) / SMC_BLOCK, SMC_GRID_MAX);
+  void* w = nullptr;
+  const size_t bytes = sizeof(Acc3) * 2 * (size_t)nb + sizeof(SmcState);
+  if (hipMallocAsync(&w, bytes, st) != hipSuccess) return RIFT_ENOMEM;
+  Acc3* part = (Acc3*)w;
+  SmcState* S = (SmcState*)(part + 2 * nb);
+  const double ln_target = log(target);
+  hipLaunchKernelGGL(k_smc_pass, dim3(nb), dim3(SMC_BLOCK), 0, st, n, (const double*)lnW, lnL,
+                     (const SmcState*)S, 0, 1, part);
+  hipLaunchKernelGGL(k_smc_init, dim3(1), dim3(SMC_BLOCK), 0, st, nb, (const Acc3*)part, 1.0 - beta, S);
+  for (int it = 0; it < SMC_ITERS; ++it) {
+    hipLaunchKernelGGL(k_smc_pass, dim3(nb), dim3(SMC_BLOCK), 0, st, n, (const double*)lnW, lnL,
+                       (const SmcState*)S, 1, 0, part);
+    hipLaunchKernelGGL(k_smc_step, dim3(1), dim3(SMC_BLOCK), 0, st, nb, (const Acc3*)part, ln_target, S);
+  }
+  hipLaunchKernelGGL(k_smc_pass, dim3(nb), dim3(SMC_BLOCK), 0, st, n, (const double*)lnW, lnL, (const SmcState*)S,
+                     1, 1, part);
+  hipLaunchKernelGGL(k_smc_finish, dim3(1), dim3(SMC_BLOCK), 0, st, nb, (const Acc3*)part, beta, S, out);
+  hipLaunchKernelGGL(k_smc_apply, dim3(nb), dim3(SMC_BLOCK), 0, st, n, lnW, lnL, (const SmcState*)S);
+  int rc = hipGetLastError() != hipSuccess ? RIFT_EDEVICE : RIFT_OK;
+  if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
+  return rc;
+}
+
+extern "C" int rift_ile_smc_resample(int64_t n, const double* lnW, double u, const double* theta_in,
+                                     double* theta_out, int64_t* ancestors, void* stream) {
+  if (n < 1 || !(u >= 0.0 && u < 1.0)) return RIFT_EINVAL;
+  auto bad = [](const void* q) { return !q || (((uintptr_t)q) & 7u); };
+  if (bad(lnW) || (ancestors && bad(ancestors))) return RIFT_EINVAL;
+  if ((theta_out != nullptr) != (theta_in != nullptr)) return RIFT_EINVAL;
+  if (theta_out && (bad(theta_in) || bad(theta_out) || theta_in == theta_out)) return RIFT_EINVAL;
+  if (!theta_out && !ancestors) return RIFT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = (int)std::min<int64_t>((n + SMC_BLOCK - 1) / SMC_BLOCK, SMC_GRID_MAX);
+  const int64_t nc = (n + SMC_CHUNK - 1) / SMC_CHUNK;
+  const size_t bytes = sizeof(Acc3) * 2 * (size_t)nb + sizeof(SmcState) + sizeof(double) * ((size_t)n + (size_t)nc);
+  void* w = nullptr;
+  if (hipMallocAsync(&w, bytes, st) != hipSuccess) return RIFT_ENOMEM;
+  Acc3* part = (Acc3*)w;
+  SmcState* S = (SmcState*)(part + 2 * nb);
+  double* C = (double*)(S + 1);
+  double* bsum = C + n;
+  hipLaunchKernelGGL(k_smc_pass, dim3(nb), dim3(SMC_BLOCK), 0, st, n, lnW, (const double*)nullptr,
+                     (const SmcState*)S, 0, 1, part);
+  hipLaunchKernelGGL(k_smc_init, dim3(1), dim3(SMC_BLOCK), 0, st, nb, (const Acc3*)part, 0.0, S);
+  hipLaunchKernelGGL(k_cdf_local, dim3((unsigned)nc), dim3(SMC_BLOCK), 0, st, n, lnW, (const SmcState*)S, C, bsum);
+  hipLaunchKernelGGL(k_cdf_blocks, dim3(1), dim3(SMC_BLOCK), 0, st, (int)nc, bsum);
+  hipLaunchKernelGGL(k_cdf_offset, dim3(nb), dim3(SMC_BLOCK), 0, st, n, C, (const double*)bsum);
+  hipLaunchKernelGGL(k_resample_pick, dim3(nb), dim3(SMC_BLOCK), 0, st, n, (const double*)C, u, theta_in, theta_out,
+                     ancestors);
+  int rc = hipGetLastError() != hipSuccess ? RIFT_EDEVICE : RIFT_OK;
+  if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
+  return rc;
+}
 
 extern "C" int rift_ile_leapfrog_drift(int64_t n, double* theta, double* p, const double* step, void* stream) {
   if (n < 0 || !step) return RIFT_EINVAL;
@@ -161,7 +473,16 @@ extern "C" int rift_ile_leapfrog_drift(int64_t n, double* theta, double* p, cons
 extern "C" int rift_ile_plan_hmc(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
                                  const double* u, const double* sigma, double eps, int32_t n_leapfrog,
                                  const rift_ile_hmc_prior* prior, double* lnL, int32_t* accepted, void* stream) {
+  return rift_ile_plan_hmc_tempered(plan, point, n, theta, z, u, sigma, eps, n_leapfrog, prior, 1.0, lnL, accepted,
+                                    stream);
+}
+
+extern "C" int rift_ile_plan_hmc_tempered(rift_ile_plan plan, int32_t point, int64_t n, double* theta,
+                                          const double* z, const double* u, const double* sigma, double eps,
+                                          int32_t n_leapfrog, const rift_ile_hmc_prior* prior, double beta,
+                                          double* lnL, int32_t* accepted, void* stream) {
   if (!plan || n < 0 || !sigma || !prior) return RIFT_EINVAL;
+  if (!(beta >= 0.0 && beta <= 1.0)) return RIFT_EINVAL;
   if (!(eps > 0.0) || !std::isfinite(eps) || n_leapfrog < 1 || n_leapfrog > 10000) return RIFT_EINVAL;
   if (!std::isfinite(prior->t_min) || !std::isfinite(prior->t_max) || !(prior->t_max > prior->t_min)) return RIFT_EINVAL;
   if (!(prior->d_min > 0.0) || !(prior->d_max > prior->d_min) || !std::isfinite(prior->d_max)) return RIFT_EINVAL;
@@ -192,16 +513,17 @@ extern "C" int rift_ile_plan_hmc(rift_ile_plan plan, int32_t point, int64_t n, d
   int rc = rift_ile_plan_grad(plan, point, n, theta, coords, l1, g, stream);
   if (!rc)
     hipLaunchKernelGGL(k_hmc_first, dim3(grid), dim3(256), 0, st, n, theta, z, (const double*)g, (const double*)l1, h,
-                       sig, step, P, p, c0, H0, l0);
+                       beta, sig, step, P, p, c0, H0, l0);
   for (int s = 1; s < n_leapfrog && !rc; ++s) {
     rc = rift_ile_plan_grad(plan, point, n, theta, coords, l1, g, stream);
-    if (!rc) hipLaunchKernelGGL(k_hmc_mid, dim3(grid), dim3(256), 0, st, n, theta, p, (const double*)g, h, step);
+    if (!rc)
+      hipLaunchKernelGGL(k_hmc_mid, dim3(grid), dim3(256), 0, st, n, theta, p, (const double*)g, h, beta, step);
   }
   if (!rc) rc = rift_ile_plan_grad(plan, point, n, theta, coords, l1, g, stream);
   if (!rc)
     hipLaunchKernelGGL(k_hmc_end, dim3(grid), dim3(256), 0, st, n, theta, (const double*)p, (const double*)g,
-                       (const double*)l1, h, (const double*)c0, (const double*)l0, (const double*)H0, u, sig, P,
-                       lnL, accepted);
+                       (const double*)l1, h, beta, (const double*)c0, (const double*)l0, (const double*)H0, u, sig,
+                       P, lnL, accepted);
   if (!rc && hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
   if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
   return rc;

@@ -68,6 +68,9 @@ EXPORTS = (
     "rift_ile_plan_hmc",
     "rift_ile_plan_lnZ_tband",
     "rift_ile_plan_lnZ_erai",
+    "rift_ile_plan_hmc_tempered",
+    "rift_ile_smc_reweight",
+    "rift_ile_smc_resample",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -188,6 +191,10 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_plan_lnZ_tband.argtypes = [vp, vp, vp, ctypes.POINTER(CBandRule), vp, vp, vp, vp]
     lib.rift_ile_plan_hmc.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, i32,
                                       ctypes.POINTER(CHmcPrior), vp, vp, vp]
+    lib.rift_ile_plan_hmc_tempered.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, i32,
+                                               ctypes.POINTER(CHmcPrior), ctypes.c_double, vp, vp, vp]
+    lib.rift_ile_smc_reweight.argtypes = [i64, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
+    lib.rift_ile_smc_resample.argtypes = [i64, vp, ctypes.c_double, vp, vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
     lib.rift_ile_strerror.restype = ctypes.c_char_p
     lib.rift_ile_version.restype = ctypes.c_int
@@ -342,6 +349,29 @@ def lnL_dmarg(point, theta, d_min, d_max, n_nodes=20, device="cuda") -> torch.Te
     finally:
         plan.close()
     return out
+
+
+def smc_reweight(lnL, lnW, beta, target, out=None):
+    """One SMC ladder update in place on lnW (rift_ile_smc_reweight); returns
+    out = [beta', dlnZ] (a device tensor)."""
+    lib = load()
+    o = out if out is not None else torch.empty(2, dtype=torch.float64, device=lnW.device)
+    _check(lib.rift_ile_smc_reweight(lnW.numel(), lnL.data_ptr(), lnW.data_ptr(), float(beta), float(target),
+                                     o.data_ptr(), _stream(lnW.device)), "rift_ile_smc_reweight")
+    return o
+
+
+def smc_resample(lnW, u, theta_in=None, theta_out=None, ancestors=None):
+    """Systematic resampling (rift_ile_smc_resample): theta_out[:, i] =
+    theta_in[:, a_i] and/or the ancestors a_i (int64)."""
+    lib = load()
+    n = lnW.numel()
+    _check(lib.rift_ile_smc_resample(n, lnW.data_ptr(), float(u),
+                                     None if theta_in is None else theta_in.data_ptr(),
+                                     None if theta_out is None else theta_out.data_ptr(),
+                                     None if ancestors is None else ancestors.data_ptr(), _stream(lnW.device)),
+           "rift_ile_smc_resample")
+    return ancestors
 
 
 def pregrid(q, r: int, out=None, device="cuda") -> torch.Tensor:
@@ -569,9 +599,10 @@ class Plan:
                                                 _stream(self.device)), "rift_ile_plan_lnZ_pmarg")
         return z, ne
 
-    def hmc(self, point, theta, z, u, sigma, eps, n_leapfrog, box, lnL_out=None, accepted_out=None):
+    def hmc(self, point, theta, z, u, sigma, eps, n_leapfrog, box, lnL_out=None, accepted_out=None, beta=None):
         """One Metropolis-adjusted HMC transition of every chain in place
-        (rift_ile_plan_hmc): theta [7, n] in the sampler coordinates, z [7, n]
+        (rift_ile_plan_hmc, or rift_ile_plan_hmc_tempered on L^beta p when
+        beta is given): theta [7, n] in the sampler coordinates, z [7, n]
         standard normals, u [n] uniforms, sigma [7], box = (t_min, t_max,
         d_min, d_max).  Returns (lnL [n], accepted [n] int32)."""
         n = theta.shape[1]
@@ -579,9 +610,16 @@ class Plan:
         acc = accepted_out if accepted_out is not None else torch.empty(n, dtype=torch.int32, device=self.device)
         sg = np.ascontiguousarray(sigma, dtype=np.float64)
         pr = CHmcPrior(*[float(b) for b in box])
-        _check(self.lib.rift_ile_plan_hmc(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(), u.data_ptr(),
-                                          sg.ctypes.data, float(eps), int(n_leapfrog), ctypes.byref(pr),
-                                          l.data_ptr(), acc.data_ptr(), _stream(self.device)), "rift_ile_plan_hmc")
+        if beta is None:
+            _check(self.lib.rift_ile_plan_hmc(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(),
+                                              u.data_ptr(), sg.ctypes.data, float(eps), int(n_leapfrog),
+                                              ctypes.byref(pr), l.data_ptr(), acc.data_ptr(), _stream(self.device)),
+                   "rift_ile_plan_hmc")
+        else:
+            _check(self.lib.rift_ile_plan_hmc_tempered(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(),
+                                                       u.data_ptr(), sg.ctypes.data, float(eps), int(n_leapfrog),
+                                                       ctypes.byref(pr), float(beta), l.data_ptr(), acc.data_ptr(),
+                                                       _stream(self.device)), "rift_ile_plan_hmc_tempered")
         return l, acc
 
     def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):

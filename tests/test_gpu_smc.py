@@ -1,0 +1,183 @@
+"""The SMC ladder's update, resampling and tempered moves through the C ABI
+against the oracle (Eqs. (sampler-menu:smc-update),
+(sampler-menu:tempered-target)).
+
+Bars (written here):
+* the rung: |d beta'| <= 1e-9 (1 - beta) + 1e-15.  The oracle bisects to
+  rounding and the library's Newton search stops at a relative step of
+  4e-16; what separates them is the rounding of the log fraction, about
+  1e-15 relative, divided by its slope;
+* dlnZ: |d| <= |mean l| |d beta'| + 1e-12 max(1, |dlnZ|) (its derivative in
+  the step is the tilted mean of ln L);
+* the new log weights: |d lnW_i| <= |l_i| |d beta'| + |d dlnZ| + 1e-12
+  (1 + |lnW_i|);
+* resampling: ancestors equal wherever (i + u) / n lies more than 1e-12 from
+  every cumulative weight (the two sums round differently only at that
+  level); the gathered states are the ancestors' columns bit for bit;
+* tempered HMC: as the untempered transition's test (states to 1e-6 sigma,
+  decisions exact away from the threshold), and beta = 1 bit for bit equal
+  to rift_ile_plan_hmc.
+"""
+import numpy as np
+import pytest
+
+from paper_2609_37393_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SIG = np.array([1e-3, 1e-3, 5e-3, 5e-3, 5e-3, 3e-6, 5e-3])
+BOX = (-0.01, 0.01, 10.0, 1000.0)
+
+
+@pytest.fixture(scope="module")
+def ile():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2609_37393_amd import ile as m
+
+    m.load()
+    return m
+
+
+def _dev(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def _check_reweight(ile, oracle_mod, lnL, lnW, beta, target):
+    want_b = oracle_mod.smc_next_beta(lnW, lnL, beta, target)
+    want_d, want_w = oracle_mod.smc_update(lnW, lnL, beta, want_b)
+    tw = _dev(lnW)
+    out = ile.smc_reweight(_dev(lnL), tw, beta, target).cpu().numpy()
+    got_w = tw.cpu().numpy()
+    db = abs(out[0] - want_b)
+    assert db <= 1e-9 * (1.0 - beta) + 1e-15, (out[0], want_b)
+    W = np.exp(want_w)
+    fin = np.isfinite(lnL) & np.isfinite(lnW)
+    mean_l = abs(np.sum(W[fin] * lnL[fin]))
+    dd = abs(out[1] - want_d)
+    assert dd <= mean_l * db + 1e-12 * max(1.0, abs(want_d)), (out[1], want_d)
+    assert np.array_equal(np.isfinite(got_w), np.isfinite(want_w))
+    ok = np.isfinite(want_w)
+    bar = np.abs(np.where(np.isfinite(lnL), lnL, 0.0))[ok] * db + dd + 1e-12 * (1 + np.abs(want_w[ok]))
+    assert np.all(np.abs(got_w[ok] - want_w[ok]) <= bar)
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 100_003])
+def test_reweight_matches_oracle(ile, oracle_mod, n):
+    rng = np.random.default_rng(n)
+    lnL = -0.5 * 40.0 * rng.chisquare(3, n)
+    lnW = rng.normal(size=n) * 2
+    if n > 10:
+        lnL[::17] = -np.inf
+        lnW[::23] = -np.inf
+    for beta, target in ((0.0, 0.5), (0.2, 0.9), (0.6, 0.3), (0.0, 1e-9), (1.0, 0.5)):
+        print(f"reweight n={n} beta={beta} target={target}", flush=True)
+        _check_reweight(ile, oracle_mod, lnL, lnW, beta, target)
+
+
+def test_reweight_ladder_and_edges(ile, oracle_mod):
+    """A ladder from 0 to 1 on the device (no resampling) telescopes to the
+    prior Monte-Carlo estimate; NaN poisons; refused arguments."""
+    import torch
+
+    rng = np.random.default_rng(3)
+    n = 20000
+    lnL = -0.5 * 60.0 * rng.chisquare(2, n)
+    tl, tw = _dev(lnL), torch.zeros(n, dtype=torch.float64, device="cuda")
+    beta, total, rungs = 0.0, 0.0, 0
+    while beta < 1.0 and rungs < 100:
+        out = ile.smc_reweight(tl, tw, beta, 0.5).cpu().numpy()
+        assert out[0] > beta
+        beta, total, rungs = out[0], total + out[1], rungs + 1
+    assert beta == 1.0 and rungs > 2
+    m = lnL.max()
+    want = m + np.log(np.mean(np.exp(lnL - m)))
+    assert abs(total - want) <= 1e-9 * max(1.0, abs(want)), (total, want)
+    bad = lnL.copy()
+    bad[5] = np.nan
+    out = ile.smc_reweight(_dev(bad), torch.zeros(n, dtype=torch.float64, device="cuda"), 0.0, 0.5).cpu().numpy()
+    assert np.isnan(out).all()
+    for args in ((0.0, 0.0), (0.0, 1.5), (-0.1, 0.5), (1.1, 0.5)):
+        with pytest.raises(RuntimeError):
+            ile.smc_reweight(tl, tw, *args)
+
+
+@pytest.mark.parametrize("n", [1, 5, 1023, 1024, 1025, 300_001])
+def test_resample_matches_oracle(ile, oracle_mod, n):
+    import torch
+
+    rng = np.random.default_rng(n + 7)
+    lnW = rng.normal(size=n) * 3
+    if n > 10:
+        lnW[::9] = -np.inf
+    th = rng.normal(size=(7, n))
+    for u in (0.0, 0.4321, 0.999999):
+        print(f"resample n={n} u={u}", flush=True)
+        want = oracle_mod.systematic_resample(lnW, u)
+        anc = torch.empty(n, dtype=torch.int64, device="cuda")
+        out = torch.empty((7, n), dtype=torch.float64, device="cuda")
+        ile.smc_resample(_dev(lnW), u, _dev(th), out, anc)
+        got = anc.cpu().numpy()
+        W = np.exp(lnW - lnW.max())
+        C = np.cumsum(W / W.sum())
+        U = (np.arange(n) + u) / n
+        # distance of each draw to the nearest cumulative weight
+        k = np.clip(np.searchsorted(C, U), 0, n - 1)
+        near = np.minimum(np.abs(C[k] - U), np.abs(C[np.maximum(k - 1, 0)] - U))
+        firm = near > 1e-12
+        assert np.array_equal(got[firm], want[firm])
+        assert np.all(np.diff(got) >= 0) and got.min() >= 0 and got.max() < n
+        assert np.array_equal(out.cpu().numpy(), th[:, got])
+    with pytest.raises(RuntimeError):
+        ile.smc_resample(_dev(lnW), 1.0, None, None, torch.empty(n, dtype=torch.int64, device="cuda"))
+    with pytest.raises(RuntimeError):
+        ile.smc_resample(_dev(lnW), 0.5)
+
+
+def _chains(oracle_mod, pt, n, seed):
+    th, _ = synth.weighted_samples(40 * n, seed)
+    best = th[:, np.argmax(oracle_mod.lnL(pt, th))]
+    c = synth.perturbed_samples(best, SIG, n, seed + 1)
+    c[3] = np.cos(c[3])
+    c[6] = np.log(c[6])
+    return c
+
+
+def test_tempered_hmc_matches_oracle(ile, oracle_mod):
+    import torch
+
+    pt = synth.make_point(3, 9, 6554, 32768.0, 100.0, 41)
+    n = 300
+    c0 = _chains(oracle_mod, pt, n, 42)
+    rng = np.random.default_rng(11)
+    z = rng.normal(size=c0.shape)
+    u = rng.uniform(0.8, 1.0, n)
+    plan = ile.Plan([pt], [n])
+    for beta in (0.0, 0.05, 0.4):
+        print(f"tempered hmc beta={beta}", flush=True)
+        want_c, want_l, want_acc = oracle_mod.hmc_step(pt, c0, z, u, SIG, 0.3, 6, *BOX, beta=beta)
+        # the oracle's energy difference, to leave out decisions at the threshold
+        p0 = z / SIG[:, None]
+        _, U0, _ = oracle_mod.hmc_potential(pt, c0, *BOX, beta=beta)
+        _, p1, _, U1 = oracle_mod.hmc_trajectory(pt, c0, p0, SIG, 0.3, 6, *BOX, beta=beta)
+        dH = (U0 + 0.5 * np.sum(SIG[:, None] ** 2 * p0 ** 2, 0)) - (U1 + 0.5 * np.sum(SIG[:, None] ** 2 * p1 ** 2, 0))
+        firm = ~(np.abs(np.log(u) - dH) < 1e-4)
+        tc = _dev(c0)
+        l, acc = plan.hmc(0, tc, _dev(z), _dev(u), SIG, 0.3, 6, BOX, beta=beta)
+        got_c, got_acc = tc.cpu().numpy(), acc.cpu().numpy().astype(bool)
+        assert firm.sum() >= n - 3
+        assert np.array_equal(got_acc[firm], want_acc[firm])
+        assert np.all(np.abs(got_c[:, firm] - want_c[:, firm]) <= 1e-6 * SIG[:, None])
+        assert np.array_equal(got_c[:, ~got_acc], c0[:, ~got_acc])
+    # beta = 1 is the untempered transition bit for bit
+    t1, t2 = _dev(c0), _dev(c0)
+    l1, a1 = plan.hmc(0, t1, _dev(z), _dev(u), SIG, 0.3, 6, BOX, beta=1.0)
+    l2, a2 = plan.hmc(0, t2, _dev(z), _dev(u), SIG, 0.3, 6, BOX)
+    assert torch.equal(t1, t2) and torch.equal(l1, l2) and torch.equal(a1, a2)
+    with pytest.raises(RuntimeError):
+        plan.hmc(0, _dev(c0), _dev(z), _dev(u), SIG, 0.3, 6, BOX, beta=1.5)
+    plan.close()
