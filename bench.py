@@ -898,13 +898,13 @@ def extra_hmc(ile, synth, torch, steps, chains=16384, n_leapfrog=8, cpu=True):
 def extra_smc(ile, synth, torch, steps, particles=65536, cpu=True):
     """An adaptive SMC ladder (Eqs. (sampler-menu:tempered-target),
     (sampler-menu:smc-update)) from the prior to the posterior of a 3-detector,
-    9-mode point at SNR 10: 65536 particles; per rung the library's reweight
+    9-mode point at SNR 5: 65536 particles; per rung the library's reweight
     (rung chosen at a conditional effective-size fraction of 0.5),
     systematic resampling, and two tempered HMC moves (4 leapfrog steps of
     0.25, proposal widths 0.2 x the cloud's spread).  The caller's logic
     (widths, random numbers, the loop) is host code; every per-particle step
     is a library kernel."""
-    pt = synth.make_point(3, 9, 6554, 32768.0, 10.0, 44)
+    pt = synth.make_point(3, 9, 6554, 32768.0, 5.0, 44)
     n = particles
     box = (-0.01, 0.01, 10.0, 1000.0)
     th = synth.prior_samples(n, 5)
@@ -954,7 +954,7 @@ def extra_smc(ile, synth, torch, steps, particles=65536, cpu=True):
     lnWt = torch.zeros(n, dtype=torch.float64, device="cuda")
     secs, _ = time_steps(lambda: ile.smc_reweight(lnLt, lnWt.zero_(), 0.0, 0.5), 10, 2, torch)
     plan.close()
-    return {"workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 10; 65536 particles from the "
+    return {"workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 5; 65536 particles from the "
                         "prior; adaptive SMC ladder (target fraction 0.5), 2 tempered HMC moves per rung",
             "rungs": rungs, "ladder_ms": 1e3 * wall, "ms_per_rung": 1e3 * wall / max(1, rungs),
             "final_beta": beta, "lnZ_smc": lnZ, "lnZ_prior_mc_4e6": float(zp[0]), "neff_prior_mc": float(nep[0]),
