@@ -488,17 +488,116 @@ def lnL_erai(pt, theta, n_phi: int, n_psi: int, nthreads: int = 0):
     return out
 
 
+PSI_CELL_GL = 8          # Gauss-Legendre points per sub-interval of a cell
+
+
+def psi_stationary(a, c1, c2):
+    """The stationary points of q(u) = a + Re(c1 e^{iu}) + Re(c2 e^{2iu}) on
+    the circle (Eq. (ap:psicells)): with z = e^{iu}, 2 i z^2 q'(u) = 0 is the
+    quartic 2 c2 z^4 + c1 z^3 - conj(c1) z - 2 conj(c2) = 0, whose roots on
+    the unit circle are the stationary points.  Roots within 1e-3 of the
+    circle are taken as candidates and polished by Newton's method on q'(u);
+    a candidate that does not settle on a root of q' is dropped (a pair of
+    roots leaving the circle is an inflection, not an extremum).  Returns
+    the sorted angles in [0, 2 pi)."""
+    roots = np.roots([2.0 * c2, c1, 0.0, -np.conj(c1), -2.0 * np.conj(c2)])
+    out = []
+    for z in roots:
+        if not np.isfinite(z) or abs(abs(z) - 1.0) > 1e-3:
+            continue
+        u = float(np.angle(z))
+        for _ in range(30):
+            e1 = np.exp(1j * u)
+            d1 = -(c1 * e1).imag - 2.0 * (c2 * e1 * e1).imag
+            d2 = -(c1 * e1).real - 4.0 * (c2 * e1 * e1).real
+            if d2 == 0.0:
+                break
+            step = d1 / d2
+            u -= step
+            if abs(step) < 1e-15:
+                break
+        e1 = np.exp(1j * u)
+        d1 = -(c1 * e1).imag - 2.0 * (c2 * e1 * e1).imag
+        scale = abs(c1) + 2.0 * abs(c2)
+        if abs(d1) <= 1e-9 * max(scale, 1e-300):
+            out.append(u % (2.0 * np.pi))
+    out = np.unique(np.round(np.sort(out), 13))
+    return out
+
+
+def psi_cell_breaks(width, sigma):
+    """Sub-interval ends, as distances from a cell's higher end, of the
+    curvature-sized rule: steps of 2 sigma out to 8 sigma, then doubling
+    distances to the cell's far end (a monotone cell's integrand falls away
+    from its top over a width sigma = A^{-1/2})."""
+    d = [0.0]
+    while d[-1] < width:
+        nxt = 2.0 * sigma * len(d) if len(d) <= 4 else 2.0 * d[-1]
+        d.append(min(width, nxt))
+    return np.array(d)
+
+
+def psi_cells_integral(a, c1, c2):
+    """ln[(1 / 2 pi) int_0^{2 pi} e^{q(u)} du] by the cell partition of
+    Eq. (ap:psicells): the stationary points cut the circle into cells on
+    which q is monotone; each cell is integrated at a density set by its own
+    curvature A = -q'' at its higher end: Gauss-Legendre (PSI_CELL_GL points)
+    on the sub-intervals of psi_cell_breaks with sigma = min(A^{-1/2},
+    width / 8) (a cell whose top is flat, A <= 0, takes width / 8: at least
+    four sub-intervals per cell).  With fewer than two
+    stationary points (a constant q) the circle is one cell."""
+    st = psi_stationary(a, c1, c2)
+
+    def q(u):
+        e1 = np.exp(1j * np.asarray(u))
+        return a + (c1 * e1).real + (c2 * e1 * e1).real
+
+    def qpp(u):
+        e1 = np.exp(1j * u)
+        return -(c1 * e1).real - 4.0 * (c2 * e1 * e1).real
+
+    if st.size < 2:
+        cells = [(0.0, 2.0 * np.pi)]
+    else:
+        cells = [(st[k], st[k + 1]) for k in range(st.size - 1)] + [(st[-1], st[0] + 2.0 * np.pi)]
+    x, w = np.polynomial.legendre.leggauss(PSI_CELL_GL)
+    vals = []
+    for lo, hi in cells:
+        width = hi - lo
+        top_lo = q(lo) >= q(hi)
+        A = -qpp(lo if top_lo else hi)
+        sigma = min(1.0 / np.sqrt(A), width / 8.0) if A > 0 else width / 8.0
+        d = psi_cell_breaks(width, sigma)
+        for j in range(d.size - 1):
+            h = d[j + 1] - d[j]
+            c = d[j] + 0.5 * h + 0.5 * h * x          # distances from the top
+            uu = lo + c if top_lo else hi - c
+            vals.append(q(uu) + np.log(0.5 * h * w))
+    v = np.concatenate(vals)
+    m = np.max(v)
+    return m + np.log(np.sum(np.exp(v - m))) - np.log(2.0 * np.pi)
+
+
 def lnL_pmarg(pt, theta, method="trapezoid", n_points=64, nthreads: int = 0):
     """ln of the likelihood marginalised over polarisation per sample, psi
     uniform on [0, pi) (u = 2 psi uniform on the circle):
       trapezoid: ln[(1/n) sum_j e^{lnL(psi + pi j / n)}], the oracle's lnL at
         each of the n angles (the periodic trapezoid rule);
+      cells: the stationary-point cells of Eq. (ap:psicells)
+        (psi_cells_integral) on the coefficients of psi_coefficients;
       laplace: Eq. (ap:psilaplace) at the dominant maximum of q(u) from
         psi_coefficients: ln L = q(u*) - ln(2 pi A) / 2 with A = -q''(u*),
         u* the best of 32 equally spaced points refined by Newton's method on
         q' = 0, where A >= 100 (the method's relative error O(1/A) is then
         below ~1e-3); otherwise (weak signal, or two maxima merging) the
         periodic trapezoid rule on 256 points of the same q."""
+    if method == "cells":
+        a, c1, c2 = psi_coefficients(pt, theta, nthreads)
+        out = np.full(a.shape[0], np.nan)
+        for i in range(a.shape[0]):
+            if np.isfinite(a[i]) and np.isfinite(c1[i]) and np.isfinite(c2[i]):
+                out[i] = psi_cells_integral(a[i], c1[i], c2[i])
+        return out
     if method == "trapezoid":
         n = int(n_points)
         l = lnL_psi_grid(pt, theta, 2.0 * np.pi * np.arange(n) / n, nthreads)
