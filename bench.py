@@ -798,8 +798,9 @@ def extra_erai(ile, synth, torch, steps, cpu=True):
 def extra_pmarg(ile, synth, torch, steps, cpu=True):
     """The headline point (3 detectors, 21 modes, SNR 600, 1e6 prior
     samples) marginalised over polarisation in the kernel: the periodic
-    trapezoid rule on 64 points of q(u) (Eq. (ap:psiexp)) and Laplace's method
-    (Eq. (ap:psilaplace)); each against the FP64 oracle on a sample."""
+    trapezoid rule on 64 points of q(u) (Eq. (ap:psiexp)), Laplace's method
+    (Eq. (ap:psilaplace)) and the stationary-point cells (Eq. (ap:psicells));
+    each against the FP64 oracle on a sample."""
     pt, th = c2_inputs(synth, 1_000_000)
     n = th.shape[1]
     tht = torch.as_tensor(th, device="cuda").contiguous()
@@ -809,7 +810,7 @@ def extra_pmarg(ile, synth, torch, steps, cpu=True):
     res = {"workload": "3 detectors, 21 modes (l<=4), Q 6554 samples at 32768 Hz, SNR 600, 1e6 prior samples; "
                        "lnL marginalised over polarisation"}
     idx = np.random.default_rng(3).choice(n, 300, replace=False)
-    for method, npts in (("trapezoid", 64), ("laplace", 0)):
+    for method, npts in (("trapezoid", 64), ("laplace", 0), ("cells", 0)):
         def step():
             plan.lnZ_pmarg(tht, method, npts, lnZ_out=z, lnL_out=ll)
 
@@ -828,7 +829,7 @@ def extra_pmarg(ile, synth, torch, steps, cpu=True):
             want = oracle.lnL_pmarg(pt, th[:, idx], method, npts)
             r["cpu_oracle_lnLp_evals_per_s"] = idx.size / (time.perf_counter() - t0)
             r["max_abs_dlnLp_vs_oracle_sampled"] = float(np.nanmax(np.abs(ll.cpu().numpy()[idx] - want)))
-        res[method if method == "laplace" else f"trapezoid{npts}"] = r
+        res[method if method != "trapezoid" else f"trapezoid{npts}"] = r
     plan.close()
     return res
 

@@ -376,12 +376,20 @@ int rift_ile_plan_lnZ_tband(rift_ile_plan plan, const double *theta, const doubl
  *   RIFT_PSI_LAPLACE:   L_psi = e^{q(u*)} sqrt(2 pi / A) / (2 pi) at the dominant
  *     maximum u* with A = -q''(u*) (Eq. (ap:psilaplace); relative error O(1/A)),
  *     where A >= 100; a q without such a maximum (weak signal, or two maxima
- *     merging) is integrated by the trapezoid rule on 256 points instead. */
+ *     merging) is integrated by the trapezoid rule on 256 points instead;
+ *   RIFT_PSI_CELLS:     the stationary-point cells of Eq. (ap:psicells): the
+ *     unit-circle roots of the quartic 2 c2 z^4 + c1 z^3 - conj(c1) z
+ *     - 2 conj(c2) (z = e^{iu}, from q' = 0) cut the circle into cells on
+ *     which q is monotone, each integrated by 8-point Gauss-Legendre on
+ *     sub-intervals sized by its own curvature (2 sigma steps to 8 sigma
+ *     from its top, then doubling; sigma = min(A^{-1/2}, width / 8)):
+ *     accurate at any amplitude and for several peaks. */
 #define RIFT_PSI_TRAPEZOID 0
 #define RIFT_PSI_LAPLACE 1
+#define RIFT_PSI_CELLS 2
 typedef struct {
-  int32_t method;   /* RIFT_PSI_TRAPEZOID or RIFT_PSI_LAPLACE */
-  int32_t n_points; /* trapezoid: 1 .. 65536 points on the circle; ignored by Laplace */
+  int32_t method;   /* RIFT_PSI_TRAPEZOID, RIFT_PSI_LAPLACE or RIFT_PSI_CELLS */
+  int32_t n_points; /* trapezoid: 1 .. 65536 points on the circle; ignored otherwise */
 } rift_ile_psi_rule;
 
 /* ln L_psi per sample (lnLp: DEVICE [N] or NULL) and, per point, ln Z_psi and

@@ -1026,6 +1026,144 @@ __device__ __forceinline__ double psi_trapezoid(int n, double ln_n, double a, do
   return m + log(sum) - ln_n;
 }
 
+// The cell partition of Eq. (ap:psicells).  With z = e^{iu}, 2 i z^2 q'(u) = 0
+// is the quartic 2 c2 z^4 + c1 z^3 - conj(c1) z - 2 conj(c2) = 0 (exact leading
+// zeros stripped); its roots, by the Aberth-Ehrlich iteration, that lie within
+// 1e-3 of the unit circle are polished by Newton's method on q'(u) and kept
+// if they settle on a zero of q'.  The sorted stationary angles cut the
+// circle into cells on which q is monotone; each cell is integrated by
+// 8-point Gauss-Legendre on sub-intervals of 2 sigma out to 8 sigma from its
+// higher end, then of doubling length to its far end, sigma =
+// min(A^{-1/2}, width / 8) from the curvature A = -q'' at that end.
+struct Cx {
+  double x, y;
+};
+__device__ __forceinline__ Cx cx_mul(Cx a, Cx b) { return Cx{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ Cx cx_add(Cx a, Cx b) { return Cx{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ Cx cx_sub(Cx a, Cx b) { return Cx{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ Cx cx_div(Cx a, Cx b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return Cx{(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+
+constexpr double PSI_GL8_X[8] = {-0.96028985649753623168, -0.79666647741362673959, -0.52553240991632898582,
+                                 -0.18343464249564980494, 0.18343464249564980494,  0.52553240991632898582,
+                                 0.79666647741362673959,  0.96028985649753623168};
+// ln of the 8-point Gauss-Legendre weights
+constexpr double PSI_GL8_LNW[8] = {-2.29037458272350180621, -1.50336299698040232187, -1.15929697855282975993,
+                                   -1.01422394453275765969, -1.01422394453275765969, -1.15929697855282975993,
+                                   -1.50336299698040232187, -2.29037458272350180621};
+
+__device__ __forceinline__ int psi_stationary(double c1r, double c1i, double c2r, double c2i, double* st) {
+  // coefficients, highest degree first: 2 c2, c1, 0, -conj(c1), -2 conj(c2)
+  Cx co[5] = {Cx{2.0 * c2r, 2.0 * c2i}, Cx{c1r, c1i}, Cx{0.0, 0.0}, Cx{-c1r, c1i}, Cx{-2.0 * c2r, 2.0 * c2i}};
+  int lead = 0;
+  while (lead < 4 && co[lead].x == 0.0 && co[lead].y == 0.0) ++lead;
+  const int D = 4 - lead;  // degree after stripping exact leading zeros
+  if (D < 1) return 0;
+  Cx z[4];
+  for (int k = 0; k < D; ++k) {
+    double sk, ck;
+    sincos(1.5707963267948966 * k + 0.4, &sk, &ck);
+    z[k] = Cx{ck, sk};
+  }
+  for (int it = 0; it < 60; ++it) {
+    double moved = 0.0;
+    for (int k = 0; k < D; ++k) {
+      Cx p = co[lead], dp = Cx{0.0, 0.0};
+      for (int j = lead + 1; j <= 4; ++j) {
+        dp = cx_add(cx_mul(dp, z[k]), p);
+        p = cx_add(cx_mul(p, z[k]), co[j]);
+      }
+      if (p.x == 0.0 && p.y == 0.0) continue;
+      const Cx ratio = cx_div(p, dp);
+      Cx sum{0.0, 0.0};
+      for (int j = 0; j < D; ++j)
+        if (j != k) sum = cx_add(sum, cx_div(Cx{1.0, 0.0}, cx_sub(z[k], z[j])));
+      const Cx w = cx_div(ratio, cx_sub(Cx{1.0, 0.0}, cx_mul(ratio, sum)));
+      z[k] = cx_sub(z[k], w);
+      moved = fmax(moved, fabs(w.x) + fabs(w.y));
+    }
+    if (!(moved > 1e-16)) break;
+  }
+  const double scale = sqrt(c1r * c1r + c1i * c1i) + 2.0 * sqrt(c2r * c2r + c2i * c2i);
+  int n = 0;
+  for (int k = 0; k < D; ++k) {
+    const double r = sqrt(z[k].x * z[k].x + z[k].y * z[k].y);
+    if (!(fabs(r - 1.0) <= 1e-3)) continue;
+    double u = atan2(z[k].y, z[k].x);
+    double q, d1, d2;
+    for (int it = 0; it < 30; ++it) {
+      double su, cu;
+      sincos(u, &su, &cu);
+      psi_q(0.0, c1r, c1i, c2r, c2i, su, cu, &q, &d1, &d2);
+      if (d2 == 0.0) break;
+      const double step = d1 / d2;
+      u -= step;
+      if (fabs(step) < 1e-15) break;
+    }
+    double su, cu;
+    sincos(u, &su, &cu);
+    psi_q(0.0, c1r, c1i, c2r, c2i, su, cu, &q, &d1, &d2);
+    if (!(fabs(d1) <= 1e-9 * fmax(scale, 1e-300))) continue;
+    u = fmod(u, 6.283185307179586477);
+    if (u < 0.0) u += 6.283185307179586477;
+    st[n++] = u;
+  }
+  // sort, and drop repeats (two roots settling on one point)
+  for (int a = 1; a < n; ++a)
+    for (int b = a; b > 0 && st[b] < st[b - 1]; --b) {
+      const double t = st[b];
+      st[b] = st[b - 1];
+      st[b - 1] = t;
+    }
+  int m = 0;
+  for (int a = 0; a < n; ++a)
+    if (m == 0 || st[a] - st[m - 1] > 1e-12) st[m++] = st[a];
+  return m;
+}
+
+__device__ __forceinline__ double psi_cells(double a, double c1r, double c1i, double c2r, double c2i) {
+  double st[4];
+  const int ns = psi_stationary(c1r, c1i, c2r, c2i, st);
+  const int nc = ns < 2 ? 1 : ns;
+  double m = -__builtin_inf(), sum = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    const double lo = ns < 2 ? 0.0 : st[c];
+    const double hi = ns < 2 ? 6.283185307179586477 : (c + 1 < ns ? st[c + 1] : st[0] + 6.283185307179586477);
+    const double width = hi - lo;
+    double ql, qh, d1, d2l, d2h, s, cc;
+    sincos(lo, &s, &cc);
+    psi_q(a, c1r, c1i, c2r, c2i, s, cc, &ql, &d1, &d2l);
+    sincos(hi, &s, &cc);
+    psi_q(a, c1r, c1i, c2r, c2i, s, cc, &qh, &d1, &d2h);
+    const bool top_lo = ql >= qh;
+    const double A = -(top_lo ? d2l : d2h);
+    const double sigma = A > 0.0 ? fmin(1.0 / sqrt(A), width / 8.0) : width / 8.0;
+    double d0 = 0.0;
+    for (int j = 1; d0 < width; ++j) {
+      const double d1e = fmin(width, j <= 4 ? 2.0 * sigma * j : 2.0 * d0);
+      const double h = d1e - d0;
+      const double lnh = log(0.5 * h);
+      for (int g = 0; g < 8; ++g) {
+        const double dist = d0 + 0.5 * h + 0.5 * h * PSI_GL8_X[g];
+        const double u = top_lo ? lo + dist : hi - dist;
+        double su, cu, q, dd1, dd2;
+        sincos(u, &su, &cu);
+        psi_q(a, c1r, c1i, c2r, c2i, su, cu, &q, &dd1, &dd2);
+        const double l = q + lnh + PSI_GL8_LNW[g];
+        const double dl = l - m;
+        const double e = exp(-fabs(dl));
+        const bool up = dl > 0.0;
+        sum = up ? fma(sum, e, 1.0) : sum + e;
+        m = up ? l : m;
+      }
+      d0 = d1e;
+    }
+  }
+  return m + log(sum) - 1.8378770664093454836;  // ln(2 pi)
+}
+
 // ln L_psi from the coefficients of q (see PsiRule).  Laplace: the best of 32
 // equally spaced points, then Newton steps on q' = 0 (the maximum is then the
 // dominant one unless another lies within the grid's resolution of it).
@@ -1033,6 +1171,7 @@ __device__ __forceinline__ double psi_marginal(const PsiRule& G, double a, doubl
                                                double c2i) {
   double q, d1, d2;
   if (G.method == 0) return psi_trapezoid(G.n, G.ln_n, a, c1r, c1i, c2r, c2i);
+  if (G.method == 2) return psi_cells(a, c1r, c1i, c2r, c2i);
   double best = -__builtin_inf(), ub = 0.0;
   for (int j = 0; j < 32; ++j) {
     double su, cu;

@@ -1993,10 +1993,11 @@ int rift_ile_plan_lnZ_pmarg(rift_ile_plan p, const double* theta, const double* 
   if (!p || !rule || check_dev_ptr(theta) || check_dev_ptr(lnZ)) return RIFT_EINVAL;
   if ((lnw && check_dev_ptr(lnw)) || (neff && check_dev_ptr(neff)) || (lnLp && check_dev_ptr(lnLp)))
     return RIFT_EINVAL;
-  if (rule->method != RIFT_PSI_TRAPEZOID && rule->method != RIFT_PSI_LAPLACE) return RIFT_EINVAL;
+  if (rule->method != RIFT_PSI_TRAPEZOID && rule->method != RIFT_PSI_LAPLACE && rule->method != RIFT_PSI_CELLS)
+    return RIFT_EINVAL;
   if (rule->method == RIFT_PSI_TRAPEZOID && (rule->n_points < 1 || rule->n_points > 65536)) return RIFT_EINVAL;
   PsiRule g{};
-  g.method = rule->method == RIFT_PSI_TRAPEZOID ? 0 : 1;
+  g.method = rule->method == RIFT_PSI_TRAPEZOID ? 0 : (rule->method == RIFT_PSI_LAPLACE ? 1 : 2);
   g.n = rule->method == RIFT_PSI_TRAPEZOID ? rule->n_points : 0;
   g.ln_n = g.n > 0 ? log((double)g.n) : 0.0;
   p->pm = g;

@@ -128,7 +128,7 @@ class CPsiRule(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("n_points", ctypes.c_int32)]
 
 
-PSI_METHODS = {"trapezoid": 0, "laplace": 1}
+PSI_METHODS = {"trapezoid": 0, "laplace": 1, "cells": 2}
 
 
 class CBandRule(ctypes.Structure):

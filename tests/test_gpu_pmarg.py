@@ -1,15 +1,17 @@
 """The likelihood marginalised over polarisation on the GPU
-(rift_ile_plan_lnZ_pmarg; Eqs. (ap:psiexp), (ap:psilaplace)) against the FP64
-oracle.  The kernel takes q(u) from one gather and one contraction (the
-complex data term and the two model-norm parts); the oracle evaluates its own
-lnL at every angle (trapezoid) or transforms five of them (Laplace), so the
-comparison also checks the harmonic decomposition.
+(rift_ile_plan_lnZ_pmarg; Eqs. (ap:psiexp), (ap:psilaplace), (ap:psicells))
+against the FP64 oracle.  The kernel takes q(u) from one gather and one
+contraction (the complex data term and the two model-norm parts); the oracle
+evaluates its own lnL at every angle (trapezoid) or transforms five of them
+(Laplace, cells), so the comparison also checks the harmonic decomposition.
 
 Bars (written here): trapezoid, |d ln L_psi| <= 1e-9 max_j S(psi_j) + 1e-12
-with S the FP64 bar's scale at each angle of the rule; Laplace, the same
-scale at the five angles plus 1e-9 (the maximum's curvature A enters through
-ln A, whose relative error is that of the coefficients); NaN must agree;
-ln Z within 1e-9 max(1, |ln Z|)."""
+with S the FP64 bar's scale at each angle of the rule; Laplace and cells, the
+same scale at the five angles plus 1e-9 (Laplace: the maximum's curvature A
+enters through ln A, whose relative error is that of the coefficients;
+cells: the nodes follow the stationary points and curvatures, which move
+with the coefficients' rounding, shifting the result by far less than the
+rule's own error); NaN must agree; ln Z within 1e-9 max(1, |ln Z|)."""
 import numpy as np
 import pytest
 
@@ -32,14 +34,14 @@ def ile():
     return m
 
 
-def _bar(oracle_mod, pt, th, n_points, laplace):
+def _bar(oracle_mod, pt, th, n_points, five):
     n = th.shape[1]
-    m = 5 if laplace else n_points
+    m = 5 if five else n_points
     big = np.repeat(th, m, axis=1)
     big[2] = big[2] + np.tile(np.pi * np.arange(m) / m, n)
     S = lnL_scale(oracle_mod, pt, big).reshape(n, m)
     S = np.where(np.isfinite(S), S, 0.0)
-    return 1e-9 * S.max(axis=1) + (1e-9 if laplace else 1e-12)
+    return 1e-9 * S.max(axis=1) + (1e-9 if five else 1e-12)
 
 
 def _compare(got, want, bar, what):
@@ -62,14 +64,15 @@ def test_pmarg_matches_oracle(ile, oracle_mod, case):
     n = th.shape[1]
     tht = torch.as_tensor(th, device="cuda").contiguous()
     w = torch.as_tensor(lnw, device="cuda").contiguous()
-    for method, n_points in (("trapezoid", 64), ("trapezoid", 7), ("laplace", 0)):
+    for method, n_points in (("trapezoid", 64), ("trapezoid", 7), ("laplace", 0), ("cells", 0)):
         want = oracle_mod.lnL_pmarg(pt, th, method, n_points)
         z_or, ne_or = oracle_mod.lnZ(want, lnw)
         plan = ile.Plan([pt], [n])
         ll = torch.empty(n, dtype=torch.float64, device="cuda")
         z, ne = plan.lnZ_pmarg(tht, method, n_points, lnw=w, lnL_out=ll)
-        _compare(ll.cpu().numpy(), want, _bar(oracle_mod, pt, th, n_points, method == "laplace"), (case, method))
-        assert abs(z.item() - z_or) <= 1e-9 * max(1.0, abs(z_or)) + (1e-9 if method == "laplace" else 0.0)
+        five = method != "trapezoid"
+        _compare(ll.cpu().numpy(), want, _bar(oracle_mod, pt, th, n_points, five), (case, method))
+        assert abs(z.item() - z_or) <= 1e-9 * max(1.0, abs(z_or)) + (1e-9 if five else 0.0)
         assert abs(ne.item() - ne_or) <= 1e-8 * ne_or
         plan.close()
 
@@ -82,7 +85,7 @@ def test_pmarg_launch_forms_binning_and_psi_row(ile, oracle_mod):
     th = np.concatenate([synth.prior_samples(c, 950 + i) for i, c in enumerate(counts)], axis=1)
     tht = torch.as_tensor(th, device="cuda").contiguous()
     plan = ile.Plan(pts, counts)
-    for method, n_points in (("trapezoid", 32), ("laplace", 0)):
+    for method, n_points in (("trapezoid", 32), ("laplace", 0), ("cells", 0)):
         res = []
         for cfg in (dict(block=256, tile_blocks=4, blocks_per_cu=0, sort=0), dict(block=128, tile_blocks=2, blocks_per_cu=4, sort=1),
                     dict(block=64, tile_blocks=1, blocks_per_cu=0, sort=0)):
@@ -99,18 +102,19 @@ def test_pmarg_launch_forms_binning_and_psi_row(ile, oracle_mod):
         for p, c in enumerate(counts):
             want = oracle_mod.lnL_pmarg(pts[p], th[:, s:s + c], method, n_points)
             _compare(res[0][0][s:s + c].cpu().numpy(), want,
-                     _bar(oracle_mod, pts[p], th[:, s:s + c], n_points, method == "laplace"), (p, method))
+                     _bar(oracle_mod, pts[p], th[:, s:s + c], n_points, method != "trapezoid"), (p, method))
             s += c
-    # Laplace does not depend on where the points start
+    # Laplace and cells do not depend on where the points start
     th2 = th.copy()
     th2[2] += np.random.default_rng(4).uniform(0, np.pi, th.shape[1])
     plan.config = dict(block=256, tile_blocks=4, blocks_per_cu=0, sort=0)
-    a = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
-    b = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
-    plan.lnZ_pmarg(tht, "laplace", 0, lnL_out=a)
-    plan.lnZ_pmarg(torch.as_tensor(th2, device="cuda").contiguous(), "laplace", 0, lnL_out=b)
-    a, b = a.cpu().numpy(), b.cpu().numpy()
-    assert np.all(np.abs(a - b) <= 1e-9 * (np.abs(a) + 1.0))
+    for method in ("laplace", "cells"):
+        a = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
+        b = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
+        plan.lnZ_pmarg(tht, method, 0, lnL_out=a)
+        plan.lnZ_pmarg(torch.as_tensor(th2, device="cuda").contiguous(), method, 0, lnL_out=b)
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.all(np.abs(a - b) <= 1e-9 * (np.abs(a) + 1.0)), method
     plan.close()
 
 
@@ -129,7 +133,7 @@ def test_pmarg_edges_and_rules(ile, oracle_mod):
     assert np.isnan(got[3]) and np.isnan(got[4])
     _compare(got, oracle_mod.lnL_pmarg(pt, th, "trapezoid", 16), _bar(oracle_mod, pt, th, 16, False), "edges")
     lib = ile.load()
-    for rule in ((2, 16), (0, 0), (0, 65537), (-1, 4)):
+    for rule in ((3, 16), (0, 0), (0, 65537), (-1, 4)):
         with pytest.raises(RuntimeError):
             pr = ile.CPsiRule(*rule)
             ile._check(lib.rift_ile_plan_lnZ_pmarg(plan.handle, tht.data_ptr(), None, pr, ll.data_ptr(), None, None,
@@ -147,10 +151,11 @@ def test_pmarg_full_size_sampled(ile, oracle_mod):
     tht = torch.as_tensor(th, device="cuda").contiguous()
     plan = ile.Plan([pt], [th.shape[1]])
     idx = np.random.default_rng(9).choice(th.shape[1], 1000, replace=False)
-    for method, n_points in (("trapezoid", 64), ("laplace", 0)):
+    for method, n_points in (("trapezoid", 64), ("laplace", 0), ("cells", 0)):
         ll = torch.empty(th.shape[1], dtype=torch.float64, device="cuda")
         z, _ = plan.lnZ_pmarg(tht, method, n_points, lnL_out=ll)
         want = oracle_mod.lnL_pmarg(pt, th[:, idx], method, n_points)
-        _compare(ll.cpu().numpy()[idx], want, _bar(oracle_mod, pt, th[:, idx], n_points, method == "laplace"), method)
+        _compare(ll.cpu().numpy()[idx], want, _bar(oracle_mod, pt, th[:, idx], n_points, method != "trapezoid"),
+                 method)
         assert np.isfinite(z.item())
     plan.close()
