@@ -719,6 +719,133 @@ def hmc_step(pt, c0, z, u, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, b
     return cout, np.where(acc, l1, l0), acc
 
 
+NUTS_MAX_DH = 1000.0   # a leaf whose energy exceeds the start's by this much diverges
+
+
+def _nuts_leapfrog(potential, c, p, gU, d, eps, sig2):
+    """One leapfrog step of signed size d eps from (c, p) with gradient gU of
+    the potential at c: half kick, drift with cos incl folded back into
+    [-1, 1] (its momentum negated on odd folds), half kick.  Returns
+    (c, p, gU, lnL, U) at the new point."""
+    p = p - 0.5 * d * eps * gU
+    c = c + d * eps * sig2 * p
+    if np.isfinite(c[3]) and abs(c[3]) > 1.0:
+        r = np.mod(c[3] + 1.0, 4.0)
+        c = c.copy()
+        c[3] = 1.0 - abs(r - 2.0)
+        if r > 2.0:
+            p = p.copy()
+            p[3] = -p[3]
+    l, U, g = potential(c[:, None])
+    g = g[:, 0]
+    p = p - 0.5 * d * eps * g
+    return c, p, g, float(l[0]), float(U[0])
+
+
+def _no_uturn(p_a, p_b, rho, sig2):
+    """The generalised no-U-turn condition of a trajectory segment with edge
+    momenta p_a, p_b and momentum sum rho (mass diag(1 / sig2))."""
+    return float(np.dot(sig2 * p_a, rho)) > 0.0 and float(np.dot(sig2 * p_b, rho)) > 0.0
+
+
+def nuts_chain(potential, c0, z, dirs, merges, leaves, sigma, eps, max_depth):
+    """One No-U-Turn transition (multinomial NUTS with the generalised
+    criterion) of one chain, the random numbers given: momenta p = z / sigma
+    (mass diag(sigma^-2)); at depth j the trajectory doubles in direction
+    -1 if dirs[j] < 1/2 else +1 by a subtree of 2^j leapfrog steps from that
+    edge.  Within a subtree the leaves are built outward in order; leaf k
+    (weight e^{-H}) replaces the subtree's candidate when the next of
+    `leaves` is below its share of the subtree's weight so far, and after
+    each leaf every completed aligned block of 2, 4, .. leaves is checked for
+    a U-turn.  A U-turn inside the subtree, or a leaf whose energy exceeds
+    the start's by NUTS_MAX_DH, discards the subtree and ends the transition;
+    otherwise its candidate replaces the transition's with probability
+    min(1, W_subtree / W_trajectory) against merges[j], the weights add, and
+    a U-turn of the whole trajectory ends it.  At most max_depth doublings.
+    potential(c [7, m]) -> (lnL, U, dU/dc).  Returns (c, lnL, depth,
+    leapfrog steps, divergent)."""
+    sig = np.asarray(sigma, np.float64)
+    sig2 = sig * sig
+    c0 = np.asarray(c0, np.float64)
+    p0 = np.asarray(z, np.float64) / sig
+    l0, U0, g0 = potential(c0[:, None])
+    l0, U0, g0 = float(l0[0]), float(U0[0]), g0[:, 0]
+    H0 = U0 + 0.5 * float(np.sum(sig2 * p0 * p0))
+    left = right = (c0, p0, g0)
+    cand, cand_l = c0, l0
+    logW = 0.0
+    rho = p0.copy()
+    n_leaf = 0
+    depth = 0
+    div = False
+    for j in range(int(max_depth)):
+        d = -1.0 if dirs[j] < 0.5 else 1.0
+        c, p, g = left if d < 0 else right
+        sub_c, sub_l, logWs = None, None, -np.inf
+        rho_s = np.zeros(7)
+        first = []          # per leaf: its momentum and the running sum before it
+        valid = True
+        for k in range(2 ** j):
+            c, p, g, l, U = _nuts_leapfrog(potential, c, p, g, d, eps, sig2)
+            H = U + 0.5 * float(np.sum(sig2 * p * p))
+            n_leaf += 1
+            if not (H - H0 <= NUTS_MAX_DH):
+                valid, div = False, True
+                break
+            lw = H0 - H
+            logWs = np.logaddexp(logWs, lw)
+            if leaves[n_leaf - 1] < np.exp(lw - logWs):
+                sub_c, sub_l = c, l
+            first.append((p.copy(), rho_s.copy()))
+            rho_s = rho_s + p
+            size = 2
+            while size <= k + 1 and (k + 1) % size == 0:
+                pa, sa = first[k + 1 - size]
+                if not _no_uturn(pa, p, rho_s - sa, sig2):
+                    valid = False
+                    break
+                size *= 2
+            if not valid:
+                break
+        if not valid:
+            break
+        depth = j + 1
+        if merges[j] < np.exp(logWs - logW):
+            cand, cand_l = sub_c, sub_l
+        logW = np.logaddexp(logW, logWs)
+        rho = rho + rho_s
+        if d < 0:
+            left = (c, p, g)
+        else:
+            right = (c, p, g)
+        if not _no_uturn(left[1], right[1], rho, sig2):
+            break
+    return cand, cand_l, depth, n_leaf, div
+
+
+def nuts_step(pt, c0, z, dirs, merges, leaves, sigma, eps, max_depth, t_min, t_max, d_min, d_max, beta=1.0):
+    """nuts_chain for every chain on the target L^beta p in the sampler
+    coordinates (the potential of hmc_potential).  c0, z [7, n]; dirs,
+    merges [max_depth, n]; leaves [2^max_depth - 1, n].  Returns (c [7, n],
+    lnL [n], depth [n], steps [n], divergent [n])."""
+    c0 = np.asarray(c0, np.float64)
+    n = c0.shape[1]
+
+    def pot(c):
+        return hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta)
+
+    out = np.empty_like(c0)
+    ll = np.empty(n)
+    dep = np.zeros(n, np.int32)
+    st = np.zeros(n, np.int32)
+    dv = np.zeros(n, bool)
+    for i in range(n):
+        c, l, dd, ss, vv = nuts_chain(pot, c0[:, i], z[:, i], dirs[:, i], merges[:, i], leaves[:, i], sigma, eps,
+                                      max_depth)
+        out[:, i], ll[i], dep[i], st[i], dv[i] = c, l, dd, ss, vv
+    return out, ll, dep, st, dv
+
+
 def _lse(v):
     v = np.asarray(v, np.float64)
     m = np.max(v)
