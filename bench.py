@@ -896,6 +896,62 @@ def extra_hmc(ile, synth, torch, steps, chains=16384, n_leapfrog=8, cpu=True):
     return res
 
 
+def extra_nuts(ile, synth, torch, steps, chains=16384, max_depth=6, cpu=True):
+    """No-U-Turn transitions of 16384 chains (3 detectors, 9 modes, SNR 100),
+    at most 6 doublings, the chains in lockstep with one gradient launch per
+    leapfrog step for the batch; random numbers drawn beforehand (not
+    timed)."""
+    pt = synth.make_point(3, 9, 6554, 32768.0, 100.0, 44)
+    sig = np.array([1e-3, 1e-3, 5e-3, 5e-3, 5e-3, 3e-6, 5e-3])
+    box = (-0.01, 0.01, 10.0, 1000.0)
+    eps, D = 0.3, max_depth
+    th0 = seed_near_peak(ile, torch, synth, pt, sig)
+    start = synth.perturbed_samples(th0, sig, chains, 6)
+    start[3] = np.cos(start[3])
+    start[6] = np.log(start[6])
+    plan = ile.Plan([pt], [chains])
+    c = torch.as_tensor(start, device="cuda").contiguous()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9)
+    burn, k = 3, max(4, steps // 2)
+    tot = burn + k
+    Z = torch.randn((tot, 7, chains), dtype=torch.float64, device="cuda", generator=gen)
+    DI = torch.rand((tot, D, chains), dtype=torch.float64, device="cuda", generator=gen)
+    ME = torch.rand((tot, D, chains), dtype=torch.float64, device="cuda", generator=gen)
+    LE = torch.rand((tot, 2 ** D - 1, chains), dtype=torch.float64, device="cuda", generator=gen)
+    ll = torch.empty(chains, dtype=torch.float64, device="cuda")
+    info = torch.empty((3, chains), dtype=torch.int32, device="cuda")
+    it = iter(range(tot))
+    stats = []
+
+    def step():
+        i = next(it)
+        plan.nuts(0, c, Z[i], DI[i], ME[i], LE[i], sig, eps, D, box, lnL_out=ll, info_out=info)
+
+    for _ in range(burn):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps_total = 0
+    depth_total = 0.0
+    for _ in range(k):
+        step()
+        inf = info.cpu().numpy()
+        steps_total += int(inf[1].sum())
+        depth_total += float(inf[0].mean())
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    per = secs / k
+    plan.close()
+    return {"workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 100; 16384 chains, one "
+                        "No-U-Turn transition (at most 6 doublings, step 0.3) per call",
+            "transitions_per_s": chains / per, "ms_per_transition": 1e3 * per,
+            "leapfrog_steps_per_s": steps_total / secs, "mean_steps": steps_total / (k * chains),
+            "mean_depth": depth_total / k, "mean_lnL": float(ll.mean().item()),
+            "note": "wall time per call, including the per-step launches and the early-stop checks (the chains "
+                    "advance in lockstep, so a call lasts as long as its longest tree)"}
+
+
 def extra_smc(ile, synth, torch, steps, particles=65536, cpu=True):
     """An adaptive SMC ladder (Eqs. (sampler-menu:tempered-target),
     (sampler-menu:smc-update)) from the prior to the posterior of a 3-detector,
@@ -968,9 +1024,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,tband,pmarg,erai,hmc,smc",
+    ap.add_argument("--workloads", default="c1,c4,c5,wide,dmarg,pregrid,tmarg,tband,pmarg,erai,hmc,nuts,smc",
                     help="workloads timed beside the headline one (comma list of c1, c4, c5, wide, dmarg, pregrid, "
-                         "tmarg, tband, pmarg, erai, hmc, smc, "
+                         "tmarg, tband, pmarg, erai, hmc, nuts, smc, "
                          "c3, c1big; "
                          "'none' for the headline alone)")
     ap.add_argument("--extras", nargs="?", const="c3,c1big,c5batch", default="",
@@ -1095,7 +1151,7 @@ def main():
     fns = {"c1": extra_c1, "c4": extra_c4, "c5": extra_c5, "c3": extra_c3, "c1big": extra_c1_big,
            "c5batch": extra_c5_batch, "wide": extra_wide, "dmarg": extra_dmarg, "pregrid": extra_pregrid,
            "tmarg": extra_tmarg, "tband": extra_tband, "pmarg": extra_pmarg, "erai": extra_erai,
-           "hmc": extra_hmc, "smc": extra_smc}
+           "hmc": extra_hmc, "nuts": extra_nuts, "smc": extra_smc}
     for name in wanted:
         log(f"workload {name}")
         try:

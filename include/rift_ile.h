@@ -497,6 +497,36 @@ int rift_ile_plan_hmc_tempered(rift_ile_plan plan, int32_t point, int64_t n, dou
                                const rift_ile_hmc_prior *prior, double beta, double *lnL, int32_t *accepted,
                                void *stream);
 
+/* One No-U-Turn transition per chain (Sec. "Sampler menu": multinomial NUTS
+ * with the generalised criterion) on the tempered target L^beta p, in the
+ * coordinates and with the prior box of rift_ile_plan_hmc, the random numbers
+ * the caller's: momenta p = z / sigma; at depth j the trajectory doubles in
+ * direction -1 if dirs[j] < 1/2 else +1 by a subtree of 2^j leapfrog steps
+ * (size eps) from that edge.  Within a subtree the leaves are built outward;
+ * leaf k (weight e^{-H}) becomes the subtree's candidate when the next of
+ * `leaves` is below its share of the subtree's weight so far, and every
+ * completed aligned block of 2, 4, .. leaves is checked for a U-turn
+ * (sigma^2 p_edge . rho > 0 at both edges, rho the block's momentum sum).  A
+ * U-turn inside the subtree, or a leaf whose energy exceeds the start's by
+ * 1000, discards it and ends the transition; otherwise its candidate
+ * replaces the transition's with probability min(1, W_subtree / W) against
+ * merges[j], and a U-turn of the whole trajectory ends it.  At most
+ * max_depth (1 .. 10) doublings.
+ * theta: DEVICE [7][n] (replaced by the transitions' draws); z: DEVICE [7][n];
+ * dirs, merges: DEVICE [max_depth][n]; leaves: DEVICE [2^max_depth - 1][n]
+ * (uniforms); sigma: HOST [7]; lnL: DEVICE [n] or NULL (lnL at the draws);
+ * info: DEVICE int32 [3][n] or NULL (doublings completed, leapfrog steps,
+ * divergent).  The chains step in lockstep, one gradient launch per step for
+ * the batch; the call synchronises `stream` every fourth step to stop once no
+ * chain is active.  Stream-ordered scratch of 8 (112 + 14 max_depth) n bytes
+ * and a little more.  A start whose energy is not finite is returned
+ * unchanged.  RIFT_EINVAL as rift_ile_plan_hmc_tempered, and for max_depth
+ * outside 1 .. 10. */
+int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, double *theta, const double *z,
+                       const double *dirs, const double *merges, const double *leaves, const double *sigma,
+                       double eps, int32_t max_depth, const rift_ile_hmc_prior *prior, double beta, double *lnL,
+                       int32_t *info, void *stream);
+
 /* One update of an SMC tempering ladder (Sec. "Sampler menu",
  * Eq. (sampler-menu:smc-update)) over n weighted particles: with W the
  * normalised weights from lnW (DEVICE [n], any normalisation; -inf excludes a

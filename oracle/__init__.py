@@ -771,6 +771,8 @@ def nuts_chain(potential, c0, z, dirs, merges, leaves, sigma, eps, max_depth):
     l0, U0, g0 = potential(c0[:, None])
     l0, U0, g0 = float(l0[0]), float(U0[0]), g0[:, 0]
     H0 = U0 + 0.5 * float(np.sum(sig2 * p0 * p0))
+    if not np.isfinite(H0):  # a start outside the prior's support does not move
+        return c0, l0, 0, 0, False
     left = right = (c0, p0, g0)
     cand, cand_l = c0, l0
     logW = 0.0

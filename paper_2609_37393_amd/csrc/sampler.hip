@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "../../include/rift_ile.h"
 
@@ -140,6 +141,279 @@ __global__ void k_hmc_end(int64_t n, double* __restrict__ c, const double* __res
     }
     if (lnL_out) lnL_out[i] = acc ? lnL1[i] : lnL0[i];
     if (accepted) accepted[i] = acc ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// No-U-Turn transitions (multinomial NUTS with the generalised criterion) of
+// a batch of chains in lockstep: every pass takes one leapfrog step of every
+// active chain from its own moving edge in its own direction, with one
+// gradient launch for the batch between a "pre" kernel (half kick and drift)
+// and a "post" kernel (half kick, energy, leaf sampling, U-turn checks,
+// merge).  Per-chain state is SoA in a stream-ordered scratch; the random
+// numbers are the caller's.
+// ---------------------------------------------------------------------------
+constexpr int NUTS_MAX_DEPTH = 10;
+constexpr double NUTS_MAX_DH = 1000.0;
+
+// Row offsets (in units of n doubles) of the state.
+struct NutsLayout {
+  int cL, pL, gL, cR, pR, gR, cX, pX, gX, cS, lS, cT, lT, rho, rhoS, ckP, ckS, H0, logW, logWs, lX, cE, lE, gE;
+  int rows;
+};
+__host__ __device__ inline NutsLayout nuts_layout(int D) {
+  NutsLayout L;
+  int r = 0;
+  L.cL = r; r += 7; L.pL = r; r += 7; L.gL = r; r += 7;
+  L.cR = r; r += 7; L.pR = r; r += 7; L.gR = r; r += 7;
+  L.cX = r; r += 7; L.pX = r; r += 7; L.gX = r; r += 7;
+  L.cS = r; r += 7; L.lS = r; r += 1; L.cT = r; r += 7; L.lT = r; r += 1;
+  L.rho = r; r += 7; L.rhoS = r; r += 7;
+  L.ckP = r; r += 7 * D; L.ckS = r; r += 7 * D;
+  L.H0 = r++; L.logW = r++; L.logWs = r++; L.lX = r++;
+  L.cE = r; r += 7; L.lE = r; r += 1; L.gE = r; r += 7;
+  L.rows = r;
+  return L;
+}
+// int state rows: depth j, leaf k within the subtree, direction, leaves used,
+// status (1 active), divergent, leapfrog steps
+enum { NI_J = 0, NI_K, NI_DIR, NI_LEAF, NI_ACT, NI_DIV, NI_STEPS, NI_ROWS };
+
+__device__ __forceinline__ double lae(double a, double b) {  // ln(e^a + e^b)
+  const double m = fmax(a, b);
+  if (m == -__builtin_inf()) return m;
+  return m + log(exp(a - m) + exp(b - m));
+}
+
+__device__ __forceinline__ double nuts_energy(const HmcPrior& P, double beta, double l, const double* c,
+                                              const double* p, Step7 sig) {
+  double kin = 0.0;
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    const double v = sig.s[a] * p[a];
+    kin = fma(v, v, kin);
+  }
+  return -(beta * l + hmc_log_prior(P, c[1], c[3], c[5], c[6])) + 0.5 * kin;
+}
+
+// After the gradient at the start: momenta, start energy, the one-state
+// trajectory.  A start whose energy is not finite is done at once.
+__global__ void k_nuts_init(int64_t n, const double* __restrict__ c0, const double* __restrict__ z, Step7 sig,
+                            double beta, HmcPrior P, double* __restrict__ W, int32_t* __restrict__ I, NutsLayout Ly) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double c[7], p[7];
+    const double l = W[Ly.lE * n + i];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      c[a] = c0[a * n + i];
+      p[a] = z[a * n + i] / sig.s[a];
+    }
+    const double dec = c[1];
+    const double H0 = nuts_energy(P, beta, l, c, p, sig);
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      const double g = dlnpi(a, beta * W[(Ly.gE + a) * n + i], dec);
+      W[(Ly.cL + a) * n + i] = c[a];
+      W[(Ly.pL + a) * n + i] = p[a];
+      W[(Ly.gL + a) * n + i] = g;
+      W[(Ly.cR + a) * n + i] = c[a];
+      W[(Ly.pR + a) * n + i] = p[a];
+      W[(Ly.gR + a) * n + i] = g;
+      W[(Ly.cS + a) * n + i] = c[a];
+      W[(Ly.rho + a) * n + i] = p[a];
+    }
+    W[Ly.lS * n + i] = l;
+    W[Ly.H0 * n + i] = H0;
+    W[Ly.logW * n + i] = 0.0;
+    I[NI_J * n + i] = 0;
+    I[NI_K * n + i] = 0;
+    I[NI_DIR * n + i] = 1;
+    I[NI_LEAF * n + i] = 0;
+    I[NI_ACT * n + i] = (fabs(H0) <= 1.0e300) ? 1 : 0;
+    I[NI_DIV * n + i] = 0;
+    I[NI_STEPS * n + i] = 0;
+  }
+}
+
+// Half kick and drift of every active chain from its moving edge (a new
+// subtree starts from the trajectory's edge in the drawn direction); the
+// point to evaluate goes to cE (inactive chains evaluate their candidate).
+__global__ void k_nuts_pre(int64_t n, const double* __restrict__ dirs, double eps, Step7 sig2, double* __restrict__ W,
+                           int32_t* __restrict__ I, NutsLayout Ly) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!I[NI_ACT * n + i]) {
+#pragma unroll
+      for (int a = 0; a < 7; ++a) W[(Ly.cE + a) * n + i] = W[(Ly.cS + a) * n + i];
+      continue;
+    }
+    const int j = I[NI_J * n + i];
+    if (I[NI_K * n + i] == 0) {
+      const int d = dirs[(int64_t)j * n + i] < 0.5 ? -1 : 1;
+      I[NI_DIR * n + i] = d;
+      const int c = d < 0 ? Ly.cL : Ly.cR, pp = d < 0 ? Ly.pL : Ly.pR, g = d < 0 ? Ly.gL : Ly.gR;
+#pragma unroll
+      for (int a = 0; a < 7; ++a) {
+        W[(Ly.cX + a) * n + i] = W[(c + a) * n + i];
+        W[(Ly.pX + a) * n + i] = W[(pp + a) * n + i];
+        W[(Ly.gX + a) * n + i] = W[(g + a) * n + i];
+        W[(Ly.rhoS + a) * n + i] = 0.0;
+      }
+      W[Ly.logWs * n + i] = -__builtin_inf();
+    }
+    const double h = 0.5 * eps * (double)I[NI_DIR * n + i];
+    const double ds = eps * (double)I[NI_DIR * n + i];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      double pa = fma(h, W[(Ly.gX + a) * n + i], W[(Ly.pX + a) * n + i]);
+      const double ca = drift_one(a, W[(Ly.cX + a) * n + i], pa, ds * sig2.s[a]);
+      W[(Ly.cX + a) * n + i] = ca;
+      W[(Ly.pX + a) * n + i] = pa;
+      W[(Ly.cE + a) * n + i] = ca;
+    }
+  }
+}
+
+__device__ __forceinline__ bool no_uturn(const double* pa, const double* pb, const double* rho, Step7 sig2) {
+  double da = 0.0, db = 0.0;
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    da = fma(sig2.s[a] * pa[a], rho[a], da);
+    db = fma(sig2.s[a] * pb[a], rho[a], db);
+  }
+  return da > 0.0 && db > 0.0;
+}
+
+// The second half kick and the leaf's bookkeeping (see nuts_chain in the
+// reference description: leaf sampling, block checks, merge, trajectory
+// check).
+__global__ void k_nuts_post(int64_t n, const double* __restrict__ merges, const double* __restrict__ leaves, double eps,
+                            double beta, Step7 sig, Step7 sig2, HmcPrior P, int D, double* __restrict__ W,
+                            int32_t* __restrict__ I, NutsLayout Ly) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!I[NI_ACT * n + i]) continue;
+    const int j = I[NI_J * n + i], k = I[NI_K * n + i], dir = I[NI_DIR * n + i];
+    const double h = 0.5 * eps * (double)dir;
+    double c[7], p[7], g[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) c[a] = W[(Ly.cX + a) * n + i];
+    const double l = W[Ly.lE * n + i];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      g[a] = dlnpi(a, beta * W[(Ly.gE + a) * n + i], c[1]);
+      p[a] = fma(h, g[a], W[(Ly.pX + a) * n + i]);
+      W[(Ly.pX + a) * n + i] = p[a];
+      W[(Ly.gX + a) * n + i] = g[a];
+    }
+    W[Ly.lX * n + i] = l;
+    const int leaf = I[NI_LEAF * n + i] + 1;
+    I[NI_LEAF * n + i] = leaf;
+    I[NI_STEPS * n + i] += 1;
+    const double H0 = W[Ly.H0 * n + i];
+    const double H = nuts_energy(P, beta, l, c, p, sig);
+    if (!(H - H0 <= NUTS_MAX_DH)) {
+      I[NI_DIV * n + i] = 1;
+      I[NI_ACT * n + i] = 0;
+      continue;
+    }
+    const double lw = H0 - H;
+    const double lws = lae(W[Ly.logWs * n + i], lw);
+    W[Ly.logWs * n + i] = lws;
+    if (leaves[(int64_t)(leaf - 1) * n + i] < exp(lw - lws)) {
+#pragma unroll
+      for (int a = 0; a < 7; ++a) W[(Ly.cT + a) * n + i] = c[a];
+      W[Ly.lT * n + i] = l;
+    }
+    // block checkpoints: the first leaf of every block that starts here
+    double rs[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) rs[a] = W[(Ly.rhoS + a) * n + i];
+    for (int lv = 1; lv <= j; ++lv) {
+      if (k % (1 << lv) != 0) break;
+#pragma unroll
+      for (int a = 0; a < 7; ++a) {
+        W[(Ly.ckP + 7 * (lv - 1) + a) * n + i] = p[a];
+        W[(Ly.ckS + 7 * (lv - 1) + a) * n + i] = rs[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      rs[a] += p[a];
+      W[(Ly.rhoS + a) * n + i] = rs[a];
+    }
+    // U-turn checks of the blocks that end here, smallest first
+    bool valid = true;
+    for (int lv = 1; lv <= j && valid; ++lv) {
+      if ((k + 1) % (1 << lv) != 0) break;
+      double pa[7], rb[7];
+#pragma unroll
+      for (int a = 0; a < 7; ++a) {
+        pa[a] = W[(Ly.ckP + 7 * (lv - 1) + a) * n + i];
+        rb[a] = rs[a] - W[(Ly.ckS + 7 * (lv - 1) + a) * n + i];
+      }
+      valid = no_uturn(pa, p, rb, sig2);
+    }
+    if (!valid) {
+      I[NI_ACT * n + i] = 0;
+      continue;
+    }
+    if (k + 1 < (1 << j)) {
+      I[NI_K * n + i] = k + 1;
+      continue;
+    }
+    // the subtree is complete and valid: merge it
+    const double logW = W[Ly.logW * n + i];
+    if (merges[(int64_t)j * n + i] < exp(lws - logW)) {
+#pragma unroll
+      for (int a = 0; a < 7; ++a) W[(Ly.cS + a) * n + i] = W[(Ly.cT + a) * n + i];
+      W[Ly.lS * n + i] = W[Ly.lT * n + i];
+    }
+    W[Ly.logW * n + i] = lae(logW, lws);
+    double rho[7], pl[7], pr[7];
+    const int ec = dir < 0 ? Ly.cL : Ly.cR, ep = dir < 0 ? Ly.pL : Ly.pR, eg = dir < 0 ? Ly.gL : Ly.gR;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      rho[a] = W[(Ly.rho + a) * n + i] + rs[a];
+      W[(Ly.rho + a) * n + i] = rho[a];
+      W[(ec + a) * n + i] = c[a];
+      W[(ep + a) * n + i] = p[a];
+      W[(eg + a) * n + i] = g[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      pl[a] = W[(Ly.pL + a) * n + i];
+      pr[a] = W[(Ly.pR + a) * n + i];
+    }
+    I[NI_J * n + i] = j + 1;
+    I[NI_K * n + i] = 0;
+    if (!no_uturn(pl, pr, rho, sig2) || j + 1 >= D) I[NI_ACT * n + i] = 0;
+  }
+}
+
+__global__ void k_nuts_count(int64_t n, const int32_t* __restrict__ I, int32_t* __restrict__ cnt) {
+  __shared__ int32_t sh[256];
+  int32_t c = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += I[NI_ACT * n + i];
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[blockIdx.x] = sh[0];
+}
+
+__global__ void k_nuts_out(int64_t n, const double* __restrict__ W, const int32_t* __restrict__ I, NutsLayout Ly,
+                           double* __restrict__ theta, double* __restrict__ lnL, int32_t* __restrict__ info) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < 7; ++a) theta[a * n + i] = W[(Ly.cS + a) * n + i];
+    if (lnL) lnL[i] = W[Ly.lS * n + i];
+    if (info) {
+      info[i] = I[NI_J * n + i];
+      info[n + i] = I[NI_STEPS * n + i];
+      info[2 * n + i] = I[NI_DIV * n + i];
+    }
   }
 }
 
@@ -394,6 +668,75 @@ __global__ void k_resample_pick(int64_t n, const double* __restrict__ C, double 
 }
 
 }  // namespace
+
+extern "C" int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
+                                  const double* dirs, const double* merges, const double* leaves, const double* sigma,
+                                  double eps, int32_t max_depth, const rift_ile_hmc_prior* prior, double beta,
+                                  double* lnL, int32_t* info, void* stream) {
+  if (!plan || n < 0 || !sigma || !prior) return RIFT_EINVAL;
+  if (!(eps > 0.0) || !std::isfinite(eps) || max_depth < 1 || max_depth > NUTS_MAX_DEPTH) return RIFT_EINVAL;
+  if (!(beta >= 0.0 && beta <= 1.0)) return RIFT_EINVAL;
+  if (!std::isfinite(prior->t_min) || !std::isfinite(prior->t_max) || !(prior->t_max > prior->t_min)) return RIFT_EINVAL;
+  if (!(prior->d_min > 0.0) || !(prior->d_max > prior->d_min) || !std::isfinite(prior->d_max)) return RIFT_EINVAL;
+  Step7 sig, sig2;
+  for (int a = 0; a < 7; ++a) {
+    if (!(sigma[a] > 0.0) || !std::isfinite(sigma[a])) return RIFT_EINVAL;
+    sig.s[a] = sigma[a];
+    sig2.s[a] = sigma[a] * sigma[a];
+  }
+  if (n == 0) return RIFT_OK;
+  auto bad = [](const void* q) { return !q || (((uintptr_t)q) & 7u); };
+  if (bad(theta) || bad(z) || bad(dirs) || bad(merges) || bad(leaves) || (lnL && bad(lnL)) ||
+      (info && (((uintptr_t)info) & 3u)))
+    return RIFT_EINVAL;
+  HmcPrior P;
+  P.t_min = prior->t_min;
+  P.t_max = prior->t_max;
+  P.lnd_min = log(prior->d_min);
+  P.lnd_max = log(prior->d_max);
+  hipStream_t st = (hipStream_t)stream;
+  const NutsLayout Ly = nuts_layout(max_depth);
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  const unsigned cgrid = (unsigned)std::min<int64_t>((n + 255) / 256, 256);
+  const size_t bytes = sizeof(double) * (size_t)Ly.rows * (size_t)n + sizeof(int32_t) * ((size_t)NI_ROWS * n + cgrid);
+  void* w = nullptr;
+  if (hipMallocAsync(&w, bytes, st) != hipSuccess) return RIFT_ENOMEM;
+  double* Wd = (double*)w;
+  int32_t* I = (int32_t*)(Wd + (size_t)Ly.rows * n);
+  int32_t* cnt = I + (size_t)NI_ROWS * n;
+  std::vector<int32_t> hc(cgrid);
+  constexpr int coords = RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST;
+  int rc = rift_ile_plan_grad(plan, point, n, theta, coords, Wd + (size_t)Ly.lE * n, Wd + (size_t)Ly.gE * n, stream);
+  if (!rc)
+    hipLaunchKernelGGL(k_nuts_init, dim3(grid), dim3(256), 0, st, n, (const double*)theta, z, sig, beta, P, Wd, I, Ly);
+  const int iters = (1 << max_depth) - 1;
+  for (int it = 0; it < iters && !rc; ++it) {
+    hipLaunchKernelGGL(k_nuts_pre, dim3(grid), dim3(256), 0, st, n, dirs, eps, sig2, Wd, I, Ly);
+    rc = rift_ile_plan_grad(plan, point, n, Wd + (size_t)Ly.cE * n, coords, Wd + (size_t)Ly.lE * n,
+                            Wd + (size_t)Ly.gE * n, stream);
+    if (rc) break;
+    hipLaunchKernelGGL(k_nuts_post, dim3(grid), dim3(256), 0, st, n, merges, leaves, eps, beta, sig, sig2, P,
+                       (int)max_depth, Wd, I, Ly);
+    // every fourth pass, stop once no chain is active (synchronises)
+    if ((it & 3) == 3 && it + 1 < iters) {
+      hipLaunchKernelGGL(k_nuts_count, dim3(cgrid), dim3(256), 0, st, n, (const int32_t*)I, cnt);
+      if (hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * cgrid, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        rc = RIFT_EDEVICE;
+        break;
+      }
+      int64_t act = 0;
+      for (int32_t v : hc) act += v;
+      if (act == 0) break;
+    }
+  }
+  if (!rc)
+    hipLaunchKernelGGL(k_nuts_out, dim3(grid), dim3(256), 0, st, n, (const double*)Wd, (const int32_t*)I, Ly, theta, lnL,
+                       info);
+  if (!rc && hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
+  if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
+  return rc;
+}
 
 extern "C" int rift_ile_smc_reweight(int64_t n, const double* lnL, double* lnW, double beta, double target,
                                      double* out, void* stream) {

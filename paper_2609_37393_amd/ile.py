@@ -71,6 +71,7 @@ EXPORTS = (
     "rift_ile_plan_hmc_tempered",
     "rift_ile_smc_reweight",
     "rift_ile_smc_resample",
+    "rift_ile_plan_nuts",
 )
 
 RESPONSES = {"rotation": 1, "arms": 2}
@@ -193,6 +194,8 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(CHmcPrior), vp, vp, vp]
     lib.rift_ile_plan_hmc_tempered.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, i32,
                                                ctypes.POINTER(CHmcPrior), ctypes.c_double, vp, vp, vp]
+    lib.rift_ile_plan_nuts.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, ctypes.c_double, i32,
+                                       ctypes.POINTER(CHmcPrior), ctypes.c_double, vp, vp, vp]
     lib.rift_ile_smc_reweight.argtypes = [i64, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
     lib.rift_ile_smc_resample.argtypes = [i64, vp, ctypes.c_double, vp, vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
@@ -621,6 +624,24 @@ class Plan:
                                                        ctypes.byref(pr), float(beta), l.data_ptr(), acc.data_ptr(),
                                                        _stream(self.device)), "rift_ile_plan_hmc_tempered")
         return l, acc
+
+    def nuts(self, point, theta, z, dirs, merges, leaves, sigma, eps, max_depth, box, beta=1.0, lnL_out=None,
+             info_out=None):
+        """One No-U-Turn transition of every chain in place
+        (rift_ile_plan_nuts): theta [7, n] sampler coordinates, z [7, n]
+        normals, dirs and merges [max_depth, n] and leaves
+        [2^max_depth - 1, n] uniforms.  Returns (lnL [n], info [3, n] int32:
+        doublings, leapfrog steps, divergent)."""
+        n = theta.shape[1]
+        l = lnL_out if lnL_out is not None else torch.empty(n, dtype=torch.float64, device=self.device)
+        inf = info_out if info_out is not None else torch.empty((3, n), dtype=torch.int32, device=self.device)
+        sg = np.ascontiguousarray(sigma, dtype=np.float64)
+        pr = CHmcPrior(*[float(b) for b in box])
+        _check(self.lib.rift_ile_plan_nuts(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(), dirs.data_ptr(),
+                                           merges.data_ptr(), leaves.data_ptr(), sg.ctypes.data, float(eps),
+                                           int(max_depth), ctypes.byref(pr), float(beta), l.data_ptr(),
+                                           inf.data_ptr(), _stream(self.device)), "rift_ile_plan_nuts")
+        return l, inf
 
     def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):
         """Gradient of lnL with theta rows 3 and 6 in the coordinates `coords`
