@@ -151,7 +151,7 @@ class _CPointWide(ctypes.Structure):
     ]
 
 
-RESPONSES = {"rotation": 1, "arms": 2}
+RESPONSES = {"rotation": 1, "arms": 2, "rotation_delay": 3}
 
 
 def _pack_wide(pt) -> _Packed:

@@ -374,7 +374,7 @@ void wide_coefficients(const PointWide& p, double ra, double dec, double psi, do
                        std::vector<Cx<double>>& C, std::vector<double>& tk) {
   C.assign((size_t)p.K * p.n_a, Cx<double>{0.0, 0.0});
   tk.assign(p.K, 0.0);
-  const double gm = (p.response == 1) ? p.gmst + p.omega * tref : p.gmst;
+  const double gm = (p.response == 1 || p.response == 3) ? p.gmst + p.omega * tref : p.gmst;
   double N[3], X[3], Y[3];
   sky_frame<double>(ra, dec, psi, gm, N, X, Y);
   for (int k = 0; k < p.K; ++k) {
@@ -388,6 +388,58 @@ void wide_coefficients(const PointWide& p, double ra, double dec, double psi, do
         const int n = a - 2;
         const double ph = n * gref + n * p.omega * (tk[k] - tref);
         C[(size_t)k * p.n_a + a] = cmul(A[a], Cx<double>{std::cos(ph), std::sin(ph)});
+      }
+    } else if (p.response == 3) {
+      // rotation with the delay drift to order P (Path B), n_a = (P + 1)(P + 5):
+      // index a = P(4 + P) offset of order p, then n~ = -(2 + p) .. 2 + p.
+      // The delay tau(g) = -r . N(g) over the hour angle g carries the
+      // harmonics 0, +-1; -dt(phi) = -(tau(g_ref + phi) - tau(g_ref)) in the
+      // modulation phase phi = Omega (t - t_ref):
+      //   m = 0: -cos(dec) Re(rho e^{i g_ref}),  m = +1: cos(dec)/2 rho e^{i g_ref},
+      //   m = -1: cos(dec)/2 conj(rho e^{i g_ref}),  rho = r_x + i r_y.
+      // C_(p, n~) = (1/p!) sum_{n + m = n~} A_n e^{i n g_ref} [(-dt)^{*p}]_m
+      // (Eq. (slowrot:master)), then the post-phase e^{i n~ Omega (t_k - t_ref)}.
+      int P = 0;
+      while ((P + 1) * (P + 5) < p.n_a) ++P;
+      Cx<double> A[5];
+      rotation_harmonics(p.det_tensor + 9 * k, dec, psi, A);
+      const double gref = gm - ra;
+      const Cx<double> eg{std::cos(gref), std::sin(gref)};
+      const Cx<double> re = cmul(Cx<double>{r[0], r[1]}, eg);
+      const double cdec = std::cos(dec);
+      // harmonics of -dt, index m + 1
+      const Cx<double> D1[3] = {Cx<double>{0.5 * cdec * re.re, -0.5 * cdec * re.im}, Cx<double>{-cdec * re.re, 0.0},
+                                Cx<double>{0.5 * cdec * re.re, 0.5 * cdec * re.im}};
+      std::vector<Cx<double>> pw(1, Cx<double>{1.0, 0.0});  // (-dt)^p, index m + p
+      double fact = 1.0;
+      int base = 0;
+      for (int pp = 0; pp <= P; ++pp) {
+        if (pp > 0) {
+          std::vector<Cx<double>> nx(2 * pp + 1, Cx<double>{0.0, 0.0});
+          for (int m = -(pp - 1); m <= pp - 1; ++m)
+            for (int d = -1; d <= 1; ++d) {
+              const Cx<double> t = cmul(pw[m + pp - 1], D1[d + 1]);
+              nx[m + d + pp].re += t.re;
+              nx[m + d + pp].im += t.im;
+            }
+          pw.swap(nx);
+          fact *= pp;
+        }
+        for (int nt = -(2 + pp); nt <= 2 + pp; ++nt) {
+          Cx<double> acc{0.0, 0.0};
+          for (int n = -2; n <= 2; ++n) {
+            const int m = nt - n;
+            if (m < -pp || m > pp) continue;
+            const Cx<double> an = cmul(A[n + 2], Cx<double>{std::cos(n * gref), std::sin(n * gref)});
+            const Cx<double> t = cmul(an, pw[m + pp]);
+            acc.re += t.re;
+            acc.im += t.im;
+          }
+          const double ph = nt * p.omega * (tk[k] - tref);
+          const Cx<double> c = cmul(acc, Cx<double>{std::cos(ph) / fact, std::sin(ph) / fact});
+          C[(size_t)k * p.n_a + base + nt + 2 + pp] = c;
+        }
+        base += 5 + 2 * pp;
       }
     } else {
       const double* ax = p.det_arms + 6 * k;

@@ -74,7 +74,7 @@ EXPORTS = (
     "rift_ile_plan_nuts",
 )
 
-RESPONSES = {"rotation": 1, "arms": 2}
+RESPONSES = {"rotation": 1, "arms": 2, "rotation_delay": 3}
 
 
 class CPoint(ctypes.Structure):

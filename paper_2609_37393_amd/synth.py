@@ -322,7 +322,8 @@ def make_point_wide(K: int, M: int, n_a: int, n_t: int, fs: float, snr: float, s
     (the elementary modulated templates, or the frequency-weighted modes of the
     finite-arm expansion, are built upstream of the likelihood): chi_(a,lm)(f) =
     h_lm(f) w_a(f), with w_a(f) = 1 for the leading term (a = 2, n = 0, for the
-    rotation response; a = 0 for the arms) and otherwise a smooth seeded
+    rotation responses, the term (p = 0, n = 0) with the delay drift; a = 0 for
+    the arms) and otherwise a smooth seeded
     complex weight of amplitude 0.2-0.6.  The injection's coefficients are a
     generic rank-one z_(k,(a,lm)) = alpha_(k,a) y_lm with arrival times t_k.
     """
@@ -330,7 +331,7 @@ def make_point_wide(K: int, M: int, n_a: int, n_t: int, fs: float, snr: float, s
     M = lm.shape[0]
     f, G = mode_spectra(lm, seed)
     rng = _rng(seed, 123)
-    lead = 2 if response == "rotation" else 0
+    lead = 2 if response in ("rotation", "rotation_delay") else 0
     Wt = np.ones((n_a, f.size), np.complex128)
     for a in range(n_a):
         if a == lead:
@@ -381,7 +382,7 @@ def make_point_wide(K: int, M: int, n_a: int, n_t: int, fs: float, snr: float, s
         "lm": lm, "t0": -j0 / fs, "dt": 1.0 / fs, "Q": Q, "U": U, "V": V,
         "det_tensor": net["det_tensor"], "det_pos": net["det_pos"], "det_arms": net["det_arms"],
         "gmst": net["gmst"], "d_ref": float(d_ref), "response": response, "n_a": int(n_a),
-        "omega": float(omega if response == "rotation" else 0.0), "snr": float(snr),
+        "omega": float(omega if response in ("rotation", "rotation_delay") else 0.0), "snr": float(snr),
         "half_dd": 0.5 * float(np.sum(w * np.abs(d) ** 2)),
     }
     if keep_spectra:

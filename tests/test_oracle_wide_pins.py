@@ -9,6 +9,9 @@ mathematics fix, not against the oracle itself:
   template sum_n C~_n chi_n placed at t_k equals F_k(t) h(t - t_k) at every
   time t, with the modulation of the bank referenced to the template's own
   time (Eqs. (slowrot:master), (slowrot:commutator), (slowrot:postphase));
+* the delay-drift coefficients (Path B): the composite template of order P
+  equals the order-P Taylor series of the strain with the drifting delay,
+  exactly, and order 0 is Path A;
 * the finite-arm coefficients: sum_p b_p W_p reproduces the Michelson response
   built from the arm transfer function, with W_p the Taylor coefficients of
   the residual transfer in u = a.n (Eqs. (slowrot:armtransfer), (fsize:FA),
@@ -77,6 +80,50 @@ def test_rotation_template_identity(oracle_mod, omega):
                 assert abs(got - F) < 1e-12, (omega, k, got, F)
 
 
+@pytest.mark.parametrize("omega", [synth.SIDEREAL_RATE * 3e3, 40.0])
+def test_delay_drift_template(oracle_mod, omega):
+    """Path B (Eq. (slowrot:delay) composed with Eq. (slowrot:Fharm) into
+    Eq. (slowrot:master)).  For a pure tone h(t) = e^{i w t}, whose p-th
+    derivative is (i w)^p h, the composite template placed at t_k,
+      sum_{p <= P, n} C~_(p,n) e^{i n W (t - t_k)} (i w)^p e^{i w (t - t_k)},
+    equals F_k(t) e^{i w (t - t_k)} sum_{p <= P} (-i w dt(t))^p / p! exactly,
+    with F_k(t) the antenna factor at the sidereal angle of time t and dt(t)
+    the drift of the arrival-time delay since t_ref (the sky frame at each
+    t): the order-P Taylor series of the strain F_k(t) h(t - t_k - dt(t)).
+    Order 0 is the rotation coefficients (Path A)."""
+    th = synth.prior_samples(6, 8)
+    pts = {n_a: synth.make_point_wide(3, 2, n_a, 400, 4096.0, 20.0, 3, response="rotation_delay", omega=omega)
+           for n_a in (5, 12, 21, 32)}
+    rot = synth.make_point_wide(3, 2, 5, 400, 4096.0, 20.0, 3, response="rotation", omega=omega)
+    for i in range(th.shape[1]):
+        C0, _ = oracle_mod.wide_coef(pts[5], th[:, i])
+        Cr, _ = oracle_mod.wide_coef(rot, th[:, i])
+        assert np.allclose(C0, Cr, rtol=0, atol=1e-14)
+        ra, dec, psi, tref = th[0, i], th[1, i], th[2, i], th[5, i]
+        for P, n_a in ((1, 12), (2, 21), (3, 32)):
+            pt = pts[n_a]
+            C, tk = oracle_mod.wide_coef(pt, th[:, i])
+            for k in range(3):
+                ts = tref + np.linspace(-0.05, 0.05, 9)
+                dts = np.array([oracle_mod.arrival_time(pt["det_pos"][k], ra, dec, pt["gmst"] + omega * t, t) - t
+                                for t in ts]) - (tk[k] - tref)
+                w = 0.7 / max(np.abs(dts).max(), 1e-9)  # w |dt| up to 0.7
+                for t, dt in zip(ts, dts):
+                    F, _ = oracle_mod.antenna(pt["det_tensor"][k], ra, dec, psi, pt["gmst"] + omega * t)
+                    want = F * sum((-1j * w * dt) ** p / np.prod(np.arange(1, p + 1)) for p in range(P + 1))
+                    got, a, scale = 0.0j, 0, 0.0
+                    for p in range(P + 1):
+                        for nt in range(-(2 + p), 3 + p):
+                            term = C[k, a] * np.exp(1j * nt * omega * (t - tk[k])) * (1j * w) ** p
+                            got += term
+                            scale += abs(term)
+                            a += 1
+                    # the harmonic form of (-dt)^p cancels: its coefficients are
+                    # of size (|r| cos dec)^p while dt^p is far smaller, so the
+                    # rounding of the sum is relative to its terms' magnitudes
+                    assert abs(got - want) <= 1e-13 * scale + 1e-12 * abs(F), (omega, P, k, got, want, scale)
+
+
 def _dhat(u, x):
     """Residual arm transfer e^{2 i x} D~(u, x) of Eq. (fsize:Dhat), from the
     two-leg transfer function of Eq. (slowrot:armtransfer) with x = pi f T."""
@@ -132,7 +179,7 @@ def _direct_wide(sp, C, tk, Y, x):
     return tot
 
 
-@pytest.mark.parametrize("resp,n_a", [("rotation", 5), ("arms", 3)])
+@pytest.mark.parametrize("resp,n_a", [("rotation", 5), ("arms", 3), ("rotation_delay", 12)])
 def test_wide_likelihood_equals_direct_inner_products(oracle_mod, resp, n_a):
     pt = synth.make_point_wide(3, 4, n_a, 6554, 32768.0, 60.0, 21, response=resp, keep_spectra=True)
     sp = pt["spectra"]
@@ -159,7 +206,7 @@ def test_zero_rotation_and_zeroth_arm_order_give_the_static_likelihood(oracle_mo
     assert np.all(np.abs(got - want) <= 1e-12 * S * 40), np.abs(got - want).max()
 
 
-@pytest.mark.parametrize("resp,n_a", [("rotation", 5), ("arms", 4)])
+@pytest.mark.parametrize("resp,n_a", [("rotation", 5), ("arms", 4), ("rotation_delay", 12)])
 def test_wide_cauchy_schwarz_and_distance(oracle_mod, resp, n_a):
     pt = synth.make_point_wide(3, 4, n_a, 3000, 32768.0, 200.0, 41, response=resp)
     th = synth.prior_samples(3000, 42)
