@@ -242,17 +242,28 @@ int rift_ile_plan_destroy(rift_ile_plan plan);
  * RIFT_RESP_ARMS (finite arms, Path D): n_terms = p_max + 1 <= 8, a <-> order p;
  *   C~_p = b_p = 1/2 [(x.N)^p e:xx - (y.N)^p e:yy] with the arm unit vectors
  *   x, y of each detector and e = e+ + i ex (Eq. (fsize:bp)); static sky frame;
- *   p_max = 0 is the static likelihood (with det_tensor = (x x^T - y y^T)/2). */
+ *   p_max = 0 is the static likelihood (with det_tensor = (x x^T - y y^T)/2).
+ * RIFT_RESP_ROTATION_DELAY (Earth rotation with the delay drift, Path B):
+ *   n_terms = 5 (order 0, Path A) or 12 (order 1); a <-> (p, n), p = 0: a = n + 2
+ *   (n = -2..2), p = 1: a = 5 + n + 3 (n = -3..3); the delay tau = -r_k . N over
+ *   the hour angle carries the harmonics 0, +-1, so the drift -dt since t_ref
+ *   has, in the modulation phase, the three terms -cos(dec) Re(rho e^{i g(tref)})
+ *   (m = 0) and cos(dec)/2 (rho e^{i g(tref)})^(+-1 conjugated for m = -1),
+ *   rho = r_x + i r_y; C_(p, n) = (1/p!) sum_{n' + m = n} A_n' e^{i n' g(tref)}
+ *   [(-dt)^{*p}]_m (Eqs. (slowrot:delay), (slowrot:master)), then the post-phase
+ *   e^{i n omega (t_k - tref)}.  The bank's term (p, n) is the p-th time
+ *   derivative of the modes, modulated. */
 #define RIFT_RESP_ROTATION 1
 #define RIFT_RESP_ARMS 2
+#define RIFT_RESP_ROTATION_DELAY 3
 typedef struct {
   int32_t n_det;            /* K, 1..RIFT_ILE_MAX_DET */
   int32_t n_modes;          /* M, 1..RIFT_ILE_MAX_MODES */
   int32_t n_t;              /* samples per series, 4 .. RIFT_ILE_MAX_NT */
   const int32_t *lm;        /* HOST [M][2] (l, m) as in rift_ile_point */
   double t0, dt;            /* Q grid t_j = t0 + j dt (s) */
-  int32_t response;         /* RIFT_RESP_ROTATION or RIFT_RESP_ARMS */
-  int32_t n_terms;          /* composite terms per detector (5, or p_max + 1 <= 8) */
+  int32_t response;         /* RIFT_RESP_ROTATION, RIFT_RESP_ARMS or RIFT_RESP_ROTATION_DELAY */
+  int32_t n_terms;          /* composite terms per detector (5; p_max + 1 <= 8; 5 or 12) */
   const double *Q;          /* DEVICE [K][n_terms][M][n_t] complex: Q_{k,(a,lm)}(t_j) */
   const double *U;          /* DEVICE [K][n_terms M][n_terms M] complex, index a M + i; Hermitian */
   const double *V;          /* DEVICE, same layout; symmetric */
@@ -260,7 +271,7 @@ typedef struct {
   const double *det_pos;    /* HOST [K][3] light-seconds */
   const double *det_arms;   /* HOST [K][2][3] arm unit vectors x, y (RIFT_RESP_ARMS), else unused */
   double gmst_rad;          /* sidereal angle at t = 0 (rad) */
-  double omega;             /* sidereal rate (rad/s), RIFT_RESP_ROTATION; |omega| |det_pos[k]| <= 1
+  double omega;             /* sidereal rate (rad/s), the rotation responses; |omega| |det_pos[k]| <= 1
                                for every detector (the turn over the light-travel time, at most
                                one radian: 1e4 times the Earth's), else RIFT_EINVAL */
   double d_ref;

@@ -45,7 +45,7 @@
 namespace rift {
 namespace {
 
-constexpr int WIDE_MAX_TERMS = 8;  // composite terms per detector
+constexpr int WIDE_MAX_TERMS = 12;  // composite terms per detector
 constexpr int WIDE_BLOCK = 256;
 
 struct WideDesc {
@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(WIDE_BLOCK, MC <= 5 ? 3 : 2) k_wide(WideDesc D
   const double ra = th[0], dec = th[n], psi = th[2 * n], incl = th[3 * n], phi = th[4 * n];
   const double tref = th[5 * n], dist = th[6 * n];
   const int K = D.K, M = D.M, n_t = D.n_t, n_a = D.n_a;
-  const bool rot = D.response == RIFT_RESP_ROTATION;
+  const bool rot = D.response == RIFT_RESP_ROTATION || D.response == RIFT_RESP_ROTATION_DELAY;
+  const bool drift = D.response == RIFT_RESP_ROTATION_DELAY && n_a > 5;
 
   // sky frame at t_ref (the rotation response advances the sidereal angle)
   const double gm = rot ? D.gmst + D.omega * tref : D.gmst;
@@ -318,6 +319,33 @@ __global__ void __launch_bounds__(WIDE_BLOCK, MC <= 5 ? 3 : 2) k_wide(WideDesc D
         const double ei = (nn == 0) ? 0.0 : (nn == 1) ? e1s : (nn == -1) ? -e1s : (nn == 2) ? e2s : -e2s;
         cre[a][t] = ar * er - ai * ei;
         cim[a][t] = ar * ei + ai * er;
+      }
+      if (drift) {
+        // first order in the delay drift (Path B, p = 1).  The drift's
+        // harmonics in the modulation phase, -dt: m = -1, 0, +1 from
+        // rho e^{i g(t_ref)}, rho = r_x + i r_y.  With the post-phases
+        // folded in, C~_(1, n) = sum_m C~_(0, n - m) D_m e^{i m Omega (t_k - t_ref)}
+        // for n = -3 .. 3, the order-0 terms read back from this lane's column
+        const double rer = D.rpos[k][0] * cg - D.rpos[k][1] * sg, rei = D.rpos[k][0] * sg + D.rpos[k][1] * cg;
+        // D_m e^{i m Omega (t_k - t_ref)}, m = -1, 0, +1
+        const double hr = 0.5 * cd * rer, hi = 0.5 * cd * rei;
+        const double dmr[3] = {hr * cdl - hi * sdl, -cd * rer, hr * cdl - hi * sdl};
+        const double dmi[3] = {hr * (-sdl) - hi * cdl, 0.0, hr * sdl + hi * cdl};
+#pragma unroll
+        for (int b = 0; b < 7; ++b) {
+          const int nn = b - 3;
+          double cr = 0.0, ci = 0.0;
+#pragma unroll
+          for (int m = -1; m <= 1; ++m) {
+            const int q = nn - m;
+            if (q < -2 || q > 2) continue;
+            const double xr = cre[q + 2][t], xi = cim[q + 2][t];
+            cr += xr * dmr[m + 1] - xi * dmi[m + 1];
+            ci += xr * dmi[m + 1] + xi * dmr[m + 1];
+          }
+          cre[5 + b][t] = cr;
+          cim[5 + b][t] = ci;
+        }
       }
     } else {
       const double* ax = D.arms[k][0];
@@ -453,6 +481,9 @@ int validate_wide(const rift_ile_point_wide* pt) {
   if (pt->response == RIFT_RESP_ROTATION) {
     if (pt->n_terms != 5) return RIFT_EINVAL;
     if (!std::isfinite(pt->omega)) return RIFT_EINVAL;
+  } else if (pt->response == RIFT_RESP_ROTATION_DELAY) {
+    if (pt->n_terms != 5 && pt->n_terms != 12) return RIFT_EINVAL;
+    if (!std::isfinite(pt->omega)) return RIFT_EINVAL;
   } else if (pt->response == RIFT_RESP_ARMS) {
     if (pt->n_terms < 1 || pt->n_terms > WIDE_MAX_TERMS || !pt->det_arms) return RIFT_EINVAL;
     for (int a = 0; a < 6 * pt->n_det; ++a)
@@ -476,7 +507,7 @@ int validate_wide(const rift_ile_point_wide* pt) {
     if (!std::isfinite(pt->det_pos[a])) return RIFT_EINVAL;
   // rotation: the turn over the light-travel time, Omega |r_k|, stays within
   // one radian (the post-phase is evaluated by a series on that range)
-  if (pt->response == RIFT_RESP_ROTATION)
+  if (pt->response == RIFT_RESP_ROTATION || pt->response == RIFT_RESP_ROTATION_DELAY)
     for (int k = 0; k < pt->n_det; ++k) {
       const double* r = pt->det_pos + 3 * k;
       if (!(fabs(pt->omega) * sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) <= 1.0)) return RIFT_EINVAL;
@@ -509,7 +540,7 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
   D.t0 = pt->t0;
   D.inv_dt = 1.0 / pt->dt;
   D.gmst = pt->gmst_rad;
-  D.omega = pt->response == RIFT_RESP_ROTATION ? pt->omega : 0.0;
+  D.omega = (pt->response == RIFT_RESP_ROTATION || pt->response == RIFT_RESP_ROTATION_DELAY) ? pt->omega : 0.0;
   D.d_ref = pt->d_ref;
   for (int k = 0; k < pt->n_det; ++k) {
     const double* d = pt->det_tensor + 9 * k;

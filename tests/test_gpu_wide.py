@@ -4,7 +4,8 @@ against the FP64 oracle, Eq. (slowrot:lnL:Decomposed).
 Bars (written here): lnL |dlnL_i| <= 1e-9 S_i with S_i = |x data_i| +
 |x^2 quad_i| from the oracle's exact quadratic dependence on x (the FP64 bar);
 ln Z to 1e-9 max(1, |ln Z|), n_eff to 1e-9 relative.  The regression limit
-(zero rotation, zeroth arm order) is checked against the static HIP path.
+(zero rotation, zeroth arm order) is checked against the static HIP path,
+and the rotation-with-delay response truncated at order 0 against rotation.
 """
 import math
 
@@ -46,6 +47,9 @@ CASES = [
     ("rotation", 3, 9, 5, 3000, 32768.0, 100.0, 40.0, 2, 1500),      # magnified rotation rate
     ("rotation", 5, 21, 5, 2000, 32768.0, 1000.0, synth.SIDEREAL_RATE, 3, 700),  # width 105
     ("rotation", 1, 2, 5, 64, 4096.0, 30.0, synth.SIDEREAL_RATE, 4, 777),  # tiny window
+    ("rotation_delay", 3, 4, 12, 6554, 32768.0, 600.0, synth.SIDEREAL_RATE, 8, 2000),
+    ("rotation_delay", 2, 8, 12, 3000, 32768.0, 100.0, 40.0, 9, 1200),  # magnified rate, width 96
+    ("rotation_delay", 4, 2, 5, 500, 4096.0, 80.0, 40.0, 10, 900),  # the drift left out
     ("arms", 3, 4, 4, 6554, 32768.0, 600.0, 0.0, 5, 2500),
     ("arms", 2, 16, 8, 1000, 32768.0, 200.0, 0.0, 6, 600),
     ("arms", 8, 2, 3, 400, 4096.0, 50.0, 0.0, 7, 1000),
@@ -75,6 +79,17 @@ def test_wide_lnL_and_lnZ_match_oracle(ile, oracle_mod, case):
     assert abs(z.item() - z_or) <= 1e-9 * max(1.0, abs(z_or))
     assert abs(ne.item() - ne_or) <= 1e-9 * ne_or
     assert np.array_equal(ll.cpu().numpy(), got)
+
+
+def test_rotation_delay_without_drift_is_rotation(ile):
+    """The rotation-with-delay response truncated at the drift's order 0 is
+    the rotation response (HIP against HIP)."""
+    pt = synth.make_point_wide(3, 4, 5, 2000, 32768.0, 200.0, 21, response="rotation", omega=40.0)
+    th = synth.prior_samples(1500, 22)
+    want = ile.wide_lnL(pt, th).cpu().numpy()
+    pt["response"] = "rotation_delay"
+    got = ile.wide_lnL(pt, th).cpu().numpy()
+    assert np.array_equal(got, want)
 
 
 def test_wide_reduces_to_the_static_path(ile):

@@ -10,8 +10,8 @@ mathematics fix, not against the oracle itself:
   time t, with the modulation of the bank referenced to the template's own
   time (Eqs. (slowrot:master), (slowrot:commutator), (slowrot:postphase));
 * the delay-drift coefficients (Path B): the composite template of order P
-  equals the order-P Taylor series of the strain with the drifting delay,
-  exactly, and order 0 is Path A;
+  equals the order-P Taylor series of the strain with the drifting delay (to
+  the rounding of its terms), and order 0 is Path A;
 * the finite-arm coefficients: sum_p b_p W_p reproduces the Michelson response
   built from the arm transfer function, with W_p the Taylor coefficients of
   the residual transfer in u = a.n (Eqs. (slowrot:armtransfer), (fsize:FA),
@@ -86,7 +86,7 @@ def test_delay_drift_template(oracle_mod, omega):
     Eq. (slowrot:master)).  For a pure tone h(t) = e^{i w t}, whose p-th
     derivative is (i w)^p h, the composite template placed at t_k,
       sum_{p <= P, n} C~_(p,n) e^{i n W (t - t_k)} (i w)^p e^{i w (t - t_k)},
-    equals F_k(t) e^{i w (t - t_k)} sum_{p <= P} (-i w dt(t))^p / p! exactly,
+    equals F_k(t) e^{i w (t - t_k)} sum_{p <= P} (-i w dt(t))^p / p!,
     with F_k(t) the antenna factor at the sidereal angle of time t and dt(t)
     the drift of the arrival-time delay since t_ref (the sky frame at each
     t): the order-P Taylor series of the strain F_k(t) h(t - t_k - dt(t)).
