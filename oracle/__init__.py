@@ -16,8 +16,10 @@ joint marginal over phiref and psi by exact reconstruction, Eqs.
 polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)), ``hmc_step``
 (a Metropolis-adjusted Hamiltonian transition on the gradient, optionally
 on the tempered target) and the SMC ladder's ``smc_cess``, ``smc_next_beta``,
-``smc_update`` and ``systematic_resample`` (Eq. (sampler-menu:smc-update))
-are written here in numpy on top of the C likelihood.
+``smc_update`` and ``systematic_resample`` (Eq. (sampler-menu:smc-update)),
+and the importance-sampling normalisation with a defensive Gaussian-mixture
+proposal (``cloud_moments``, ``mixture_is``, Eq. (sampler-menu:is)) are
+written here in numpy on top of the C likelihood.
 
 Every function states the passage of the paper it follows.  Parity status of
 each function (what pins it) is listed in the tests' docstrings.
@@ -918,6 +920,162 @@ def systematic_resample(lnW, u):
     U = (np.arange(n) + u) / n
     a = np.searchsorted(C, U, side="right")
     return np.minimum(a, n - 1)
+
+
+# ---------------------------------------------------------------------------
+# The importance-sampling normalisation of Eq. (sampler-menu:is) with the
+# defensive proposal of Sec. "Mode coverage, adaptive clouds, and evidence":
+# q = alpha p + (1 - alpha) sum_m a_m N(mu_m, s C_m), one Gaussian component
+# per recovered mode, fitted by the moments of that mode's chains or cloud,
+# with s > 1 widening its tails.  Coordinates are the samplers' (ra, dec, psi,
+# cos incl, phiref, tref, ln D); ra, psi and phiref are periodic, so a
+# component is the density of its Gaussian draw taken modulo those periods.
+
+IS_PERIODS = ((0, 2.0 * np.pi), (2, np.pi), (4, 2.0 * np.pi))
+
+
+def is_log_prior(c, t_min, t_max, d_min, d_max):
+    """ln p of the samples' prior, normalised, in the sampler coordinates on
+    the box ra, phiref in [0, 2 pi), psi in [0, pi), |dec| < pi/2,
+    |cos incl| <= 1, tref in [t_min, t_max], D in [d_min, d_max]: the product
+    of the one-dimensional densities 1/(2 pi), cos(dec)/2, 1/pi, 1/2,
+    1/(2 pi), 1/(t_max - t_min) and 3 D^3 / (d_max^3 - d_min^3) (p(D) ~ D^2
+    and dD = D d ln D); -inf outside the box."""
+    c = np.asarray(c, np.float64)
+    inside = (c[0] >= 0.0) & (c[0] < 2 * np.pi) & (np.abs(c[1]) < np.pi / 2) & (c[2] >= 0.0) & (c[2] < np.pi) & \
+        (np.abs(c[3]) <= 1.0) & (c[4] >= 0.0) & (c[4] < 2 * np.pi) & (c[5] >= t_min) & (c[5] <= t_max) & \
+        (c[6] >= np.log(d_min)) & (c[6] <= np.log(d_max))
+    const = -2.0 * np.log(2 * np.pi) - 2.0 * np.log(2.0) - np.log(np.pi) - np.log(t_max - t_min) + np.log(3.0) - \
+        np.log(d_max ** 3 - d_min ** 3)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        v = const + np.log(np.cos(c[1])) + 3.0 * c[6]
+    return np.where(inside, v, -np.inf)
+
+
+def cloud_moments(c, lnw=None):
+    """Weighted mean and covariance of a cloud (the moments that fit one
+    component): with normalised weights W_i (equal without lnw),
+    mu = sum_i W_i c_i and C = sum_i W_i (c_i - mu)(c_i - mu)^T, over the
+    samples of non-zero weight.  NaN when no sample has weight or a weight is
+    NaN."""
+    c = np.asarray(c, np.float64)
+    n = c.shape[1]
+    if n == 0:
+        return np.full(7, np.nan), np.full((7, 7), np.nan)
+    if lnw is None:
+        W = np.full(n, 1.0 / n)
+    else:
+        lw = np.asarray(lnw, np.float64)
+        t = _lse(lw)
+        if not np.isfinite(t):
+            return np.full(7, np.nan), np.full((7, 7), np.nan)
+        W = np.exp(lw - t)
+    keep = W > 0
+    mu = np.sum(W[keep] * c[:, keep], axis=1)
+    d = c[:, keep] - mu[:, None]
+    return mu, (W[keep] * d) @ d.T
+
+
+def wrapped_normal_logpdf(c, mu, cov, images=6):
+    """ln of the density, at the columns of c, of x ~ N(mu, cov) with ra, psi
+    and phiref taken modulo their periods: the sum of the Gaussian density
+    over the lattice of periodic images of each point, here the images within
+    `images` periods of the one nearest the mean in each periodic row."""
+    c = np.asarray(c, np.float64)
+    cov = np.asarray(cov, np.float64)
+    Cinv = np.linalg.inv(cov)
+    _, logdet = np.linalg.slogdet(cov)
+    d = c - np.asarray(mu, np.float64)[:, None]
+    for j, P in IS_PERIODS:
+        d[j] -= P * np.round(d[j] / P)
+    ks = np.arange(-images, images + 1, dtype=np.float64)
+    k0, k2, k4 = np.meshgrid(ks, ks, ks, indexing="ij")
+    off = np.zeros((k0.size, 7))
+    off[:, 0] = k0.ravel() * IS_PERIODS[0][1]
+    off[:, 2] = k2.ravel() * IS_PERIODS[1][1]
+    off[:, 4] = k4.ravel() * IS_PERIODS[2][1]
+    out = np.empty(d.shape[1])
+    for s0 in range(0, d.shape[1], 128):
+        e = d[None, :, s0:s0 + 128] + off[:, :, None]       # [image, 7, chunk]
+        q = -0.5 * np.sum(e * np.matmul(Cinv, e), axis=1)   # [image, chunk]
+        m = np.max(q, axis=0)
+        out[s0:s0 + 128] = m + np.log(np.sum(np.exp(q - m), axis=0))
+    return out - 0.5 * logdet - 3.5 * np.log(2 * np.pi)
+
+
+def mixture_log_density(c, alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max):
+    """ln q of the defensive mixture q = alpha p + (1 - alpha) sum_m a_m
+    N_m, N_m the wrapped Gaussian of mean mean[m] and covariance
+    scale cov[m]."""
+    c = np.asarray(c, np.float64)
+    parts = []
+    if alpha > 0:
+        parts.append(np.log(alpha) + is_log_prior(c, t_min, t_max, d_min, d_max))
+    for m in range(len(a)):
+        if a[m] > 0 and alpha < 1:
+            parts.append(np.log((1.0 - alpha) * a[m]) + wrapped_normal_logpdf(c, mean[m], scale * np.asarray(cov[m])))
+    P = np.array(parts)
+    mx = np.max(P, axis=0)
+    with np.errstate(invalid="ignore"):
+        out = mx + np.log(np.sum(np.exp(P - mx), axis=0))
+    return np.where(np.isneginf(mx), -np.inf, out)
+
+
+def mixture_draw(alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, z, v, u):
+    """Independent draws from q with the caller's random numbers: u [n] in
+    [0, 1) picks the prior when u < alpha, else component m, the first with
+    u < alpha + (1 - alpha) (a_0 + .. + a_m) (the last one if none); a prior
+    draw takes the inverse distribution functions of v [7, n] (ra = 2 pi v0,
+    dec = asin(2 v1 - 1), psi = pi v2, cos incl = 2 v3 - 1, phiref = 2 pi v4,
+    tref = t_min + (t_max - t_min) v5, ln D = ln(d_min^3 + v6 (d_max^3 -
+    d_min^3)) / 3); a component draw is mean[m] + L z with L L^T = scale
+    cov[m] (Cholesky), z [7, n] standard normals, then ra, psi, phiref
+    reduced into [0, P).  Returns (c [7, n], comp [n]: -1 for the prior)."""
+    z = np.asarray(z, np.float64)
+    v = np.asarray(v, np.float64)
+    u = np.asarray(u, np.float64)
+    n = u.size
+    c = np.empty((7, n))
+    comp = np.full(n, -1, np.int64)
+    ncomp = len(a)
+    cum = np.cumsum(np.asarray(a, np.float64))
+    T = alpha + (1.0 - alpha) * cum
+    for i in range(n):
+        if u[i] < alpha or ncomp == 0:
+            w = v[:, i]
+            c[:, i] = (2 * np.pi * w[0], np.arcsin(2 * w[1] - 1), np.pi * w[2], 2 * w[3] - 1, 2 * np.pi * w[4],
+                       t_min + (t_max - t_min) * w[5], np.log(d_min ** 3 + w[6] * (d_max ** 3 - d_min ** 3)) / 3.0)
+            continue
+        m = int(np.argmax(u[i] < T)) if np.any(u[i] < T) else ncomp - 1
+        L = np.linalg.cholesky(scale * np.asarray(cov[m], np.float64))
+        x = np.asarray(mean[m], np.float64) + L @ z[:, i]
+        for j, P in IS_PERIODS:
+            x[j] -= P * np.floor(x[j] / P)
+        c[:, i] = x
+        comp[i] = m
+    return c, comp
+
+
+def mixture_is(alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, z, v, u):
+    """Draws from the defensive mixture and their log weights ln p - ln q of
+    Eq. (sampler-menu:is), so that ln Z = lnZ(lnL(theta), lnw).  Returns
+    (theta [7, n] in the likelihood's coordinates, lnw [n], comp [n]).  A draw
+    outside the prior's box has lnw = -inf and is returned moved onto the box
+    (dec, cos incl, tref and ln D clamped), so its likelihood is finite."""
+    box = (t_min, t_max, d_min, d_max)
+    c, comp = mixture_draw(alpha, a, mean, cov, scale, *box, z, v, u)
+    lp = is_log_prior(c, *box)
+    lq = mixture_log_density(c, alpha, a, mean, cov, scale, *box)
+    lnw = np.where(np.isfinite(lp), lp - lq, -np.inf)
+    cc = c.copy()
+    cc[1] = np.clip(cc[1], -np.pi / 2, np.pi / 2)
+    cc[3] = np.clip(cc[3], -1.0, 1.0)
+    cc[5] = np.clip(cc[5], t_min, t_max)
+    cc[6] = np.clip(cc[6], np.log(d_min), np.log(d_max))
+    th = cc.copy()
+    th[3] = np.arccos(cc[3])
+    th[6] = np.exp(cc[6])
+    return th, lnw, comp
 
 
 def rotation_harmonics(det_tensor, dec, psi):
