@@ -565,6 +565,70 @@ int rift_ile_smc_reweight(int64_t n, const double *lnL, double *lnW, double beta
 int rift_ile_smc_resample(int64_t n, const double *lnW, double u, const double *theta_in, double *theta_out,
                           int64_t *ancestors, void *stream);
 
+/* Weighted mean and covariance of a cloud of states (the moments that fit one
+ * component of the proposal below; Sec. "Mode coverage, adaptive clouds, and
+ * evidence"): with W_i the weights e^{lnw_i} normalised over the cloud (equal
+ * when lnw is NULL), mean = sum_i W_i c_i and cov = sum_i W_i (c_i - mean)
+ * (c_i - mean)^T, the population form, over the samples of non-zero weight
+ * (a sample with lnw = -inf is not read).  c: DEVICE [7][n] in any
+ * coordinates (no periodic reduction: pass chain states unwrapped); lnw:
+ * DEVICE [n] or NULL; mean: DEVICE [7], cov: DEVICE [7][7] (symmetric)
+ * outputs, NaN when no sample has weight (n = 0 included) or a weight is NaN.
+ * RIFT_EINVAL: n < 0, null or misaligned pointers.  Enqueues and returns;
+ * deterministic; stream-ordered scratch of about 300 bytes per 256 samples
+ * (at most 300 KB). */
+int rift_ile_moments(int64_t n, const double *c, const double *lnw, double *mean, double *cov, void *stream);
+
+/* Independent draws from a defensive Gaussian-mixture proposal and their
+ * importance weights, Eq. (sampler-menu:is): q = alpha p + (1 - alpha)
+ * sum_m a_m N_m, with p the samples' prior and N_m the Gaussian of mean
+ * mean[m] and covariance scale cov[m] (one component per recovered mode,
+ * Sec. "Mode coverage, adaptive clouds, and evidence"), in the sampler
+ * coordinates (ra, dec, psi, cos incl, phiref, tref, ln D).
+ * The prior is the isotropic, uniform-in-volume one, normalised on the box
+ * ra, phiref in [0, 2 pi), psi in [0, pi), |dec| < pi/2, |cos incl| <= 1,
+ * tref in [t_min, t_max], D in [d_min, d_max]: ln p = ln cos dec + 3 ln D +
+ * const.  ra, psi and phiref are periodic, so N_m is the density of its
+ * Gaussian draw taken modulo the periods (the sum over periodic images,
+ * truncated where the images left out carry under 2e-19 of the mass per row).
+ * Per draw i: u[i] < alpha draws from the prior by its inverse distribution
+ * functions of v[:, i] (ra = 2 pi v0, dec = asin(2 v1 - 1), psi = pi v2,
+ * cos incl = 2 v3 - 1, phiref = 2 pi v4, tref = t_min + (t_max - t_min) v5,
+ * ln D = ln(d_min^3 + v6 (d_max^3 - d_min^3)) / 3); otherwise component m,
+ * the first with u[i] < alpha + (1 - alpha)(a_0 + .. + a_m), draws
+ * mean[m] + L z[:, i] with L L^T = scale cov[m] (Cholesky), reduced into the
+ * box's periods.  lnw[i] = ln p - ln q with q's full density (every
+ * component), so that rift_ile_lnZ(theta, lnw) is ln Z_IS = ln (1/N) sum_i
+ * L_i p_i / q_i.  A draw outside the box has lnw = -inf and is returned
+ * clamped onto it (dec, cos incl, tref, ln D), so its likelihood is finite.
+ * theta: DEVICE [7][n] output in the likelihood's coordinates (incl = acos,
+ * dist = exp); lnw: DEVICE [n] output; comp: DEVICE int32 [n] or NULL (-1
+ * for the prior, else m); z: DEVICE [7][n] standard normals; v: DEVICE
+ * [7][n] and u: DEVICE [n] uniforms in [0, 1); status: DEVICE int32 [1] or
+ * NULL, set to 0, or to 1 + m for the first refused component.
+ * mix->a: HOST [n_comp], each > 0, summing to 1 within 1e-12; mean: DEVICE
+ * [n_comp][7]; cov: DEVICE [n_comp][7][7] symmetric (the lower triangle is
+ * read).  A component is refused on the device when scale cov[m] is not
+ * positive definite or a mean is not finite, or when its marginal width in a
+ * periodic row exceeds half the period (|sigma| <= pi for ra and phiref,
+ * pi/2 for psi): every lnw and theta is then NaN.  RIFT_EINVAL: n < 0;
+ * n_comp outside [0, RIFT_IS_MAX_COMP]; alpha outside [0, 1] (alpha = 1 when
+ * n_comp = 0); scale not finite and > 0; an empty box or d_min <= 0; a bad
+ * a; null or misaligned pointers.  Enqueues and returns; stream-ordered
+ * scratch of 768 bytes per component. */
+#define RIFT_IS_MAX_COMP 32
+typedef struct {
+  int32_t n_comp;     /* components, 0 .. RIFT_IS_MAX_COMP */
+  double alpha;       /* the prior's share, 0 <= alpha <= 1 */
+  double scale;       /* s > 0, the covariance widening */
+  const double *a;    /* HOST [n_comp] component weights */
+  const double *mean; /* DEVICE [n_comp][7] */
+  const double *cov;  /* DEVICE [n_comp][7][7] */
+} rift_ile_mixture;
+int rift_ile_mixture_is(int64_t n, const rift_ile_mixture *mix, const rift_ile_hmc_prior *prior, const double *z,
+                        const double *v, const double *u, double *theta, double *lnw, int32_t *comp,
+                        int32_t *status, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): rift_ile_lnZ with

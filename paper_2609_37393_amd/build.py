@@ -45,7 +45,8 @@ def _objects():
     objs = [(os.path.join(CSRC, "rift_ile.hip"), os.path.join(OBJDIR, "rift_ile.o"), []),
             (os.path.join(CSRC, "wide.hip"), os.path.join(OBJDIR, "wide.o"), []),
             (os.path.join(CSRC, "sampler.hip"), os.path.join(OBJDIR, "sampler.o"), []),
-            (os.path.join(CSRC, "pregrid.hip"), os.path.join(OBJDIR, "pregrid.o"), [])]
+            (os.path.join(CSRC, "pregrid.hip"), os.path.join(OBJDIR, "pregrid.o"), []),
+            (os.path.join(CSRC, "importance.hip"), os.path.join(OBJDIR, "importance.o"), [])]
     for kt in KT_CLASSES:
         for kind in KINDS:
             objs.append((os.path.join(CSRC, "inst.hip"), os.path.join(OBJDIR, f"inst_kt{kt}_k{kind}.o"),

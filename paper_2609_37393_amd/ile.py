@@ -68,6 +68,8 @@ EXPORTS = (
     "rift_ile_plan_hmc",
     "rift_ile_plan_lnZ_tband",
     "rift_ile_plan_lnZ_erai",
+    "rift_ile_moments",
+    "rift_ile_mixture_is",
     "rift_ile_plan_hmc_tempered",
     "rift_ile_smc_reweight",
     "rift_ile_smc_resample",
@@ -146,6 +148,11 @@ class CHmcPrior(ctypes.Structure):
                 ("d_max", ctypes.c_double)]
 
 
+class CMixture(ctypes.Structure):
+    _fields_ = [("n_comp", ctypes.c_int32), ("alpha", ctypes.c_double), ("scale", ctypes.c_double),
+                ("a", ctypes.c_void_p), ("mean", ctypes.c_void_p), ("cov", ctypes.c_void_p)]
+
+
 class CConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile_blocks", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("sort", ctypes.c_int32)]
@@ -198,6 +205,9 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(CHmcPrior), ctypes.c_double, vp, vp, vp]
     lib.rift_ile_smc_reweight.argtypes = [i64, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
     lib.rift_ile_smc_resample.argtypes = [i64, vp, ctypes.c_double, vp, vp, vp, vp]
+    lib.rift_ile_moments.argtypes = [i64, vp, vp, vp, vp, vp]
+    lib.rift_ile_mixture_is.argtypes = [i64, ctypes.POINTER(CMixture), ctypes.POINTER(CHmcPrior), vp, vp, vp, vp,
+                                        vp, vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
     lib.rift_ile_strerror.restype = ctypes.c_char_p
     lib.rift_ile_version.restype = ctypes.c_int
@@ -375,6 +385,44 @@ def smc_resample(lnW, u, theta_in=None, theta_out=None, ancestors=None):
                                      None if ancestors is None else ancestors.data_ptr(), _stream(lnW.device)),
            "rift_ile_smc_resample")
     return ancestors
+
+
+def moments(c, lnw=None):
+    """Weighted mean [7] and covariance [7, 7] of a cloud c [7, n] on the
+    device (rift_ile_moments); lnw [n] log weights or None (equal)."""
+    lib = load()
+    dev = c.device
+    mean = torch.empty(7, dtype=torch.float64, device=dev)
+    cov = torch.empty((7, 7), dtype=torch.float64, device=dev)
+    n = c.shape[1]
+    _check(lib.rift_ile_moments(n, c.data_ptr() if n else None, None if lnw is None else lnw.data_ptr(),
+                                mean.data_ptr(), cov.data_ptr(), _stream(dev)), "rift_ile_moments")
+    return mean, cov
+
+
+def mixture_is(alpha, a, mean, cov, scale, box, z, v, u, theta=None, lnw=None, comp=None, status=None):
+    """Draws from the defensive mixture alpha p + (1 - alpha) sum_m a_m
+    N(mean[m], scale cov[m]) and their log weights ln p - ln q
+    (rift_ile_mixture_is).  a: host sequence; mean [n_comp, 7], cov
+    [n_comp, 7, 7], z, v [7, n], u [n]: device tensors; box = (t_min, t_max,
+    d_min, d_max).  Returns (theta [7, n], lnw [n], comp [n] int32, status [1]
+    int32)."""
+    lib = load()
+    dev = u.device
+    n = u.numel()
+    a_h = np.ascontiguousarray(np.asarray(a, np.float64))
+    nc = a_h.size
+    theta = theta if theta is not None else torch.empty((7, n), dtype=torch.float64, device=dev)
+    lnw = lnw if lnw is not None else torch.empty(n, dtype=torch.float64, device=dev)
+    comp = comp if comp is not None else torch.empty(n, dtype=torch.int32, device=dev)
+    status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
+    mix = CMixture(nc, float(alpha), float(scale), a_h.ctypes.data if nc else None,
+                   mean.data_ptr() if nc else None, cov.data_ptr() if nc else None)
+    pr = CHmcPrior(*[float(x) for x in box])
+    ptr = (lambda t: t.data_ptr() if n else None)
+    _check(lib.rift_ile_mixture_is(n, ctypes.byref(mix), ctypes.byref(pr), ptr(z), ptr(v), ptr(u), ptr(theta),
+                                   ptr(lnw), ptr(comp), status.data_ptr(), _stream(dev)), "rift_ile_mixture_is")
+    return theta, lnw, comp, status
 
 
 def pregrid(q, r: int, out=None, device="cuda") -> torch.Tensor:
