@@ -208,17 +208,19 @@ __global__ void __launch_bounds__(MOM_BLOCK) k_mom_final(int nb, const double* _
 // Mixture draws and weights
 // ---------------------------------------------------------------------------
 
-// One component's table (96 doubles).  L and its inverse Li are lower
+// One component's table (98 doubles).  L and its inverse Li are lower
 // triangular, packed by rows (row r starts at r (r + 1) / 2).
 struct IsComp {
   double mu[7];     // the mean as given (the draws)
   double mur[7];    // the mean with ra, psi, phiref reduced into [0, P) (the density)
   double L[28];     // Cholesky factor of s C_m
   double Li[28];    // L^-1
-  double g[3][7];   // P_j times column j of L^-1, j = 0, 2, 4 (one image step)
+  double g[3][7];   // P_j times column j of L^-1 for the periodic rows (one image step), the row
+                    // with the most images last
   double lognorm;   // ln((1 - alpha) a_m) - sum_j ln L_jj - 3.5 ln(2 pi)
   double thr;       // alpha + (1 - alpha) (a_0 + .. + a_m)
-  double K[3];      // image half-counts in rows 0, 2, 4
+  double K[3];      // image half-counts in the order of g
+  double gg, egg;   // |g[2]|^2 and e^{-|g[2]|^2}
 };
 
 struct IsArgs {
@@ -274,15 +276,31 @@ __global__ void k_is_setup(IsArgs A, const double* __restrict__ mean, const doub
       }
     double ldet = 0.0;
     for (int r = 0; r < 7; ++r) ldet += log(T.L[tri(r) + r]);
+    double K[3];
     for (int p = 0; p < 3; ++p) {
       const int j = PER_ROW[p];
       const double P = period(p);
       T.mur[j] = T.mu[j] - P * floor(T.mu[j] / P);
       const double sig = sqrt(S[j][j]);
       ok = ok && sig <= 0.5 * P && T.mu[j] == T.mu[j] && fabs(T.mu[j]) < 1e15;
-      T.K[p] = ok ? fmax(0.0, ceil(9.0 * sig / P - 0.5)) : 0.0;
-      for (int r = 0; r < 7; ++r) T.g[p][r] = r >= j ? P * T.Li[tri(r) + j] : 0.0;
+      K[p] = ok ? fmax(0.0, ceil(9.0 * sig / P - 0.5)) : 0.0;
     }
+    // the row with the most images innermost (summed by a recurrence)
+    int inner = 2;
+    if (K[0] > K[inner]) inner = 0;
+    if (K[1] > K[inner]) inner = 1;
+    int order[3] = {0, 1, 2};
+    order[inner] = 2;
+    order[2] = inner;
+    for (int q = 0; q < 3; ++q) {
+      const int p = order[q], j = PER_ROW[p];
+      const double P = period(p);
+      T.K[q] = K[p];
+      for (int r = 0; r < 7; ++r) T.g[q][r] = r >= j ? P * T.Li[tri(r) + j] : 0.0;
+    }
+    T.gg = 0.0;
+    for (int r = 0; r < 7; ++r) T.gg += T.g[2][r] * T.g[2][r];
+    T.egg = exp(-T.gg);
     for (int j = 0; j < 7; ++j) ok = ok && T.mu[j] == T.mu[j] && fabs(T.mu[j]) < __builtin_inf();
     T.lognorm = log((1.0 - A.alpha) * A.a[m]) - ldet - 3.5 * log(TWO_PI);
     double cum = 0.0;
@@ -395,18 +413,43 @@ __global__ void __launch_bounds__(IS_BLOCK) k_is_draw(int64_t n, IsArgs A, const
           for (int q = 0; q <= r; ++q) x += T.Li[tri(r) + q] * d[q];
           y0[r] = x;
         }
-        const int K0 = (int)T.K[0], K2 = (int)T.K[1], K4 = (int)T.K[2];
-        for (int k0 = -K0; k0 <= K0; ++k0)
-          for (int k2 = -K2; k2 <= K2; ++k2)
-            for (int k4 = -K4; k4 <= K4; ++k4) {
-              double q2 = 0.0;
+        // the images: outer rows by loops; along the inner row the quadratic
+        // form is Q(k) = C + 2 B k + A k^2, summed from its smallest term
+        // outwards by the ratio e^{-(Q(k+-1) - Q(k))/2}, itself multiplied by
+        // e^{-A} per step (two exponentials and a logarithm per line)
+        const int Ka = (int)T.K[0], Kb = (int)T.K[1], Kc = (int)T.K[2];
+        const double A = T.gg;
+        for (int ka = -Ka; ka <= Ka; ++ka)
+          for (int kb = -Kb; kb <= Kb; ++kb) {
+            double C = 0.0, B = 0.0;
 #pragma unroll
-              for (int r = 0; r < 7; ++r) {
-                const double y = y0[r] + k0 * T.g[0][r] + k2 * T.g[1][r] + k4 * T.g[2][r];
-                q2 += y * y;
-              }
-              lse_push(mx, s, T.lognorm - 0.5 * q2);
+            for (int r = 0; r < 7; ++r) {
+              const double b = y0[r] + ka * T.g[0][r] + kb * T.g[1][r];
+              C += b * b;
+              B += b * T.g[2][r];
             }
+            if (Kc == 0) {
+              lse_push(mx, s, T.lognorm - 0.5 * C);
+              continue;
+            }
+            const double kc = fmin(fmax(rint(-B / A), (double)-Kc), (double)Kc);
+            const double Qc = C + kc * (2.0 * B + A * kc);
+            double line = 1.0, t = 1.0;
+            double r = exp(-B - A * (kc + 0.5));
+            for (int k = (int)kc + 1; k <= Kc; ++k) {
+              t *= r;
+              line += t;
+              r *= T.egg;
+            }
+            t = 1.0;
+            r = exp(B + A * (kc - 0.5));
+            for (int k = (int)kc - 1; k >= -Kc; --k) {
+              t *= r;
+              line += t;
+              r *= T.egg;
+            }
+            lse_push(mx, s, T.lognorm - 0.5 * Qc + log(line));
+          }
       }
       const double lq = mx == -__builtin_inf() ? mx : mx + log(s);
       out_w = lp - lq;
