@@ -548,19 +548,27 @@ def wide_flops_per_sample(K, M, n_a, response):
     projections and n_a powers)."""
     A = n_a * M
     P = A * (A + 1) // 2
-    coef = (5 * 40 + 200 + 40) if response == "rotation" else (40 + 12 * n_a)
+    if response in ("rotation", "rotation_delay"):
+        # with the delay drift: its three harmonics (~20 flops) and, per
+        # order-p coefficient, one complex product per drift harmonic (8 flops)
+        coef = 5 * 40 + 200 + 40 + (0 if n_a == 5 else 20 + 8 * 3 * 7 + (0 if n_a == 12 else 8 * (9 + 5 * 9)))
+    else:
+        coef = 40 + 12 * n_a
     return 40 + 57 * K + 10 * M + K * coef + 6 * K * A + 20 * K * A + 8 * K * P + P
 
 
 def extra_wide(ile, synth, torch, steps, cpu=True):
     """The generalised response (composite index A = (a, lm)): Earth rotation
-    (5 sidereal terms) at widths 20 and 105, finite arms (p_max = 3) at width
-    16; 3 detectors, Q 6554 samples at 32768 Hz, SNR 600.  Each call is
+    (5 sidereal terms) at widths 20 and 105, rotation with the delay drift to
+    orders 1 and 2 (12 and 21 terms) at 4 modes, finite arms (p_max = 3) at
+    width 16; 3 detectors, Q 6554 samples at 32768 Hz, SNR 600.  Each call is
     timed whole (the description's upload and the synchronisation
     included)."""
     res = {}
     for name, resp, M, n_a, n in (("rotation_w20", "rotation", 4, 5, 1_000_000),
                                   ("rotation_w105", "rotation", 21, 5, 200_000),
+                                  ("rotation_delay_w48", "rotation_delay", 4, 12, 1_000_000),
+                                  ("rotation_delay_w84", "rotation_delay", 4, 21, 200_000),
                                   ("arms_w16", "arms", 4, 4, 1_000_000)):
         pt = synth.make_point_wide(3, M, n_a, 6554, 32768.0, 600.0, 60 + M, response=resp)
         dp = ile.DeviceWidePoint.from_dict(pt)

@@ -244,8 +244,9 @@ int rift_ile_plan_destroy(rift_ile_plan plan);
  *   x, y of each detector and e = e+ + i ex (Eq. (fsize:bp)); static sky frame;
  *   p_max = 0 is the static likelihood (with det_tensor = (x x^T - y y^T)/2).
  * RIFT_RESP_ROTATION_DELAY (Earth rotation with the delay drift, Path B):
- *   n_terms = 5 (order 0, Path A) or 12 (order 1); a <-> (p, n), p = 0: a = n + 2
- *   (n = -2..2), p = 1: a = 5 + n + 3 (n = -3..3); the delay tau = -r_k . N over
+ *   n_terms = 5 (order 0, Path A), 12 (order 1) or 21 (order 2); a <-> (p, n),
+ *   p = 0: a = n + 2 (n = -2..2), p = 1: a = 5 + n + 3 (n = -3..3), p = 2:
+ *   a = 12 + n + 4 (n = -4..4); the delay tau = -r_k . N over
  *   the hour angle carries the harmonics 0, +-1, so the drift -dt since t_ref
  *   has, in the modulation phase, the three terms -cos(dec) Re(rho e^{i g(tref)})
  *   (m = 0) and cos(dec)/2 (rho e^{i g(tref)})^(+-1 conjugated for m = -1),
@@ -263,7 +264,7 @@ typedef struct {
   const int32_t *lm;        /* HOST [M][2] (l, m) as in rift_ile_point */
   double t0, dt;            /* Q grid t_j = t0 + j dt (s) */
   int32_t response;         /* RIFT_RESP_ROTATION, RIFT_RESP_ARMS or RIFT_RESP_ROTATION_DELAY */
-  int32_t n_terms;          /* composite terms per detector (5; p_max + 1 <= 8; 5 or 12) */
+  int32_t n_terms;          /* composite terms per detector (5; p_max + 1 <= 8; 5, 12 or 21) */
   const double *Q;          /* DEVICE [K][n_terms][M][n_t] complex: Q_{k,(a,lm)}(t_j) */
   const double *U;          /* DEVICE [K][n_terms M][n_terms M] complex, index a M + i; Hermitian */
   const double *V;          /* DEVICE, same layout; symmetric */

@@ -45,8 +45,9 @@
 namespace rift {
 namespace {
 
-constexpr int WIDE_MAX_TERMS = 12;  // composite terms per detector
-constexpr int WIDE_BLOCK = 256;
+constexpr int WIDE_ARMS_MAX_TERMS = 8;
+constexpr int WIDE_BLOCK = 256;     // lanes per block up to 12 terms
+constexpr int WIDE_BLOCK_21 = 128;  // up to 21 terms: the coefficient columns in 43 KB of LDS
 
 struct WideDesc {
   int32_t K, M, n_t, n_a, response, npairs;
@@ -197,15 +198,16 @@ __device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
 }
 
 // Occupancy: three wavefronts per SIMD (<= 168 VGPRs) for up to 5 modes, two
-// otherwise (the 25-mode capacity's Y alone holds 100 VGPRs).
-template <int MC>
-__global__ void __launch_bounds__(WIDE_BLOCK, MC <= 5 ? 3 : 2) k_wide(WideDesc D, const double* __restrict__ theta, int64_t n,
-                                                     const double* __restrict__ lnw, double* __restrict__ lnL,
-                                                     double* __restrict__ part) {
-  __shared__ double cre[WIDE_MAX_TERMS][WIDE_BLOCK], cim[WIDE_MAX_TERMS][WIDE_BLOCK];
-  __shared__ MS sh[WIDE_BLOCK / 64];
+// otherwise (the 25-mode capacity's Y alone holds 100 VGPRs).  NT is the
+// capacity of the coefficient columns in LDS (NT x BLK complex values).
+template <int MC, int NT, int BLK>
+__global__ void __launch_bounds__(BLK, MC <= 5 && NT <= 12 ? 3 : 2) k_wide(WideDesc D, const double* __restrict__ theta, int64_t n,
+                                                              const double* __restrict__ lnw,
+                                                              double* __restrict__ lnL, double* __restrict__ part) {
+  __shared__ double cre[NT][BLK], cim[NT][BLK];
+  __shared__ MS sh[BLK / 64];
   const int t = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * WIDE_BLOCK + t;
+  const int64_t i0 = (int64_t)blockIdx.x * BLK + t;
   const bool live = i0 < n;
   const int64_t i = live ? i0 : n - 1;
   const RIFT_GLOBAL double* th = as_global(theta) + i;
@@ -346,6 +348,38 @@ __global__ void __launch_bounds__(WIDE_BLOCK, MC <= 5 ? 3 : 2) k_wide(WideDesc D
           cre[5 + b][t] = cr;
           cim[5 + b][t] = ci;
         }
+        if (NT >= 21 && n_a >= 21) {
+          // order 2: the drift's square, (D~ * D~)_m for m = -2..2, and
+          // C~_(2, n) = 1/2 sum_m C~_(0, n - m) (D~ * D~)_m for n = -4..4
+          double d2r[5], d2i[5];
+#pragma unroll
+          for (int m = 0; m < 5; ++m) {
+            d2r[m] = 0.0;
+            d2i[m] = 0.0;
+          }
+#pragma unroll
+          for (int m1 = 0; m1 < 3; ++m1)
+#pragma unroll
+            for (int m2 = 0; m2 < 3; ++m2) {
+              d2r[m1 + m2] += dmr[m1] * dmr[m2] - dmi[m1] * dmi[m2];
+              d2i[m1 + m2] += dmr[m1] * dmi[m2] + dmi[m1] * dmr[m2];
+            }
+#pragma unroll
+          for (int b = 0; b < 9; ++b) {
+            const int nn = b - 4;
+            double cr = 0.0, ci = 0.0;
+#pragma unroll
+            for (int m = -2; m <= 2; ++m) {
+              const int q = nn - m;
+              if (q < -2 || q > 2) continue;
+              const double xr = cre[q + 2][t], xi = cim[q + 2][t];
+              cr += xr * d2r[m + 2] - xi * d2i[m + 2];
+              ci += xr * d2i[m + 2] + xi * d2r[m + 2];
+            }
+            cre[12 + b][t] = 0.5 * cr;
+            cim[12 + b][t] = 0.5 * ci;
+          }
+        }
       }
     } else {
       const double* ax = D.arms[k][0];
@@ -482,10 +516,10 @@ int validate_wide(const rift_ile_point_wide* pt) {
     if (pt->n_terms != 5) return RIFT_EINVAL;
     if (!std::isfinite(pt->omega)) return RIFT_EINVAL;
   } else if (pt->response == RIFT_RESP_ROTATION_DELAY) {
-    if (pt->n_terms != 5 && pt->n_terms != 12) return RIFT_EINVAL;
+    if (pt->n_terms != 5 && pt->n_terms != 12 && pt->n_terms != 21) return RIFT_EINVAL;
     if (!std::isfinite(pt->omega)) return RIFT_EINVAL;
   } else if (pt->response == RIFT_RESP_ARMS) {
-    if (pt->n_terms < 1 || pt->n_terms > WIDE_MAX_TERMS || !pt->det_arms) return RIFT_EINVAL;
+    if (pt->n_terms < 1 || pt->n_terms > WIDE_ARMS_MAX_TERMS || !pt->det_arms) return RIFT_EINVAL;
     for (int a = 0; a < 6 * pt->n_det; ++a)
       if (!std::isfinite(pt->det_arms[a])) return RIFT_EINVAL;
   } else {
@@ -527,7 +561,8 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
       (neff && bad_ptr(neff)))
     return RIFT_EINVAL;
   if (!lnL && !lnZ) return RIFT_EINVAL;
-  const int64_t nb = (n + WIDE_BLOCK - 1) / WIDE_BLOCK;
+  const int blk = pt->n_terms <= 12 ? WIDE_BLOCK : WIDE_BLOCK_21;
+  const int64_t nb = (n + blk - 1) / blk;
   if (nb > 0x7fffffff) return RIFT_EUNSUPPORTED;
   WideDesc D;
   memset(&D, 0, sizeof(D));
@@ -573,18 +608,29 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
   double* d_part = lnZ ? (double*)((char*)scratch + uv_bytes) : nullptr;
   const int64_t pe = (int64_t)D.K * D.npairs * MC * MC;
   const unsigned pgrid = (unsigned)std::min<int64_t>((pe + 255) / 256, 1024);
+  const bool wide21 = blk == WIDE_BLOCK_21;
+  const dim3 grid((unsigned)nb), block(blk);
   switch (MC) {
     case 5:
       hipLaunchKernelGGL(k_wide_pack<5>, dim3(pgrid), dim3(256), 0, st, D, pt->U, pt->V, (double*)scratch);
-      hipLaunchKernelGGL(k_wide<5>, dim3((unsigned)nb), dim3(WIDE_BLOCK), 0, st, D, theta, n, lnw, lnL, d_part);
+      if (wide21)
+        hipLaunchKernelGGL((k_wide<5, 21, WIDE_BLOCK_21>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
+      else
+        hipLaunchKernelGGL((k_wide<5, 12, WIDE_BLOCK>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
       break;
     case 12:
       hipLaunchKernelGGL(k_wide_pack<12>, dim3(pgrid), dim3(256), 0, st, D, pt->U, pt->V, (double*)scratch);
-      hipLaunchKernelGGL(k_wide<12>, dim3((unsigned)nb), dim3(WIDE_BLOCK), 0, st, D, theta, n, lnw, lnL, d_part);
+      if (wide21)
+        hipLaunchKernelGGL((k_wide<12, 21, WIDE_BLOCK_21>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
+      else
+        hipLaunchKernelGGL((k_wide<12, 12, WIDE_BLOCK>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
       break;
     default:
       hipLaunchKernelGGL(k_wide_pack<25>, dim3(pgrid), dim3(256), 0, st, D, pt->U, pt->V, (double*)scratch);
-      hipLaunchKernelGGL(k_wide<25>, dim3((unsigned)nb), dim3(WIDE_BLOCK), 0, st, D, theta, n, lnw, lnL, d_part);
+      if (wide21)
+        hipLaunchKernelGGL((k_wide<25, 21, WIDE_BLOCK_21>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
+      else
+        hipLaunchKernelGGL((k_wide<25, 12, WIDE_BLOCK>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
   }
   if (lnZ)
     hipLaunchKernelGGL(k_wide_merge, dim3(1), dim3(WIDE_BLOCK), 0, st, log((double)n), (const double*)d_part, (int)nb,

@@ -159,7 +159,8 @@ def _point_wide(ile, **over):
 
 BAD_WIDE = BAD + [
     dict(response=0), dict(response=4), dict(n_terms=4), dict(omega=float("nan")),
-    dict(response=3, n_terms=7), dict(response=3, n_terms=21), dict(response=3, omega=float("inf")),
+    dict(response=3, n_terms=7), dict(response=3, n_terms=32), dict(response=3, omega=float("inf")),
+    dict(response=2, n_terms=9),
     dict(response=2, n_terms=0), dict(response=2, n_terms=33), dict(response=2, det_arms=None),
 ]
 

@@ -50,6 +50,8 @@ CASES = [
     ("rotation_delay", 3, 4, 12, 6554, 32768.0, 600.0, synth.SIDEREAL_RATE, 8, 2000),
     ("rotation_delay", 2, 8, 12, 3000, 32768.0, 100.0, 40.0, 9, 1200),  # magnified rate, width 96
     ("rotation_delay", 4, 2, 5, 500, 4096.0, 80.0, 40.0, 10, 900),  # the drift left out
+    ("rotation_delay", 3, 2, 21, 3000, 32768.0, 150.0, 40.0, 12, 1000),  # order 2, magnified rate
+    ("rotation_delay", 2, 4, 21, 2000, 32768.0, 300.0, synth.SIDEREAL_RATE, 13, 777),  # order 2, width 84
     ("arms", 3, 4, 4, 6554, 32768.0, 600.0, 0.0, 5, 2500),
     ("arms", 2, 16, 8, 1000, 32768.0, 200.0, 0.0, 6, 600),
     ("arms", 8, 2, 3, 400, 4096.0, 50.0, 0.0, 7, 1000),
