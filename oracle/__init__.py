@@ -934,22 +934,35 @@ def systematic_resample(lnW, u):
 IS_PERIODS = ((0, 2.0 * np.pi), (2, np.pi), (4, 2.0 * np.pi))
 
 
-def is_log_prior(c, t_min, t_max, d_min, d_max):
+def _rows(rows):
+    """The sampled rows of a bit mask (bit j: row j), all seven for None."""
+    return list(range(7)) if rows is None else [j for j in range(7) if (int(rows) >> j) & 1]
+
+
+def is_log_prior(c, t_min, t_max, d_min, d_max, rows=None):
     """ln p of the samples' prior, normalised, in the sampler coordinates on
     the box ra, phiref in [0, 2 pi), psi in [0, pi), |dec| < pi/2,
     |cos incl| <= 1, tref in [t_min, t_max], D in [d_min, d_max]: the product
     of the one-dimensional densities 1/(2 pi), cos(dec)/2, 1/pi, 1/2,
     1/(2 pi), 1/(t_max - t_min) and 3 D^3 / (d_max^3 - d_min^3) (p(D) ~ D^2
-    and dD = D d ln D); -inf outside the box."""
+    and dD = D d ln D); -inf outside the box.  With `rows` (a bit mask), the
+    marginal density of those rows alone."""
     c = np.asarray(c, np.float64)
-    inside = (c[0] >= 0.0) & (c[0] < 2 * np.pi) & (np.abs(c[1]) < np.pi / 2) & (c[2] >= 0.0) & (c[2] < np.pi) & \
-        (np.abs(c[3]) <= 1.0) & (c[4] >= 0.0) & (c[4] < 2 * np.pi) & (c[5] >= t_min) & (c[5] <= t_max) & \
-        (c[6] >= np.log(d_min)) & (c[6] <= np.log(d_max))
-    const = -2.0 * np.log(2 * np.pi) - 2.0 * np.log(2.0) - np.log(np.pi) - np.log(t_max - t_min) + np.log(3.0) - \
-        np.log(d_max ** 3 - d_min ** 3)
+    S = _rows(rows)
+    inside = [(c[0] >= 0.0) & (c[0] < 2 * np.pi), np.abs(c[1]) < np.pi / 2, (c[2] >= 0.0) & (c[2] < np.pi),
+              np.abs(c[3]) <= 1.0, (c[4] >= 0.0) & (c[4] < 2 * np.pi), (c[5] >= t_min) & (c[5] <= t_max),
+              (c[6] >= np.log(d_min)) & (c[6] <= np.log(d_max))]
     with np.errstate(invalid="ignore", divide="ignore"):
-        v = const + np.log(np.cos(c[1])) + 3.0 * c[6]
-    return np.where(inside, v, -np.inf)
+        dens = [np.full(c.shape[1], -np.log(2 * np.pi)), np.log(np.cos(c[1])) - np.log(2.0),
+                np.full(c.shape[1], -np.log(np.pi)), np.full(c.shape[1], -np.log(2.0)),
+                np.full(c.shape[1], -np.log(2 * np.pi)), np.full(c.shape[1], -np.log(t_max - t_min)),
+                np.log(3.0) + 3.0 * c[6] - np.log(d_max ** 3 - d_min ** 3)]
+    ok = np.ones(c.shape[1], bool)
+    v = np.zeros(c.shape[1])
+    for j in S:
+        ok &= inside[j]
+        v = v + dens[j]
+    return np.where(ok, v, -np.inf)
 
 
 def cloud_moments(c, lnw=None):
@@ -976,44 +989,48 @@ def cloud_moments(c, lnw=None):
     return mu, (W[keep] * d) @ d.T
 
 
-def wrapped_normal_logpdf(c, mu, cov, images=6):
+def wrapped_normal_logpdf(c, mu, cov, images=6, rows=None):
     """ln of the density, at the columns of c, of x ~ N(mu, cov) with ra, psi
     and phiref taken modulo their periods: the sum of the Gaussian density
     over the lattice of periodic images of each point, here the images within
-    `images` periods of the one nearest the mean in each periodic row."""
-    c = np.asarray(c, np.float64)
-    cov = np.asarray(cov, np.float64)
+    `images` periods of the one nearest the mean in each periodic row.  With
+    `rows`, the Gaussian of those rows alone (mean and covariance restricted
+    to them)."""
+    S = _rows(rows)
+    c = np.asarray(c, np.float64)[S]
+    cov = np.asarray(cov, np.float64)[np.ix_(S, S)]
     Cinv = np.linalg.inv(cov)
     _, logdet = np.linalg.slogdet(cov)
-    d = c - np.asarray(mu, np.float64)[:, None]
-    for j, P in IS_PERIODS:
+    d = c - np.asarray(mu, np.float64)[S][:, None]
+    per = [(S.index(j), P) for j, P in IS_PERIODS if j in S]
+    for j, P in per:
         d[j] -= P * np.round(d[j] / P)
     ks = np.arange(-images, images + 1, dtype=np.float64)
-    k0, k2, k4 = np.meshgrid(ks, ks, ks, indexing="ij")
-    off = np.zeros((k0.size, 7))
-    off[:, 0] = k0.ravel() * IS_PERIODS[0][1]
-    off[:, 2] = k2.ravel() * IS_PERIODS[1][1]
-    off[:, 4] = k4.ravel() * IS_PERIODS[2][1]
+    grids = np.meshgrid(*([ks] * len(per)), indexing="ij") if per else []
+    off = np.zeros((grids[0].size if per else 1, len(S)))
+    for g, (j, P) in zip(grids, per):
+        off[:, j] = g.ravel() * P
     out = np.empty(d.shape[1])
     for s0 in range(0, d.shape[1], 128):
-        e = d[None, :, s0:s0 + 128] + off[:, :, None]       # [image, 7, chunk]
+        e = d[None, :, s0:s0 + 128] + off[:, :, None]       # [image, rows, chunk]
         q = -0.5 * np.sum(e * np.matmul(Cinv, e), axis=1)   # [image, chunk]
         m = np.max(q, axis=0)
         out[s0:s0 + 128] = m + np.log(np.sum(np.exp(q - m), axis=0))
-    return out - 0.5 * logdet - 3.5 * np.log(2 * np.pi)
+    return out - 0.5 * logdet - 0.5 * len(S) * np.log(2 * np.pi)
 
 
-def mixture_log_density(c, alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max):
+def mixture_log_density(c, alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, rows=None):
     """ln q of the defensive mixture q = alpha p + (1 - alpha) sum_m a_m
     N_m, N_m the wrapped Gaussian of mean mean[m] and covariance
-    scale cov[m]."""
+    scale cov[m]; with `rows`, the density of those rows alone."""
     c = np.asarray(c, np.float64)
     parts = []
     if alpha > 0:
-        parts.append(np.log(alpha) + is_log_prior(c, t_min, t_max, d_min, d_max))
+        parts.append(np.log(alpha) + is_log_prior(c, t_min, t_max, d_min, d_max, rows))
     for m in range(len(a)):
         if a[m] > 0 and alpha < 1:
-            parts.append(np.log((1.0 - alpha) * a[m]) + wrapped_normal_logpdf(c, mean[m], scale * np.asarray(cov[m])))
+            parts.append(np.log((1.0 - alpha) * a[m]) +
+                         wrapped_normal_logpdf(c, mean[m], scale * np.asarray(cov[m]), rows=rows))
     P = np.array(parts)
     mx = np.max(P, axis=0)
     with np.errstate(invalid="ignore"):
@@ -1021,7 +1038,12 @@ def mixture_log_density(c, alpha, a, mean, cov, scale, t_min, t_max, d_min, d_ma
     return np.where(np.isneginf(mx), -np.inf, out)
 
 
-def mixture_draw(alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, z, v, u):
+def _prior_draw(w, t_min, t_max, d_min, d_max):
+    return np.array([2 * np.pi * w[0], np.arcsin(2 * w[1] - 1), np.pi * w[2], 2 * w[3] - 1, 2 * np.pi * w[4],
+                     t_min + (t_max - t_min) * w[5], np.log(d_min ** 3 + w[6] * (d_max ** 3 - d_min ** 3)) / 3.0])
+
+
+def mixture_draw(alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, z, v, u, rows=None):
     """Independent draws from q with the caller's random numbers: u [n] in
     [0, 1) picks the prior when u < alpha, else component m, the first with
     u < alpha + (1 - alpha) (a_0 + .. + a_m) (the last one if none); a prior
@@ -1030,10 +1052,14 @@ def mixture_draw(alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, z, v, u
     tref = t_min + (t_max - t_min) v5, ln D = ln(d_min^3 + v6 (d_max^3 -
     d_min^3)) / 3); a component draw is mean[m] + L z with L L^T = scale
     cov[m] (Cholesky), z [7, n] standard normals, then ra, psi, phiref
-    reduced into [0, P).  Returns (c [7, n], comp [n]: -1 for the prior)."""
+    reduced into [0, P).  With `rows`, a component draws those rows (the
+    Cholesky factor of their covariance applied to z at those rows) and the
+    others from the prior as a prior draw does.  Returns
+    (c [7, n], comp [n]: -1 for the prior)."""
     z = np.asarray(z, np.float64)
     v = np.asarray(v, np.float64)
     u = np.asarray(u, np.float64)
+    S = _rows(rows)
     n = u.size
     c = np.empty((7, n))
     comp = np.full(n, -1, np.int64)
@@ -1041,31 +1067,32 @@ def mixture_draw(alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, z, v, u
     cum = np.cumsum(np.asarray(a, np.float64))
     T = alpha + (1.0 - alpha) * cum
     for i in range(n):
+        c[:, i] = _prior_draw(v[:, i], t_min, t_max, d_min, d_max)
         if u[i] < alpha or ncomp == 0:
-            w = v[:, i]
-            c[:, i] = (2 * np.pi * w[0], np.arcsin(2 * w[1] - 1), np.pi * w[2], 2 * w[3] - 1, 2 * np.pi * w[4],
-                       t_min + (t_max - t_min) * w[5], np.log(d_min ** 3 + w[6] * (d_max ** 3 - d_min ** 3)) / 3.0)
             continue
         m = int(np.argmax(u[i] < T)) if np.any(u[i] < T) else ncomp - 1
-        L = np.linalg.cholesky(scale * np.asarray(cov[m], np.float64))
-        x = np.asarray(mean[m], np.float64) + L @ z[:, i]
-        for j, P in IS_PERIODS:
-            x[j] -= P * np.floor(x[j] / P)
-        c[:, i] = x
+        L = np.linalg.cholesky(scale * np.asarray(cov[m], np.float64)[np.ix_(S, S)])
+        x = np.asarray(mean[m], np.float64)[S] + L @ z[S, i]
+        for k, j in enumerate(S):
+            P = dict(IS_PERIODS).get(j)
+            c[j, i] = x[k] - P * np.floor(x[k] / P) if P else x[k]
         comp[i] = m
     return c, comp
 
 
-def mixture_is(alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, z, v, u):
+def mixture_is(alpha, a, mean, cov, scale, t_min, t_max, d_min, d_max, z, v, u, rows=None):
     """Draws from the defensive mixture and their log weights ln p - ln q of
     Eq. (sampler-menu:is), so that ln Z = lnZ(lnL(theta), lnw).  Returns
     (theta [7, n] in the likelihood's coordinates, lnw [n], comp [n]).  A draw
     outside the prior's box has lnw = -inf and is returned moved onto the box
-    (dec, cos incl, tref and ln D clamped), so its likelihood is finite."""
+    (dec, cos incl, tref and ln D clamped), so its likelihood is finite.
+    With `rows`, p and q are the densities of those rows alone: the weights of
+    a likelihood marginalised over the other rows (their draws are the
+    prior's and do not enter the weight)."""
     box = (t_min, t_max, d_min, d_max)
-    c, comp = mixture_draw(alpha, a, mean, cov, scale, *box, z, v, u)
-    lp = is_log_prior(c, *box)
-    lq = mixture_log_density(c, alpha, a, mean, cov, scale, *box)
+    c, comp = mixture_draw(alpha, a, mean, cov, scale, *box, z, v, u, rows)
+    lp = is_log_prior(c, *box, rows)
+    lq = mixture_log_density(c, alpha, a, mean, cov, scale, *box, rows)
     lnw = np.where(np.isfinite(lp), lp - lq, -np.inf)
     cc = c.copy()
     cc[1] = np.clip(cc[1], -np.pi / 2, np.pi / 2)

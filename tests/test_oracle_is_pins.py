@@ -17,7 +17,12 @@ coverage, adaptive clouds, and evidence", against what the mathematics fixes:
 * the estimator is unbiased: with L = 1 the mean weight is 1, and for a
   likelihood bump of known integral the estimate lies within four standard
   errors.  Weighting each draw by its own component density instead of the
-  full mixture is biased, and that planted mistake fails the pin.
+  full mixture is biased, and that planted mistake fails the pin;
+* for a likelihood marginalised over some rows (the `rows` mask): the
+  restricted component is the full one integrated over a left-out row (by
+  quadrature), the restricted prior is normalised, all seven rows are the
+  default bit for bit, and the estimate of a bump over the sampled rows is
+  unbiased while the left-out rows take prior draws.
 """
 import numpy as np
 import pytest
@@ -204,3 +209,69 @@ def test_is_estimate_is_unbiased(oracle_mod, alpha):
         bad[sel] = oracle_mod.is_log_prior(c[:, sel], *BOX) - lq
     tb = np.exp(lnL + bad)
     assert abs(tb.mean() - Z) > 4 * tb.std() / np.sqrt(n)
+
+
+def test_restricted_component_is_the_marginal(oracle_mod):
+    """Leaving out ln D (row 6) gives the full wrapped density integrated over
+    ln D: the Gaussian's marginal is its sub-covariance, images included."""
+    cov = _corr_cov(broad=True)
+    cov[6, 0] = cov[0, 6] = 0.5 * np.sqrt(cov[0, 0] * cov[6, 6])  # coupled to a periodic row
+    mu = np.array([0.1, 0.2, 3.0, 0.0, 6.1, 0.0, 5.0])
+    c = np.array([2.5, 0.25, 0.4, -0.05, 0.3, 0.0005, 0.0])
+    got = oracle_mod.wrapped_normal_logpdf(c[:, None], mu, cov, rows=0b0111111)[0]
+
+    def f(x):
+        cc = c.copy()
+        cc[6] = x
+        return np.exp(oracle_mod.wrapped_normal_logpdf(cc[:, None], mu, cov)[0] - got)
+    val, _ = integrate.quad(f, mu[6] - 12 * np.sqrt(cov[6, 6]), mu[6] + 12 * np.sqrt(cov[6, 6]), epsabs=0,
+                            epsrel=1e-12, limit=200)
+    assert abs(val - 1.0) < 1e-10, val
+
+
+def test_restricted_prior_and_default_rows(oracle_mod):
+    c0 = _interior()
+    lp0 = oracle_mod.is_log_prior(c0[:, None], *BOX, rows=0b1000010)[0]
+
+    def f(lnd, dec):
+        c = c0.copy()
+        c[1], c[6] = dec, lnd
+        return np.exp(oracle_mod.is_log_prior(c[:, None], *BOX, rows=0b1000010)[0])
+    val, _ = integrate.dblquad(f, -np.pi / 2, np.pi / 2, np.log(BOX[2]), np.log(BOX[3]), epsabs=0, epsrel=1e-10)
+    assert abs(val - 1.0) < 1e-8, val
+    assert np.isfinite(lp0)
+    rng = np.random.default_rng(9)
+    a, means, covs = _mixture()
+    n = 300
+    args = (0.2, a, means, covs, 1.5, *BOX, rng.normal(size=(7, n)), rng.uniform(size=(7, n)), rng.uniform(size=n))
+    t1, w1, c1 = oracle_mod.mixture_is(*args)
+    t2, w2, c2 = oracle_mod.mixture_is(*args, rows=0b1111111)
+    assert np.array_equal(t1, t2) and np.array_equal(w1, w2) and np.array_equal(c1, c2)
+
+
+def test_is_estimate_unbiased_over_sampled_rows(oracle_mod):
+    """A likelihood marginalised over phiref and ln D (rows 4 and 6 left out):
+    the components sample the other five rows, the left-out rows are prior
+    draws, and the weights carry the five rows' densities only."""
+    rng = np.random.default_rng(10)
+    a, means, covs = _mixture()
+    rows = 0b0101111
+    n = 24000
+    th, lnw, comp = oracle_mod.mixture_is(0.2, a, means, covs, 1.5, *BOX, rng.normal(size=(7, n)),
+                                          rng.uniform(size=(7, n)), rng.uniform(size=n), rows=rows)
+    c = th.copy()
+    c[3] = np.cos(th[3])
+    c[6] = np.log(th[6])
+    # left-out rows follow the prior whatever the component
+    assert stats.kstest(c[4], lambda x: x / (2 * np.pi)).pvalue > 1e-3
+    assert stats.kstest(c[6], lambda x: (np.exp(3 * x) - BOX[2] ** 3) / (BOX[3] ** 3 - BOX[2] ** 3)).pvalue > 1e-3
+    s_r, s_c = 0.1, 0.08
+    lnL = _bump(c, 1.1, 0.25, s_r, s_c)
+    Z = np.sqrt(2 * np.pi) * s_r / (2 * np.pi) * np.sqrt(2 * np.pi) * s_c / 2
+    terms = np.exp(lnL + lnw)
+    assert abs(terms.mean() - Z) < 4 * terms.std() / np.sqrt(n), (terms.mean(), Z)
+    # the full seven-row weights on these draws are wrong: the left-out rows
+    # were not drawn from the components
+    full = oracle_mod.is_log_prior(c, *BOX) - oracle_mod.mixture_log_density(c, 0.2, a, means, covs, 1.5, *BOX)
+    tf = np.exp(lnL + full)
+    assert abs(tf.mean() - Z) > 4 * tf.std() / np.sqrt(n)
