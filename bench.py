@@ -1079,12 +1079,113 @@ def extra_is(ile, synth, torch, steps, draws=1_000_000, cpu=True):
     def kish(t):
         w = torch.exp(t - t.max())
         return float((w.sum() ** 2 / (w * w).sum()).cpu())
-    return {"workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 4; a component fitted to "
-                        "the best 4000 of 1e6 prior draws; 1e6 draws from 0.3 prior + 0.7 N(mu, 1.5 C)",
-            "status": int(st.cpu()[0]), "mixture_is_ms": 1e3 * secs_draw / steps,
-            "mixture_draws_per_s": n * steps / secs_draw, "moments_1e6_ms": 1e3 * secs_mom / steps,
-            "lnZ_ms": 1e3 * secs_z / steps, "lnZ_is": float(zi.cpu()[0]), "kish_is": kish(li + lnw),
-            "lnZ_prior_mc_4e6": float(zp.cpu()[0]), "kish_prior_mc_4e6": kish(lq)}
+    out = {"workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 4; a component fitted to "
+                       "the best 4000 of 1e6 prior draws; 1e6 draws from 0.3 prior + 0.7 N(mu, 1.5 C)",
+           "status": int(st.cpu()[0]), "mixture_is_ms": 1e3 * secs_draw / steps,
+           "mixture_draws_per_s": n * steps / secs_draw, "moments_1e6_ms": 1e3 * secs_mom / steps,
+           "lnZ_ms": 1e3 * secs_z / steps, "lnZ_is": float(zi.cpu()[0]), "kish_is": kish(li + lnw),
+           "lnZ_prior_mc_4e6": float(zp.cpu()[0]), "kish_prior_mc_4e6": kish(lq)}
+    del z, v, u, th, lnw, comp, big, li, lq
+    torch.cuda.empty_cache()
+    out["distance_marginalised_snr12"] = _is_dmarg_multimode(ile, synth, torch, steps)
+    return out
+
+
+def _kmeans(X, k, iters=50, seed=0):
+    rng = np.random.default_rng(seed)
+    C = X[rng.choice(len(X), k, replace=False)]
+    for _ in range(iters):
+        lab = ((X[:, None, :] - C[None]) ** 2).sum(-1).argmin(1)
+        for j in range(k):
+            if np.any(lab == j):
+                C[j] = X[lab == j].mean(0)
+    return lab
+
+
+def _is_dmarg_multimode(ile, synth, torch, steps):
+    """SNR 12 with the likelihood marginalised over distance in the kernel:
+    one component per k-means cluster (4) of the best 8000 of 2e6 pilot draws,
+    each fitted by the device moments over the six sampled rows; 2e6 draws
+    from 0.1 prior + 0.9 sum_m a_m N(mu_m, 2 C_m) weighted over those rows,
+    ln Z through rift_ile_plan_lnZ_dmarg; against brute-force prior Monte
+    Carlo of 1e8 draws (drawn by rift_ile_mixture_is with alpha = 1)."""
+    box = (-0.01, 0.01, 10.0, 1000.0)
+    per = ((0, 2 * np.pi), (2, np.pi), (4, 2 * np.pi))
+    pt = synth.make_point(3, 9, 6554, 32768.0, 12.0, 61)
+    N = 2_000_000
+    plan = ile.Plan([pt], [N])
+    ll = torch.empty(N, dtype=torch.float64, device="cuda")
+    zeros = torch.zeros(N, dtype=torch.float64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    m_run, s_run, s2_run, pilot = -np.inf, 0.0, 0.0, None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        v = torch.rand((7, N), dtype=torch.float64, device="cuda", generator=gen)
+        th, _, _, _ = ile.mixture_is(1.0, [], None, None, 1.0, box, v, v, zeros)
+        plan.lnZ_dmarg(th, box[2], box[3], 20, lnL_out=ll)
+        lm = float(ll.max())
+        w = torch.exp(ll - lm)
+        s1, s2 = float(w.sum()), float((w * w).sum())
+        m = max(m_run, lm)
+        s_run = s_run * np.exp(m_run - m) + s1 * np.exp(lm - m)
+        s2_run = s2_run * np.exp(2 * (m_run - m)) + s2 * np.exp(2 * (lm - m))
+        m_run = m
+        if pilot is None:
+            pilot = (th.cpu().numpy(), ll.cpu().numpy())
+    torch.cuda.synchronize()
+    prior_s = time.perf_counter() - t0
+    thp, lp = pilot
+    best = np.argsort(lp)[-8000:]
+    c = thp[:, best].copy()
+    c[3] = np.cos(c[3])
+    c[6] = np.log(c[6])
+    lb = lp[best]
+    feats = np.stack([np.cos(c[0]) * np.cos(c[1]), np.sin(c[0]) * np.cos(c[1]), np.sin(c[1]), np.cos(c[4]),
+                      np.sin(c[4]), np.cos(2 * c[2]), np.sin(2 * c[2]), c[3]], 1)
+    lab = _kmeans(feats, 4)
+    means, covs, a = [], [], []
+    for j in range(4):
+        sel = lab == j
+        cj = c[:, sel].copy()
+        for r, P in per:
+            mu = np.arctan2(np.sin(2 * np.pi * cj[r] / P).mean(), np.cos(2 * np.pi * cj[r] / P).mean()) * P / (2 * np.pi)
+            cj[r] = mu + ((cj[r] - mu + P / 2) % P) - P / 2
+        mm, C = ile.moments(torch.as_tensor(cj, device="cuda").contiguous(),
+                            torch.as_tensor(0.5 * (lb[sel] - lb[sel].max()), device="cuda").contiguous())
+        C = C.cpu().numpy()
+        f = np.ones(7)
+        for r, P in per:
+            f[r] = min(1.0, 0.45 * P / np.sqrt(2.0 * C[r, r]))
+        means.append(mm.cpu().numpy())
+        covs.append(f[:, None] * C * f[None, :])
+        a.append(np.exp(lb[sel] - lb.max()).sum())
+    a = np.array(a) / np.sum(a)
+    mt = torch.as_tensor(np.array(means), device="cuda").contiguous()
+    ct = torch.as_tensor(np.array(covs), device="cuda").contiguous()
+    gen.manual_seed(7)
+    z = torch.randn((7, N), dtype=torch.float64, device="cuda", generator=gen)
+    v = torch.rand((7, N), dtype=torch.float64, device="cuda", generator=gen)
+    u = torch.rand(N, dtype=torch.float64, device="cuda", generator=gen)
+    th = torch.empty((7, N), dtype=torch.float64, device="cuda")
+    lnw = torch.empty(N, dtype=torch.float64, device="cuda")
+    comp = torch.empty(N, dtype=torch.int32, device="cuda")
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    draw = (lambda: ile.mixture_is(0.1, a, mt, ct, 2.0, box, z, v, u, th, lnw, comp, st, rows=0b0111111))
+    secs_draw, _ = time_steps(draw, steps, 2, torch)
+    zi, _ = plan.lnZ_dmarg(th, box[2], box[3], 20, lnw=lnw, lnL_out=ll)
+    t = ll + lnw
+    t = t[torch.isfinite(t)]
+    w = torch.exp(t - t.max())
+    plan.close()
+    return {"workload": "3 detectors, 9 modes, SNR 12, distance marginalised in the kernel (20-node Gauss-Hermite); "
+                        "4 components from k-means clusters of the best 8000 of 2e6 pilot draws; 2e6 IS draws over "
+                        "the other six rows",
+            "status": int(st.cpu()[0]), "mixture_is_ms_2e6": 1e3 * secs_draw / steps,
+            "lnZ_is": float(zi.cpu()[0]), "kish_is_2e6": float((w.sum() ** 2 / (w * w).sum()).cpu()),
+            "lnZ_prior_mc_1e8": float(m_run + np.log(s_run / (50 * N))), "kish_prior_mc_1e8": s_run ** 2 / s2_run,
+            "prior_mc_1e8_s": prior_s}
 
 
 def main():

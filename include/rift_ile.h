@@ -615,8 +615,15 @@ int rift_ile_moments(int64_t n, const double *c, const double *lnw, double *mean
  * pi/2 for psi): every lnw and theta is then NaN.  RIFT_EINVAL: n < 0;
  * n_comp outside [0, RIFT_IS_MAX_COMP]; alpha outside [0, 1] (alpha = 1 when
  * n_comp = 0); scale not finite and > 0; an empty box or d_min <= 0; a bad
- * a; null or misaligned pointers.  Enqueues and returns; stream-ordered
- * scratch of 768 bytes per component. */
+ * a; rows outside 1 .. 0x7f; null or misaligned pointers.  Enqueues and
+ * returns; stream-ordered scratch of 784 bytes per component.
+ * A likelihood marginalised over some rows (distance, phiref, psi in the
+ * kernel) is normalised over the others: with mix->rows naming the sampled
+ * rows S, the components are the Gaussians of those rows (mean and
+ * covariance restricted to S, drawn from z at the rows of S), every other
+ * row is drawn from the prior by v as a prior draw is, and p and q in the
+ * weight are the densities of the rows of S alone (the marginal prior of S;
+ * the box and the periodic images of S). */
 #define RIFT_IS_MAX_COMP 32
 typedef struct {
   int32_t n_comp;     /* components, 0 .. RIFT_IS_MAX_COMP */
@@ -625,6 +632,7 @@ typedef struct {
   const double *a;    /* HOST [n_comp] component weights */
   const double *mean; /* DEVICE [n_comp][7] */
   const double *cov;  /* DEVICE [n_comp][7][7] */
+  int32_t rows;       /* bit j set when row j is sampled by the components, 1 .. 0x7f (0x7f: all) */
 } rift_ile_mixture;
 int rift_ile_mixture_is(int64_t n, const rift_ile_mixture *mix, const rift_ile_hmc_prior *prior, const double *z,
                         const double *v, const double *u, double *theta, double *lnw, int32_t *comp,

@@ -224,11 +224,11 @@ struct IsComp {
 };
 
 struct IsArgs {
-  int32_t n_comp;
+  int32_t n_comp, rows, n_rows;  // rows: bit j set when row j is sampled by the components
   double alpha, scale;
   double a[RIFT_IS_MAX_COMP];
   double t_min, t_max, lnd_min, lnd_max, d3min, d3span;
-  double lp_const;  // ln of the prior's normalisation
+  double lc[7];  // the constant part of each row's normalised prior log-density
 };
 
 __device__ __forceinline__ int tri(int r) { return r * (r + 1) / 2; }
@@ -246,10 +246,15 @@ __global__ void k_is_setup(IsArgs A, const double* __restrict__ mean, const doub
   if (m < A.n_comp) {
     IsComp T;
     bool ok = true;
+    // the sampled rows' covariance embedded in 7 x 7 with the identity on the
+    // other rows (no cross terms, so their factor rows are unit and unused)
     double S[7][7];
     for (int r = 0; r < 7; ++r)
-      for (int q = 0; q <= r; ++q) S[r][q] = A.scale * cov[(size_t)m * 49 + r * 7 + q];  // lower triangle
-    for (int j = 0; j < 7; ++j) T.mu[j] = T.mur[j] = mean[m * 7 + j];
+      for (int q = 0; q <= r; ++q) {
+        const bool sr = (A.rows >> r) & 1, sq = (A.rows >> q) & 1;
+        S[r][q] = (sr && sq) ? A.scale * cov[(size_t)m * 49 + r * 7 + q] : (r == q ? 1.0 : 0.0);  // lower triangle
+      }
+    for (int j = 0; j < 7; ++j) T.mu[j] = T.mur[j] = ((A.rows >> j) & 1) ? mean[m * 7 + j] : 0.0;
     // Cholesky by columns of rows
     for (int r = 0; r < 7; ++r) {
       for (int q = 0; q <= r; ++q) {
@@ -281,9 +286,10 @@ __global__ void k_is_setup(IsArgs A, const double* __restrict__ mean, const doub
       const int j = PER_ROW[p];
       const double P = period(p);
       T.mur[j] = T.mu[j] - P * floor(T.mu[j] / P);
+      const bool sampled = (A.rows >> j) & 1;
       const double sig = sqrt(S[j][j]);
-      ok = ok && sig <= 0.5 * P && T.mu[j] == T.mu[j] && fabs(T.mu[j]) < 1e15;
-      K[p] = ok ? fmax(0.0, ceil(9.0 * sig / P - 0.5)) : 0.0;
+      ok = ok && (!sampled || (sig <= 0.5 * P && T.mu[j] == T.mu[j] && fabs(T.mu[j]) < 1e15));
+      K[p] = (ok && sampled) ? fmax(0.0, ceil(9.0 * sig / P - 0.5)) : 0.0;
     }
     // the row with the most images innermost (summed by a recurrence)
     int inner = 2;
@@ -302,7 +308,7 @@ __global__ void k_is_setup(IsArgs A, const double* __restrict__ mean, const doub
     for (int r = 0; r < 7; ++r) T.gg += T.g[2][r] * T.g[2][r];
     T.egg = exp(-T.gg);
     for (int j = 0; j < 7; ++j) ok = ok && T.mu[j] == T.mu[j] && fabs(T.mu[j]) < __builtin_inf();
-    T.lognorm = log((1.0 - A.alpha) * A.a[m]) - ldet - 3.5 * log(TWO_PI);
+    T.lognorm = log((1.0 - A.alpha) * A.a[m]) - ldet - 0.5 * A.n_rows * log(TWO_PI);
     double cum = 0.0;
     for (int k = 0; k <= m; ++k) cum += A.a[k];
     T.thr = A.alpha + (1.0 - A.alpha) * cum;
@@ -345,7 +351,9 @@ __global__ void __launch_bounds__(IS_BLOCK) k_is_draw(int64_t n, IsArgs A, const
     const double ui = u[i];
     double c[7];
     int m = -1;
-    if (ui < A.alpha || A.n_comp == 0) {
+    const bool all_rows = A.rows == 0x7f;
+    if (ui < A.alpha || A.n_comp == 0 || !all_rows) {
+      // a prior draw (the rows a component does not sample keep it)
       double w[7];
 #pragma unroll
       for (int j = 0; j < 7; ++j) w[j] = v[j * n + i];
@@ -356,7 +364,8 @@ __global__ void __launch_bounds__(IS_BLOCK) k_is_draw(int64_t n, IsArgs A, const
       c[4] = TWO_PI * w[4];
       c[5] = A.t_min + (A.t_max - A.t_min) * w[5];
       c[6] = log(A.d3min + w[6] * A.d3span) / 3.0;
-    } else {
+    }
+    if (!(ui < A.alpha || A.n_comp == 0)) {
       m = A.n_comp - 1;
       for (int k = 0; k < A.n_comp - 1; ++k)
         if (ui < sh[k].thr) {
@@ -372,7 +381,7 @@ __global__ void __launch_bounds__(IS_BLOCK) k_is_draw(int64_t n, IsArgs A, const
         double x = T.mu[r];
 #pragma unroll
         for (int k = 0; k <= r; ++k) x += T.L[tri(r) + k] * zz[k];
-        c[r] = x;
+        if ((A.rows >> r) & 1) c[r] = x;
       }
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
@@ -383,11 +392,21 @@ __global__ void __launch_bounds__(IS_BLOCK) k_is_draw(int64_t n, IsArgs A, const
         c[j] = x;
       }
     }
-    // ln p, normalised, on the box
-    const bool inside = c[0] >= 0.0 && c[0] < TWO_PI && fabs(c[1]) < HALF_PI && c[2] >= 0.0 && c[2] < PI &&
-                        fabs(c[3]) <= 1.0 && c[4] >= 0.0 && c[4] < TWO_PI && c[5] >= A.t_min && c[5] <= A.t_max &&
-                        c[6] >= A.lnd_min && c[6] <= A.lnd_max;
-    const double lp = inside ? A.lp_const + log(cos(c[1])) + 3.0 * c[6] : -__builtin_inf();
+    // ln p of the sampled rows, normalised, on the box
+    const bool in_row[7] = {c[0] >= 0.0 && c[0] < TWO_PI, fabs(c[1]) < HALF_PI, c[2] >= 0.0 && c[2] < PI,
+                            fabs(c[3]) <= 1.0, c[4] >= 0.0 && c[4] < TWO_PI, c[5] >= A.t_min && c[5] <= A.t_max,
+                            c[6] >= A.lnd_min && c[6] <= A.lnd_max};
+    bool inside = true;
+    double lp = 0.0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+      if ((A.rows >> j) & 1) {
+        inside = inside && in_row[j];
+        lp += A.lc[j];
+      }
+    if (A.rows & 2) lp += log(cos(c[1]));
+    if (A.rows & 64) lp += 3.0 * c[6];
+    if (!inside) lp = -__builtin_inf();
     double out_w = -__builtin_inf();
     if (inside) {
       // ln q: the prior's share and every component's wrapped density
@@ -398,7 +417,7 @@ __global__ void __launch_bounds__(IS_BLOCK) k_is_draw(int64_t n, IsArgs A, const
         if (T.lognorm == -__builtin_inf()) continue;
         double d[7];
 #pragma unroll
-        for (int j = 0; j < 7; ++j) d[j] = c[j] - T.mur[j];
+        for (int j = 0; j < 7; ++j) d[j] = ((A.rows >> j) & 1) ? c[j] - T.mur[j] : 0.0;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
           const int j = p == 0 ? 0 : (p == 1 ? 2 : 4);
@@ -506,12 +525,15 @@ extern "C" int rift_ile_mixture_is(int64_t n, const rift_ile_mixture* mix, const
   if (nc < 0 || nc > RIFT_IS_MAX_COMP) return RIFT_EINVAL;
   if (!(mix->alpha >= 0.0 && mix->alpha <= 1.0)) return RIFT_EINVAL;
   if (nc == 0 && mix->alpha != 1.0) return RIFT_EINVAL;
+  if (mix->rows < 1 || mix->rows > 0x7f) return RIFT_EINVAL;
   if (!(mix->scale > 0.0 && mix->scale < __builtin_inf())) return RIFT_EINVAL;
   if (!(prior->t_min < prior->t_max) || !std::isfinite(prior->t_min) || !std::isfinite(prior->t_max) ||
       !(prior->d_min > 0.0 && prior->d_min < prior->d_max) || !std::isfinite(prior->d_max))
     return RIFT_EINVAL;
   IsArgs A{};
   A.n_comp = nc;
+  A.rows = mix->rows;
+  A.n_rows = __builtin_popcount((unsigned)mix->rows);
   A.alpha = mix->alpha;
   A.scale = mix->scale;
   if (nc > 0) {
@@ -534,8 +556,9 @@ extern "C" int rift_ile_mixture_is(int64_t n, const rift_ile_mixture* mix, const
   A.lnd_max = log(prior->d_max);
   A.d3min = prior->d_min * prior->d_min * prior->d_min;
   A.d3span = prior->d_max * prior->d_max * prior->d_max - A.d3min;
-  A.lp_const = -2.0 * log(TWO_PI) - 2.0 * log(2.0) - log(PI) - log(prior->t_max - prior->t_min) + log(3.0) -
-               log(A.d3span);
+  const double lc[7] = {-log(TWO_PI), -log(2.0), -log(PI), -log(2.0), -log(TWO_PI),
+                        -log(prior->t_max - prior->t_min), log(3.0) - log(A.d3span)};
+  for (int j = 0; j < 7; ++j) A.lc[j] = lc[j];
   hipStream_t st = (hipStream_t)stream;
   const size_t bytes = sizeof(IsComp) * (size_t)std::max(nc, 1) + 256;
   void* w = nullptr;

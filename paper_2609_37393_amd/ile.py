@@ -150,7 +150,8 @@ class CHmcPrior(ctypes.Structure):
 
 class CMixture(ctypes.Structure):
     _fields_ = [("n_comp", ctypes.c_int32), ("alpha", ctypes.c_double), ("scale", ctypes.c_double),
-                ("a", ctypes.c_void_p), ("mean", ctypes.c_void_p), ("cov", ctypes.c_void_p)]
+                ("a", ctypes.c_void_p), ("mean", ctypes.c_void_p), ("cov", ctypes.c_void_p),
+                ("rows", ctypes.c_int32)]
 
 
 class CConfig(ctypes.Structure):
@@ -400,13 +401,14 @@ def moments(c, lnw=None):
     return mean, cov
 
 
-def mixture_is(alpha, a, mean, cov, scale, box, z, v, u, theta=None, lnw=None, comp=None, status=None):
+def mixture_is(alpha, a, mean, cov, scale, box, z, v, u, theta=None, lnw=None, comp=None, status=None, rows=0x7F):
     """Draws from the defensive mixture alpha p + (1 - alpha) sum_m a_m
     N(mean[m], scale cov[m]) and their log weights ln p - ln q
     (rift_ile_mixture_is).  a: host sequence; mean [n_comp, 7], cov
     [n_comp, 7, 7], z, v [7, n], u [n]: device tensors; box = (t_min, t_max,
-    d_min, d_max).  Returns (theta [7, n], lnw [n], comp [n] int32, status [1]
-    int32)."""
+    d_min, d_max); rows: bit mask of the rows the components sample (the
+    weights then cover those rows alone).  Returns (theta [7, n], lnw [n],
+    comp [n] int32, status [1] int32)."""
     lib = load()
     dev = u.device
     n = u.numel()
@@ -417,7 +419,7 @@ def mixture_is(alpha, a, mean, cov, scale, box, z, v, u, theta=None, lnw=None, c
     comp = comp if comp is not None else torch.empty(n, dtype=torch.int32, device=dev)
     status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
     mix = CMixture(nc, float(alpha), float(scale), a_h.ctypes.data if nc else None,
-                   mean.data_ptr() if nc else None, cov.data_ptr() if nc else None)
+                   mean.data_ptr() if nc else None, cov.data_ptr() if nc else None, int(rows))
     pr = CHmcPrior(*[float(x) for x in box])
     ptr = (lambda t: t.data_ptr() if n else None)
     _check(lib.rift_ile_mixture_is(n, ctypes.byref(mix), ctypes.byref(pr), ptr(z), ptr(v), ptr(u), ptr(theta),

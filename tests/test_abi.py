@@ -243,8 +243,8 @@ def test_importance_arguments(lib):
     box = ile.CHmcPrior(-0.01, 0.01, 10.0, 1000.0)
     a = np.array([0.25, 0.75])
 
-    def call(n=4, nc=2, alpha=0.1, scale=1.5, w=a, prior=box, z=fake, comp=None, status=None):
-        mix = ile.CMixture(nc, alpha, scale, None if w is None else w.ctypes.data, fake, fake)
+    def call(n=4, nc=2, alpha=0.1, scale=1.5, w=a, prior=box, z=fake, comp=None, status=None, rows=0x7F):
+        mix = ile.CMixture(nc, alpha, scale, None if w is None else w.ctypes.data, fake, fake, rows)
         return lib.rift_ile_mixture_is(n, ctypes.byref(mix), None if prior is None else ctypes.byref(prior), z, fake,
                                        fake, fake, fake, comp, status, None)
 
@@ -261,6 +261,7 @@ def test_importance_arguments(lib):
     assert call(prior=ile.CHmcPrior(-0.01, 0.01, 0.0, 1000.0)) == EINVAL
     assert call(z=None) == EINVAL and call(z=0x1004) == EINVAL
     assert call(comp=0x1002) == EINVAL and call(status=0x1001) == EINVAL
+    assert call(rows=0) == EINVAL and call(rows=0x80) == EINVAL
     assert lib.rift_ile_mixture_is(4, None, ctypes.byref(box), fake, fake, fake, fake, fake, None, None, None) \
         == EINVAL
 

@@ -110,7 +110,7 @@ MIXES = {
 }
 
 
-def _run(ile, oracle_mod, name, n, seed):
+def _run(ile, oracle_mod, name, n, seed, rows=0x7F):
     alpha, a, means, covs, scale = MIXES[name]
     rng = np.random.default_rng(seed)
     z = rng.normal(size=(7, n))
@@ -118,19 +118,21 @@ def _run(ile, oracle_mod, name, n, seed):
     u = rng.uniform(size=n)
     means = np.asarray(means, np.float64).reshape(len(a), 7)
     covs = np.asarray(covs, np.float64).reshape(len(a), 7, 7)
-    th, lnw, comp, status = ile.mixture_is(alpha, a, _dev(means), _dev(covs), scale, BOX, _dev(z), _dev(v), _dev(u))
-    return (alpha, a, means, covs, scale, z, v, u), (th.cpu().numpy(), lnw.cpu().numpy(), comp.cpu().numpy(),
-                                                     int(status.cpu().numpy()[0]))
+    th, lnw, comp, status = ile.mixture_is(alpha, a, _dev(means), _dev(covs), scale, BOX, _dev(z), _dev(v), _dev(u),
+                                           rows=rows)
+    return (alpha, a, means, covs, scale, z, v, u, rows), (th.cpu().numpy(), lnw.cpu().numpy(), comp.cpu().numpy(),
+                                                           int(status.cpu().numpy()[0]))
 
 
 def _compare(oracle_mod, args, got, cols=None):
-    alpha, a, means, covs, scale, z, v, u = args
+    alpha, a, means, covs, scale, z, v, u, rows = args
+    S = [j for j in range(7) if (rows >> j) & 1]
     th, lnw, comp, status = got
     assert status == 0
     if cols is not None:
         z, v, u = z[:, cols], v[:, cols], u[cols]
         th, lnw, comp = th[:, cols], lnw[cols], comp[cols]
-    want_th, want_w, want_comp = oracle_mod.mixture_is(alpha, a, means, covs, scale, *BOX, z, v, u)
+    want_th, want_w, want_comp = oracle_mod.mixture_is(alpha, a, means, covs, scale, *BOX, z, v, u, rows=rows)
     # the selection, where u is firm
     T = alpha + (1.0 - alpha) * np.cumsum(a) if len(a) else np.zeros(0)
     firm = np.all(np.abs(u[:, None] - np.r_[alpha, T][None, :]) > 1e-14, axis=1)
@@ -147,8 +149,9 @@ def _compare(oracle_mod, args, got, cols=None):
     bound[:, pri] = 1e-14 * (1 + np.abs(cw[:, pri]))
     for m in range(len(a)):
         sel = want_comp == m
-        L = np.linalg.cholesky(scale * covs[m])
-        bound[:, sel] = 1e-13 * (np.abs(means[m])[:, None] + np.abs(L) @ np.abs(z[:, sel])) + 1e-15
+        L = np.linalg.cholesky(scale * covs[m][np.ix_(S, S)])
+        bound[:, sel] = 1e-14 * (1 + np.abs(cw[:, sel]))  # the rows left to the prior
+        bound[np.ix_(S, sel)] = 1e-13 * (np.abs(means[m][S])[:, None] + np.abs(L) @ np.abs(z[np.ix_(S, sel)])) + 1e-15
     diff = cg - cw
     for j, P in PERIODIC:
         diff[j] -= P * np.round(diff[j] / P)
@@ -165,7 +168,7 @@ def _compare(oracle_mod, args, got, cols=None):
     ok = same & ~edge
     assert np.array_equal(np.isneginf(lnw[ok]), np.isneginf(want_w[ok]))
     fin = ok & inside
-    lp = oracle_mod.is_log_prior(c_or[:, fin], *BOX)
+    lp = oracle_mod.is_log_prior(c_or[:, fin], *BOX, rows=rows)
     lq = lp - want_w[fin]
     bar = 1e-11 * (1 + np.abs(lp) + np.abs(lq))
     err = np.abs(lnw[fin] - want_w[fin])
@@ -181,6 +184,16 @@ def test_mixture_is_matches_oracle(ile, oracle_mod, name):
     assert inside.mean() > 0.3
     if name == "prior":
         assert np.all(got[1][np.isfinite(got[1])] == 0.0) and np.all(got[2] == -1)
+
+
+@pytest.mark.parametrize("name,rows", [("three", 0b0101111), ("wrapped", 0b0111011), ("half", 0b1000010)],
+                         ids=["three-no-phiref-lnD", "wrapped-no-psi-lnD", "half-dec-lnD"])
+def test_mixture_is_over_sampled_rows(ile, oracle_mod, name, rows):
+    """The weights of a likelihood marginalised over the rows left out: the
+    components sample the masked rows, the others are prior draws."""
+    print(f"mixture {name} rows={rows:07b}", flush=True)
+    args, got = _run(ile, oracle_mod, name, 3000, 17 + rows)
+    _compare(oracle_mod, args, got)
 
 
 def test_mixture_is_full_size_sampled(ile, oracle_mod):
@@ -273,3 +286,92 @@ def test_mixture_is_lnZ_end_to_end(ile, oracle_mod):
     k_is, k_pr = _kish(l_or + want_w), _kish(lp)
     assert k_is > 300 and k_pr > 300, (k_is, k_pr)
     assert abs(z_or - z_prior) < 5 * np.sqrt(1 / k_is + 1 / k_pr), (z_or, z_prior, k_is, k_pr)
+
+
+def _kmeans(X, k, iters=50, seed=0):
+    rng = np.random.default_rng(seed)
+    C = X[rng.choice(len(X), k, replace=False)]
+    for _ in range(iters):
+        lab = ((X[:, None, :] - C[None]) ** 2).sum(-1).argmin(1)
+        for j in range(k):
+            if np.any(lab == j):
+                C[j] = X[lab == j].mean(0)
+    return lab
+
+
+def test_mixture_is_distance_marginalised_multimode(ile, oracle_mod):
+    """SNR 12, the likelihood marginalised over distance in the kernel
+    (rift_ile_plan_lnZ_dmarg), and one component per mode: k-means clusters
+    of the best pilot draws (host logic, as a sampler's), each fitted by the
+    device moments over the six sampled rows.  The IS estimate agrees with
+    brute-force prior Monte Carlo of 1e8 draws (drawn by rift_ile_mixture_is
+    with alpha = 1) within five joint standard errors, each side's relative
+    error about 1 / sqrt(its Kish size)."""
+    import torch
+
+    box = BOX
+    pt = synth.make_point(3, 9, 2000, 16384.0, 12.0, 61)
+    N = 2_000_000
+    plan = ile.Plan([pt], [N])
+    ll = torch.empty(N, dtype=torch.float64, device="cuda")
+    zeros = torch.zeros(N, dtype=torch.float64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    m_run, s_run, s2_run, pilot = -np.inf, 0.0, 0.0, None
+    for it in range(50):
+        v = torch.rand((7, N), dtype=torch.float64, device="cuda", generator=gen)
+        th, _, _, _ = ile.mixture_is(1.0, [], None, None, 1.0, box, v, v, zeros)
+        plan.lnZ_dmarg(th, box[2], box[3], 20, lnL_out=ll)
+        lm = float(ll.max())
+        w = torch.exp(ll - lm)
+        s1, s2 = float(w.sum()), float((w * w).sum())
+        m = max(m_run, lm)
+        s_run = s_run * np.exp(m_run - m) + s1 * np.exp(lm - m)
+        s2_run = s2_run * np.exp(2 * (m_run - m)) + s2 * np.exp(2 * (lm - m))
+        m_run = m
+        if pilot is None:
+            pilot = (th.cpu().numpy(), ll.cpu().numpy())
+    z_prior = m_run + np.log(s_run / (50 * N))
+    k_prior = s_run ** 2 / s2_run
+    thp, lp = pilot
+    best = np.argsort(lp)[-8000:]
+    c = thp[:, best].copy()
+    c[3] = np.cos(c[3])
+    c[6] = np.log(c[6])
+    lb = lp[best]
+    feats = np.stack([np.cos(c[0]) * np.cos(c[1]), np.sin(c[0]) * np.cos(c[1]), np.sin(c[1]), np.cos(c[4]),
+                      np.sin(c[4]), np.cos(2 * c[2]), np.sin(2 * c[2]), c[3]], 1)
+    lab = _kmeans(feats, 4)
+    means, covs, a = [], [], []
+    for j in range(4):
+        sel = lab == j
+        cj = c[:, sel].copy()
+        for r, P in PERIODIC:  # unwrap the cluster around its circular mean
+            mu = np.arctan2(np.sin(2 * np.pi * cj[r] / P).mean(), np.cos(2 * np.pi * cj[r] / P).mean()) * P / (2 * np.pi)
+            cj[r] = mu + ((cj[r] - mu + P / 2) % P) - P / 2
+        m, C = ile.moments(_dev(cj), _dev(0.5 * (lb[sel] - lb[sel].max())))
+        C = C.cpu().numpy()
+        f = np.ones(7)
+        for r, P in PERIODIC:
+            f[r] = min(1.0, 0.45 * P / np.sqrt(2.0 * C[r, r]))
+        means.append(m.cpu().numpy())
+        covs.append(f[:, None] * C * f[None, :])
+        a.append(np.exp(lb[sel] - lb.max()).sum())
+    a = np.array(a) / np.sum(a)
+    gen.manual_seed(7)
+    z = torch.randn((7, N), dtype=torch.float64, device="cuda", generator=gen)
+    v = torch.rand((7, N), dtype=torch.float64, device="cuda", generator=gen)
+    u = torch.rand(N, dtype=torch.float64, device="cuda", generator=gen)
+    th, lnw, comp, st = ile.mixture_is(0.1, a, _dev(np.array(means)), _dev(np.array(covs)), 2.0, box, z, v, u,
+                                       rows=0b0111111)
+    assert int(st.cpu()[0]) == 0
+    zi, _ = plan.lnZ_dmarg(th, box[2], box[3], 20, lnw=lnw, lnL_out=ll)
+    z_is = float(zi.cpu()[0])
+    t = (ll + lnw).cpu().numpy()
+    t = t[np.isfinite(t)]
+    w = np.exp(t - t.max())
+    k_is = w.sum() ** 2 / np.sum(w * w)
+    plan.close()
+    print(f"IS {z_is:.4f} (Kish {k_is:.0f}) prior MC {z_prior:.4f} (Kish {k_prior:.0f})", flush=True)
+    assert k_is > 30 and k_prior > 10, (k_is, k_prior)
+    assert abs(z_is - z_prior) < 5 * np.sqrt(1 / k_is + 1 / k_prior), (z_is, z_prior, k_is, k_prior)
