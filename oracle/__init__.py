@@ -17,7 +17,8 @@ polarisation marginal, Eqs. (ap:psiexp), (ap:psilaplace)), ``hmc_step``
 (a Metropolis-adjusted Hamiltonian transition on the gradient, optionally
 on the tempered target) and the SMC ladder's ``smc_cess``, ``smc_next_beta``,
 ``smc_update`` and ``systematic_resample`` (Eq. (sampler-menu:smc-update)),
-and the importance-sampling normalisation with a defensive Gaussian-mixture
+the cloud's random-walk Metropolis move (``rwm_step``), and the
+importance-sampling normalisation with a defensive Gaussian-mixture
 proposal (``cloud_moments``, ``mixture_is``, Eq. (sampler-menu:is)) are
 written here in numpy on top of the C likelihood.
 
@@ -848,6 +849,46 @@ def nuts_step(pt, c0, z, dirs, merges, leaves, sigma, eps, max_depth, t_min, t_m
                                       max_depth)
         out[:, i], ll[i], dep[i], st[i], dv[i] = c, l, dd, ss, vv
     return out, ll, dep, st, dv
+
+
+def rwm_chain(log_target, c0, z, u, cov, scale, l0=None):
+    """One random-walk Metropolis move per column (the move of the adaptive
+    cloud after resampling, Sec. "Mode coverage, adaptive clouds, and
+    evidence": a proposal covariance estimated from the cloud): c' = c + L z
+    with L L^T = scale cov (Cholesky), accepted when ln u < ln pi(c') -
+    ln pi(c); a NaN or -inf target at c' rejects.  log_target(c) -> [n];
+    l0: ln pi at c0 if known.  Returns (c, ln pi, accepted)."""
+    c0 = np.asarray(c0, np.float64)
+    L = np.linalg.cholesky(scale * np.asarray(cov, np.float64))
+    c1 = c0 + L @ np.asarray(z, np.float64)
+    t0 = log_target(c0) if l0 is None else np.asarray(l0, np.float64)
+    t1 = log_target(c1)
+    with np.errstate(invalid="ignore"):
+        acc = np.log(np.asarray(u, np.float64)) < t1 - t0
+    acc &= np.isfinite(t1)
+    return np.where(acc, c1, c0), np.where(acc, t1, t0), acc
+
+
+def rwm_step(pt, c0, z, u, cov, scale, t_min, t_max, d_min, d_max, lnL0, beta=1.0):
+    """The move on the tempered target L^beta p of Eq.
+    (sampler-menu:tempered-target) in the sampler coordinates (the prior of
+    hmc_log_prior; a proposal outside its box is rejected): accepted when
+    ln u < beta (lnL' - lnL) + ln p(c') - ln p(c), with L^0 = 1.  lnL0: lnL at
+    c0.  Returns (c, lnL, accepted)."""
+    c0 = np.asarray(c0, np.float64)
+    lnL0 = np.asarray(lnL0, np.float64)
+    L = np.linalg.cholesky(scale * np.asarray(cov, np.float64))
+    c1 = c0 + L @ np.asarray(z, np.float64)
+    lp0 = hmc_log_prior(c0, t_min, t_max, d_min, d_max)
+    lp1 = hmc_log_prior(c1, t_min, t_max, d_min, d_max)
+    inside = np.isfinite(lp1)
+    l1 = np.full(c0.shape[1], np.nan)
+    if inside.any():
+        l1[inside] = lnL(pt, _to_physical(c1[:, inside]))
+    with np.errstate(invalid="ignore"):
+        d = (0.0 if beta == 0.0 else beta * (l1 - lnL0)) + lp1 - lp0
+        acc = inside & (np.log(np.asarray(u, np.float64)) < d)
+    return np.where(acc, c1, c0), np.where(acc, l1, lnL0), acc
 
 
 def _lse(v):

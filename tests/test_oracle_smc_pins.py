@@ -13,7 +13,11 @@ moves, against what the mathematics fixes:
 * systematic resampling draws every index floor(N W) or ceil(N W) times, in
   order, and is the identity for equal weights;
 * the tempered potential's gradient is the derivative of the tempered
-  potential, and at beta = 0 only the prior remains.
+  potential, and at beta = 0 only the prior remains;
+* the cloud's random-walk Metropolis move keeps a correlated Gaussian
+  target under a mismatched proposal; its increments have covariance
+  scale C; a ratio of 1 is always taken and a NaN target never; at beta = 0
+  it is the prior's Metropolis move and at beta = 1 the move on L p.
 """
 import numpy as np
 
@@ -116,3 +120,72 @@ def test_tempered_potential(oracle_mod):
     _, U0, g0 = oracle_mod.hmc_potential(pt, c, *box, beta=0.0)
     assert np.array_equal(U0, -lp)
     assert np.all(g0[[0, 2, 3, 4, 5]] == 0) and np.allclose(g0[1], np.tan(c[1])) and np.all(g0[6] == -3.0)
+
+
+def _gauss_target(scale):
+    scale = np.asarray(scale, np.float64)
+    return lambda c: -0.5 * np.sum((np.asarray(c) / scale[:, None]) ** 2, axis=0)
+
+
+def test_rwm_leaves_a_gaussian_invariant(oracle_mod):
+    """The cloud's random-walk Metropolis move keeps its target: exact draws
+    of a correlated Gaussian, three moves each with a proposal covariance that
+    does not match, keep their mean and variance within sampling error."""
+    rng = np.random.default_rng(21)
+    n = 6000
+    A = rng.normal(size=(7, 7)) * 0.3 + np.eye(7)
+    Sig = A @ A.T
+    Li = np.linalg.inv(np.linalg.cholesky(Sig))
+    logpi = (lambda c: -0.5 * np.sum((Li @ np.asarray(c)) ** 2, axis=0))
+    c = np.linalg.cholesky(Sig) @ rng.normal(size=(7, n))
+    prop = np.diag(np.diag(Sig))  # the diagonal only: a mismatched proposal
+    acc_all = []
+    for _ in range(3):
+        c, _, acc = oracle_mod.rwm_chain(logpi, c, rng.normal(size=(7, n)), rng.uniform(size=n), prop, 2.38 ** 2 / 7)
+        acc_all.append(acc.mean())
+    assert 0.1 < np.mean(acc_all) < 0.9
+    w = Li @ c  # whitened: unit normal if the target is kept
+    assert np.all(np.abs(w.mean(axis=1)) < 4.0 / np.sqrt(n)), w.mean(axis=1)
+    assert np.all(np.abs(w.var(axis=1) - 1.0) < 4.0 * np.sqrt(2.0 / n)), w.var(axis=1)
+
+
+def test_rwm_proposal_and_decisions(oracle_mod):
+    """The proposal's increments have covariance scale C (a transposed
+    Cholesky factor fails on a correlated C); a move whose target ratio is 1
+    is always taken, one to a NaN or -inf target never; at beta = 0 the
+    tempered move on the likelihood is the prior's Metropolis move."""
+    rng = np.random.default_rng(22)
+    n = 40000
+    C = np.eye(7) * 0.04
+    C[0, 2] = C[2, 0] = 0.03
+    flat = (lambda c: np.zeros(np.asarray(c).shape[1]))
+    c0 = np.zeros((7, n))
+    c1, _, acc = oracle_mod.rwm_chain(flat, c0, rng.normal(size=(7, n)), rng.uniform(size=n), C, 0.5)
+    assert acc.all()
+    S = np.cov(c1)
+    assert abs(S[0, 2] - 0.5 * 0.03) < 5 * np.sqrt((0.02 * 0.02 + 0.015 ** 2) / n)
+    assert abs(S[0, 0] - 0.02) < 5 * 0.02 * np.sqrt(2.0 / n)
+    nan_t = (lambda c: np.where(np.asarray(c)[0] == 0.0, 0.0, np.nan))
+    _, _, acc = oracle_mod.rwm_chain(nan_t, c0[:, :100], rng.normal(size=(7, 100)), rng.uniform(size=100), C, 1.0)
+    assert not acc.any()
+    # beta = 0 on the likelihood: the decision is the prior ratio alone
+    pt = synth.make_point(2, 4, 2000, 16384.0, 50.0, 23)
+    th, _ = synth.weighted_samples(400, 24)
+    c = th.copy()
+    c[3] = np.cos(c[3])
+    c[6] = np.log(c[6])
+    box = (-0.01, 0.01, 10.0, 1000.0)
+    l0 = oracle_mod.lnL(pt, th)
+    z, u = rng.normal(size=(7, 400)), rng.uniform(size=400)
+    got_c, got_l, got_a = oracle_mod.rwm_step(pt, c, z, u, C * 0.01, 1.0, *box, l0, beta=0.0)
+    lp = (lambda x: oracle_mod.hmc_log_prior(x, *box))
+    want_c, _, want_a = oracle_mod.rwm_chain(lp, c, z, u, C * 0.01, 1.0)
+    assert np.array_equal(got_a, want_a) and np.array_equal(got_c, want_c)
+    # and beta = 1 is the Metropolis move on L p
+    got_c, got_l, got_a = oracle_mod.rwm_step(pt, c, z, u, C * 0.01, 1.0, *box, l0, beta=1.0)
+    post = (lambda x: np.where(np.isfinite(lp(x)),
+                               oracle_mod.lnL(pt, oracle_mod._to_physical(np.where(np.isfinite(lp(x)), x, c)))
+                               + lp(x), -np.inf))
+    want_c, _, want_a = oracle_mod.rwm_chain(post, c, z, u, C * 0.01, 1.0)
+    assert np.array_equal(got_a, want_a)
+    assert 0.05 < got_a.mean() < 0.95
