@@ -1005,15 +1005,72 @@ def extra_smc(ile, synth, torch, steps, particles=65536, cpu=True):
                 acc_sum += float(acc.double().mean().item())
         return beta, lnZ, rungs, acc_sum / max(1, 2 * rungs)
 
+    def ladder_rwm(moves=4):
+        """The same ladder with the paper's moves: after resampling, random-walk
+        Metropolis with the proposal covariance (2.38^2 / 7) C of the cloud,
+        C from the device moments."""
+        c = torch.as_tensor(th, device="cuda").contiguous()
+        c2 = torch.empty_like(c)
+        lnL = torch.empty(n, dtype=torch.float64, device="cuda")
+        g = torch.empty((7, n), dtype=torch.float64, device="cuda")
+        plan.grad(0, c, lnL_out=lnL, grad_out=g, coords="sampler")
+        l2 = torch.empty_like(lnL)
+        lnW = torch.zeros(n, dtype=torch.float64, device="cuda")
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        beta, lnZ, rungs, acc_sum = 0.0, 0.0, 0, 0.0
+        while beta < 1.0 and rungs < 200:
+            ile.smc_reweight(lnL, lnW, beta, 0.5, out=out)
+            o = out.cpu().numpy()
+            beta, lnZ, rungs = float(o[0]), lnZ + float(o[1]), rungs + 1
+            u = float(torch.rand(1, generator=gen, device="cuda").item())
+            anc = torch.empty(n, dtype=torch.int64, device="cuda")
+            ile.smc_resample(lnW, u, c, c2, anc)
+            torch.index_select(lnL, 0, anc, out=l2)
+            c, c2, lnL, l2 = c2, c, l2, lnL
+            lnW.zero_()
+            _, cov = ile.moments(c)
+            for _ in range(moves):
+                z = torch.randn((7, n), dtype=torch.float64, device="cuda", generator=gen)
+                uu = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+                acc, _ = plan.rwm(0, c, z, uu, cov, 2.38 ** 2 / 7, box, lnL, beta=beta)
+                acc_sum += float(acc.double().mean().item())
+        return beta, lnZ, rungs, acc_sum / max(1, moves * rungs)
+
     ladder()  # warm
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     beta, lnZ, rungs, acc = ladder()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # the same normalisation by prior Monte Carlo on 1e6 fresh prior draws
-    thp = synth.prior_samples(4_000_000, 6)
-    zp, nep = ile.lnZ([pt], thp)
+    ladder_rwm()  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    beta_r, lnZ_r, rungs_r, acc_r = ladder_rwm()
+    torch.cuda.synchronize()
+    wall_r = time.perf_counter() - t0
+    # the same normalisation by brute-force prior Monte Carlo: 4e9 prior draws
+    # (rift_ile_mixture_is with alpha = 1) in chunks of 4e6
+    Nc = 4_000_000
+    gref = torch.Generator(device="cuda")
+    gref.manual_seed(3)
+    zeros = torch.zeros(Nc, dtype=torch.float64, device="cuda")
+    m_run, s_run, s2_run = -np.inf, 0.0, 0.0
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter()
+    for _ in range(1000):
+        vv = torch.rand((7, Nc), dtype=torch.float64, device="cuda", generator=gref)
+        thr, _, _, _ = ile.mixture_is(1.0, [], None, None, 1.0, box, vv, vv, zeros)
+        _, _, llr = ile.lnZ([pt], thr, want_lnL=True)
+        lm = float(llr.max())
+        w = torch.exp(llr - lm)
+        s1, s2 = float(w.sum()), float((w * w).sum())
+        m = max(m_run, lm)
+        s_run = s_run * np.exp(m_run - m) + s1 * np.exp(lm - m)
+        s2_run = s2_run * np.exp(2 * (m_run - m)) + s2 * np.exp(2 * (lm - m))
+        m_run = m
+    torch.cuda.synchronize()
+    ref_s = time.perf_counter() - t_ref
+    del vv, thr, llr, w, zeros
     # the reweight alone at this size
     lnLt = torch.as_tensor(-0.5 * 40.0 * np.random.default_rng(1).chisquare(3, n), device="cuda")
     lnWt = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -1022,8 +1079,12 @@ def extra_smc(ile, synth, torch, steps, particles=65536, cpu=True):
     return {"workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 5; 65536 particles from the "
                         "prior; adaptive SMC ladder (target fraction 0.5), 2 tempered HMC moves per rung",
             "rungs": rungs, "ladder_ms": 1e3 * wall, "ms_per_rung": 1e3 * wall / max(1, rungs),
-            "final_beta": beta, "lnZ_smc": lnZ, "lnZ_prior_mc_4e6": float(zp[0]), "neff_prior_mc": float(nep[0]),
-            "move_acceptance": acc, "reweight_ms": 1e3 * secs / 10}
+            "final_beta": beta, "lnZ_smc": lnZ, "lnZ_prior_mc_4e9": float(m_run + np.log(s_run / (1000 * Nc))),
+            "kish_prior_mc_4e9": s_run ** 2 / s2_run, "prior_mc_4e9_s": ref_s,
+            "move_acceptance": acc, "reweight_ms": 1e3 * secs / 10,
+            "rwm_moves": {"moves_per_rung": 4, "rungs": rungs_r, "ladder_ms": 1e3 * wall_r,
+                          "ms_per_rung": 1e3 * wall_r / max(1, rungs_r), "final_beta": beta_r, "lnZ_smc": lnZ_r,
+                          "move_acceptance": acc_r}}
 
 
 def extra_is(ile, synth, torch, steps, draws=1_000_000, cpu=True):

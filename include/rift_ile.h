@@ -566,6 +566,28 @@ int rift_ile_smc_reweight(int64_t n, const double *lnL, double *lnW, double beta
 int rift_ile_smc_resample(int64_t n, const double *lnW, double u, const double *theta_in, double *theta_out,
                           int64_t *ancestors, void *stream);
 
+/* The adaptive cloud's random-walk Metropolis move after resampling (Sec.
+ * "Mode coverage, adaptive clouds, and evidence": a proposal covariance
+ * estimated from the current cloud), one per chain, on the tempered target
+ * L^beta p of Eq. (sampler-menu:tempered-target) in the sampler coordinates
+ * (ra, dec, psi, cos incl, phiref, tref, ln dist): the proposal
+ * c' = c + L z with L L^T = scale cov (Cholesky on the device), accepted when
+ * ln u < beta (lnL(c') - lnL(c)) + ln p(c') - ln p(c) with L^0 = 1 and p the
+ * prior of rift_ile_plan_hmc (a proposal outside its box, or a NaN, is
+ * rejected).  lnL(c') comes from the plan's point `point`.
+ * theta: DEVICE [7][n] chain states (updated where accepted); z: DEVICE
+ * [7][n] standard normals; u: DEVICE [n] uniforms in (0, 1); cov: DEVICE
+ * [7][7] symmetric (the lower triangle is read; e.g. rift_ile_moments of the
+ * cloud); lnL: DEVICE [n], lnL at the states on entry and at the returned
+ * states on exit; accepted: DEVICE int32 [n] or NULL; status: DEVICE int32
+ * [1] or NULL, 0, or 1 when scale cov is not positive definite (then no
+ * chain moves).  RIFT_EINVAL: n < 0, beta outside [0, 1], scale not finite
+ * and > 0, an empty box or d_min <= 0, null or misaligned pointers.  Enqueues
+ * and returns; stream-ordered scratch of 120 n + 256 bytes. */
+int rift_ile_plan_rwm(rift_ile_plan plan, int32_t point, int64_t n, double *theta, const double *z, const double *u,
+                      const double *cov, double scale, const rift_ile_hmc_prior *prior, double beta, double *lnL,
+                      int32_t *accepted, int32_t *status, void *stream);
+
 /* Weighted mean and covariance of a cloud of states (the moments that fit one
  * component of the proposal below; Sec. "Mode coverage, adaptive clouds, and
  * evidence"): with W_i the weights e^{lnw_i} normalised over the cloud (equal

@@ -667,7 +667,113 @@ __global__ void k_resample_pick(int64_t n, const double* __restrict__ C, double 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The cloud's random-walk Metropolis move (after resampling, with a proposal
+// covariance estimated from the cloud): c' = c + L z, L L^T = scale C.
+
+// One thread: the Cholesky factor of scale C (lower, packed by rows) into L;
+// status 0, or 1 when scale C is not positive definite or not finite.
+__global__ void k_rwm_setup(const double* __restrict__ cov, double scale, double* __restrict__ L,
+                            int32_t* __restrict__ status, int32_t* __restrict__ user) {
+  if (threadIdx.x != 0) return;
+  bool ok = true;
+  double F[28];
+  for (int r = 0; r < 7; ++r)
+    for (int q = 0; q <= r; ++q) {
+      double v = scale * cov[r * 7 + q];
+      for (int k = 0; k < q; ++k) v -= F[r * (r + 1) / 2 + k] * F[q * (q + 1) / 2 + k];
+      if (q == r) {
+        ok = ok && v > 0.0 && v < __builtin_inf();
+        F[r * (r + 1) / 2 + r] = sqrt(v);
+      } else {
+        F[r * (r + 1) / 2 + q] = v / F[q * (q + 1) / 2 + q];
+      }
+    }
+  for (int k = 0; k < 28; ++k) L[k] = ok ? F[k] : 0.0;
+  status[0] = ok ? 0 : 1;
+  if (user) user[0] = status[0];
+}
+
+__global__ void k_rwm_propose(int64_t n, const double* __restrict__ c, const double* __restrict__ z,
+                              const double* __restrict__ L, double* __restrict__ c1) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double zz[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) zz[a] = z[a * n + i];
+#pragma unroll
+    for (int r = 0; r < 7; ++r) {
+      double x = c[r * n + i];
+#pragma unroll
+      for (int k = 0; k <= r; ++k) x += L[r * (r + 1) / 2 + k] * zz[k];
+      c1[r * n + i] = x;
+    }
+  }
+}
+
+// Accepted when ln u < beta (lnL' - lnL) + ln p(c') - ln p(c) (L^0 = 1); a
+// proposal outside the prior's box, a NaN, or a refused factor rejects.
+__global__ void k_rwm_accept(int64_t n, double* __restrict__ c, const double* __restrict__ c1,
+                             const double* __restrict__ l1, double* __restrict__ lnL, const double* __restrict__ u,
+                             double beta, HmcPrior P, const int32_t* __restrict__ status,
+                             int32_t* __restrict__ accepted) {
+  const bool refused = status[0] != 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double lp0 = hmc_log_prior(P, c[n + i], c[3 * n + i], c[5 * n + i], c[6 * n + i]);
+    const double lp1 = hmc_log_prior(P, c1[n + i], c1[3 * n + i], c1[5 * n + i], c1[6 * n + i]);
+    const double l0 = lnL[i], ln1 = l1[i];
+    const double d = (beta == 0.0 ? 0.0 : beta * (ln1 - l0)) + lp1 - lp0;
+    const bool acc = !refused && lp1 != -__builtin_inf() && log(u[i]) < d;
+    if (acc) {
+#pragma unroll
+      for (int a = 0; a < 7; ++a) c[a * n + i] = c1[a * n + i];
+      lnL[i] = ln1;
+    }
+    if (accepted) accepted[i] = acc ? 1 : 0;
+  }
+}
+
 }  // namespace
+
+extern "C" int rift_ile_plan_rwm(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
+                                 const double* u, const double* cov, double scale, const rift_ile_hmc_prior* prior,
+                                 double beta, double* lnL, int32_t* accepted, int32_t* status, void* stream) {
+  if (!plan || n < 0 || !prior) return RIFT_EINVAL;
+  if (!(beta >= 0.0 && beta <= 1.0)) return RIFT_EINVAL;
+  if (!(scale > 0.0) || !std::isfinite(scale)) return RIFT_EINVAL;
+  if (!std::isfinite(prior->t_min) || !std::isfinite(prior->t_max) || !(prior->t_max > prior->t_min)) return RIFT_EINVAL;
+  if (!(prior->d_min > 0.0) || !(prior->d_max > prior->d_min) || !std::isfinite(prior->d_max)) return RIFT_EINVAL;
+  auto bad = [](const void* q) { return !q || (((uintptr_t)q) & 7u); };
+  if (bad(cov) || (status && (((uintptr_t)status) & 3u))) return RIFT_EINVAL;
+  if (n > 0 && (bad(theta) || bad(z) || bad(u) || bad(lnL) || (accepted && (((uintptr_t)accepted) & 3u))))
+    return RIFT_EINVAL;
+  HmcPrior P;
+  P.t_min = prior->t_min;
+  P.t_max = prior->t_max;
+  P.lnd_min = log(prior->d_min);
+  P.lnd_max = log(prior->d_max);
+  hipStream_t st = (hipStream_t)stream;
+  // stream-ordered scratch: the factor and status, then c', g [7][n] and lnL' [n]
+  double* w = nullptr;
+  if (hipMallocAsync((void**)&w, sizeof(double) * (32 + 15 * (size_t)n), st) != hipSuccess) return RIFT_ENOMEM;
+  double* L = w;
+  int32_t* stat = (int32_t*)(w + 28);
+  double *c1 = w + 32, *g = c1 + 7 * n, *l1 = g + 7 * n;
+  hipLaunchKernelGGL(k_rwm_setup, dim3(1), dim3(64), 0, st, cov, scale, L, stat, status);
+  int rc = RIFT_OK;
+  if (n > 0) {
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    constexpr int coords = RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST;
+    hipLaunchKernelGGL(k_rwm_propose, dim3(grid), dim3(256), 0, st, n, (const double*)theta, z, (const double*)L,
+                       c1);
+    rc = rift_ile_plan_grad(plan, point, n, c1, coords, l1, g, stream);
+    if (!rc)
+      hipLaunchKernelGGL(k_rwm_accept, dim3(grid), dim3(256), 0, st, n, theta, (const double*)c1,
+                         (const double*)l1, lnL, u, beta, P, (const int32_t*)stat, accepted);
+  }
+  if (!rc && hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
+  if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
+  return rc;
+}
 
 extern "C" int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
                                   const double* dirs, const double* merges, const double* leaves, const double* sigma,

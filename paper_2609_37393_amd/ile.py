@@ -69,6 +69,7 @@ EXPORTS = (
     "rift_ile_plan_lnZ_tband",
     "rift_ile_plan_lnZ_erai",
     "rift_ile_moments",
+    "rift_ile_plan_rwm",
     "rift_ile_mixture_is",
     "rift_ile_plan_hmc_tempered",
     "rift_ile_smc_reweight",
@@ -207,6 +208,8 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_smc_reweight.argtypes = [i64, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
     lib.rift_ile_smc_resample.argtypes = [i64, vp, ctypes.c_double, vp, vp, vp, vp]
     lib.rift_ile_moments.argtypes = [i64, vp, vp, vp, vp, vp]
+    lib.rift_ile_plan_rwm.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(CHmcPrior),
+                                      ctypes.c_double, vp, vp, vp, vp]
     lib.rift_ile_mixture_is.argtypes = [i64, ctypes.POINTER(CMixture), ctypes.POINTER(CHmcPrior), vp, vp, vp, vp,
                                         vp, vp, vp, vp]
     lib.rift_ile_strerror.argtypes = [ctypes.c_int]
@@ -692,6 +695,21 @@ class Plan:
                                            int(max_depth), ctypes.byref(pr), float(beta), l.data_ptr(),
                                            inf.data_ptr(), _stream(self.device)), "rift_ile_plan_nuts")
         return l, inf
+
+    def rwm(self, point, theta, z, u, cov, scale, box, lnL, beta=1.0, accepted_out=None, status_out=None):
+        """One random-walk Metropolis move per chain with proposal covariance
+        scale cov (rift_ile_plan_rwm); theta [7, n] in the sampler
+        coordinates and lnL [n] (lnL at the states) are updated in place.
+        Returns (accepted int32 [n], status int32 [1])."""
+        n = theta.shape[1]
+        acc = accepted_out if accepted_out is not None else torch.empty(n, dtype=torch.int32, device=self.device)
+        st = status_out if status_out is not None else torch.empty(1, dtype=torch.int32, device=self.device)
+        pr = CHmcPrior(*[float(x) for x in box])
+        ptr = (lambda t: t.data_ptr() if n else None)
+        _check(self.lib.rift_ile_plan_rwm(self.handle, int(point), n, ptr(theta), ptr(z), ptr(u), cov.data_ptr(),
+                                          float(scale), ctypes.byref(pr), float(beta), ptr(lnL), ptr(acc),
+                                          st.data_ptr(), _stream(self.device)), "rift_ile_plan_rwm")
+        return acc, st
 
     def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):
         """Gradient of lnL with theta rows 3 and 6 in the coordinates `coords`

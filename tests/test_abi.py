@@ -266,6 +266,23 @@ def test_importance_arguments(lib):
         == EINVAL
 
 
+def test_rwm_arguments(lib):
+    from paper_2609_37393_amd import ile
+
+    box = ile.CHmcPrior(-0.01, 0.01, 10.0, 1000.0)
+    fake = 0x1000  # never dereferenced on these paths
+
+    def call(plan=fake, n=4, cov=fake, scale=0.5, prior=box, beta=1.0, lnL=fake, acc=None, status=None):
+        return lib.rift_ile_plan_rwm(plan, 0, n, fake, fake, fake, cov, scale,
+                                     None if prior is None else ctypes.byref(prior), beta, lnL, acc, status, None)
+
+    assert call(plan=None) == EINVAL and call(n=-1) == EINVAL and call(cov=None) == EINVAL
+    assert call(scale=0.0) == EINVAL and call(scale=float("nan")) == EINVAL
+    assert call(beta=-0.5) == EINVAL and call(beta=2.0) == EINVAL and call(prior=None) == EINVAL
+    assert call(prior=ile.CHmcPrior(0.01, -0.01, 10.0, 1000.0)) == EINVAL
+    assert call(lnL=None) == EINVAL and call(acc=0x1002) == EINVAL and call(status=0x1001) == EINVAL
+
+
 def test_tband_null_plan(lib):
     from paper_2609_37393_amd import ile
 

@@ -16,7 +16,12 @@ Bars (written here):
   level); the gathered states are the ancestors' columns bit for bit;
 * tempered HMC: as the untempered transition's test (states to 1e-6 sigma,
   decisions exact away from the threshold), and beta = 1 bit for bit equal
-  to rift_ile_plan_hmc.
+  to rift_ile_plan_hmc;
+* the random-walk Metropolis move (rift_ile_plan_rwm): decisions exact
+  wherever ln u lies more than 1e-6 (1 + |d|) from the log ratio d (the
+  likelihood's FP64 bar times beta, far below that); accepted states within
+  1e-13 (|c| + sum |L z|) of the oracle's proposal, rejected ones and their
+  lnL bit for bit; accepted lnL within the FP64 bar of the oracle's.
 """
 import numpy as np
 import pytest
@@ -180,4 +185,52 @@ def test_tempered_hmc_matches_oracle(ile, oracle_mod):
     assert torch.equal(t1, t2) and torch.equal(l1, l2) and torch.equal(a1, a2)
     with pytest.raises(RuntimeError):
         plan.hmc(0, _dev(c0), _dev(z), _dev(u), SIG, 0.3, 6, BOX, beta=1.5)
+    plan.close()
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.3, 1.0])
+def test_rwm_matches_oracle(ile, oracle_mod, beta):
+    import torch
+
+    pt = synth.make_point(3, 9, 6554, 32768.0, 100.0, 41)
+    n = 400
+    c0 = _chains(oracle_mod, pt, n, 52)
+    l0 = oracle_mod.lnL(pt, oracle_mod._to_physical(c0))
+    C = np.cov(c0) * 4.0 + np.diag([1e-8, 1e-8, 1e-6, 1e-6, 1e-6, 1e-12, 1e-6])
+    rng = np.random.default_rng(int(10 * beta) + 5)
+    z, u = rng.normal(size=c0.shape), rng.uniform(size=n)
+    print(f"rwm beta={beta}", flush=True)
+    want_c, want_l, want_a = oracle_mod.rwm_step(pt, c0, z, u, C, 0.8, *BOX, l0, beta=beta)
+    plan = ile.Plan([pt], [n])
+    tc, tl = _dev(c0), _dev(l0)
+    acc, st = plan.rwm(0, tc, _dev(z), _dev(u), _dev(C), 0.8, BOX, tl, beta=beta)
+    got_c, got_l, got_a = tc.cpu().numpy(), tl.cpu().numpy(), acc.cpu().numpy().astype(bool)
+    assert int(st.cpu()[0]) == 0
+    # the oracle's log ratio, to leave out decisions at the threshold
+    L = np.linalg.cholesky(0.8 * C)
+    c1 = c0 + L @ z
+    lp0, lp1 = oracle_mod.hmc_log_prior(c0, *BOX), oracle_mod.hmc_log_prior(c1, *BOX)
+    l1 = np.full(n, np.nan)
+    ins = np.isfinite(lp1)
+    l1[ins] = oracle_mod.lnL(pt, oracle_mod._to_physical(c1[:, ins]))
+    d = (0.0 if beta == 0.0 else beta * (l1 - l0)) + lp1 - lp0
+    firm = ~ins | (np.abs(np.log(u) - d) > 1e-6 * (1 + np.abs(d)))
+    assert firm.sum() >= n - 3
+    assert np.array_equal(got_a[firm], want_a[firm])
+    assert 0 < want_a.sum() < n
+    rej = ~got_a
+    assert np.array_equal(got_c[:, rej], c0[:, rej]) and np.array_equal(got_l[rej], l0[rej])
+    ok = got_a & firm
+    bound = 1e-13 * (np.abs(c0) + np.abs(L) @ np.abs(z)) + 1e-300
+    assert np.all(np.abs(got_c[:, ok] - want_c[:, ok]) <= bound[:, ok])
+    _, g = oracle_mod.grad(pt, oracle_mod._to_physical(want_c[:, ok]))
+    bar = 1e-9 * (1.0 + np.abs(want_l[ok])) + 1e-12 * np.sum(np.abs(g) * np.abs(want_c[:, ok]), axis=0)
+    assert np.all(np.abs(got_l[ok] - want_l[ok]) <= bar)
+    # a factor that does not exist moves nothing
+    bad = C.copy()
+    bad[0, 0] = -1.0
+    tc2, tl2 = _dev(c0), _dev(l0)
+    acc2, st2 = plan.rwm(0, tc2, _dev(z), _dev(u), _dev(bad), 0.8, BOX, tl2, beta=beta)
+    assert int(st2.cpu()[0]) == 1 and not acc2.any()
+    assert torch.equal(tc2, _dev(c0)) and torch.equal(tl2, _dev(l0))
     plan.close()
