@@ -11,7 +11,7 @@ with its error statement.
 
     python bench.py [--steps K] [--warmup W] [--extras] [--no-cpu]
 
-Prints ONE JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N > 1 exits: this library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -56,7 +56,7 @@ def basis_count(L):
 
 
 def flops_per_sample(K, M, lmax):
-    """Flops of one lnL evaluation as this build computes it (FMA = 2; the
+    """Flops of one lnL evaluation as this library computes it (FMA = 2; the
     model-norm term as the harmonic-basis contraction), transcendentals (5
     sincos) not included.  Reported beside the algorithmic count."""
     L = lclass(lmax)
@@ -1277,7 +1277,7 @@ def main():
     global WARM_S
     WARM_S = max(0.0, args.warm_s)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
                                    "design only)", "n_gpus": args.gpus}))
         sys.exit(2)
 

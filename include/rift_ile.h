@@ -76,7 +76,7 @@ typedef enum {
   RIFT_EINVAL = -1,      /* bad argument (null pointer, size or mode out of range) */
   RIFT_EDEVICE = -2,     /* a HIP runtime call failed */
   RIFT_ENOMEM = -3,      /* device or host allocation failed */
-  RIFT_EUNSUPPORTED = -4, /* valid request this build does not implement */
+  RIFT_EUNSUPPORTED = -4, /* valid request this library does not implement */
   RIFT_ESCRATCH = -5      /* rift_ile_lnZ_noalloc: the request needs more device memory than
                              its fixed scratch (RIFT_ILE_NOALLOC_SCRATCH_BYTES) */
 } rift_status;

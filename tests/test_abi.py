@@ -103,7 +103,7 @@ def test_invalid_call_arguments_rejected(lib):
     assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0, 0x5000, None, 0, None) == EINVAL
     assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 4, 0x5000, 0x6000, 0, None) == EINVAL
     assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, -1, 0x5000, 0x6000, 0, None) == EINVAL
-    # the gradient is FP64 only: a valid request this build does not implement
+    # the gradient is FP64 only: a valid request this library does not implement
     assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0, 0x5000, 0x6000, 1, None) == EUNSUPPORTED
     assert lib.rift_ile_grad(ctypes.byref(cp), 10, 0x4000, 0, 0x5000, 0x6000, 2, None) == EUNSUPPORTED
     # RIFT_FP32 is an rift_ile_lnL-only precision
