@@ -324,6 +324,63 @@ def lnL_dmarg(pt, theta, d_min, d_max, n_nodes, power=2.0, nthreads: int = 0):
     return out
 
 
+def grad_dmarg(pt, c, d_min, d_max, n_nodes):
+    """(ln L_d [n], d ln L_d / d(ra, dec, psi, cos incl, phiref, tref, -)
+    [7, n]) of the likelihood marginalised over distance (Eq. (ap:dgh), prior
+    p(D) ~ D^2 on [d_min, d_max]) in the samplers' coordinates c, whose
+    distance row is not read (its derivative is 0).  lnL(x) = K x - R x^2 / 2
+    exactly (Eq. (ap:dexp)), so the derivative of ln int dx p_x e^{lnL} is
+    <x> grad K - <x^2> grad R / 2, the moments taken under the distance
+    posterior by the same adaptive rule as lnL_dmarg (node weights
+    W_i p_x(x* + xi_i sigma)); grad K and grad R come from the gradient at
+    x = 1 and x = 2: g1 = grad K - grad R / 2, g2 = 2 grad K - 2 grad R.
+    Where the model has no power (R <= 0) the moments are the prior's
+    (numerical quadrature of p_x); with no node inside the prior the value is
+    -inf and the derivative 0; a non-finite sample gives NaN."""
+    from scipy import integrate as _integrate
+
+    c = np.asarray(c, np.float64)
+    d_ref = float(pt["d_ref"])
+    th = _to_physical(c)
+    t1 = th.copy()
+    t1[6] = d_ref
+    t2 = th.copy()
+    t2[6] = d_ref / 2.0
+    _, g1 = grad(pt, t1)
+    _, g2 = grad(pt, t2)
+    dK = 2.0 * g1 - 0.5 * g2
+    dR = 2.0 * g1 - g2
+    ld = lnL_dmarg(pt, t1, d_min, d_max, n_nodes)
+    Kv, Rv = lnL_terms(pt, t1)
+    xi, W = np.polynomial.hermite_e.hermegauss(int(n_nodes))
+    n = c.shape[1]
+    m1 = np.full(n, np.nan)
+    m2 = np.full(n, np.nan)
+    ok = np.isfinite(Kv) & np.isfinite(Rv) & (Rv > 0.0)
+    xs = np.where(ok, Kv, 0.0) / np.where(ok, Rv, 1.0)
+    sig = 1.0 / np.sqrt(np.where(ok, Rv, 1.0))
+    x = xs[:, None] + xi[None, :] * sig[:, None]
+    om = W[None, :] * dist_prior_x(x, d_ref, d_min, d_max)
+    so = om.sum(axis=1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        m1[ok] = (om * x).sum(axis=1)[ok] / so[ok]
+        m2[ok] = (om * x * x).sum(axis=1)[ok] / so[ok]
+    nopow = np.isfinite(Kv) & np.isfinite(Rv) & (Rv <= 0.0)
+    if nopow.any():
+        lo, hi = d_ref / d_max, d_ref / d_min
+        e1 = _integrate.quad(lambda y: y * dist_prior_x(y, d_ref, d_min, d_max), lo, hi, epsabs=0, epsrel=1e-13)[0]
+        e2 = _integrate.quad(lambda y: y * y * dist_prior_x(y, d_ref, d_min, d_max), lo, hi, epsabs=0,
+                             epsrel=1e-13)[0]
+        m1[nopow], m2[nopow] = e1, e2
+    g = m1[None, :] * dK - 0.5 * m2[None, :] * dR
+    g[6] = 0.0
+    empty = ok & ~(so > 0.0)
+    g[:, empty] = 0.0
+    bad = ~np.isfinite(Kv) | ~np.isfinite(Rv)
+    g[:, bad] = np.nan
+    return ld, g
+
+
 def simpson_weights(n_t: int) -> np.ndarray:
     """Composite Simpson weights on n_t (odd) equally spaced nodes, in units
     of the spacing: (1, 4, 2, 4, ..., 2, 4, 1) / 3."""
