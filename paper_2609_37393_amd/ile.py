@@ -69,6 +69,7 @@ EXPORTS = (
     "rift_ile_plan_lnZ_tband",
     "rift_ile_plan_lnZ_erai",
     "rift_ile_moments",
+    "rift_ile_plan_grad_dmarg",
     "rift_ile_plan_rwm",
     "rift_ile_mixture_is",
     "rift_ile_plan_hmc_tempered",
@@ -208,6 +209,7 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_smc_reweight.argtypes = [i64, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
     lib.rift_ile_smc_resample.argtypes = [i64, vp, ctypes.c_double, vp, vp, vp, vp]
     lib.rift_ile_moments.argtypes = [i64, vp, vp, vp, vp, vp]
+    lib.rift_ile_plan_grad_dmarg.argtypes = [vp, i32, i64, vp, ctypes.POINTER(CDistPrior), vp, vp, vp]
     lib.rift_ile_plan_rwm.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(CHmcPrior),
                                       ctypes.c_double, vp, vp, vp, vp]
     lib.rift_ile_mixture_is.argtypes = [i64, ctypes.POINTER(CMixture), ctypes.POINTER(CHmcPrior), vp, vp, vp, vp,
@@ -710,6 +712,22 @@ class Plan:
                                           float(scale), ctypes.byref(pr), float(beta), ptr(lnL), ptr(acc),
                                           st.data_ptr(), _stream(self.device)), "rift_ile_plan_rwm")
         return acc, st
+
+    def grad_dmarg(self, point, theta, d_min, d_max, n_nodes=20, lnLd_out=None, grad_out=None):
+        """(ln L_d [n], d ln L_d / d(ra, dec, psi, cos incl, phiref, tref, -)
+        [7, n]) of the likelihood marginalised over distance
+        (rift_ile_plan_grad_dmarg); theta in the samplers' coordinates, row 6
+        not read."""
+        th = theta if (isinstance(theta, torch.Tensor) and theta.is_contiguous() and theta.dtype == torch.float64) \
+            else _theta(theta, self.device)
+        n = th.shape[1]
+        ld = lnLd_out if lnLd_out is not None else torch.empty(n, dtype=torch.float64, device=self.device)
+        g = grad_out if grad_out is not None else torch.empty((7, n), dtype=torch.float64, device=self.device)
+        pr = CDistPrior(float(d_min), float(d_max), int(n_nodes))
+        _check(self.lib.rift_ile_plan_grad_dmarg(self.handle, int(point), n, th.data_ptr(), ctypes.byref(pr),
+                                                 ld.data_ptr(), g.data_ptr(), _stream(self.device)),
+               "rift_ile_plan_grad_dmarg")
+        return ld, g
 
     def grad(self, point, theta, lnL_out=None, grad_out=None, coords="sampler"):
         """Gradient of lnL with theta rows 3 and 6 in the coordinates `coords`

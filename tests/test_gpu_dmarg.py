@@ -162,3 +162,53 @@ def test_dmarg_full_size_sampled(ile, oracle_mod):
     z_or, _ = oracle_mod.lnZ(allw)
     assert abs(z.item() - z_or) <= 1e-9 * max(1.0, abs(z_or))
     assert math.isfinite(z.item())
+
+
+@pytest.mark.parametrize("snr,d_box,nodes", [(30.0, (10.0, 1000.0), 20), (100.0, (10.0, 1000.0), 32),
+                                             (60.0, (50.0, 400.0), 20)])
+def test_grad_dmarg_matches_oracle(ile, oracle_mod, snr, d_box, nodes):
+    """rift_ile_plan_grad_dmarg against oracle.grad_dmarg on the same states
+    (samplers' coordinates).  Bars: ln L_d as above (its K and R come from
+    lnL at two distances, K = 2 l1 - l2 / 2 and R = 2 l1 - l2, each with the
+    FP64 bar of lnL, ~1e-12 S); the gradient within 1e-8 (|g_a| + 1e-3 |g| +
+    |<x>| |dK_a| + |<x^2>| |dR_a|) per row, the rounding of the two-distance
+    differences carried through the moments; row 6 exactly 0; -inf with a
+    zero gradient where no node lies in the prior."""
+    import torch
+
+    pt = synth.make_point(3, 9, 2000, 16384.0, snr, 81)
+    th, _ = synth.weighted_samples(4000, 82)
+    l = oracle_mod.lnL(pt, th)
+    th = th[:, np.argsort(l)[-300:]]
+    th = np.concatenate([th, synth.prior_samples(200, 83)], axis=1)
+    c = th.copy()
+    c[3] = np.cos(th[3])
+    c[6] = np.log(th[6])
+    n = c.shape[1]
+    print(f"grad_dmarg snr={snr} box={d_box} nodes={nodes}", flush=True)
+    want_l, want_g = oracle_mod.grad_dmarg(pt, c, *d_box, nodes)
+    plan = ile.Plan([pt], [n])
+    ld, g = plan.grad_dmarg(0, torch.as_tensor(c, device="cuda").contiguous(), *d_box, nodes)
+    ld, g = ld.cpu().numpy(), g.cpu().numpy()
+    plan.close()
+    assert np.array_equal(np.isneginf(ld), np.isneginf(want_l))
+    fin = np.isfinite(want_l)
+    bar_l = _bar(oracle_mod, pt, oracle_mod._to_physical(np.where(np.arange(7)[:, None] == 6, np.log(pt["d_ref"]), c)))
+    ok = fin & np.isfinite(bar_l)
+    assert np.all(np.abs(ld[ok] - want_l[ok]) <= bar_l[ok])
+    assert np.all(g[6] == 0.0)
+    # the two-distance parts, for the bar
+    t1 = oracle_mod._to_physical(c)
+    t1[6] = pt["d_ref"]
+    t2 = t1.copy()
+    t2[6] = pt["d_ref"] / 2
+    _, g1 = oracle_mod.grad(pt, t1)
+    _, g2 = oracle_mod.grad(pt, t2)
+    dK, dR = np.abs(2 * g1 - 0.5 * g2), np.abs(2 * g1 - g2)
+    x_hi = pt["d_ref"] / d_box[0]
+    norm = np.sqrt(np.sum(want_g[:6] ** 2, axis=0))
+    for a in range(6):
+        bar = 1e-8 * (np.abs(want_g[a]) + 1e-3 * norm + x_hi * dK[a] + x_hi ** 2 * dR[a])
+        assert np.all(np.abs(g[a, ok] - want_g[a, ok]) <= bar[ok]), (a, np.max(np.abs(g[a, ok] - want_g[a, ok]) / bar[ok]))
+    empty = np.isneginf(want_l)
+    assert np.all(g[:, empty] == 0.0)
