@@ -708,39 +708,47 @@ def _to_physical(c):
     return t
 
 
-def hmc_log_prior(c, t_min, t_max, d_min, d_max):
+def hmc_log_prior(c, t_min, t_max, d_min, d_max, dmarg=False):
     """ln of the prior density in the sampler coordinates (up to a constant):
     the isotropic, uniform-in-volume prior of the samples (ra, psi, phiref
     periodic; sin dec, cos incl, tref uniform; p(D) ~ D^2 on [d_min, d_max])
-    is, in (dec, ln D), ln cos dec + 3 ln D on the box, -inf outside."""
+    is, in (dec, ln D), ln cos dec + 3 ln D on the box, -inf outside.  With
+    `dmarg` (distance marginalised in the likelihood) the distance row is not
+    part of the target: no ln D term and no distance box."""
     c = np.asarray(c, np.float64)
-    inside = (np.abs(c[1]) < np.pi / 2) & (np.abs(c[3]) <= 1.0) & (c[5] >= t_min) & (c[5] <= t_max) & \
-        (c[6] >= np.log(d_min)) & (c[6] <= np.log(d_max))
+    inside = (np.abs(c[1]) < np.pi / 2) & (np.abs(c[3]) <= 1.0) & (c[5] >= t_min) & (c[5] <= t_max)
+    if not dmarg:
+        inside &= (c[6] >= np.log(d_min)) & (c[6] <= np.log(d_max))
     with np.errstate(invalid="ignore", divide="ignore"):
-        v = np.log(np.cos(c[1])) + 3.0 * c[6]
+        v = np.log(np.cos(c[1])) + (0.0 if dmarg else 3.0 * c[6])
     return np.where(inside, v, -np.inf)
 
 
-def hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta=1.0):
+def hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta=1.0, dmarg=None):
     """(lnL, U = -beta lnL - ln prior, dU/dc) in the sampler coordinates: the
     tempered target L^beta p of Eq. (sampler-menu:tempered-target) (beta = 1:
-    the posterior)."""
-    l, g = grad(pt, _to_physical(c))
-    lp = hmc_log_prior(c, t_min, t_max, d_min, d_max)
+    the posterior).  With dmarg = (d_min, d_max, n_nodes) of a distance
+    prior, L is the likelihood marginalised over distance (grad_dmarg) and
+    the distance row is not part of the target."""
+    if dmarg is None:
+        l, g = grad(pt, _to_physical(c))
+    else:
+        l, g = grad_dmarg(pt, c, *dmarg)
+    lp = hmc_log_prior(c, t_min, t_max, d_min, d_max, dmarg is not None)
     gp = np.zeros_like(g)
     gp[1] = -np.tan(c[1])
-    gp[6] = 3.0
+    gp[6] = 0.0 if dmarg is not None else 3.0
     return l, -(beta * l + lp), -(beta * g + gp)
 
 
-def hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta=1.0):
+def hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta=1.0, dmarg=None):
     """n_leapfrog leapfrog steps from (c0, p0): half kick, drift c += eps
     sigma^2 p with cos incl folded back into [-1, 1] (period 4) and its
     momentum negated on odd folds, half kick.  Returns (c, p, lnL, U)."""
     sig = np.asarray(sigma, np.float64)[:, None]
     c = np.array(c0, np.float64, copy=True)
     p = np.array(p0, np.float64, copy=True)
-    l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta)
+    l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta, dmarg)
     for _ in range(int(n_leapfrog)):
         p = p - 0.5 * eps * gU
         c = c + eps * sig * sig * p
@@ -750,12 +758,12 @@ def hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_ma
         flip = np.zeros(c.shape[1], bool)
         flip[np.where(out)[0][r > 2.0]] = True
         p[3][flip] = -p[3][flip]
-        l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta)
+        l, U, gU = hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta, dmarg)
         p = p - 0.5 * eps * gU
     return c, p, l, U
 
 
-def hmc_step(pt, c0, z, u, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta=1.0):
+def hmc_step(pt, c0, z, u, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta=1.0, dmarg=None):
     """One Metropolis-adjusted Hamiltonian Monte Carlo transition per chain
     (the gradient sampler of Sec. "Sampling the differentiable extrinsic
     likelihood"), with the random inputs given: momenta p = z / sigma (mass
@@ -765,12 +773,17 @@ def hmc_step(pt, c0, z, u, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, b
     cos incl reflected at +-1 and its momentum flipped), then acceptance when
     ln u < H0 - H1 with H = U + sum sigma^2 p^2 / 2.  Returns (c, lnL at c,
     accepted).  With beta < 1 the target is the tempered L^beta p of Eq.
-    (sampler-menu:tempered-target) (the moves of an SMC ladder)."""
+    (sampler-menu:tempered-target) (the moves of an SMC ladder).  With dmarg =
+    (d_min, d_max, n_nodes), the likelihood marginalised over distance: the
+    distance row carries no momentum (p_6 = 0), so it is not moved."""
     sig = np.asarray(sigma, np.float64)[:, None]
-    l0, U0, _ = hmc_potential(pt, c0, t_min, t_max, d_min, d_max, beta)
+    l0, U0, _ = hmc_potential(pt, c0, t_min, t_max, d_min, d_max, beta, dmarg)
     p0 = np.asarray(z, np.float64) / sig
+    if dmarg is not None:
+        p0 = p0.copy()
+        p0[6] = 0.0
     H0 = U0 + 0.5 * np.sum(sig * sig * p0 * p0, axis=0)
-    c, p, l1, U1 = hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta)
+    c, p, l1, U1 = hmc_trajectory(pt, c0, p0, sigma, eps, n_leapfrog, t_min, t_max, d_min, d_max, beta, dmarg)
     H1 = U1 + 0.5 * np.sum(sig * sig * p * p, axis=0)
     with np.errstate(invalid="ignore"):
         acc = np.log(np.asarray(u, np.float64)) < (H0 - H1)
@@ -808,7 +821,7 @@ def _no_uturn(p_a, p_b, rho, sig2):
     return float(np.dot(sig2 * p_a, rho)) > 0.0 and float(np.dot(sig2 * p_b, rho)) > 0.0
 
 
-def nuts_chain(potential, c0, z, dirs, merges, leaves, sigma, eps, max_depth):
+def nuts_chain(potential, c0, z, dirs, merges, leaves, sigma, eps, max_depth, frozen=()):
     """One No-U-Turn transition (multinomial NUTS with the generalised
     criterion) of one chain, the random numbers given: momenta p = z / sigma
     (mass diag(sigma^-2)); at depth j the trajectory doubles in direction
@@ -822,12 +835,15 @@ def nuts_chain(potential, c0, z, dirs, merges, leaves, sigma, eps, max_depth):
     otherwise its candidate replaces the transition's with probability
     min(1, W_subtree / W_trajectory) against merges[j], the weights add, and
     a U-turn of the whole trajectory ends it.  At most max_depth doublings.
-    potential(c [7, m]) -> (lnL, U, dU/dc).  Returns (c, lnL, depth,
+    potential(c [7, m]) -> (lnL, U, dU/dc).  The rows in `frozen` carry no
+    momentum (they are not part of the target).  Returns (c, lnL, depth,
     leapfrog steps, divergent)."""
     sig = np.asarray(sigma, np.float64)
     sig2 = sig * sig
     c0 = np.asarray(c0, np.float64)
     p0 = np.asarray(z, np.float64) / sig
+    for a in frozen:
+        p0[a] = 0.0
     l0, U0, g0 = potential(c0[:, None])
     l0, U0, g0 = float(l0[0]), float(U0[0]), g0[:, 0]
     H0 = U0 + 0.5 * float(np.sum(sig2 * p0 * p0))
@@ -885,16 +901,19 @@ def nuts_chain(potential, c0, z, dirs, merges, leaves, sigma, eps, max_depth):
     return cand, cand_l, depth, n_leaf, div
 
 
-def nuts_step(pt, c0, z, dirs, merges, leaves, sigma, eps, max_depth, t_min, t_max, d_min, d_max, beta=1.0):
+def nuts_step(pt, c0, z, dirs, merges, leaves, sigma, eps, max_depth, t_min, t_max, d_min, d_max, beta=1.0,
+              dmarg=None):
     """nuts_chain for every chain on the target L^beta p in the sampler
     coordinates (the potential of hmc_potential).  c0, z [7, n]; dirs,
-    merges [max_depth, n]; leaves [2^max_depth - 1, n].  Returns (c [7, n],
-    lnL [n], depth [n], steps [n], divergent [n])."""
+    merges [max_depth, n]; leaves [2^max_depth - 1, n].  With dmarg =
+    (d_min, d_max, n_nodes), the likelihood marginalised over distance and the
+    distance row frozen.  Returns (c [7, n], lnL [n], depth [n], steps [n],
+    divergent [n])."""
     c0 = np.asarray(c0, np.float64)
     n = c0.shape[1]
 
     def pot(c):
-        return hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta)
+        return hmc_potential(pt, c, t_min, t_max, d_min, d_max, beta, dmarg)
 
     out = np.empty_like(c0)
     ll = np.empty(n)
@@ -903,7 +922,7 @@ def nuts_step(pt, c0, z, dirs, merges, leaves, sigma, eps, max_depth, t_min, t_m
     dv = np.zeros(n, bool)
     for i in range(n):
         c, l, dd, ss, vv = nuts_chain(pot, c0[:, i], z[:, i], dirs[:, i], merges[:, i], leaves[:, i], sigma, eps,
-                                      max_depth)
+                                      max_depth, frozen=(6,) if dmarg is not None else ())
         out[:, i], ll[i], dep[i], st[i], dv[i] = c, l, dd, ss, vv
     return out, ll, dep, st, dv
 
