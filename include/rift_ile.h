@@ -560,6 +560,25 @@ int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, double *the
                        double eps, int32_t max_depth, const rift_ile_hmc_prior *prior, double beta, double *lnL,
                        int32_t *info, void *stream);
 
+/* HMC and NUTS transitions on the likelihood marginalised over distance
+ * (Sec. "Sampler menu": a chain with distance marginalised): as
+ * rift_ile_plan_hmc_tempered and rift_ile_plan_nuts, with the target
+ * L_d^beta p, L_d the marginal of rift_ile_plan_lnZ_dmarg under the distance
+ * prior `dprior` and its gradient from rift_ile_plan_grad_dmarg.  The
+ * distance row is not part of the target: it carries no momentum (it is
+ * returned unchanged), and the prior drops its ln D term and distance box.
+ * lnLd: DEVICE [n] or NULL, ln L_d at the returned states.  RIFT_EINVAL as
+ * the untempered entries, and for a null or invalid dprior. */
+int rift_ile_plan_hmc_dmarg(rift_ile_plan plan, int32_t point, int64_t n, double *theta, const double *z,
+                            const double *u, const double *sigma, double eps, int32_t n_leapfrog,
+                            const rift_ile_hmc_prior *prior, const rift_ile_dist_prior *dprior, double beta,
+                            double *lnLd, int32_t *accepted, void *stream);
+int rift_ile_plan_nuts_dmarg(rift_ile_plan plan, int32_t point, int64_t n, double *theta, const double *z,
+                             const double *dirs, const double *merges, const double *leaves, const double *sigma,
+                             double eps, int32_t max_depth, const rift_ile_hmc_prior *prior,
+                             const rift_ile_dist_prior *dprior, double beta, double *lnLd, int32_t *info,
+                             void *stream);
+
 /* One update of an SMC tempering ladder (Sec. "Sampler menu",
  * Eq. (sampler-menu:smc-update)) over n weighted particles: with W the
  * normalised weights from lnW (DEVICE [n], any normalisation; -inf excludes a

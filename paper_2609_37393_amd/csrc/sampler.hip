@@ -47,22 +47,25 @@ __global__ void k_drift(int64_t n, double* __restrict__ theta, double* __restric
 
 struct HmcPrior {
   double t_min, t_max, lnd_min, lnd_max;
+  int32_t dmarg;  // the likelihood marginalised over distance: row 6 not part of the target
 };
 
 // ln of the prior density in the sampler coordinates, up to a constant: the
 // isotropic, uniform-in-volume prior is ln cos dec + 3 ln D on the box (ra,
 // psi and phiref periodic, cos incl in [-1, 1]), -inf outside.
+// With the distance marginalised, the distance row is not part of the
+// target: no ln D term and no distance box.
 __device__ __forceinline__ double hmc_log_prior(const HmcPrior& P, double dec, double ci, double t, double lnd) {
   const bool inside = fabs(dec) < 1.57079632679489661923 && fabs(ci) <= 1.0 && t >= P.t_min && t <= P.t_max &&
-                      lnd >= P.lnd_min && lnd <= P.lnd_max;
-  return inside ? log(cos(dec)) + 3.0 * lnd : -__builtin_inf();
+                      (P.dmarg || (lnd >= P.lnd_min && lnd <= P.lnd_max));
+  return inside ? log(cos(dec)) + (P.dmarg ? 0.0 : 3.0 * lnd) : -__builtin_inf();
 }
 
 // d ln pi / dc_a = dlnL/dc_a + d ln prior / dc_a; the prior's part is
 // -tan(dec) in dec and 3 in ln D.
-__device__ __forceinline__ double dlnpi(int a, double g, double dec) {
+__device__ __forceinline__ double dlnpi(const HmcPrior& P, int a, double g, double dec) {
   if (a == 1) return g - tan(dec);
-  if (a == 6) return g + 3.0;
+  if (a == 6) return P.dmarg ? 0.0 : g + 3.0;
   return g;
 }
 
@@ -80,7 +83,7 @@ __global__ void k_hmc_first(int64_t n, double* __restrict__ c, const double* __r
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
       ca[a] = c[a * n + i];
-      pa[a] = z[a * n + i] / sig.s[a];
+      pa[a] = (P.dmarg && a == 6) ? 0.0 : z[a * n + i] / sig.s[a];
       const double v = sig.s[a] * pa[a];
       kin = fma(v, v, kin);
       c0[a * n + i] = ca[a];
@@ -91,7 +94,7 @@ __global__ void k_hmc_first(int64_t n, double* __restrict__ c, const double* __r
     const double dec = ca[1];
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      pa[a] = fma(h, dlnpi(a, beta * g[a * n + i], dec), pa[a]);
+      pa[a] = fma(h, dlnpi(P, a, beta * g[a * n + i], dec), pa[a]);
       c[a * n + i] = drift_one(a, ca[a], pa[a], step.s[a]);
       p[a * n + i] = pa[a];
     }
@@ -101,12 +104,12 @@ __global__ void k_hmc_first(int64_t n, double* __restrict__ c, const double* __r
 // Between two drifts: the half kick that ends one leapfrog step and the one
 // that starts the next (both at the current state), then the drift.
 __global__ void k_hmc_mid(int64_t n, double* __restrict__ c, double* __restrict__ p, const double* __restrict__ g,
-                          double h, double beta, Step7 step) {
+                          double h, double beta, Step7 step, HmcPrior P) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double dec = c[n + i];
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      const double ga = dlnpi(a, beta * g[a * n + i], dec);
+      const double ga = dlnpi(P, a, beta * g[a * n + i], dec);
       double pa = fma(h, ga, p[a * n + i]);
       pa = fma(h, ga, pa);
       c[a * n + i] = drift_one(a, c[a * n + i], pa, step.s[a]);
@@ -127,7 +130,7 @@ __global__ void k_hmc_end(int64_t n, double* __restrict__ c, const double* __res
     double kin = 0.0;
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      const double pa = fma(h, dlnpi(a, beta * g[a * n + i], dec), p[a * n + i]);
+      const double pa = fma(h, dlnpi(P, a, beta * g[a * n + i], dec), p[a * n + i]);
       const double v = sig.s[a] * pa;
       kin = fma(v, v, kin);
     }
@@ -206,13 +209,13 @@ __global__ void k_nuts_init(int64_t n, const double* __restrict__ c0, const doub
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
       c[a] = c0[a * n + i];
-      p[a] = z[a * n + i] / sig.s[a];
+      p[a] = (P.dmarg && a == 6) ? 0.0 : z[a * n + i] / sig.s[a];
     }
     const double dec = c[1];
     const double H0 = nuts_energy(P, beta, l, c, p, sig);
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      const double g = dlnpi(a, beta * W[(Ly.gE + a) * n + i], dec);
+      const double g = dlnpi(P, a, beta * W[(Ly.gE + a) * n + i], dec);
       W[(Ly.cL + a) * n + i] = c[a];
       W[(Ly.pL + a) * n + i] = p[a];
       W[(Ly.gL + a) * n + i] = g;
@@ -299,7 +302,7 @@ __global__ void k_nuts_post(int64_t n, const double* __restrict__ merges, const 
     const double l = W[Ly.lE * n + i];
 #pragma unroll
     for (int a = 0; a < 7; ++a) {
-      g[a] = dlnpi(a, beta * W[(Ly.gE + a) * n + i], c[1]);
+      g[a] = dlnpi(P, a, beta * W[(Ly.gE + a) * n + i], c[1]);
       p[a] = fma(h, g[a], W[(Ly.pX + a) * n + i]);
       W[(Ly.pX + a) * n + i] = p[a];
       W[(Ly.gX + a) * n + i] = g[a];
@@ -732,6 +735,20 @@ __global__ void k_rwm_accept(int64_t n, double* __restrict__ c, const double* __
   }
 }
 
+// lnL and its gradient in the samplers' coordinates: of the likelihood, or,
+// with a distance prior, of the likelihood marginalised over distance.
+int sampler_grad(rift_ile_plan plan, int32_t point, int64_t n, const double* c, const rift_ile_dist_prior* dm,
+                 double* l, double* g, void* stream) {
+  constexpr int coords = RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST;
+  return dm ? rift_ile_plan_grad_dmarg(plan, point, n, c, dm, l, g, stream)
+            : rift_ile_plan_grad(plan, point, n, c, coords, l, g, stream);
+}
+
+bool bad_dist_prior(const rift_ile_dist_prior* dm) {
+  return dm && (!(dm->d_min > 0.0) || !(dm->d_max > dm->d_min) || !(dm->d_max <= 1.0e60) || dm->n_nodes < 1 ||
+                dm->n_nodes > 64);
+}
+
 }  // namespace
 
 extern "C" int rift_ile_plan_rwm(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
@@ -746,7 +763,7 @@ extern "C" int rift_ile_plan_rwm(rift_ile_plan plan, int32_t point, int64_t n, d
   if (bad(cov) || (status && (((uintptr_t)status) & 3u))) return RIFT_EINVAL;
   if (n > 0 && (bad(theta) || bad(z) || bad(u) || bad(lnL) || (accepted && (((uintptr_t)accepted) & 3u))))
     return RIFT_EINVAL;
-  HmcPrior P;
+  HmcPrior P{};
   P.t_min = prior->t_min;
   P.t_max = prior->t_max;
   P.lnd_min = log(prior->d_min);
@@ -775,11 +792,11 @@ extern "C" int rift_ile_plan_rwm(rift_ile_plan plan, int32_t point, int64_t n, d
   return rc;
 }
 
-extern "C" int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
-                                  const double* dirs, const double* merges, const double* leaves, const double* sigma,
-                                  double eps, int32_t max_depth, const rift_ile_hmc_prior* prior, double beta,
-                                  double* lnL, int32_t* info, void* stream) {
-  if (!plan || n < 0 || !sigma || !prior) return RIFT_EINVAL;
+static int nuts_impl(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
+                     const double* dirs, const double* merges, const double* leaves, const double* sigma, double eps,
+                     int32_t max_depth, const rift_ile_hmc_prior* prior, const rift_ile_dist_prior* dm, double beta,
+                     double* lnL, int32_t* info, void* stream) {
+  if (!plan || n < 0 || !sigma || !prior || bad_dist_prior(dm)) return RIFT_EINVAL;
   if (!(eps > 0.0) || !std::isfinite(eps) || max_depth < 1 || max_depth > NUTS_MAX_DEPTH) return RIFT_EINVAL;
   if (!(beta >= 0.0 && beta <= 1.0)) return RIFT_EINVAL;
   if (!std::isfinite(prior->t_min) || !std::isfinite(prior->t_max) || !(prior->t_max > prior->t_min)) return RIFT_EINVAL;
@@ -795,7 +812,7 @@ extern "C" int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, 
   if (bad(theta) || bad(z) || bad(dirs) || bad(merges) || bad(leaves) || (lnL && bad(lnL)) ||
       (info && (((uintptr_t)info) & 3u)))
     return RIFT_EINVAL;
-  HmcPrior P;
+  HmcPrior P{};
   P.t_min = prior->t_min;
   P.t_max = prior->t_max;
   P.lnd_min = log(prior->d_min);
@@ -811,15 +828,15 @@ extern "C" int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, 
   int32_t* I = (int32_t*)(Wd + (size_t)Ly.rows * n);
   int32_t* cnt = I + (size_t)NI_ROWS * n;
   std::vector<int32_t> hc(cgrid);
-  constexpr int coords = RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST;
-  int rc = rift_ile_plan_grad(plan, point, n, theta, coords, Wd + (size_t)Ly.lE * n, Wd + (size_t)Ly.gE * n, stream);
+  P.dmarg = dm ? 1 : 0;
+  int rc = sampler_grad(plan, point, n, theta, dm, Wd + (size_t)Ly.lE * n, Wd + (size_t)Ly.gE * n, stream);
   if (!rc)
     hipLaunchKernelGGL(k_nuts_init, dim3(grid), dim3(256), 0, st, n, (const double*)theta, z, sig, beta, P, Wd, I, Ly);
   const int iters = (1 << max_depth) - 1;
   for (int it = 0; it < iters && !rc; ++it) {
     hipLaunchKernelGGL(k_nuts_pre, dim3(grid), dim3(256), 0, st, n, dirs, eps, sig2, Wd, I, Ly);
-    rc = rift_ile_plan_grad(plan, point, n, Wd + (size_t)Ly.cE * n, coords, Wd + (size_t)Ly.lE * n,
-                            Wd + (size_t)Ly.gE * n, stream);
+    rc = sampler_grad(plan, point, n, Wd + (size_t)Ly.cE * n, dm, Wd + (size_t)Ly.lE * n, Wd + (size_t)Ly.gE * n,
+                      stream);
     if (rc) break;
     hipLaunchKernelGGL(k_nuts_post, dim3(grid), dim3(256), 0, st, n, merges, leaves, eps, beta, sig, sig2, P,
                        (int)max_depth, Wd, I, Ly);
@@ -842,6 +859,24 @@ extern "C" int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, 
   if (!rc && hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
   if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
   return rc;
+}
+
+extern "C" int rift_ile_plan_nuts(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
+                                  const double* dirs, const double* merges, const double* leaves, const double* sigma,
+                                  double eps, int32_t max_depth, const rift_ile_hmc_prior* prior, double beta,
+                                  double* lnL, int32_t* info, void* stream) {
+  return nuts_impl(plan, point, n, theta, z, dirs, merges, leaves, sigma, eps, max_depth, prior, nullptr, beta, lnL,
+                   info, stream);
+}
+
+extern "C" int rift_ile_plan_nuts_dmarg(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
+                                        const double* dirs, const double* merges, const double* leaves,
+                                        const double* sigma, double eps, int32_t max_depth,
+                                        const rift_ile_hmc_prior* prior, const rift_ile_dist_prior* dprior,
+                                        double beta, double* lnLd, int32_t* info, void* stream) {
+  if (!dprior) return RIFT_EINVAL;
+  return nuts_impl(plan, point, n, theta, z, dirs, merges, leaves, sigma, eps, max_depth, prior, dprior, beta, lnLd,
+                   info, stream);
 }
 
 extern "C" int rift_ile_smc_reweight(int64_t n, const double* lnL, double* lnW, double beta, double target,
@@ -926,11 +961,10 @@ extern "C" int rift_ile_plan_hmc(rift_ile_plan plan, int32_t point, int64_t n, d
                                     stream);
 }
 
-extern "C" int rift_ile_plan_hmc_tempered(rift_ile_plan plan, int32_t point, int64_t n, double* theta,
-                                          const double* z, const double* u, const double* sigma, double eps,
-                                          int32_t n_leapfrog, const rift_ile_hmc_prior* prior, double beta,
-                                          double* lnL, int32_t* accepted, void* stream) {
-  if (!plan || n < 0 || !sigma || !prior) return RIFT_EINVAL;
+static int hmc_impl(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z, const double* u,
+                    const double* sigma, double eps, int32_t n_leapfrog, const rift_ile_hmc_prior* prior,
+                    const rift_ile_dist_prior* dm, double beta, double* lnL, int32_t* accepted, void* stream) {
+  if (!plan || n < 0 || !sigma || !prior || bad_dist_prior(dm)) return RIFT_EINVAL;
   if (!(beta >= 0.0 && beta <= 1.0)) return RIFT_EINVAL;
   if (!(eps > 0.0) || !std::isfinite(eps) || n_leapfrog < 1 || n_leapfrog > 10000) return RIFT_EINVAL;
   if (!std::isfinite(prior->t_min) || !std::isfinite(prior->t_max) || !(prior->t_max > prior->t_min)) return RIFT_EINVAL;
@@ -945,7 +979,7 @@ extern "C" int rift_ile_plan_hmc_tempered(rift_ile_plan plan, int32_t point, int
   auto bad = [](const void* q) { return !q || (((uintptr_t)q) & 7u); };
   if (bad(theta) || bad(z) || bad(u) || (lnL && bad(lnL)) || (accepted && (((uintptr_t)accepted) & 3u)))
     return RIFT_EINVAL;
-  HmcPrior P;
+  HmcPrior P{};
   P.t_min = prior->t_min;
   P.t_max = prior->t_max;
   P.lnd_min = log(prior->d_min);
@@ -956,19 +990,19 @@ extern "C" int rift_ile_plan_hmc_tempered(rift_ile_plan plan, int32_t point, int
   if (hipMallocAsync((void**)&w, sizeof(double) * 24 * (size_t)n, st) != hipSuccess) return RIFT_ENOMEM;
   double *p = w, *c0 = w + 7 * n, *g = w + 14 * n, *l1 = w + 21 * n, *l0 = w + 22 * n, *H0 = w + 23 * n;
   const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-  constexpr int coords = RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST;
   const double h = 0.5 * eps;
+  P.dmarg = dm ? 1 : 0;
   // L + 1 gradients; between them one fused kernel each (kicks and drift)
-  int rc = rift_ile_plan_grad(plan, point, n, theta, coords, l1, g, stream);
+  int rc = sampler_grad(plan, point, n, theta, dm, l1, g, stream);
   if (!rc)
     hipLaunchKernelGGL(k_hmc_first, dim3(grid), dim3(256), 0, st, n, theta, z, (const double*)g, (const double*)l1, h,
                        beta, sig, step, P, p, c0, H0, l0);
   for (int s = 1; s < n_leapfrog && !rc; ++s) {
-    rc = rift_ile_plan_grad(plan, point, n, theta, coords, l1, g, stream);
+    rc = sampler_grad(plan, point, n, theta, dm, l1, g, stream);
     if (!rc)
-      hipLaunchKernelGGL(k_hmc_mid, dim3(grid), dim3(256), 0, st, n, theta, p, (const double*)g, h, beta, step);
+      hipLaunchKernelGGL(k_hmc_mid, dim3(grid), dim3(256), 0, st, n, theta, p, (const double*)g, h, beta, step, P);
   }
-  if (!rc) rc = rift_ile_plan_grad(plan, point, n, theta, coords, l1, g, stream);
+  if (!rc) rc = sampler_grad(plan, point, n, theta, dm, l1, g, stream);
   if (!rc)
     hipLaunchKernelGGL(k_hmc_end, dim3(grid), dim3(256), 0, st, n, theta, (const double*)p, (const double*)g,
                        (const double*)l1, h, beta, (const double*)c0, (const double*)l0, (const double*)H0, u, sig,
@@ -976,4 +1010,19 @@ extern "C" int rift_ile_plan_hmc_tempered(rift_ile_plan plan, int32_t point, int
   if (!rc && hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
   if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
   return rc;
+}
+
+extern "C" int rift_ile_plan_hmc_tempered(rift_ile_plan plan, int32_t point, int64_t n, double* theta,
+                                          const double* z, const double* u, const double* sigma, double eps,
+                                          int32_t n_leapfrog, const rift_ile_hmc_prior* prior, double beta,
+                                          double* lnL, int32_t* accepted, void* stream) {
+  return hmc_impl(plan, point, n, theta, z, u, sigma, eps, n_leapfrog, prior, nullptr, beta, lnL, accepted, stream);
+}
+
+extern "C" int rift_ile_plan_hmc_dmarg(rift_ile_plan plan, int32_t point, int64_t n, double* theta, const double* z,
+                                       const double* u, const double* sigma, double eps, int32_t n_leapfrog,
+                                       const rift_ile_hmc_prior* prior, const rift_ile_dist_prior* dprior, double beta,
+                                       double* lnLd, int32_t* accepted, void* stream) {
+  if (!dprior) return RIFT_EINVAL;
+  return hmc_impl(plan, point, n, theta, z, u, sigma, eps, n_leapfrog, prior, dprior, beta, lnLd, accepted, stream);
 }

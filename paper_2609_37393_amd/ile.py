@@ -70,6 +70,8 @@ EXPORTS = (
     "rift_ile_plan_lnZ_erai",
     "rift_ile_moments",
     "rift_ile_plan_grad_dmarg",
+    "rift_ile_plan_hmc_dmarg",
+    "rift_ile_plan_nuts_dmarg",
     "rift_ile_plan_rwm",
     "rift_ile_mixture_is",
     "rift_ile_plan_hmc_tempered",
@@ -210,6 +212,12 @@ def load(path: str = LIB_PATH):
     lib.rift_ile_smc_resample.argtypes = [i64, vp, ctypes.c_double, vp, vp, vp, vp]
     lib.rift_ile_moments.argtypes = [i64, vp, vp, vp, vp, vp]
     lib.rift_ile_plan_grad_dmarg.argtypes = [vp, i32, i64, vp, ctypes.POINTER(CDistPrior), vp, vp, vp]
+    lib.rift_ile_plan_hmc_dmarg.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, i32,
+                                            ctypes.POINTER(CHmcPrior), ctypes.POINTER(CDistPrior), ctypes.c_double,
+                                            vp, vp, vp]
+    lib.rift_ile_plan_nuts_dmarg.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, ctypes.c_double, i32,
+                                             ctypes.POINTER(CHmcPrior), ctypes.POINTER(CDistPrior), ctypes.c_double,
+                                             vp, vp, vp]
     lib.rift_ile_plan_rwm.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(CHmcPrior),
                                       ctypes.c_double, vp, vp, vp, vp]
     lib.rift_ile_mixture_is.argtypes = [i64, ctypes.POINTER(CMixture), ctypes.POINTER(CHmcPrior), vp, vp, vp, vp,
@@ -657,18 +665,28 @@ class Plan:
                                                 _stream(self.device)), "rift_ile_plan_lnZ_pmarg")
         return z, ne
 
-    def hmc(self, point, theta, z, u, sigma, eps, n_leapfrog, box, lnL_out=None, accepted_out=None, beta=None):
+    def hmc(self, point, theta, z, u, sigma, eps, n_leapfrog, box, lnL_out=None, accepted_out=None, beta=None,
+            dmarg=None):
         """One Metropolis-adjusted HMC transition of every chain in place
         (rift_ile_plan_hmc, or rift_ile_plan_hmc_tempered on L^beta p when
         beta is given): theta [7, n] in the sampler coordinates, z [7, n]
         standard normals, u [n] uniforms, sigma [7], box = (t_min, t_max,
-        d_min, d_max).  Returns (lnL [n], accepted [n] int32)."""
+        d_min, d_max).  With dmarg = (d_min, d_max, n_nodes), the target is
+        the likelihood marginalised over distance (rift_ile_plan_hmc_dmarg).
+        Returns (lnL [n], accepted [n] int32)."""
         n = theta.shape[1]
         l = lnL_out if lnL_out is not None else torch.empty(n, dtype=torch.float64, device=self.device)
         acc = accepted_out if accepted_out is not None else torch.empty(n, dtype=torch.int32, device=self.device)
         sg = np.ascontiguousarray(sigma, dtype=np.float64)
         pr = CHmcPrior(*[float(b) for b in box])
-        if beta is None:
+        if dmarg is not None:
+            dp = CDistPrior(float(dmarg[0]), float(dmarg[1]), int(dmarg[2]))
+            _check(self.lib.rift_ile_plan_hmc_dmarg(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(),
+                                                    u.data_ptr(), sg.ctypes.data, float(eps), int(n_leapfrog),
+                                                    ctypes.byref(pr), ctypes.byref(dp),
+                                                    1.0 if beta is None else float(beta), l.data_ptr(),
+                                                    acc.data_ptr(), _stream(self.device)), "rift_ile_plan_hmc_dmarg")
+        elif beta is None:
             _check(self.lib.rift_ile_plan_hmc(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(),
                                               u.data_ptr(), sg.ctypes.data, float(eps), int(n_leapfrog),
                                               ctypes.byref(pr), l.data_ptr(), acc.data_ptr(), _stream(self.device)),
@@ -681,7 +699,7 @@ class Plan:
         return l, acc
 
     def nuts(self, point, theta, z, dirs, merges, leaves, sigma, eps, max_depth, box, beta=1.0, lnL_out=None,
-             info_out=None):
+             info_out=None, dmarg=None):
         """One No-U-Turn transition of every chain in place
         (rift_ile_plan_nuts): theta [7, n] sampler coordinates, z [7, n]
         normals, dirs and merges [max_depth, n] and leaves
@@ -692,6 +710,14 @@ class Plan:
         inf = info_out if info_out is not None else torch.empty((3, n), dtype=torch.int32, device=self.device)
         sg = np.ascontiguousarray(sigma, dtype=np.float64)
         pr = CHmcPrior(*[float(b) for b in box])
+        if dmarg is not None:
+            dp = CDistPrior(float(dmarg[0]), float(dmarg[1]), int(dmarg[2]))
+            _check(self.lib.rift_ile_plan_nuts_dmarg(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(),
+                                                     dirs.data_ptr(), merges.data_ptr(), leaves.data_ptr(),
+                                                     sg.ctypes.data, float(eps), int(max_depth), ctypes.byref(pr),
+                                                     ctypes.byref(dp), float(beta), l.data_ptr(), inf.data_ptr(),
+                                                     _stream(self.device)), "rift_ile_plan_nuts_dmarg")
+            return l, inf
         _check(self.lib.rift_ile_plan_nuts(self.handle, int(point), n, theta.data_ptr(), z.data_ptr(), dirs.data_ptr(),
                                            merges.data_ptr(), leaves.data_ptr(), sg.ctypes.data, float(eps),
                                            int(max_depth), ctypes.byref(pr), float(beta), l.data_ptr(),

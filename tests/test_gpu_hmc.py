@@ -166,3 +166,76 @@ def test_hmc_edge_cases(ile, oracle_mod):
     tc = dev(c_out)
     _, acc = plan.hmc(0, tc, z, u, SIG, 0.1, 2, BOX)
     assert np.array_equal(acc.cpu().numpy().astype(bool), want_acc)
+
+
+def _dm_chains(oracle_mod, pt, n, seed, d_box):
+    """States near the posterior whose distance peak lies well inside the
+    distance prior (the marginal's gradient is the rule's there)."""
+    th, _ = synth.weighted_samples(60 * n, seed)
+    l = oracle_mod.lnL(pt, th)
+    th = th[:, np.argsort(l)[-6 * n:]]
+    t1 = th.copy()
+    t1[6] = pt["d_ref"]
+    K, R = oracle_mod.lnL_terms(pt, t1)
+    xs, sg = K / R, 1.0 / np.sqrt(R)
+    inner = (xs - 10 * sg > pt["d_ref"] / d_box[1]) & (xs + 10 * sg < pt["d_ref"] / d_box[0])
+    th = th[:, inner][:, :n]
+    c = th.copy()
+    c[3] = np.cos(th[3])
+    c[6] = np.log(th[6])
+    return c
+
+
+def test_hmc_and_nuts_on_the_distance_marginal(ile, oracle_mod):
+    """rift_ile_plan_hmc_dmarg and rift_ile_plan_nuts_dmarg against
+    oracle.hmc_step / nuts_step with dmarg (same bars as the untempered
+    transitions; the distance row returned unchanged bit for bit)."""
+    import torch
+
+    pt = synth.make_point(3, 9, 2000, 16384.0, 100.0, 91)
+    dm = (10.0, 1000.0, 24)
+    n = 40
+    c0 = _dm_chains(oracle_mod, pt, n, 92, dm)
+    assert c0.shape[1] == n
+    rng = np.random.default_rng(93)
+    z = rng.normal(size=c0.shape)
+    u = rng.uniform(0.5, 1.0, n)
+    plan = ile.Plan([pt], [n])
+    for eps, L, beta in ((0.3, 4, 1.0), (0.2, 6, 0.5)):
+        print(f"hmc dmarg eps={eps} L={L} beta={beta}", flush=True)
+        want_c, want_l, want_a = oracle_mod.hmc_step(pt, c0, z, u, SIG, eps, L, *BOX, beta=beta, dmarg=dm)
+        tc = torch.as_tensor(c0, device="cuda").contiguous()
+        l, acc = plan.hmc(0, tc, torch.as_tensor(z, device="cuda").contiguous(),
+                          torch.as_tensor(u, device="cuda").contiguous(), SIG, eps, L, BOX, beta=beta, dmarg=dm)
+        got_c, got_l, got_a = tc.cpu().numpy(), l.cpu().numpy(), acc.cpu().numpy().astype(bool)
+        # energy difference of the oracle, to leave out decisions at the threshold
+        p0 = z / SIG[:, None]
+        p0[6] = 0.0
+        _, U0, _ = oracle_mod.hmc_potential(pt, c0, *BOX, beta=beta, dmarg=dm)
+        _, p1, _, U1 = oracle_mod.hmc_trajectory(pt, c0, p0, SIG, eps, L, *BOX, beta=beta, dmarg=dm)
+        dH = (U0 + 0.5 * np.sum(SIG[:, None] ** 2 * p0 ** 2, 0)) - (U1 + 0.5 * np.sum(SIG[:, None] ** 2 * p1 ** 2, 0))
+        firm = ~(np.abs(np.log(u) - dH) < 1e-4)
+        assert firm.sum() >= n - 2
+        assert np.array_equal(got_a[firm], want_a[firm])
+        assert np.all(np.abs(got_c[:, firm] - want_c[:, firm]) <= 1e-6 * SIG[:, None])
+        assert np.array_equal(got_c[6], c0[6])
+        _, g = oracle_mod.grad_dmarg(pt, want_c, *dm)
+        bar = 1e-6 * (1.0 + np.sum(SIG[:, None] * np.abs(g), axis=0)) + 1e-9 * np.abs(want_l)
+        assert np.all(np.abs(got_l[firm] - want_l[firm]) <= bar[firm])
+    # NUTS
+    D = 4
+    dirs, merges = rng.uniform(size=(D, n)), rng.uniform(size=(D, n))
+    leaves = rng.uniform(size=(2 ** D - 1, n))
+    print("nuts dmarg", flush=True)
+    want = oracle_mod.nuts_step(pt, c0, z, dirs, merges, leaves, SIG, 0.3, D, *BOX, dmarg=dm)
+    tc = torch.as_tensor(c0, device="cuda").contiguous()
+    dev = (lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda"))
+    l, info = plan.nuts(0, tc, dev(z), dev(dirs), dev(merges), dev(leaves), SIG, 0.3, D, BOX, dmarg=dm)
+    got_c, info = tc.cpu().numpy(), info.cpu().numpy()
+    assert np.array_equal(info[0], want[2]) and np.array_equal(info[1], want[3])
+    assert np.all(np.abs(got_c - want[0]) <= 1e-6 * SIG[:, None])
+    assert np.array_equal(got_c[6], c0[6])
+    assert info[1].mean() > 2
+    with pytest.raises(RuntimeError):
+        plan.hmc(0, dev(c0), dev(z), dev(u), SIG, 0.3, 4, BOX, dmarg=(10.0, 5.0, 24))
+    plan.close()
