@@ -900,6 +900,23 @@ def extra_hmc(ile, synth, torch, steps, chains=16384, n_leapfrog=8, cpu=True):
             oracle.hmc_step(pt, cs, z, u, sig, eps, n_leapfrog, *box)
             done += 256
         res["cpu_oracle_transitions_per_s"] = done / (time.perf_counter() - t0)
+    # the same chains on the likelihood marginalised over distance (20-node
+    # rule): two gradient evaluations and a combine per leapfrog point
+    dm = (10.0, 1000.0, 20)
+    it2 = iter(range(burn + k))
+
+    def step_dm():
+        i = next(it2)
+        plan.hmc(0, c, Z[i], U[i], sig, eps, n_leapfrog, box, lnL_out=ll, accepted_out=acc, dmarg=dm)
+        acc_sum.add_(acc)
+
+    for _ in range(burn):
+        step_dm()
+    acc_sum.zero_()
+    secs_dm, _ = time_steps(step_dm, k, 0, torch)
+    res["distance_marginalised"] = {"transitions_per_s": chains * k / secs_dm, "ms_per_transition": 1e3 * secs_dm / k,
+                                    "acceptance": float(acc_sum.double().mean().item() / k),
+                                    "mean_lnLd": float(ll.mean().item())}
     plan.close()
     return res
 
