@@ -330,8 +330,8 @@ int rift_ile_plan_lnZ_dmarg(rift_ile_plan plan, const double *theta, const doubl
  * that move in the six other coordinates (Sec. "Sampler menu": a chain with
  * distance marginalised).  lnL is exactly K x - R x^2 / 2 in x = d_ref / D
  * (Eq. (ap:dexp)), so d ln L_d = <x> grad K - <x^2> grad R / 2 under the
- * distance posterior; K, R and their gradients come from rift_ile_plan_grad
- * at D = d_ref and D = d_ref / 2, and the moments from the same adaptive
+ * distance posterior; one pass of the gradient's adjoint forms K, R and their
+ * gradients, and its last step takes the moments from the same adaptive
  * Gauss-Hermite rule as rift_ile_plan_lnZ_dmarg (node weights
  * W_i p_x(x_i)).  This is the derivative of the integral; it differs from
  * the rule's own derivative by the rule's error (small where the distance
@@ -343,7 +343,7 @@ int rift_ile_plan_lnZ_dmarg(rift_ile_plan plan, const double *theta, const doubl
  * grad: DEVICE [7][n] output, d ln L_d / d(ra, dec, psi, cos incl, phiref,
  * tref) and 0 in row 6.  `point` is a point of the plan.  RIFT_EINVAL: as
  * rift_ile_plan_lnZ_dmarg's prior, n < 0, a bad point, null or misaligned
- * pointers.  Enqueues and returns; stream-ordered scratch of 240 n bytes. */
+ * pointers.  Enqueues and returns; no scratch. */
 int rift_ile_plan_grad_dmarg(rift_ile_plan plan, int32_t point, int64_t n, const double *theta,
                              const rift_ile_dist_prior *prior, double *lnLd, double *grad, void *stream);
 

@@ -48,10 +48,67 @@ __device__ __forceinline__ void grad_coords(int coords, double c3, double dist, 
   if (!(coords & COORD_LN_DIST)) g6 = g6 / dist;
 }
 
-template <int KT, int L>
+// The distance factors of both epilogues.  lnL = x data - x^2 quad in
+// x = d_ref / D, and every derivative along the other coordinates is
+// x d(data) - x^2 d(quad).  At the sample's distance: m1 = x, m2 = x^2.  For
+// the likelihood marginalised over distance (`marg`, Eq. (ap:dgh)):
+// ln L_d by the rule, and d ln L_d = <x> d(data) - <x^2> d(quad) with the
+// moments under the distance posterior taken by the rule's node weights
+// W_i p_x(x_i), p_x ~ x^-4; where the model has no power (R = 2 quad <= 0)
+// the prior's moments of x; no node inside the prior: `none` (derivative 0).
+struct DistFactors {
+  double m1, m2, lnL;
+  bool none;
+};
+__device__ __forceinline__ DistFactors dist_factors(PDesc P, double dist, double data, double quad, bool bad,
+                                                    const DistRule& G, bool marg) {
+  DistFactors f;
+  f.none = false;
+  if (!marg) {
+    const double x = P->d_ref / dist;
+    const double x2 = x * x;
+    f.m1 = x;
+    f.m2 = x2;
+    f.lnL = x * data - x2 * quad;
+    return f;
+  }
+  const double d_ref = P->d_ref;
+  Terms t;
+  t.data = data;
+  t.quad = quad;
+  t.wq = 0.0;
+  t.bad = bad;
+  f.lnL = dist_marginal(G, d_ref, t);
+  const double a = d_ref / G.d_max, b = d_ref / G.d_min;
+  const double Rd = 2.0 * quad;
+  if (!(Rd > 0.0)) {
+    const double i3 = 1.0 / (a * a * a) - 1.0 / (b * b * b);
+    f.m1 = 1.5 * (1.0 / (a * a) - 1.0 / (b * b)) / i3;
+    f.m2 = 3.0 * (1.0 / a - 1.0 / b) / i3;
+    return f;
+  }
+  const double xs = data / Rd, sig = 1.0 / sqrt(Rd);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int k = 0; k < G.n; ++k) {
+    const double x = fma(G.xi[k], sig, xs);
+    if (x >= a && x <= b) {
+      const double r = d_ref / x;
+      const double w = G.w[k] * (r * r) * (r * r);
+      s0 += w;
+      s1 = fma(w, x, s1);
+      s2 = fma(w * x, x, s2);
+    }
+  }
+  f.none = !(s0 > 0.0);
+  f.m1 = s1 / s0;
+  f.m2 = s2 / s0;
+  return f;
+}
+
+template <int KT, int L, bool MARG = false>
 __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, int ts, double ra,
                                             double dec, double psi, double incl, double phi,
-                                            double tref, double dist, double g[7]) {
+                                            double tref, double dist, double g[7], const DistRule* dm = nullptr) {
   typedef Cls<L> CL;
   constexpr int NI = CL::NI;
   constexpr int NY = CL::NY;
@@ -304,16 +361,30 @@ __device__ __forceinline__ double eval_grad(PDesc P, double* __restrict__ trig, 
     }
   }
 
-  const double x = P->d_ref / dist;
-  const double x2 = x * x;
-  const double lnL = x * data - x2 * quad;
+  double x, x2, lnL;
+  bool none = false;
+  if constexpr (MARG) {
+    const DistFactors Df = dist_factors(P, dist, data, quad, bad, *dm, true);
+    x = Df.m1;
+    x2 = Df.m2;
+    lnL = Df.lnL;
+    none = Df.none;
+  } else {
+    x = P->d_ref / dist;
+    x2 = x * x;
+    lnL = x * data - x2 * quad;
+  }
   g[0] = -(x * gg - x2 * qg);          // d/dra = -d/dgha
   g[1] = x * gdec - x2 * qdec;
   g[2] = x * gpsi - x2 * qpsi;
   g[3] = x * gi - x2 * qi;             // d/d incl
   g[4] = x * gf - x2 * qf;
   g[5] = x * gt;
-  g[6] = -x * data + 2.0 * x2 * quad;  // d/d ln(dist), x = D_ref e^{-ln dist}
+  g[6] = MARG ? 0.0 : -x * data + 2.0 * x2 * quad;  // d/d ln(dist), x = D_ref e^{-ln dist}
+  if (none) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) g[a] = 0.0;
+  }
   if (bad) {
     const double nan = __builtin_nan("");
 #pragma unroll
@@ -342,10 +413,10 @@ __device__ __forceinline__ double gsum(double v) {
   for (int off = G / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
-template <int KT, int L, int G>
+template <int KT, int L, int G, bool MARG = false>
 __device__ __forceinline__ double eval_grad_group(PDesc P, double ra, double dec, double psi, double incl,
                                                   double phi, double tref, double dist, double* tab,
-                                                  double g[7]) {
+                                                  double g[7], const DistRule* dm = nullptr) {
   constexpr int NI = 2 * L;
   constexpr int NY = L + 1;
   const int lg = (int)(threadIdx.x & (G - 1));
@@ -555,16 +626,30 @@ __device__ __forceinline__ double eval_grad_group(PDesc P, double ra, double dec
   qi = gsum<G>(qi);
   qf = gsum<G>(qf);
   bad = gsum<G>(bad);
-  const double x = P->d_ref / dist;
-  const double x2 = x * x;
-  const double lnL = x * data - x2 * quad;
+  double x, x2, lnL;
+  bool none = false;
+  if constexpr (MARG) {
+    const DistFactors Df = dist_factors(P, dist, data, quad, bad != 0.0, *dm, true);
+    x = Df.m1;
+    x2 = Df.m2;
+    lnL = Df.lnL;
+    none = Df.none;
+  } else {
+    x = P->d_ref / dist;
+    x2 = x * x;
+    lnL = x * data - x2 * quad;
+  }
   g[0] = -(x * gg - x2 * qg);
   g[1] = x * gdec - x2 * qdec;
   g[2] = x * gpsi - x2 * qpsi;
   g[3] = x * gi - x2 * qi;
   g[4] = x * gf - x2 * qf;
   g[5] = x * gt;
-  g[6] = -x * data + 2.0 * x2 * quad;
+  g[6] = MARG ? 0.0 : -x * data + 2.0 * x2 * quad;
+  if (none) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) g[a] = 0.0;
+  }
   if (bad != 0.0) {
     const double nan = __builtin_nan("");
 #pragma unroll

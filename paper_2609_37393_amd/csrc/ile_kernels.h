@@ -411,11 +411,10 @@ __global__ void __launch_bounds__(256) k_refine(const PointDesc* __restrict__ de
 }
 
 // Gradient: one lane per sample, grid-stride.
-template <int KT, int L>
-__global__ void __launch_bounds__(256) k_grad(const PointDesc* __restrict__ P,
-                                              const double* __restrict__ theta, int64_t n,
-                                              double* __restrict__ lnL, double* __restrict__ grad,
-                                              int coords) {
+template <int KT, int L, bool MARG>
+__device__ __forceinline__ void grad_lanes(const PointDesc* __restrict__ P, const double* __restrict__ theta,
+                                           int64_t n, double* __restrict__ lnL, double* __restrict__ grad,
+                                           int coords, const DistRule* dm) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* trig = reinterpret_cast<double*>(smem) + threadIdx.x;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -425,8 +424,8 @@ __global__ void __launch_bounds__(256) k_grad(const PointDesc* __restrict__ P,
     double incl = c3, dist = th[6 * n];
     const bool ok = theta_coords(coords, incl, dist);
     double g[7];
-    double l = eval_grad<KT, L>(opaque(P), trig, blockDim.x, th[0], th[n], th[2 * n], incl, th[4 * n],
-                                th[5 * n], dist, g);
+    double l = eval_grad<KT, L, MARG>(opaque(P), trig, blockDim.x, th[0], th[n], th[2 * n], incl, th[4 * n],
+                                      th[5 * n], dist, g, dm);
     grad_coords(coords, c3, dist, g[3], g[6]);
     if (!ok) {
       l = __builtin_nan("");
@@ -439,17 +438,34 @@ __global__ void __launch_bounds__(256) k_grad(const PointDesc* __restrict__ P,
   }
 }
 
+template <int KT, int L>
+__global__ void __launch_bounds__(256) k_grad(const PointDesc* __restrict__ P,
+                                              const double* __restrict__ theta, int64_t n,
+                                              double* __restrict__ lnL, double* __restrict__ grad,
+                                              int coords) {
+  grad_lanes<KT, L, false>(P, theta, n, lnL, grad, coords, nullptr);
+}
+
+// The same for the likelihood marginalised over distance under the rule `dm`
+// (ln L_d and its gradient; row 6 of theta is not used).
+template <int KT, int L>
+__global__ void __launch_bounds__(256) k_grad_dm(const PointDesc* __restrict__ P,
+                                                 const double* __restrict__ theta, int64_t n,
+                                                 double* __restrict__ lnL, double* __restrict__ grad,
+                                                 int coords, DistRule dm) {
+  grad_lanes<KT, L, true>(P, theta, n, lnL, grad, coords, &dm);
+}
+
 
 // Gradient, a group of GRAD_G lanes per sample (batches too small to fill the
 // GPU one lane per sample).  A wavefront holds 64 / GRAD_G samples; groups
 // past the end repeat the last sample and drop it.  Lanes 0..6 of a group
 // write the seven components.
 constexpr int GRAD_G = 16;
-template <int KT, int L>
-__global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__ P,
-                                                   const double* __restrict__ theta, int64_t n,
-                                                   double* __restrict__ lnL, double* __restrict__ grad,
-                                                   int coords) {
+template <int KT, int L, bool MARG>
+__device__ __forceinline__ void grad_groups(const PointDesc* __restrict__ P, const double* __restrict__ theta,
+                                            int64_t n, double* __restrict__ lnL, double* __restrict__ grad,
+                                            int coords, const DistRule* dm) {
   constexpr int SPW = 64 / GRAD_G;  // samples per wavefront
   __shared__ double tabs[4 * SPW * GRAD_TAB(L, KT)];
   const int lg = (int)(threadIdx.x & (GRAD_G - 1));
@@ -465,8 +481,8 @@ __global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__
     double incl = c3, dist = th[6 * n];
     const bool ok = theta_coords(coords, incl, dist);
     double g[7];
-    double l = eval_grad_group<KT, L, GRAD_G>(opaque(P), th[0], th[n], th[2 * n], incl, th[4 * n],
-                                              th[5 * n], dist, tab, g);
+    double l = eval_grad_group<KT, L, GRAD_G, MARG>(opaque(P), th[0], th[n], th[2 * n], incl, th[4 * n],
+                                                    th[5 * n], dist, tab, g, dm);
     grad_coords(coords, c3, dist, g[3], g[6]);
     if (!ok) {
       l = __builtin_nan("");
@@ -483,9 +499,26 @@ __global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__
   }
 }
 
+template <int KT, int L>
+__global__ void __launch_bounds__(256) k_grad_wide(const PointDesc* __restrict__ P,
+                                                   const double* __restrict__ theta, int64_t n,
+                                                   double* __restrict__ lnL, double* __restrict__ grad,
+                                                   int coords) {
+  grad_groups<KT, L, false>(P, theta, n, lnL, grad, coords, nullptr);
+}
+
+template <int KT, int L>
+__global__ void __launch_bounds__(256) k_grad_wide_dm(const PointDesc* __restrict__ P,
+                                                      const double* __restrict__ theta, int64_t n,
+                                                      double* __restrict__ lnL, double* __restrict__ grad,
+                                                      int coords, DistRule dm) {
+  grad_groups<KT, L, true>(P, theta, n, lnL, grad, coords, &dm);
+}
+
 typedef void (*tile_fn)(TileArgs);
 typedef void (*refine_fn)(const PointDesc*, const double*, int64_t, const int32_t*, const int32_t*, double*);
 typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, double*, int);
+typedef void (*grad_dm_fn)(const PointDesc*, const double*, int64_t, double*, double*, int, DistRule);
 
 // Getters (one translation unit per detector class and kernel kind).
 #define RIFT_DECL_GETTERS(KT)                        \
@@ -498,7 +531,9 @@ typedef void (*grad_fn)(const PointDesc*, const double*, int64_t, double*, doubl
   tile_fn get_tilesea_kt##KT(int lset);              \
   refine_fn get_refine_kt##KT(int lset);             \
   grad_fn get_grad_kt##KT(int L);                   \
-  grad_fn get_gradw_kt##KT(int L);
+  grad_fn get_gradw_kt##KT(int L);                  \
+  grad_dm_fn get_graddm_kt##KT(int L);              \
+  grad_dm_fn get_gradwdm_kt##KT(int L);
 RIFT_DECL_GETTERS(2)
 RIFT_DECL_GETTERS(3)
 RIFT_DECL_GETTERS(5)

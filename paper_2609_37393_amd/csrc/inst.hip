@@ -88,6 +88,24 @@ grad_fn RIFT_CAT(get_gradw_kt, RIFT_KT)(int L) {
     default: return nullptr;
   }
 }
+grad_dm_fn RIFT_CAT(get_graddm_kt, RIFT_KT)(int L) {
+  switch (L) {
+    case 2: return k_grad_dm<RIFT_KT, 2>;
+    case 3: return k_grad_dm<RIFT_KT, 3>;
+    case 4: return k_grad_dm<RIFT_KT, 4>;
+    case 8: return k_grad_dm<RIFT_KT, 8>;
+    default: return nullptr;
+  }
+}
+grad_dm_fn RIFT_CAT(get_gradwdm_kt, RIFT_KT)(int L) {
+  switch (L) {
+    case 2: return k_grad_wide_dm<RIFT_KT, 2>;
+    case 3: return k_grad_wide_dm<RIFT_KT, 3>;
+    case 4: return k_grad_wide_dm<RIFT_KT, 4>;
+    case 8: return k_grad_wide_dm<RIFT_KT, 8>;
+    default: return nullptr;
+  }
+}
 #endif
 
 }  // namespace rift

@@ -1222,6 +1222,14 @@ grad_fn pick_gradw_kt(int KT, int L) {
     default: return get_gradw_kt8(L);
   }
 }
+grad_dm_fn pick_graddm_kt(int KT, int L, bool wide) {
+  switch (KT) {
+    case 2: return wide ? get_gradwdm_kt2(L) : get_graddm_kt2(L);
+    case 3: return wide ? get_gradwdm_kt3(L) : get_graddm_kt3(L);
+    case 5: return wide ? get_gradwdm_kt5(L) : get_graddm_kt5(L);
+    default: return wide ? get_gradwdm_kt8(L) : get_graddm_kt8(L);
+  }
+}
 
 int validate_config(const rift_ile_config* c) {
   if (!c) return RIFT_EINVAL;
@@ -1807,74 +1815,8 @@ extern "C" int rift_ile_gauss_hermite(int n, double* nodes, double* weights) {
 
 namespace {
 
-// Gradient of the distance marginal.  The sample's state at x = 1 and at
-// x = 2 (row 6, ln D, set to ln d_ref and ln(d_ref / 2)).
-__global__ void k_gdm_prep(int64_t n, const double* __restrict__ theta, double lnd1, double lnd2,
-                           double* __restrict__ t1, double* __restrict__ t2) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      const double v = theta[a * n + i];
-      t1[a * n + i] = v;
-      t2[a * n + i] = v;
-    }
-    t1[6 * n + i] = lnd1;
-    t2[6 * n + i] = lnd2;
-  }
-}
-
-// lnL(x) = K x - R x^2 / 2 exactly, so from lnL and its gradient at x = 1, 2:
-// K = 2 l1 - l2 / 2, R = 2 l1 - l2, grad K = 2 g1 - g2 / 2, grad R = 2 g1 - g2.
-// ln L_d by the rule (dist_marginal), and d ln L_d = <x> grad K - <x^2> grad R
-// / 2 with the moments under the distance posterior taken by the same rule's
-// node weights W_i p_x(x_i) (the prior's moments m1p, m2p where the model has
-// no power); no node inside the prior: derivative 0; a NaN sample: NaN.
-__global__ void k_gdm_combine(int64_t n, DistRule G, double d_ref, double m1p, double m2p,
-                              const double* __restrict__ l1, const double* __restrict__ l2,
-                              const double* __restrict__ g1, const double* __restrict__ g2,
-                              double* __restrict__ lnLd, double* __restrict__ grad) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double a1 = l1[i], a2 = l2[i];
-    const double K = 2.0 * a1 - 0.5 * a2, R = 2.0 * a1 - a2;
-    Terms t;
-    t.data = K;
-    t.quad = 0.5 * R;
-    t.wq = 0.0;
-    t.bad = !(fabs(a1) <= 1.0e300) || !(fabs(a2) <= 1.0e300);
-    const double ld = dist_marginal(G, d_ref, t);
-    double m1 = m1p, m2 = m2p;
-    bool none = false;
-    if (R > 0.0 && !t.bad) {
-      const double xs = K / R, sig = 1.0 / sqrt(R);
-      const double xlo = d_ref / G.d_max, xhi = d_ref / G.d_min;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      for (int k = 0; k < G.n; ++k) {
-        const double x = fma(G.xi[k], sig, xs);
-        if (x >= xlo && x <= xhi) {
-          const double r = d_ref / x;
-          const double w = G.w[k] * (r * r) * (r * r);
-          s0 += w;
-          s1 = fma(w, x, s1);
-          s2 = fma(w * x, x, s2);
-        }
-      }
-      none = !(s0 > 0.0);
-      m1 = s1 / s0;
-      m2 = s2 / s0;
-    }
-    if (lnLd) lnLd[i] = ld;
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      const double b1 = g1[a * n + i], b2 = g2[a * n + i];
-      const double dK = 2.0 * b1 - 0.5 * b2, dR = 2.0 * b1 - b2;
-      double v = m1 * dK - 0.5 * m2 * dR;
-      if (none) v = 0.0;
-      if (t.bad) v = __builtin_nan("");
-      grad[a * n + i] = v;
-    }
-    grad[6 * n + i] = t.bad ? __builtin_nan("") : 0.0;
-  }
-}
+int plan_grad_rule(rift_ile_plan p, int32_t point, int64_t n, const double* theta, int coords, double* lnL,
+                   double* grad, bool marg, void* stream);
 
 // The plan's distance rule for `prior` (nodes cached per node count).
 int set_dist_rule(rift_ile_plan p, const rift_ile_dist_prior* prior) {
@@ -1928,29 +1870,8 @@ int rift_ile_plan_grad_dmarg(rift_ile_plan p, int32_t point, int64_t n, const do
   int rc = set_dist_rule(p, prior);
   if (rc) return rc;
   if (n == 0) return RIFT_OK;
-  if (check_dev_ptr(theta) || check_dev_ptr(grad) || (lnLd && check_dev_ptr(lnLd))) return RIFT_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
-  p->last = st;
-  const double d_ref = p->h_desc[point].d_ref;
-  // the prior's moments of x = d_ref / D for p_x ~ x^-4 on [a, b]
-  const double a = d_ref / prior->d_max, b = d_ref / prior->d_min;
-  const double i3 = 1.0 / (a * a * a) - 1.0 / (b * b * b);
-  const double m1p = 1.5 * (1.0 / (a * a) - 1.0 / (b * b)) / i3, m2p = 3.0 * (1.0 / a - 1.0 / b) / i3;
-  // stream-ordered scratch: the two states, their gradients, their lnL
-  double* w = nullptr;
-  if (hipMallocAsync((void**)&w, sizeof(double) * 30 * (size_t)n, st) != hipSuccess) return RIFT_ENOMEM;
-  double *t1 = w, *t2 = w + 7 * n, *g1 = w + 14 * n, *g2 = w + 21 * n, *l1 = w + 28 * n, *l2 = w + 29 * n;
-  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-  constexpr int coords = RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST;
-  hipLaunchKernelGGL(k_gdm_prep, dim3(grid), dim3(256), 0, st, n, theta, log(d_ref), log(0.5 * d_ref), t1, t2);
-  rc = rift_ile_plan_grad(p, point, n, t1, coords, l1, g1, stream);
-  if (!rc) rc = rift_ile_plan_grad(p, point, n, t2, coords, l2, g2, stream);
-  if (!rc)
-    hipLaunchKernelGGL(k_gdm_combine, dim3(grid), dim3(256), 0, st, n, p->dm, d_ref, m1p, m2p, (const double*)l1,
-                       (const double*)l2, (const double*)g1, (const double*)g2, lnLd, grad);
-  if (!rc && hipGetLastError() != hipSuccess) rc = RIFT_EDEVICE;
-  if (hipFreeAsync(w, st) != hipSuccess && !rc) rc = RIFT_EDEVICE;
-  return rc;
+  // one adjoint pass: its epilogue takes the distance posterior's moments
+  return plan_grad_rule(p, point, n, theta, RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST, lnLd, grad, true, stream);
 }
 
 int rift_ile_plan_lnZ_tmarg(rift_ile_plan p, const double* theta, const double* lnw, const rift_ile_time_rule* rule,
@@ -2144,8 +2065,14 @@ int rift_ile_plan_refined(rift_ile_plan p, int64_t* n_refined) {
   return RIFT_OK;
 }
 
-int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, int coords,
-                       double* lnL, double* grad, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The plan's gradient launch; with `marg`, of the likelihood marginalised over
+// distance under the plan's current distance rule.
+int plan_grad_rule(rift_ile_plan p, int32_t point, int64_t n, const double* theta, int coords, double* lnL,
+                   double* grad, bool marg, void* stream) {
   if (!p || point < 0 || point >= p->n_points || n < 0) return RIFT_EINVAL;
   if (coords < 0 || coords > (RIFT_COORD_COS_INCL | RIFT_COORD_LN_DIST)) return RIFT_EINVAL;
   if (n == 0) return RIFT_OK;
@@ -2156,7 +2083,8 @@ int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* 
   // a batch that cannot give every CU 256 samples runs 16 lanes per sample
   const bool wide = n <= (int64_t)256 * p->di.n_cu;
   grad_fn f = wide ? pick_gradw_kt(p->KT, D.L) : pick_grad_kt(p->KT, D.L);
-  if (!f) return RIFT_EUNSUPPORTED;
+  grad_dm_fn fdm = marg ? pick_graddm_kt(p->KT, D.L, wide) : nullptr;
+  if (!f || (marg && !fdm)) return RIFT_EUNSUPPORTED;
   const int64_t blocks = wide ? std::min<int64_t>((n + 15) / 16, (int64_t)p->di.n_cu * 8)
                               : std::min<int64_t>((n + 255) / 256, (int64_t)p->di.n_cu * 16);
   const size_t shm = wide ? 0 : (size_t)trig_rows(lbit(D.L)) * 256 * sizeof(double);
@@ -2168,12 +2096,25 @@ int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* 
     p->ev.push_back(e1);
     HCHK(hipEventRecord(e0, st));
   }
-  hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), shm, st,
-                     (const PointDesc*)(p->d_desc + point),
-                     theta, n, lnL, grad, coords);
+  if (marg)
+    hipLaunchKernelGGL(fdm, dim3((unsigned)blocks), dim3(256), shm, st, (const PointDesc*)(p->d_desc + point), theta,
+                       n, lnL, grad, coords, p->dm);
+  else
+    hipLaunchKernelGGL(f, dim3((unsigned)blocks), dim3(256), shm, st,
+                       (const PointDesc*)(p->d_desc + point),
+                       theta, n, lnL, grad, coords);
   HCHK(hipGetLastError());
   if (p->profiling) HCHK(hipEventRecord(e1, st));
   return RIFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rift_ile_plan_grad(rift_ile_plan p, int32_t point, int64_t n, const double* theta, int coords,
+                       double* lnL, double* grad, void* stream) {
+  return plan_grad_rule(p, point, n, theta, coords, lnL, grad, false, stream);
 }
 
 int rift_ile_plan_tune(rift_ile_plan p, const double* theta, const double* lnw, void* stream) {
