@@ -212,3 +212,50 @@ def test_grad_dmarg_matches_oracle(ile, oracle_mod, snr, d_box, nodes):
         assert np.all(np.abs(g[a, ok] - want_g[a, ok]) <= bar[ok]), (a, np.max(np.abs(g[a, ok] - want_g[a, ok]) / bar[ok]))
     empty = np.isneginf(want_l)
     assert np.all(g[:, empty] == 0.0)
+
+
+def test_grad_dmarg_lane_form_sampled(ile, oracle_mod):
+    """A batch above 256 samples per CU runs the lane-per-sample form of the
+    marginal gradient (k_grad_dm); sampled columns against the oracle, and
+    the group form on the same columns (a batch of those alone) within the
+    same bars."""
+    import torch
+
+    pt = synth.make_point(3, 9, 2000, 16384.0, 60.0, 85)
+    n = 70_000
+    th = synth.prior_samples(n, 86)
+    near, _ = synth.weighted_samples(4000, 87)
+    l = oracle_mod.lnL(pt, near)
+    th[:, :300] = near[:, np.argsort(l)[-300:]]
+    c = th.copy()
+    c[3] = np.cos(th[3])
+    c[6] = np.log(th[6])
+    d_box, nodes = (10.0, 1000.0), 20
+    plan = ile.Plan([pt], [n])
+    ld, g = plan.grad_dmarg(0, torch.as_tensor(c, device="cuda").contiguous(), *d_box, nodes)
+    ld, g = ld.cpu().numpy(), g.cpu().numpy()
+    idx = np.r_[np.arange(300), np.random.default_rng(2).choice(np.arange(300, n), 300, replace=False)]
+    cs = c[:, idx]
+    want_l, want_g = oracle_mod.grad_dmarg(pt, cs, *d_box, nodes)
+    ld2, g2 = plan.grad_dmarg(0, torch.as_tensor(cs, device="cuda").contiguous(), *d_box, nodes)
+    ld2, g2 = ld2.cpu().numpy(), g2.cpu().numpy()
+    plan.close()
+    t1 = oracle_mod._to_physical(cs)
+    t1[6] = pt["d_ref"]
+    bar_l = _bar(oracle_mod, pt, t1)
+    ok = np.isfinite(want_l) & np.isfinite(bar_l)
+    assert ok.sum() > 500
+    assert np.array_equal(np.isneginf(ld[idx]), np.isneginf(want_l))
+    for got_l, got_g in ((ld[idx], g[:, idx]), (ld2, g2)):
+        assert np.all(np.abs(got_l[ok] - want_l[ok]) <= bar_l[ok])
+        t2 = t1.copy()
+        t2[6] = pt["d_ref"] / 2
+        _, a1 = oracle_mod.grad(pt, t1)
+        _, a2 = oracle_mod.grad(pt, t2)
+        dK, dR = np.abs(2 * a1 - 0.5 * a2), np.abs(2 * a1 - a2)
+        x_hi = pt["d_ref"] / d_box[0]
+        norm = np.sqrt(np.sum(want_g[:6] ** 2, axis=0))
+        for a in range(6):
+            bar = 1e-8 * (np.abs(want_g[a]) + 1e-3 * norm + x_hi * dK[a] + x_hi ** 2 * dR[a])
+            assert np.all(np.abs(got_g[a, ok] - want_g[a, ok]) <= bar[ok]), a
+        assert np.all(got_g[6] == 0.0)
