@@ -1093,6 +1093,7 @@ def extra_smc(ile, synth, torch, steps, particles=65536, cpu=True):
     lnWt = torch.zeros(n, dtype=torch.float64, device="cuda")
     secs, _ = time_steps(lambda: ile.smc_reweight(lnLt, lnWt.zero_(), 0.0, 0.5), 10, 2, torch)
     plan.close()
+    dm12 = _smc_dmarg_snr12(ile, synth, torch, box)
     return {"workload": "3 detectors, 9 modes (l<=3), Q 6554 samples at 32768 Hz, SNR 5; 65536 particles from the "
                         "prior; adaptive SMC ladder (target fraction 0.5), 2 tempered HMC moves per rung",
             "rungs": rungs, "ladder_ms": 1e3 * wall, "ms_per_rung": 1e3 * wall / max(1, rungs),
@@ -1101,7 +1102,101 @@ def extra_smc(ile, synth, torch, steps, particles=65536, cpu=True):
             "move_acceptance": acc, "reweight_ms": 1e3 * secs / 10,
             "rwm_moves": {"moves_per_rung": 4, "rungs": rungs_r, "ladder_ms": 1e3 * wall_r,
                           "ms_per_rung": 1e3 * wall_r / max(1, rungs_r), "final_beta": beta_r, "lnZ_smc": lnZ_r,
-                          "move_acceptance": acc_r}}
+                          "move_acceptance": acc_r},
+            "distance_marginalised_snr12": dm12}
+
+
+def _smc_dmarg_snr12(ile, synth, torch, box, n=262144):
+    """The SMC ladder on the likelihood marginalised over distance against the
+    same ladder on all seven rows, for a 3-detector, 9-mode point at SNR 12:
+    262144 particles from the prior, rungs at a conditional effective-size
+    fraction of 0.9, 8 tempered HMC moves per rung of 4 leapfrog steps of
+    0.15 (widths 0.2 x the cloud's spread); on the marginal the moves are
+    rift_ile_plan_hmc_dmarg's (the distance row carries no momentum).  The
+    reference is brute-force prior Monte Carlo of the marginal likelihood,
+    1e9 prior draws (rift_ile_mixture_is with alpha = 1) through
+    rift_ile_plan_lnZ_dmarg; both ladders estimate the same ln Z."""
+    pt = synth.make_point(3, 9, 6554, 32768.0, 12.0, 61)
+    dm = (10.0, 1000.0, 20)
+    th = synth.prior_samples(n, 5)
+    th[3] = np.cos(th[3])
+    th[6] = np.log(th[6])
+    plan = ile.Plan([pt], [n])
+
+    def ladder(marg, seed):
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        c = torch.as_tensor(th, device="cuda").contiguous()
+        c2 = torch.empty_like(c)
+        lnL = torch.empty(n, dtype=torch.float64, device="cuda")
+        g = torch.empty((7, n), dtype=torch.float64, device="cuda")
+        if marg:
+            plan.grad_dmarg(0, c, *dm, lnLd_out=lnL, grad_out=g)
+        else:
+            plan.grad(0, c, lnL_out=lnL, grad_out=g, coords="sampler")
+        lnW = torch.zeros(n, dtype=torch.float64, device="cuda")
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        beta, lnZ, rungs, acc_sum = 0.0, 0.0, 0, 0.0
+        while beta < 1.0 and rungs < 200:
+            ile.smc_reweight(lnL, lnW, beta, 0.9, out=out)
+            o = out.cpu().numpy()
+            beta, lnZ, rungs = float(o[0]), lnZ + float(o[1]), rungs + 1
+            u = float(torch.rand(1, generator=gen, device="cuda").item())
+            anc = torch.empty(n, dtype=torch.int64, device="cuda")
+            ile.smc_resample(lnW, u, c, c2, anc)
+            c, c2 = c2, c
+            lnW.zero_()
+            sig = np.maximum(0.2 * c.std(dim=1).cpu().numpy(), 1e-12)
+            for _ in range(8):
+                z = torch.randn((7, n), dtype=torch.float64, device="cuda", generator=gen)
+                uu = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen)
+                _, acc = plan.hmc(0, c, z, uu, sig, 0.15, 4, box, lnL_out=lnL, beta=beta,
+                                  dmarg=dm if marg else None)
+                acc_sum += float(acc.double().mean().item())
+        return lnZ, rungs, acc_sum / max(1, 8 * rungs)
+
+    ladder(True, 1)  # warm
+    res = {}
+    for marg, key in ((True, "marginal"), (False, "all_rows")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = [ladder(marg, 11 + 100 * s) for s in range(3)]
+        torch.cuda.synchronize()
+        z = [r[0] for r in runs]
+        res[key] = {"lnZ_smc_seeds": z, "lnZ_smc_mean": float(np.mean(z)), "lnZ_smc_sd": float(np.std(z, ddof=1)),
+                    "rungs": float(np.mean([r[1] for r in runs])),
+                    "move_acceptance": float(np.mean([r[2] for r in runs])),
+                    "ladder_ms": 1e3 * (time.perf_counter() - t0) / 3}
+    plan.close()
+    Nc, chunks = 4_000_000, 250
+    plan_ref = ile.Plan([pt], [Nc])
+    gref = torch.Generator(device="cuda")
+    gref.manual_seed(3)
+    zeros = torch.zeros(Nc, dtype=torch.float64, device="cuda")
+    ll = torch.empty(Nc, dtype=torch.float64, device="cuda")
+    m_run, s_run, s2_run = -np.inf, 0.0, 0.0
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter()
+    for _ in range(chunks):
+        vv = torch.rand((7, Nc), dtype=torch.float64, device="cuda", generator=gref)
+        thr, _, _, _ = ile.mixture_is(1.0, [], None, None, 1.0, box, vv, vv, zeros)
+        plan_ref.lnZ_dmarg(thr, *dm, lnL_out=ll)
+        lm = float(ll.max())
+        w = torch.exp(ll - lm)
+        s1, s2 = float(w.sum()), float((w * w).sum())
+        m = max(m_run, lm)
+        s_run = s_run * np.exp(m_run - m) + s1 * np.exp(lm - m)
+        s2_run = s2_run * np.exp(2 * (m_run - m)) + s2 * np.exp(2 * (lm - m))
+        m_run = m
+    torch.cuda.synchronize()
+    ref_s = time.perf_counter() - t_ref
+    plan_ref.close()
+    res.update({"workload": "3 detectors, 9 modes, SNR 12; 262144 particles; ladder at fraction 0.9, 8 HMC moves "
+                            "per rung (4 leapfrog steps of 0.15); 3 seeds each, on L marginalised over distance "
+                            "(20 nodes) and on all 7 rows",
+                "lnZ_prior_mc_1e9": float(m_run + np.log(s_run / (chunks * Nc))),
+                "kish_prior_mc_1e9": s_run ** 2 / s2_run, "prior_mc_1e9_s": ref_s})
+    return res
 
 
 def extra_is(ile, synth, torch, steps, draws=1_000_000, cpu=True):
