@@ -21,7 +21,9 @@ Bars (written here):
   wherever ln u lies more than 1e-6 (1 + |d|) from the log ratio d (the
   likelihood's FP64 bar times beta, far below that); accepted states within
   1e-13 (|c| + sum |L z|) of the oracle's proposal, rejected ones and their
-  lnL bit for bit; accepted lnL within the FP64 bar of the oracle's.
+  lnL bit for bit; accepted lnL within the FP64 bar of the oracle's;
+* at full size (4e6 particles) the rung and dlnZ against the local-Gaussian
+  closed forms within six delta-method standard errors.
 """
 import numpy as np
 import pytest
@@ -234,3 +236,49 @@ def test_rwm_matches_oracle(ile, oracle_mod, beta):
     assert int(st2.cpu()[0]) == 1 and not acc2.any()
     assert torch.equal(tc2, _dev(c0)) and torch.equal(tl2, _dev(l0))
     plan.close()
+
+
+@pytest.mark.parametrize("beta,target", [(0.05, 0.5), (0.3, 0.9), (0.8, 0.9), (0.8, 0.5)])
+def test_reweight_local_gaussian_limit(ile, beta, target):
+    """The library's rung and normalisation ratio at full size against the
+    local-Gaussian closed forms (Eq. (temper:cost) and the scaling
+    Z_a ~ a^(-d/2) it comes from): 4e6 exact draws of the rung at beta for
+    L = exp(-|x|^2 / 2) in d = 6 dimensions under a flat prior.  The chosen
+    step dbeta meets [beta (beta + 2 dbeta) / (beta + dbeta)^2]^(d/2) =
+    target (or is the whole remaining step when [beta (2 - beta)]^(d/2)
+    already meets it), dlnZ = -(d/2) ln((beta + dbeta) / beta), and the new
+    weights are normalised; each within six delta-method standard errors."""
+    import torch
+
+    n, d = 4_000_000, 6
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(1000 * beta + 100 * target))
+    x = torch.randn((n, d), dtype=torch.float64, device="cuda", generator=g) / np.sqrt(beta)
+    lnL = (-0.5 * (x * x).sum(dim=1)).contiguous()
+    del x
+    lnW = torch.zeros(n, dtype=torch.float64, device="cuda")
+    out = ile.smc_reweight(lnL, lnW, beta, target).cpu().numpy()
+    b, dz = float(out[0]), float(out[1])
+
+    def se_log_frac(db):
+        r = torch.exp(db * lnL)
+        m1, m2 = r.mean(), (r * r).mean()
+        g1, g2 = 2.0 * r / m1, -(r * r) / m2
+        v = (g1.var() + g2.var() + 2.0 * ((g1 - g1.mean()) * (g2 - g2.mean())).mean())
+        return float(torch.sqrt(v / n)), float(r.std() / (r.mean() * np.sqrt(n)))
+
+    rest = 1.0 - beta
+    full = 0.5 * d * np.log(beta * (2.0 - beta))
+    se_full, _ = se_log_frac(rest)
+    if full - np.log(target) > 6.0 * se_full:
+        assert b == 1.0
+    else:
+        assert beta < b < 1.0
+        db = b - beta
+        se_f, _ = se_log_frac(db)
+        frac = 0.5 * d * np.log(beta * (beta + 2.0 * db) / (beta + db) ** 2)
+        assert abs(frac - np.log(target)) <= 6.0 * se_f, (b, frac, np.log(target), se_f)
+    _, se_z = se_log_frac(b - beta)
+    assert abs(dz + 0.5 * d * np.log(b / beta)) <= 6.0 * se_z, (dz, -0.5 * d * np.log(b / beta), se_z)
+    m = float(lnW.max())
+    assert abs(m + np.log(float(torch.exp(lnW - m).sum())) ) <= 1e-9

@@ -17,7 +17,10 @@ moves, against what the mathematics fixes:
 * the cloud's random-walk Metropolis move keeps a correlated Gaussian
   target under a mismatched proposal; its increments have covariance
   scale C; a ratio of 1 is always taken and a NaN target never; at beta = 0
-  it is the prior's Metropolis move and at beta = 1 the move on L p.
+  it is the prior's Metropolis move and at beta = 1 the move on L p;
+* in the local Gaussian limit the fraction, the chosen rung and the update
+  follow from Z_a ~ a^(-d/2) in closed form, with the retained fraction
+  [beta (2 - beta)]^(d/2) of Eq. (temper:cost) at the whole remaining step.
 """
 import numpy as np
 
@@ -189,3 +192,50 @@ def test_rwm_proposal_and_decisions(oracle_mod):
     want_c, _, want_a = oracle_mod.rwm_chain(post, c, z, u, C * 0.01, 1.0)
     assert np.array_equal(got_a, want_a)
     assert 0.05 < got_a.mean() < 0.95
+
+
+def _tempered_gauss(n, d, beta, seed):
+    """Exact draws x ~ N(0, I / beta) of the tempered target L^beta for
+    L = exp(-|x|^2 / 2) under a flat prior, and their ln L."""
+    x = np.random.default_rng(seed).normal(size=(n, d)) / np.sqrt(beta)
+    return -0.5 * np.sum(x * x, axis=1)
+
+
+def _log_frac_se(lnL, dbeta):
+    """Delta-method standard error of the log of the sampled fraction
+    mean(r)^2 / mean(r^2), r = L^dbeta."""
+    r = np.exp(dbeta * lnL)
+    m1, m2 = r.mean(), (r * r).mean()
+    g = np.stack([2.0 * r / m1, -(r * r) / m2])
+    return float(np.sqrt(np.cov(g).sum() / r.size))
+
+
+def test_cess_local_gaussian_limit(oracle_mod):
+    """In the local Gaussian limit with a flat prior, Z_a scales as a^(-d/2),
+    so the fraction of the incremental weights L^dbeta over draws from the
+    rung at beta is Z_(beta+dbeta)^2 / (Z_beta Z_(beta+2 dbeta)) =
+    [beta (beta + 2 dbeta) / (beta + dbeta)^2]^(d/2) and the normalisation
+    ratio is (beta / (beta + dbeta))^(d/2); the whole remaining step
+    dbeta = 1 - beta gives the retained fraction [beta (2 - beta)]^(d/2) of
+    Eq. (temper:cost).  Exact draws of that limit check the oracle's
+    fraction, its chosen rung and its update within six standard errors."""
+    n, d = 400_000, 6
+    for beta, seed in ((0.05, 31), (0.3, 32), (0.8, 33)):
+        lnL = _tempered_gauss(n, d, beta, seed)
+        lnW = np.zeros(n)
+        rest = 1.0 - beta
+        want = 0.5 * d * np.log(beta * (2.0 - beta))
+        got = np.log(oracle_mod.smc_cess(lnW, lnL, rest))
+        assert abs(got - want) <= 6.0 * _log_frac_se(lnL, rest), (beta, got, want)
+        for target in (0.5, 0.9):
+            b = oracle_mod.smc_next_beta(lnW, lnL, beta, target)
+            db = b - beta
+            if want - np.log(target) > 6.0 * _log_frac_se(lnL, rest):
+                assert b == 1.0  # the whole remaining step qualifies
+            else:
+                assert 0.0 < db < rest
+                frac = 0.5 * d * np.log(beta * (beta + 2.0 * db) / (beta + db) ** 2)
+                assert abs(frac - np.log(target)) <= 6.0 * _log_frac_se(lnL, db), (beta, target, b)
+            dz, _ = oracle_mod.smc_update(lnW, lnL, beta, b)
+            r = np.exp(db * lnL)
+            assert abs(dz + 0.5 * d * np.log(b / beta)) <= 6.0 * r.std() / (r.mean() * np.sqrt(n)), (beta, target, dz)
