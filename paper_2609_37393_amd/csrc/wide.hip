@@ -30,6 +30,17 @@
 // contraction walks, [k][pair][i][j] (Re U, Im U, Re V, Im V) with internal
 // mode indices and row stride equal to the capacity, so that the uniform
 // entries reach the lanes through the scalar path at constant offsets.
+//
+// For the longer mode sets (l <= 3 with 10 or more modes, l <= 4 with 13 or
+// more) the pair forms take the harmonic form of the static path instead:
+// each of Re G, Im G, Re H, Im H of a block is a trigonometric polynomial in
+// (incl, phiref) of degree 2L in each, with the parity that d_i d_j has in
+// incl (that of m_i - m_j, equal to that of m_i + m_j), so it lies in the
+// static path's real basis of class L (145 functions at L = 4).  A set-up
+// kernel projects every block onto that basis per call; a lane then sums
+// 4 B uniform coefficients against basis values built from cos(n incl),
+// sin(n incl), cos(q phiref), sin(q phiref), instead of 4 M^2 entries
+// (580 against 1764 at 21 modes).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,6 +62,7 @@ constexpr int WIDE_BLOCK_21 = 128;  // up to 21 terms: the coefficient columns i
 
 struct WideDesc {
   int32_t K, M, n_t, n_a, response, npairs;
+  int32_t hb, hb_pad;         // class L of the harmonic form of the pair forms, 0: the entries
   double t0, inv_dt, gmst, omega, d_ref;
   double dten[KMAX][6];      // D00, D11, D22, 2 D01, 2 D02, 2 D12
   double rpos[KMAX][3];      // light-seconds
@@ -60,7 +72,7 @@ struct WideDesc {
   int32_t odd[MMAX];
   double ycoef[MMAX][LMAXC + 1];
   const double* Q;           // caller's [K][n_a][M][n_t] complex
-  const double* UV;          // packed [K][pair][MC][MC][4] (see the kernel)
+  const double* UV;          // packed [K][pair][MC][MC][4], or [K][pair][B][4] coefficients (hb > 0)
 };
 static_assert(sizeof(WideDesc) <= 3584, "the description travels as a kernel argument");
 
@@ -162,6 +174,137 @@ struct PairForms {
   }
 };
 
+// The same four forms of one block in the harmonic basis of class L, summed
+// per harmonic q in phi: the rows of one q are consecutive and q increases
+// along them (basis_row), so
+// g[c] += cos(q phi) sum_n C[(n, cos)][c] T_n(incl)
+//       + sin(q phi) sum_n C[(n, sin)][c] T_n(incl),
+// T_n = cos(n incl) for even q and sin(n incl) for odd q (q = 0: the first
+// sum alone), with e^{i q phi} advanced by one factor e^{i phi} per q.
+// Every row's kind and degrees are template constants; no product of basis
+// values is formed, so only the cos(n incl), sin(n incl) tables stay live
+// across the pairs.
+template <int L>
+struct HarmForms {
+  static constexpr int B = Cls<L>::B;
+  struct Run {
+    double pc[4], ps[4];  // the two sums of the current q
+    double er, ei;        // e^{i q phi}
+  };
+  template <int J>
+  static __device__ __forceinline__ void term(const RIFT_CONST double* c, const double* cn, const double* sn,
+                                              double cf, double sf, double* g, Run& R) {
+    constexpr int rb = basis_row<L>(J);
+    constexpr int kind = rb & 15, nn = (rb >> 4) & 255, q = rb >> 12;
+    constexpr bool last = (J + 1 == B) || ((basis_row<L>(J + 1) >> 12) != q);
+    const double tn = (kind == 3 || kind == 4) ? sn[nn] : cn[nn];
+    const RIFT_CONST double* e = c + 4 * J;
+    if constexpr (kind == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g[k] = fma(e[k], tn, g[k]);
+    } else {
+      double* acc = (kind == 1 || kind == 3) ? R.pc : R.ps;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] = fma(e[k], tn, acc[k]);
+      if constexpr (last) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          g[k] = fma(R.pc[k], R.er, fma(R.ps[k], R.ei, g[k]));
+          R.pc[k] = 0.0;
+          R.ps[k] = 0.0;
+        }
+        const double nr = R.er * cf - R.ei * sf, ni = R.er * sf + R.ei * cf;
+        R.er = nr;
+        R.ei = ni;
+      }
+    }
+  }
+  template <int... J>
+  static __device__ __forceinline__ void all(const RIFT_CONST double* c, const double* cn, const double* sn,
+                                             double cf, double sf, double* g, std::integer_sequence<int, J...>) {
+    Run R;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) R.pc[k] = R.ps[k] = 0.0;
+    R.er = cf;  // the first group after q = 0 is q = 1
+    R.ei = sf;
+    (term<J>(c, cn, sn, cf, sf, g, R), ...);
+  }
+  static __device__ __forceinline__ void run(const RIFT_CONST double* c, const double* cn, const double* sn,
+                                             double cf, double sf, double* g) {
+    all(c, cn, sn, cf, sf, g, std::make_integer_sequence<int, B>{});
+  }
+};
+
+// Harmonic-basis coefficients of the pair forms, one block per (detector,
+// pair a <= b): Re G, Im G, Re H, Im H of the block sampled on an NG x NG
+// grid of (incl, phi) over [0, 2 pi)^2, NG = 4L + 4 (more than twice the
+// degree 2L in each), then projected on the basis rows (discrete
+// orthogonality on that grid).  U, V in the caller's order [K][A][A]
+// complex; out [K][pair][B][4].
+template <int L>
+__global__ void k_wide_basis(WideDesc D, const double* __restrict__ U, const double* __restrict__ V,
+                             double* __restrict__ out) {
+  constexpr int NG = 4 * L + 4, B = Cls<L>::B;
+  __shared__ double g[4][NG * NG];
+  const int k = blockIdx.x / D.npairs, pr = blockIdx.x - k * D.npairs;
+  int a = 0, rem = pr;
+  while (rem >= D.n_a - a) {
+    rem -= D.n_a - a;
+    ++a;
+  }
+  const int b = a + rem;
+  const int M = D.M, A = D.n_a * D.M;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int gp = threadIdx.x; gp < NG * NG; gp += blockDim.x) {
+    const double inc = two_pi * (gp / NG) / NG, ph = two_pi * (gp % NG) / NG;
+    double yr[MMAX], yi[MMAX];
+    for (int i = 0; i < M; ++i) {
+      double d = 0.0;
+      for (int q = 0; q <= LMAXC; ++q) d += D.ycoef[i][q] * (D.odd[i] ? sin(q * inc) : cos(q * inc));
+      double sm, cm;
+      sincos(D.m[i] * ph, &sm, &cm);
+      yr[i] = d * cm;
+      yi[i] = d * sm;
+    }
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < M; ++i) {
+      double tr = 0.0, ti = 0.0, wr = 0.0, wi = 0.0;
+      for (int j = 0; j < M; ++j) {
+        const int64_t o = 2 * (((int64_t)k * A + a * M + D.perm[i]) * A + b * M + D.perm[j]);
+        const double ur = U[o], ui = U[o + 1], vr = V[o], vi = V[o + 1];
+        tr += ur * yr[j] - ui * yi[j];
+        ti += ur * yi[j] + ui * yr[j];
+        wr += vr * yr[j] - vi * yi[j];
+        wi += vr * yi[j] + vi * yr[j];
+      }
+      v[0] += yr[i] * tr + yi[i] * ti;
+      v[1] += yr[i] * ti - yi[i] * tr;
+      v[2] += yr[i] * wr - yi[i] * wi;
+      v[3] += yr[i] * wi + yi[i] * wr;
+    }
+    for (int c = 0; c < 4; ++c) g[c][gp] = v[c];
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < B; r += blockDim.x) {
+    const int rb = basis_row<L>(r);
+    const int kind = rb & 15, nn = (rb >> 4) & 255, q = rb >> 12;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int gp = 0; gp < NG * NG; ++gp) {
+      const double inc = two_pi * (gp / NG) / NG, ph = two_pi * (gp % NG) / NG;
+      double t;
+      if (kind == 0) t = cos(nn * inc);
+      else if (kind == 1) t = cos(nn * inc) * cos(q * ph);
+      else if (kind == 2) t = cos(nn * inc) * sin(q * ph);
+      else if (kind == 3) t = sin(nn * inc) * cos(q * ph);
+      else t = sin(nn * inc) * sin(q * ph);
+      for (int c = 0; c < 4; ++c) acc[c] += g[c][gp] * t;
+    }
+    const double norm = 1.0 / ((double)NG * NG * (nn == 0 ? 1.0 : 0.5) * (q == 0 ? 1.0 : 0.5));
+    double* o = out + ((int64_t)blockIdx.x * B + r) * 4;
+    for (int c = 0; c < 4; ++c) o[c] = acc[c] * norm;
+  }
+}
+
 // cos(2 pi j / 5), sin(2 pi j / 5), j = 0..4: the five hour angles of the
 // rotation harmonics and the factors of their transform (e^{-2 pi i n j / 5}
 // is entry (n j) mod 5, conjugated).
@@ -200,7 +343,7 @@ __device__ __forceinline__ void sincos_small(double x, double* s, double* c) {
 // Occupancy: three wavefronts per SIMD (<= 168 VGPRs) for up to 5 modes, two
 // otherwise (the 25-mode capacity's Y alone holds 100 VGPRs).  NT is the
 // capacity of the coefficient columns in LDS (NT x BLK complex values).
-template <int MC, int NT, int BLK>
+template <int MC, int NT, int BLK, int HL = 0>
 __global__ void __launch_bounds__(BLK, MC <= 5 && NT <= 12 ? 3 : 2) k_wide(WideDesc D, const double* __restrict__ theta, int64_t n,
                                                               const double* __restrict__ lnw,
                                                               double* __restrict__ lnL, double* __restrict__ part) {
@@ -450,11 +593,20 @@ __global__ void __launch_bounds__(BLK, MC <= 5 && NT <= 12 ? 3 : 2) k_wide(WideD
       data += cre[a][t] * zr + cim[a][t] * zi;
     }
     // model-norm term over pairs a <= a'
-    const RIFT_CONST double* blk = as_const(D.UV) + (int64_t)k * D.npairs * (MC * MC * 4);
+    constexpr int BS = HL > 0 ? 4 * Cls<(HL > 0 ? HL : 2)>::B : MC * MC * 4;
+    const RIFT_CONST double* blk = as_const(D.UV) + (int64_t)k * D.npairs * BS;
     for (int a = 0; a < n_a; ++a) {
-      for (int b = a; b < n_a; ++b, blk += MC * MC * 4) {
+      for (int b = a; b < n_a; ++b, blk += BS) {
         double g[4] = {0.0, 0.0, 0.0, 0.0};  // Re G, Im G, Re H, Im H
-        PairForms<0, MC>::run(opaque(blk), M, yr, yi, g);
+        if constexpr (HL > 0) {
+          // the phase sequence is rebuilt per pair, not hoisted out of the
+          // loops (it would hold 4 HL values in registers throughout)
+          double cfo = cf, sfo = sf;
+          asm volatile("" : "+v"(cfo), "+v"(sfo));
+          HarmForms<HL>::run(opaque(blk), cn, sn, cfo, sfo, g);
+        }
+        else
+          PairForms<0, MC>::run(opaque(blk), M, yr, yi, g);
         const double gr = g[0], gi = g[1], hr = g[2], hi = g[3];
         const double car = cre[a][t], cai = cim[a][t], cbr = cre[b][t], cbi = cim[b][t];
         // conj(C_a) C_b G_ab and C_a C_b H_ab, counted twice off the diagonal
@@ -598,8 +750,15 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
   }
   D.Q = pt->Q;
   const int MC = pt->n_modes <= 5 ? 5 : (pt->n_modes <= 12 ? 12 : 25);
-  // stream-ordered scratch: the packed U/V blocks, then the blocks' (max, sum) pairs
-  const size_t uv_bytes = sizeof(double) * 4 * (size_t)D.K * D.npairs * MC * MC;
+  // the harmonic form where its basis is shorter than a block's entries
+  int lmax = 0;
+  for (int i = 0; i < pt->n_modes; ++i) lmax = std::max(lmax, (int)pt->lm[2 * i]);
+  const int M2 = pt->n_modes * pt->n_modes;
+  D.hb = (MC == 12 && lmax == 3 && Cls<3>::B < M2) ? 3 : (MC == 25 && lmax == 4 && Cls<4>::B < M2) ? 4 : 0;
+  const int blk_vals = D.hb == 3 ? 4 * Cls<3>::B : D.hb == 4 ? 4 * Cls<4>::B : 4 * MC * MC;
+  // stream-ordered scratch: the packed U/V blocks (or their coefficients),
+  // then the blocks' (max, sum) pairs
+  const size_t uv_bytes = sizeof(double) * (size_t)D.K * D.npairs * blk_vals;
   const size_t part_bytes = lnZ ? sizeof(double) * 2 * (size_t)nb : 0;
   hipStream_t st = (hipStream_t)stream;
   void* scratch = nullptr;
@@ -619,6 +778,15 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
         hipLaunchKernelGGL((k_wide<5, 12, WIDE_BLOCK>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
       break;
     case 12:
+      if (D.hb == 3) {
+        hipLaunchKernelGGL(k_wide_basis<3>, dim3((unsigned)(D.K * D.npairs)), dim3(256), 0, st, D, pt->U, pt->V,
+                           (double*)scratch);
+        if (wide21)
+          hipLaunchKernelGGL((k_wide<12, 21, WIDE_BLOCK_21, 3>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
+        else
+          hipLaunchKernelGGL((k_wide<12, 12, WIDE_BLOCK, 3>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
+        break;
+      }
       hipLaunchKernelGGL(k_wide_pack<12>, dim3(pgrid), dim3(256), 0, st, D, pt->U, pt->V, (double*)scratch);
       if (wide21)
         hipLaunchKernelGGL((k_wide<12, 21, WIDE_BLOCK_21>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
@@ -626,6 +794,15 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
         hipLaunchKernelGGL((k_wide<12, 12, WIDE_BLOCK>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
       break;
     default:
+      if (D.hb == 4) {
+        hipLaunchKernelGGL(k_wide_basis<4>, dim3((unsigned)(D.K * D.npairs)), dim3(256), 0, st, D, pt->U, pt->V,
+                           (double*)scratch);
+        if (wide21)
+          hipLaunchKernelGGL((k_wide<21, 21, WIDE_BLOCK_21, 4>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
+        else
+          hipLaunchKernelGGL((k_wide<21, 12, WIDE_BLOCK, 4>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
+        break;
+      }
       hipLaunchKernelGGL(k_wide_pack<25>, dim3(pgrid), dim3(256), 0, st, D, pt->U, pt->V, (double*)scratch);
       if (wide21)
         hipLaunchKernelGGL((k_wide<25, 21, WIDE_BLOCK_21>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);

@@ -41,7 +41,11 @@ def wide_scale(oracle_mod, pt, th):
     return np.abs(Kc * x) + np.abs(R * x * x / 2)
 
 
-# response, K, M, n_terms, n_t, fs, snr, omega, seed, n
+LM3 = [(2, m) for m in range(-2, 3)] + [(3, m) for m in range(-3, 4)]  # the twelve l <= 3 modes
+
+# response, K, M, n_terms, n_t, fs, snr, omega, seed, n[, modes]
+# (10 or more modes with l <= 3, and 13 or more with l <= 4, take the
+# harmonic form of the pair forms: the l <= 3 cases, the 21- and 16-mode ones)
 CASES = [
     ("rotation", 3, 4, 5, 6554, 32768.0, 600.0, synth.SIDEREAL_RATE, 1, 3000),
     ("rotation", 3, 9, 5, 3000, 32768.0, 100.0, 40.0, 2, 1500),      # magnified rotation rate
@@ -55,12 +59,16 @@ CASES = [
     ("arms", 3, 4, 4, 6554, 32768.0, 600.0, 0.0, 5, 2500),
     ("arms", 2, 16, 8, 1000, 32768.0, 200.0, 0.0, 6, 600),
     ("arms", 8, 2, 3, 400, 4096.0, 50.0, 0.0, 7, 1000),
+    ("rotation", 3, 12, 5, 3000, 32768.0, 300.0, synth.SIDEREAL_RATE, 14, 900, LM3),  # harmonic class 3
+    ("rotation_delay", 2, 11, 21, 2000, 32768.0, 200.0, 40.0, 15, 500, LM3[:11]),  # class 3, order 2
+    ("rotation_delay", 1, 21, 21, 1000, 32768.0, 300.0, 40.0, 16, 300),  # class 4, order 2, width 441
 ]
 
 
 def _case(c):
-    resp, K, M, n_a, n_t, fs, snr, omega, seed, n = c
-    pt = synth.make_point_wide(K, M, n_a, n_t, fs, snr, seed, response=resp, omega=omega)
+    resp, K, M, n_a, n_t, fs, snr, omega, seed, n = c[:10]
+    lm = c[10] if len(c) > 10 else None
+    pt = synth.make_point_wide(K, M, n_a, n_t, fs, snr, seed, response=resp, omega=omega, lm=lm)
     th = synth.prior_samples(n, seed + 10)
     return pt, th
 
