@@ -187,51 +187,90 @@ struct PairForms {
 template <int L>
 struct HarmForms {
   static constexpr int B = Cls<L>::B;
+  static constexpr int NC = 4 * B;              // coefficients of one block
+  static constexpr int CH = 16;                 // one 128-byte chunk: four rows
+  static constexpr int NCH = (NC + CH - 1) / CH;
   struct Run {
     double pc[4], ps[4];  // the two sums of the current q
     double er, ei;        // e^{i q phi}
   };
   template <int J>
-  static __device__ __forceinline__ void term(const RIFT_CONST double* c, const double* cn, const double* sn,
-                                              double cf, double sf, double* g, Run& R) {
-    constexpr int rb = basis_row<L>(J);
-    constexpr int kind = rb & 15, nn = (rb >> 4) & 255, q = rb >> 12;
-    constexpr bool last = (J + 1 == B) || ((basis_row<L>(J + 1) >> 12) != q);
-    const double tn = (kind == 3 || kind == 4) ? sn[nn] : cn[nn];
-    const RIFT_CONST double* e = c + 4 * J;
-    if constexpr (kind == 0) {
+  static __device__ __forceinline__ void term(const double* e, const double* cn, const double* sn, double cf,
+                                              double sf, double* g, Run& R) {
+    if constexpr (J < B) {
+      constexpr int rb = basis_row<L>(J);
+      constexpr int kind = rb & 15, nn = (rb >> 4) & 255, q = rb >> 12;
+      constexpr bool last = (J + 1 == B) || ((basis_row<L>(J + 1) >> 12) != q);
+      const double tn = (kind == 3 || kind == 4) ? sn[nn] : cn[nn];
+      if constexpr (kind == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) g[k] = fma(e[k], tn, g[k]);
-    } else {
-      double* acc = (kind == 1 || kind == 3) ? R.pc : R.ps;
+        for (int k = 0; k < 4; ++k) g[k] = fma(e[k], tn, g[k]);
+      } else {
+        double* acc = (kind == 1 || kind == 3) ? R.pc : R.ps;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[k] = fma(e[k], tn, acc[k]);
-      if constexpr (last) {
+        for (int k = 0; k < 4; ++k) acc[k] = fma(e[k], tn, acc[k]);
+        if constexpr (last) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          g[k] = fma(R.pc[k], R.er, fma(R.ps[k], R.ei, g[k]));
-          R.pc[k] = 0.0;
-          R.ps[k] = 0.0;
+          for (int k = 0; k < 4; ++k) {
+            g[k] = fma(R.pc[k], R.er, fma(R.ps[k], R.ei, g[k]));
+            R.pc[k] = 0.0;
+            R.ps[k] = 0.0;
+          }
+          const double nr = R.er * cf - R.ei * sf, ni = R.er * sf + R.ei * cf;
+          R.er = nr;
+          R.ei = ni;
         }
-        const double nr = R.er * cf - R.ei * sf, ni = R.er * sf + R.ei * cf;
-        R.er = nr;
-        R.ei = ni;
       }
     }
   }
-  template <int... J>
-  static __device__ __forceinline__ void all(const RIFT_CONST double* c, const double* cn, const double* sn,
-                                             double cf, double sf, double* g, std::integer_sequence<int, J...>) {
+  // The uniform coefficients stream through SGPRs in 128-byte chunks, each
+  // chunk prefetched while the previous one is used (the static path's
+  // scheme): the wait for a chunk comes before the next chunk is issued, and
+  // the accumulators are pinned after each chunk's FMAs so that those FMAs
+  // stay ahead of the next wait.
+  template <int C>
+  static __device__ __forceinline__ void ld(double (&buf)[CH], const RIFT_CONST double* c) {
+    const RIFT_CONST double* p = c + C * CH;
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (C * CH + i < NC) buf[i] = p[i];
+  }
+  template <int C>
+  static __device__ __forceinline__ void wait(const double (&buf)[CH]) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (C * CH + i < NC) pin_s(buf[i]);
+  }
+  template <int C>
+  static __device__ __forceinline__ void step(const RIFT_CONST double* c, double (&cur)[CH], double (&nxt)[CH],
+                                              const double* cn, const double* sn, double cf, double sf, double* g,
+                                              Run& R) {
+    if constexpr (C < NCH) {
+      wait<C>(cur);
+      if constexpr (C + 1 < NCH) ld<C + 1>(nxt, c);
+      term<4 * C>(cur, cn, sn, cf, sf, g, R);
+      term<4 * C + 1>(cur + 4, cn, sn, cf, sf, g, R);
+      term<4 * C + 2>(cur + 8, cn, sn, cf, sf, g, R);
+      term<4 * C + 3>(cur + 12, cn, sn, cf, sf, g, R);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        pin(g[k]);
+        pin(R.pc[k]);
+        pin(R.ps[k]);
+      }
+      step<C + 1>(c, nxt, cur, cn, sn, cf, sf, g, R);
+    }
+  }
+  static __device__ __forceinline__ void run(const RIFT_CONST double* c, const double* cn, const double* sn,
+                                             double cf, double sf, double* g) {
     Run R;
 #pragma unroll
     for (int k = 0; k < 4; ++k) R.pc[k] = R.ps[k] = 0.0;
     R.er = cf;  // the first group after q = 0 is q = 1
     R.ei = sf;
-    (term<J>(c, cn, sn, cf, sf, g, R), ...);
-  }
-  static __device__ __forceinline__ void run(const RIFT_CONST double* c, const double* cn, const double* sn,
-                                             double cf, double sf, double* g) {
-    all(c, cn, sn, cf, sf, g, std::make_integer_sequence<int, B>{});
+    double bA[CH], bB[CH];
+    ld<0>(bA, c);
+    step<0>(c, bA, bB, cn, sn, cf, sf, g, R);
   }
 };
 
