@@ -278,13 +278,17 @@ struct HarmForms {
 // pair a <= b): Re G, Im G, Re H, Im H of the block sampled on an NG x NG
 // grid of (incl, phi) over [0, 2 pi)^2, NG = 4L + 4 (more than twice the
 // degree 2L in each), then projected on the basis rows (discrete
-// orthogonality on that grid).  U, V in the caller's order [K][A][A]
-// complex; out [K][pair][B][4].
+// orthogonality on that grid).  Every angle on the grid is a multiple of
+// 2 pi / NG, so cos and sin come from one table of NG entries each; the
+// block's U and V entries are staged in LDS.  U, V in the caller's order
+// [K][A][A] complex; out [K][pair][B][4].
 template <int L>
 __global__ void k_wide_basis(WideDesc D, const double* __restrict__ U, const double* __restrict__ V,
                              double* __restrict__ out) {
-  constexpr int NG = 4 * L + 4, B = Cls<L>::B;
+  constexpr int NG = 4 * L + 4, B = Cls<L>::B, MX = Cls<L>::MAXM;
   __shared__ double g[4][NG * NG];
+  __shared__ double ct[NG], st[NG];
+  __shared__ double uv[MX * MX][4];
   const int k = blockIdx.x / D.npairs, pr = blockIdx.x - k * D.npairs;
   int a = 0, rem = pr;
   while (rem >= D.n_a - a) {
@@ -293,33 +297,57 @@ __global__ void k_wide_basis(WideDesc D, const double* __restrict__ U, const dou
   }
   const int b = a + rem;
   const int M = D.M, A = D.n_a * D.M;
-  const double two_pi = 6.283185307179586476925286766559;
+  for (int j = threadIdx.x; j < NG; j += blockDim.x) {
+    double sj, cj;
+    sincospi(2.0 * j / NG, &sj, &cj);
+    ct[j] = cj;
+    st[j] = sj;
+  }
+  for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
+    const int i = e / M, j = e - (e / M) * M;
+    const int64_t o = 2 * (((int64_t)k * A + a * M + D.perm[i]) * A + b * M + D.perm[j]);
+    uv[e][0] = U[o];
+    uv[e][1] = U[o + 1];
+    uv[e][2] = V[o];
+    uv[e][3] = V[o + 1];
+  }
+  __syncthreads();
+  // index of the angle n * (2 pi c / NG) in the tables
+  auto ix = [](int n, int c) { return ((n * c) % NG + NG) % NG; };
   for (int gp = threadIdx.x; gp < NG * NG; gp += blockDim.x) {
-    const double inc = two_pi * (gp / NG) / NG, ph = two_pi * (gp % NG) / NG;
-    double yr[MMAX], yi[MMAX];
-    for (int i = 0; i < M; ++i) {
-      double d = 0.0;
-      for (int q = 0; q <= LMAXC; ++q) d += D.ycoef[i][q] * (D.odd[i] ? sin(q * inc) : cos(q * inc));
-      double sm, cm;
-      sincos(D.m[i] * ph, &sm, &cm);
-      yr[i] = d * cm;
-      yi[i] = d * sm;
+    const int pi_ = gp / NG, pf = gp - (gp / NG) * NG;
+    double yr[MX], yi[MX];
+#pragma unroll
+    for (int i = 0; i < MX; ++i) {
+      yr[i] = yi[i] = 0.0;
+      if (i < M) {
+        double d = 0.0;
+        for (int q = 0; q <= L; ++q) d += D.ycoef[i][q] * (D.odd[i] ? st[ix(q, pi_)] : ct[ix(q, pi_)]);
+        const int r = ix(D.m[i], pf);
+        yr[i] = d * ct[r];
+        yi[i] = d * st[r];
+      }
     }
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = 0; i < M; ++i) {
-      double tr = 0.0, ti = 0.0, wr = 0.0, wi = 0.0;
-      for (int j = 0; j < M; ++j) {
-        const int64_t o = 2 * (((int64_t)k * A + a * M + D.perm[i]) * A + b * M + D.perm[j]);
-        const double ur = U[o], ui = U[o + 1], vr = V[o], vi = V[o + 1];
-        tr += ur * yr[j] - ui * yi[j];
-        ti += ur * yi[j] + ui * yr[j];
-        wr += vr * yr[j] - vi * yi[j];
-        wi += vr * yi[j] + vi * yr[j];
+#pragma unroll
+    for (int i = 0; i < MX; ++i) {
+      if (i < M) {
+        double tr = 0.0, ti = 0.0, wr = 0.0, wi = 0.0;
+#pragma unroll
+        for (int j = 0; j < MX; ++j) {
+          if (j < M) {
+            const double* e = uv[i * M + j];
+            tr += e[0] * yr[j] - e[1] * yi[j];
+            ti += e[0] * yi[j] + e[1] * yr[j];
+            wr += e[2] * yr[j] - e[3] * yi[j];
+            wi += e[2] * yi[j] + e[3] * yr[j];
+          }
+        }
+        v[0] += yr[i] * tr + yi[i] * ti;
+        v[1] += yr[i] * ti - yi[i] * tr;
+        v[2] += yr[i] * wr - yi[i] * wi;
+        v[3] += yr[i] * wi + yi[i] * wr;
       }
-      v[0] += yr[i] * tr + yi[i] * ti;
-      v[1] += yr[i] * ti - yi[i] * tr;
-      v[2] += yr[i] * wr - yi[i] * wi;
-      v[3] += yr[i] * wi + yi[i] * wr;
     }
     for (int c = 0; c < 4; ++c) g[c][gp] = v[c];
   }
@@ -329,13 +357,10 @@ __global__ void k_wide_basis(WideDesc D, const double* __restrict__ U, const dou
     const int kind = rb & 15, nn = (rb >> 4) & 255, q = rb >> 12;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int gp = 0; gp < NG * NG; ++gp) {
-      const double inc = two_pi * (gp / NG) / NG, ph = two_pi * (gp % NG) / NG;
-      double t;
-      if (kind == 0) t = cos(nn * inc);
-      else if (kind == 1) t = cos(nn * inc) * cos(q * ph);
-      else if (kind == 2) t = cos(nn * inc) * sin(q * ph);
-      else if (kind == 3) t = sin(nn * inc) * cos(q * ph);
-      else t = sin(nn * inc) * sin(q * ph);
+      const int pi_ = gp / NG, pf = gp - (gp / NG) * NG;
+      const double ti = (kind >= 3) ? st[ix(nn, pi_)] : ct[ix(nn, pi_)];
+      const double tf = (kind == 0) ? 1.0 : (kind == 1 || kind == 3) ? ct[ix(q, pf)] : st[ix(q, pf)];
+      const double t = ti * tf;
       for (int c = 0; c < 4; ++c) acc[c] += g[c][gp] * t;
     }
     const double norm = 1.0 / ((double)NG * NG * (nn == 0 ? 1.0 : 0.5) * (q == 0 ? 1.0 : 0.5));
