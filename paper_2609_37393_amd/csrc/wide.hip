@@ -59,6 +59,7 @@ namespace {
 constexpr int WIDE_ARMS_MAX_TERMS = 8;
 constexpr int WIDE_BLOCK = 256;     // lanes per block up to 12 terms
 constexpr int WIDE_BLOCK_21 = 128;  // up to 21 terms: the coefficient columns in 43 KB of LDS
+constexpr int WIDE_BASIS_BLOCK = 512;  // threads of the harmonic set-up: one per grid point
 
 struct WideDesc {
   int32_t K, M, n_t, n_a, response, npairs;
@@ -280,13 +281,16 @@ struct HarmForms {
 // degree 2L in each), then projected on the basis rows (discrete
 // orthogonality on that grid).  Every angle on the grid is a multiple of
 // 2 pi / NG, so cos and sin come from one table of NG entries each; the
-// block's U and V entries are staged in LDS.  U, V in the caller's order
+// block's U and V entries are staged in LDS; a thread per grid point, then
+// each basis row's projection split over WIDE_BASIS_BLOCK / B threads.  U, V in the caller's order
 // [K][A][A] complex; out [K][pair][B][4].
 template <int L>
 __global__ void k_wide_basis(WideDesc D, const double* __restrict__ U, const double* __restrict__ V,
                              double* __restrict__ out) {
   constexpr int NG = 4 * L + 4, B = Cls<L>::B, MX = Cls<L>::MAXM;
+  constexpr int PS = WIDE_BASIS_BLOCK / B;  // threads per basis row in the projection
   __shared__ double g[4][NG * NG];
+  __shared__ double part[PS][B][4];
   __shared__ double ct[NG], st[NG];
   __shared__ double uv[MX * MX][4];
   const int k = blockIdx.x / D.npairs, pr = blockIdx.x - k * D.npairs;
@@ -352,20 +356,32 @@ __global__ void k_wide_basis(WideDesc D, const double* __restrict__ U, const dou
     for (int c = 0; c < 4; ++c) g[c][gp] = v[c];
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < B; r += blockDim.x) {
+  // each row's sum over the grid split over PS threads, then reduced
+  for (int w = threadIdx.x; w < PS * B; w += blockDim.x) {
+    const int r = w % B, sp = w / B;
     const int rb = basis_row<L>(r);
     const int kind = rb & 15, nn = (rb >> 4) & 255, q = rb >> 12;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int gp = 0; gp < NG * NG; ++gp) {
+    for (int gp = sp; gp < NG * NG; gp += PS) {
       const int pi_ = gp / NG, pf = gp - (gp / NG) * NG;
       const double ti = (kind >= 3) ? st[ix(nn, pi_)] : ct[ix(nn, pi_)];
       const double tf = (kind == 0) ? 1.0 : (kind == 1 || kind == 3) ? ct[ix(q, pf)] : st[ix(q, pf)];
       const double t = ti * tf;
       for (int c = 0; c < 4; ++c) acc[c] += g[c][gp] * t;
     }
+    for (int c = 0; c < 4; ++c) part[sp][r][c] = acc[c];
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < B; r += blockDim.x) {
+    const int rb = basis_row<L>(r);
+    const int nn = (rb >> 4) & 255, q = rb >> 12;
     const double norm = 1.0 / ((double)NG * NG * (nn == 0 ? 1.0 : 0.5) * (q == 0 ? 1.0 : 0.5));
     double* o = out + ((int64_t)blockIdx.x * B + r) * 4;
-    for (int c = 0; c < 4; ++c) o[c] = acc[c] * norm;
+    for (int c = 0; c < 4; ++c) {
+      double v = 0.0;
+      for (int sp = 0; sp < PS; ++sp) v += part[sp][r][c];
+      o[c] = v * norm;
+    }
   }
 }
 
@@ -843,8 +859,8 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
       break;
     case 12:
       if (D.hb == 3) {
-        hipLaunchKernelGGL(k_wide_basis<3>, dim3((unsigned)(D.K * D.npairs)), dim3(256), 0, st, D, pt->U, pt->V,
-                           (double*)scratch);
+        hipLaunchKernelGGL(k_wide_basis<3>, dim3((unsigned)(D.K * D.npairs)), dim3(WIDE_BASIS_BLOCK), 0, st, D,
+                           pt->U, pt->V, (double*)scratch);
         if (wide21)
           hipLaunchKernelGGL((k_wide<12, 21, WIDE_BLOCK_21, 3>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
         else
@@ -859,8 +875,8 @@ int wide_run(const rift_ile_point_wide* pt, int64_t n, const double* theta, cons
       break;
     default:
       if (D.hb == 4) {
-        hipLaunchKernelGGL(k_wide_basis<4>, dim3((unsigned)(D.K * D.npairs)), dim3(256), 0, st, D, pt->U, pt->V,
-                           (double*)scratch);
+        hipLaunchKernelGGL(k_wide_basis<4>, dim3((unsigned)(D.K * D.npairs)), dim3(WIDE_BASIS_BLOCK), 0, st, D,
+                           pt->U, pt->V, (double*)scratch);
         if (wide21)
           hipLaunchKernelGGL((k_wide<21, 21, WIDE_BLOCK_21, 4>), grid, block, 0, st, D, theta, n, lnw, lnL, d_part);
         else
