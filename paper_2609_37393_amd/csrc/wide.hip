@@ -175,6 +175,79 @@ struct PairForms {
   }
 };
 
+// The entry form for the 5-mode capacity with the coefficients streamed
+// through double-buffered 128-byte scalar chunks (four entries each; the
+// static path's prefetch): the whole MC x MC block is read, the entries past
+// M being zero in the pack and Y zero there, so every index is a template
+// constant.  Row i's (U Y)_i and (V Y)_i accumulate across chunk boundaries.
+template <int MC>
+struct PairFormsP {
+  static constexpr int NC = 4 * MC * MC;
+  static constexpr int CH = 16;
+  static constexpr int NCH = (NC + CH - 1) / CH;
+  struct Row {
+    double tr, ti, vr, vi;
+  };
+  template <int E>
+  static __device__ __forceinline__ void entry(const double* e, const double* yr, const double* yi, double* g,
+                                               Row& R) {
+    if constexpr (E < MC * MC) {
+      constexpr int i = E / MC, j = E % MC;
+      if constexpr (j == 0) R.tr = R.ti = R.vr = R.vi = 0.0;
+      R.tr += e[0] * yr[j] - e[1] * yi[j];
+      R.ti += e[0] * yi[j] + e[1] * yr[j];
+      R.vr += e[2] * yr[j] - e[3] * yi[j];
+      R.vi += e[2] * yi[j] + e[3] * yr[j];
+      if constexpr (j == MC - 1) {
+        g[0] += yr[i] * R.tr + yi[i] * R.ti;
+        g[1] += yr[i] * R.ti - yi[i] * R.tr;
+        g[2] += yr[i] * R.vr - yi[i] * R.vi;
+        g[3] += yr[i] * R.vi + yi[i] * R.vr;
+      }
+    }
+  }
+  template <int C>
+  static __device__ __forceinline__ void ld(double (&buf)[CH], const RIFT_CONST double* c) {
+    const RIFT_CONST double* p = c + C * CH;
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (C * CH + i < NC) buf[i] = p[i];
+  }
+  template <int C>
+  static __device__ __forceinline__ void wait(const double (&buf)[CH]) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+      if (C * CH + i < NC) pin_s(buf[i]);
+  }
+  template <int C>
+  static __device__ __forceinline__ void step(const RIFT_CONST double* c, double (&cur)[CH], double (&nxt)[CH],
+                                              const double* yr, const double* yi, double* g, Row& R) {
+    if constexpr (C < NCH) {
+      wait<C>(cur);
+      if constexpr (C + 1 < NCH) ld<C + 1>(nxt, c);
+      entry<4 * C>(cur, yr, yi, g, R);
+      entry<4 * C + 1>(cur + 4, yr, yi, g, R);
+      entry<4 * C + 2>(cur + 8, yr, yi, g, R);
+      entry<4 * C + 3>(cur + 12, yr, yi, g, R);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) pin(g[k]);
+      pin(R.tr);
+      pin(R.ti);
+      pin(R.vr);
+      pin(R.vi);
+      step<C + 1>(c, nxt, cur, yr, yi, g, R);
+    }
+  }
+  static __device__ __forceinline__ void run(const RIFT_CONST double* c, const double* yr, const double* yi,
+                                             double* g) {
+    Row R;
+    R.tr = R.ti = R.vr = R.vi = 0.0;
+    double bA[CH], bB[CH];
+    ld<0>(bA, c);
+    step<0>(c, bA, bB, yr, yi, g, R);
+  }
+};
+
 // The same four forms of one block in the harmonic basis of class L, summed
 // per harmonic q in phi: the rows of one q are consecutive and q increases
 // along them (basis_row), so
@@ -685,6 +758,8 @@ __global__ void __launch_bounds__(BLK, MC <= 5 && NT <= 12 ? 3 : 2) k_wide(WideD
           asm volatile("" : "+v"(cfo), "+v"(sfo));
           HarmForms<HL>::run(opaque(blk), cn, sn, cfo, sfo, g);
         }
+        else if constexpr (MC == 5)
+          PairFormsP<5>::run(opaque(blk), yr, yi, g);
         else
           PairForms<0, MC>::run(opaque(blk), M, yr, yi, g);
         const double gr = g[0], gi = g[1], hr = g[2], hi = g[3];
