@@ -62,6 +62,8 @@ CASES = [
     ("rotation", 3, 12, 5, 3000, 32768.0, 300.0, synth.SIDEREAL_RATE, 14, 900, LM3),  # harmonic class 3
     ("rotation_delay", 2, 11, 21, 2000, 32768.0, 200.0, 40.0, 15, 500, LM3[:11]),  # class 3, order 2
     ("rotation_delay", 1, 21, 21, 1000, 32768.0, 300.0, 40.0, 16, 300),  # class 4, order 2, width 441
+    ("rotation", 2, 10, 5, 1500, 32768.0, 200.0, 40.0, 17, 700, LM3[:10]),  # the fewest modes of class 3
+    ("arms", 2, 13, 3, 1500, 32768.0, 200.0, 0.0, 18, 700),  # the fewest modes of class 4
 ]
 
 
